@@ -1,0 +1,279 @@
+"""Plain FP64 CPU oracle of the TPFA black-oil Newton path (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``.  The GPU library never calls it.
+The C sources (``oracle.c``) are compiled with gcc into ``liboracle.so``
+next to this file; ``build()`` recompiles them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SOURCES = [os.path.join(_HERE, "oracle.c")]
+_libs = {}
+
+OK, EINVAL, ESINGULAR, ENOTCONV, EBREAKDOWN, ENONFINITE = 0, -1, -2, -3, -4, -5
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+class Fluid(ctypes.Structure):
+    _fields_ = [("rho_s", ctypes.c_double * 3), ("c", ctypes.c_double * 3),
+                ("p_ref", ctypes.c_double), ("mu", ctypes.c_double * 3),
+                ("swc", ctypes.c_double), ("n_corey", ctypes.c_double), ("g", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol_cnv", ctypes.c_double), ("tol_mb", ctypes.c_double),
+                ("ds_max", ctypes.c_double), ("dp_max_rel", ctypes.c_double),
+                ("lin_rtol", ctypes.c_double), ("max_newton", ctypes.c_int),
+                ("lin_maxit", ctypes.c_int), ("max_cuts", ctypes.c_int)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("newton_its", ctypes.c_int),
+                ("substeps", ctypes.c_int), ("cuts", ctypes.c_int),
+                ("lin_its", ctypes.c_double), ("cnv", ctypes.c_double * 3),
+                ("mb", ctypes.c_double * 3), ("mass_err", ctypes.c_double * 3),
+                ("t_assemble", ctypes.c_double), ("t_factor", ctypes.c_double),
+                ("t_krylov", ctypes.c_double), ("t_update", ctypes.c_double),
+                ("cell_newton_its", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"status": self.status, "newton_its": self.newton_its, "substeps": self.substeps,
+                "cuts": self.cuts, "lin_its": self.lin_its, "cnv": list(self.cnv),
+                "mb": list(self.mb), "mass_err": list(self.mass_err),
+                "t_assemble": self.t_assemble, "t_factor": self.t_factor,
+                "t_krylov": self.t_krylov, "t_update": self.t_update,
+                "cell_newton_its": self.cell_newton_its}
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (plain -O2, IEEE semantics, single thread)."""
+    if not force and os.path.exists(_LIB_PATH) and all(
+            os.path.getmtime(_LIB_PATH) >= os.path.getmtime(s) for s in _SOURCES
+            + [os.path.join(_HERE, "oracle.h")]):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", tmp] + _SOURCES + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib(path: Optional[str] = None):
+    """Load the oracle library (``path`` selects another build of the same
+    sources, e.g. a deliberately mutated copy used by the pin tests)."""
+    key = path or _LIB_PATH
+    if key not in _libs:
+        if path is None:
+            build(force=False)
+        L = ctypes.CDLL(key)
+        L.ora_create.restype = ctypes.c_void_p
+        L.ora_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_double, _dp, _dp, ctypes.c_double, _dp, _u8p,
+                                 ctypes.POINTER(Fluid), ctypes.c_int, _ip, _ip, _dp, _dp, _ip, _ip]
+        L.ora_destroy.argtypes = [ctypes.c_void_p]
+        for name in ("ora_n_cells", "ora_n_faces", "ora_nnzb", "ora_n_conns"):
+            getattr(L, name).argtypes = [ctypes.c_void_p]
+            getattr(L, name).restype = ctypes.c_int
+        L.ora_geometry.argtypes = [ctypes.c_void_p, _ip, _dp, _dp, _dp, _ip]
+        L.ora_pattern.argtypes = [ctypes.c_void_p, _ip, _ip]
+        L.ora_conns.argtypes = [ctypes.c_void_p, _ip, _dp, _ip]
+        L.ora_accumulation.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.ora_well_rates.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.ora_assemble.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, _dp, _dp]
+        L.ora_norms.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, _dp, _dp]
+        L.ora_ilu0.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.ora_ilu0_apply.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.ora_spmv.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.ora_bicgstab.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, ctypes.c_double,
+                                   ctypes.c_int, _dp, _dp]
+        L.ora_newton_step.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double,
+                                      ctypes.POINTER(Opts), ctypes.POINTER(Report)]
+        L.ora_advance.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.POINTER(Opts),
+                                  ctypes.POINTER(Report)]
+        L.ora_dense_solve.argtypes = [ctypes.c_int, _dp, _dp]
+        _libs[key] = L
+    return _libs[key]
+
+
+def _d(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a: np.ndarray):
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(_ip)
+
+
+def default_opts(case=None, **kw) -> Opts:
+    o = Opts(tol_cnv=1e-8, tol_mb=1e-11, ds_max=0.2, dp_max_rel=0.3, lin_rtol=1e-6,
+             max_newton=20, lin_maxit=500, max_cuts=8)
+    if case is not None:
+        o.tol_cnv, o.tol_mb, o.lin_rtol = case.tol_cnv, case.tol_mb, case.lin_rtol
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Model:
+    """Oracle model of one case (owns the C handle)."""
+
+    def __init__(self, case, lib_path: Optional[str] = None):
+        L = lib(lib_path)
+        f = case.fluid
+        self.fluid = Fluid((ctypes.c_double * 3)(*f.rho_s), (ctypes.c_double * 3)(*f.c), f.p_ref,
+                           (ctypes.c_double * 3)(*f.mu), f.swc, f.n_corey, f.g)
+        dz = np.ascontiguousarray(case.dz, dtype=np.float64)
+        perm = np.ascontiguousarray(case.perm_h, dtype=np.float64).ravel()
+        poro = np.ascontiguousarray(case.poro, dtype=np.float64).ravel()
+        mask = np.ascontiguousarray(case.mask, dtype=np.uint8).ravel()
+        nw = len(case.wells)
+        kind = np.array([w.kind for w in case.wells] + [0], dtype=np.int32)
+        phase = np.array([w.phase for w in case.wells] + [0], dtype=np.int32)
+        target = np.array([w.target for w in case.wells] + [0.0], dtype=np.float64)
+        rw = np.array([w.rw for w in case.wells] + [1.0], dtype=np.float64)
+        nconn = np.array([len(w.cells) for w in case.wells] + [0], dtype=np.int32)
+        ijk = np.array([c for w in case.wells for c in w.cells] + [(0, 0, 0)], dtype=np.int32)
+        self._keep = (dz, perm, poro, mask, kind, phase, target, rw, nconn, ijk)
+        h = L.ora_create(case.nx, case.ny, case.nz, case.dx, case.dy, _d(dz), _d(perm), case.kv_kh,
+                         _d(poro), mask.ctypes.data_as(_u8p), ctypes.byref(self.fluid), nw,
+                         _i(kind), _i(phase), _d(target), _d(rw), _i(nconn), _i(ijk))
+        if not h:
+            raise ValueError("oracle: invalid case")
+        self.h = ctypes.c_void_p(h)
+        self.L = L
+        self.case = case
+        self.n = L.ora_n_cells(self.h)
+        self.nf = L.ora_n_faces(self.h)
+        self.nnzb = L.ora_nnzb(self.h)
+        self.nc = L.ora_n_conns(self.h)
+
+    def __del__(self):
+        try:
+            self.L.ora_destroy(self.h)
+        except Exception:
+            pass
+
+    # ---- geometry / pattern
+    def geometry(self):
+        fc = np.zeros((max(self.nf, 1), 2), np.int32)
+        T = np.zeros(max(self.nf, 1))
+        pv = np.zeros(self.n)
+        z = np.zeros(self.n)
+        cb = np.zeros(self.n, np.int32)
+        self.L.ora_geometry(self.h, _i(fc), _d(T), _d(pv), _d(z), _i(cb))
+        return {"face_cells": fc[:self.nf], "trans": T[:self.nf], "pore_vol": pv, "depth": z,
+                "cell_box": cb}
+
+    def pattern(self):
+        rp = np.zeros(self.n + 1, np.int32)
+        ci = np.zeros(self.nnzb, np.int32)
+        self.L.ora_pattern(self.h, _i(rp), _i(ci))
+        return rp, ci
+
+    def conns(self):
+        cell = np.zeros(max(self.nc, 1), np.int32)
+        wi = np.zeros(max(self.nc, 1))
+        well = np.zeros(max(self.nc, 1), np.int32)
+        self.L.ora_conns(self.h, _i(cell), _d(wi), _i(well))
+        return cell[:self.nc], wi[:self.nc], well[:self.nc]
+
+    # ---- path steps
+    def accumulation(self, y):
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        acc = np.zeros((self.n, 3))
+        self.L.ora_accumulation(self.h, _d(y), _d(acc))
+        return acc
+
+    def well_rates(self, y):
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        q = np.zeros((self.n, 3))
+        self.L.ora_well_rates(self.h, _d(y), _d(q))
+        return q
+
+    def assemble(self, y, acc0, dt, jacobian=True):
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        acc0 = np.ascontiguousarray(acc0, dtype=np.float64)
+        R = np.zeros((self.n, 3))
+        J = np.zeros((self.nnzb, 3, 3)) if jacobian else None
+        st = self.L.ora_assemble(self.h, _d(y), _d(acc0), dt, _d(R),
+                                 _d(J) if jacobian else ctypes.cast(None, _dp))
+        return st, R, J
+
+    def norms(self, y, R, dt):
+        cnv = np.zeros(3)
+        mb = np.zeros(3)
+        self.L.ora_norms(self.h, _d(np.ascontiguousarray(y)), _d(np.ascontiguousarray(R)), dt,
+                         _d(cnv), _d(mb))
+        return cnv, mb
+
+    def ilu0(self, J):
+        F = np.zeros_like(J)
+        st = self.L.ora_ilu0(self.h, _d(np.ascontiguousarray(J)), _d(F))
+        return st, F
+
+    def ilu0_apply(self, F, r):
+        x = np.zeros((self.n, 3))
+        self.L.ora_ilu0_apply(self.h, _d(F), _d(np.ascontiguousarray(r, dtype=np.float64)), _d(x))
+        return x
+
+    def spmv(self, J, x):
+        y = np.zeros((self.n, 3))
+        self.L.ora_spmv(self.h, _d(J), _d(np.ascontiguousarray(x, dtype=np.float64)), _d(y))
+        return y
+
+    def bicgstab(self, J, F, b, rtol=1e-6, maxit=500):
+        x = np.zeros((self.n, 3))
+        its = ctypes.c_double()
+        rr = ctypes.c_double()
+        st = self.L.ora_bicgstab(self.h, _d(J), _d(F), _d(np.ascontiguousarray(b, dtype=np.float64)),
+                                 _d(x), rtol, maxit, ctypes.byref(its), ctypes.byref(rr))
+        return st, x, its.value, rr.value
+
+    def newton_step(self, y, y_prev, dt, opts: Optional[Opts] = None):
+        y = np.array(y, dtype=np.float64, order="C")
+        yp = np.ascontiguousarray(y_prev, dtype=np.float64)
+        rep = Report()
+        o = opts or default_opts(self.case)
+        st = self.L.ora_newton_step(self.h, _d(y), _d(yp), dt, ctypes.byref(o), ctypes.byref(rep))
+        return st, y, rep
+
+    def advance(self, y, dt, opts: Optional[Opts] = None):
+        y = np.array(y, dtype=np.float64, order="C")
+        rep = Report()
+        o = opts or default_opts(self.case)
+        st = self.L.ora_advance(self.h, _d(y), dt, ctypes.byref(o), ctypes.byref(rep))
+        return st, y, rep
+
+    def run(self, y0=None, n_steps=None, opts=None):
+        """Advance over the case's report schedule; returns states after each report step."""
+        y = self.case.initial_state() if y0 is None else np.array(y0, dtype=np.float64)
+        states, reps = [], []
+        for dt in self.case.report_dt[:n_steps]:
+            st, y, rep = self.advance(y, dt, opts)
+            if st != OK:
+                raise RuntimeError(f"oracle advance failed with status {st}")
+            states.append(y.copy())
+            reps.append(rep.as_dict())
+        return states, reps
+
+
+def dense_solve(A: np.ndarray, b: np.ndarray, lib_path: Optional[str] = None) -> np.ndarray:
+    A = np.array(A, dtype=np.float64, order="C")
+    x = np.array(b, dtype=np.float64, order="C")
+    st = lib(lib_path).ora_dense_solve(A.shape[0], _d(A), _d(x))
+    if st != OK:
+        raise np.linalg.LinAlgError("singular")
+    return x

@@ -1,0 +1,835 @@
+/*
+ * oracle.c -- plain FP64 CPU reference of the TPFA black-oil Newton path.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Written for readability, not
+ * speed: one generic dual-number type, faces visited once, block entries
+ * located by searching the row, generic IKJ ILU(0), textbook BiCGStab.
+ *
+ * What pins each part (tests/test_oracle_*.py):
+ *   geometry        series-resistance and equal-permeability closed forms,
+ *                   the layered-depth definition, Peaceman worked value
+ *   properties      defining ODE of constant compressibility (b'/b = c),
+ *                   Corey worked values, gwseg two-phase reductions
+ *   residual        hydrostatic column (R = 0 to round-off), 1-D Darcy flux
+ *                   against the series-resistance formula, upwind selection,
+ *                   single-phase pressure block closed form, exact flux
+ *                   cancellation (sum of residuals = accumulation + wells)
+ *   Jacobian        central finite differences of the residual
+ *   ILU(0)          (LU)_ij = A_ij on every pattern entry; exact LU on 1-D
+ *   BiCGStab        dense direct solve (numpy) on tiny grids
+ *   Newton          one-cell producer root by bisection, quadratic
+ *                   convergence, mass balance per step, mirror symmetry
+ * Full multi-step runs are not pinned against the paper (it prints no
+ * states); they are pinned only through the properties above.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+
+/* ------------------------------------------------------------------ timing */
+static double now_s(void) {
+  struct timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/* ------------------------------------------- forward-mode AD (sec. 2.4.1)
+ * A value paired with a fixed number of partial derivatives; every operation
+ * applies the chain rule.  Slots 0-2 are d/d(p, s_w, s_g) of the first cell
+ * of a connection, slots 3-5 those of the second cell. */
+#define ND 6
+typedef struct {
+  double v;
+  double d[ND];
+} dual;
+
+static dual dconst(double v) {
+  dual r;
+  r.v = v;
+  for (int i = 0; i < ND; ++i) r.d[i] = 0.0;
+  return r;
+}
+static dual dvar(double v, int slot) {
+  dual r = dconst(v);
+  r.d[slot] = 1.0;
+  return r;
+}
+static dual dadd(dual a, dual b) {
+  dual r;
+  r.v = a.v + b.v;
+  for (int i = 0; i < ND; ++i) r.d[i] = a.d[i] + b.d[i];
+  return r;
+}
+static dual dsub(dual a, dual b) {
+  dual r;
+  r.v = a.v - b.v;
+  for (int i = 0; i < ND; ++i) r.d[i] = a.d[i] - b.d[i];
+  return r;
+}
+static dual dmul(dual a, dual b) {   /* (uv)' = u'v + uv' */
+  dual r;
+  r.v = a.v * b.v;
+  for (int i = 0; i < ND; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+  return r;
+}
+static dual ddiv(dual a, dual b) {   /* (u/v)' = (u'v - uv')/v^2 */
+  dual r;
+  r.v = a.v / b.v;
+  for (int i = 0; i < ND; ++i) r.d[i] = (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v);
+  return r;
+}
+static dual dscale(dual a, double s) {
+  dual r;
+  r.v = a.v * s;
+  for (int i = 0; i < ND; ++i) r.d[i] = a.d[i] * s;
+  return r;
+}
+static dual dexp(dual a) {
+  dual r;
+  r.v = exp(a.v);
+  for (int i = 0; i < ND; ++i) r.d[i] = r.v * a.d[i];
+  return r;
+}
+static dual dpow(dual a, double n) {   /* a >= 0, n >= 1 */
+  dual r;
+  r.v = pow(a.v, n);
+  double dv = n * pow(a.v, n - 1.0);
+  for (int i = 0; i < ND; ++i) r.d[i] = dv * a.d[i];
+  return r;
+}
+/* clamp to [0,1]; on the bounds themselves the argument passes through */
+static dual dclamp01(dual a) {
+  if (a.v < 0.0) return dconst(0.0);
+  if (a.v > 1.0) return dconst(1.0);
+  return a;
+}
+/* max(a, 0); at a == 0 the constant branch is taken */
+static dual dmax0(dual a) {
+  if (a.v > 0.0) return a;
+  return dconst(0.0);
+}
+
+/* ------------------------------------------------------------------ model */
+struct ora_model {
+  int nx, ny, nz, n, nf, nnzb, nw, nc;
+  double dx, dy;
+  ora_fluid fl;
+  double* dz;      /* [nz] */
+  int* cell_box;   /* [n]  */
+  int* box_cell;   /* [nx*ny*nz], -1 if inactive */
+  double* kh;      /* [n] horizontal permeability */
+  double* kv;      /* [n] vertical permeability   */
+  double* pv;      /* [n] phi_ref V                */
+  double* depth;   /* [n] cell-centre depth, positive down */
+  int* face;       /* [nf][2], face[f][0] < face[f][1] */
+  double* trans;   /* [nf] */
+  int* row_ptr;    /* [n+1] */
+  int* col_idx;    /* [nnzb] */
+  int* well_kind;  /* [nw] */
+  int* well_phase; /* [nw] */
+  double* well_target;
+  int* well_beg;   /* [nw+1] connection ranges */
+  int* conn_cell;  /* [nc] */
+  double* conn_wi; /* [nc] */
+  int* conn_well;  /* [nc] */
+};
+
+int ora_n_cells(const ora_model* m) { return m->n; }
+int ora_n_faces(const ora_model* m) { return m->nf; }
+int ora_nnzb(const ora_model* m) { return m->nnzb; }
+int ora_n_conns(const ora_model* m) { return m->nc; }
+
+void ora_destroy(ora_model* m) {
+  if (!m) return;
+  free(m->dz); free(m->cell_box); free(m->box_cell); free(m->kh); free(m->kv);
+  free(m->pv); free(m->depth); free(m->face); free(m->trans); free(m->row_ptr);
+  free(m->col_idx); free(m->well_kind); free(m->well_phase); free(m->well_target);
+  free(m->well_beg); free(m->conn_cell); free(m->conn_wi); free(m->conn_well);
+  free(m);
+}
+
+/* Cell centre of box cell (i, j, k); z is depth measured down from the top. */
+static double layer_top(const ora_model* m, int k) {
+  double z = 0.0;
+  for (int q = 0; q < k; ++q) z += m->dz[q];
+  return z;
+}
+
+/* Half-transmissibility of appendix B:
+ * t = |F| (K (c_f - c) . n) / |c_f - c|^2 for a diagonal K. */
+static double half_trans(double area, const double K[3], const double c[3], const double cf[3],
+                         const double nrm[3]) {
+  double d[3] = {cf[0] - c[0], cf[1] - c[1], cf[2] - c[2]};
+  double Kd[3] = {K[0] * d[0], K[1] * d[1], K[2] * d[2]};
+  double num = Kd[0] * nrm[0] + Kd[1] * nrm[1] + Kd[2] * nrm[2];
+  double den = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  return area * num / den;
+}
+
+static int find_block(const ora_model* m, int i, int j) {
+  for (int q = m->row_ptr[i]; q < m->row_ptr[i + 1]; ++q)
+    if (m->col_idx[q] == j) return q;
+  return -1;
+}
+
+ora_model* ora_create(int nx, int ny, int nz, double dx, double dy, const double* dz,
+                      const double* perm_h, double kv_kh, const double* poro,
+                      const unsigned char* mask, const ora_fluid* fluid, int n_wells,
+                      const int* well_kind, const int* well_phase, const double* well_target,
+                      const double* well_rw, const int* well_nconn, const int* conn_ijk) {
+  if (nx <= 0 || ny <= 0 || nz <= 0 || n_wells < 0) return NULL;
+  ora_model* m = (ora_model*)calloc(1, sizeof(ora_model));
+  const int nb = nx * ny * nz;
+  m->nx = nx; m->ny = ny; m->nz = nz; m->dx = dx; m->dy = dy; m->fl = *fluid;
+  m->dz = (double*)malloc(sizeof(double) * nz);
+  memcpy(m->dz, dz, sizeof(double) * nz);
+  m->box_cell = (int*)malloc(sizeof(int) * nb);
+  int n = 0;
+  for (int b = 0; b < nb; ++b) m->box_cell[b] = (mask == NULL || mask[b]) ? n++ : -1;
+  m->n = n;
+  m->cell_box = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+  for (int b = 0; b < nb; ++b)
+    if (m->box_cell[b] >= 0) m->cell_box[m->box_cell[b]] = b;
+
+  /* rock: porosity, permeability tensor diag(kh, kh, kv), pore volume, depth */
+  m->kh = (double*)malloc(sizeof(double) * (n + 1));
+  m->kv = (double*)malloc(sizeof(double) * (n + 1));
+  m->pv = (double*)malloc(sizeof(double) * (n + 1));
+  m->depth = (double*)malloc(sizeof(double) * (n + 1));
+  for (int c = 0; c < n; ++c) {
+    int b = m->cell_box[c];
+    int k = b / (nx * ny);
+    m->kh[c] = perm_h[b];
+    m->kv[c] = kv_kh * perm_h[b];
+    m->pv[c] = poro[b] * (dx * dy * dz[k]);
+    m->depth[c] = layer_top(m, k) + 0.5 * dz[k];
+  }
+
+  /* faces: the +x, +y, +z neighbours of each active cell (so i < j) */
+  m->face = (int*)malloc(sizeof(int) * 2 * (3 * n + 1));
+  m->trans = (double*)malloc(sizeof(double) * (3 * n + 1));
+  int nf = 0;
+  for (int c = 0; c < n; ++c) {
+    int b = m->cell_box[c];
+    int i = b % nx, j = (b / nx) % ny, k = b / (nx * ny);
+    double ci[3] = {(i + 0.5) * dx, (j + 0.5) * dy, m->depth[c]};
+    double Ki[3] = {m->kh[c], m->kh[c], m->kv[c]};
+    for (int dir = 0; dir < 3; ++dir) {
+      int ii = i + (dir == 0), jj = j + (dir == 1), kk = k + (dir == 2);
+      if (ii >= nx || jj >= ny || kk >= nz) continue;
+      int nbx = ii + nx * (jj + ny * kk);
+      int cn = m->box_cell[nbx];
+      if (cn < 0) continue;
+      double cj[3] = {(ii + 0.5) * dx, (jj + 0.5) * dy, m->depth[cn]};
+      double Kj[3] = {m->kh[cn], m->kh[cn], m->kv[cn]};
+      double cf[3] = {ci[0], ci[1], ci[2]};
+      double nrm[3] = {0.0, 0.0, 0.0};
+      double area;
+      if (dir == 0) { cf[0] = (i + 1) * dx; area = dy * dz[k]; }
+      else if (dir == 1) { cf[1] = (j + 1) * dy; area = dx * dz[k]; }
+      else { cf[2] = layer_top(m, k + 1); area = dx * dy; }
+      nrm[dir] = 1.0;
+      double mnrm[3] = {-nrm[0], -nrm[1], -nrm[2]};
+      double tij = half_trans(area, Ki, ci, cf, nrm);
+      double tji = half_trans(area, Kj, cj, cf, mnrm);
+      m->face[2 * nf] = c;
+      m->face[2 * nf + 1] = cn;
+      m->trans[nf] = (tij + tji > 0.0) ? tij * tji / (tij + tji) : 0.0;
+      ++nf;
+    }
+  }
+  m->nf = nf;
+
+  /* block-CSR pattern: diagonal plus both cells of every face, columns sorted */
+  m->row_ptr = (int*)calloc((size_t)n + 1, sizeof(int));
+  for (int c = 0; c < n; ++c) m->row_ptr[c + 1] = 1;
+  for (int f = 0; f < nf; ++f) {
+    m->row_ptr[m->face[2 * f] + 1]++;
+    m->row_ptr[m->face[2 * f + 1] + 1]++;
+  }
+  for (int c = 0; c < n; ++c) m->row_ptr[c + 1] += m->row_ptr[c];
+  m->nnzb = m->row_ptr[n];
+  m->col_idx = (int*)malloc(sizeof(int) * (m->nnzb + 1));
+  int* fill = (int*)malloc(sizeof(int) * (n + 1));
+  for (int c = 0; c < n; ++c) {
+    fill[c] = m->row_ptr[c];
+    m->col_idx[fill[c]++] = c;
+  }
+  for (int f = 0; f < nf; ++f) {
+    int a = m->face[2 * f], b = m->face[2 * f + 1];
+    m->col_idx[fill[a]++] = b;
+    m->col_idx[fill[b]++] = a;
+  }
+  free(fill);
+  for (int c = 0; c < n; ++c) {   /* insertion sort of each row */
+    for (int q = m->row_ptr[c] + 1; q < m->row_ptr[c + 1]; ++q) {
+      int v = m->col_idx[q], r = q - 1;
+      while (r >= m->row_ptr[c] && m->col_idx[r] > v) {
+        m->col_idx[r + 1] = m->col_idx[r];
+        --r;
+      }
+      m->col_idx[r + 1] = v;
+    }
+  }
+
+  /* wells and their connections; Peaceman well index (skin 0) */
+  m->nw = n_wells;
+  m->well_kind = (int*)malloc(sizeof(int) * (n_wells + 1));
+  m->well_phase = (int*)malloc(sizeof(int) * (n_wells + 1));
+  m->well_target = (double*)malloc(sizeof(double) * (n_wells + 1));
+  m->well_beg = (int*)malloc(sizeof(int) * (n_wells + 1));
+  int nc = 0;
+  for (int w = 0; w < n_wells; ++w) nc += well_nconn[w];
+  m->nc = nc;
+  m->conn_cell = (int*)malloc(sizeof(int) * (nc + 1));
+  m->conn_wi = (double*)malloc(sizeof(double) * (nc + 1));
+  m->conn_well = (int*)malloc(sizeof(int) * (nc + 1));
+  int q = 0;
+  for (int w = 0; w < n_wells; ++w) {
+    m->well_kind[w] = well_kind[w];
+    m->well_phase[w] = well_phase[w];
+    m->well_target[w] = well_target[w];
+    m->well_beg[w] = q;
+    for (int t = 0; t < well_nconn[w]; ++t, ++q) {
+      int i = conn_ijk[3 * q], j = conn_ijk[3 * q + 1], k = conn_ijk[3 * q + 2];
+      if (i < 0 || i >= nx || j < 0 || j >= ny || k < 0 || k >= nz ||
+          m->box_cell[i + nx * (j + ny * k)] < 0) {
+        ora_destroy(m);
+        return NULL;
+      }
+      int c = m->box_cell[i + nx * (j + ny * k)];
+      double ro = 0.14 * sqrt(dx * dx + dy * dy);
+      m->conn_cell[q] = c;
+      m->conn_wi[q] = 2.0 * M_PI * m->kh[c] * dz[k] / log(ro / well_rw[w]);
+      m->conn_well[q] = w;
+    }
+  }
+  m->well_beg[n_wells] = q;
+  return m;
+}
+
+void ora_geometry(const ora_model* m, int* face_cells, double* trans, double* pv, double* depth,
+                  int* cell_box) {
+  if (face_cells) memcpy(face_cells, m->face, sizeof(int) * 2 * m->nf);
+  if (trans) memcpy(trans, m->trans, sizeof(double) * m->nf);
+  if (pv) memcpy(pv, m->pv, sizeof(double) * m->n);
+  if (depth) memcpy(depth, m->depth, sizeof(double) * m->n);
+  if (cell_box) memcpy(cell_box, m->cell_box, sizeof(int) * m->n);
+}
+
+void ora_pattern(const ora_model* m, int* row_ptr, int* col_idx) {
+  memcpy(row_ptr, m->row_ptr, sizeof(int) * (m->n + 1));
+  memcpy(col_idx, m->col_idx, sizeof(int) * m->nnzb);
+}
+
+void ora_conns(const ora_model* m, int* cell, double* wi, int* well) {
+  if (cell) memcpy(cell, m->conn_cell, sizeof(int) * m->nc);
+  if (wi) memcpy(wi, m->conn_wi, sizeof(double) * m->nc);
+  if (well) memcpy(well, m->conn_well, sizeof(int) * m->nc);
+}
+
+/* ------------------------------------------- cell properties (sec. 2.1.4-6) */
+typedef struct {
+  dual p;
+  dual s[3];    /* s_w, s_o, s_g */
+  dual b[3];    /* shrinkage / expansion factors */
+  dual rho[3];  /* reservoir densities */
+  dual lam[3];  /* mobilities k_r / mu */
+} props;
+
+static void cell_props(const ora_fluid* f, const double* y, int off, props* P) {
+  P->p = dvar(y[0], off + 0);
+  dual sw = dvar(y[1], off + 1);
+  dual sg = dvar(y[2], off + 2);
+  dual so = dsub(dsub(dconst(1.0), sw), sg);   /* s_w + s_o + s_g = 1 */
+  P->s[0] = sw; P->s[1] = so; P->s[2] = sg;
+  for (int a = 0; a < 3; ++a) {
+    /* constant compressibility: (1/b) db/dp = c with b(p_ref) = 1 */
+    P->b[a] = dexp(dscale(dsub(P->p, dconst(f->p_ref)), f->c[a]));
+    P->rho[a] = dscale(P->b[a], f->rho_s[a]);   /* rho = b rho_S */
+  }
+  /* Corey two-phase curves with residuals 0 except connate water */
+  double den = 1.0 - f->swc;
+  dual swn = dclamp01(ddiv(dsub(sw, dconst(f->swc)), dconst(den)));
+  dual sgn = dclamp01(ddiv(sg, dconst(den)));
+  dual son = dclamp01(ddiv(so, dconst(den)));
+  dual krw = dpow(swn, f->n_corey);
+  dual krg = dpow(sgn, f->n_corey);
+  dual krow = dpow(son, f->n_corey);
+  dual krog = dpow(son, f->n_corey);
+  /* three-phase oil by the segregation model, eq. (gwseg) */
+  dual ww = dmax0(dsub(sw, dconst(f->swc)));
+  dual wg = dmax0(sg);
+  dual wsum = dadd(ww, wg);
+  dual kro;
+  if (wsum.v > 1e-14)
+    kro = ddiv(dadd(dmul(ww, krow), dmul(wg, krog)), wsum);
+  else
+    kro = krow;
+  P->lam[0] = ddiv(krw, dconst(f->mu[0]));
+  P->lam[1] = ddiv(kro, dconst(f->mu[1]));
+  P->lam[2] = ddiv(krg, dconst(f->mu[2]));
+}
+
+void ora_accumulation(const ora_model* m, const double* y, double* acc) {
+  for (int c = 0; c < m->n; ++c) {
+    props P;
+    cell_props(&m->fl, y + 3 * c, 0, &P);
+    for (int a = 0; a < 3; ++a) acc[3 * c + a] = P.b[a].v * P.s[a].v;
+  }
+}
+
+/* Well term of one connection as duals in slots 0-2 (sec. 2.2.1):
+ * rate injector: fixed surface rate split over connections by WI share;
+ * BHP producer: q_alpha = b_alpha lambda_alpha WI (p - p_bhp)^+ . */
+static void conn_rates(const ora_model* m, int q, const double* y, dual out[3]) {
+  int w = m->conn_well[q];
+  int c = m->conn_cell[q];
+  for (int a = 0; a < 3; ++a) out[a] = dconst(0.0);
+  if (m->well_kind[w] == ORA_WELL_RATE_INJ) {
+    double wsum = 0.0;
+    for (int t = m->well_beg[w]; t < m->well_beg[w + 1]; ++t) wsum += m->conn_wi[t];
+    out[m->well_phase[w]] = dconst(-m->well_target[w] * m->conn_wi[q] / wsum);
+  } else {
+    props P;
+    cell_props(&m->fl, y + 3 * c, 0, &P);
+    dual dp = dsub(P.p, dconst(m->well_target[w]));
+    if (dp.v > 0.0) {
+      for (int a = 0; a < 3; ++a)
+        out[a] = dmul(dscale(dmul(P.b[a], P.lam[a]), m->conn_wi[q]), dp);
+    }
+  }
+}
+
+void ora_well_rates(const ora_model* m, const double* y, double* qout) {
+  memset(qout, 0, sizeof(double) * 3 * m->n);
+  for (int q = 0; q < m->nc; ++q) {
+    dual r[3];
+    conn_rates(m, q, y, r);
+    for (int a = 0; a < 3; ++a) qout[3 * m->conn_cell[q] + a] += r[a].v;
+  }
+}
+
+/* --------------------------------------- residual + Jacobian (sec. 2.1.1) */
+static void add_block(double* J, int blk, int a, const double* d, double sign) {
+  for (int v = 0; v < 3; ++v) J[9 * blk + 3 * a + v] += sign * d[v];
+}
+
+int ora_assemble(const ora_model* m, const double* y, const double* acc0, double dt, double* R,
+                 double* J) {
+  const ora_fluid* f = &m->fl;
+  memset(R, 0, sizeof(double) * 3 * m->n);
+  if (J) memset(J, 0, sizeof(double) * 9 * m->nnzb);
+  /* accumulation: PV/dt (A - A0) */
+  for (int c = 0; c < m->n; ++c) {
+    props P;
+    cell_props(f, y + 3 * c, 0, &P);
+    int dblk = J ? find_block(m, c, c) : -1;
+    for (int a = 0; a < 3; ++a) {
+      dual A = dmul(P.b[a], P.s[a]);
+      dual r = dscale(dsub(A, dconst(acc0[3 * c + a])), m->pv[c] / dt);
+      R[3 * c + a] += r.v;
+      if (J) add_block(J, dblk, a, r.d, 1.0);
+    }
+  }
+  /* connection fluxes, each face once; u_ij = -u_ji exactly */
+  for (int fc = 0; fc < m->nf; ++fc) {
+    int i = m->face[2 * fc], j = m->face[2 * fc + 1];
+    props Pi, Pj;
+    cell_props(f, y + 3 * i, 0, &Pi);
+    cell_props(f, y + 3 * j, 3, &Pj);
+    double T = m->trans[fc];
+    dual dzij = dconst(m->depth[i] - m->depth[j]);
+    int bii = -1, bij = -1, bjj = -1, bji = -1;
+    if (J) {
+      bii = find_block(m, i, i); bij = find_block(m, i, j);
+      bjj = find_block(m, j, j); bji = find_block(m, j, i);
+    }
+    for (int a = 0; a < 3; ++a) {
+      dual rho_avg = dscale(dadd(Pi.rho[a], Pj.rho[a]), 0.5);
+      dual dphi = dsub(dsub(Pi.p, Pj.p), dmul(dscale(rho_avg, f->g), dzij));
+      const props* U = (dphi.v >= 0.0) ? &Pi : &Pj;
+      dual F = dmul(dmul(U->b[a], U->lam[a]), dscale(dphi, T));
+      R[3 * i + a] += F.v;
+      R[3 * j + a] -= F.v;
+      if (J) {
+        add_block(J, bii, a, F.d, 1.0);
+        add_block(J, bij, a, F.d + 3, 1.0);
+        add_block(J, bjj, a, F.d + 3, -1.0);
+        add_block(J, bji, a, F.d, -1.0);
+      }
+    }
+  }
+  /* wells: q_alpha (outflux positive) */
+  for (int q = 0; q < m->nc; ++q) {
+    int c = m->conn_cell[q];
+    dual r[3];
+    conn_rates(m, q, y, r);
+    int dblk = J ? find_block(m, c, c) : -1;
+    for (int a = 0; a < 3; ++a) {
+      R[3 * c + a] += r[a].v;
+      if (J) add_block(J, dblk, a, r[a].d, 1.0);
+    }
+  }
+  for (int k = 0; k < 3 * m->n; ++k)
+    if (!isfinite(R[k])) return ORA_ENONFINITE;
+  return ORA_OK;
+}
+
+/* CNV: max local residual in saturation units; MB: reservoir average. */
+void ora_norms(const ora_model* m, const double* y, const double* R, double dt, double cnv[3],
+               double mb[3]) {
+  double sumR[3] = {0, 0, 0}, sumb[3] = {0, 0, 0}, pvsum = 0.0;
+  for (int a = 0; a < 3; ++a) cnv[a] = 0.0;
+  for (int c = 0; c < m->n; ++c) {
+    props P;
+    cell_props(&m->fl, y + 3 * c, 0, &P);
+    pvsum += m->pv[c];
+    for (int a = 0; a < 3; ++a) {
+      double v = dt * fabs(R[3 * c + a]) / (P.b[a].v * m->pv[c]);
+      if (v > cnv[a]) cnv[a] = v;
+      sumR[a] += R[3 * c + a];
+      sumb[a] += P.b[a].v;
+    }
+  }
+  for (int a = 0; a < 3; ++a) mb[a] = dt * fabs(sumR[a]) / ((sumb[a] / m->n) * pvsum);
+}
+
+/* ------------------------------------------------------- small dense algebra */
+/* Gauss-Jordan inverse with partial pivoting; -1 on an exactly zero pivot. */
+static int inv3(const double* A, double* X) {
+  double a[3][6];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 6; ++c) a[r][c] = (c < 3) ? A[3 * r + c] : (c - 3 == r ? 1.0 : 0.0);
+  for (int col = 0; col < 3; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 3; ++r)
+      if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
+    if (a[piv][col] == 0.0 || !isfinite(a[piv][col])) return -1;
+    if (piv != col)
+      for (int c = 0; c < 6; ++c) {
+        double t = a[col][c]; a[col][c] = a[piv][c]; a[piv][c] = t;
+      }
+    for (int r = 0; r < 3; ++r) {
+      if (r == col) continue;
+      double fct = a[r][col] / a[col][col];
+      for (int c = 0; c < 6; ++c) a[r][c] -= fct * a[col][c];
+    }
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) X[3 * r + c] = a[r][3 + c] / a[r][r];
+  return 0;
+}
+
+static void mat3_mul(const double* A, const double* B, double* C) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += A[3 * r + k] * B[3 * k + c];
+      C[3 * r + c] = s;
+    }
+}
+
+int ora_dense_solve(int n, double* A, double* b) {
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabs(A[(size_t)r * n + col]) > fabs(A[(size_t)piv * n + col])) piv = r;
+    if (A[(size_t)piv * n + col] == 0.0) return ORA_ESINGULAR;
+    if (piv != col) {
+      for (int c = 0; c < n; ++c) {
+        double t = A[(size_t)col * n + c];
+        A[(size_t)col * n + c] = A[(size_t)piv * n + c];
+        A[(size_t)piv * n + c] = t;
+      }
+      double t = b[col]; b[col] = b[piv]; b[piv] = t;
+    }
+    for (int r = col + 1; r < n; ++r) {
+      double fct = A[(size_t)r * n + col] / A[(size_t)col * n + col];
+      if (fct == 0.0) continue;
+      for (int c = col; c < n; ++c) A[(size_t)r * n + c] -= fct * A[(size_t)col * n + c];
+      b[r] -= fct * b[col];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double s = b[r];
+    for (int c = r + 1; c < n; ++c) s -= A[(size_t)r * n + c] * b[c];
+    b[r] = s / A[(size_t)r * n + r];
+  }
+  return ORA_OK;
+}
+
+/* -------------------------------------------------- block ILU(0) (sec. 2.3.1)
+ * Generic IKJ elimination restricted to the sparsity pattern of A: for each
+ * row i and each k < i in the row, L_ik = A_ik U_kk^{-1}; then every entry
+ * (i, j) with j > k that is also in row k's pattern is updated by -L_ik U_kj. */
+int ora_ilu0(const ora_model* m, const double* J, double* F) {
+  memcpy(F, J, sizeof(double) * 9 * m->nnzb);
+  double inv[9], tmp[9];
+  for (int i = 0; i < m->n; ++i) {
+    for (int q = m->row_ptr[i]; q < m->row_ptr[i + 1]; ++q) {
+      int k = m->col_idx[q];
+      if (k >= i) break;
+      int dk = find_block(m, k, k);
+      if (inv3(F + 9 * dk, inv)) return ORA_ESINGULAR;
+      mat3_mul(F + 9 * q, inv, tmp);
+      memcpy(F + 9 * q, tmp, sizeof(tmp));
+      for (int r = q + 1; r < m->row_ptr[i + 1]; ++r) {
+        int j = m->col_idx[r];
+        int kj = find_block(m, k, j);
+        if (kj < 0) continue;
+        mat3_mul(F + 9 * q, F + 9 * kj, tmp);
+        for (int e = 0; e < 9; ++e) F[9 * r + e] -= tmp[e];
+      }
+    }
+  }
+  for (int i = 0; i < m->n; ++i)
+    if (inv3(F + 9 * find_block(m, i, i), inv)) return ORA_ESINGULAR;
+  return ORA_OK;
+}
+
+/* x = (LU)^{-1} r: forward substitution with unit L, then backward with U. */
+void ora_ilu0_apply(const ora_model* m, const double* F, const double* r, double* x) {
+  double* w = (double*)malloc(sizeof(double) * 3 * m->n);
+  for (int i = 0; i < m->n; ++i) {
+    double t[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
+    for (int q = m->row_ptr[i]; q < m->row_ptr[i + 1]; ++q) {
+      int k = m->col_idx[q];
+      if (k >= i) break;
+      for (int a = 0; a < 3; ++a)
+        for (int v = 0; v < 3; ++v) t[a] -= F[9 * q + 3 * a + v] * w[3 * k + v];
+    }
+    for (int a = 0; a < 3; ++a) w[3 * i + a] = t[a];
+  }
+  for (int i = m->n - 1; i >= 0; --i) {
+    double t[3] = {w[3 * i], w[3 * i + 1], w[3 * i + 2]};
+    int dq = -1;
+    for (int q = m->row_ptr[i]; q < m->row_ptr[i + 1]; ++q) {
+      int j = m->col_idx[q];
+      if (j == i) dq = q;
+      if (j <= i) continue;
+      for (int a = 0; a < 3; ++a)
+        for (int v = 0; v < 3; ++v) t[a] -= F[9 * q + 3 * a + v] * x[3 * j + v];
+    }
+    double D[9];
+    memcpy(D, F + 9 * dq, sizeof(D));
+    ora_dense_solve(3, D, t);
+    for (int a = 0; a < 3; ++a) x[3 * i + a] = t[a];
+  }
+  free(w);
+}
+
+void ora_spmv(const ora_model* m, const double* J, const double* x, double* y) {
+  for (int i = 0; i < m->n; ++i) {
+    double t[3] = {0, 0, 0};
+    for (int q = m->row_ptr[i]; q < m->row_ptr[i + 1]; ++q) {
+      int j = m->col_idx[q];
+      for (int a = 0; a < 3; ++a)
+        for (int v = 0; v < 3; ++v) t[a] += J[9 * q + 3 * a + v] * x[3 * j + v];
+    }
+    for (int a = 0; a < 3; ++a) y[3 * i + a] = t[a];
+  }
+}
+
+/* ----------------------------------------------- BiCGStab (sec. 2.3.1)
+ * van der Vorst's stabilised BiCG with right preconditioning M = LU,
+ * x0 = 0, stopping on the 2-norm of the residual relative to ||b||. */
+static double dot(int n, const double* a, const double* b) {
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) s += a[k] * b[k];
+  return s;
+}
+
+int ora_bicgstab(const ora_model* m, const double* J, const double* F, const double* b, double* x,
+                 double rtol, int maxit, double* its_out, double* relres_out) {
+  const int N = 3 * m->n;
+  double* r = (double*)malloc(sizeof(double) * N);
+  double* rh = (double*)malloc(sizeof(double) * N);
+  double* p = (double*)calloc(N, sizeof(double));
+  double* v = (double*)calloc(N, sizeof(double));
+  double* ph = (double*)malloc(sizeof(double) * N);
+  double* s = (double*)malloc(sizeof(double) * N);
+  double* sh = (double*)malloc(sizeof(double) * N);
+  double* t = (double*)malloc(sizeof(double) * N);
+  for (int k = 0; k < N; ++k) { x[k] = 0.0; r[k] = b[k]; rh[k] = b[k]; }
+  double bnorm = sqrt(dot(N, b, b));
+  double rho0 = 1.0, alpha = 1.0, omega = 1.0;
+  int status = ORA_ENOTCONV;
+  double its = 0.0, relres = 1.0;
+  if (bnorm == 0.0) { status = ORA_OK; relres = 0.0; goto done; }
+  for (int it = 1; it <= maxit; ++it) {
+    double rho = dot(N, rh, r);
+    if (fabs(rho) < 1e-300) { status = ORA_EBREAKDOWN; break; }
+    double beta = (rho / rho0) * (alpha / omega);
+    for (int k = 0; k < N; ++k) p[k] = r[k] + beta * (p[k] - omega * v[k]);
+    ora_ilu0_apply(m, F, p, ph);
+    ora_spmv(m, J, ph, v);
+    double rv = dot(N, rh, v);
+    if (rv == 0.0) { status = ORA_EBREAKDOWN; break; }
+    alpha = rho / rv;
+    for (int k = 0; k < N; ++k) s[k] = r[k] - alpha * v[k];
+    double snorm = sqrt(dot(N, s, s));
+    if (snorm <= rtol * bnorm) {
+      for (int k = 0; k < N; ++k) x[k] += alpha * ph[k];
+      its = it - 0.5; relres = snorm / bnorm; status = ORA_OK;
+      break;
+    }
+    ora_ilu0_apply(m, F, s, sh);
+    ora_spmv(m, J, sh, t);
+    double tt = dot(N, t, t);
+    if (tt == 0.0) { status = ORA_EBREAKDOWN; break; }
+    omega = dot(N, t, s) / tt;
+    for (int k = 0; k < N; ++k) {
+      x[k] += alpha * ph[k] + omega * sh[k];
+      r[k] = s[k] - omega * t[k];
+    }
+    double rnorm = sqrt(dot(N, r, r));
+    its = it; relres = rnorm / bnorm;
+    if (rnorm <= rtol * bnorm) { status = ORA_OK; break; }
+    if (omega == 0.0) { status = ORA_EBREAKDOWN; break; }
+    rho0 = rho;
+  }
+done:
+  if (its_out) *its_out = its;
+  if (relres_out) *relres_out = relres;
+  free(r); free(rh); free(p); free(v); free(ph); free(s); free(sh); free(t);
+  return status;
+}
+
+/* ------------------------------------------------ Newton (sec. 2.3, eq. linsystem) */
+static int all_finite(int n, const double* a) {
+  for (int k = 0; k < n; ++k)
+    if (!isfinite(a[k])) return 0;
+  return 1;
+}
+
+int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double dt,
+                    const ora_opts* o, ora_report* rep) {
+  const int n = m->n, N = 3 * n;
+  double* acc0 = (double*)malloc(sizeof(double) * N);
+  double* R = (double*)malloc(sizeof(double) * N);
+  double* J = (double*)malloc(sizeof(double) * 9 * m->nnzb);
+  double* F = (double*)malloc(sizeof(double) * 9 * m->nnzb);
+  double* b = (double*)malloc(sizeof(double) * N);
+  double* dx = (double*)malloc(sizeof(double) * N);
+  memset(rep, 0, sizeof(*rep));
+  ora_accumulation(m, y_prev, acc0);
+  int status = ORA_ENOTCONV;
+  for (int it = 0;; ++it) {
+    double t0 = now_s();
+    int st = ora_assemble(m, y, acc0, dt, R, J);
+    rep->t_assemble += now_s() - t0;
+    if (st != ORA_OK) { status = st; break; }
+    ora_norms(m, y, R, dt, rep->cnv, rep->mb);
+    double cmax = fmax(rep->cnv[0], fmax(rep->cnv[1], rep->cnv[2]));
+    double mmax = fmax(rep->mb[0], fmax(rep->mb[1], rep->mb[2]));
+    if (cmax <= o->tol_cnv && mmax <= o->tol_mb) { status = ORA_OK; break; }
+    if (it >= o->max_newton) { status = ORA_ENOTCONV; break; }
+    t0 = now_s();
+    st = ora_ilu0(m, J, F);
+    rep->t_factor += now_s() - t0;
+    if (st != ORA_OK) { status = st; break; }
+    for (int k = 0; k < N; ++k) b[k] = -R[k];
+    double its = 0.0, rr = 0.0;
+    t0 = now_s();
+    st = ora_bicgstab(m, J, F, b, dx, o->lin_rtol, o->lin_maxit, &its, &rr);
+    rep->t_krylov += now_s() - t0;
+    rep->lin_its += its;
+    if (st != ORA_OK) { status = st; break; }
+    t0 = now_s();
+    /* Appleyard-type chop: bound |dp| by dp_max_rel |p|, scale the saturation
+     * update of a cell so that its largest component is at most ds_max. */
+    for (int c = 0; c < n; ++c) {
+      double dp = dx[3 * c], lim = o->dp_max_rel * fabs(y[3 * c]);
+      if (dp > lim) dp = lim;
+      if (dp < -lim) dp = -lim;
+      double dsw = dx[3 * c + 1], dsg = dx[3 * c + 2];
+      double mx = fmax(fabs(dsw), fabs(dsg));
+      if (mx > o->ds_max) {
+        double sc = o->ds_max / mx;
+        dsw *= sc;
+        dsg *= sc;
+      }
+      y[3 * c] += dp;
+      y[3 * c + 1] += dsw;
+      y[3 * c + 2] += dsg;
+    }
+    rep->t_update += now_s() - t0;
+    rep->newton_its++;
+    rep->cell_newton_its += (double)n;
+    if (!all_finite(N, y)) { status = ORA_ENONFINITE; break; }
+  }
+  rep->status = status;
+  free(acc0); free(R); free(J); free(F); free(b); free(dx);
+  return status;
+}
+
+static void mass_error(const ora_model* m, const double* y_old, const double* y_new, double dt,
+                       double err[3]) {
+  const int n = m->n;
+  double* a0 = (double*)malloc(sizeof(double) * 3 * n);
+  double* a1 = (double*)malloc(sizeof(double) * 3 * n);
+  double* q = (double*)malloc(sizeof(double) * 3 * n);
+  ora_accumulation(m, y_old, a0);
+  ora_accumulation(m, y_new, a1);
+  ora_well_rates(m, y_new, q);
+  for (int a = 0; a < 3; ++a) {
+    double M0 = 0.0, M1 = 0.0, Q = 0.0, bsum = 0.0, pvs = 0.0;
+    for (int c = 0; c < n; ++c) {
+      M0 += m->pv[c] * a0[3 * c + a];
+      M1 += m->pv[c] * a1[3 * c + a];
+      Q += q[3 * c + a];
+      props P;
+      cell_props(&m->fl, y_new + 3 * c, 0, &P);
+      bsum += P.b[a].v;
+      pvs += m->pv[c];
+    }
+    err[a] = fabs(M1 - M0 + dt * Q) / ((bsum / n) * pvs);
+  }
+  free(a0); free(a1); free(q);
+}
+
+int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts* o,
+                ora_report* rep) {
+  const int N = 3 * m->n;
+  double* yn = (double*)malloc(sizeof(double) * N);
+  memcpy(yn, y, sizeof(double) * N);
+  memset(rep, 0, sizeof(*rep));
+  double t = 0.0, dt_try = dt_report;
+  int status = ORA_OK;
+  while (dt_report - t > 1e-9 * dt_report) {
+    double dt = fmin(dt_try, dt_report - t);
+    ora_report r1;
+    int st = ora_newton_step(m, y, yn, dt, o, &r1);
+    rep->newton_its += r1.newton_its;
+    rep->lin_its += r1.lin_its;
+    rep->cell_newton_its += r1.cell_newton_its;
+    rep->t_assemble += r1.t_assemble;
+    rep->t_factor += r1.t_factor;
+    rep->t_krylov += r1.t_krylov;
+    rep->t_update += r1.t_update;
+    if (st == ORA_OK) {
+      double e[3];
+      mass_error(m, yn, y, dt, e);
+      for (int a = 0; a < 3; ++a) {
+        if (e[a] > rep->mass_err[a]) rep->mass_err[a] = e[a];
+        rep->cnv[a] = r1.cnv[a];
+        rep->mb[a] = r1.mb[a];
+      }
+      memcpy(yn, y, sizeof(double) * N);
+      t += dt;
+      rep->substeps++;
+    } else {
+      memcpy(y, yn, sizeof(double) * N);
+      dt_try = 0.5 * dt;
+      rep->cuts++;
+      if (rep->cuts > o->max_cuts) { status = st; break; }
+    }
+  }
+  rep->status = status;
+  free(yn);
+  return status;
+}

@@ -1,0 +1,142 @@
+/*
+ * oracle.h -- plain, slow, FP64 CPU reference for the fully implicit
+ * three-phase TPFA Newton path of the Open Porous Media Flow paper
+ * (arXiv 1910.06059).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the GPU library includes, links or
+ * calls this code; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source with the GPU path: its own
+ * grid and transmissibility code, its own forward-mode AD type, a generic
+ * IKJ block ILU(0), a textbook BiCGStab and its own Newton loop.
+ *
+ * Paper references (section / equation labels of the paper):
+ *   residual            sec. 2.1.1 "Discrete equations", eq. (materialbalance)
+ *   fluxes, upwinding   sec. 2.1.1, eqs. (flux1), (head) and the upwind rule
+ *   relative perm.      sec. 2.1.5, eq. (gwseg)
+ *   PVT                 sec. 2.1.6 (constant compressibility)
+ *   wells               sec. 2.2.1, eq. (wellinflow)
+ *   Newton / chop       sec. 2.3, eq. (linsystem)
+ *   CNV / MB criteria   sec. 2.3 (tolerance-cnv / tolerance-mb)
+ *   ILU0 + BiCGStab     sec. 2.3.1
+ *   forward-mode AD     sec. 2.4.1
+ *   transmissibility    appendix B
+ *
+ * Units are SI throughout.  Phase / component order is (water, oil, gas);
+ * the primary variables per cell are (p_o, s_w, s_g).  Cell numbering is the
+ * natural order of active cells, c = i + nx*(j + ny*k) restricted to the mask.
+ *
+ * Parity status of each function (what pins it) is listed in the header of
+ * oracle.c.
+ */
+#ifndef ORACLE_H
+#define ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORA_OK 0
+#define ORA_EINVAL (-1)
+#define ORA_ESINGULAR (-2)
+#define ORA_ENOTCONV (-3)
+#define ORA_EBREAKDOWN (-4)
+#define ORA_ENONFINITE (-5)
+
+#define ORA_WELL_RATE_INJ 0
+#define ORA_WELL_BHP_PROD 1
+
+typedef struct ora_fluid {
+  double rho_s[3];   /* surface densities (w, o, g) [kg/m^3]              */
+  double c[3];       /* compressibilities [1/Pa]                           */
+  double p_ref;      /* reference pressure of b = exp(c (p - p_ref)) [Pa]  */
+  double mu[3];      /* viscosities [Pa s]                                 */
+  double swc;        /* connate water saturation                           */
+  double n_corey;    /* Corey exponent of every two-phase curve            */
+  double g;          /* gravitational acceleration [m/s^2]                 */
+} ora_fluid;
+
+typedef struct ora_opts {
+  double tol_cnv;     /* max local scaled residual                          */
+  double tol_mb;      /* reservoir-average scaled residual                  */
+  double ds_max;      /* Appleyard chop: max saturation change / iteration  */
+  double dp_max_rel;  /* Appleyard chop: max |dp| / |p| per iteration       */
+  double lin_rtol;    /* BiCGStab relative residual tolerance               */
+  int max_newton;     /* max linear solves per time step                    */
+  int lin_maxit;      /* BiCGStab iteration cap                             */
+  int max_cuts;       /* time-step halvings allowed per report step         */
+} ora_opts;
+
+typedef struct ora_report {
+  int status;           /* ORA_OK or an error code                          */
+  int newton_its;       /* linear solves (summed over substeps in advance)  */
+  int substeps;         /* accepted substeps                                */
+  int cuts;             /* time-step halvings                               */
+  double lin_its;       /* BiCGStab iterations (half iterations count 0.5)  */
+  double cnv[3], mb[3]; /* final norms of the last accepted substep         */
+  double mass_err[3];   /* max over substeps of the mass-balance error      */
+  double t_assemble, t_factor, t_krylov, t_update;   /* seconds              */
+  double cell_newton_its;   /* sum over Newton iterations of active cells   */
+} ora_report;
+
+typedef struct ora_model ora_model;
+
+/* Build the discrete model of a (masked) Cartesian box.  All arrays are host
+ * memory and are copied.  3-D fields are [nz][ny][nx] in C order.  Wells:
+ * conn_ijk holds (i, j, k) triples of all wells' connections in well order. */
+ora_model* ora_create(int nx, int ny, int nz, double dx, double dy, const double* dz,
+                      const double* perm_h, double kv_kh, const double* poro,
+                      const unsigned char* mask, const ora_fluid* fluid, int n_wells,
+                      const int* well_kind, const int* well_phase, const double* well_target,
+                      const double* well_rw, const int* well_nconn, const int* conn_ijk);
+void ora_destroy(ora_model* m);
+
+int ora_n_cells(const ora_model* m);
+int ora_n_faces(const ora_model* m);
+int ora_nnzb(const ora_model* m);
+int ora_n_conns(const ora_model* m);
+
+/* Geometry (appendix B): face_cells [nf][2] (i<j), trans [nf], pore volume and
+ * cell-centre depth [n], box index of each active cell [n]. */
+void ora_geometry(const ora_model* m, int* face_cells, double* trans, double* pv,
+                  double* depth, int* cell_box);
+/* Block-CSR pattern of the Jacobian: row_ptr [n+1], col_idx [nnzb], sorted. */
+void ora_pattern(const ora_model* m, int* row_ptr, int* col_idx);
+/* Well connections: active cell, well index, owning well [n_conns]. */
+void ora_conns(const ora_model* m, int* cell, double* wi, int* well);
+
+/* A_alpha = b_alpha s_alpha per cell (m_phi = 1): acc [n][3]. */
+void ora_accumulation(const ora_model* m, const double* y, double* acc);
+/* Surface well rates q [n][3] (outflux positive) at state y. */
+void ora_well_rates(const ora_model* m, const double* y, double* q);
+/* Residual R [n][3] and, if J != NULL, Jacobian blocks J [nnzb][3][3]
+ * (row = equation w,o,g; column = variable p,s_w,s_g). */
+int ora_assemble(const ora_model* m, const double* y, const double* acc0, double dt,
+                 double* R, double* J);
+/* CNV_alpha and MB_alpha of a residual. */
+void ora_norms(const ora_model* m, const double* y, const double* R, double dt,
+               double cnv[3], double mb[3]);
+
+/* Block ILU(0), generic IKJ form: F [nnzb][3][3] holds L (unit diagonal
+ * implied) below and U (with diagonal) on/above the block diagonal. */
+int ora_ilu0(const ora_model* m, const double* J, double* F);
+void ora_ilu0_apply(const ora_model* m, const double* F, const double* r, double* x);
+void ora_spmv(const ora_model* m, const double* J, const double* x, double* y);
+/* Right-preconditioned BiCGStab, x0 = 0.  its counts half iterations as 0.5. */
+int ora_bicgstab(const ora_model* m, const double* J, const double* F, const double* b,
+                 double* x, double rtol, int maxit, double* its, double* relres);
+
+/* One implicit Euler step of length dt: Newton from the guess in y (in/out),
+ * y_prev is the state at the start of the step.  No time-step cutting. */
+int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double dt,
+                    const ora_opts* o, ora_report* rep);
+/* Advance y over one report step of length dt with halving on failure. */
+int ora_advance(const ora_model* m, double* y, double dt, const ora_opts* o, ora_report* rep);
+
+/* Dense LU with partial pivoting: solves A x = b in place (A [n][n] row-major
+ * is overwritten).  Returns ORA_ESINGULAR on a zero pivot. */
+int ora_dense_solve(int n, double* A, double* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,83 @@
+"""Planted mistakes in the oracle must be caught by its pins (CPU only).
+
+Each mutant is a copy of ``oracle/oracle.c`` with one plausible slip (a
+dropped term, a wrong sign, a swapped index or operand) compiled into a
+temporary library; at least one pin of ``oracle_pins.py`` has to fail on it.
+This shows the pins constrain every part of the oracle, not just re-run it.
+"""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+from oracle_pins import ALL_PINS
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = [
+    ("gravity_sign", "dsub(dsub(Pi.p, Pj.p), dmul(dscale(rho_avg, f->g), dzij))",
+     "dadd(dsub(Pi.p, Pj.p), dmul(dscale(rho_avg, f->g), dzij))"),
+    ("density_not_averaged", "dscale(dadd(Pi.rho[a], Pj.rho[a]), 0.5)", "Pi.rho[a]"),
+    ("upwind_reversed", "(dphi.v >= 0.0) ? &Pi : &Pj", "(dphi.v >= 0.0) ? &Pj : &Pi"),
+    ("flux_not_antisymmetric", "R[3 * j + a] -= F.v;", "R[3 * j + a] += F.v;"),
+    ("offdiag_block_sign", "add_block(J, bij, a, F.d + 3, 1.0);", "add_block(J, bij, a, F.d + 3, -1.0);"),
+    ("neighbour_block_swapped", "add_block(J, bji, a, F.d, -1.0);", "add_block(J, bji, a, F.d + 3, -1.0);"),
+    ("arithmetic_mean_trans", "tij * tji / (tij + tji)", "0.5 * (tij + tji)"),
+    ("full_cell_half_trans", "return area * num / den;", "return 0.5 * area * num / den;"),
+    ("linearised_b", "P->b[a] = dexp(dscale(dsub(P->p, dconst(f->p_ref)), f->c[a]));",
+     "P->b[a] = dadd(dconst(1.0), dscale(dsub(P->p, dconst(f->p_ref)), f->c[a]));"),
+    ("gwseg_weight_sum", "dual wsum = dadd(ww, wg);", "dual wsum = dadd(ww, ww);"),
+    ("corey_linear", "dual krw = dpow(swn, f->n_corey);", "dual krw = dpow(swn, 1.0);"),
+    ("gas_relperm_scaling", "dual sgn = dclamp01(ddiv(sg, dconst(den)));", "dual sgn = dclamp01(sg);"),
+    ("oil_sat_sign", "dual so = dsub(dsub(dconst(1.0), sw), sg);", "dual so = dadd(dsub(dconst(1.0), sw), sg);"),
+    ("quotient_rule", "(a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v)", "(a.d[i] * b.v + a.v * b.d[i]) / (b.v * b.v)"),
+    ("accumulation_deriv_dropped", "      if (J) add_block(J, dblk, a, r.d, 1.0);\n    }\n  }\n  /* connection",
+     "    }\n  }\n  /* connection"),
+    ("ilu_transposed_operand", "mat3_mul(F + 9 * q, inv, tmp);", "mat3_mul(inv, F + 9 * q, tmp);"),
+    ("ilu_update_sign", "F[9 * r + e] -= tmp[e];", "F[9 * r + e] += tmp[e];"),
+    ("ilu_forward_uses_rhs", "t[a] -= F[9 * q + 3 * a + v] * w[3 * k + v];",
+     "t[a] -= F[9 * q + 3 * a + v] * r[3 * k + v];"),
+    ("bicgstab_direction", "p[k] = r[k] + beta * (p[k] - omega * v[k]);",
+     "p[k] = r[k] + beta * (p[k] + omega * v[k]);"),
+    ("producer_drawdown_sign", "dual dp = dsub(P.p, dconst(m->well_target[w]));",
+     "dual dp = dsub(dconst(m->well_target[w]), P.p);"),
+    ("injector_sign", "dconst(-m->well_target[w] * m->conn_wi[q] / wsum)",
+     "dconst(m->well_target[w] * m->conn_wi[q] / wsum)"),
+    ("cnv_without_b", "dt * fabs(R[3 * c + a]) / (P.b[a].v * m->pv[c])", "dt * fabs(R[3 * c + a]) / m->pv[c]"),
+    ("depth_top_not_centre", "m->depth[c] = layer_top(m, k) + 0.5 * dz[k];", "m->depth[c] = layer_top(m, k);"),
+    ("kv_not_scaled", "m->kv[c] = kv_kh * perm_h[b];", "m->kv[c] = perm_h[b];"),
+    ("peaceman_radius", "double ro = 0.14 * sqrt(dx * dx + dy * dy);", "double ro = 0.2 * dx;"),
+    ("chop_not_applied_to_dp", "y[3 * c] += dp;", "y[3 * c] += 0.9 * dp;"),
+]
+
+
+@pytest.fixture(scope="module")
+def mutant_dir(tmp_path_factory):
+    return tmp_path_factory.mktemp("oracle_mutants")
+
+
+def _build(mdir, name, old, new):
+    src = open(os.path.join(ROOT, "oracle", "oracle.c")).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} must occur exactly once"
+    d = os.path.join(str(mdir), name)
+    os.makedirs(d, exist_ok=True)
+    shutil.copy(os.path.join(ROOT, "oracle", "oracle.h"), d)
+    with open(os.path.join(d, "oracle.c"), "w") as fh:
+        fh.write(src.replace(old, new))
+    so = os.path.join(d, "liboracle_mut.so")
+    subprocess.run(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", so,
+                    os.path.join(d, "oracle.c"), "-lm"], check=True)
+    return so
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(mutant_dir, name, old, new):
+    so = _build(mutant_dir, name, old, new)
+    caught = []
+    for pin in ALL_PINS:
+        try:
+            pin(lib_path=so)
+        except Exception as e:   # an assertion, a solver failure or a NaN all count
+            caught.append(f"{pin.__name__}: {type(e).__name__}")
+    assert caught, f"planted mistake '{name}' passed every pin"
