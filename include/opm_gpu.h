@@ -1,0 +1,310 @@
+/*
+ * opm_gpu.h -- C ABI of the MI355X (gfx950) Newton linearisation and solve
+ * of the fully implicit three-phase black-oil equations of the Open Porous
+ * Media Flow paper (arXiv 1910.06059), immiscible subset.
+ *
+ * The discrete problem (paper sec. 2.1.1, eq. materialbalance) is, per cell
+ * i and component alpha in (water, oil, gas):
+ *
+ *   R_alpha,i = PV_i/dt (A_alpha,i - A0_alpha,i) + sum_{j in C(i)} u_alpha,ij + q_alpha,i = 0
+ *
+ * with A_alpha = b_alpha s_alpha (m_phi = 1), TPFA fluxes
+ * u_alpha,ij = (b_alpha lambda_alpha)_U T_ij dPhi_alpha,ij (eqs. flux1, head;
+ * U the upwind cell of dPhi), primary variables y_i = (p_o, s_w, s_g)
+ * (sec. 2.1.2), capillary pressure zero, constant-compressibility PVT
+ * b = exp(c (p - p_ref)) (sec. 2.1.6), Corey two-phase curves combined by the
+ * segregation model for oil (eq. gwseg), and wells as cell source terms
+ * (eq. wellinflow with fixed BHP, or a fixed surface-rate injector).
+ * Newton (sec. 2.3, eq. linsystem) solves J dy = -R with block-ILU(0)
+ * preconditioned BiCGStab (sec. 2.3.1) on a 3x3-block CSR Jacobian.
+ *
+ * Conventions shared by every entry point:
+ *  - Units are SI.  Vectors indexed by cell are [n_cells][3] row-major:
+ *    state (p [Pa], s_w, s_g), residual (water, oil, gas) [surface m^3/s].
+ *  - Jacobian blocks J[nnzb][3][3]: row = equation (w, o, g), column =
+ *    variable (p, s_w, s_g), row-major; block q of row i sits at column
+ *    col_idx[q], with row_ptr/col_idx the block-CSR pattern of opm_topology.
+ *  - "device" pointers are HIP device memory owned by the caller (the Python
+ *    binding passes torch CUDA tensors); "host" pointers are host memory.
+ *    The library keeps no pointer after a call returns and never allocates
+ *    device memory: every buffer, workspaces included, comes from the caller.
+ *  - stream is a hipStream_t (NULL = default stream).  Calls are asynchronous
+ *    on that stream unless their comment says that they synchronise.
+ *  - Every entry point returns an int status: OPM_OK (0) or a negative code;
+ *    opm_strerror names it.  No exception crosses the ABI.  Invalid arguments
+ *    are reported as OPM_EINVAL before any device work is queued.
+ */
+#ifndef OPM_GPU_H
+#define OPM_GPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OPM_OK 0
+#define OPM_EINVAL (-1)        /* bad argument or unsupported pattern        */
+#define OPM_ESINGULAR (-2)     /* zero / non-finite 3x3 pivot in ILU(0)       */
+#define OPM_ENOTCONV (-3)      /* Newton or BiCGStab did not converge        */
+#define OPM_EBREAKDOWN (-4)    /* BiCGStab breakdown (rho, <r^,v>, omega, <t,t>) */
+#define OPM_ENONFINITE (-5)    /* NaN or Inf in residual or state            */
+#define OPM_EHIP (-6)          /* a HIP runtime call failed                   */
+
+#define OPM_WELL_RATE_INJ 0    /* fixed surface rate of one component          */
+#define OPM_WELL_BHP_PROD 1    /* bottom-hole pressure producer                */
+
+#define OPM_PREC_FP64 0        /* ILU(0) factors and sweeps in FP64            */
+#define OPM_PREC_MIXED 1       /* ILU(0) factors stored and swept in FP32      */
+
+/* Fluid and rock-fluid constants (phase order water, oil, gas). */
+typedef struct opm_fluid {
+  double rho_s[3];   /* surface densities [kg/m^3]                          */
+  double c[3];       /* compressibilities [1/Pa]: b = exp(c (p - p_ref))   */
+  double p_ref;      /* reference pressure [Pa]                             */
+  double mu[3];      /* viscosities [Pa s]                                  */
+  double swc;        /* connate water saturation of the Corey curves        */
+  double n_corey;    /* Corey exponent of every two-phase curve (>= 1)      */
+  double g;          /* gravitational acceleration [m/s^2], depth positive down */
+} opm_fluid;
+
+/* Connectivity of a masked nx*ny*nz Cartesian box (host arrays, filled by
+ * opm_topology_build, sized from opm_topology_count).  Active cells are
+ * numbered in natural order c = i + nx (j + ny k) restricted to the mask;
+ * faces are the (+x, +y, +z) neighbours of each active cell, so
+ * face_cells[f][0] < face_cells[f][1].  The level schedule lists rows by
+ * level of the lower-triangular dependency graph of ILU(0):
+ * level(i) = 1 + max level(lower neighbours), rows of one level in ascending
+ * order; it is the order in which ILU(0) factorisation and triangular sweeps
+ * may proceed in parallel. */
+typedef struct opm_topology {
+  int32_t* cell_box;    /* [n_cells]  box index of each active cell            */
+  int32_t* face_cells;  /* [n_faces][2] lower and upper cell                   */
+  int32_t* face_dir;    /* [n_faces]  0 = x, 1 = y, 2 = z                      */
+  int32_t* row_ptr;     /* [n_cells+1]                                          */
+  int32_t* col_idx;     /* [nnzb], nnzb = n_cells + 2 n_faces, sorted per row   */
+  int32_t* blk_face;    /* [nnzb] face of an off-diagonal block, -1 on diagonal */
+  int32_t* diag_pos;    /* [n_cells] position of the diagonal block            */
+  int32_t* level_ptr;   /* [n_cells+1] level l holds positions level_ptr[l..l+1) */
+  int32_t* perm;        /* [n_cells] level-order position -> cell               */
+  int32_t* iperm;       /* [n_cells] cell -> level-order position               */
+  int32_t* lo_blk;      /* [n_cells][3] by position: block (i,k) of each lower
+                           neighbour k (-1 if absent)                           */
+  int32_t* lo_tblk;     /* [n_cells][3] the transposed block (k,i)              */
+  int32_t* lo_pos;      /* [n_cells][3] level-order position of k               */
+  int32_t* up_blk;      /* [n_cells][3] block (i,j) of each upper neighbour j   */
+  int32_t* up_pos;      /* [n_cells][3] level-order position of j               */
+  int32_t n_levels;     /* out                                                  */
+  int32_t max_level;    /* out: largest number of rows in one level             */
+} opm_topology;
+
+/* Count active cells and faces (host, synchronous).  mask may be NULL (all
+ * cells active).  Returns OPM_EINVAL for non-positive sizes. */
+int opm_topology_count(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask,
+                       int32_t* n_cells, int32_t* n_faces);
+/* Fill an opm_topology whose arrays the caller sized from opm_topology_count
+ * (host, synchronous; paper sec. 2.1.1 connection set C(i), sec. 2.3.1 block
+ * matrix storage, ILU(0) dependency levels). */
+int opm_topology_build(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask,
+                       opm_topology* topo);
+
+/* Transmissibility, pore volume and depth (appendix B; sec. 2.1.4), device:
+ * T_ij = t_ij t_ji / (t_ij + t_ji) with half-transmissibilities
+ * t = |F| k / (d/2) of the axis-aligned cells, k = perm_h for x/y faces and
+ * kv_kh * perm_h for z faces; PV = poro dx dy dz_k; depth = cell centre.
+ * perm_h, poro: [n_cells] (active-cell order); dz: [nz]; cell_box,
+ * face_cells, face_dir from opm_topology (device copies).  Outputs trans
+ * [n_faces], pore_vol [n_cells], depth [n_cells]. */
+int opm_geometry(int32_t nx, int32_t ny, int32_t nz, double dx, double dy, const double* dz,
+                 const double* perm_h, double kv_kh, const double* poro, int32_t n_cells,
+                 int32_t n_faces, const int32_t* cell_box, const int32_t* face_cells,
+                 const int32_t* face_dir, double* trans, double* pore_vol, double* depth,
+                 void* stream);
+
+/* Well connections (sec. 2.2.1, eq. wellinflow), device.  Inputs per well
+ * [n_wells]: kind, injected phase, target (surface rate [m^3/s] for
+ * OPM_WELL_RATE_INJ, BHP [Pa] for OPM_WELL_BHP_PROD) and wellbore radius rw;
+ * per connection [n_conns]: active cell and owning well.  Outputs per
+ * connection: the Peaceman index wi = 2 pi k_h dz / ln(0.14 sqrt(dx^2+dy^2)
+ * / rw) (skin 0), the fixed injection source rate = -target wi / sum(wi of
+ * the well) (0 for producers), and the well's kind, phase and BHP target
+ * (0 for injectors).  perm_h [n_cells], dz [nz], cell_box as above. */
+int opm_well_index(int32_t nx, int32_t ny, double dx, double dy, const double* dz,
+                   const double* perm_h, const int32_t* cell_box, int32_t n_wells,
+                   const int32_t* well_kind, const int32_t* well_phase,
+                   const double* well_target, const double* well_rw, int32_t n_conns,
+                   const int32_t* conn_cell, const int32_t* conn_well, double* conn_wi,
+                   double* conn_rate, int32_t* conn_kind, int32_t* conn_phase,
+                   double* conn_bhp, void* stream);
+
+/* Group well connections by cell (host, synchronous): cell_conn_ptr
+ * [n_cells+1] and cell_conn [n_conns] list the connections of each cell in
+ * ascending connection order.  conn_cell [n_conns] (host).  OPM_EINVAL if a
+ * cell index is out of range. */
+int opm_well_groups(int32_t n_cells, int32_t n_conns, const int32_t* conn_cell,
+                    int32_t* cell_conn_ptr, int32_t* cell_conn);
+
+/* The discrete problem handed to the path (device pointers unless noted).
+ * Well connections must be grouped by cell: cell_conn_ptr[n_cells+1] gives
+ * the connections of cell i as conn ids cell_conn[cell_conn_ptr[i] ..]. */
+typedef struct opm_problem {
+  int32_t n_cells, n_faces, nnzb, n_levels, max_level;
+  int32_t n_conns;
+  const double* trans;          /* [n_faces]                                  */
+  const double* pore_vol;       /* [n_cells]                                  */
+  const double* depth;          /* [n_cells]                                  */
+  const int32_t* row_ptr;       /* [n_cells+1]                                */
+  const int32_t* col_idx;       /* [nnzb]                                     */
+  const int32_t* blk_face;      /* [nnzb]                                     */
+  const int32_t* face_cells;    /* [n_faces][2]                               */
+  const int32_t* diag_pos;      /* [n_cells]                                  */
+  const int32_t* level_ptr;     /* [n_levels+1] device copy                   */
+  const int32_t* level_ptr_h;   /* [n_levels+1] HOST copy (launch schedule)   */
+  const int32_t* perm;          /* [n_cells]                                  */
+  const int32_t* iperm;         /* [n_cells]                                  */
+  const int32_t* lo_blk;        /* [n_cells][3]                               */
+  const int32_t* lo_tblk;       /* [n_cells][3]                               */
+  const int32_t* lo_pos;        /* [n_cells][3]                               */
+  const int32_t* up_blk;        /* [n_cells][3]                               */
+  const int32_t* up_pos;        /* [n_cells][3]                               */
+  const int32_t* cell_conn_ptr; /* [n_cells+1]                                */
+  const int32_t* cell_conn;     /* [n_conns]                                  */
+  const int32_t* conn_kind;     /* [n_conns] OPM_WELL_* of the owning well    */
+  const int32_t* conn_phase;    /* [n_conns] injected component               */
+  const double* conn_wi;        /* [n_conns]                                  */
+  const double* conn_rate;      /* [n_conns] fixed source (injectors)         */
+  const double* conn_bhp;       /* [n_conns] BHP target (producers)           */
+  opm_fluid fluid;
+} opm_problem;
+
+/* Library set-up: checks that the current device is a gfx950 (MI355X) and
+ * that its kernels load.  Call once per process and device before any other
+ * device entry point (synchronous); returns OPM_EHIP otherwise. */
+int opm_init(void);
+
+/* ---------------------------------------------------------- hot path ---- */
+
+/* A0 = b(p) s per cell at the start of a time step (eq. acc): y [n][3] ->
+ * acc0 [n][3] (device). */
+int opm_accumulation(const opm_problem* pb, const double* y, double* acc0, void* stream);
+
+/* Size in bytes of the device buffer `norms` of opm_assemble. */
+size_t opm_norms_bytes(const opm_problem* pb);
+
+/* Residual and Jacobian by forward-mode AD (sec. 2.4.1-2.4.2; eqs.
+ * materialbalance, flux1, head, gwseg, wellinflow).  y, acc0: [n][3]; R:
+ * [n][3] out; J: [nnzb][3][3] out (may be NULL for the residual only).
+ * norms (may be NULL): device buffer of opm_norms_bytes; its first 8
+ * doubles receive CNV_w, CNV_o, CNV_g, MB_w, MB_o, MB_g, max CNV, max MB,
+ * where CNV_a = dt max_i |R_a,i| / (b_a(p_i) PV_i) and
+ * MB_a = dt |sum_i R_a,i| / (mean_i b_a(p_i) sum_i PV_i) (sec. 2.3,
+ * tolerance-cnv / tolerance-mb); the rest holds per-workgroup partials.
+ * All device pointers. */
+int opm_assemble(const opm_problem* pb, const double* y, const double* acc0, double dt,
+                 double* R, double* J, double* norms, void* stream);
+
+/* Size in bytes of the ILU(0) factor storage for a precision
+ * (OPM_PREC_FP64 or OPM_PREC_MIXED). */
+size_t opm_ilu0_bytes(const opm_problem* pb, int precision);
+
+/* Block ILU(0) of J (sec. 2.3.1) into ilu (device, opm_ilu0_bytes): the
+ * inverse pivot blocks D_i^{-1} with D_i = A_ii - sum_{k<i} A_ik D_k^{-1} A_ki
+ * (exact ILU(0) for a pattern without triangles, which the 7-point TPFA
+ * stencil is) and level-ordered copies of the off-diagonal blocks, in FP64 or
+ * FP32.  status (device int, may be NULL) receives OPM_ESINGULAR on a zero or
+ * non-finite pivot. */
+int opm_ilu0_factor(const opm_problem* pb, const double* J, void* ilu, int precision,
+                    int32_t* status, void* stream);
+
+/* x = (LU)^{-1} r with the factors of opm_ilu0_factor (device [n][3]). */
+int opm_ilu0_apply(const opm_problem* pb, const void* ilu, int precision, const double* r,
+                   double* x, void* stream);
+
+/* y = J x (device [n][3]). */
+int opm_spmv(const opm_problem* pb, const double* J, const double* x, double* y, void* stream);
+
+/* Report of one linear solve. */
+typedef struct opm_solve_report {
+  int32_t status;     /* OPM_OK, OPM_ENOTCONV or OPM_EBREAKDOWN             */
+  int32_t half;       /* 1 if it stopped after the first half of an iteration */
+  int32_t its;        /* iterations started                                  */
+  int32_t pad;
+  double rel_res;     /* ||r|| / ||b|| at exit                               */
+} opm_solve_report;
+
+/* Size in bytes of the Krylov workspace (device). */
+size_t opm_krylov_bytes(const opm_problem* pb);
+
+/* Right-preconditioned BiCGStab (sec. 2.3.1), x0 = 0, stops when
+ * ||r||_2 <= rtol ||b||_2 or after maxit iterations.  b, x: device [n][3];
+ * work: device, opm_krylov_bytes; report: HOST struct (the call then
+ * synchronises the stream). */
+int opm_bicgstab(const opm_problem* pb, const double* J, const void* ilu, int precision,
+                 const double* b, double* x, double rtol, int32_t maxit, void* work,
+                 opm_solve_report* report, void* stream);
+
+/* Newton options (sec. 2.3). */
+typedef struct opm_newton_opts {
+  double tol_cnv;      /* converged when max CNV <= tol_cnv ...             */
+  double tol_mb;       /* ... and max MB <= tol_mb                          */
+  double ds_max;       /* Appleyard chop: largest saturation change         */
+  double dp_max_rel;   /* Appleyard chop: largest |dp| / |p|                */
+  double lin_rtol;     /* BiCGStab relative tolerance                       */
+  int32_t max_newton;  /* linear solves allowed per time step               */
+  int32_t lin_maxit;   /* BiCGStab iteration cap                            */
+  int32_t precision;   /* OPM_PREC_FP64 or OPM_PREC_MIXED                   */
+  int32_t max_cuts;    /* time-step halvings per report step (opm_advance)  */
+} opm_newton_opts;
+
+/* Report of one time step (or of one report step for opm_advance). */
+typedef struct opm_newton_report {
+  int32_t status;
+  int32_t newton_its;  /* linear solves                                     */
+  int32_t lin_its;     /* BiCGStab iterations (half iterations round up)    */
+  int32_t substeps;    /* accepted substeps (opm_advance)                   */
+  int32_t cuts;        /* time-step halvings (opm_advance)                  */
+  int32_t pad;
+  double cnv[3], mb[3];
+  double cell_newton_its;   /* sum over Newton iterations of n_cells        */
+  double t_assemble, t_factor, t_krylov, t_update;   /* s, HIP events     */
+} opm_newton_report;
+
+/* Size in bytes of the Newton workspace (device) for a precision. */
+size_t opm_newton_bytes(const opm_problem* pb, int precision);
+
+/* One implicit Euler step of length dt (sec. 2.3): Newton iterations from
+ * the guess in y (device [n][3], in/out) with y_prev the state at the start
+ * of the step, each one assemble -> convergence test -> ILU(0) ->
+ * BiCGStab -> Appleyard-chopped update, at most max_newton linear solves.
+ * No time-step cutting (opm_advance does that).  work: device,
+ * opm_newton_bytes.  report: HOST; the call synchronises the stream once per
+ * Newton iteration (convergence test) and a few times per linear solve. */
+int opm_newton_step(const opm_problem* pb, double* y, const double* y_prev, double dt,
+                    const opm_newton_opts* opts, void* work, opm_newton_report* report,
+                    void* stream);
+
+/* Advance y (device, in/out) over a report step of length dt: substeps with
+ * halving on failure (sec. 2.3 time-step cutting), at most max_cuts halvings;
+ * after a cut the shorter substep length is kept for the rest of the report
+ * step.  y_save: device [n][3] scratch for the last accepted state. */
+int opm_advance(const opm_problem* pb, double* y, double dt, const opm_newton_opts* opts,
+                void* work, double* y_save, opm_newton_report* report, void* stream);
+
+/* Process-wide tuning knobs (host, synchronous); they change speed, never
+ * results beyond round-off.  Returns OPM_OK, or OPM_EINVAL for an unknown
+ * option or value.
+ *   OPM_OPT_SWEEP_MODE: ILU(0) factor/sweep launch shape: -1 automatic,
+ *     0 one workgroup walks all levels, 1 one launch per level.
+ *   OPM_OPT_KRYLOV_CHUNK: BiCGStab iterations enqueued between reads of the
+ *     convergence state (0 automatic, else >= 1). */
+#define OPM_OPT_SWEEP_MODE 1
+#define OPM_OPT_KRYLOV_CHUNK 2
+int opm_set_option(int option, int value);
+
+const char* opm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,371 @@
+// Block-CSR SpMV and right-preconditioned BiCGStab (paper sec. 2.3.1, the
+// default Krylov method; van der Vorst's stabilised BiCG, x0 = 0, stopping on
+// ||r||_2 <= rtol ||b||_2).
+//
+// The iteration runs without host round trips: every scalar (rho, alpha,
+// omega, norms) lives in device memory, every dot product is a two-stage
+// fixed-order reduction whose per-workgroup partials are summed by the
+// consuming kernel itself (same order in every workgroup, so all of them see
+// bit-identical scalars), and a small state word (running / half-step exit /
+// done) lets kernels of an iteration that is no longer needed return at once.
+// The host only enqueues iterations in chunks and reads the state word
+// between chunks.
+#include <algorithm>
+
+#include "common.h"
+
+namespace opm {
+
+int ilu_apply(const opm_problem* pb, void* ilu, int precision, const double* r, double* x,
+              hipStream_t s, const int32_t* skip);
+int sweep_mode(const opm_problem* pb);
+
+namespace {
+
+constexpr int kMaxGrid = 1024;   // workgroups of the vector kernels
+
+enum State : int32_t { kRunning = 0, kHalfPending = 1, kDone = 2 };
+
+struct Scalars {
+  double rho, rho0, alpha, omega, bnorm, tol, relres, pad;
+  int32_t state, status, its, half, maxit, pad2[3];
+};
+
+struct Work {
+  double *r, *rh, *p, *v, *ph, *s, *sh, *t;
+  double *part_bb, *part_rr, *part_rhr, *part_rv, *part_ss, *part_ts, *part_tt;
+  Scalars* sc;
+};
+
+inline int vec_grid(int n) { return std::min(kMaxGrid, std::max(1, blocks_for(n, kBlock))); }
+
+Work carve(const opm_problem* pb, void* work) {
+  const size_t N = 3 * (size_t)pb->n_cells;
+  const size_t Np = (N + 31) / 32 * 32;
+  double* d = (double*)work;
+  Work w;
+  double** vecs[8] = {&w.r, &w.rh, &w.p, &w.v, &w.ph, &w.s, &w.sh, &w.t};
+  for (int k = 0; k < 8; ++k) {
+    *vecs[k] = d;
+    d += Np;
+  }
+  double** parts[7] = {&w.part_bb, &w.part_rr, &w.part_rhr, &w.part_rv,
+                       &w.part_ss, &w.part_ts, &w.part_tt};
+  for (int k = 0; k < 7; ++k) {
+    *parts[k] = d;
+    d += kMaxGrid;
+  }
+  w.sc = (Scalars*)d;
+  return w;
+}
+
+// Sum of the G partials of a reduction, identical in every workgroup.
+__device__ __forceinline__ double sum_partials(const double* part, int G, double* sh) {
+  double v = 0.0;
+  for (int k = threadIdx.x; k < G; k += kBlock) v += part[k];
+  return block_sum<kBlock>(v, sh);
+}
+
+__device__ __forceinline__ void store_partial(double v, double* part, double* sh) {
+  const double s = block_sum<kBlock>(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// One block row of y = J x (3 outputs).
+__device__ __forceinline__ void spmv_row(const int32_t* row_ptr, const int32_t* col,
+                                         const double* J, const double* x, int i, double* y3) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+    const int j = col[q];
+    const double* B = J + 9 * (size_t)q;
+    const double x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
+    a0 += B[0] * x0 + B[1] * x1 + B[2] * x2;
+    a1 += B[3] * x0 + B[4] * x1 + B[5] * x2;
+    a2 += B[6] * x0 + B[7] * x1 + B[8] * x2;
+  }
+  y3[0] = a0;
+  y3[1] = a1;
+  y3[2] = a2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_spmv(int n, const int32_t* row_ptr, const int32_t* col,
+                                                  const double* J, const double* x, double* y) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double y3[3];
+  spmv_row(row_ptr, col, J, x, i, y3);
+  y[3 * i] = y3[0];
+  y[3 * i + 1] = y3[1];
+  y[3 * i + 2] = y3[2];
+}
+
+// x = 0, r = r^ = b, p = v = 0; partials of <b,b>.
+__global__ __launch_bounds__(kBlock) void k_init(int N, const double* b, double* x, Work w) {
+  __shared__ double sh[kBlock / kWave];
+  double bb = 0.0;
+  for (int k = blockIdx.x * kBlock + threadIdx.x; k < N; k += gridDim.x * kBlock) {
+    const double v = b[k];
+    x[k] = 0.0;
+    w.r[k] = v;
+    w.rh[k] = v;
+    w.p[k] = 0.0;
+    w.v[k] = 0.0;
+    bb += v * v;
+  }
+  store_partial(bb, w.part_bb, sh);
+}
+
+__global__ __launch_bounds__(kBlock) void k_init2(Work w, int G, double rtol, int maxit) {
+  __shared__ double sh[kBlock / kWave];
+  const double bb = sum_partials(w.part_bb, G, sh);
+  if (threadIdx.x == 0) {
+    Scalars& s = *w.sc;
+    s.bnorm = sqrt(bb);
+    s.tol = rtol * s.bnorm;
+    s.rho0 = s.alpha = s.omega = 1.0;
+    s.rho = 0.0;
+    s.its = 0;
+    s.half = 0;
+    s.maxit = maxit;
+    s.relres = bb == 0.0 ? 0.0 : 1.0;
+    s.status = OPM_OK;
+    s.state = bb == 0.0 ? kDone : kRunning;
+  }
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < G; k += kBlock) {
+      w.part_rr[k] = w.part_bb[k];    // r = b
+      w.part_rhr[k] = w.part_bb[k];   // <r^, r> = <b, b>
+    }
+}
+
+// Start of an iteration: convergence / cap / breakdown tests on the
+// residual of the previous iteration, then p = r + beta (p - omega v).
+__global__ __launch_bounds__(kBlock) void k_begin(int N, Work w, int G) {
+  __shared__ double sh[kBlock / kWave];
+  Scalars& s = *w.sc;
+  const int state = s.state;
+  if (state != kRunning) {
+    if (state == kHalfPending && blockIdx.x == 0 && threadIdx.x == 0) s.state = kDone;
+    return;
+  }
+  const double rr = sum_partials(w.part_rr, G, sh);
+  const double rho = sum_partials(w.part_rhr, G, sh);
+  const int its = s.its;
+  const double rnorm = sqrt(rr);
+  int verdict = kRunning, status = OPM_OK;
+  if (rnorm <= s.tol) {
+    verdict = kDone;
+  } else if (its > 0 && s.omega == 0.0) {
+    verdict = kDone;
+    status = OPM_EBREAKDOWN;
+  } else if (its >= s.maxit) {
+    verdict = kDone;
+    status = OPM_ENOTCONV;
+  } else if (fabs(rho) < 1e-300) {
+    verdict = kDone;
+    status = OPM_EBREAKDOWN;
+  }
+  if (verdict == kDone) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      s.status = status;
+      s.relres = s.bnorm > 0.0 ? rnorm / s.bnorm : 0.0;
+      s.state = kDone;
+    }
+    return;
+  }
+  const double beta = its == 0 ? 0.0 : (rho / s.rho0) * (s.alpha / s.omega);
+  const double om = s.omega;
+  for (int k = blockIdx.x * kBlock + threadIdx.x; k < N; k += gridDim.x * kBlock)
+    w.p[k] = w.r[k] + beta * (w.p[k] - om * w.v[k]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) s.rho = rho;
+}
+
+// v = A p^ ; partials of <r^, v>.
+__global__ __launch_bounds__(kBlock) void k_spmv_rv(int n, const int32_t* row_ptr,
+                                                     const int32_t* col, const double* J, Work w) {
+  __shared__ double sh[kBlock / kWave];
+  if (w.sc->state != kRunning) return;
+  double acc = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    double y3[3];
+    spmv_row(row_ptr, col, J, w.ph, i, y3);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      w.v[3 * i + c] = y3[c];
+      acc += w.rh[3 * i + c] * y3[c];
+    }
+  }
+  store_partial(acc, w.part_rv, sh);
+}
+
+// alpha = rho / <r^, v>; s = r - alpha v; partials of <s, s>.
+__global__ __launch_bounds__(kBlock) void k_s(int N, Work w, int G) {
+  __shared__ double sh[kBlock / kWave];
+  Scalars& sc = *w.sc;
+  if (sc.state != kRunning) return;
+  const double rv = sum_partials(w.part_rv, G, sh);
+  if (rv == 0.0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc.status = OPM_EBREAKDOWN;
+      sc.state = kDone;
+    }
+    return;
+  }
+  const double alpha = sc.rho / rv;
+  double ss = 0.0;
+  for (int k = blockIdx.x * kBlock + threadIdx.x; k < N; k += gridDim.x * kBlock) {
+    const double v = w.r[k] - alpha * w.v[k];
+    w.s[k] = v;
+    ss += v * v;
+  }
+  store_partial(ss, w.part_ss, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc.alpha = alpha;
+}
+
+// Half-step exit test ||s|| <= tol (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_s_check(Work w, int G) {
+  __shared__ double sh[kBlock / kWave];
+  Scalars& sc = *w.sc;
+  if (sc.state != kRunning) return;
+  const double snorm = sqrt(sum_partials(w.part_ss, G, sh));
+  if (threadIdx.x == 0 && snorm <= sc.tol) {
+    sc.half = 1;
+    sc.relres = snorm / sc.bnorm;
+    sc.its += 1;
+    sc.state = kHalfPending;
+  }
+}
+
+// t = A s^ ; partials of <t, s> and <t, t>.
+__global__ __launch_bounds__(kBlock) void k_spmv_t(int n, const int32_t* row_ptr,
+                                                    const int32_t* col, const double* J, Work w) {
+  __shared__ double sh[kBlock / kWave];
+  if (w.sc->state != kRunning) return;
+  double ts = 0.0, tt = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    double y3[3];
+    spmv_row(row_ptr, col, J, w.sh, i, y3);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      w.t[3 * i + c] = y3[c];
+      ts += y3[c] * w.s[3 * i + c];
+      tt += y3[c] * y3[c];
+    }
+  }
+  store_partial(ts, w.part_ts, sh);
+  store_partial(tt, w.part_tt, sh);
+}
+
+// omega = <t,s>/<t,t>; x += alpha p^ + omega s^; r = s - omega t; partials of
+// <r, r> and <r^, r>.  On a half-step exit only x += alpha p^.
+__global__ __launch_bounds__(kBlock) void k_x(int N, double* x, Work w, int G) {
+  __shared__ double sh[kBlock / kWave];
+  Scalars& sc = *w.sc;
+  const int state = sc.state;
+  const double alpha = sc.alpha;
+  if (state == kHalfPending) {
+    for (int k = blockIdx.x * kBlock + threadIdx.x; k < N; k += gridDim.x * kBlock)
+      x[k] += alpha * w.ph[k];
+    return;
+  }
+  if (state != kRunning) return;
+  const double ts = sum_partials(w.part_ts, G, sh);
+  const double tt = sum_partials(w.part_tt, G, sh);
+  if (tt == 0.0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc.status = OPM_EBREAKDOWN;
+      sc.state = kDone;
+    }
+    return;
+  }
+  const double omega = ts / tt;
+  double rr = 0.0, rhr = 0.0;
+  for (int k = blockIdx.x * kBlock + threadIdx.x; k < N; k += gridDim.x * kBlock) {
+    x[k] += alpha * w.ph[k] + omega * w.sh[k];
+    const double r = w.s[k] - omega * w.t[k];
+    w.r[k] = r;
+    rr += r * r;
+    rhr += w.rh[k] * r;
+  }
+  store_partial(rr, w.part_rr, sh);
+  store_partial(rhr, w.part_rhr, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc.omega = omega;
+    sc.rho0 = sc.rho;
+    sc.its += 1;
+  }
+}
+
+}  // namespace
+
+// Iterations enqueued between two reads of the state word (0 = automatic).
+int g_krylov_chunk = 0;
+
+int chunk_size(const opm_problem* pb) {
+  if (g_krylov_chunk > 0) return g_krylov_chunk;
+  return sweep_mode(pb) == 0 ? 6 : 3;
+}
+
+size_t krylov_bytes(const opm_problem* pb) {
+  const size_t N = 3 * (size_t)pb->n_cells;
+  const size_t Np = (N + 31) / 32 * 32;
+  return sizeof(double) * (8 * Np + 7 * kMaxGrid) + sizeof(Scalars) + 256;
+}
+
+int spmv(const opm_problem* pb, const double* J, const double* x, double* y, hipStream_t s) {
+  if (pb->n_cells == 0) return OPM_OK;
+  hipLaunchKernelGGL(k_spmv, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock), 0, s,
+                     pb->n_cells, pb->row_ptr, pb->col_idx, J, x, y);
+  OPM_TRY_HIP(hipGetLastError());
+  return OPM_OK;
+}
+
+// Enqueue the whole solve; returns after reading the final scalars.
+int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, const double* b,
+             double* x, double rtol, int maxit, void* work, opm_solve_report* rep,
+             hipStream_t st) {
+  const int n = pb->n_cells, N = 3 * n;
+  Work w = carve(pb, work);
+  const int G = vec_grid(N), Gr = vec_grid(n);
+  hipLaunchKernelGGL(k_init, dim3(G), dim3(kBlock), 0, st, N, b, x, w);
+  hipLaunchKernelGGL(k_init2, dim3(1), dim3(kBlock), 0, st, w, G, rtol, maxit);
+  OPM_TRY_HIP(hipGetLastError());
+  const int chunk = chunk_size(pb);
+  Scalars host;
+  int launched = 0;
+  for (;;) {
+    for (int c = 0; c < chunk; ++c) {
+      hipLaunchKernelGGL(k_begin, dim3(G), dim3(kBlock), 0, st, N, w, G);
+      OPM_TRY(ilu_apply(pb, ilu, precision, w.p, w.ph, st, &w.sc->state));
+      hipLaunchKernelGGL(k_spmv_rv, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr, pb->col_idx,
+                         J, w);
+      hipLaunchKernelGGL(k_s, dim3(G), dim3(kBlock), 0, st, N, w, Gr);
+      hipLaunchKernelGGL(k_s_check, dim3(1), dim3(kBlock), 0, st, w, G);
+      OPM_TRY(ilu_apply(pb, ilu, precision, w.s, w.sh, st, &w.sc->state));
+      hipLaunchKernelGGL(k_spmv_t, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr, pb->col_idx, J,
+                         w);
+      hipLaunchKernelGGL(k_x, dim3(G), dim3(kBlock), 0, st, N, x, w, Gr);
+      OPM_TRY_HIP(hipGetLastError());
+      ++launched;
+    }
+    // a final begin turns a pending half-step exit into done and performs the
+    // convergence test of the last full iteration
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBlock), 0, st, 0, w, G);
+    OPM_TRY_HIP(hipMemcpyAsync(&host, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    OPM_TRY_HIP(hipStreamSynchronize(st));
+    if (host.state == kDone) break;
+    if (launched > maxit + 2) {   // cannot happen: k_begin enforces maxit
+      host.status = OPM_ENOTCONV;
+      break;
+    }
+  }
+  if (rep) {
+    rep->status = host.status;
+    rep->half = host.half;
+    rep->its = host.its;
+    rep->rel_res = host.relres;
+  }
+  return OPM_OK;
+}
+
+}  // namespace opm

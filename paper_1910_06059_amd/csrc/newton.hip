@@ -1,0 +1,377 @@
+// Newton-Raphson time step and report-step driver (paper sec. 2.3, eq.
+// linsystem: J(y_n)(y_{n+1} - y_n) = -R(y_n) from the previous step's state,
+// Appleyard-type chop of each update, time-step cutting on failure), and the
+// C-ABI entry points of the library.
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace opm {
+
+extern int g_sweep_mode;
+extern int g_krylov_chunk;
+int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, double dt,
+                    double* R, double* J, double* norms, hipStream_t s);
+int launch_accumulation(const opm_problem* pb, const double* y, double* acc0, hipStream_t s);
+size_t ilu_bytes(const opm_problem* pb, int precision);
+int ilu_factor(const opm_problem* pb, const double* J, void* ilu, int precision, int32_t* status,
+               hipStream_t s);
+int ilu_apply(const opm_problem* pb, void* ilu, int precision, const double* r, double* x,
+              hipStream_t s, const int32_t* skip);
+size_t krylov_bytes(const opm_problem* pb);
+int spmv(const opm_problem* pb, const double* J, const double* x, double* y, hipStream_t s);
+int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, const double* b,
+             double* x, double rtol, int maxit, void* work, opm_solve_report* rep,
+             hipStream_t st);
+
+namespace {
+
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t norms_bytes(const opm_problem* pb) {
+  return sizeof(double) * (8 + (size_t)kNormStride * blocks_for(pb->n_cells, kBlock));
+}
+
+struct NewtonWork {
+  double* acc0;
+  double* R;
+  double* J;
+  double* d;
+  double* norms;
+  int32_t* flags;   // [0] factor status, [1] non-finite update
+  void* ilu;
+  void* krylov;
+};
+
+size_t newton_bytes(const opm_problem* pb, int precision) {
+  const size_t N = 3 * (size_t)pb->n_cells;
+  return align256(sizeof(double) * N) * 3 + align256(sizeof(double) * 9 * (size_t)pb->nnzb) +
+         align256(norms_bytes(pb)) + 256 + align256(ilu_bytes(pb, precision)) +
+         align256(krylov_bytes(pb));
+}
+
+NewtonWork carve(const opm_problem* pb, int precision, void* work) {
+  const size_t N = 3 * (size_t)pb->n_cells;
+  char* c = (char*)work;
+  NewtonWork w;
+  w.acc0 = (double*)c;
+  c += align256(sizeof(double) * N);
+  w.R = (double*)c;
+  c += align256(sizeof(double) * N);
+  w.d = (double*)c;
+  c += align256(sizeof(double) * N);
+  w.J = (double*)c;
+  c += align256(sizeof(double) * 9 * (size_t)pb->nnzb);
+  w.norms = (double*)c;
+  c += align256(norms_bytes(pb));
+  w.flags = (int32_t*)c;
+  c += 256;
+  w.ilu = c;
+  c += align256(ilu_bytes(pb, precision));
+  w.krylov = c;
+  return w;
+}
+
+__global__ void k_clear_flags(int32_t* flags) {
+  if (threadIdx.x < 4) flags[threadIdx.x] = 0;
+}
+
+// y <- y - chop(d) where J d = R (so -d is the Newton update): |dp| is
+// bounded by dp_max_rel |p|; the saturation part is scaled so that its
+// largest component is at most ds_max.
+__global__ __launch_bounds__(kBlock) void k_update(int n, double* y, const double* d,
+                                                    double ds_max, double dp_max_rel,
+                                                    int32_t* flags) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double p = y[3 * i];
+  double dp = -d[3 * i];
+  const double lim = dp_max_rel * fabs(p);
+  if (dp > lim) dp = lim;
+  if (dp < -lim) dp = -lim;
+  double dsw = -d[3 * i + 1], dsg = -d[3 * i + 2];
+  const double mx = fmax(fabs(dsw), fabs(dsg));
+  if (mx > ds_max) {
+    const double sc = ds_max / mx;
+    dsw *= sc;
+    dsg *= sc;
+  }
+  const double y0 = p + dp, y1 = y[3 * i + 1] + dsw, y2 = y[3 * i + 2] + dsg;
+  y[3 * i] = y0;
+  y[3 * i + 1] = y1;
+  y[3 * i + 2] = y2;
+  if (!isfinite(y0) || !isfinite(y1) || !isfinite(y2)) flags[1] = 1;
+}
+
+struct Events {
+  hipEvent_t e[5];
+  bool ok = false;
+};
+
+Events& events() {
+  static thread_local Events ev;
+  if (!ev.ok) {
+    for (auto& x : ev.e) (void)hipEventCreate(&x);
+    ev.ok = true;
+  }
+  return ev;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  return ms * 1e-3f;
+}
+
+bool valid_problem(const opm_problem* pb) {
+  if (!pb || pb->n_cells < 0 || pb->n_faces < 0 || pb->nnzb != pb->n_cells + 2 * pb->n_faces)
+    return false;
+  if (pb->n_cells == 0) return true;
+  return pb->trans && pb->pore_vol && pb->depth && pb->row_ptr && pb->col_idx && pb->blk_face &&
+         pb->diag_pos && pb->level_ptr && pb->level_ptr_h && pb->perm && pb->iperm &&
+         pb->lo_blk && pb->lo_tblk && pb->lo_pos && pb->up_blk && pb->up_pos &&
+         pb->cell_conn_ptr && (pb->n_conns == 0 || (pb->cell_conn && pb->conn_kind &&
+                                                     pb->conn_phase && pb->conn_wi &&
+                                                     pb->conn_rate && pb->conn_bhp)) &&
+         pb->n_levels > 0 && pb->level_ptr_h[pb->n_levels] == pb->n_cells;
+}
+
+bool valid_prec(int p) { return p == OPM_PREC_FP64 || p == OPM_PREC_MIXED; }
+
+int newton_step(const opm_problem* pb, double* y, const double* y_prev, double dt,
+                const opm_newton_opts* o, void* work, opm_newton_report* rep, hipStream_t s) {
+  const int n = pb->n_cells;
+  NewtonWork w = carve(pb, o->precision, work);
+  Events& ev = events();
+  memset(rep, 0, sizeof(*rep));
+  OPM_TRY(launch_accumulation(pb, y_prev, w.acc0, s));
+  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, w.flags);
+  int status = OPM_ENOTCONV;
+  for (int it = 0;; ++it) {
+    OPM_TRY_HIP(hipEventRecord(ev.e[0], s));
+    OPM_TRY(launch_assemble(pb, y, w.acc0, dt, w.R, w.J, w.norms, s));
+    OPM_TRY_HIP(hipEventRecord(ev.e[1], s));
+    double nrm[8];
+    int32_t flags[4];
+    OPM_TRY_HIP(hipMemcpyAsync(nrm, w.norms, sizeof(nrm), hipMemcpyDeviceToHost, s));
+    OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    OPM_TRY_HIP(hipStreamSynchronize(s));
+    rep->t_assemble += elapsed(ev.e[0], ev.e[1]);
+    for (int c = 0; c < 3; ++c) {
+      rep->cnv[c] = nrm[c];
+      rep->mb[c] = nrm[3 + c];
+    }
+    if (flags[1] || !std::isfinite(nrm[6]) || !std::isfinite(nrm[7])) {
+      status = OPM_ENONFINITE;
+      break;
+    }
+    if (nrm[6] <= o->tol_cnv && nrm[7] <= o->tol_mb) {
+      status = OPM_OK;
+      break;
+    }
+    if (it >= o->max_newton) {
+      status = OPM_ENOTCONV;
+      break;
+    }
+    OPM_TRY(ilu_factor(pb, w.J, w.ilu, o->precision, &w.flags[0], s));
+    OPM_TRY_HIP(hipEventRecord(ev.e[2], s));
+    opm_solve_report lr;
+    OPM_TRY(bicgstab(pb, w.J, w.ilu, o->precision, w.R, w.d, o->lin_rtol, o->lin_maxit, w.krylov,
+                     &lr, s));
+    OPM_TRY_HIP(hipEventRecord(ev.e[3], s));
+    rep->lin_its += lr.its;
+    OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    OPM_TRY_HIP(hipStreamSynchronize(s));
+    rep->t_factor += elapsed(ev.e[1], ev.e[2]);
+    rep->t_krylov += elapsed(ev.e[2], ev.e[3]);
+    if (flags[0] != 0) {
+      status = flags[0];
+      break;
+    }
+    if (lr.status != OPM_OK) {
+      status = lr.status;
+      break;
+    }
+    hipLaunchKernelGGL(k_update, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, n, y, w.d,
+                       o->ds_max, o->dp_max_rel, w.flags);
+    OPM_TRY_HIP(hipGetLastError());
+    OPM_TRY_HIP(hipEventRecord(ev.e[4], s));
+    OPM_TRY_HIP(hipEventSynchronize(ev.e[4]));
+    rep->t_update += elapsed(ev.e[3], ev.e[4]);
+    rep->newton_its++;
+    rep->cell_newton_its += (double)n;
+  }
+  rep->status = status;
+  return status;
+}
+
+}  // namespace
+}  // namespace opm
+
+using namespace opm;
+
+extern "C" {
+
+int opm_init(void) {
+  int dev = 0;
+  OPM_TRY_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  OPM_TRY_HIP(hipGetDeviceProperties(&prop, dev));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return OPM_EHIP;
+  (void)events();
+  return OPM_OK;
+}
+
+int opm_set_option(int option, int value) {
+  switch (option) {
+    case OPM_OPT_SWEEP_MODE:
+      if (value < -1 || value > 1) return OPM_EINVAL;
+      g_sweep_mode = value;
+      return OPM_OK;
+    case OPM_OPT_KRYLOV_CHUNK:
+      if (value < 0) return OPM_EINVAL;
+      g_krylov_chunk = value;
+      return OPM_OK;
+    default:
+      return OPM_EINVAL;
+  }
+}
+
+const char* opm_strerror(int code) {
+  switch (code) {
+    case OPM_OK: return "ok";
+    case OPM_EINVAL: return "invalid argument";
+    case OPM_ESINGULAR: return "singular 3x3 pivot block in ILU(0)";
+    case OPM_ENOTCONV: return "not converged";
+    case OPM_EBREAKDOWN: return "BiCGStab breakdown";
+    case OPM_ENONFINITE: return "non-finite residual or state";
+    case OPM_EHIP: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+int opm_accumulation(const opm_problem* pb, const double* y, double* acc0, void* stream) {
+  if (!valid_problem(pb) || (pb->n_cells > 0 && (!y || !acc0))) return OPM_EINVAL;
+  if (pb->n_cells == 0) return OPM_OK;
+  return launch_accumulation(pb, y, acc0, as_stream(stream));
+}
+
+size_t opm_norms_bytes(const opm_problem* pb) { return pb ? norms_bytes(pb) : 0; }
+
+int opm_assemble(const opm_problem* pb, const double* y, const double* acc0, double dt, double* R,
+                 double* J, double* norms, void* stream) {
+  if (!valid_problem(pb) || !(dt > 0.0) || (pb->n_cells > 0 && (!y || !acc0 || !R)))
+    return OPM_EINVAL;
+  if (pb->n_cells == 0) return OPM_OK;
+  return launch_assemble(pb, y, acc0, dt, R, J, norms, as_stream(stream));
+}
+
+size_t opm_ilu0_bytes(const opm_problem* pb, int precision) {
+  return pb && valid_prec(precision) ? ilu_bytes(pb, precision) : 0;
+}
+
+int opm_ilu0_factor(const opm_problem* pb, const double* J, void* ilu, int precision,
+                    int32_t* status, void* stream) {
+  if (!valid_problem(pb) || !valid_prec(precision) || (pb->n_cells > 0 && (!J || !ilu)))
+    return OPM_EINVAL;
+  if (pb->n_cells == 0) return OPM_OK;
+  return ilu_factor(pb, J, ilu, precision, status, as_stream(stream));
+}
+
+int opm_ilu0_apply(const opm_problem* pb, const void* ilu, int precision, const double* r,
+                   double* x, void* stream) {
+  if (!valid_problem(pb) || !valid_prec(precision) || (pb->n_cells > 0 && (!ilu || !r || !x)) ||
+      (pb->n_cells > 0 && r == x))
+    return OPM_EINVAL;
+  if (pb->n_cells == 0) return OPM_OK;
+  return ilu_apply(pb, const_cast<void*>(ilu), precision, r, x, as_stream(stream), nullptr);
+}
+
+int opm_spmv(const opm_problem* pb, const double* J, const double* x, double* y, void* stream) {
+  if (!valid_problem(pb) || (pb->n_cells > 0 && (!J || !x || !y))) return OPM_EINVAL;
+  return spmv(pb, J, x, y, as_stream(stream));
+}
+
+size_t opm_krylov_bytes(const opm_problem* pb) { return pb ? krylov_bytes(pb) : 0; }
+
+int opm_bicgstab(const opm_problem* pb, const double* J, const void* ilu, int precision,
+                 const double* b, double* x, double rtol, int32_t maxit, void* work,
+                 opm_solve_report* report, void* stream) {
+  if (!valid_problem(pb) || !valid_prec(precision) || !(rtol >= 0.0) || maxit < 0 || !report ||
+      (pb->n_cells > 0 && (!J || !ilu || !b || !x || !work)))
+    return OPM_EINVAL;
+  if (pb->n_cells == 0) {
+    memset(report, 0, sizeof(*report));
+    return OPM_OK;
+  }
+  return bicgstab(pb, J, const_cast<void*>(ilu), precision, b, x, rtol, maxit, work, report,
+                  as_stream(stream));
+}
+
+size_t opm_newton_bytes(const opm_problem* pb, int precision) {
+  return pb && valid_prec(precision) ? newton_bytes(pb, precision) : 0;
+}
+
+static bool valid_opts(const opm_newton_opts* o) {
+  return o && valid_prec(o->precision) && o->max_newton >= 0 && o->lin_maxit >= 0 &&
+         o->max_cuts >= 0 && o->ds_max > 0.0 && o->dp_max_rel > 0.0 && o->lin_rtol >= 0.0 &&
+         o->tol_cnv >= 0.0 && o->tol_mb >= 0.0;
+}
+
+int opm_newton_step(const opm_problem* pb, double* y, const double* y_prev, double dt,
+                    const opm_newton_opts* opts, void* work, opm_newton_report* report,
+                    void* stream) {
+  if (!valid_problem(pb) || pb->n_cells == 0 || !valid_opts(opts) || !(dt > 0.0) || !y ||
+      !y_prev || !work || !report)
+    return OPM_EINVAL;
+  return newton_step(pb, y, y_prev, dt, opts, work, report, as_stream(stream));
+}
+
+int opm_advance(const opm_problem* pb, double* y, double dt, const opm_newton_opts* opts,
+                void* work, double* y_save, opm_newton_report* report, void* stream) {
+  if (!valid_problem(pb) || pb->n_cells == 0 || !valid_opts(opts) || !(dt > 0.0) || !y ||
+      !y_save || !work || !report)
+    return OPM_EINVAL;
+  hipStream_t s = as_stream(stream);
+  const size_t bytes = sizeof(double) * 3 * (size_t)pb->n_cells;
+  memset(report, 0, sizeof(*report));
+  OPM_TRY_HIP(hipMemcpyAsync(y_save, y, bytes, hipMemcpyDeviceToDevice, s));
+  double t = 0.0, dt_try = dt;
+  int status = OPM_OK;
+  while (dt - t > 1e-9 * dt) {
+    const double h = fmin(dt_try, dt - t);
+    opm_newton_report r1;
+    int st = newton_step(pb, y, y_save, h, opts, work, &r1, s);
+    if (st == OPM_EHIP || st == OPM_EINVAL) return st;
+    report->newton_its += r1.newton_its;
+    report->lin_its += r1.lin_its;
+    report->cell_newton_its += r1.cell_newton_its;
+    report->t_assemble += r1.t_assemble;
+    report->t_factor += r1.t_factor;
+    report->t_krylov += r1.t_krylov;
+    report->t_update += r1.t_update;
+    if (st == OPM_OK) {
+      for (int c = 0; c < 3; ++c) {
+        report->cnv[c] = r1.cnv[c];
+        report->mb[c] = r1.mb[c];
+      }
+      OPM_TRY_HIP(hipMemcpyAsync(y_save, y, bytes, hipMemcpyDeviceToDevice, s));
+      t += h;
+      report->substeps++;
+    } else {
+      OPM_TRY_HIP(hipMemcpyAsync(y, y_save, bytes, hipMemcpyDeviceToDevice, s));
+      dt_try = 0.5 * h;
+      report->cuts++;
+      if (report->cuts > opts->max_cuts) {
+        status = st;
+        break;
+      }
+    }
+  }
+  OPM_TRY_HIP(hipStreamSynchronize(s));
+  report->status = status;
+  return status;
+}
+
+}  // extern "C"

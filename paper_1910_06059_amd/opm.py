@@ -1,0 +1,398 @@
+"""Python binding of the MI355X Newton linearisation and solve library.
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libopm_gpu.so`` (C ABI declared in ``include/opm_gpu.h``).  torch provides
+device memory and the stream; nothing here computes any part of the method.
+The library must be built (``__graft_entry__.build()``); importing this
+module on a machine without the built library or without a gfx950 GPU raises
+instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import cases as _cases
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libopm_gpu.so")
+
+OK, EINVAL, ESINGULAR, ENOTCONV, EBREAKDOWN, ENONFINITE, EHIP = 0, -1, -2, -3, -4, -5, -6
+PREC_FP64, PREC_MIXED = 0, 1
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_ip = ctypes.POINTER(ctypes.c_int32)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class Fluid(ctypes.Structure):
+    _fields_ = [("rho_s", ctypes.c_double * 3), ("c", ctypes.c_double * 3),
+                ("p_ref", ctypes.c_double), ("mu", ctypes.c_double * 3),
+                ("swc", ctypes.c_double), ("n_corey", ctypes.c_double), ("g", ctypes.c_double)]
+
+
+class Topology(ctypes.Structure):
+    _fields_ = [(name, _ip) for name in (
+        "cell_box", "face_cells", "face_dir", "row_ptr", "col_idx", "blk_face", "diag_pos",
+        "level_ptr", "perm", "iperm", "lo_blk", "lo_tblk", "lo_pos", "up_blk", "up_pos")] + [
+        ("n_levels", _i32), ("max_level", _i32)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n_cells", _i32), ("n_faces", _i32), ("nnzb", _i32), ("n_levels", _i32),
+                ("max_level", _i32), ("n_conns", _i32),
+                ("trans", _vp), ("pore_vol", _vp), ("depth", _vp),
+                ("row_ptr", _vp), ("col_idx", _vp), ("blk_face", _vp), ("face_cells", _vp),
+                ("diag_pos", _vp), ("level_ptr", _vp), ("level_ptr_h", _vp), ("perm", _vp),
+                ("iperm", _vp), ("lo_blk", _vp), ("lo_tblk", _vp), ("lo_pos", _vp),
+                ("up_blk", _vp), ("up_pos", _vp), ("cell_conn_ptr", _vp), ("cell_conn", _vp),
+                ("conn_kind", _vp), ("conn_phase", _vp), ("conn_wi", _vp), ("conn_rate", _vp),
+                ("conn_bhp", _vp), ("fluid", Fluid)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("status", _i32), ("half", _i32), ("its", _i32), ("pad", _i32),
+                ("rel_res", ctypes.c_double)]
+
+
+class NewtonOpts(ctypes.Structure):
+    _fields_ = [("tol_cnv", ctypes.c_double), ("tol_mb", ctypes.c_double),
+                ("ds_max", ctypes.c_double), ("dp_max_rel", ctypes.c_double),
+                ("lin_rtol", ctypes.c_double), ("max_newton", _i32), ("lin_maxit", _i32),
+                ("precision", _i32), ("max_cuts", _i32)]
+
+
+class NewtonReport(ctypes.Structure):
+    _fields_ = [("status", _i32), ("newton_its", _i32), ("lin_its", _i32), ("substeps", _i32),
+                ("cuts", _i32), ("pad", _i32), ("cnv", ctypes.c_double * 3),
+                ("mb", ctypes.c_double * 3), ("cell_newton_its", ctypes.c_double),
+                ("t_assemble", ctypes.c_double), ("t_factor", ctypes.c_double),
+                ("t_krylov", ctypes.c_double), ("t_update", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: (list(getattr(self, k)) if k in ("cnv", "mb") else getattr(self, k))
+                for k, _ in self._fields_ if k != "pad"}
+
+
+EXPORTS = [
+    "opm_init", "opm_strerror", "opm_topology_count", "opm_topology_build", "opm_geometry",
+    "opm_well_index", "opm_well_groups", "opm_accumulation", "opm_norms_bytes", "opm_assemble",
+    "opm_ilu0_bytes", "opm_ilu0_factor", "opm_ilu0_apply", "opm_spmv", "opm_krylov_bytes",
+    "opm_bicgstab", "opm_newton_bytes", "opm_newton_step", "opm_advance", "opm_set_option",
+]
+
+OPT_SWEEP_MODE, OPT_KRYLOV_CHUNK = 1, 2
+
+_lib = None
+
+
+class OpmError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {_strerror(code)} ({code})")
+        self.code = code
+
+
+def _strerror(code):
+    try:
+        return lib().opm_strerror(code).decode()
+    except Exception:
+        return "error"
+
+
+def lib():
+    """Load libopm_gpu.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.opm_strerror.restype = ctypes.c_char_p
+        L.opm_strerror.argtypes = [ctypes.c_int]
+        L.opm_init.restype = ctypes.c_int
+        L.opm_set_option.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.opm_topology_count.argtypes = [_i32, _i32, _i32, _vp, _ip, _ip]
+        L.opm_topology_build.argtypes = [_i32, _i32, _i32, _vp, ctypes.POINTER(Topology)]
+        L.opm_geometry.argtypes = [_i32, _i32, _i32, ctypes.c_double, ctypes.c_double, _vp, _vp,
+                                   ctypes.c_double, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
+                                   _vp, _vp]
+        L.opm_well_index.argtypes = [_i32, _i32, ctypes.c_double, ctypes.c_double, _vp, _vp, _vp,
+                                     _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
+                                     _vp, _vp, _vp]
+        L.opm_well_groups.argtypes = [_i32, _i32, _vp, _vp, _vp]
+        P = ctypes.POINTER(Problem)
+        L.opm_accumulation.argtypes = [P, _vp, _vp, _vp]
+        L.opm_norms_bytes.argtypes = [P]
+        L.opm_norms_bytes.restype = ctypes.c_size_t
+        L.opm_assemble.argtypes = [P, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp]
+        L.opm_ilu0_bytes.argtypes = [P, ctypes.c_int]
+        L.opm_ilu0_bytes.restype = ctypes.c_size_t
+        L.opm_ilu0_factor.argtypes = [P, _vp, _vp, ctypes.c_int, _vp, _vp]
+        L.opm_ilu0_apply.argtypes = [P, _vp, ctypes.c_int, _vp, _vp, _vp]
+        L.opm_spmv.argtypes = [P, _vp, _vp, _vp, _vp]
+        L.opm_krylov_bytes.argtypes = [P]
+        L.opm_krylov_bytes.restype = ctypes.c_size_t
+        L.opm_bicgstab.argtypes = [P, _vp, _vp, ctypes.c_int, _vp, _vp, ctypes.c_double, _i32,
+                                   _vp, ctypes.POINTER(SolveReport), _vp]
+        L.opm_newton_bytes.argtypes = [P, ctypes.c_int]
+        L.opm_newton_bytes.restype = ctypes.c_size_t
+        L.opm_newton_step.argtypes = [P, _vp, _vp, ctypes.c_double, ctypes.POINTER(NewtonOpts),
+                                      _vp, ctypes.POINTER(NewtonReport), _vp]
+        L.opm_advance.argtypes = [P, _vp, ctypes.c_double, ctypes.POINTER(NewtonOpts), _vp, _vp,
+                                  ctypes.POINTER(NewtonReport), _vp]
+        _lib = L
+    return _lib
+
+
+def _check(code, what):
+    if code != OK:
+        raise OpmError(code, what)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_initialised = set()
+
+
+def init(device=None):
+    """opm_init on the current device (once per device)."""
+    dev = torch.cuda.current_device() if device is None else device
+    if dev not in _initialised:
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the MI355X path cannot run here")
+        with torch.cuda.device(dev):
+            _check(lib().opm_init(), "opm_init (needs a gfx950 device)")
+        _initialised.add(dev)
+
+
+def set_option(option: int, value: int) -> None:
+    """Set a tuning knob (OPT_SWEEP_MODE, OPT_KRYLOV_CHUNK)."""
+    _check(lib().opm_set_option(option, value), "opm_set_option")
+
+
+def default_opts(case=None, precision=PREC_FP64, **kw) -> NewtonOpts:
+    o = NewtonOpts(tol_cnv=1e-8, tol_mb=1e-11, ds_max=0.2, dp_max_rel=0.3, lin_rtol=1e-6,
+                   max_newton=20, lin_maxit=500, precision=precision, max_cuts=8)
+    if case is not None:
+        o.tol_cnv, o.tol_mb, o.lin_rtol = case.tol_cnv, case.tol_mb, case.lin_rtol
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class GpuModel:
+    """A case laid out on the GPU: topology, geometry and wells on device."""
+
+    def __init__(self, case: _cases.Case, device: str = "cuda"):
+        L = lib()
+        init()
+        self.case = case
+        self.dev = torch.device(device)
+        nx, ny, nz = case.nx, case.ny, case.nz
+        mask = np.ascontiguousarray(case.mask, dtype=np.uint8).ravel()
+        n, nf = _i32(), _i32()
+        _check(L.opm_topology_count(nx, ny, nz, mask.ctypes.data, ctypes.byref(n),
+                                    ctypes.byref(nf)), "opm_topology_count")
+        n, nf = n.value, nf.value
+        nnzb = n + 2 * nf
+        sizes = dict(cell_box=n, face_cells=2 * nf, face_dir=nf, row_ptr=n + 1, col_idx=nnzb,
+                     blk_face=nnzb, diag_pos=n, level_ptr=n + 1, perm=n, iperm=n, lo_blk=3 * n,
+                     lo_tblk=3 * n, lo_pos=3 * n, up_blk=3 * n, up_pos=3 * n)
+        host = {k: np.zeros(max(v, 1), np.int32) for k, v in sizes.items()}
+        topo = Topology(**{k: a.ctypes.data_as(_ip) for k, a in host.items()})
+        _check(L.opm_topology_build(nx, ny, nz, mask.ctypes.data, ctypes.byref(topo)),
+               "opm_topology_build")
+        self.n, self.nf, self.nnzb = n, nf, nnzb
+        self.n_levels, self.max_level = topo.n_levels, topo.max_level
+        self.host = host
+        self.level_ptr_h = np.ascontiguousarray(host["level_ptr"][:self.n_levels + 1])
+        d = {k: torch.from_numpy(a).to(self.dev) for k, a in host.items()}
+        self.t = d
+        cell_box = host["cell_box"][:n]
+        box_cell = np.full(case.n_box, -1, np.int64)
+        box_cell[cell_box] = np.arange(n)
+        self.cell_box, self.box_cell = cell_box, box_cell
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        self.perm_h = torch.from_numpy(np.ascontiguousarray(case.perm_h.ravel()[cell_box])).to(self.dev)
+        self.poro = torch.from_numpy(np.ascontiguousarray(case.poro.ravel()[cell_box])).to(self.dev)
+        self.dz = torch.tensor(np.asarray(case.dz, dtype=np.float64), **f64)
+        self.trans = torch.zeros(max(nf, 1), **f64)
+        self.pore_vol = torch.zeros(n, **f64)
+        self.depth = torch.zeros(n, **f64)
+        st = _stream()
+        _check(L.opm_geometry(nx, ny, nz, case.dx, case.dy, _ptr(self.dz), _ptr(self.perm_h),
+                              case.kv_kh, _ptr(self.poro), n, nf, _ptr(d["cell_box"]),
+                              _ptr(d["face_cells"]), _ptr(d["face_dir"]), _ptr(self.trans),
+                              _ptr(self.pore_vol), _ptr(self.depth), st), "opm_geometry")
+        # wells
+        wells = case.wells
+        nw = len(wells)
+        conn_cell = np.array([box_cell[case.box_index(*c)] for w in wells for c in w.cells],
+                             dtype=np.int32)
+        if np.any(conn_cell < 0):
+            raise ValueError("well connection in an inactive cell")
+        conn_well = np.array([k for k, w in enumerate(wells) for _ in w.cells], dtype=np.int32)
+        nc = len(conn_cell)
+        self.nc = nc
+        i32 = dict(dtype=torch.int32, device=self.dev)
+        self.well_kind = torch.tensor([w.kind for w in wells] + [0], **i32)
+        self.well_phase = torch.tensor([w.phase for w in wells] + [0], **i32)
+        self.well_target = torch.tensor([w.target for w in wells] + [0.0], **f64)
+        self.well_rw = torch.tensor([w.rw for w in wells] + [1.0], **f64)
+        self.conn_cell = torch.from_numpy(np.append(conn_cell, 0).astype(np.int32)).to(self.dev)
+        self.conn_well = torch.from_numpy(np.append(conn_well, 0).astype(np.int32)).to(self.dev)
+        m = max(nc, 1)
+        self.conn_wi = torch.zeros(m, **f64)
+        self.conn_rate = torch.zeros(m, **f64)
+        self.conn_bhp = torch.zeros(m, **f64)
+        self.conn_kind = torch.zeros(m, **i32)
+        self.conn_phase = torch.zeros(m, **i32)
+        _check(L.opm_well_index(nx, ny, case.dx, case.dy, _ptr(self.dz), _ptr(self.perm_h),
+                                _ptr(d["cell_box"]), nw, _ptr(self.well_kind),
+                                _ptr(self.well_phase), _ptr(self.well_target), _ptr(self.well_rw),
+                                nc, _ptr(self.conn_cell), _ptr(self.conn_well), _ptr(self.conn_wi),
+                                _ptr(self.conn_rate), _ptr(self.conn_kind), _ptr(self.conn_phase),
+                                _ptr(self.conn_bhp), st), "opm_well_index")
+        ccp = np.zeros(n + 1, np.int32)
+        cc = np.zeros(m, np.int32)
+        cc_src = np.append(conn_cell, 0).astype(np.int32)
+        _check(L.opm_well_groups(n, nc, cc_src.ctypes.data, ccp.ctypes.data, cc.ctypes.data),
+               "opm_well_groups")
+        self.cell_conn_ptr = torch.from_numpy(ccp).to(self.dev)
+        self.cell_conn = torch.from_numpy(cc).to(self.dev)
+        f = case.fluid
+        fl = Fluid((ctypes.c_double * 3)(*f.rho_s), (ctypes.c_double * 3)(*f.c), f.p_ref,
+                   (ctypes.c_double * 3)(*f.mu), f.swc, f.n_corey, f.g)
+        self.pb = Problem(
+            n_cells=n, n_faces=nf, nnzb=nnzb, n_levels=self.n_levels, max_level=self.max_level,
+            n_conns=nc, trans=self.trans.data_ptr(), pore_vol=self.pore_vol.data_ptr(),
+            depth=self.depth.data_ptr(), row_ptr=d["row_ptr"].data_ptr(),
+            col_idx=d["col_idx"].data_ptr(), blk_face=d["blk_face"].data_ptr(),
+            face_cells=d["face_cells"].data_ptr(), diag_pos=d["diag_pos"].data_ptr(),
+            level_ptr=d["level_ptr"].data_ptr(), level_ptr_h=self.level_ptr_h.ctypes.data,
+            perm=d["perm"].data_ptr(), iperm=d["iperm"].data_ptr(), lo_blk=d["lo_blk"].data_ptr(),
+            lo_tblk=d["lo_tblk"].data_ptr(), lo_pos=d["lo_pos"].data_ptr(),
+            up_blk=d["up_blk"].data_ptr(), up_pos=d["up_pos"].data_ptr(),
+            cell_conn_ptr=self.cell_conn_ptr.data_ptr(), cell_conn=self.cell_conn.data_ptr(),
+            conn_kind=self.conn_kind.data_ptr(), conn_phase=self.conn_phase.data_ptr(),
+            conn_wi=self.conn_wi.data_ptr(), conn_rate=self.conn_rate.data_ptr(),
+            conn_bhp=self.conn_bhp.data_ptr(), fluid=fl)
+        self._work = {}
+        torch.cuda.current_stream().synchronize()
+
+    # ------------------------------------------------------------ helpers
+    def _pbp(self):
+        return ctypes.byref(self.pb)
+
+    def zeros_state(self):
+        return torch.zeros((self.n, 3), dtype=torch.float64, device=self.dev)
+
+    def state(self, y) -> torch.Tensor:
+        return torch.as_tensor(np.ascontiguousarray(y, dtype=np.float64)).to(self.dev).contiguous()
+
+    def initial_state(self) -> torch.Tensor:
+        return self.state(self.case.initial_state())
+
+    def pattern(self):
+        return (self.host["row_ptr"][:self.n + 1].copy(), self.host["col_idx"][:self.nnzb].copy())
+
+    def workspace(self, kind: str, nbytes: int) -> torch.Tensor:
+        w = self._work.get(kind)
+        if w is None or w.numel() < nbytes:
+            w = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.dev)
+            self._work[kind] = w
+        return w
+
+    # ------------------------------------------------------------ path steps
+    def accumulation(self, y: torch.Tensor) -> torch.Tensor:
+        acc = self.zeros_state()
+        _check(lib().opm_accumulation(self._pbp(), _ptr(y), _ptr(acc), _stream()),
+               "opm_accumulation")
+        return acc
+
+    def assemble(self, y, acc0, dt, jacobian=True, norms=True):
+        L = lib()
+        R = self.zeros_state()
+        J = torch.zeros((self.nnzb, 3, 3), dtype=torch.float64, device=self.dev) if jacobian else None
+        nb = None
+        if norms:
+            nb = torch.zeros(L.opm_norms_bytes(self._pbp()) // 8, dtype=torch.float64,
+                             device=self.dev)
+        _check(L.opm_assemble(self._pbp(), _ptr(y), _ptr(acc0), dt, _ptr(R), _ptr(J), _ptr(nb),
+                              _stream()), "opm_assemble")
+        return R, J, (nb[:8] if norms else None)
+
+    def ilu0_factor(self, J, precision=PREC_FP64):
+        L = lib()
+        ilu = torch.zeros(L.opm_ilu0_bytes(self._pbp(), precision), dtype=torch.uint8,
+                          device=self.dev)
+        status = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        _check(L.opm_ilu0_factor(self._pbp(), _ptr(J), _ptr(ilu), precision, _ptr(status),
+                                 _stream()), "opm_ilu0_factor")
+        return ilu, status
+
+    def ilu0_apply(self, ilu, r, precision=PREC_FP64):
+        x = self.zeros_state()
+        _check(lib().opm_ilu0_apply(self._pbp(), _ptr(ilu), precision, _ptr(r), _ptr(x),
+                                    _stream()), "opm_ilu0_apply")
+        return x
+
+    def spmv(self, J, x):
+        y = self.zeros_state()
+        _check(lib().opm_spmv(self._pbp(), _ptr(J), _ptr(x), _ptr(y), _stream()), "opm_spmv")
+        return y
+
+    def bicgstab(self, J, ilu, b, rtol=1e-6, maxit=500, precision=PREC_FP64):
+        L = lib()
+        x = self.zeros_state()
+        work = self.workspace("krylov", L.opm_krylov_bytes(self._pbp()))
+        rep = SolveReport()
+        _check(L.opm_bicgstab(self._pbp(), _ptr(J), _ptr(ilu), precision, _ptr(b), _ptr(x), rtol,
+                              maxit, _ptr(work), ctypes.byref(rep), _stream()), "opm_bicgstab")
+        return x, rep
+
+    def newton_step(self, y, y_prev, dt, opts: Optional[NewtonOpts] = None):
+        L = lib()
+        o = opts or default_opts(self.case)
+        work = self.workspace(f"newton{o.precision}", L.opm_newton_bytes(self._pbp(), o.precision))
+        rep = NewtonReport()
+        st = L.opm_newton_step(self._pbp(), _ptr(y), _ptr(y_prev), dt, ctypes.byref(o),
+                               _ptr(work), ctypes.byref(rep), _stream())
+        if st in (EINVAL, EHIP):
+            _check(st, "opm_newton_step")
+        return st, rep
+
+    def advance(self, y, dt, opts: Optional[NewtonOpts] = None):
+        L = lib()
+        o = opts or default_opts(self.case)
+        work = self.workspace(f"newton{o.precision}", L.opm_newton_bytes(self._pbp(), o.precision))
+        ysave = self.workspace("ysave", 24 * self.n).view(torch.float64)[:3 * self.n].view(self.n, 3)
+        rep = NewtonReport()
+        st = L.opm_advance(self._pbp(), _ptr(y), dt, ctypes.byref(o), _ptr(work), _ptr(ysave),
+                           ctypes.byref(rep), _stream())
+        if st in (EINVAL, EHIP):
+            _check(st, "opm_advance")
+        return st, rep
+
+    def run(self, y=None, n_steps=None, opts=None, keep_states=True):
+        """Advance over the case's report schedule (raises on a failed step)."""
+        y = self.initial_state() if y is None else y
+        states, reps = [], []
+        for dt in self.case.report_dt[:n_steps]:
+            st, rep = self.advance(y, dt, opts)
+            if st != OK:
+                raise OpmError(st, "opm_advance")
+            if keep_states:
+                states.append(y.detach().cpu().numpy().copy())
+            reps.append(rep.as_dict())
+        return y, states, reps
