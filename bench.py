@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the Newton linearisation and solve on one MI355X.
+
+Workload: the 24x25x15 waterflood (9000 active cells, lognormal layered
+permeability, one rate injector over the (0,0) column, four BHP producers),
+FP64 state, block-ILU(0) BiCGStab to 1e-6, Newton to CNV 1e-8 / MB 1e-11.
+One benchmark step is one 10-day implicit time step: every Newton iteration
+assembles the residual and Jacobian by AD, tests convergence, factors
+ILU(0), solves with BiCGStab and applies the chopped update, all in the HIP
+kernels of libopm_gpu.so.  Inputs are resident in HBM before timing starts.
+
+Metric: cell-Newton-iterations per second = sum over timed Newton iterations
+of the active cell count / wall time of the timed steps.
+
+Also printed on the same JSON line:
+  roofline      the dominant kernel's algorithmic bytes per launch / its
+                average launch time (HIP events around repeated launches of
+                the same kernel on the same stream, inside this run), against
+                the 8 TB/s HBM peak;
+  cpu_baseline  the CPU oracle (plain FP64 C, one thread) on a bounded sample
+                of the same workload, on this machine's host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "cell-Newton-iterations/s (assembly+ILU0-BiCGStab) & % HBM roofline vs plain FP64"
+
+
+def sweep_bytes_per_cell(precision: int) -> float:
+    """Algorithmic bytes of one preconditioner application (forward plus
+    backward sweep) per cell: three lower and three upper off-diagonal blocks
+    read once, D^{-1} read in both sweeps, the right-hand side read, the
+    result written by the forward sweep and updated by the backward sweep,
+    plus the level-order index tables (perm twice, lower and upper positions)."""
+    w = 8 if precision == 0 else 4
+    blocks = (27 + 27) * w + 2 * 9 * w
+    vectors = 24 + 24 + 24 + 24
+    index = 4 * 2 + 12 + 12
+    return blocks + vectors + index
+
+
+def spmv_bytes_per_cell(nnzb: int, n: int) -> float:
+    """Algorithmic bytes of y = J x per block row: every 3x3 FP64 block and
+    its column index once, the row pointer, x once and y once."""
+    return (72 + 4) * nnzb / n + 4 + 24 + 24
+
+
+def assemble_bytes(n: int, nnzb: int, nf: int) -> float:
+    """Algorithmic bytes of one assembly: per cell the state, A0, pore volume,
+    depth, row pointer and well pointer read and the residual written; per
+    block the 3x3 FP64 block written and its column and face index read; per
+    face the transmissibility read once."""
+    return n * (24 + 24 + 8 + 8 + 4 + 4 + 24) + nnzb * (72 + 4 + 4) + nf * 8
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 FP32 ILU(0) factors")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="time budget of the CPU-oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the path is single-GPU; --gpus {args.gpus} "
+              "is not supported)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1910_06059_amd import cases, opm
+
+    torch.cuda.set_device(0)
+    case = cases.config2()
+    g = opm.GpuModel(case, device="cuda:0")
+    opts = opm.default_opts(case, precision=args.precision)
+    dt = case.report_dt[0]
+    y = g.initial_state()
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        st, rep = g.advance(y, dt, opts)
+        if st != opm.OK:
+            raise RuntimeError(f"warm-up step failed: {opm._strerror(st)}")
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, rep = g.advance(y, dt, opts)
+        if st != opm.OK:
+            raise RuntimeError(f"timed step failed: {opm._strerror(st)}")
+        reps.append(rep.as_dict())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cni = sum(r["cell_newton_its"] for r in reps)
+    newton = sum(r["newton_its"] for r in reps)
+    lin = sum(r["lin_its"] for r in reps)
+    value = cni / wall
+
+    # ---- dominant kernel: HIP-event timing of repeated launches ------------
+    acc0 = g.accumulation(y)
+    yk = y.clone()
+    yk[:, 0] += 1e4   # a state off equilibrium: a representative system
+    R, J, _ = g.assemble(yk, acc0, dt)
+    ilu, status = g.ilu0_factor(J, args.precision)
+    r = R.clone()
+    x = g.zeros_state()
+    L = opm.lib()
+    pbp = g._pbp()
+    sp = opm._ptr
+    s = opm._stream()
+
+    def timed(fn, reps):
+        for _ in range(5):
+            fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    t_apply = timed(lambda: L.opm_ilu0_apply(pbp, sp(ilu), args.precision, sp(r), sp(x), s),
+                    args.kernel_reps)
+    t_spmv = timed(lambda: L.opm_spmv(pbp, sp(J), sp(r), sp(x), s), args.kernel_reps)
+    norms = torch.zeros(L.opm_norms_bytes(pbp) // 8, dtype=torch.float64, device=g.dev)
+    Rb = torch.empty_like(R)
+    Jb = torch.empty_like(J)
+    t_asm = timed(lambda: L.opm_assemble(pbp, sp(yk), sp(acc0), dt, sp(Rb), sp(Jb), sp(norms), s),
+                  args.kernel_reps)
+    n = g.n
+    sweep_b = sweep_bytes_per_cell(args.precision) * n
+    spmv_b = spmv_bytes_per_cell(g.nnzb, n) * n
+    asm_b = assemble_bytes(n, g.nnzb, g.nf)
+    kernels = {
+        "ilu0_apply": {"seconds": t_apply, "bytes": sweep_b,
+                       "kernel": "ilu0 forward+backward sweeps (k_apply_wg / k_fwd_level+k_bwd_level)"},
+        "spmv": {"seconds": t_spmv, "bytes": spmv_b, "kernel": "k_spmv"},
+        "assemble": {"seconds": t_asm, "bytes": asm_b, "kernel": "k_assemble+k_norms_final"},
+    }
+    # time share of each kernel class in one Newton iteration of the run
+    its_per_newton = lin / max(newton, 1)
+    share = {"ilu0_apply": 2 * its_per_newton * t_apply, "spmv": 2 * its_per_newton * t_spmv,
+             "assemble": t_asm}
+    dom = max(share, key=share.get)
+    k = kernels[dom]
+    achieved = k["bytes"] / k["seconds"] / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": k["kernel"], "avg_launch_us": round(k["seconds"] * 1e6, 3),
+                "bytes_per_launch": int(k["bytes"])}
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "cell-Newton-iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == 0 else "f64+f32-ilu",
+        "data": "synthetic",
+        "config": {"workload": "24x25x15 waterflood, 9000 cells, 10-day implicit steps",
+                   "n_cells": n, "nnzb": g.nnzb, "ilu_levels": g.n_levels,
+                   "newton_tol_cnv": case.tol_cnv, "lin_rtol": case.lin_rtol,
+                   "precision": "fp64" if args.precision == 0 else "mixed"},
+        "roofline": roofline,
+        "breakdown": {
+            "newton_its": newton, "lin_its_per_newton": round(its_per_newton, 2),
+            "t_assemble_s": round(sum(r["t_assemble"] for r in reps), 4),
+            "t_factor_s": round(sum(r["t_factor"] for r in reps), 4),
+            "t_krylov_s": round(sum(r["t_krylov"] for r in reps), 4),
+            "t_update_s": round(sum(r["t_update"] for r in reps), 4),
+            "kernels_us": {kk: round(v["seconds"] * 1e6, 2) for kk, v in kernels.items()},
+            "kernels_gbs": {kk: round(v["bytes"] / v["seconds"] / 1e9, 1) for kk, v in kernels.items()},
+        },
+    }
+
+    if not args.no_cpu:
+        import oracle
+        m = oracle.Model(case)
+        yo = case.initial_state()
+        c_cni, c_wall, c_steps = 0.0, 0.0, 0
+        while c_wall < args.cpu_seconds and c_steps < len(case.report_dt):
+            t1 = time.perf_counter()
+            ost, yo, orep = m.advance(yo, dt)
+            c_wall += time.perf_counter() - t1
+            if ost != 0:
+                break
+            c_cni += orep.cell_newton_its
+            c_steps += 1
+        line["cpu_baseline"] = {"value": round(c_cni / c_wall, 1), "unit": "cell-Newton-iterations/s",
+                                "cores": 1, "kind": "oracle",
+                                "sample": f"first {c_steps} of the 10-day steps of the same workload "
+                                          f"({c_wall:.1f} s, single-threaded plain C, -O2)"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -334,7 +334,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Args a) {
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      part[c] = a.dt * fabs(r[c].v) / (Ai.b[c] * pv);
+      // an exactly balanced cell contributes 0 (also when it has no pore volume)
+      part[c] = r[c].v == 0.0 ? 0.0 : a.dt * fabs(r[c].v) / (Ai.b[c] * pv);
       part[3 + c] = r[c].v;
       part[6 + c] = Ai.b[c];
     }
@@ -367,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_norms_final(const double* partials, 
   for (int b = threadIdx.x; b < nblk; b += kBlock) {
     const double* pb = partials + (size_t)b * kNormStride;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) part[c] = fmax(part[c], pb[c]);
+    for (int c = 0; c < 3; ++c) part[c] = nan_max(part[c], pb[c]);
 #pragma unroll
     for (int k = 3; k < kNormStride; ++k) part[k] += pb[k];
   }
@@ -383,8 +384,8 @@ __global__ __launch_bounds__(kBlock) void k_norms_final(const double* partials, 
       const double mb = dt * fabs(out[3 + c]) / (bbar * out[9]);
       norms[c] = out[c];
       norms[3 + c] = mb;
-      cmax = fmax(cmax, out[c]);
-      mmax = fmax(mmax, mb);
+      cmax = nan_max(cmax, out[c]);
+      mmax = nan_max(mmax, mb);
     }
     norms[6] = cmax;
     norms[7] = mmax;

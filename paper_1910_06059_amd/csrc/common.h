@@ -45,15 +45,20 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
+// max that propagates NaN (fmax would drop it and hide a non-finite residual)
+__device__ __forceinline__ double nan_max(double a, double b) {
+  return (a != a || a > b) ? a : b;
+}
+
 template <int NT>
 __device__ __forceinline__ double block_max(double v, double* sh) {
-  for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, kWave));
+  for (int off = kWave / 2; off > 0; off >>= 1) v = nan_max(v, __shfl_down(v, off, kWave));
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   __syncthreads();
   if (lane == 0) sh[w] = v;
   __syncthreads();
   double s = sh[0];
-  for (int k = 1; k < NT / kWave; ++k) s = fmax(s, sh[k]);
+  for (int k = 1; k < NT / kWave; ++k) s = nan_max(s, sh[k]);
   return s;
 }
 

@@ -11,30 +11,52 @@
 // factors as the natural order.  The triangular solves of M = LU become
 //   forward:  y_i = D_i^{-1} (r_i - sum_{k<i} A_ik y_k)        (y = D^{-1} w)
 //   backward: x_i = y_i - D_i^{-1} sum_{j>i} A_ij x_j .
-// The factor step also copies the off-diagonal blocks of each row into
-// level-ordered, structure-of-arrays storage so that the sweeps read them with
-// fully coalesced loads; in mixed precision these copies and D^{-1} are FP32.
 //
-// Two launch shapes: one workgroup that walks all levels with workgroup
-// barriers (small systems: no kernel launch per level), or one launch per
-// level over many workgroups (large systems).
+// Data layout: everything the sweeps read is in level order (position p of
+// the schedule, rows of one level contiguous) and structure-of-arrays
+// (element e of row p at [e * ns + p]), so a wavefront reads consecutive
+// addresses: the three lower and three upper off-diagonal blocks of each row,
+// D^{-1}, and a level-ordered scratch vector z that holds y after the
+// forward sweep and x after the backward sweep.  In mixed precision these
+// arrays are FP32 while D^{-1} is still computed in FP64.
+//
+// Launch shapes:
+//  - one workgroup walks all levels with workgroup barriers (systems whose
+//    widest level is small): the results of the previous level stay in an
+//    LDS window, and the matrix data of the next level is loaded before the
+//    barrier so that its latency overlaps the current level;
+//  - one launch per level over many workgroups (large systems).
+// Packing the off-diagonal blocks into level order does not depend on the
+// levels and runs as one wide kernel over all rows.
 #include "common.h"
 
 namespace opm {
 namespace {
 
-constexpr int kSweepBlock = 1024;
+constexpr int kWgThreads = 512;        // threads of the one-workgroup sweep
+constexpr int kFacThreads = 256;       // threads of the one-workgroup factorisation
+constexpr int kMaxWindowRows = 2048;   // widest level served by the one-workgroup sweep
+constexpr int kMaxFactorWindowRows = 640;
 
 inline size_t padded(int n) { return ((size_t)n + 63) / 64 * 64; }
 
 template <typename T>
 struct IluView {
   int ns;          // SoA stride (n padded to 64)
-  double* dinv64;  // [9][ns] FP64 pivots' inverses (factor recursion)
+  double* dinv64;  // [9][ns] FP64 inverse pivots (factor recursion)
   T* dinv;         // [9][ns] sweep copy (aliases dinv64 for FP64)
   T* lov;          // [27][ns] A_ik of the lower neighbours, slot-major
   T* upv;          // [27][ns] A_ij of the upper neighbours
+  T* z;            // [3][ns] level-ordered sweep scratch
 };
+
+template <typename T>
+size_t view_bytes(int n) {
+  const size_t ns = padded(n);
+  size_t b = sizeof(double) * 9 * ns;
+  if (sizeof(T) != sizeof(double)) b += sizeof(T) * 9 * ns;
+  return b + sizeof(T) * (27 + 27 + 3) * ns;
+}
 
 template <typename T>
 IluView<T> view(const opm_problem* pb, void* ilu) {
@@ -52,6 +74,8 @@ IluView<T> view(const opm_problem* pb, void* ilu) {
   v.lov = (T*)base;
   base += sizeof(T) * 27 * v.ns;
   v.upv = (T*)base;
+  base += sizeof(T) * 27 * v.ns;
+  v.z = (T*)base;
   return v;
 }
 
@@ -64,11 +88,13 @@ struct Topo {
   const int32_t* up_blk;
   const int32_t* up_pos;
   const int32_t* level_ptr;
+  int n, nlev, max_level;
 };
 
 Topo topo_of(const opm_problem* pb) {
-  return Topo{pb->perm, pb->diag_pos, pb->lo_blk, pb->lo_tblk, pb->lo_pos, pb->up_blk, pb->up_pos,
-              pb->level_ptr};
+  return Topo{pb->perm,   pb->diag_pos,  pb->lo_blk,   pb->lo_tblk, pb->lo_pos,
+              pb->up_blk, pb->up_pos,    pb->level_ptr, pb->n_cells, pb->n_levels,
+              pb->max_level};
 }
 
 // Inverse of a 3x3 block by cofactors; false on a zero or non-finite
@@ -100,50 +126,70 @@ __device__ __forceinline__ void mat3_mul(const double* A, const double* B, doubl
       C[3 * r + c] = A[3 * r] * B[c] + A[3 * r + 1] * B[3 + c] + A[3 * r + 2] * B[6 + c];
 }
 
+// ---------------------------------------------------------------- packing
+// Level-ordered SoA copies of the off-diagonal blocks (no level dependence).
 template <typename T>
-__device__ __forceinline__ void factor_row(const Topo& t, const double* J, IluView<T> v, int pos,
-                                           int32_t* status) {
+__global__ __launch_bounds__(kBlock) void k_pack(Topo t, const double* J, IluView<T> v) {
+  const int pos = blockIdx.x * kBlock + threadIdx.x;
+  if (pos >= t.n) return;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int bl = t.lo_blk[3 * pos + s];
+    const int bu = t.up_blk[3 * pos + s];
+    const double* Al = J + 9 * (size_t)(bl < 0 ? 0 : bl);
+    const double* Au = J + 9 * (size_t)(bu < 0 ? 0 : bu);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      v.lov[(size_t)(9 * s + e) * v.ns + pos] = bl < 0 ? (T)0 : (T)Al[e];
+      v.upv[(size_t)(9 * s + e) * v.ns + pos] = bu < 0 ? (T)0 : (T)Au[e];
+    }
+  }
+}
+
+// ---------------------------------------------------------- pivot recursion
+struct FacJob {
+  double D[9];       // A_ii
+  double Aik[3][9];  // lower blocks
+  double Aki[3][9];  // transposed blocks
+  int kp[3];         // level positions of the lower neighbours
+};
+
+__device__ __forceinline__ void load_fac(const Topo& t, const double* J, int pos, FacJob& j) {
   const int i = t.perm[pos];
-  double D[9];
   const double* Aii = J + 9 * (size_t)t.diag_pos[i];
 #pragma unroll
-  for (int e = 0; e < 9; ++e) D[e] = Aii[e];
+  for (int e = 0; e < 9; ++e) j.D[e] = Aii[e];
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     const int b = t.lo_blk[3 * pos + s];
-    T* dst = v.lov + (size_t)(9 * s) * v.ns + pos;
-    if (b < 0) {
-#pragma unroll
-      for (int e = 0; e < 9; ++e) dst[(size_t)e * v.ns] = (T)0;
-      continue;
-    }
-    const int kpos = t.lo_pos[3 * pos + s];
-    const double* Aik = J + 9 * (size_t)b;
-    const double* Aki = J + 9 * (size_t)t.lo_tblk[3 * pos + s];
-    double Dk[9], tmp[9], upd[9], aik[9];
+    j.kp[s] = b < 0 ? -1 : t.lo_pos[3 * pos + s];
+    const double* A = J + 9 * (size_t)(b < 0 ? 0 : b);
+    const double* B = J + 9 * (size_t)(b < 0 ? 0 : t.lo_tblk[3 * pos + s]);
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
-      Dk[e] = v.dinv64[(size_t)e * v.ns + kpos];
-      aik[e] = Aik[e];
-      dst[(size_t)e * v.ns] = (T)aik[e];
+      j.Aik[s][e] = A[e];
+      j.Aki[s][e] = B[e];
     }
-    mat3_mul(aik, Dk, tmp);   // L_ik = A_ik D_k^{-1}
-    double aki[9];
+  }
+}
+
+// D = A_ii - sum_k A_ik D_k^{-1} A_ki, then D^{-1}; `dk` fetches D_k^{-1}.
+template <typename T, typename DkFn>
+__device__ __forceinline__ void finish_fac(const FacJob& j, int pos, IluView<T> v, DkFn dk,
+                                           int32_t* status, double* inv) {
+  double D[9];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) aki[e] = Aki[e];
-    mat3_mul(tmp, aki, upd);
+  for (int e = 0; e < 9; ++e) D[e] = j.D[e];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    if (j.kp[s] < 0) continue;
+    double Dk[9], tmp[9], upd[9];
+    dk(j.kp[s], Dk);
+    mat3_mul(j.Aik[s], Dk, tmp);   // L_ik = A_ik D_k^{-1}
+    mat3_mul(tmp, j.Aki[s], upd);
 #pragma unroll
     for (int e = 0; e < 9; ++e) D[e] -= upd[e];
   }
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    const int b = t.up_blk[3 * pos + s];
-    T* dst = v.upv + (size_t)(9 * s) * v.ns + pos;
-    const double* Aij = J + 9 * (size_t)(b < 0 ? 0 : b);
-#pragma unroll
-    for (int e = 0; e < 9; ++e) dst[(size_t)e * v.ns] = b < 0 ? (T)0 : (T)Aij[e];
-  }
-  double inv[9];
   if (!inverse3(D, inv)) {
     if (status) *status = OPM_ESINGULAR;
 #pragma unroll
@@ -157,74 +203,148 @@ __device__ __forceinline__ void factor_row(const Topo& t, const double* J, IluVi
 }
 
 template <typename T>
-__device__ __forceinline__ void fwd_row(const Topo& t, IluView<T> v, int pos, const double* r,
-                                        double* x) {
-  const int i = t.perm[pos];
-  T acc[3] = {(T)r[3 * i], (T)r[3 * i + 1], (T)r[3 * i + 2]};
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    const int kpos = t.lo_pos[3 * pos + s];
-    if (kpos < 0) continue;
-    const int k = t.perm[kpos];
-    const T yk[3] = {(T)x[3 * k], (T)x[3 * k + 1], (T)x[3 * k + 2]};
-    const T* L = v.lov + (size_t)(9 * s) * v.ns + pos;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc[a] -= L[(size_t)(3 * a + c) * v.ns] * yk[c];
-  }
-  const T* Di = v.dinv + pos;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    T s = Di[(size_t)(3 * a) * v.ns] * acc[0] + Di[(size_t)(3 * a + 1) * v.ns] * acc[1] +
-          Di[(size_t)(3 * a + 2) * v.ns] * acc[2];
-    x[3 * i + a] = (double)s;
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void bwd_row(const Topo& t, IluView<T> v, int pos, double* x) {
-  const int i = t.perm[pos];
-  T acc[3] = {(T)0, (T)0, (T)0};
-  bool any = false;
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    const int jpos = t.up_pos[3 * pos + s];
-    if (jpos < 0) continue;
-    any = true;
-    const int j = t.perm[jpos];
-    const T xj[3] = {(T)x[3 * j], (T)x[3 * j + 1], (T)x[3 * j + 2]};
-    const T* U = v.upv + (size_t)(9 * s) * v.ns + pos;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc[a] += U[(size_t)(3 * a + c) * v.ns] * xj[c];
-  }
-  if (!any) return;
-  const T* Di = v.dinv + pos;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    T s = Di[(size_t)(3 * a) * v.ns] * acc[0] + Di[(size_t)(3 * a + 1) * v.ns] * acc[1] +
-          Di[(size_t)(3 * a + 2) * v.ns] * acc[2];
-    x[3 * i + a] -= (double)s;
-  }
-}
-
-// ---- one launch per level -------------------------------------------------
-template <typename T>
 __global__ __launch_bounds__(kBlock) void k_factor_level(Topo t, const double* J, IluView<T> v,
                                                           int p0, int p1, int32_t* status) {
   const int pos = p0 + blockIdx.x * kBlock + threadIdx.x;
-  if (pos < p1) factor_row<T>(t, J, v, pos, status);
+  if (pos >= p1) return;
+  FacJob j;
+  load_fac(t, J, pos, j);
+  double inv[9];
+  finish_fac<T>(j, pos, v,
+                [&](int kp, double* Dk) {
+#pragma unroll
+                  for (int e = 0; e < 9; ++e) Dk[e] = v.dinv64[(size_t)e * v.ns + kp];
+                },
+                status, inv);
+}
+
+// One workgroup walks all levels.  With WINDOW the inverse pivots of the
+// previous level are also kept in LDS (2 buffers of max_level x 9 doubles).
+template <typename T, bool WINDOW>
+__global__ __launch_bounds__(kFacThreads) void k_factor_wg(Topo t, const double* J, IluView<T> v,
+                                                           int32_t* status) {
+  extern __shared__ double win[];
+  const int L = t.max_level;
+  FacJob next;
+  int npos = t.level_ptr[0] + threadIdx.x;
+  if (npos < t.level_ptr[1]) load_fac(t, J, npos, next);
+  int prev0 = 0, prev1 = 0, buf = 0;
+  for (int l = 0; l < t.nlev; ++l) {
+    const int p0 = t.level_ptr[l], p1 = t.level_ptr[l + 1];
+    for (int pos = p0 + threadIdx.x; pos < p1; pos += kFacThreads) {
+      FacJob cur;
+      if (pos == p0 + (int)threadIdx.x)
+        cur = next;
+      else
+        load_fac(t, J, pos, cur);
+      double inv[9];
+      finish_fac<T>(cur, pos, v,
+                    [&](int kp, double* Dk) {
+                      if (WINDOW && kp >= prev0 && kp < prev1) {
+                        const double* w = win + (size_t)((buf ^ 1) * L + (kp - prev0)) * 9;
+#pragma unroll
+                        for (int e = 0; e < 9; ++e) Dk[e] = w[e];
+                      } else {
+#pragma unroll
+                        for (int e = 0; e < 9; ++e) Dk[e] = v.dinv64[(size_t)e * v.ns + kp];
+                      }
+                    },
+                    status, inv);
+      if (WINDOW) {
+        double* w = win + (size_t)(buf * L + (pos - p0)) * 9;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) w[e] = inv[e];
+      }
+    }
+    if (l + 1 < t.nlev) {
+      npos = p1 + threadIdx.x;
+      if (npos < t.level_ptr[l + 2]) load_fac(t, J, npos, next);
+    }
+    __syncthreads();
+    prev0 = p0;
+    prev1 = p1;
+    buf ^= 1;
+  }
+}
+
+// -------------------------------------------------------------- sweeps
+template <typename T>
+struct SweepJob {
+  T a[27];    // three neighbour blocks
+  T D[9];     // D^{-1}
+  T rhs[3];   // r_i (forward) or y_i (backward)
+  int kp[3];  // neighbour positions (-1 if absent)
+  int cell;
+};
+
+// lower: forward-sweep data of row pos (r gathered from natural order)
+template <typename T>
+__device__ __forceinline__ void load_fwd(const Topo& t, IluView<T> v, const double* r, int pos,
+                                         SweepJob<T>& j) {
+  j.cell = t.perm[pos];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) j.rhs[c] = (T)r[3 * j.cell + c];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) j.kp[s] = t.lo_pos[3 * pos + s];
+#pragma unroll
+  for (int e = 0; e < 27; ++e) j.a[e] = v.lov[(size_t)e * v.ns + pos];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) j.D[e] = v.dinv[(size_t)e * v.ns + pos];
+}
+
+template <typename T>
+__device__ __forceinline__ void load_bwd(const Topo& t, IluView<T> v, int pos, SweepJob<T>& j) {
+  j.cell = t.perm[pos];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) j.rhs[c] = v.z[(size_t)c * v.ns + pos];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) j.kp[s] = t.up_pos[3 * pos + s];
+#pragma unroll
+  for (int e = 0; e < 27; ++e) j.a[e] = v.upv[(size_t)e * v.ns + pos];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) j.D[e] = v.dinv[(size_t)e * v.ns + pos];
+}
+
+// forward: y = D^{-1} (r - sum_s A_s y_{k_s});  backward: x = y - D^{-1} sum_s A_s x_{k_s}
+template <typename T, bool FWD, typename NbrFn>
+__device__ __forceinline__ void solve_row(const SweepJob<T>& j, NbrFn nbr, T* out) {
+  T acc[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) acc[c] = FWD ? j.rhs[c] : (T)0;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    if (j.kp[s] < 0) continue;
+    T xv[3];
+    nbr(j.kp[s], xv);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T t = j.a[9 * s + 3 * a] * xv[0] + j.a[9 * s + 3 * a + 1] * xv[1] +
+                  j.a[9 * s + 3 * a + 2] * xv[2];
+      acc[a] = FWD ? acc[a] - t : acc[a] + t;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T d = j.D[3 * a] * acc[0] + j.D[3 * a + 1] * acc[1] + j.D[3 * a + 2] * acc[2];
+    out[a] = FWD ? d : j.rhs[a] - d;
+  }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fwd_level(Topo t, IluView<T> v, int p0, int p1,
-                                                       const double* r, double* x,
-                                                       const int32_t* skip) {
+                                                       const double* r, const int32_t* skip) {
   if (skip && *skip != 0) return;
   const int pos = p0 + blockIdx.x * kBlock + threadIdx.x;
-  if (pos < p1) fwd_row<T>(t, v, pos, r, x);
+  if (pos >= p1) return;
+  SweepJob<T> j;
+  load_fwd(t, v, r, pos, j);
+  T y[3];
+  solve_row<T, true>(j, [&](int kp, T* xv) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xv[c] = v.z[(size_t)c * v.ns + kp];
+  }, y);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v.z[(size_t)c * v.ns + pos] = y[c];
 }
 
 template <typename T>
@@ -232,38 +352,127 @@ __global__ __launch_bounds__(kBlock) void k_bwd_level(Topo t, IluView<T> v, int 
                                                        double* x, const int32_t* skip) {
   if (skip && *skip != 0) return;
   const int pos = p0 + blockIdx.x * kBlock + threadIdx.x;
-  if (pos < p1) bwd_row<T>(t, v, pos, x);
-}
-
-// ---- one workgroup walks every level --------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kSweepBlock) void k_factor_wg(Topo t, const double* J, IluView<T> v,
-                                                            int nlev, int32_t* status) {
-  for (int l = 0; l < nlev; ++l) {
-    const int p1 = t.level_ptr[l + 1];
-    for (int pos = t.level_ptr[l] + threadIdx.x; pos < p1; pos += kSweepBlock)
-      factor_row<T>(t, J, v, pos, status);
-    __syncthreads();
+  if (pos >= p1) return;
+  SweepJob<T> j;
+  load_bwd(t, v, pos, j);
+  T xo[3];
+  solve_row<T, false>(j, [&](int kp, T* xv) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xv[c] = v.z[(size_t)c * v.ns + kp];
+  }, xo);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    v.z[(size_t)c * v.ns + pos] = xo[c];
+    x[3 * j.cell + c] = (double)xo[c];
   }
 }
 
+// One workgroup applies the whole preconditioner.  The window holds the
+// values of the level just finished (2 buffers of max_level x 3 entries).
 template <typename T>
-__global__ __launch_bounds__(kSweepBlock) void k_apply_wg(Topo t, IluView<T> v, int nlev,
-                                                           const double* r, double* x,
-                                                           const int32_t* skip) {
+__global__ __launch_bounds__(kWgThreads) void k_apply_wg(Topo t, IluView<T> v, const double* r,
+                                                          double* x, const int32_t* skip) {
   if (skip && *skip != 0) return;
-  for (int l = 0; l < nlev; ++l) {
-    const int p1 = t.level_ptr[l + 1];
-    for (int pos = t.level_ptr[l] + threadIdx.x; pos < p1; pos += kSweepBlock)
-      fwd_row<T>(t, v, pos, r, x);
+  extern __shared__ unsigned char smem[];
+  T* win = reinterpret_cast<T*>(smem);
+  const int L = t.max_level;
+  const int tid = threadIdx.x;
+  // ---- forward sweep, levels ascending
+  SweepJob<T> next;
+  if (t.level_ptr[0] + tid < t.level_ptr[1]) load_fwd(t, v, r, t.level_ptr[0] + tid, next);
+  int prev0 = 0, prev1 = 0, buf = 0;
+  for (int l = 0; l < t.nlev; ++l) {
+    const int p0 = t.level_ptr[l], p1 = t.level_ptr[l + 1];
+    for (int pos = p0 + tid; pos < p1; pos += kWgThreads) {
+      SweepJob<T> cur;
+      if (pos == p0 + tid)
+        cur = next;
+      else
+        load_fwd(t, v, r, pos, cur);
+      T y[3];
+      solve_row<T, true>(cur, [&](int kp, T* xv) {
+        if (kp >= prev0 && kp < prev1) {
+          const T* w = win + (size_t)((buf ^ 1) * L + (kp - prev0)) * 3;
+          xv[0] = w[0];
+          xv[1] = w[1];
+          xv[2] = w[2];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) xv[c] = v.z[(size_t)c * v.ns + kp];
+        }
+      }, y);
+      T* w = win + (size_t)(buf * L + (pos - p0)) * 3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        w[c] = y[c];
+        v.z[(size_t)c * v.ns + pos] = y[c];
+      }
+    }
+    if (l + 1 < t.nlev && p1 + tid < t.level_ptr[l + 2]) load_fwd(t, v, r, p1 + tid, next);
     __syncthreads();
+    prev0 = p0;
+    prev1 = p1;
+    buf ^= 1;
   }
-  for (int l = nlev - 1; l >= 0; --l) {
-    const int p1 = t.level_ptr[l + 1];
-    for (int pos = t.level_ptr[l] + threadIdx.x; pos < p1; pos += kSweepBlock)
-      bwd_row<T>(t, v, pos, x);
+  // ---- backward sweep, levels descending; z[pos] turns from y into x
+  {
+    const int l = t.nlev - 1;
+    if (t.level_ptr[l] + tid < t.level_ptr[l + 1]) load_bwd(t, v, t.level_ptr[l] + tid, next);
+  }
+  prev0 = prev1 = 0;
+  for (int l = t.nlev - 1; l >= 0; --l) {
+    const int p0 = t.level_ptr[l], p1 = t.level_ptr[l + 1];
+    for (int pos = p0 + tid; pos < p1; pos += kWgThreads) {
+      SweepJob<T> cur;
+      if (pos == p0 + tid)
+        cur = next;
+      else
+        load_bwd(t, v, pos, cur);
+      T xo[3];
+      solve_row<T, false>(cur, [&](int kp, T* xv) {
+        if (kp >= prev0 && kp < prev1) {
+          const T* w = win + (size_t)((buf ^ 1) * L + (kp - prev0)) * 3;
+          xv[0] = w[0];
+          xv[1] = w[1];
+          xv[2] = w[2];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) xv[c] = v.z[(size_t)c * v.ns + kp];
+        }
+      }, xo);
+      T* w = win + (size_t)(buf * L + (pos - p0)) * 3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        w[c] = xo[c];
+        v.z[(size_t)c * v.ns + pos] = xo[c];
+        x[3 * cur.cell + c] = (double)xo[c];
+      }
+    }
+    if (l > 0 && t.level_ptr[l - 1] + tid < p0) load_bwd(t, v, t.level_ptr[l - 1] + tid, next);
     __syncthreads();
+    prev0 = p0;
+    prev1 = p1;
+    buf ^= 1;
   }
+}
+
+template <typename T>
+size_t apply_lds(const opm_problem* pb) {
+  return sizeof(T) * 2 * 3 * (size_t)pb->max_level;
+}
+
+size_t factor_lds(const opm_problem* pb) { return sizeof(double) * 2 * 9 * (size_t)pb->max_level; }
+
+bool g_lds_attr_set[4] = {false, false, false, false};
+
+template <typename K>
+int allow_lds(K kernel, int slot) {
+  if (!g_lds_attr_set[slot]) {
+    OPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    g_lds_attr_set[slot] = true;
+  }
+  return OPM_OK;
 }
 
 template <typename T>
@@ -271,9 +480,17 @@ int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* stat
                 hipStream_t s) {
   IluView<T> v = view<T>(pb, ilu);
   Topo t = topo_of(pb);
+  hipLaunchKernelGGL(k_pack<T>, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock), 0, s, t, J,
+                     v);
   if (mode == 0) {
-    hipLaunchKernelGGL(k_factor_wg<T>, dim3(1), dim3(kSweepBlock), 0, s, t, J, v, pb->n_levels,
-                       status);
+    if (pb->max_level <= kMaxFactorWindowRows) {
+      OPM_TRY(allow_lds(k_factor_wg<T, true>, sizeof(T) == 8 ? 0 : 1));
+      hipLaunchKernelGGL((k_factor_wg<T, true>), dim3(1), dim3(kFacThreads), factor_lds(pb), s, t,
+                         J, v, status);
+    } else {
+      hipLaunchKernelGGL((k_factor_wg<T, false>), dim3(1), dim3(kFacThreads), 0, s, t, J, v,
+                         status);
+    }
     OPM_TRY_HIP(hipGetLastError());
     return OPM_OK;
   }
@@ -292,7 +509,8 @@ int apply_impl(const opm_problem* pb, void* ilu, const double* r, double* x, int
   IluView<T> v = view<T>(pb, ilu);
   Topo t = topo_of(pb);
   if (mode == 0) {
-    hipLaunchKernelGGL(k_apply_wg<T>, dim3(1), dim3(kSweepBlock), 0, s, t, v, pb->n_levels, r, x,
+    OPM_TRY(allow_lds(k_apply_wg<T>, sizeof(T) == 8 ? 2 : 3));
+    hipLaunchKernelGGL(k_apply_wg<T>, dim3(1), dim3(kWgThreads), apply_lds<T>(pb), s, t, v, r, x,
                        skip);
     OPM_TRY_HIP(hipGetLastError());
     return OPM_OK;
@@ -300,7 +518,7 @@ int apply_impl(const opm_problem* pb, void* ilu, const double* r, double* x, int
   for (int l = 0; l < pb->n_levels; ++l) {
     const int p0 = pb->level_ptr_h[l], p1 = pb->level_ptr_h[l + 1];
     hipLaunchKernelGGL(k_fwd_level<T>, dim3(blocks_for(p1 - p0, kBlock)), dim3(kBlock), 0, s, t,
-                       v, p0, p1, r, x, skip);
+                       v, p0, p1, r, skip);
   }
   for (int l = pb->n_levels - 1; l >= 0; --l) {
     const int p0 = pb->level_ptr_h[l], p1 = pb->level_ptr_h[l + 1];
@@ -314,19 +532,21 @@ int apply_impl(const opm_problem* pb, void* ilu, const double* r, double* x, int
 }  // namespace
 
 size_t ilu_bytes(const opm_problem* pb, int precision) {
-  const size_t ns = padded(pb->n_cells);
-  if (precision == OPM_PREC_MIXED) return ns * (9 * sizeof(double) + 63 * sizeof(float));
-  return ns * 63 * sizeof(double);
+  return precision == OPM_PREC_MIXED ? view_bytes<float>(pb->n_cells)
+                                     : view_bytes<double>(pb->n_cells);
 }
 
-// Sweep shape: one workgroup for systems whose widest level fits in a few
-// passes of one workgroup, else one launch per level; g_sweep_mode (set by
-// opm_set_option) forces one of them.
+// Sweep shape: one workgroup when the widest level fits the LDS window and
+// the system is small enough for one compute unit, else one launch per
+// level; g_sweep_mode (set by opm_set_option) forces one of them.
 int g_sweep_mode = -1;
 
 int sweep_mode(const opm_problem* pb) {
-  if (g_sweep_mode == 0 || g_sweep_mode == 1) return g_sweep_mode;
-  return pb->max_level <= 4 * kSweepBlock && pb->n_cells <= 200000 ? 0 : 1;
+  if (g_sweep_mode == 0 || g_sweep_mode == 1) {
+    if (g_sweep_mode == 0 && pb->max_level > kMaxWindowRows) return 1;
+    return g_sweep_mode;
+  }
+  return pb->max_level <= kMaxWindowRows && pb->n_cells <= 200000 ? 0 : 1;
 }
 
 int ilu_factor(const opm_problem* pb, const double* J, void* ilu, int precision, int32_t* status,
