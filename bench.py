@@ -60,6 +60,25 @@ def assemble_bytes(n: int, nnzb: int, nf: int) -> float:
     return n * (24 + 24 + 8 + 8 + 4 + 4 + 24) + nnzb * (72 + 4 + 4) + nf * 8
 
 
+def measured_traffic(kernel_class: str, precision: int):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (profiles/counters.json, scaled by a plain
+    256 MiB copy), or None when there is no record or the kernel's source has
+    changed since the counters were taken."""
+    import hashlib
+    tags = {("ilu0_apply", 0): "c2_fp64_ilu0_sweep", ("ilu0_apply", 1): "c2_mixed_ilu0_sweep"}
+    tag = tags.get((kernel_class, precision))
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if tag is None or not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(tag)
+    if not rec or not rec.get("traffic_bytes"):
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return round(rec["traffic_bytes"]) if h == rec["source_sha256_16"] else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +89,9 @@ def main():
                     help="time budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run a plain device-to-device copy of this many MiB (a reference "
+                         "kernel for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the path is single-GPU; --gpus {args.gpus} "
@@ -133,6 +155,15 @@ def main():
         e1.synchronize()
         return e0.elapsed_time(e1) * 1e-3 / reps
 
+    if args.copy_probe_mb > 0:
+        nbytes = args.copy_probe_mb << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device=g.dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     t_apply = timed(lambda: L.opm_ilu0_apply(pbp, sp(ilu), args.precision, sp(r), sp(x), s),
                     args.kernel_reps)
     t_spmv = timed(lambda: L.opm_spmv(pbp, sp(J), sp(r), sp(x), s), args.kernel_reps)
@@ -159,7 +190,8 @@ def main():
     k = kernels[dom]
     achieved = k["bytes"] / k["seconds"] / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic(dom, args.precision),
                 "kernel": k["kernel"], "avg_launch_us": round(k["seconds"] * 1e6, 3),
                 "bytes_per_launch": int(k["bytes"])}
 
