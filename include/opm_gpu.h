@@ -291,6 +291,46 @@ int opm_newton_step(const opm_problem* pb, double* y, const double* y_prev, doub
 int opm_advance(const opm_problem* pb, double* y, double dt, const opm_newton_opts* opts,
                 void* work, double* y_save, opm_newton_report* report, void* stream);
 
+/* ------------------------------------------------------ batched ensemble --
+ * Many independent members (each a complete opm_problem of its own grid,
+ * rock and wells) advanced over n_steps report steps of length dt_report in
+ * one launch of a persistent kernel: one workgroup per member runs that
+ * member's time loop (substeps halved on failure, at most max_cuts
+ * halvings per report step), Newton iterations (sec. 2.3), assembly
+ * (sec. 2.1.1, 2.4), block ILU(0) and BiCGStab (sec. 2.3.1) entirely on the
+ * device.  Members never wait for each other.  The launch reads only device
+ * memory prepared by opm_ensemble_prepare, so it can be captured in a graph. */
+typedef struct opm_ensemble_report {
+  int32_t status;      /* OPM_OK, or the code of the step that failed      */
+  int32_t newton_its;  /* linear solves over all substeps                  */
+  int32_t lin_its;     /* BiCGStab iterations                              */
+  int32_t substeps;    /* accepted substeps                                */
+  int32_t cuts;        /* time-step halvings                               */
+  int32_t steps_done;  /* report steps completed                           */
+  double cell_newton_its;
+  double cnv[3], mb[3];   /* norms of the last Newton iteration           */
+} opm_ensemble_report;
+
+/* Device workspace of an ensemble (bytes); members: host array [n_members]
+ * of problems whose pointers are device memory. */
+size_t opm_ensemble_bytes(const opm_problem* members, int32_t n_members, int precision);
+
+/* Lay out the workspace (device, opm_ensemble_bytes) for the members and
+ * their states y[m] (host array of device pointers [n_cells_m][3], updated in
+ * place by the launches).  Host, synchronous (copies a member table to the
+ * device).  OPM_EINVAL if the widest ILU(0) level of a member does not fit
+ * the kernel's LDS window. */
+int opm_ensemble_prepare(const opm_problem* members, double* const* y, int32_t n_members,
+                         int precision, void* work, size_t work_bytes);
+
+/* One asynchronous launch advancing every member by n_steps report steps.
+ * max_level: the largest max_level of the members; reports: device
+ * [n_members].  opts->precision is ignored (the workspace's precision is
+ * passed explicitly). */
+int opm_ensemble_launch(const void* work, int32_t n_members, int precision, int32_t max_level,
+                        double dt_report, int32_t n_steps, const opm_newton_opts* opts,
+                        opm_ensemble_report* reports, void* stream);
+
 /* Process-wide tuning knobs (host, synchronous); they change speed, never
  * results beyond round-off.  Returns OPM_OK, or OPM_EINVAL for an unknown
  * option or value.

@@ -1,0 +1,343 @@
+// Device-side pieces of the residual and Jacobian assembly, shared by the
+// one-launch-per-step kernels (assemble.hip) and the persistent ensemble
+// kernel (ensemble.hip): dual numbers, cell properties, face flux and the
+// work of one block row.  Paper sec. 2.1.1 (eqs. materialbalance, flux1,
+// head), sec. 2.1.5 (eq. gwseg), sec. 2.1.6 (PVT), sec. 2.2.1 (eq.
+// wellinflow), sec. 2.4.1 (forward-mode AD).
+//
+// Floating-point contraction is disabled for everything in this header: a
+// face flux is evaluated by both of its cells, in the same orientation, and
+// the two evaluations must round identically (u_ij = -u_ji exactly).
+#pragma once
+#pragma clang fp contract(off)
+
+#include "common.h"
+
+namespace opm {
+namespace asmdev {
+
+// ---------------------------------------------------------- dual numbers
+template <int N>
+struct Dual {
+  double v;
+  double d[N];
+};
+
+template <int N>
+__device__ __forceinline__ Dual<N> cst(double v) {
+  Dual<N> r;
+  r.v = v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = 0.0;
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r;
+  r.v = a.v + b.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r;
+  r.v = a.v - b.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r;
+  r.v = a.v * b.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator*(const Dual<N>& a, double s) {
+  Dual<N> r;
+  r.v = a.v * s;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * s;
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator/(const Dual<N>& a, double s) {
+  Dual<N> r;
+  r.v = a.v / s;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = a.d[k] / s;
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> quot(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r;
+  r.v = a.v / b.v;
+  const double b2 = b.v * b.v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / b2;
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> dexp(const Dual<N>& a) {
+  Dual<N> r;
+  r.v = exp(a.v);
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = r.v * a.d[k];
+  return r;
+}
+// x^n for x >= 0, n >= 1 (Corey curves)
+template <int N>
+__device__ __forceinline__ Dual<N> dpow(const Dual<N>& a, double n) {
+  Dual<N> r;
+  double dv;
+  if (n == 2.0) {
+    r.v = a.v * a.v;
+    dv = 2.0 * a.v;
+  } else {
+    r.v = pow(a.v, n);
+    dv = n * pow(a.v, n - 1.0);
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = dv * a.d[k];
+  return r;
+}
+// clamp to [0, 1]; the argument passes through on the bounds themselves
+template <int N>
+__device__ __forceinline__ Dual<N> clamp01(const Dual<N>& a) {
+  if (a.v < 0.0) return cst<N>(0.0);
+  if (a.v > 1.0) return cst<N>(1.0);
+  return a;
+}
+// max(a, 0); the constant branch is taken at a == 0
+template <int N>
+__device__ __forceinline__ Dual<N> pos(const Dual<N>& a) {
+  return a.v > 0.0 ? a : cst<N>(0.0);
+}
+
+using D3 = Dual<3>;
+using D6 = Dual<6>;
+
+// Lift a cell quantity (derivatives w.r.t. the cell's own (p, sw, sg)) into
+// the face slots: slots 0-2 for the lower cell, 3-5 for the upper cell.
+__device__ __forceinline__ D6 lift(const D3& a, int side) {
+  D6 r;
+  r.v = a.v;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r.d[k] = side == 0 ? a.d[k] : 0.0;
+    r.d[3 + k] = side == 0 ? 0.0 : a.d[k];
+  }
+  return r;
+}
+
+// ------------------------------------------------------ cell properties
+struct FaceProps {
+  double p;
+  double rho[3], drho[3];   // density and d rho / dp (rho depends on p only)
+  D3 mob[3];                // b_alpha * lambda_alpha
+};
+
+// Element-wise select (keeps both operands in registers; a reference picked
+// at run time would force them to memory).
+__device__ __forceinline__ FaceProps pick(bool c, const FaceProps& x, const FaceProps& y) {
+  FaceProps r;
+  r.p = c ? x.p : y.p;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r.rho[a] = c ? x.rho[a] : y.rho[a];
+    r.drho[a] = c ? x.drho[a] : y.drho[a];
+    r.mob[a].v = c ? x.mob[a].v : y.mob[a].v;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r.mob[a].d[k] = c ? x.mob[a].d[k] : y.mob[a].d[k];
+  }
+  return r;
+}
+
+struct CellAcc {
+  D3 A[3];                  // b_alpha s_alpha
+  double b[3];
+};
+
+// b = exp(c (p - p_ref)); rho = rho_S b; Corey curves with the segregation
+// model for three-phase oil; mob = b k_r / mu.
+__device__ __forceinline__ void properties(const opm_fluid& f, double p_v, double sw_v,
+                                           double sg_v, FaceProps& P, CellAcc* acc) {
+  D3 p = cst<3>(p_v);
+  p.d[0] = 1.0;
+  D3 sw = cst<3>(sw_v);
+  sw.d[1] = 1.0;
+  D3 sg = cst<3>(sg_v);
+  sg.d[2] = 1.0;
+  D3 so = (cst<3>(1.0) - sw) - sg;
+  D3 b[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) b[a] = dexp((p - cst<3>(f.p_ref)) * f.c[a]);
+  const double den = 1.0 - f.swc;
+  D3 krw = dpow(clamp01((sw - cst<3>(f.swc)) / den), f.n_corey);
+  D3 krg = dpow(clamp01(sg / den), f.n_corey);
+  D3 kr_o2 = dpow(clamp01(so / den), f.n_corey);   // k_row = k_rog (same curve)
+  D3 ww = pos(sw - cst<3>(f.swc));
+  D3 wg = pos(sg);
+  D3 wsum = ww + wg;
+  D3 kro = wsum.v > 1e-14 ? quot(ww * kr_o2 + wg * kr_o2, wsum) : kr_o2;
+  P.p = p_v;
+  const D3 kr[3] = {krw, kro, krg};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    P.rho[a] = f.rho_s[a] * b[a].v;
+    P.drho[a] = f.rho_s[a] * b[a].d[0];
+    P.mob[a] = b[a] * (kr[a] / f.mu[a]);
+  }
+  if (acc) {
+    const D3 s[3] = {sw, so, sg};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      acc->A[a] = b[a] * s[a];
+      acc->b[a] = b[a].v;
+    }
+  }
+}
+
+// Flux of component a from lower cell L to upper cell H through a face of
+// transmissibility T: (b lambda)_U T dPhi with dPhi = p_L - p_H -
+// g (rho_L + rho_H)/2 (z_L - z_H), U = L if dPhi >= 0 else H.
+__device__ __forceinline__ D6 face_flux(const FaceProps& L, const FaceProps& H, int a, double dz,
+                                        double T, double g) {
+  D6 pl = cst<6>(L.p);
+  pl.d[0] = 1.0;
+  D6 ph = cst<6>(H.p);
+  ph.d[3] = 1.0;
+  D6 rl = cst<6>(L.rho[a]);
+  rl.d[0] = L.drho[a];
+  D6 rh = cst<6>(H.rho[a]);
+  rh.d[3] = H.drho[a];
+  D6 rho_avg = (rl + rh) * 0.5;
+  D6 dphi = (pl - ph) - (rho_avg * g) * dz;
+  D6 mob = dphi.v >= 0.0 ? lift(L.mob[a], 0) : lift(H.mob[a], 1);
+  return mob * (dphi * T);
+}
+
+struct AsmArgs {
+  int n;
+  const double* y;
+  const double* acc0;
+  double dt;
+  const double* trans;
+  const double* pv;
+  const double* depth;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const int32_t* blk_face;
+  const int32_t* cell_conn_ptr;
+  const int32_t* cell_conn;
+  const int32_t* conn_kind;
+  const int32_t* conn_phase;
+  const double* conn_wi;
+  const double* conn_rate;
+  const double* conn_bhp;
+  opm_fluid fluid;
+  double* R;
+  double* J;
+  double* partials;   // [gridDim.x][kNormStride] or null
+};
+
+// Residual and Jacobian block row of cell i (one lane): writes R_i, the
+// blocks J_i* (if a.J) and the cell's contributions to the CNV/MB norms:
+// part = (dt|R_a|/(b_a PV) for a = w,o,g; R_a; b_a; PV).
+__device__ __forceinline__ void assemble_row(const AsmArgs& a, int i, double dt,
+                                             double part[kNormStride]) {
+  const double yi0 = a.y[3 * i], yi1 = a.y[3 * i + 1], yi2 = a.y[3 * i + 2];
+  FaceProps Pi;
+  CellAcc Ai;
+  properties(a.fluid, yi0, yi1, yi2, Pi, &Ai);
+  const double pv = a.pv[i];
+  const double zi = a.depth[i];
+  D3 r[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r[c] = (Ai.A[c] - cst<3>(a.acc0[3 * i + c])) * (pv / dt);
+  const int q0 = a.row_ptr[i], q1 = a.row_ptr[i + 1];
+  int qd = q0;
+  for (int q = q0; q < q1; ++q) {
+    const int j = a.col_idx[q];
+    if (j == i) {
+      qd = q;
+      continue;
+    }
+    FaceProps Pj;
+    properties(a.fluid, a.y[3 * j], a.y[3 * j + 1], a.y[3 * j + 2], Pj, nullptr);
+    const double T = a.trans[a.blk_face[q]];
+    const double zj = a.depth[j];
+    const bool lower = i < j;
+    const FaceProps L = pick(lower, Pi, Pj);
+    const FaceProps H = pick(lower, Pj, Pi);
+    const double dz = lower ? zi - zj : zj - zi;
+    double blk[9];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      D6 F = face_flux(L, H, c, dz, T, a.fluid.g);
+      if (lower) {
+        r[c].v += F.v;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          r[c].d[v] += F.d[v];
+          blk[3 * c + v] = F.d[3 + v];
+        }
+      } else {
+        r[c].v -= F.v;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          r[c].d[v] -= F.d[3 + v];
+          blk[3 * c + v] = -F.d[v];
+        }
+      }
+    }
+    if (a.J) {
+      double* Jq = a.J + 9 * (size_t)q;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) Jq[e] = blk[e];
+    }
+  }
+  // wells of this cell (sec. 2.2.1): fixed-rate injector source or BHP
+  // producer q = b lambda WI (p - p_bhp)^+
+  for (int t = a.cell_conn_ptr[i]; t < a.cell_conn_ptr[i + 1]; ++t) {
+    const int k = a.cell_conn[t];
+    if (a.conn_kind[k] == OPM_WELL_RATE_INJ) {
+      const int ph = a.conn_phase[k];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (c == ph) r[c].v += a.conn_rate[k];
+    } else {
+      D3 dp = cst<3>(yi0 - a.conn_bhp[k]);
+      dp.d[0] = 1.0;
+      if (dp.v > 0.0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r[c] = r[c] + (Pi.mob[c] * a.conn_wi[k]) * dp;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) a.R[3 * i + c] = r[c].v;
+  if (a.J) {
+    double* Jd = a.J + 9 * (size_t)qd;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int v = 0; v < 3; ++v) Jd[3 * c + v] = r[c].d[v];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    // an exactly balanced cell contributes 0 (also when it has no pore volume)
+    part[c] = r[c].v == 0.0 ? 0.0 : dt * fabs(r[c].v) / (Ai.b[c] * pv);
+    part[3 + c] = r[c].v;
+    part[6 + c] = Ai.b[c];
+  }
+  part[9] = pv;
+}
+
+}  // namespace asmdev
+}  // namespace opm
+
+#pragma clang fp contract(fast)

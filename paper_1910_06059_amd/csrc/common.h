@@ -8,10 +8,15 @@
 
 #include "opm_gpu.h"
 
+// A failed HIP call is reported as OPM_EHIP; the runtime's last-error state
+// is cleared so that the caller's next HIP call does not inherit it.
 #define OPM_TRY_HIP(call)                      \
   do {                                         \
     hipError_t opm_e_ = (call);                \
-    if (opm_e_ != hipSuccess) return OPM_EHIP; \
+    if (opm_e_ != hipSuccess) {                \
+      (void)hipGetLastError();                 \
+      return OPM_EHIP;                         \
+    }                                          \
   } while (0)
 
 #define OPM_TRY(call)                \

@@ -12,7 +12,7 @@
 // between chunks.
 #include <algorithm>
 
-#include "common.h"
+#include "solver_dev.h"
 
 namespace opm {
 
@@ -71,22 +71,7 @@ __device__ __forceinline__ void store_partial(double v, double* part, double* sh
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// One block row of y = J x (3 outputs).
-__device__ __forceinline__ void spmv_row(const int32_t* row_ptr, const int32_t* col,
-                                         const double* J, const double* x, int i, double* y3) {
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
-    const int j = col[q];
-    const double* B = J + 9 * (size_t)q;
-    const double x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
-    a0 += B[0] * x0 + B[1] * x1 + B[2] * x2;
-    a1 += B[3] * x0 + B[4] * x1 + B[5] * x2;
-    a2 += B[6] * x0 + B[7] * x1 + B[8] * x2;
-  }
-  y3[0] = a0;
-  y3[1] = a1;
-  y3[2] = a2;
-}
+using ilu::spmv_row;
 
 __global__ __launch_bounds__(kBlock) void k_spmv(int n, const int32_t* row_ptr, const int32_t* col,
                                                   const double* J, const double* x, double* y) {

@@ -84,6 +84,7 @@ EXPORTS = [
     "opm_well_index", "opm_well_groups", "opm_accumulation", "opm_norms_bytes", "opm_assemble",
     "opm_ilu0_bytes", "opm_ilu0_factor", "opm_ilu0_apply", "opm_spmv", "opm_krylov_bytes",
     "opm_bicgstab", "opm_newton_bytes", "opm_newton_step", "opm_advance", "opm_set_option",
+    "opm_ensemble_bytes", "opm_ensemble_prepare", "opm_ensemble_launch",
 ]
 
 OPT_SWEEP_MODE, OPT_KRYLOV_CHUNK = 1, 2
@@ -396,3 +397,74 @@ class GpuModel:
                 states.append(y.detach().cpu().numpy().copy())
             reps.append(rep.as_dict())
         return y, states, reps
+
+
+class EnsembleReport(ctypes.Structure):
+    _fields_ = [("status", _i32), ("newton_its", _i32), ("lin_its", _i32), ("substeps", _i32),
+                ("cuts", _i32), ("steps_done", _i32), ("cell_newton_its", ctypes.c_double),
+                ("cnv", ctypes.c_double * 3), ("mb", ctypes.c_double * 3)]
+
+
+_ENS_REPORT_DOUBLES = ctypes.sizeof(EnsembleReport) // 8
+
+
+def _ensemble_lib():
+    L = lib()
+    if not getattr(L, "_ens_ready", False):
+        P = ctypes.POINTER(Problem)
+        L.opm_ensemble_bytes.argtypes = [P, _i32, ctypes.c_int]
+        L.opm_ensemble_bytes.restype = ctypes.c_size_t
+        L.opm_ensemble_prepare.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), _i32, ctypes.c_int,
+                                           _vp, ctypes.c_size_t]
+        L.opm_ensemble_launch.argtypes = [_vp, _i32, ctypes.c_int, _i32, ctypes.c_double, _i32,
+                                          ctypes.POINTER(NewtonOpts), _vp, _vp]
+        L._ens_ready = True
+    return L
+
+
+class Ensemble:
+    """Independent members advanced together by one persistent kernel launch
+    per call (one workgroup per member)."""
+
+    def __init__(self, member_cases, precision=PREC_MIXED, device="cuda"):
+        L = _ensemble_lib()
+        self.members = [GpuModel(c, device=device) for c in member_cases]
+        self.precision = precision
+        self.dev = self.members[0].dev
+        nm = len(self.members)
+        self.n_members = nm
+        self.problems = (Problem * nm)(*[m.pb for m in self.members])
+        self.y = [m.initial_state() for m in self.members]
+        self.yptr = (ctypes.c_void_p * nm)(*[t.data_ptr() for t in self.y])
+        self.max_level = max(m.max_level for m in self.members)
+        nbytes = L.opm_ensemble_bytes(self.problems, nm, precision)
+        if nbytes == 0:
+            raise OpmError(EINVAL, "opm_ensemble_bytes")
+        self.work = torch.empty(nbytes, dtype=torch.uint8, device=self.dev)
+        _check(L.opm_ensemble_prepare(self.problems, self.yptr, nm, precision,
+                                      ctypes.c_void_p(self.work.data_ptr()), nbytes),
+               "opm_ensemble_prepare")
+        self.reports = torch.zeros((nm, _ENS_REPORT_DOUBLES), dtype=torch.float64, device=self.dev)
+        self.n_cells = [m.n for m in self.members]
+
+    def launch(self, dt_report, n_steps, opts: Optional[NewtonOpts] = None):
+        """Enqueue one launch (asynchronous)."""
+        o = opts or default_opts(self.members[0].case, precision=self.precision)
+        _check(_ensemble_lib().opm_ensemble_launch(
+            ctypes.c_void_p(self.work.data_ptr()), self.n_members, self.precision, self.max_level,
+            dt_report, n_steps, ctypes.byref(o), ctypes.c_void_p(self.reports.data_ptr()),
+            _stream()), "opm_ensemble_launch")
+
+    def read_reports(self):
+        raw = self.reports.cpu().numpy().tobytes()
+        size = ctypes.sizeof(EnsembleReport)
+        out = []
+        for m in range(self.n_members):
+            r = EnsembleReport.from_buffer_copy(raw[m * size:(m + 1) * size])
+            out.append({"status": r.status, "newton_its": r.newton_its, "lin_its": r.lin_its,
+                        "substeps": r.substeps, "cuts": r.cuts, "steps_done": r.steps_done,
+                        "cell_newton_its": r.cell_newton_its, "cnv": list(r.cnv), "mb": list(r.mb)})
+        return out
+
+    def states(self):
+        return [t.detach().cpu().numpy().copy() for t in self.y]

@@ -1,0 +1,144 @@
+"""Batched ensemble (one persistent launch, one workgroup per member) against
+the oracle run of every member on its own, and against the single-system GPU
+path.  Parity bar as for single systems: pressure 1e-6 relative, saturations
+1e-6 absolute after every launch of report steps."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1910_06059_amd import cases
+from paper_1910_06059_amd.cases import DAY, PSI, STB, Well
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def opm():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_1910_06059_amd import opm as _opm
+    _opm.init()
+    return _opm
+
+
+def _members():
+    ms = [
+        cases.box_case(6, 5, 3, seed=11, name="m0"),
+        cases.box_case(9, 4, 5, seed=12, name="m1", wells=[
+            Well("G", cases.WELL_RATE_INJ, [(0, 0, 0)], 2e3 * cases.MSCF / DAY, phase=cases.GAS),
+            Well("P", cases.WELL_BHP_PROD, [(8, 3, 4)], 3000 * PSI)]),
+        cases.config1(),
+        cases.box_case(3, 3, 3, seed=13, name="m3"),
+        cases.box_case(12, 10, 2, seed=14, name="m4", mask=cases.masked_mask(
+            np.random.default_rng(3), (2, 10, 12), 150), wells=[]),
+    ]
+    act = np.argwhere(ms[4].mask)
+    k, j, i = act[0]
+    k2, j2, i2 = act[-1]
+    ms[4].wells = [Well("I", cases.WELL_RATE_INJ, [(int(i), int(j), int(k))], 200 * STB / DAY),
+                   Well("P", cases.WELL_BHP_PROD, [(int(i2), int(j2), int(k2))], 3000 * PSI)]
+    return ms
+
+
+def _check(yg, yo, what):
+    ep = np.abs(yg[:, 0] - yo[:, 0]).max() / np.abs(yo[:, 0]).max()
+    es = np.abs(yg[:, 1:] - yo[:, 1:]).max()
+    assert ep <= 1e-6 and es <= 1e-6, f"{what}: p {ep:.2e} s {es:.2e}"
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ensemble_matches_oracle(opm, precision):
+    ms = _members()
+    ens = opm.Ensemble(ms, precision=precision)
+    dt = 10 * DAY
+    ens.launch(dt, 2)
+    torch.cuda.synchronize()
+    reps = ens.read_reports()
+    states = ens.states()
+    for m, case in enumerate(ms):
+        assert reps[m]["status"] == 0 and reps[m]["steps_done"] == 2, reps[m]
+        om = oracle.Model(case)
+        y = case.initial_state()
+        its = 0
+        for _ in range(2):
+            st, y, r = om.advance(y, dt)
+            assert st == 0
+            its += r.newton_its
+        _check(states[m], y, f"member {m}")
+        assert abs(reps[m]["newton_its"] - its) <= 2
+    # a second launch continues from the states left by the first
+    ens.launch(dt, 1)
+    torch.cuda.synchronize()
+    states2 = ens.states()
+    om = oracle.Model(ms[0])
+    st, y, r = om.advance(states[0], dt)
+    _check(states2[0], y, "member 0, second launch")
+
+
+def test_ensemble_matches_single_system_path(opm):
+    ms = _members()[:3]
+    ens = opm.Ensemble(ms, precision=opm.PREC_FP64)
+    dt = 10 * DAY
+    ens.launch(dt, 1)
+    torch.cuda.synchronize()
+    reps = ens.read_reports()
+    for m, case in enumerate(ms):
+        g = opm.GpuModel(case)
+        y = g.initial_state()
+        st, rep = g.advance(y, dt)
+        assert st == 0
+        yg = y.cpu().numpy()
+        ye = ens.states()[m]
+        assert np.abs(ye[:, 0] - yg[:, 0]).max() <= 1e-9 * np.abs(yg[:, 0]).max()
+        assert np.abs(ye[:, 1:] - yg[:, 1:]).max() <= 1e-9
+        assert reps[m]["newton_its"] == rep.newton_its
+
+
+def test_ensemble_graph_capture(opm):
+    """The launch is one graph node: replays equal eager launches."""
+    ms = _members()[:2]
+    dt = 5 * DAY
+    eager = opm.Ensemble(ms, precision=opm.PREC_MIXED)
+    for _ in range(3):
+        eager.launch(dt, 1)
+        torch.cuda.synchronize()
+    ref = eager.states()
+    ens = opm.Ensemble(ms, precision=opm.PREC_MIXED)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ens.launch(dt, 1)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    # capture does not run the kernel: states are still initial
+    assert np.array_equal(ens.states()[0], ms[0].initial_state())
+    for _ in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        _ = ens.read_reports()   # eager work between replays
+    got = ens.states()
+    for m in range(2):
+        assert np.array_equal(got[m], ref[m]), f"member {m}: graph replay differs from eager"
+
+
+def test_ensemble_c4_members(opm):
+    """Three of the 64 ensemble members (the smallest), one 15-day report step,
+    against the oracle."""
+    sizes = []
+    for m in range(64):
+        c = cases.config4_member(m)
+        sizes.append((c.n_active, m))
+    picks = [m for _, m in sorted(sizes)[:3]]
+    ms = [cases.config4_member(m) for m in picks]
+    ens = opm.Ensemble(ms, precision=opm.PREC_MIXED)
+    ens.launch(15 * DAY, 1)
+    torch.cuda.synchronize()
+    reps = ens.read_reports()
+    for k, case in enumerate(ms):
+        assert reps[k]["status"] == 0
+        st, y, r = oracle.Model(case).advance(case.initial_state(), 15 * DAY)
+        assert st == 0
+        _check(ens.states()[k], y, case.name)
