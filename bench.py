@@ -79,11 +79,126 @@ def measured_traffic(kernel_class: str, precision: int):
     return round(rec["traffic_bytes"]) if h == rec["source_sha256_16"] else None
 
 
+def _run_single(g, dt, steps, opts, opm):
+    """Advance a single-system model over `steps` report steps; returns
+    (wall seconds, cell-Newton-iterations, Newton its, linear its)."""
+    import torch
+    y = g.initial_state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cni = newton = lin = 0
+    for _ in range(steps):
+        st, rep = g.advance(y, dt, opts)
+        if st != opm.OK:
+            raise RuntimeError(f"step failed: {opm._strerror(st)}")
+        cni += rep.cell_newton_its
+        newton += rep.newton_its
+        lin += rep.lin_its
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, cni, newton, lin, y
+
+
+def bench_mixed(args):
+    """FP32 ILU(0) factors and sweeps inside FP64 BiCGStab against the plain
+    FP64 GPU path on the masked 46x112x22 grid (about 45k active cells), same
+    Newton (CNV 1e-8, MB 1e-11) and linear (1e-6) tolerances."""
+    import numpy as np
+    from paper_1910_06059_amd import cases, opm
+    steps = args.steps or 10
+    case = cases.config3()
+    g = opm.GpuModel(case)
+    dt = case.report_dt[0]
+    res = {}
+    for prec in (0, 1):
+        opts = opm.default_opts(case, precision=prec)
+        _run_single(g, dt, 1, opts, opm)   # warm-up (kernel loading)
+        wall, cni, newton, lin, y = _run_single(g, dt, steps, opts, opm)
+        res[prec] = {"wall_s": round(wall, 4), "cell_newton_its_per_s": round(cni / wall, 1),
+                     "newton_its": newton, "lin_its": lin, "state": y.cpu().numpy()}
+    y64, y32 = res[0].pop("state"), res[1].pop("state")
+    err_p = float(np.abs(y32[:, 0] - y64[:, 0]).max() / np.abs(y64[:, 0]).max())
+    err_s = float(np.abs(y32[:, 1:] - y64[:, 1:]).max())
+    line = {"metric": "mixed-precision speedup over the plain FP64 GPU path (same tolerances)",
+            "value": round(res[0]["wall_s"] / res[1]["wall_s"], 3), "unit": "x", "n_gpus": 1,
+            "steps": steps, "warmup": 1, "higher_is_better": True, "dtype": "f64+f32-ilu",
+            "data": "synthetic",
+            "config": {"workload": f"46x112x22 masked grid, {g.n} active cells, 10-day steps",
+                       "n_cells": g.n, "ilu_levels": g.n_levels},
+            "fp64": res[0], "mixed": res[1],
+            "mixed_vs_fp64_state": {"p_rel": err_p, "s_abs": err_s}}
+    print(json.dumps(line), flush=True)
+
+
+def bench_ensemble(args):
+    """64 members (uneven grids 20..60 x 20..60 x 20..30) advanced 20 report
+    steps of 15 days in one persistent launch, against the single-system FP64
+    GPU path run member by member on a sample of members."""
+    import torch
+    from paper_1910_06059_amd import cases, opm
+    steps = args.steps or 20
+    nm = args.members
+    member_cases = [cases.config4_member(m) for m in range(nm)]
+    dt = member_cases[0].report_dt[0]
+    # warm-up: load the kernels on a two-member ensemble
+    warm = opm.Ensemble([cases.box_case(4, 4, 3, seed=1), cases.box_case(3, 5, 2, seed=2)],
+                        precision=opm.PREC_MIXED)
+    warm.launch(dt, 1)
+    torch.cuda.synchronize()
+    out = {}
+    for prec in (opm.PREC_MIXED, opm.PREC_FP64):
+        ens = opm.Ensemble(member_cases, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ens.launch(dt, steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        reps = ens.read_reports()
+        ok = sum(1 for r in reps if r["status"] == 0 and r["steps_done"] == steps)
+        out[prec] = {"wall_s": round(wall, 3), "members_steps_per_s": round(nm * steps / wall, 3),
+                     "members_ok": ok,
+                     "newton_its": sum(r["newton_its"] for r in reps),
+                     "lin_its": sum(r["lin_its"] for r in reps),
+                     "cell_newton_its_per_s": round(sum(r["cell_newton_its"] for r in reps) / wall, 1)}
+        del ens
+    # single-system FP64 path, member by member, on a sample spread over sizes
+    order = sorted(range(nm), key=lambda m: member_cases[m].n_active)
+    k = max(1, min(args.baseline_members, nm))
+    sample = [order[int(round(i * (nm - 1) / max(1, k - 1)))] for i in range(k)]
+    base_steps = min(steps, 2)
+    bwall = 0.0
+    for m in sample:
+        g = opm.GpuModel(member_cases[m])
+        opts = opm.default_opts(member_cases[m], precision=opm.PREC_FP64)
+        _run_single(g, dt, 1, opts, opm)
+        wall, *_ = _run_single(g, dt, base_steps, opts, opm)
+        bwall += wall
+    base_rate = len(sample) * base_steps / bwall
+    line = {"metric": "ensemble members-steps/s (one persistent launch) and speedup over the "
+                      "single-system FP64 GPU path", "value": out[opm.PREC_MIXED]["members_steps_per_s"],
+            "unit": "members-steps/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+            "higher_is_better": True, "dtype": "f64+f32-ilu", "data": "synthetic",
+            "config": {"workload": f"{nm} members, grids 20..60 x 20..60 x 20..30, 15-day steps",
+                       "total_cells": sum(c.n_active for c in member_cases)},
+            "ensemble_mixed": out[opm.PREC_MIXED], "ensemble_fp64": out[opm.PREC_FP64],
+            "single_system_fp64": {"members_steps_per_s": round(base_rate, 4),
+                                   "sample": f"members {sample}, first {base_steps} steps each"},
+            "speedup_vs_single_fp64": round(out[opm.PREC_MIXED]["members_steps_per_s"] / base_rate, 2),
+            "speedup_fp64_ensemble_vs_single_fp64": round(out[opm.PREC_FP64]["members_steps_per_s"] / base_rate, 2)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed report steps (default: 30 for c2, 10 for c3, 20 for c4)")
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3-mixed", "c4-ensemble"],
+                    help="c2: the headline metric line; c3-mixed: FP32 ILU(0) vs FP64 on the "
+                         "masked 45k-cell grid; c4-ensemble: 64 members in one launch")
+    ap.add_argument("--members", type=int, default=64, help="ensemble size (c4-ensemble)")
+    ap.add_argument("--baseline-members", type=int, default=4,
+                    help="members timed one by one on the single-system FP64 path (c4-ensemble)")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 FP32 ILU(0) factors")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="time budget of the CPU-oracle sample")
@@ -104,6 +219,12 @@ def main():
     from paper_1910_06059_amd import cases, opm
 
     torch.cuda.set_device(0)
+    if args.workload == "c3-mixed":
+        return bench_mixed(args)
+    if args.workload == "c4-ensemble":
+        return bench_ensemble(args)
+    if args.steps is None:
+        args.steps = 30
     case = cases.config2()
     g = opm.GpuModel(case, device="cuda:0")
     opts = opm.default_opts(case, precision=args.precision)

@@ -97,6 +97,8 @@ typedef struct opm_topology {
   int32_t* up_pos;      /* [n_cells][3] level-order position of j               */
   int32_t n_levels;     /* out                                                  */
   int32_t max_level;    /* out: largest number of rows in one level             */
+  int32_t sweep_span;   /* out: largest |position(i) - position(j)| over the
+                           connections (i,j) in the level order                 */
 } opm_topology;
 
 /* Count active cells and faces (host, synchronous).  mask may be NULL (all
@@ -176,6 +178,7 @@ typedef struct opm_problem {
   const double* conn_rate;      /* [n_conns] fixed source (injectors)         */
   const double* conn_bhp;       /* [n_conns] BHP target (producers)           */
   opm_fluid fluid;
+  int32_t sweep_span;           /* opm_topology.sweep_span                    */
 } opm_problem;
 
 /* Library set-up: checks that the current device is a gfx950 (MI355X) and

@@ -39,6 +39,7 @@ constexpr int kWgThreads = 512;        // threads of the one-workgroup sweep
 constexpr int kFacThreads = 256;       // threads of the one-workgroup factorisation
 constexpr int kMaxWindowRows = 2048;   // widest level served by the one-workgroup sweep
 constexpr int kMaxFactorWindowRows = 640;
+constexpr size_t kMaxRingBytes = 128 * 1024;   // LDS budget of the sweep ring
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pack(Topo t, const double* J, IluView<T> v) {
@@ -107,6 +108,15 @@ __global__ __launch_bounds__(kBlock) void k_bwd_level(Topo t, IluView<T> v, int 
 }
 
 template <typename T>
+__global__ __launch_bounds__(kWgThreads) void k_apply_ring(Topo t, IluView<T> v, const double* r,
+                                                            double* x, const int32_t* skip,
+                                                            unsigned mask) {
+  if (skip && *skip != 0) return;
+  extern __shared__ unsigned char smem[];
+  apply_levels_ring<T, kWgThreads>(t, v, r, x, reinterpret_cast<T*>(smem), mask);
+}
+
+template <typename T>
 __global__ __launch_bounds__(kWgThreads) void k_apply_wg(Topo t, IluView<T> v, const double* r,
                                                           double* x, const int32_t* skip) {
   if (skip && *skip != 0) return;
@@ -121,7 +131,7 @@ size_t apply_lds(const opm_problem* pb) {
 
 size_t factor_lds(const opm_problem* pb) { return sizeof(double) * 2 * 9 * (size_t)pb->max_level; }
 
-bool g_lds_attr_set[4] = {false, false, false, false};
+bool g_lds_attr_set[8] = {false, false, false, false, false, false, false, false};
 
 template <typename K>
 int allow_lds(K kernel, int slot) {
@@ -167,6 +177,15 @@ int apply_impl(const opm_problem* pb, void* ilu, const double* r, double* x, int
   IluView<T> v = view<T>(pb, ilu);
   Topo t = topo_of(pb);
   if (mode == 0) {
+    const int ring = ring_rows(pb->sweep_span, pb->max_level);
+    const size_t ring_bytes = sizeof(T) * 3 * (size_t)ring;
+    if (ring_bytes <= kMaxRingBytes) {   // every neighbour value in LDS
+      OPM_TRY(allow_lds(k_apply_ring<T>, sizeof(T) == 8 ? 4 : 5));
+      hipLaunchKernelGGL(k_apply_ring<T>, dim3(1), dim3(kWgThreads), ring_bytes, s, t, v, r, x,
+                         skip, (unsigned)(ring - 1));
+      OPM_TRY_HIP(hipGetLastError());
+      return OPM_OK;
+    }
     OPM_TRY(allow_lds(k_apply_wg<T>, sizeof(T) == 8 ? 2 : 3));
     hipLaunchKernelGGL(k_apply_wg<T>, dim3(1), dim3(kWgThreads), apply_lds<T>(pb), s, t, v, r, x,
                        skip);

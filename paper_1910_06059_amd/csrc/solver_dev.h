@@ -232,32 +232,35 @@ struct SweepJob {
   int cell;
 };
 
-// lower: forward-sweep data of row pos (r gathered from natural order)
+// lower: forward-sweep data of row pos (r gathered from natural order).
+// Offsets are 32-bit so that addresses stay (uniform base, lane offset).
 template <typename T>
 __device__ __forceinline__ void load_fwd(const Topo& t, IluView<T> v, const double* r, int pos,
                                          SweepJob<T>& j) {
-  j.cell = t.perm[pos];
+  const unsigned ns = (unsigned)v.ns, up = (unsigned)pos;
+  j.cell = t.perm[up];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) j.rhs[c] = (T)r[3 * j.cell + c];
+  for (unsigned c = 0; c < 3; ++c) j.rhs[c] = (T)r[3u * (unsigned)j.cell + c];
 #pragma unroll
-  for (int s = 0; s < 3; ++s) j.kp[s] = t.lo_pos[3 * pos + s];
+  for (unsigned s = 0; s < 3; ++s) j.kp[s] = t.lo_pos[3u * up + s];
 #pragma unroll
-  for (int e = 0; e < 27; ++e) j.a[e] = v.lov[(size_t)e * v.ns + pos];
+  for (unsigned e = 0; e < 27; ++e) j.a[e] = v.lov[e * ns + up];
 #pragma unroll
-  for (int e = 0; e < 9; ++e) j.D[e] = v.dinv[(size_t)e * v.ns + pos];
+  for (unsigned e = 0; e < 9; ++e) j.D[e] = v.dinv[e * ns + up];
 }
 
 template <typename T>
 __device__ __forceinline__ void load_bwd(const Topo& t, IluView<T> v, int pos, SweepJob<T>& j) {
-  j.cell = t.perm[pos];
+  const unsigned ns = (unsigned)v.ns, up = (unsigned)pos;
+  j.cell = t.perm[up];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) j.rhs[c] = v.z[(size_t)c * v.ns + pos];
+  for (unsigned c = 0; c < 3; ++c) j.rhs[c] = v.z[c * ns + up];
 #pragma unroll
-  for (int s = 0; s < 3; ++s) j.kp[s] = t.up_pos[3 * pos + s];
+  for (unsigned s = 0; s < 3; ++s) j.kp[s] = t.up_pos[3u * up + s];
 #pragma unroll
-  for (int e = 0; e < 27; ++e) j.a[e] = v.upv[(size_t)e * v.ns + pos];
+  for (unsigned e = 0; e < 27; ++e) j.a[e] = v.upv[e * ns + up];
 #pragma unroll
-  for (int e = 0; e < 9; ++e) j.D[e] = v.dinv[(size_t)e * v.ns + pos];
+  for (unsigned e = 0; e < 9; ++e) j.D[e] = v.dinv[e * ns + up];
 }
 
 // forward: y = D^{-1} (r - sum_s A_s y_{k_s});  backward: x = y - D^{-1} sum_s A_s x_{k_s}
@@ -289,86 +292,77 @@ __device__ __forceinline__ void solve_row(const SweepJob<T>& j, NbrFn nbr, T* ou
 // levels ascending, backward sweep descending; the values of the level just
 // finished stay in the LDS window `win` (2 buffers of max_level x 3 entries),
 // the next level's data is loaded before the barrier.
+template <typename T, bool FWD>
+__device__ __forceinline__ void wg_row(const SweepJob<T>& j, IluView<T> v, double* x, T* win,
+                                       int L, int buf, int prev0, int prev1, int p0, int pos) {
+  T out[3];
+  solve_row<T, FWD>(j, [&](int kp, T* xv) {
+    if (kp >= prev0 && kp < prev1) {
+      const T* w = win + (unsigned)((buf ^ 1) * L + (kp - prev0)) * 3u;
+      xv[0] = w[0];
+      xv[1] = w[1];
+      xv[2] = w[2];
+    } else {
+#pragma unroll
+      for (unsigned c = 0; c < 3; ++c) xv[c] = v.z[c * (unsigned)v.ns + (unsigned)kp];
+    }
+  }, out);
+  T* w = win + (unsigned)(buf * L + (pos - p0)) * 3u;
+#pragma unroll
+  for (unsigned c = 0; c < 3; ++c) {
+    w[c] = out[c];
+    v.z[c * (unsigned)v.ns + (unsigned)pos] = out[c];
+    if (!FWD) x[3u * (unsigned)j.cell + c] = (double)out[c];
+  }
+}
+
+// One sweep (forward: levels ascending; backward: descending) by one
+// workgroup; the data of the next level is requested before the current
+// level is computed.
+template <typename T, int NT, bool FWD>
+__device__ __forceinline__ void wg_sweep(const Topo& t, IluView<T> v, const double* r, double* x,
+                                         T* win) {
+  const int L = t.max_level;
+  const int tid = threadIdx.x;
+  auto load = [&](int pos, SweepJob<T>& j) {
+    if (FWD)
+      load_fwd(t, v, r, pos, j);
+    else
+      load_bwd(t, v, pos, j);
+  };
+  SweepJob<T> next, cur;
+  {
+    const int l0 = FWD ? 0 : t.nlev - 1;
+    if (t.level_ptr[l0] + tid < t.level_ptr[l0 + 1]) load(t.level_ptr[l0] + tid, next);
+  }
+  int prev0 = 0, prev1 = 0, buf = 0;
+  for (int k = 0; k < t.nlev; ++k) {
+    const int l = FWD ? k : t.nlev - 1 - k;
+    const int p0 = t.level_ptr[l], p1 = t.level_ptr[l + 1];
+    cur = next;
+    if (k + 1 < t.nlev) {
+      const int ln = FWD ? l + 1 : l - 1;
+      const int q0 = t.level_ptr[ln];
+      if (q0 + tid < t.level_ptr[ln + 1]) load(q0 + tid, next);
+    }
+    if (p0 + tid < p1) wg_row<T, FWD>(cur, v, x, win, L, buf, prev0, prev1, p0, p0 + tid);
+    for (int pos = p0 + tid + NT; pos < p1; pos += NT) {   // levels wider than the workgroup
+      SweepJob<T> j;
+      load(pos, j);
+      wg_row<T, FWD>(j, v, x, win, L, buf, prev0, prev1, p0, pos);
+    }
+    __syncthreads();
+    prev0 = p0;
+    prev1 = p1;
+    buf ^= 1;
+  }
+}
+
 template <typename T, int NT>
 __device__ __forceinline__ void apply_levels_wg(const Topo& t, IluView<T> v, const double* r,
                                                 double* x, T* win) {
-  const int L = t.max_level;
-  const int tid = threadIdx.x;
-  SweepJob<T> next;
-  if (t.level_ptr[0] + tid < t.level_ptr[1]) load_fwd(t, v, r, t.level_ptr[0] + tid, next);
-  int prev0 = 0, prev1 = 0, buf = 0;
-  for (int l = 0; l < t.nlev; ++l) {
-    const int p0 = t.level_ptr[l], p1 = t.level_ptr[l + 1];
-    for (int pos = p0 + tid; pos < p1; pos += NT) {
-      SweepJob<T> cur;
-      if (pos == p0 + tid)
-        cur = next;
-      else
-        load_fwd(t, v, r, pos, cur);
-      T y[3];
-      solve_row<T, true>(cur, [&](int kp, T* xv) {
-        if (kp >= prev0 && kp < prev1) {
-          const T* w = win + (size_t)((buf ^ 1) * L + (kp - prev0)) * 3;
-          xv[0] = w[0];
-          xv[1] = w[1];
-          xv[2] = w[2];
-        } else {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) xv[c] = v.z[(size_t)c * v.ns + kp];
-        }
-      }, y);
-      T* w = win + (size_t)(buf * L + (pos - p0)) * 3;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        w[c] = y[c];
-        v.z[(size_t)c * v.ns + pos] = y[c];
-      }
-    }
-    if (l + 1 < t.nlev && p1 + tid < t.level_ptr[l + 2]) load_fwd(t, v, r, p1 + tid, next);
-    __syncthreads();
-    prev0 = p0;
-    prev1 = p1;
-    buf ^= 1;
-  }
-  {
-    const int l = t.nlev - 1;
-    if (t.level_ptr[l] + tid < t.level_ptr[l + 1]) load_bwd(t, v, t.level_ptr[l] + tid, next);
-  }
-  prev0 = prev1 = 0;
-  for (int l = t.nlev - 1; l >= 0; --l) {
-    const int p0 = t.level_ptr[l], p1 = t.level_ptr[l + 1];
-    for (int pos = p0 + tid; pos < p1; pos += NT) {
-      SweepJob<T> cur;
-      if (pos == p0 + tid)
-        cur = next;
-      else
-        load_bwd(t, v, pos, cur);
-      T xo[3];
-      solve_row<T, false>(cur, [&](int kp, T* xv) {
-        if (kp >= prev0 && kp < prev1) {
-          const T* w = win + (size_t)((buf ^ 1) * L + (kp - prev0)) * 3;
-          xv[0] = w[0];
-          xv[1] = w[1];
-          xv[2] = w[2];
-        } else {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) xv[c] = v.z[(size_t)c * v.ns + kp];
-        }
-      }, xo);
-      T* w = win + (size_t)(buf * L + (pos - p0)) * 3;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        w[c] = xo[c];
-        v.z[(size_t)c * v.ns + pos] = xo[c];
-        x[3 * cur.cell + c] = (double)xo[c];
-      }
-    }
-    if (l > 0 && t.level_ptr[l - 1] + tid < p0) load_bwd(t, v, t.level_ptr[l - 1] + tid, next);
-    __syncthreads();
-    prev0 = p0;
-    prev1 = p1;
-    buf ^= 1;
-  }
+  wg_sweep<T, NT, true>(t, v, r, x, win);
+  wg_sweep<T, NT, false>(t, v, r, x, win);
 }
 
 // One block row of y = J x (3 outputs).
@@ -386,6 +380,280 @@ __device__ __forceinline__ void spmv_row(const int32_t* row_ptr, const int32_t* 
   y3[0] = a0;
   y3[1] = a1;
   y3[2] = a2;
+}
+
+}  // namespace ilu
+}  // namespace opm
+
+namespace opm {
+namespace ilu {
+
+// ---------------------------------------------------------------------------
+// Quad sweep: x = (LU)^{-1} r by one workgroup of NT threads where four lanes
+// share one row (NT/4 rows per pass).  Lane q < 3 owns equation q of the row:
+// it holds row q of each neighbour block and of D^{-1} (13 values), so a
+// row's data is spread over three lanes and each lane can keep the data of
+// the next three levels in registers: the loads for level l+3 are issued
+// while level l is computed, which hides the memory latency of one level
+// behind three levels of work.  The three partial results of a row are
+// exchanged inside the quad.  Lane 3 of a quad only takes part in the
+// exchange.
+template <typename T>
+struct QuadJob {
+  T a[9];     // row q of the three neighbour blocks: a[3*s + c]
+  T d[3];     // row q of D^{-1}
+  T rhs;      // r_q (forward) or y_q (backward)
+  int kp[3];  // neighbour positions
+  int cell;
+};
+
+template <typename T, bool FWD>
+__device__ __forceinline__ void quad_load(const Topo& t, IluView<T> v, const double* r, int pos,
+                                          int q, QuadJob<T>& j) {
+  // 32-bit element offsets keep the addresses as (uniform base, lane offset)
+  const unsigned qq = q < 3 ? (unsigned)q : 0u;
+  const unsigned ns = (unsigned)v.ns, up = (unsigned)pos;
+  j.cell = t.perm[up];
+  const T* blk = FWD ? v.lov : v.upv;
+  const int32_t* kp = FWD ? t.lo_pos : t.up_pos;
+#pragma unroll
+  for (unsigned s = 0; s < 3; ++s) {
+    j.kp[s] = kp[3u * up + s];
+#pragma unroll
+    for (unsigned c = 0; c < 3; ++c) j.a[3 * s + c] = blk[(9u * s + 3u * qq + c) * ns + up];
+  }
+#pragma unroll
+  for (unsigned c = 0; c < 3; ++c) j.d[c] = v.dinv[(3u * qq + c) * ns + up];
+  j.rhs = FWD ? (T)r[3u * (unsigned)j.cell + qq] : v.z[qq * ns + up];
+}
+
+// One row by its quad: neighbour values come from the LDS window (previous
+// level) or from z; returns this lane's component.  The arithmetic is that of
+// solve_row, term by term, so both launch shapes give bitwise equal results.
+template <typename T, bool FWD>
+__device__ __forceinline__ T quad_row(const QuadJob<T>& j, IluView<T> v, const T* win_prev,
+                                      int prev0, int prev1) {
+  T acc = FWD ? j.rhs : (T)0;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int kp = j.kp[s];
+    if (kp < 0) continue;
+    T xv[3];
+    if (kp >= prev0 && kp < prev1) {
+      const T* w = win_prev + (unsigned)(kp - prev0) * 3u;
+      xv[0] = w[0];
+      xv[1] = w[1];
+      xv[2] = w[2];
+    } else {
+#pragma unroll
+      for (unsigned c = 0; c < 3; ++c) xv[c] = v.z[c * (unsigned)v.ns + (unsigned)kp];
+    }
+    const T t = j.a[3 * s] * xv[0] + j.a[3 * s + 1] * xv[1] + j.a[3 * s + 2] * xv[2];
+    acc = FWD ? acc - t : acc + t;
+  }
+  // exchange the three components of the row inside the quad
+  const int base = (threadIdx.x & (kWave - 1)) & ~3;
+  const T t0 = __shfl(acc, base + 0, kWave);
+  const T t1 = __shfl(acc, base + 1, kWave);
+  const T t2 = __shfl(acc, base + 2, kWave);
+  const T d = j.d[0] * t0 + j.d[1] * t1 + j.d[2] * t2;
+  return FWD ? d : j.rhs - d;
+}
+
+template <typename T, bool FWD>
+__device__ __forceinline__ void quad_store(IluView<T> v, double* x, T* wcur, int p0, int pos,
+                                           int q, int cell, T val) {
+  if (q < 3) {
+    wcur[(unsigned)(pos - p0) * 3u + (unsigned)q] = val;
+    v.z[(unsigned)q * (unsigned)v.ns + (unsigned)pos] = val;
+    if (!FWD) x[3u * (unsigned)cell + (unsigned)q] = (double)val;
+  }
+}
+
+template <typename T, int NT, bool FWD>
+__device__ __forceinline__ void quad_level(const Topo& t, IluView<T> v, const double* r, double* x,
+                                           T* win, int L, int l, int& prev0, int& prev1, int& buf,
+                                           const QuadJob<T>& first) {
+  const int p0 = t.level_ptr[l], p1 = t.level_ptr[l + 1];
+  const int q = threadIdx.x & 3, row0 = threadIdx.x >> 2;
+  const T* wprev = win + (size_t)((buf ^ 1) * L) * 3;
+  T* wcur = win + (size_t)(buf * L) * 3;
+  if (p0 + row0 < p1) {   // first pass: data loaded levels ago
+    const T val = quad_row<T, FWD>(first, v, wprev, prev0, prev1);
+    quad_store<T, FWD>(v, x, wcur, p0, p0 + row0, q, first.cell, val);
+  }
+  for (int pos = p0 + row0 + NT / 4; pos < p1; pos += NT / 4) {   // wide levels
+    QuadJob<T> j;
+    quad_load<T, FWD>(t, v, r, pos, q, j);
+    const T val = quad_row<T, FWD>(j, v, wprev, prev0, prev1);
+    quad_store<T, FWD>(v, x, wcur, p0, pos, q, j.cell, val);
+  }
+  __syncthreads();
+  prev0 = p0;
+  prev1 = p1;
+  buf ^= 1;
+}
+
+// level index of the k-th step of a sweep (ascending forward, descending backward)
+template <bool FWD>
+__device__ __forceinline__ int sweep_level(const Topo& t, int k) {
+  return FWD ? k : t.nlev - 1 - k;
+}
+
+template <typename T, int NT, bool FWD>
+__device__ __forceinline__ void quad_prefetch(const Topo& t, IluView<T> v, const double* r, int k,
+                                              QuadJob<T>& j) {
+  if (k >= t.nlev) return;
+  const int l = sweep_level<FWD>(t, k);
+  const int pos = t.level_ptr[l] + (threadIdx.x >> 2);
+  if (pos < t.level_ptr[l + 1]) quad_load<T, FWD>(t, v, r, pos, threadIdx.x & 3, j);
+}
+
+// Three levels in flight (FP32 data fits the register budget of 1024 threads).
+template <typename T, int NT, bool FWD>
+__device__ __forceinline__ void quad_sweep3(const Topo& t, IluView<T> v, const double* r,
+                                            double* x, T* win) {
+  const int L = t.max_level;
+  int prev0 = 0, prev1 = 0, buf = 0;
+  QuadJob<T> ja, jb, jc;
+  quad_prefetch<T, NT, FWD>(t, v, r, 0, ja);
+  quad_prefetch<T, NT, FWD>(t, v, r, 1, jb);
+  quad_prefetch<T, NT, FWD>(t, v, r, 2, jc);
+  for (int k = 0; k < t.nlev; k += 3) {
+    quad_level<T, NT, FWD>(t, v, r, x, win, L, sweep_level<FWD>(t, k), prev0, prev1, buf, ja);
+    quad_prefetch<T, NT, FWD>(t, v, r, k + 3, ja);
+    if (k + 1 >= t.nlev) break;
+    quad_level<T, NT, FWD>(t, v, r, x, win, L, sweep_level<FWD>(t, k + 1), prev0, prev1, buf, jb);
+    quad_prefetch<T, NT, FWD>(t, v, r, k + 4, jb);
+    if (k + 2 >= t.nlev) break;
+    quad_level<T, NT, FWD>(t, v, r, x, win, L, sweep_level<FWD>(t, k + 2), prev0, prev1, buf, jc);
+    quad_prefetch<T, NT, FWD>(t, v, r, k + 5, jc);
+  }
+}
+
+// Two levels in flight (FP64).
+template <typename T, int NT, bool FWD>
+__device__ __forceinline__ void quad_sweep2(const Topo& t, IluView<T> v, const double* r,
+                                            double* x, T* win) {
+  const int L = t.max_level;
+  int prev0 = 0, prev1 = 0, buf = 0;
+  QuadJob<T> ja, jb;
+  quad_prefetch<T, NT, FWD>(t, v, r, 0, ja);
+  quad_prefetch<T, NT, FWD>(t, v, r, 1, jb);
+  for (int k = 0; k < t.nlev; k += 2) {
+    quad_level<T, NT, FWD>(t, v, r, x, win, L, sweep_level<FWD>(t, k), prev0, prev1, buf, ja);
+    quad_prefetch<T, NT, FWD>(t, v, r, k + 2, ja);
+    if (k + 1 >= t.nlev) break;
+    quad_level<T, NT, FWD>(t, v, r, x, win, L, sweep_level<FWD>(t, k + 1), prev0, prev1, buf, jb);
+    quad_prefetch<T, NT, FWD>(t, v, r, k + 3, jb);
+  }
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void apply_levels_quad(const Topo& t, IluView<T> v, const double* r,
+                                                  double* x, T* win) {
+  if (sizeof(T) == sizeof(double)) {
+    quad_sweep2<T, NT, true>(t, v, r, x, win);
+    quad_sweep2<T, NT, false>(t, v, r, x, win);
+  } else {
+    quad_sweep3<T, NT, true>(t, v, r, x, win);
+    quad_sweep3<T, NT, false>(t, v, r, x, win);
+  }
+}
+
+}  // namespace ilu
+}  // namespace opm
+
+namespace opm {
+namespace ilu {
+
+// Ring capacity (rows, a power of two) that holds every value a sweep can
+// still need: a row reads neighbours at most `span` positions away, and the
+// rows of one level (at most max_level) write concurrently.
+__host__ __device__ inline int ring_rows(int span, int max_level) {
+  int c = 1;
+  while (c < span + max_level + 1) c <<= 1;
+  return c;
+}
+
+// One row of a sweep with every neighbour value read from the LDS ring.
+template <typename T, bool FWD>
+__device__ __forceinline__ void ring_row(const SweepJob<T>& j, IluView<T> v, double* x, T* ring,
+                                         unsigned mask, int pos) {
+  T out[3];
+  solve_row<T, FWD>(j, [&](int kp, T* xv) {
+    const T* w = ring + ((unsigned)kp & mask) * 3u;
+    xv[0] = w[0];
+    xv[1] = w[1];
+    xv[2] = w[2];
+  }, out);
+  T* w = ring + ((unsigned)pos & mask) * 3u;
+#pragma unroll
+  for (unsigned c = 0; c < 3; ++c) {
+    w[c] = out[c];
+    if (FWD)
+      v.z[c * (unsigned)v.ns + (unsigned)pos] = out[c];
+    else
+      x[3u * (unsigned)j.cell + c] = (double)out[c];
+  }
+}
+
+// Rows of level l by the workgroup: the first row of each thread comes from
+// registers loaded earlier (`first`), further rows of a wide level are loaded
+// here.
+template <typename T, int NT, bool FWD, typename LoadFn>
+__device__ __forceinline__ void ring_level(const Topo& t, IluView<T> v, double* x, T* ring,
+                                           unsigned mask, int l, const SweepJob<T>& first,
+                                           LoadFn load) {
+  const int tid = threadIdx.x;
+  const int p0 = t.level_ptr[l], p1 = t.level_ptr[l + 1];
+  if (p0 + tid < p1) ring_row<T, FWD>(first, v, x, ring, mask, p0 + tid);
+  for (int pos = p0 + tid + NT; pos < p1; pos += NT) {
+    SweepJob<T> j;
+    load(pos, j);
+    ring_row<T, FWD>(j, v, x, ring, mask, pos);
+  }
+  __syncthreads();
+}
+
+// One sweep by one workgroup with the LDS ring: no neighbour value is read
+// from global memory, so the only global loads are the row data.  Two
+// register sets alternate between levels, and the next level's row data is
+// requested before the current level is computed (no register copy, which
+// would force the loads to complete).
+template <typename T, int NT, bool FWD>
+__device__ __forceinline__ void ring_sweep(const Topo& t, IluView<T> v, const double* r, double* x,
+                                           T* ring, unsigned mask) {
+  const int tid = threadIdx.x;
+  auto load = [&](int pos, SweepJob<T>& j) {
+    if (FWD)
+      load_fwd(t, v, r, pos, j);
+    else
+      load_bwd(t, v, pos, j);
+  };
+  auto level_of = [&](int k) { return FWD ? k : t.nlev - 1 - k; };
+  auto prefetch = [&](int k, SweepJob<T>& j) {
+    if (k >= t.nlev) return;
+    const int l = level_of(k);
+    const int pos = t.level_ptr[l] + tid;
+    if (pos < t.level_ptr[l + 1]) load(pos, j);
+  };
+  SweepJob<T> ja, jb;
+  prefetch(0, ja);
+  for (int k = 0; k < t.nlev; k += 2) {
+    prefetch(k + 1, jb);
+    ring_level<T, NT, FWD>(t, v, x, ring, mask, level_of(k), ja, load);
+    if (k + 1 >= t.nlev) break;
+    prefetch(k + 2, ja);
+    ring_level<T, NT, FWD>(t, v, x, ring, mask, level_of(k + 1), jb, load);
+  }
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void apply_levels_ring(const Topo& t, IluView<T> v, const double* r,
+                                                  double* x, T* ring, unsigned mask) {
+  ring_sweep<T, NT, true>(t, v, r, x, ring, mask);
+  ring_sweep<T, NT, false>(t, v, r, x, ring, mask);
 }
 
 }  // namespace ilu

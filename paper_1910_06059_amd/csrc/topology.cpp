@@ -149,8 +149,15 @@ extern "C" int opm_topology_build(int32_t nx, int32_t ny, int32_t nz, const uint
     }
     for (; s < 3; ++s) t->up_blk[3 * pos + s] = t->up_pos[3 * pos + s] = -1;
   }
+  int32_t span = 0;
+  for (int32_t pos = 0; pos < n; ++pos)
+    for (int s2 = 0; s2 < 3; ++s2) {
+      if (t->lo_pos[3 * pos + s2] >= 0) span = std::max(span, pos - t->lo_pos[3 * pos + s2]);
+      if (t->up_pos[3 * pos + s2] >= 0) span = std::max(span, t->up_pos[3 * pos + s2] - pos);
+    }
   t->n_levels = nlev;
   t->max_level = mx;
+  t->sweep_span = span;
   return OPM_OK;
 }
 

@@ -40,7 +40,7 @@ class Topology(ctypes.Structure):
     _fields_ = [(name, _ip) for name in (
         "cell_box", "face_cells", "face_dir", "row_ptr", "col_idx", "blk_face", "diag_pos",
         "level_ptr", "perm", "iperm", "lo_blk", "lo_tblk", "lo_pos", "up_blk", "up_pos")] + [
-        ("n_levels", _i32), ("max_level", _i32)]
+        ("n_levels", _i32), ("max_level", _i32), ("sweep_span", _i32)]
 
 
 class Problem(ctypes.Structure):
@@ -52,7 +52,7 @@ class Problem(ctypes.Structure):
                 ("iperm", _vp), ("lo_blk", _vp), ("lo_tblk", _vp), ("lo_pos", _vp),
                 ("up_blk", _vp), ("up_pos", _vp), ("cell_conn_ptr", _vp), ("cell_conn", _vp),
                 ("conn_kind", _vp), ("conn_phase", _vp), ("conn_wi", _vp), ("conn_rate", _vp),
-                ("conn_bhp", _vp), ("fluid", Fluid)]
+                ("conn_bhp", _vp), ("fluid", Fluid), ("sweep_span", _i32)]
 
 
 class SolveReport(ctypes.Structure):
@@ -215,6 +215,7 @@ class GpuModel:
                "opm_topology_build")
         self.n, self.nf, self.nnzb = n, nf, nnzb
         self.n_levels, self.max_level = topo.n_levels, topo.max_level
+        self.sweep_span = topo.sweep_span
         self.host = host
         self.level_ptr_h = np.ascontiguousarray(host["level_ptr"][:self.n_levels + 1])
         d = {k: torch.from_numpy(a).to(self.dev) for k, a in host.items()}
@@ -287,7 +288,7 @@ class GpuModel:
             cell_conn_ptr=self.cell_conn_ptr.data_ptr(), cell_conn=self.cell_conn.data_ptr(),
             conn_kind=self.conn_kind.data_ptr(), conn_phase=self.conn_phase.data_ptr(),
             conn_wi=self.conn_wi.data_ptr(), conn_rate=self.conn_rate.data_ptr(),
-            conn_bhp=self.conn_bhp.data_ptr(), fluid=fl)
+            conn_bhp=self.conn_bhp.data_ptr(), fluid=fl, sweep_span=topo.sweep_span)
         self._work = {}
         torch.cuda.current_stream().synchronize()
 
