@@ -187,15 +187,139 @@ def bench_ensemble(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_guess(args):
+    """Learned Newton initial guess on the 100x100x50 waterflood (500k active
+    cells, lognormal permeability median 100 mD and sigma_ln 2, four water
+    injectors, five BHP producers, 10-day report steps).  The network trains
+    on the report steps that the FP64 GPU simulator produces for the
+    training seeds; each held-out seed is then advanced three ways at the same
+    Newton (CNV 1e-8, MB 1e-11) and linear (1e-6) tolerances: from the
+    previous state, from the linear extrapolation y_n + (y_n - y_{n-1}) alone
+    (the network's skip path with a zero correction), and from the learned
+    guess (each step taking the lowest-CNV start among the previous state,
+    the learned guess and its extrapolation path alone).  The first report
+    step of every run starts from the previous state (it has no previous
+    change)."""
+    import numpy as np
+    import torch
+    from paper_1910_06059_amd import cases, guess, opm
+    steps = args.steps or 25
+    train_seeds = list(range(5000, 5000 + args.train_seeds))
+    test_seeds = [5008, 5009][:args.test_seeds]
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    data = []
+    gen_newton = 0
+    for seed in train_seeds:
+        g = opm.GpuModel(cases.config5(seed))
+        states, reps = guess.simulate(g, steps, log=log)
+        gen_newton += sum(r["newton_its"] for r in reps)
+        g._work.clear()            # training needs the problem and the states only
+        data.append((g, states))
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    net = opm.GuessNet(seed=0)
+    t0 = time.perf_counter()
+    hist = guess.train(net, data, epochs=args.epochs, lr=args.lr, lr_final=0.1 * args.lr,
+                       log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    n_samples = sum(len(guess.sample_indices(len(st))) for _, st in data)
+    if args.save_net:
+        np.save(args.save_net, net.params())
+    del data
+    torch.cuda.empty_cache()
+    zero = opm.GuessNet(np.zeros(opm.GUESS_PARAMS, np.float32))
+    runs = {"previous_state": None, "extrapolation": zero, "learned": net}
+    tot = {k: {"wall_s": 0.0, "newton_its": 0, "lin_its": 0, "guess_starts": 0,
+               "learned_starts": 0, "extrapolation_starts": 0} for k in runs}
+    per_seed = {}
+    state_diff = 0.0
+    for seed in test_seeds:
+        g = opm.GpuModel(cases.config5(seed))
+        out = {}
+        for name, n_ in runs.items():
+            r = guess.compare(g, n_, steps, log=log)
+            out[name] = r
+            t = tot[name]
+            t["wall_s"] += sum(r["wall"])
+            t["newton_its"] += sum(r["newton"])
+            t["lin_its"] += sum(r["lin"])
+            t["guess_starts"] += sum(1 for u in r["used"] if u)
+            t["learned_starts"] += sum(1 for u in r["used"] if u == 1)
+            t["extrapolation_starts"] += sum(1 for u in r["used"] if u == 2)
+        base = out["previous_state"]["final"]
+        for name in ("extrapolation", "learned"):
+            f = out[name]["final"]
+            state_diff = max(state_diff, float(np.max(np.abs(f[:, 0] - base[:, 0]) / np.abs(base[:, 0]))),
+                             float(np.max(np.abs(f[:, 1:] - base[:, 1:]))))
+        per_seed[seed] = {k: {"newton": v["newton"], "used": v["used"]} for k, v in out.items()}
+    # inference cost: HIP events around repeated opm_guess_infer on the last test model
+    y = g.initial_state()
+    yg = g.zeros_state()
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        g.guess_infer(net, y, y)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 50
+    s_work = net.struct(g)
+    L = opm._guess_lib()
+    import ctypes
+    work = g.workspace("guess", L.opm_guess_work_bytes(g._pbp(), ctypes.byref(s_work)))
+    e0.record(stream)
+    for _ in range(reps):
+        L.opm_guess_infer(g._pbp(), ctypes.byref(s_work), opm._ptr(y), opm._ptr(y), opm._ptr(yg),
+                          opm._ptr(work), opm._stream())
+    e1.record(stream)
+    e1.synchronize()
+    t_inf = e0.elapsed_time(e1) * 1e-3 / reps
+    nbox = g.case.n_box
+    flops = 3 * 2 * 27 * 16 * 16 * nbox
+    pt = tot["previous_state"]
+    line = {"metric": "learned Newton guess: speedup over the previous-state start (wall time of "
+                      "the held-out runs, same tolerances)",
+            "value": round(pt["wall_s"] / tot["learned"]["wall_s"], 4), "unit": "x",
+            "n_gpus": 1, "steps": steps, "warmup": 0, "higher_is_better": True,
+            "dtype": "f64 (simulator) + bf16/f32 (network)", "data": "synthetic",
+            "config": {"workload": f"100x100x50 waterflood, {g.n} cells, 10-day steps, "
+                                   f"train seeds {train_seeds[0]}-{train_seeds[-1]}, "
+                                   f"test seeds {test_seeds}"},
+            "runs": tot,
+            "speedup_extrapolation": round(pt["wall_s"] / tot["extrapolation"]["wall_s"], 4),
+            "newton_its_ratio_learned": round(tot["learned"]["newton_its"] / pt["newton_its"], 4),
+            "newton_its_ratio_extrapolation": round(tot["extrapolation"]["newton_its"] / pt["newton_its"], 4),
+            "max_state_difference_vs_previous_state_start": state_diff,
+            "training": {"samples": n_samples, "epochs": args.epochs, "lr": args.lr,
+                         "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
+                         "train_s": round(t_train, 2), "data_generation_s": round(t_gen, 2),
+                         "data_generation_newton_its": gen_newton},
+            "inference": {"us_per_call": round(t_inf * 1e6, 2),
+                          "conv_tflops": round(flops / t_inf / 1e12, 2),
+                          "frac_of_bf16_mfma_peak": round(flops / t_inf / 2.5e15, 5)},
+            "per_seed": per_seed}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
                     help="timed report steps (default: 30 for c2, 10 for c3, 20 for c4)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3-mixed", "c4-ensemble"],
+    ap.add_argument("--workload", default="c2",
+                    choices=["c2", "c3-mixed", "c4-ensemble", "c5-guess"],
                     help="c2: the headline metric line; c3-mixed: FP32 ILU(0) vs FP64 on the "
-                         "masked 45k-cell grid; c4-ensemble: 64 members in one launch")
+                         "masked 45k-cell grid; c4-ensemble: 64 members in one launch; "
+                         "c5-guess: learned Newton guess on the 500k-cell waterflood")
+    ap.add_argument("--train-seeds", type=int, default=8, help="training seeds (c5-guess)")
+    ap.add_argument("--test-seeds", type=int, default=2, help="held-out seeds (c5-guess)")
+    ap.add_argument("--epochs", type=int, default=40, help="training epochs (c5-guess)")
+    ap.add_argument("--lr", type=float, default=1e-3, help="Adam step size (c5-guess)")
+    ap.add_argument("--save-net", default=None, help="save the trained parameters (.npy)")
     ap.add_argument("--members", type=int, default=64, help="ensemble size (c4-ensemble)")
     ap.add_argument("--baseline-members", type=int, default=4,
                     help="members timed one by one on the single-system FP64 path (c4-ensemble)")
@@ -223,6 +347,8 @@ def main():
         return bench_mixed(args)
     if args.workload == "c4-ensemble":
         return bench_ensemble(args)
+    if args.workload == "c5-guess":
+        return bench_guess(args)
     if args.steps is None:
         args.steps = 30
     case = cases.config2()

@@ -334,6 +334,126 @@ int opm_ensemble_launch(const void* work, int32_t n_members, int precision, int3
                         double dt_report, int32_t n_steps, const opm_newton_opts* opts,
                         opm_ensemble_report* reports, void* stream);
 
+/* ------------------------------------------- learned Newton initial guess --
+ * Newton starts each time step from the previous state (sec. 2.3).  These
+ * calls add a learned start: a three-layer 3-D convolutional network
+ * (3x3x3 kernels, 16 channels, zero padding at the box faces, ReLU after
+ * layers 1 and 2) on the nx*ny*nz box of the grid predicts the change of
+ * (p, s_w, s_g) over one report step from the two last states, the
+ * log-permeability and the well terms of each cell: the last change
+ * y_n - y_{n-1} (linear extrapolation, a skip connection kept in FP64) plus a
+ * learned correction, applied away from wells: in cells whose 3x3x3 box
+ * neighbourhood has no non-zero well channel in the features (equal report
+ * steps are assumed).  The prediction is used
+ * only when its max CNV (sec. 2.3) is below that of the previous state, and
+ * the convergence test is unchanged, so a converged step meets the same
+ * tolerances whichever start it took.
+ *
+ * Tensors of the network (device, caller-owned):
+ *  - master: FP32 parameters, OPM_GUESS_PARAMS floats: for layer l = 0, 1, 2
+ *    the weights W_l[27][16 out][16 in] followed by the bias b_l[16]; tap
+ *    t = 9 (dz+1) + 3 (dy+1) + (dx+1) reads box cell (x+dx, y+dy, z+dz).
+ *  - wbf16: BF16 copies of the weights (2 * 3 * 27*16*16 uint16; the forward
+ *    layout [l][t][out][in], then the backward layout [l][t][in][out]),
+ *    written by opm_guess_pack_weights.
+ *  - activations: BF16 (uint16, round to nearest even) channels-last
+ *    [box cell][16], box cell = x + nx (y + ny z), padded to a multiple of
+ *    16 box cells; products accumulate in FP32.
+ *  - features (layer-0 input) of an active cell: (p_n - 4800 psi)/1000 psi,
+ *    s_w,n, s_g,n, the last change (p_n - p_{n-1})/100 psi,
+ *    (s_w,n - s_w,n-1)/0.1, (s_g,n - s_g,n-1)/0.1, log10(k_h / 1 mD) - 2, the fixed
+ *    injection rates of water, oil and gas per 10 m^3/day, and
+ *    ln(1 + sum WI (p_n - p_bhp)^+ / 1 cP per 10 m^3/day) of producers;
+ *    channels 11-15 and inactive box cells are zero.
+ *  - output (layer 2, FP32): channels 0-2 correct the extrapolated step
+ *    y_n - y_{n-1}, as dp / 100 psi, ds_w / 0.1 and ds_g / 0.1. */
+#define OPM_GUESS_CHANNELS 16
+#define OPM_GUESS_PARAMS (3 * (27 * 16 * 16 + 16))
+
+typedef struct opm_guess_net {
+  int32_t nx, ny, nz, pad;
+  const int32_t* cell_box;   /* device [n_cells] (opm_topology.cell_box)      */
+  const double* perm_h;      /* device [n_cells] horizontal permeability [m^2] */
+  float* master;             /* device [OPM_GUESS_PARAMS]                      */
+  void* wbf16;               /* device, see above                             */
+} opm_guess_net;
+
+/* BF16 operand copies of the master weights (device in, device out). */
+int opm_guess_pack_weights(const float* master, void* wbf16, void* stream);
+
+/* One convolution layer: out = conv(in, W) + b over the box; relu != 0
+ * gives max(out, 0) in BF16 into out_bf16, else FP32 into out_f32.  in:
+ * BF16 [box][16]; w_fwd: BF16 [27][16 out][16 in] of that layer. */
+int opm_guess_conv(int32_t nx, int32_t ny, int32_t nz, const void* in, const void* w_fwd,
+                   const float* bias, int32_t relu, void* out_bf16, float* out_f32,
+                   void* stream);
+
+/* Workspace (bytes) of opm_guess_conv_backward. */
+size_t opm_guess_conv_backward_bytes(int32_t nx, int32_t ny, int32_t nz);
+
+/* Backward of one layer: grad (device FP32 [27*16*16 + 16], overwritten) =
+ * dL/dW in [t][out][in] order then dL/db, from the layer input `in` and
+ * dout = dL/d(pre-activation output) (both BF16 [box][16]).  If din is not
+ * NULL it receives dL/d(pre-activation input) in BF16: the transposed
+ * convolution of dout with w_bwd (BF16 [27][16 in][16 out]) where
+ * act_in > 0, else 0.  The sums over cells run in a fixed order. */
+int opm_guess_conv_backward(int32_t nx, int32_t ny, int32_t nz, const void* in, const void* dout,
+                            const void* w_bwd, const void* act_in, void* din, float* grad,
+                            void* work, size_t work_bytes, void* stream);
+
+/* Layer-0 input (BF16 [box][16], all of it written) from y_n and y_{n-1}. */
+int opm_guess_features(const opm_problem* pb, const opm_guess_net* net, const double* y_n,
+                       const double* y_nm1, void* feats, void* stream);
+
+/* Workspace (bytes) of opm_guess_infer / opm_guess_train_step; 0 if the
+ * problem or the network is invalid. */
+size_t opm_guess_work_bytes(const opm_problem* pb, const opm_guess_net* net);
+
+/* y_guess (device [n][3]) = y_n + (y_n - y_{n-1}) + the network's
+ * correction (output channels 0-2 scaled back: dp = 100 psi * out_0,
+ * ds = 0.1 * out_1,2), the correction used only away from wells (see above)
+ * and only where finite; s_w and s_g clamped to [0, 1] and s_g
+ * lowered so that s_w + s_g <= 1. */
+int opm_guess_infer(const opm_problem* pb, const opm_guess_net* net, const double* y_n,
+                    const double* y_nm1, double* y_guess, void* work, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step >= 1) on
+ * loss = sum over active cells away from wells and the three outputs of
+ * (output - target)^2, divided by 3 n_cells, where target is the
+ * scaled correction of the step to the extrapolated one:
+ * d = (y_next - y_n) - (y_n - y_{n-1}), target = (d_p / 100 psi,
+ * d_sw / 0.1, d_sg / 0.1).  Updates master, adam_m, adam_v (device FP32
+ * [OPM_GUESS_PARAMS]) and wbf16; loss: device double, the loss before the
+ * step. */
+int opm_guess_train_step(const opm_problem* pb, const opm_guess_net* net, const double* y_n,
+                         const double* y_nm1, const double* y_next, float* adam_m, float* adam_v,
+                         int32_t step, float lr, double* loss, void* work, void* stream);
+
+/* Choice of the Newton start: assembles at y_prev and at y_guess (both
+ * against the accumulation of y_prev over dt) and copies into y the one
+ * with the lower max CNV (y_prev on ties; a guess with a non-finite norm is
+ * never taken).  work: the
+ * Newton workspace (opm_newton_bytes, any precision).  chosen (host): 1 if
+ * y_guess was taken; cnv (host [2]): max CNV at y_prev and at y_guess.
+ * Synchronises the stream. */
+int opm_guess_select(const opm_problem* pb, double* y, const double* y_prev,
+                     const double* y_guess, double dt, void* work, int32_t* chosen, double* cnv,
+                     void* stream);
+
+/* opm_advance whose first attempt at the full report step starts from the
+ * best of three (lowest max CNV against the accumulation of the previous
+ * state, earlier ones winning ties): the previous state, the learned guess
+ * (opm_guess_infer from y and y_nm1), the extrapolation y_n + (y_n - y_{n-1})
+ * alone (the guess without its learned correction); every substep after a
+ * cut starts from the previous state.  net may be NULL (then it is
+ * opm_advance).  guess_work: opm_guess_work_bytes; y_guess: device [n][3]
+ * scratch; guess_used (host): 0 previous state, 1 learned guess,
+ * 2 extrapolation. */
+int opm_advance_guess(const opm_problem* pb, double* y, const double* y_nm1, double dt,
+                      const opm_newton_opts* opts, const opm_guess_net* net, void* guess_work,
+                      double* y_guess, void* work, double* y_save, opm_newton_report* report,
+                      int32_t* guess_used, void* stream);
+
 /* Process-wide tuning knobs (host, synchronous); they change speed, never
  * results beyond round-off.  Returns OPM_OK, or OPM_EINVAL for an unknown
  * option or value.

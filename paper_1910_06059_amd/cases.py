@@ -13,6 +13,7 @@ the flat index ``c = i + nx*(j + ny*k)`` is the natural cell order.
 from __future__ import annotations
 
 import dataclasses
+import math
 from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -290,3 +291,39 @@ def random_state(case: Case, seed: int, p_jitter: float = 50 * PSI,
 
 
 CONFIGS = {"C1": config1, "C2": config2, "C3": config3, "C5": config5}
+
+
+# ---------------------------------------------- learned-guess network inputs
+GUESS_CH = 16
+GUESS_LAYER_W = 27 * GUESS_CH * GUESS_CH
+GUESS_LAYER = GUESS_LAYER_W + GUESS_CH
+GUESS_PARAMS = 3 * GUESS_LAYER
+
+
+def guess_init_params(seed: int = 0, last_scale: float = 0.01) -> np.ndarray:
+    """Seeded starting parameters of the 3-layer 3x3x3 guess network (FP32
+    [W_l[27][16 out][16 in], b_l[16]] for l = 0, 1, 2): He-normal weights
+    (std sqrt(2 / fan_in), fan_in = 27 * 16), zero biases, the last layer
+    scaled by last_scale so that the first corrections stay near zero."""
+    rng = np.random.default_rng(seed)
+    std = math.sqrt(2.0 / (27 * GUESS_CH))
+    p = np.zeros(GUESS_PARAMS, dtype=np.float64)
+    for l in range(3):
+        w = rng.standard_normal(GUESS_LAYER_W) * std * (last_scale if l == 2 else 1.0)
+        p[l * GUESS_LAYER:l * GUESS_LAYER + GUESS_LAYER_W] = w
+    return p.astype(np.float32)
+
+
+def guess_random_feats(shape, seed: int, active=None, channels: int = 11) -> np.ndarray:
+    """Seeded BF16-representable layer inputs [nz, ny, nx, 16] (float32) for
+    layer-level tests: standard normal in the first `channels` channels of
+    active box cells, zero elsewhere."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    x = np.zeros((nz, ny, nx, GUESS_CH), dtype=np.float32)
+    v = rng.standard_normal((nz, ny, nx, channels)).astype(np.float32)
+    v = (v.view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32)   # exact in BF16
+    x[..., :channels] = v
+    if active is not None:
+        x[~np.asarray(active, dtype=bool)] = 0.0
+    return x

@@ -25,6 +25,10 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
              double* x, double rtol, int maxit, void* work, opm_solve_report* rep,
              hipStream_t st);
 
+int guess_infer(const opm_problem* pb, const opm_guess_net* net, const double* y_n,
+                const double* y_nm1, double* y_guess, void* work, hipStream_t s,
+                const double** y_extrap = nullptr);
+
 namespace {
 
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -206,6 +210,92 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
   return status;
 }
 
+// Start of a Newton solve: y_prev or one of the candidates, whichever has the
+// lowest max CNV (earlier entries win ties; non-finite norms never win).
+// chosen = 0 for y_prev, k + 1 for cand[k]; cnv[0 .. ncand] the norms.
+int guess_select(const opm_problem* pb, double* y, const double* y_prev,
+                 const double* const* cand, int ncand, double dt, void* work, int32_t* chosen,
+                 double* cnv, hipStream_t s) {
+  NewtonWork w = carve(pb, OPM_PREC_FP64, work);
+  OPM_TRY(launch_accumulation(pb, y_prev, w.acc0, s));
+  double best = 0.0;
+  int take = 0;
+  for (int k = 0; k <= ncand; ++k) {
+    const double* yk = k == 0 ? y_prev : cand[k - 1];
+    double c = 0.0;
+    OPM_TRY(launch_assemble(pb, yk, w.acc0, dt, w.R, w.J, w.norms, s));
+    OPM_TRY_HIP(hipMemcpyAsync(&c, w.norms + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+    OPM_TRY_HIP(hipStreamSynchronize(s));
+    if (cnv) cnv[k] = c;
+    if (k == 0 || (std::isfinite(c) && c < best)) {
+      if (k == 0 && !std::isfinite(c)) best = INFINITY;
+      else best = c;
+      take = k;
+    }
+  }
+  const double* src = take == 0 ? y_prev : cand[take - 1];
+  const size_t bytes = sizeof(double) * 3 * (size_t)pb->n_cells;
+  if (src != y) OPM_TRY_HIP(hipMemcpyAsync(y, src, bytes, hipMemcpyDeviceToDevice, s));
+  OPM_TRY_HIP(hipStreamSynchronize(s));
+  if (chosen) *chosen = take;
+  return OPM_OK;
+}
+
+// Report step with cuts (sec. 2.3); the first full-length attempt may start
+// from the learned guess or from its extrapolation path alone.
+int advance(const opm_problem* pb, double* y, const double* y_nm1, double dt,
+            const opm_newton_opts* opts, const opm_guess_net* net, void* guess_work,
+            double* y_guess, void* work, double* y_save, opm_newton_report* report,
+            int32_t* guess_used, hipStream_t s) {
+  const size_t bytes = sizeof(double) * 3 * (size_t)pb->n_cells;
+  memset(report, 0, sizeof(*report));
+  if (guess_used) *guess_used = 0;
+  OPM_TRY_HIP(hipMemcpyAsync(y_save, y, bytes, hipMemcpyDeviceToDevice, s));
+  double t = 0.0, dt_try = dt;
+  int status = OPM_OK;
+  bool first = true;
+  while (dt - t > 1e-9 * dt) {
+    const double h = fmin(dt_try, dt - t);
+    if (first && net) {
+      const double* y_ext = nullptr;
+      OPM_TRY(guess_infer(pb, net, y_save, y_nm1, y_guess, guess_work, s, &y_ext));
+      const double* cand[2] = {y_guess, y_ext};
+      OPM_TRY(guess_select(pb, y, y_save, cand, 2, h, work, guess_used, nullptr, s));
+    }
+    first = false;
+    opm_newton_report r1;
+    int st = newton_step(pb, y, y_save, h, opts, work, &r1, s);
+    if (st == OPM_EHIP || st == OPM_EINVAL) return st;
+    report->newton_its += r1.newton_its;
+    report->lin_its += r1.lin_its;
+    report->cell_newton_its += r1.cell_newton_its;
+    report->t_assemble += r1.t_assemble;
+    report->t_factor += r1.t_factor;
+    report->t_krylov += r1.t_krylov;
+    report->t_update += r1.t_update;
+    if (st == OPM_OK) {
+      for (int c = 0; c < 3; ++c) {
+        report->cnv[c] = r1.cnv[c];
+        report->mb[c] = r1.mb[c];
+      }
+      OPM_TRY_HIP(hipMemcpyAsync(y_save, y, bytes, hipMemcpyDeviceToDevice, s));
+      t += h;
+      report->substeps++;
+    } else {
+      OPM_TRY_HIP(hipMemcpyAsync(y, y_save, bytes, hipMemcpyDeviceToDevice, s));
+      dt_try = 0.5 * h;
+      report->cuts++;
+      if (report->cuts > opts->max_cuts) {
+        status = st;
+        break;
+      }
+    }
+  }
+  OPM_TRY_HIP(hipStreamSynchronize(s));
+  report->status = status;
+  return status;
+}
+
 }  // namespace
 }  // namespace opm
 
@@ -333,45 +423,30 @@ int opm_advance(const opm_problem* pb, double* y, double dt, const opm_newton_op
   if (!valid_problem(pb) || pb->n_cells == 0 || !valid_opts(opts) || !(dt > 0.0) || !y ||
       !y_save || !work || !report)
     return OPM_EINVAL;
-  hipStream_t s = as_stream(stream);
-  const size_t bytes = sizeof(double) * 3 * (size_t)pb->n_cells;
-  memset(report, 0, sizeof(*report));
-  OPM_TRY_HIP(hipMemcpyAsync(y_save, y, bytes, hipMemcpyDeviceToDevice, s));
-  double t = 0.0, dt_try = dt;
-  int status = OPM_OK;
-  while (dt - t > 1e-9 * dt) {
-    const double h = fmin(dt_try, dt - t);
-    opm_newton_report r1;
-    int st = newton_step(pb, y, y_save, h, opts, work, &r1, s);
-    if (st == OPM_EHIP || st == OPM_EINVAL) return st;
-    report->newton_its += r1.newton_its;
-    report->lin_its += r1.lin_its;
-    report->cell_newton_its += r1.cell_newton_its;
-    report->t_assemble += r1.t_assemble;
-    report->t_factor += r1.t_factor;
-    report->t_krylov += r1.t_krylov;
-    report->t_update += r1.t_update;
-    if (st == OPM_OK) {
-      for (int c = 0; c < 3; ++c) {
-        report->cnv[c] = r1.cnv[c];
-        report->mb[c] = r1.mb[c];
-      }
-      OPM_TRY_HIP(hipMemcpyAsync(y_save, y, bytes, hipMemcpyDeviceToDevice, s));
-      t += h;
-      report->substeps++;
-    } else {
-      OPM_TRY_HIP(hipMemcpyAsync(y, y_save, bytes, hipMemcpyDeviceToDevice, s));
-      dt_try = 0.5 * h;
-      report->cuts++;
-      if (report->cuts > opts->max_cuts) {
-        status = st;
-        break;
-      }
-    }
-  }
-  OPM_TRY_HIP(hipStreamSynchronize(s));
-  report->status = status;
-  return status;
+  return advance(pb, y, nullptr, dt, opts, nullptr, nullptr, nullptr, work, y_save, report,
+                 nullptr, as_stream(stream));
+}
+
+int opm_guess_select(const opm_problem* pb, double* y, const double* y_prev,
+                     const double* y_guess, double dt, void* work, int32_t* chosen, double* cnv,
+                     void* stream) {
+  if (!valid_problem(pb) || pb->n_cells == 0 || !(dt > 0.0) || !y || !y_prev || !y_guess ||
+      !work)
+    return OPM_EINVAL;
+  return guess_select(pb, y, y_prev, &y_guess, 1, dt, work, chosen, cnv, as_stream(stream));
+}
+
+int opm_advance_guess(const opm_problem* pb, double* y, const double* y_nm1, double dt,
+                      const opm_newton_opts* opts, const opm_guess_net* net, void* guess_work,
+                      double* y_guess, void* work, double* y_save, opm_newton_report* report,
+                      int32_t* guess_used, void* stream) {
+  if (!valid_problem(pb) || pb->n_cells == 0 || !valid_opts(opts) || !(dt > 0.0) || !y ||
+      !y_save || !work || !report)
+    return OPM_EINVAL;
+  if (net && (!y_nm1 || !guess_work || !y_guess || opm_guess_work_bytes(pb, net) == 0))
+    return OPM_EINVAL;
+  return advance(pb, y, y_nm1, dt, opts, net, guess_work, y_guess, work, y_save, report,
+                 guess_used, as_stream(stream));
 }
 
 }  // extern "C"

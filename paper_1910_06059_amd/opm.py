@@ -399,6 +399,70 @@ class GpuModel:
             reps.append(rep.as_dict())
         return y, states, reps
 
+    # ------------------------------------------------ learned initial guess
+    def guess_features(self, net, y_n, y_nm1):
+        c = self.case
+        s = net.struct(self)
+        feats = torch.zeros((guess_act_rows(c.nx, c.ny, c.nz), GUESS_CH), dtype=torch.int16,
+                            device=self.dev)
+        _check(_guess_lib().opm_guess_features(self._pbp(), ctypes.byref(s), _ptr(y_n), _ptr(y_nm1),
+                                               _ptr(feats), _stream()), "opm_guess_features")
+        return feats
+
+
+    def guess_infer(self, net, y_n, y_nm1):
+        s, work = _model_guess_work(self, net)
+        yg = self.zeros_state()
+        _check(_guess_lib().opm_guess_infer(self._pbp(), ctypes.byref(s), _ptr(y_n), _ptr(y_nm1),
+                                            _ptr(yg), _ptr(work), _stream()), "opm_guess_infer")
+        return yg
+
+
+    def guess_train_step(self, net, y_n, y_nm1, y_next, lr, loss_out=None):
+        """One Adam step on one sample; returns the device loss (before the step)."""
+        s, work = _model_guess_work(self, net)
+        loss = loss_out if loss_out is not None else torch.zeros(1, dtype=torch.float64,
+                                                                 device=self.dev)
+        net.step += 1
+        _check(_guess_lib().opm_guess_train_step(self._pbp(), ctypes.byref(s), _ptr(y_n), _ptr(y_nm1),
+                                                 _ptr(y_next), _ptr(net.adam_m), _ptr(net.adam_v),
+                                                 net.step, float(lr), _ptr(loss), _ptr(work),
+                                                 _stream()), "opm_guess_train_step")
+        return loss
+
+
+    def guess_select(self, y, y_prev, y_guess, dt, precision=PREC_FP64):
+        L = _guess_lib()
+        work = self.workspace(f"newton{precision}", L.opm_newton_bytes(self._pbp(), precision))
+        chosen = _i32()
+        cnv = (ctypes.c_double * 2)()
+        _check(L.opm_guess_select(self._pbp(), _ptr(y), _ptr(y_prev), _ptr(y_guess), dt, _ptr(work),
+                                  ctypes.byref(chosen), cnv, _stream()), "opm_guess_select")
+        return chosen.value, (cnv[0], cnv[1])
+
+
+    def advance_guess(self, y, y_nm1, dt, net=None, opts: Optional[NewtonOpts] = None):
+        """opm_advance_guess: (status, report, guess_used)."""
+        L = _guess_lib()
+        o = opts or default_opts(self.case)
+        work = self.workspace(f"newton{o.precision}", L.opm_newton_bytes(self._pbp(), o.precision))
+        ysave = self.workspace("ysave", 24 * self.n).view(torch.float64)[:3 * self.n].view(self.n, 3)
+        rep = NewtonReport()
+        used = _i32()
+        if net is not None:
+            s, gwork = _model_guess_work(self, net)
+            yg = self.workspace("yguess", 24 * self.n).view(torch.float64)[:3 * self.n]
+            st = L.opm_advance_guess(self._pbp(), _ptr(y), _ptr(y_nm1), dt, ctypes.byref(o),
+                                     ctypes.byref(s), _ptr(gwork), _ptr(yg), _ptr(work), _ptr(ysave),
+                                     ctypes.byref(rep), ctypes.byref(used), _stream())
+        else:
+            st = L.opm_advance_guess(self._pbp(), _ptr(y), None, dt, ctypes.byref(o), None, None,
+                                     None, _ptr(work), _ptr(ysave), ctypes.byref(rep),
+                                     ctypes.byref(used), _stream())
+        if st in (EINVAL, EHIP):
+            _check(st, "opm_advance_guess")
+        return st, rep, used.value
+
 
 class EnsembleReport(ctypes.Structure):
     _fields_ = [("status", _i32), ("newton_its", _i32), ("lin_its", _i32), ("substeps", _i32),
@@ -469,3 +533,133 @@ class Ensemble:
 
     def states(self):
         return [t.detach().cpu().numpy().copy() for t in self.y]
+
+
+# ------------------------------------------------ learned Newton initial guess
+GUESS_CH = _cases.GUESS_CH
+GUESS_LAYER_W = _cases.GUESS_LAYER_W
+GUESS_LAYER = _cases.GUESS_LAYER
+GUESS_PARAMS = _cases.GUESS_PARAMS
+
+EXPORTS += ["opm_guess_pack_weights", "opm_guess_conv", "opm_guess_conv_backward_bytes",
+            "opm_guess_conv_backward", "opm_guess_features", "opm_guess_work_bytes",
+            "opm_guess_infer", "opm_guess_train_step", "opm_guess_select", "opm_advance_guess"]
+
+
+class GuessNetStruct(ctypes.Structure):
+    _fields_ = [("nx", _i32), ("ny", _i32), ("nz", _i32), ("pad", _i32), ("cell_box", _vp),
+                ("perm_h", _vp), ("master", _vp), ("wbf16", _vp)]
+
+
+def _guess_lib():
+    L = lib()
+    if not getattr(L, "_guess_ready", False):
+        P = ctypes.POINTER(Problem)
+        N = ctypes.POINTER(GuessNetStruct)
+        sz = ctypes.c_size_t
+        L.opm_guess_pack_weights.argtypes = [_vp, _vp, _vp]
+        L.opm_guess_conv.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp]
+        L.opm_guess_conv_backward_bytes.argtypes = [_i32, _i32, _i32]
+        L.opm_guess_conv_backward_bytes.restype = sz
+        L.opm_guess_conv_backward.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                              _vp, sz, _vp]
+        L.opm_guess_features.argtypes = [P, N, _vp, _vp, _vp, _vp]
+        L.opm_guess_work_bytes.argtypes = [P, N]
+        L.opm_guess_work_bytes.restype = sz
+        L.opm_guess_infer.argtypes = [P, N, _vp, _vp, _vp, _vp, _vp]
+        L.opm_guess_train_step.argtypes = [P, N, _vp, _vp, _vp, _vp, _vp, _i32, ctypes.c_float,
+                                           _vp, _vp, _vp]
+        L.opm_guess_select.argtypes = [P, _vp, _vp, _vp, ctypes.c_double, _vp, _ip, _dp, _vp]
+        L.opm_advance_guess.argtypes = [P, _vp, _vp, ctypes.c_double, ctypes.POINTER(NewtonOpts),
+                                        N, _vp, _vp, _vp, _vp, ctypes.POINTER(NewtonReport), _ip,
+                                        _vp]
+        L._guess_ready = True
+    return L
+
+
+def guess_act_rows(nx, ny, nz) -> int:
+    """Rows of a BF16 activation buffer: the box padded to 16 cells."""
+    return (nx * ny * nz + 15) // 16 * 16
+
+
+def guess_pack_weights(master: torch.Tensor, wbf16: torch.Tensor) -> None:
+    _check(_guess_lib().opm_guess_pack_weights(_ptr(master), _ptr(wbf16), _stream()),
+           "opm_guess_pack_weights")
+
+
+def guess_conv(shape, x: torch.Tensor, w_fwd: torch.Tensor, bias: torch.Tensor, relu: bool):
+    """One layer on the box (nz, ny, nx): BF16 out (int16 view) if relu, else FP32."""
+    nz, ny, nx = shape
+    rows = guess_act_rows(nx, ny, nz)
+    if relu:
+        out = torch.zeros((rows, GUESS_CH), dtype=torch.int16, device=x.device)
+        args = (_ptr(out), None)
+    else:
+        out = torch.zeros((rows, GUESS_CH), dtype=torch.float32, device=x.device)
+        args = (None, _ptr(out))
+    _check(_guess_lib().opm_guess_conv(nx, ny, nz, _ptr(x), _ptr(w_fwd), _ptr(bias), int(relu),
+                                       *args, _stream()), "opm_guess_conv")
+    return out
+
+
+def guess_conv_backward(shape, x, dout, w_bwd=None, act_in=None):
+    """(grad [27*16*16 + 16] FP32, din BF16 or None) of one layer."""
+    nz, ny, nx = shape
+    L = _guess_lib()
+    nbytes = L.opm_guess_conv_backward_bytes(nx, ny, nz)
+    work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=x.device)
+    grad = torch.zeros(GUESS_LAYER, dtype=torch.float32, device=x.device)
+    din = None
+    if w_bwd is not None:
+        din = torch.zeros((guess_act_rows(nx, ny, nz), GUESS_CH), dtype=torch.int16,
+                          device=x.device)
+    _check(L.opm_guess_conv_backward(nx, ny, nz, _ptr(x), _ptr(dout), _ptr(w_bwd), _ptr(act_in),
+                                     _ptr(din), _ptr(grad), _ptr(work), nbytes, _stream()),
+           "opm_guess_conv_backward")
+    return grad, din
+
+
+class GuessNet:
+    """Parameters of the learned guess on the device: FP32 master copy, BF16
+    operand copies and Adam moments."""
+
+    def __init__(self, params: Optional[np.ndarray] = None, seed: int = 0, device="cuda"):
+        init()
+        p = _cases.guess_init_params(seed) if params is None else np.asarray(params, np.float32)
+        if p.shape != (GUESS_PARAMS,):
+            raise ValueError("guess parameters must have %d entries" % GUESS_PARAMS)
+        self.dev = torch.device(device)
+        self.master = torch.from_numpy(p.copy()).to(self.dev)
+        self.wbf16 = torch.zeros(2 * 3 * GUESS_LAYER_W, dtype=torch.int16, device=self.dev)
+        self.adam_m = torch.zeros(GUESS_PARAMS, dtype=torch.float32, device=self.dev)
+        self.adam_v = torch.zeros(GUESS_PARAMS, dtype=torch.float32, device=self.dev)
+        self.step = 0
+        guess_pack_weights(self.master, self.wbf16)
+
+    def params(self) -> np.ndarray:
+        return self.master.detach().cpu().numpy().copy()
+
+    def w_fwd(self, layer):
+        return self.wbf16[layer * GUESS_LAYER_W:(layer + 1) * GUESS_LAYER_W]
+
+    def w_bwd(self, layer):
+        base = 3 * GUESS_LAYER_W
+        return self.wbf16[base + layer * GUESS_LAYER_W:base + (layer + 1) * GUESS_LAYER_W]
+
+    def bias(self, layer):
+        return self.master[layer * GUESS_LAYER + GUESS_LAYER_W:(layer + 1) * GUESS_LAYER]
+
+    def struct(self, model: "GpuModel") -> GuessNetStruct:
+        c = model.case
+        return GuessNetStruct(nx=c.nx, ny=c.ny, nz=c.nz, pad=0,
+                              cell_box=model.t["cell_box"].data_ptr(),
+                              perm_h=model.perm_h.data_ptr(), master=self.master.data_ptr(),
+                              wbf16=self.wbf16.data_ptr())
+
+
+def _model_guess_work(model, net):
+    s = net.struct(model)
+    nbytes = _guess_lib().opm_guess_work_bytes(model._pbp(), ctypes.byref(s))
+    if nbytes == 0:
+        raise OpmError(EINVAL, "opm_guess_work_bytes")
+    return s, model.workspace("guess", nbytes)
