@@ -131,8 +131,9 @@ def bench_mixed(args):
 
 def bench_ensemble(args):
     """64 members (uneven grids 20..60 x 20..60 x 20..30) advanced 20 report
-    steps of 15 days in one persistent launch, against the single-system FP64
-    GPU path run member by member on a sample of members."""
+    steps of 15 days in one persistent launch (replayed from a captured
+    graph, launch shape picked by the autotuner beforehand), against the
+    single-system FP64 GPU path run member by member on a sample of members."""
     import torch
     from paper_1910_06059_amd import cases, opm
     steps = args.steps or 20
@@ -147,9 +148,20 @@ def bench_ensemble(args):
     out = {}
     for prec in (opm.PREC_MIXED, opm.PREC_FP64):
         ens = opm.Ensemble(member_cases, precision=prec)
+        # launch shape from the autotuner (untimed: one trial report step per
+        # shape, states restored afterwards), then the timed work as one
+        # captured graph holding the single persistent launch
+        tuning = ens.autotune(dt, cache=args.tuning_cache)
+        graph = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cap):
+            with torch.cuda.graph(graph, stream=cap):
+                ens.launch(dt, steps)
+        torch.cuda.current_stream().wait_stream(cap)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ens.launch(dt, steps)
+        graph.replay()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         reps = ens.read_reports()
@@ -158,8 +170,9 @@ def bench_ensemble(args):
                      "members_ok": ok,
                      "newton_its": sum(r["newton_its"] for r in reps),
                      "lin_its": sum(r["lin_its"] for r in reps),
-                     "cell_newton_its_per_s": round(sum(r["cell_newton_its"] for r in reps) / wall, 1)}
-        del ens
+                     "cell_newton_its_per_s": round(sum(r["cell_newton_its"] for r in reps) / wall, 1),
+                     "launch_shape": tuning}
+        del ens, graph
     # single-system FP64 path, member by member, on a sample spread over sizes
     order = sorted(range(nm), key=lambda m: member_cases[m].n_active)
     k = max(1, min(args.baseline_members, nm))
@@ -321,6 +334,8 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3, help="Adam step size (c5-guess)")
     ap.add_argument("--save-net", default=None, help="save the trained parameters (.npy)")
     ap.add_argument("--members", type=int, default=64, help="ensemble size (c4-ensemble)")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="JSON file of autotuned ensemble launch shapes (c4-ensemble)")
     ap.add_argument("--baseline-members", type=int, default=4,
                     help="members timed one by one on the single-system FP64 path (c4-ensemble)")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 FP32 ILU(0) factors")

@@ -454,6 +454,50 @@ int opm_advance_guess(const opm_problem* pb, double* y, const double* y_nm1, dou
                       double* y_guess, void* work, double* y_save, opm_newton_report* report,
                       int32_t* guess_used, void* stream);
 
+/* Launch shape of the ensemble kernel: the schedule knobs that the
+ * autotuner chooses.  threads: workgroup size per member (128 or 256);
+ * fac_window: keep the previous level's ILU(0) pivots in LDS during the
+ * factorisation (allowed when every member has at most 640 rows per level);
+ * ring: members whose LDS ring (the values of the last sweep_span +
+ * max_level + 1 rows, rounded up to a power of two) fits sweep through the
+ * ring, the others through the two-level LDS window; sweep_bytes: out, the
+ * sweep storage of a launch (set by opm_ensemble_default_config and
+ * opm_ensemble_configure). */
+typedef struct opm_ensemble_config {
+  int32_t threads, fac_window, ring, sweep_bytes;
+} opm_ensemble_config;
+
+/* The shape opm_ensemble_launch uses (256 threads, factor window when
+ * allowed, window sweeps); host. */
+int opm_ensemble_default_config(const opm_problem* members, int32_t n_members, int precision,
+                                opm_ensemble_config* cfg);
+
+/* Apply a shape to a prepared workspace: writes each member's sweep choice
+ * into the device table and fills cfg->sweep_bytes.  Host, synchronous.
+ * OPM_EINVAL if the shape is invalid or does not fit in LDS. */
+int opm_ensemble_configure(const opm_problem* members, int32_t n_members, int precision,
+                           void* work, opm_ensemble_config* cfg);
+
+/* opm_ensemble_launch with the shape last passed to opm_ensemble_configure
+ * (asynchronous, capturable like opm_ensemble_launch). */
+int opm_ensemble_launch_config(const void* work, int32_t n_members, int precision,
+                               int32_t max_level, const opm_ensemble_config* cfg,
+                               double dt_report, int32_t n_steps, const opm_newton_opts* opts,
+                               opm_ensemble_report* reports, void* stream);
+
+/* Autotuner: times one report step of length dt_report of the whole
+ * ensemble for every valid shape (threads 256/128 x ring off/on x factor
+ * window on/off), restoring the members' states before each trial and at
+ * the end, then configures the workspace with the fastest shape and returns
+ * it in best.  seconds (host, optional, >= 8 entries) receives the trial
+ * times in trial order, n_tried (host, optional) their number.  Host,
+ * synchronous; results of later launches do not depend on the shape beyond
+ * the order of summation in reductions. */
+int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int precision,
+                          void* work, double dt_report, const opm_newton_opts* opts,
+                          opm_ensemble_config* best, double* seconds, int32_t* n_tried,
+                          void* stream);
+
 /* Process-wide tuning knobs (host, synchronous); they change speed, never
  * results beyond round-off.  Returns OPM_OK, or OPM_EINVAL for an unknown
  * option or value.

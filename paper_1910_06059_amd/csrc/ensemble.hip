@@ -38,6 +38,9 @@ struct EnsMember {
   double *y_save, *acc0, *R, *J, *d;
   void* ilu;
   double *r, *rh, *p, *v, *ph, *s, *sh, *t;
+  double* backup;        // copy of y kept by the autotuner between trials
+  int32_t ring;          // 1: ILU(0) sweeps through the LDS ring, 0: the LDS window
+  uint32_t ring_mask;    // ring capacity - 1 (rows)
 };
 
 inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
@@ -50,19 +53,26 @@ size_t member_bytes(const opm_problem& pb, int precision) {
          al256(ilu);
 }
 
-// LDS of the kernel: reduction scratch, sweep window, factor window.
+// LDS of the kernel: reduction scratch, sweep storage (the largest over the
+// members of the window, 2 levels x 3 values per row, or the ring), factor
+// window (previous level's pivots, when enabled).
+constexpr size_t kEnsLds = 150 * 1024;
+constexpr int kMaxFacWindowLevel = 640;
+
 struct LdsPlan {
   size_t red, sweep, fac, total;
-  bool fac_window;
 };
 
-template <typename T, int NT>
-LdsPlan lds_plan(int max_level) {
+inline size_t window_bytes(size_t tsize, int max_level) { return tsize * 2 * 3 * (size_t)max_level; }
+inline size_t ring_bytes(size_t tsize, const opm_problem& pb) {
+  return tsize * 3 * (size_t)ilu::ring_rows(pb.sweep_span, pb.max_level);
+}
+
+LdsPlan lds_plan(size_t tsize, int threads, size_t sweep_bytes, int max_level, bool fac_window) {
   LdsPlan p;
-  p.red = sizeof(double) * 2 * (NT / kWave);
-  p.sweep = al256(sizeof(T) * 2 * 3 * (size_t)max_level);
-  p.fac_window = max_level <= 640;
-  p.fac = p.fac_window ? sizeof(double) * 2 * 9 * (size_t)max_level : 0;
+  p.red = sizeof(double) * 2 * (threads / kWave);
+  p.sweep = al256(sweep_bytes);
+  p.fac = fac_window ? sizeof(double) * 2 * 9 * (size_t)max_level : 0;
   p.total = al256(p.red) + p.sweep + p.fac;
   return p;
 }
@@ -80,7 +90,8 @@ __device__ __forceinline__ double wg_max(double v, double* red) {
 // Right-preconditioned BiCGStab for J d = b by one workgroup (x0 = 0).
 template <typename T, int NT>
 __device__ int wg_bicgstab(const EnsMember& M, const Topo& tp, IluView<T> iv, const double* b,
-                           double* x, double rtol, int maxit, double* red, T* swin, int* its_out) {
+                           double* x, double rtol, int maxit, double* red, T* swin, bool ring,
+                           int* its_out) {
   const int n = M.pb.n_cells, N = 3 * n;
   const int tid = threadIdx.x;
   double bb = 0.0;
@@ -105,7 +116,10 @@ __device__ int wg_bicgstab(const EnsMember& M, const Topo& tp, IluView<T> iv, co
     const double beta = it == 1 ? 0.0 : (rho / rho0) * (alpha / omega);
     for (int k = tid; k < N; k += NT) M.p[k] = M.r[k] + beta * (M.p[k] - omega * M.v[k]);
     __syncthreads();
-    ilu::apply_levels_wg<T, NT>(tp, iv, M.p, M.ph, swin);
+    if (ring)
+      ilu::apply_levels_ring<T, NT>(tp, iv, M.p, M.ph, swin, M.ring_mask);
+    else
+      ilu::apply_levels_wg<T, NT>(tp, iv, M.p, M.ph, swin);
     double rv = 0.0;
     for (int i = tid; i < n; i += NT) {
       double y3[3];
@@ -131,7 +145,10 @@ __device__ int wg_bicgstab(const EnsMember& M, const Topo& tp, IluView<T> iv, co
       __syncthreads();
       return OPM_OK;
     }
-    ilu::apply_levels_wg<T, NT>(tp, iv, M.s, M.sh, swin);
+    if (ring)
+      ilu::apply_levels_ring<T, NT>(tp, iv, M.s, M.sh, swin, M.ring_mask);
+    else
+      ilu::apply_levels_wg<T, NT>(tp, iv, M.s, M.sh, swin);
     double ts = 0.0, tt = 0.0;
     for (int i = tid; i < n; i += NT) {
       double y3[3];
@@ -168,7 +185,7 @@ __device__ int wg_bicgstab(const EnsMember& M, const Topo& tp, IluView<T> iv, co
 // ------------------------------------------------------------------ Newton
 template <typename T, int NT, bool FACWIN>
 __device__ int wg_newton(const EnsMember& M, const Topo& tp, IluView<T> iv, double h,
-                         const opm_newton_opts& o, double* red, T* swin, double* fwin,
+                         const opm_newton_opts& o, double* red, T* swin, bool ring, double* fwin,
                          int* flag, opm_ensemble_report& rep) {
   const int n = M.pb.n_cells;
   const int tid = threadIdx.x;
@@ -238,7 +255,8 @@ __device__ int wg_newton(const EnsMember& M, const Topo& tp, IluView<T> iv, doub
     if (*flag != 0) return OPM_ESINGULAR;
     // BiCGStab: J d = R, Newton update y <- y - chop(d)
     int lits = 0;
-    const int st = wg_bicgstab<T, NT>(M, tp, iv, M.R, M.d, o.lin_rtol, o.lin_maxit, red, swin, &lits);
+    const int st = wg_bicgstab<T, NT>(M, tp, iv, M.R, M.d, o.lin_rtol, o.lin_maxit, red, swin,
+                                      ring, &lits);
     rep.lin_its += lits;
     if (st != OPM_OK) return st;
     if (tid == 0) *flag = 0;
@@ -285,6 +303,8 @@ __global__ __launch_bounds__(NT) void k_ensemble(const EnsMember* tab, int n_ste
   T* swin = reinterpret_cast<T*>(reinterpret_cast<char*>(smem) + red_bytes);
   double* fwin = reinterpret_cast<double*>(reinterpret_cast<char*>(smem) + red_bytes + sweep_bytes);
   const EnsMember M = tab[blockIdx.x];
+  // the ring is used only if it fits the sweep storage of this launch
+  const bool ring = M.ring && (size_t)(M.ring_mask + 1u) * 3u * sizeof(T) <= sweep_bytes;
   const Topo tp = ilu::topo_of(&M.pb);
   IluView<T> iv = ilu::view<T>(&M.pb, M.ilu);
   opm_ensemble_report rep = {};
@@ -296,7 +316,7 @@ __global__ __launch_bounds__(NT) void k_ensemble(const EnsMember* tab, int n_ste
     int cuts = 0;
     while (dt_report - t > 1e-9 * dt_report) {
       const double h = fmin(dt_try, dt_report - t);
-      const int st = wg_newton<T, NT, FACWIN>(M, tp, iv, h, o, red, swin, fwin, &flag, rep);
+      const int st = wg_newton<T, NT, FACWIN>(M, tp, iv, h, o, red, swin, ring, fwin, &flag, rep);
       __syncthreads();
       if (st == OPM_OK) {
         t += h;
@@ -318,32 +338,39 @@ __global__ __launch_bounds__(NT) void k_ensemble(const EnsMember* tab, int n_ste
   if (threadIdx.x == 0) reps[blockIdx.x] = rep;
 }
 
-constexpr int kEnsThreads = 256;
-
-// Raise the dynamic-LDS limit of the kernel instances (done at prepare time,
-// outside any graph capture).
+// Raise the dynamic-LDS limit of every kernel instance (done at prepare
+// time, outside any graph capture).
 template <typename T>
 int allow_ensemble_lds() {
-  OPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ensemble<T, kEnsThreads, true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
-  OPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ensemble<T, kEnsThreads, false>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
+  const void* k[4] = {reinterpret_cast<const void*>(k_ensemble<T, 256, true>),
+                      reinterpret_cast<const void*>(k_ensemble<T, 256, false>),
+                      reinterpret_cast<const void*>(k_ensemble<T, 128, true>),
+                      reinterpret_cast<const void*>(k_ensemble<T, 128, false>)};
+  for (const void* f : k)
+    OPM_TRY_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kEnsLds));
   return OPM_OK;
 }
 
 template <typename T>
-int launch_ensemble(const EnsMember* tab, int n_members, int max_level, double dt_report,
-                    int n_steps, const opm_newton_opts* o, opm_ensemble_report* reps,
-                    hipStream_t s) {
-  const LdsPlan lp = lds_plan<T, kEnsThreads>(max_level);
-  if (lp.total > 150 * 1024) return OPM_EINVAL;
+int launch_ensemble(const EnsMember* tab, int n_members, int max_level,
+                    const opm_ensemble_config& cfg, double dt_report, int n_steps,
+                    const opm_newton_opts* o, opm_ensemble_report* reps, hipStream_t s) {
+  const LdsPlan lp = lds_plan(sizeof(T), cfg.threads, (size_t)cfg.sweep_bytes, max_level,
+                              cfg.fac_window != 0);
+  if (lp.total > kEnsLds) return OPM_EINVAL;
   const size_t red = al256(lp.red);
-  if (lp.fac_window)
-    hipLaunchKernelGGL((k_ensemble<T, kEnsThreads, true>), dim3(n_members), dim3(kEnsThreads),
-                       lp.total, s, tab, n_steps, dt_report, *o, red, lp.sweep, reps);
-  else
-    hipLaunchKernelGGL((k_ensemble<T, kEnsThreads, false>), dim3(n_members), dim3(kEnsThreads),
-                       lp.total, s, tab, n_steps, dt_report, *o, red, lp.sweep, reps);
+  const dim3 grid(n_members);
+#define OPM_ENS_LAUNCH(NT, FW)                                                                   \
+  hipLaunchKernelGGL((k_ensemble<T, NT, FW>), grid, dim3(NT), lp.total, s, tab, n_steps,        \
+                     dt_report, *o, red, lp.sweep, reps)
+  if (cfg.threads == 256) {
+    if (cfg.fac_window) OPM_ENS_LAUNCH(256, true);
+    else OPM_ENS_LAUNCH(256, false);
+  } else {
+    if (cfg.fac_window) OPM_ENS_LAUNCH(128, true);
+    else OPM_ENS_LAUNCH(128, false);
+  }
+#undef OPM_ENS_LAUNCH
   OPM_TRY_HIP(hipGetLastError());
   return OPM_OK;
 }
@@ -351,6 +378,49 @@ int launch_ensemble(const EnsMember* tab, int n_members, int max_level, double d
 struct EnsHeader {
   int32_t n_members, precision, max_level, pad;
 };
+
+bool valid_config(const opm_ensemble_config& c, int max_level) {
+  return (c.threads == 128 || c.threads == 256) && (c.fac_window == 0 || c.fac_window == 1) &&
+         (c.ring == 0 || c.ring == 1) && (!c.fac_window || max_level <= kMaxFacWindowLevel);
+}
+
+// Per-member sweep choice and the LDS the launch needs; false if it does not fit.
+bool plan_members(const opm_problem* members, int n, int precision, opm_ensemble_config& c,
+                  std::vector<int32_t>* ring, int* max_level_out) {
+  const size_t ts = precision == OPM_PREC_MIXED ? sizeof(float) : sizeof(double);
+  int max_level = 0;
+  for (int m = 0; m < n; ++m) max_level = std::max(max_level, (int)members[m].max_level);
+  if (!valid_config(c, max_level)) return false;
+  const size_t fixed = lds_plan(ts, c.threads, 0, max_level, c.fac_window != 0).total;
+  size_t sweep = 0;
+  for (int m = 0; m < n; ++m) {
+    size_t b = window_bytes(ts, members[m].max_level);
+    int use_ring = 0;
+    if (c.ring && members[m].sweep_span > 0 && al256(ring_bytes(ts, members[m])) + fixed <= kEnsLds) {
+      b = ring_bytes(ts, members[m]);
+      use_ring = 1;
+    }
+    if (ring) (*ring)[m] = use_ring;
+    sweep = std::max(sweep, b);
+  }
+  c.sweep_bytes = (int32_t)al256(sweep);
+  if (lds_plan(ts, c.threads, sweep, max_level, c.fac_window != 0).total > kEnsLds) return false;
+  *max_level_out = max_level;
+  return true;
+}
+
+// Workspace: header, member table, the autotuner's trial reports, members.
+EnsMember* table_of(void* work) {
+  return reinterpret_cast<EnsMember*>((char*)work + al256(sizeof(EnsHeader)));
+}
+opm_ensemble_report* trial_reports_of(void* work, int n_members) {
+  return reinterpret_cast<opm_ensemble_report*>(
+      (char*)work + al256(sizeof(EnsHeader)) + al256(sizeof(EnsMember) * (size_t)n_members));
+}
+size_t members_offset(int n_members) {
+  return al256(sizeof(EnsHeader)) + al256(sizeof(EnsMember) * (size_t)n_members) +
+         al256(sizeof(opm_ensemble_report) * (size_t)n_members);
+}
 
 }  // namespace
 }  // namespace opm
@@ -362,9 +432,22 @@ extern "C" {
 size_t opm_ensemble_bytes(const opm_problem* members, int32_t n_members, int precision) {
   if (!members || n_members <= 0 || (precision != OPM_PREC_FP64 && precision != OPM_PREC_MIXED))
     return 0;
-  size_t b = al256(sizeof(EnsHeader)) + al256(sizeof(EnsMember) * (size_t)n_members);
+  size_t b = members_offset(n_members);
   for (int m = 0; m < n_members; ++m) b += member_bytes(members[m], precision);
   return b;
+}
+
+int opm_ensemble_default_config(const opm_problem* members, int32_t n_members, int precision,
+                                opm_ensemble_config* cfg) {
+  if (!members || n_members <= 0 || !cfg ||
+      (precision != OPM_PREC_FP64 && precision != OPM_PREC_MIXED))
+    return OPM_EINVAL;
+  int max_level = 0;
+  for (int m = 0; m < n_members; ++m) max_level = std::max(max_level, (int)members[m].max_level);
+  opm_ensemble_config c{256, max_level <= kMaxFacWindowLevel ? 1 : 0, 0, 0};
+  if (!plan_members(members, n_members, precision, c, nullptr, &max_level)) return OPM_EINVAL;
+  *cfg = c;
+  return OPM_OK;
 }
 
 int opm_ensemble_prepare(const opm_problem* members, double* const* y, int32_t n_members,
@@ -379,12 +462,11 @@ int opm_ensemble_prepare(const opm_problem* members, double* const* y, int32_t n
       return OPM_EINVAL;
     max_level = std::max(max_level, (int)pb.max_level);
   }
-  const size_t lds = precision == OPM_PREC_MIXED ? lds_plan<float, kEnsThreads>(max_level).total
-                                                 : lds_plan<double, kEnsThreads>(max_level).total;
-  if (lds > 150 * 1024) return OPM_EINVAL;
+  opm_ensemble_config c;
+  OPM_TRY(opm_ensemble_default_config(members, n_members, precision, &c));
   std::vector<EnsMember> tab(n_members);
   char* base = (char*)work;
-  char* c = base + al256(sizeof(EnsHeader)) + al256(sizeof(EnsMember) * (size_t)n_members);
+  char* cur = base + members_offset(n_members);
   for (int m = 0; m < n_members; ++m) {
     const opm_problem& pb = members[m];
     const size_t N = 3 * (size_t)pb.n_cells;
@@ -393,41 +475,147 @@ int opm_ensemble_prepare(const opm_problem* members, double* const* y, int32_t n
     e.pb.level_ptr_h = nullptr;
     e.y = y[m];
     double** vecs[13] = {&e.y_save, &e.acc0, &e.R, &e.d, &e.r, &e.rh, &e.p,
-                         &e.v,      &e.ph,   &e.s, &e.sh, &e.t, nullptr};
-    for (int k = 0; k < 12; ++k) {
-      *vecs[k] = (double*)c;
-      c += al256(sizeof(double) * N);
+                         &e.v,      &e.ph,   &e.s, &e.sh, &e.t, &e.backup};
+    for (int k = 0; k < 13; ++k) {
+      *vecs[k] = (double*)cur;
+      cur += al256(sizeof(double) * N);
     }
-    c += al256(sizeof(double) * N);   // spare vector slot
-    e.J = (double*)c;
-    c += al256(sizeof(double) * 9 * (size_t)pb.nnzb);
-    e.ilu = c;
-    c += al256(precision == OPM_PREC_MIXED ? ilu::view_bytes<float>(pb.n_cells)
-                                           : ilu::view_bytes<double>(pb.n_cells));
+    e.J = (double*)cur;
+    cur += al256(sizeof(double) * 9 * (size_t)pb.nnzb);
+    e.ilu = cur;
+    cur += al256(precision == OPM_PREC_MIXED ? ilu::view_bytes<float>(pb.n_cells)
+                                             : ilu::view_bytes<double>(pb.n_cells));
+    e.ring = 0;
+    e.ring_mask = (uint32_t)ilu::ring_rows(pb.sweep_span, pb.max_level) - 1u;
   }
   OPM_TRY(precision == OPM_PREC_MIXED ? allow_ensemble_lds<float>() : allow_ensemble_lds<double>());
   EnsHeader hdr{n_members, precision, max_level, 0};
   OPM_TRY_HIP(hipMemcpy(base, &hdr, sizeof(hdr), hipMemcpyHostToDevice));
-  OPM_TRY_HIP(hipMemcpy(base + al256(sizeof(EnsHeader)), tab.data(),
-                        sizeof(EnsMember) * (size_t)n_members, hipMemcpyHostToDevice));
+  OPM_TRY_HIP(hipMemcpy(table_of(work), tab.data(), sizeof(EnsMember) * (size_t)n_members,
+                        hipMemcpyHostToDevice));
   return OPM_OK;
+}
+
+int opm_ensemble_configure(const opm_problem* members, int32_t n_members, int precision,
+                           void* work, opm_ensemble_config* cfg) {
+  if (!members || n_members <= 0 || !work || !cfg ||
+      (precision != OPM_PREC_FP64 && precision != OPM_PREC_MIXED))
+    return OPM_EINVAL;
+  std::vector<int32_t> ring(n_members, 0);
+  int max_level = 0;
+  opm_ensemble_config c = *cfg;
+  if (!plan_members(members, n_members, precision, c, &ring, &max_level)) return OPM_EINVAL;
+  std::vector<EnsMember> tab(n_members);
+  OPM_TRY_HIP(hipMemcpy(tab.data(), table_of(work), sizeof(EnsMember) * (size_t)n_members,
+                        hipMemcpyDeviceToHost));
+  for (int m = 0; m < n_members; ++m) tab[m].ring = ring[m];
+  OPM_TRY_HIP(hipMemcpy(table_of(work), tab.data(), sizeof(EnsMember) * (size_t)n_members,
+                        hipMemcpyHostToDevice));
+  *cfg = c;
+  return OPM_OK;
+}
+
+int opm_ensemble_launch_config(const void* work, int32_t n_members, int precision,
+                               int32_t max_level, const opm_ensemble_config* cfg,
+                               double dt_report, int32_t n_steps, const opm_newton_opts* opts,
+                               opm_ensemble_report* reports, void* stream) {
+  if (!work || n_members <= 0 || !opts || !reports || n_steps < 0 || !(dt_report > 0.0) ||
+      max_level <= 0 || opts->max_newton < 0 || opts->lin_maxit < 0 || opts->max_cuts < 0 ||
+      !cfg || !valid_config(*cfg, max_level) || cfg->sweep_bytes <= 0)
+    return OPM_EINVAL;
+  const EnsMember* tab = table_of(const_cast<void*>(work));
+  hipStream_t s = as_stream(stream);
+  if (precision == OPM_PREC_MIXED)
+    return launch_ensemble<float>(tab, n_members, max_level, *cfg, dt_report, n_steps, opts,
+                                  reports, s);
+  if (precision == OPM_PREC_FP64)
+    return launch_ensemble<double>(tab, n_members, max_level, *cfg, dt_report, n_steps, opts,
+                                   reports, s);
+  return OPM_EINVAL;
 }
 
 int opm_ensemble_launch(const void* work, int32_t n_members, int precision, int32_t max_level,
                         double dt_report, int32_t n_steps, const opm_newton_opts* opts,
                         opm_ensemble_report* reports, void* stream) {
-  if (!work || n_members <= 0 || !opts || !reports || n_steps < 0 || !(dt_report > 0.0) ||
-      max_level <= 0 || opts->max_newton < 0 || opts->lin_maxit < 0 || opts->max_cuts < 0)
+  if (precision != OPM_PREC_FP64 && precision != OPM_PREC_MIXED) return OPM_EINVAL;
+  // default shape: 256 threads, factor window when it fits, window sweeps for
+  // every member (a member flagged for the ring by opm_ensemble_configure
+  // falls back to the window: the kernel checks the ring against this size)
+  const size_t ts = precision == OPM_PREC_MIXED ? sizeof(float) : sizeof(double);
+  opm_ensemble_config c{256, max_level > 0 && max_level <= kMaxFacWindowLevel ? 1 : 0, 0,
+                        (int32_t)al256(window_bytes(ts, max_level))};
+  return opm_ensemble_launch_config(work, n_members, precision, max_level, &c, dt_report,
+                                    n_steps, opts, reports, stream);
+}
+
+int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int precision,
+                          void* work, double dt_report, const opm_newton_opts* opts,
+                          opm_ensemble_config* best, double* seconds, int32_t* n_tried,
+                          void* stream) {
+  if (!members || n_members <= 0 || !work || !opts || !best || !(dt_report > 0.0) ||
+      (precision != OPM_PREC_FP64 && precision != OPM_PREC_MIXED))
     return OPM_EINVAL;
-  const EnsMember* tab =
-      reinterpret_cast<const EnsMember*>((const char*)work + al256(sizeof(EnsHeader)));
   hipStream_t s = as_stream(stream);
-  if (precision == OPM_PREC_MIXED)
-    return launch_ensemble<float>(tab, n_members, max_level, dt_report, n_steps, opts, reports, s);
-  if (precision == OPM_PREC_FP64)
-    return launch_ensemble<double>(tab, n_members, max_level, dt_report, n_steps, opts, reports,
-                                   s);
-  return OPM_EINVAL;
+  int max_level = 0;
+  for (int m = 0; m < n_members; ++m) max_level = std::max(max_level, (int)members[m].max_level);
+  std::vector<EnsMember> tab(n_members);
+  OPM_TRY_HIP(hipMemcpy(tab.data(), table_of(work), sizeof(EnsMember) * (size_t)n_members,
+                        hipMemcpyDeviceToHost));
+  // the backup slot of each member keeps its state between trials
+  auto copy_states = [&](bool to_backup) -> int {
+    for (int m = 0; m < n_members; ++m) {
+      const size_t bytes = sizeof(double) * 3 * (size_t)members[m].n_cells;
+      OPM_TRY_HIP(hipMemcpyAsync(to_backup ? tab[m].backup : tab[m].y,
+                                 to_backup ? tab[m].y : tab[m].backup, bytes,
+                                 hipMemcpyDeviceToDevice, s));
+    }
+    return OPM_OK;
+  };
+  OPM_TRY(copy_states(true));
+  opm_ensemble_report* reps = trial_reports_of(work, n_members);
+  hipEvent_t e0, e1;
+  OPM_TRY_HIP(hipEventCreate(&e0));
+  OPM_TRY_HIP(hipEventCreate(&e1));
+  int tried = 0;
+  double best_t = INFINITY;
+  opm_ensemble_config best_c{};
+  int status = OPM_OK;
+  for (int threads : {256, 128})
+    for (int ring : {0, 1})
+      for (int facw : {1, 0}) {
+        opm_ensemble_config c{threads, facw, ring, 0};
+        if (!valid_config(c, max_level)) continue;
+        if (opm_ensemble_configure(members, n_members, precision, work, &c) != OPM_OK) continue;
+        status = copy_states(false);
+        if (status != OPM_OK) break;
+        (void)hipEventRecord(e0, s);
+        status = opm_ensemble_launch_config(work, n_members, precision, max_level, &c, dt_report,
+                                            1, opts, reps, s);
+        (void)hipEventRecord(e1, s);
+        if (status != OPM_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          status = OPM_EHIP;
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (seconds) seconds[tried] = ms * 1e-3;
+        ++tried;
+        if (ms * 1e-3 < best_t) {
+          best_t = ms * 1e-3;
+          best_c = c;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status == OPM_OK) status = copy_states(false);
+  if (status == OPM_OK && hipStreamSynchronize(s) != hipSuccess) status = OPM_EHIP;
+  if (status != OPM_OK) return status;
+  if (tried == 0) return OPM_EINVAL;
+  OPM_TRY(opm_ensemble_configure(members, n_members, precision, work, &best_c));
+  *best = best_c;
+  if (n_tried) *n_tried = tried;
+  return OPM_OK;
 }
 
 }  // extern "C"

@@ -473,6 +473,17 @@ class EnsembleReport(ctypes.Structure):
 _ENS_REPORT_DOUBLES = ctypes.sizeof(EnsembleReport) // 8
 
 
+class EnsembleConfig(ctypes.Structure):
+    _fields_ = [("threads", _i32), ("fac_window", _i32), ("ring", _i32), ("sweep_bytes", _i32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS += ["opm_ensemble_default_config", "opm_ensemble_configure",
+            "opm_ensemble_launch_config", "opm_ensemble_autotune"]
+
+
 def _ensemble_lib():
     L = lib()
     if not getattr(L, "_ens_ready", False):
@@ -483,6 +494,13 @@ def _ensemble_lib():
                                            _vp, ctypes.c_size_t]
         L.opm_ensemble_launch.argtypes = [_vp, _i32, ctypes.c_int, _i32, ctypes.c_double, _i32,
                                           ctypes.POINTER(NewtonOpts), _vp, _vp]
+        C = ctypes.POINTER(EnsembleConfig)
+        L.opm_ensemble_default_config.argtypes = [P, _i32, ctypes.c_int, C]
+        L.opm_ensemble_configure.argtypes = [P, _i32, ctypes.c_int, _vp, C]
+        L.opm_ensemble_launch_config.argtypes = [_vp, _i32, ctypes.c_int, _i32, C, ctypes.c_double,
+                                                 _i32, ctypes.POINTER(NewtonOpts), _vp, _vp]
+        L.opm_ensemble_autotune.argtypes = [P, _i32, ctypes.c_int, _vp, ctypes.c_double,
+                                            ctypes.POINTER(NewtonOpts), C, _dp, _ip, _vp]
         L._ens_ready = True
     return L
 
@@ -511,14 +529,63 @@ class Ensemble:
                "opm_ensemble_prepare")
         self.reports = torch.zeros((nm, _ENS_REPORT_DOUBLES), dtype=torch.float64, device=self.dev)
         self.n_cells = [m.n for m in self.members]
+        self.config = EnsembleConfig()
+        _check(L.opm_ensemble_default_config(self.problems, nm, precision,
+                                             ctypes.byref(self.config)),
+               "opm_ensemble_default_config")
+        self.tuning = None
+
+    def signature(self) -> str:
+        """Key of the tuning cache: precision and the members' grids."""
+        import hashlib
+        dims = ";".join(f"{m.case.nx}x{m.case.ny}x{m.case.nz}:{m.n}" for m in self.members)
+        return f"p{self.precision}-" + hashlib.sha256(dims.encode()).hexdigest()[:16]
+
+    def configure(self, threads: int, fac_window: int, ring: int) -> None:
+        c = EnsembleConfig(threads=threads, fac_window=fac_window, ring=ring, sweep_bytes=0)
+        _check(_ensemble_lib().opm_ensemble_configure(
+            self.problems, self.n_members, self.precision, ctypes.c_void_p(self.work.data_ptr()),
+            ctypes.byref(c)), "opm_ensemble_configure")
+        self.config = c
+
+    def autotune(self, dt_report, opts: Optional[NewtonOpts] = None,
+                 cache: Optional[str] = None) -> dict:
+        """Pick the launch shape with opm_ensemble_autotune (one trial report
+        step per shape; states are restored), or reuse the shape stored for
+        this ensemble's signature in the JSON file `cache`."""
+        import json
+        key = self.signature()
+        if cache and os.path.exists(cache):
+            entry = json.load(open(cache)).get(key)
+            if entry:
+                self.configure(entry["threads"], entry["fac_window"], entry["ring"])
+                self.tuning = {"cached": True, **entry}
+                return self.tuning
+        o = opts or default_opts(self.members[0].case, precision=self.precision)
+        best = EnsembleConfig()
+        secs = (ctypes.c_double * 16)()
+        tried = _i32()
+        _check(_ensemble_lib().opm_ensemble_autotune(
+            self.problems, self.n_members, self.precision, ctypes.c_void_p(self.work.data_ptr()),
+            dt_report, ctypes.byref(o), ctypes.byref(best), secs, ctypes.byref(tried), _stream()),
+            "opm_ensemble_autotune")
+        self.config = best
+        self.tuning = {"cached": False, **best.as_dict(),
+                       "trial_seconds": [round(secs[k], 4) for k in range(tried.value)]}
+        if cache:
+            table = json.load(open(cache)) if os.path.exists(cache) else {}
+            table[key] = {k: v for k, v in best.as_dict().items() if k != "sweep_bytes"}
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+        return self.tuning
 
     def launch(self, dt_report, n_steps, opts: Optional[NewtonOpts] = None):
-        """Enqueue one launch (asynchronous)."""
+        """Enqueue one launch with the current shape (asynchronous)."""
         o = opts or default_opts(self.members[0].case, precision=self.precision)
-        _check(_ensemble_lib().opm_ensemble_launch(
+        _check(_ensemble_lib().opm_ensemble_launch_config(
             ctypes.c_void_p(self.work.data_ptr()), self.n_members, self.precision, self.max_level,
-            dt_report, n_steps, ctypes.byref(o), ctypes.c_void_p(self.reports.data_ptr()),
-            _stream()), "opm_ensemble_launch")
+            ctypes.byref(self.config), dt_report, n_steps, ctypes.byref(o),
+            ctypes.c_void_p(self.reports.data_ptr()), _stream()), "opm_ensemble_launch_config")
 
     def read_reports(self):
         raw = self.reports.cpu().numpy().tobytes()

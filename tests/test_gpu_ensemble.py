@@ -142,3 +142,96 @@ def test_ensemble_c4_members(opm):
         st, y, r = oracle.Model(case).advance(case.initial_state(), 15 * DAY)
         assert st == 0
         _check(ens.states()[k], y, case.name)
+
+
+_ORACLE_ONE_STEP = {}
+
+
+def _oracle_step(case, dt):
+    key = (case.name, dt)
+    if key not in _ORACLE_ONE_STEP:
+        st, y, _ = oracle.Model(case).advance(case.initial_state(), dt)
+        assert st == 0
+        _ORACLE_ONE_STEP[key] = y
+    return _ORACLE_ONE_STEP[key]
+
+
+SHAPES = [(t, f, r) for t in (256, 128) for f in (1, 0) for r in (0, 1)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "t%d-fw%d-ring%d" % s)
+def test_ensemble_shapes_match_oracle(opm, shape, precision):
+    """Every launch shape the autotuner can pick gives oracle-matching states."""
+    ms = _members()
+    ens = opm.Ensemble(ms, precision=precision)
+    ens.configure(*shape)
+    if shape[2]:
+        # the ring holds sweep_span + max_level + 1 rows rounded up to a power of two
+        ts = 4 if precision else 8
+        rings = []
+        for m in ens.members:
+            c = 1
+            while c < m.sweep_span + m.max_level + 1:
+                c <<= 1
+            rings.append(3 * ts * c)
+        assert ens.config.sweep_bytes >= max(rings)
+    dt = 10 * DAY
+    ens.launch(dt, 1)
+    torch.cuda.synchronize()
+    reps = ens.read_reports()
+    for m, case in enumerate(ms):
+        assert reps[m]["status"] == 0 and reps[m]["steps_done"] == 1, (m, reps[m])
+        _check(ens.states()[m], _oracle_step(case, dt), f"{shape} member {m}")
+
+
+def test_ensemble_autotune(opm, tmp_path):
+    """The autotuner times every shape, restores the states, configures the
+    fastest; a cached choice is reused without trials."""
+    ms = _members()
+    ens = opm.Ensemble(ms, precision=opm.PREC_MIXED)
+    y0 = ens.states()
+    cache = str(tmp_path / "ensemble_tuning.json")
+    dt = 10 * DAY
+    t = ens.autotune(dt, cache=cache)
+    assert not t["cached"] and len(t["trial_seconds"]) == 8
+    assert t["threads"] in (128, 256) and t["ring"] in (0, 1) and t["fac_window"] in (0, 1)
+    for m, y in enumerate(ens.states()):
+        assert np.array_equal(y, y0[m]), f"member {m} not restored"
+    ens.launch(dt, 1)
+    torch.cuda.synchronize()
+    for m, case in enumerate(ms):
+        assert ens.read_reports()[m]["status"] == 0
+        _check(ens.states()[m], _oracle_step(case, dt), f"tuned member {m}")
+    ens2 = opm.Ensemble(ms, precision=opm.PREC_MIXED)
+    t2 = ens2.autotune(dt, cache=cache)
+    assert t2["cached"] and (t2["threads"], t2["ring"], t2["fac_window"]) == (
+        t["threads"], t["ring"], t["fac_window"])
+
+
+def test_ensemble_graph_capture_tuned_shape(opm):
+    """A configured shape is captured and replayed like the default one."""
+    ms = _members()[:3]
+    dt = 5 * DAY
+    eager = opm.Ensemble(ms, precision=opm.PREC_FP64)
+    eager.configure(128, 0, 1)
+    for _ in range(2):
+        eager.launch(dt, 1)
+        torch.cuda.synchronize()
+    ref = eager.states()
+    ens = opm.Ensemble(ms, precision=opm.PREC_FP64)
+    ens.configure(128, 0, 1)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ens.launch(dt, 1)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        g.replay()
+        torch.cuda.synchronize()
+        _ = ens.read_reports()
+    for m in range(3):
+        assert np.array_equal(ens.states()[m], ref[m])
