@@ -60,11 +60,24 @@ def assemble_bytes(n: int, nnzb: int, nf: int) -> float:
     return n * (24 + 24 + 8 + 8 + 4 + 4 + 24) + nnzb * (72 + 4 + 4) + nf * 8
 
 
+def factor_bytes_per_cell(precision: int) -> float:
+    """Algorithmic bytes of the ILU(0) factorisation per cell: the block row
+    of J read once (7 FP64 blocks and their column indices), the level-order
+    copies of the off-diagonal blocks and the inverse pivot written (27 + 27
+    + 9 values, plus the FP64 pivot copy in mixed precision), and the three
+    lower and three transposed blocks plus the neighbours' inverse pivots
+    read again by the pivot recursion."""
+    w = 8 if precision == 0 else 4
+    pack = 7 * (72 + 4) + (27 + 27 + 9) * w + (72 if precision else 0)
+    recurse = (27 + 27) * w + 3 * 9 * 8 + 9 * 8
+    return pack + recurse
+
+
 def measured_traffic(kernel_class: str, precision: int):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs (profiles/counters.json, scaled by a plain
-    256 MiB copy), or None when there is no record or the kernel's source has
-    changed since the counters were taken."""
+    256 MiB copy), or None when there is no record or one of the kernel's
+    source files has changed since the counters were taken."""
     import hashlib
     tags = {("ilu0_apply", 0): "c2_fp64_ilu0_sweep", ("ilu0_apply", 1): "c2_mixed_ilu0_sweep"}
     tag = tags.get((kernel_class, precision))
@@ -72,11 +85,15 @@ def measured_traffic(kernel_class: str, precision: int):
     if tag is None or not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(tag)
-    if not rec or not rec.get("traffic_bytes"):
+    if not rec or not rec.get("traffic_bytes") or not rec.get("sources"):
         return None
-    src = os.path.join(ROOT, rec["source"])
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    return round(rec["traffic_bytes"]) if h == rec["source_sha256_16"] else None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        p = os.path.join(ROOT, src)
+        if not os.path.exists(p):
+            return None
+        h.update(open(p, "rb").read())
+    return round(rec["traffic_bytes"]) if h.hexdigest()[:16] == rec.get("sources_sha256_16") else None
 
 
 def _run_single(g, dt, steps, opts, opm):
@@ -317,6 +334,85 @@ def bench_guess(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_kernels(args):
+    """Per-kernel HBM roofline on the 100x100x50 system (500k cells, 3.46M
+    blocks), where the data no longer fits the caches: HIP-event timing of
+    repeated launches (on the launch stream) of the BSR SpMV, the ILU(0)
+    application with FP64 and FP32 factors, the assembly and the ILU(0)
+    factorisation, each divided into its algorithmic bytes."""
+    import torch
+    from paper_1910_06059_amd import cases, opm
+    case = cases.config5(5008)
+    g = opm.GpuModel(case)
+    dt = case.report_dt[0]
+    y = g.initial_state()
+    acc0 = g.accumulation(y)
+    yk = y.clone()
+    yk[:, 0] += 1e4
+    R, J, _ = g.assemble(yk, acc0, dt)
+    ilu = {p: g.ilu0_factor(J, p)[0] for p in (0, 1)}
+    x = g.zeros_state()
+    L = opm.lib()
+    pbp = g._pbp()
+    sp = opm._ptr
+    st = opm._stream()
+    stream = torch.cuda.current_stream()
+    reps = args.kernel_reps
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    if args.copy_probe_mb > 0:
+        src = torch.empty(args.copy_probe_mb << 20, dtype=torch.uint8, device=g.dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    n = g.n
+    norms = torch.zeros(L.opm_norms_bytes(pbp) // 8, dtype=torch.float64, device=g.dev)
+    Rb, Jb = torch.empty_like(R), torch.empty_like(J)
+    status = torch.zeros(1, dtype=torch.int32, device=g.dev)
+    ilu_tmp = {p: torch.empty_like(ilu[p]) for p in (0, 1)}
+    kern = {
+        "spmv": (lambda: L.opm_spmv(pbp, sp(J), sp(R), sp(x), st),
+                 spmv_bytes_per_cell(g.nnzb, n) * n, "k_spmv"),
+        "ilu0_apply_fp64": (lambda: L.opm_ilu0_apply(pbp, sp(ilu[0]), 0, sp(R), sp(x), st),
+                            sweep_bytes_per_cell(0) * n, "k_fwd_level + k_bwd_level (FP64)"),
+        "ilu0_apply_fp32": (lambda: L.opm_ilu0_apply(pbp, sp(ilu[1]), 1, sp(R), sp(x), st),
+                            sweep_bytes_per_cell(1) * n, "k_fwd_level + k_bwd_level (FP32)"),
+        "assemble": (lambda: L.opm_assemble(pbp, sp(yk), sp(acc0), dt, sp(Rb), sp(Jb), sp(norms), st),
+                     assemble_bytes(n, g.nnzb, g.nf), "k_assemble + k_norms_final"),
+        "ilu0_factor_fp64": (lambda: L.opm_ilu0_factor(pbp, sp(J), sp(ilu_tmp[0]), 0, sp(status), st),
+                             factor_bytes_per_cell(0) * n, "k_pack + k_factor_level (FP64)"),
+    }
+    if args.kernels:
+        keep = set(args.kernels.split(","))
+        kern = {k: v for k, v in kern.items() if k in keep}
+    res = {}
+    for name, (fn, nbytes, kname) in kern.items():
+        t = timed(fn)
+        res[name] = {"kernel": kname, "us": round(t * 1e6, 2), "bytes": int(nbytes),
+                     "gbs": round(nbytes / t / 1e9, 1), "frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4)}
+    line = {"metric": "kernel HBM roofline on the 500k-cell system (algorithmic bytes / HIP-event "
+                      "time per launch)", "value": res.get("spmv", {}).get("frac"),
+            "unit": "fraction of 8 TB/s (SpMV)", "n_gpus": 1, "steps": reps, "warmup": 3,
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"100x100x50 system, {n} cells, {g.nnzb} blocks, "
+                                   f"{g.n_levels} ILU levels (max {g.max_level} rows)"},
+            "kernels": res}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,10 +420,11 @@ def main():
                     help="timed report steps (default: 30 for c2, 10 for c3, 20 for c4)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c3-mixed", "c4-ensemble", "c5-guess"],
+                    choices=["c2", "c3-mixed", "c4-ensemble", "c5-guess", "c5-kernels"],
                     help="c2: the headline metric line; c3-mixed: FP32 ILU(0) vs FP64 on the "
                          "masked 45k-cell grid; c4-ensemble: 64 members in one launch; "
-                         "c5-guess: learned Newton guess on the 500k-cell waterflood")
+                         "c5-guess: learned Newton guess on the 500k-cell waterflood; "
+                         "c5-kernels: per-kernel HBM roofline at 500k cells")
     ap.add_argument("--train-seeds", type=int, default=8, help="training seeds (c5-guess)")
     ap.add_argument("--test-seeds", type=int, default=2, help="held-out seeds (c5-guess)")
     ap.add_argument("--epochs", type=int, default=40, help="training epochs (c5-guess)")
@@ -343,6 +440,9 @@ def main():
                     help="time budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--kernels", default=None,
+                    help="comma-separated subset of the c5-kernels table (spmv, ilu0_apply_fp64, "
+                         "ilu0_apply_fp32, assemble, ilu0_factor_fp64)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (a reference "
                          "kernel for scaling HBM counters)")
@@ -364,6 +464,8 @@ def main():
         return bench_ensemble(args)
     if args.workload == "c5-guess":
         return bench_guess(args)
+    if args.workload == "c5-kernels":
+        return bench_kernels(args)
     if args.steps is None:
         args.steps = 30
     case = cases.config2()
@@ -440,7 +542,7 @@ def main():
     asm_b = assemble_bytes(n, g.nnzb, g.nf)
     kernels = {
         "ilu0_apply": {"seconds": t_apply, "bytes": sweep_b,
-                       "kernel": "ilu0 forward+backward sweeps (k_apply_wg / k_fwd_level+k_bwd_level)"},
+                       "kernel": "ilu0 forward+backward sweeps (k_apply_ring, one workgroup)"},
         "spmv": {"seconds": t_spmv, "bytes": spmv_b, "kernel": "k_spmv"},
         "assemble": {"seconds": t_asm, "bytes": asm_b, "kernel": "k_assemble+k_norms_final"},
     }
