@@ -71,17 +71,52 @@ __device__ __forceinline__ void store_partial(double v, double* part, double* sh
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-using ilu::spmv_row;
+// Block SpMV with three block rows per wavefront.  Lane l serves row l / 21
+// of the group, block (l % 21) / 3 of that row (and every 7th block after
+// it) and output component l % 3, so the 21 lanes of a row read its blocks
+// (at most 7 on the 7-point stencil) as one contiguous run of doubles and a
+// wavefront reads one contiguous span of the matrix.  The per-block partial
+// sums of an output component sit in lanes l, l+3, ..., l+18 and are added in
+// block order by the lane of block 0, which returns true and the row and
+// component it owns.  Lane 63 and rows past n contribute nothing.  Every lane
+// of the wavefront must call it (cross-lane reads).
+constexpr int kSpmvRowsPerWave = 3;
+
+__device__ __forceinline__ bool spmv_group(int n, const int32_t* row_ptr, const int32_t* col,
+                                           const double* J, const double* x, int group,
+                                           int lane, int& row, int& comp, double& yv) {
+  const int rl = lane / 21, rem = lane - 21 * rl;
+  const int q = rem / 3;
+  comp = rem - 3 * q;
+  row = group * kSpmvRowsPerWave + rl;
+  double v = 0.0;
+  const bool live = lane < 21 * kSpmvRowsPerWave && row < n;
+  if (live) {
+    const int q1 = row_ptr[row + 1];
+    for (int qb = row_ptr[row] + q; qb < q1; qb += 7) {
+      const double* B = J + 9 * (size_t)qb + 3 * comp;
+      const double* xj = x + 3 * (size_t)col[qb];
+      v += B[0] * xj[0] + B[1] * xj[1] + B[2] * xj[2];
+    }
+  }
+  double sum = v;
+#pragma unroll
+  for (int k = 1; k < 7; ++k) sum += __shfl(v, lane + 3 * k, kWave);
+  yv = sum;
+  return live && q == 0;
+}
+
+__host__ __device__ inline int spmv_groups(int n) { return (n + kSpmvRowsPerWave - 1) / kSpmvRowsPerWave; }
+inline int spmv_blocks(int n) { return blocks_for(spmv_groups(n), kBlock / kWave); }
 
 __global__ __launch_bounds__(kBlock) void k_spmv(int n, const int32_t* row_ptr, const int32_t* col,
                                                   const double* J, const double* x, double* y) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  double y3[3];
-  spmv_row(row_ptr, col, J, x, i, y3);
-  y[3 * i] = y3[0];
-  y[3 * i + 1] = y3[1];
-  y[3 * i + 2] = y3[2];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int group = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  if (group >= spmv_groups(n)) return;   // whole wavefront
+  int row, comp;
+  double yv;
+  if (spmv_group(n, row_ptr, col, J, x, group, lane, row, comp, yv)) y[3 * row + comp] = yv;
 }
 
 // x = 0, r = r^ = b, p = v = 0; partials of <b,b>.
@@ -171,13 +206,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv_rv(int n, const int32_t* row_pt
   __shared__ double sh[kBlock / kWave];
   if (w.sc->state != kRunning) return;
   double acc = 0.0;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    double y3[3];
-    spmv_row(row_ptr, col, J, w.ph, i, y3);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      w.v[3 * i + c] = y3[c];
-      acc += w.rh[3 * i + c] * y3[c];
+  const int lane = threadIdx.x & (kWave - 1), ng = spmv_groups(n);
+  for (int g = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; g < ng;
+       g += gridDim.x * (kBlock / kWave)) {
+    int row, comp;
+    double yv;
+    if (spmv_group(n, row_ptr, col, J, w.ph, g, lane, row, comp, yv)) {
+      w.v[3 * row + comp] = yv;
+      acc += w.rh[3 * row + comp] * yv;
     }
   }
   store_partial(acc, w.part_rv, sh);
@@ -227,14 +263,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv_t(int n, const int32_t* row_ptr
   __shared__ double sh[kBlock / kWave];
   if (w.sc->state != kRunning) return;
   double ts = 0.0, tt = 0.0;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    double y3[3];
-    spmv_row(row_ptr, col, J, w.sh, i, y3);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      w.t[3 * i + c] = y3[c];
-      ts += y3[c] * w.s[3 * i + c];
-      tt += y3[c] * y3[c];
+  const int lane = threadIdx.x & (kWave - 1), ng = spmv_groups(n);
+  for (int g = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; g < ng;
+       g += gridDim.x * (kBlock / kWave)) {
+    int row, comp;
+    double yv;
+    if (spmv_group(n, row_ptr, col, J, w.sh, g, lane, row, comp, yv)) {
+      w.t[3 * row + comp] = yv;
+      ts += yv * w.s[3 * row + comp];
+      tt += yv * yv;
     }
   }
   store_partial(ts, w.part_ts, sh);
@@ -299,7 +336,7 @@ size_t krylov_bytes(const opm_problem* pb) {
 
 int spmv(const opm_problem* pb, const double* J, const double* x, double* y, hipStream_t s) {
   if (pb->n_cells == 0) return OPM_OK;
-  hipLaunchKernelGGL(k_spmv, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL(k_spmv, dim3(spmv_blocks(pb->n_cells)), dim3(kBlock), 0, s,
                      pb->n_cells, pb->row_ptr, pb->col_idx, J, x, y);
   OPM_TRY_HIP(hipGetLastError());
   return OPM_OK;
@@ -311,7 +348,7 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
              hipStream_t st) {
   const int n = pb->n_cells, N = 3 * n;
   Work w = carve(pb, work);
-  const int G = vec_grid(N), Gr = vec_grid(n);
+  const int G = vec_grid(N), Gr = std::min(kMaxGrid, std::max(1, spmv_blocks(n)));
   hipLaunchKernelGGL(k_init, dim3(G), dim3(kBlock), 0, st, N, b, x, w);
   hipLaunchKernelGGL(k_init2, dim3(1), dim3(kBlock), 0, st, w, G, rtol, maxit);
   OPM_TRY_HIP(hipGetLastError());
