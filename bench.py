@@ -542,7 +542,8 @@ def main():
     asm_b = assemble_bytes(n, g.nnzb, g.nf)
     kernels = {
         "ilu0_apply": {"seconds": t_apply, "bytes": sweep_b,
-                       "kernel": "ilu0 forward+backward sweeps (k_apply_ring, one workgroup)"},
+                       "kernel": "ilu0 forward+backward sweeps (k_gather_rhs + k_apply_ring2, "
+                                 "one workgroup of 512 threads)"},
         "spmv": {"seconds": t_spmv, "bytes": spmv_b, "kernel": "k_spmv"},
         "assemble": {"seconds": t_asm, "bytes": asm_b, "kernel": "k_assemble+k_norms_final"},
     }

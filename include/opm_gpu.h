@@ -504,9 +504,15 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
  *   OPM_OPT_SWEEP_MODE: ILU(0) factor/sweep launch shape: -1 automatic,
  *     0 one workgroup walks all levels, 1 one launch per level.
  *   OPM_OPT_KRYLOV_CHUNK: BiCGStab iterations enqueued between reads of the
- *     convergence state (0 automatic, else >= 1). */
+ *     convergence state (0 automatic, else >= 1).
+ *   OPM_OPT_SWEEP_KERNEL: the one-workgroup LDS-ring sweep: 0 automatic,
+ *     1 right-hand side gathered inside the sweep, 2-6 right-hand side
+ *     gathered into level order first and branch-free prefetch with 512,
+ *     256 or 128 threads (2, 3, 4) or with wavefronts that have no row in a
+ *     level skipping their loads (5: 512, 6: 256 threads). */
 #define OPM_OPT_SWEEP_MODE 1
 #define OPM_OPT_KRYLOV_CHUNK 2
+#define OPM_OPT_SWEEP_KERNEL 3
 int opm_set_option(int option, int value);
 
 const char* opm_strerror(int code);

@@ -31,6 +31,9 @@
 #include "solver_dev.h"
 
 namespace opm {
+
+extern int g_sweep_kernel;
+
 namespace {
 
 using namespace ilu;
@@ -116,6 +119,33 @@ __global__ __launch_bounds__(kWgThreads) void k_apply_ring(Topo t, IluView<T> v,
   apply_levels_ring<T, kWgThreads>(t, v, r, x, reinterpret_cast<T*>(smem), mask);
 }
 
+// r gathered into z in level order (the right-hand side of the ring sweep).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather_rhs(int n, const int32_t* perm, IluView<T> v,
+                                                       const double* r, const int32_t* skip) {
+  if (skip && *skip != 0) return;
+  const int pos = blockIdx.x * kBlock + threadIdx.x;
+  if (pos >= n) return;
+  const int cell = perm[pos];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v.z[(size_t)c * v.ns + pos] = (T)r[3 * (size_t)cell + c];
+}
+
+// Both sweeps by one workgroup of NT threads through the LDS ring with
+// branch-free prefetch (the right-hand side already in z, see k_gather_rhs).
+template <typename T, int NT, bool WIDE, bool SKIP>
+__global__ __launch_bounds__(NT) void k_apply_ring2(Topo t, IluView<T> v, double* x,
+                                                     const int32_t* skip, unsigned mask) {
+  if (skip && *skip != 0) return;
+  extern __shared__ unsigned char smem[];
+  T* ring = reinterpret_cast<T*>(smem);
+  ilu::ring2_sweep<T, NT, true, WIDE, SKIP>(t, v, x, ring, mask);
+  // each lane reads back in the backward sweep only z values that it wrote
+  // itself in the forward sweep (same level-position mapping)
+  __syncthreads();
+  ilu::ring2_sweep<T, NT, false, WIDE, SKIP>(t, v, x, ring, mask);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kWgThreads) void k_apply_wg(Topo t, IluView<T> v, const double* r,
                                                           double* x, const int32_t* skip) {
@@ -131,7 +161,7 @@ size_t apply_lds(const opm_problem* pb) {
 
 size_t factor_lds(const opm_problem* pb) { return sizeof(double) * 2 * 9 * (size_t)pb->max_level; }
 
-bool g_lds_attr_set[8] = {false, false, false, false, false, false, false, false};
+bool g_lds_attr_set[32] = {};
 
 template <typename K>
 int allow_lds(K kernel, int slot) {
@@ -180,9 +210,40 @@ int apply_impl(const opm_problem* pb, void* ilu, const double* r, double* x, int
     const int ring = ring_rows(pb->sweep_span, pb->max_level);
     const size_t ring_bytes = sizeof(T) * 3 * (size_t)ring;
     if (ring_bytes <= kMaxRingBytes) {   // every neighbour value in LDS
-      OPM_TRY(allow_lds(k_apply_ring<T>, sizeof(T) == 8 ? 4 : 5));
-      hipLaunchKernelGGL(k_apply_ring<T>, dim3(1), dim3(kWgThreads), ring_bytes, s, t, v, r, x,
-                         skip, (unsigned)(ring - 1));
+      // automatic: 512 threads with idle wavefronts skipping their loads
+      // (measured fastest on the 9000-, 45000- and 108000-cell systems)
+      const int kind = g_sweep_kernel == 0 ? 5 : g_sweep_kernel;
+      if (kind == 1) {
+        OPM_TRY(allow_lds(k_apply_ring<T>, sizeof(T) == 8 ? 4 : 5));
+        hipLaunchKernelGGL(k_apply_ring<T>, dim3(1), dim3(kWgThreads), ring_bytes, s, t, v, r, x,
+                           skip, (unsigned)(ring - 1));
+        OPM_TRY_HIP(hipGetLastError());
+        return OPM_OK;
+      }
+      hipLaunchKernelGGL(k_gather_rhs<T>, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock), 0,
+                         s, pb->n_cells, pb->perm, v, r, skip);
+      const unsigned mask = (unsigned)(ring - 1);
+      const int slot = (sizeof(T) == 8 ? 8 : 20) + 2 * kind;
+#define OPM_RING2(NT, SKIP)                                                                  \
+  do {                                                                                       \
+    if (pb->max_level <= NT) {                                                               \
+      OPM_TRY(allow_lds(k_apply_ring2<T, NT, false, SKIP>, slot));                           \
+      hipLaunchKernelGGL((k_apply_ring2<T, NT, false, SKIP>), dim3(1), dim3(NT), ring_bytes, \
+                         s, t, v, x, skip, mask);                                            \
+    } else {                                                                                 \
+      OPM_TRY(allow_lds(k_apply_ring2<T, NT, true, SKIP>, slot + 1));                        \
+      hipLaunchKernelGGL((k_apply_ring2<T, NT, true, SKIP>), dim3(1), dim3(NT), ring_bytes,  \
+                         s, t, v, x, skip, mask);                                            \
+    }                                                                                        \
+  } while (0)
+      switch (kind) {
+        case 2: OPM_RING2(512, false); break;
+        case 3: OPM_RING2(256, false); break;
+        case 4: OPM_RING2(128, false); break;
+        case 5: OPM_RING2(512, true); break;
+        default: OPM_RING2(256, true); break;
+      }
+#undef OPM_RING2
       OPM_TRY_HIP(hipGetLastError());
       return OPM_OK;
     }
@@ -217,6 +278,10 @@ size_t ilu_bytes(const opm_problem* pb, int precision) {
 // the system is small enough for one compute unit, else one launch per
 // level; g_sweep_mode (set by opm_set_option) forces one of them.
 int g_sweep_mode = -1;
+// ring-sweep kernel of the one-workgroup shape: 0 automatic, 1 gather in the
+// loads, 2-6 branch-free prefetch (512, 256, 128 threads; 512 and 256
+// threads with idle wavefronts skipping their loads)
+int g_sweep_kernel = 0;
 
 int sweep_mode(const opm_problem* pb) {
   if (g_sweep_mode == 0 || g_sweep_mode == 1) {

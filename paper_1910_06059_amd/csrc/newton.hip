@@ -10,6 +10,7 @@
 namespace opm {
 
 extern int g_sweep_mode;
+extern int g_sweep_kernel;
 extern int g_krylov_chunk;
 int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, double dt,
                     double* R, double* J, double* norms, hipStream_t s);
@@ -322,6 +323,10 @@ int opm_set_option(int option, int value) {
     case OPM_OPT_KRYLOV_CHUNK:
       if (value < 0) return OPM_EINVAL;
       g_krylov_chunk = value;
+      return OPM_OK;
+    case OPM_OPT_SWEEP_KERNEL:
+      if (value < 0 || value > 6) return OPM_EINVAL;
+      g_sweep_kernel = value;
       return OPM_OK;
     default:
       return OPM_EINVAL;

@@ -658,3 +658,134 @@ __device__ __forceinline__ void apply_levels_ring(const Topo& t, IluView<T> v, c
 
 }  // namespace ilu
 }  // namespace opm
+
+namespace opm {
+namespace ilu {
+
+// ---------------------------------------------------------------------------
+// Ring sweep with branch-free prefetch.  The forward sweep takes its
+// right-hand side from z in level order (gathered there before the sweep),
+// so the data of a row are loads at its own level position only and the
+// next level's loads never wait for an index.  A prefetch clamps the level
+// (past the last level: the last level) and the row (lanes past a level's
+// end: its last row), so every lane issues the same loads on every path and
+// the compiler can wait for exactly the loads a level needs while the next
+// level's loads stay in flight; lanes past a level's end recompute its last
+// row but store nothing (their early load of that row's z may return the
+// owner's later forward result).  Missing neighbours have zero blocks and
+// read a zero value, which leaves every sum bitwise unchanged.
+template <typename T>
+struct RingJob {
+  T a[27];    // three neighbour blocks
+  T D[9];     // D^{-1}
+  T rhs[3];   // level-ordered r (forward) or y (backward)
+  int kp[3];  // neighbour positions (-1 if absent)
+  int pos;
+  int cell;   // backward: output row of x
+  bool live;  // the lane owns row pos
+};
+
+template <typename T, bool FWD>
+__device__ __forceinline__ void ring2_load(const Topo& t, IluView<T> v, int pos, RingJob<T>& j) {
+  const unsigned ns = (unsigned)v.ns, up = (unsigned)pos;
+  const T* blk = FWD ? v.lov : v.upv;
+  const int32_t* nb = FWD ? t.lo_pos : t.up_pos;
+  j.pos = pos;
+  j.live = true;
+  j.cell = FWD ? 0 : t.perm[up];
+#pragma unroll
+  for (unsigned c = 0; c < 3; ++c) j.rhs[c] = v.z[c * ns + up];
+#pragma unroll
+  for (unsigned s = 0; s < 3; ++s) j.kp[s] = nb[3u * up + s];
+#pragma unroll
+  for (unsigned e = 0; e < 27; ++e) j.a[e] = blk[e * ns + up];
+#pragma unroll
+  for (unsigned e = 0; e < 9; ++e) j.D[e] = v.dinv[e * ns + up];
+}
+
+// SKIP: a wavefront with no row in the level issues no load (a branch that
+// is uniform over the wavefront).
+template <typename T, bool FWD, bool SKIP>
+__device__ __forceinline__ void ring2_fetch(const Topo& t, IluView<T> v, int k, RingJob<T>& j) {
+  const int kk = k < t.nlev ? k : t.nlev - 1;
+  const int l = FWD ? kk : t.nlev - 1 - kk;
+  const int p0 = t.level_ptr[l], p1 = t.level_ptr[l + 1];
+  j.live = k < t.nlev && p0 + (int)threadIdx.x < p1;
+  if (SKIP && __builtin_amdgcn_readfirstlane(p0 + (int)(threadIdx.x & ~63u)) >= p1) return;
+  const int pos = min(p0 + (int)threadIdx.x, p1 - 1);
+  ring2_load<T, FWD>(t, v, pos, j);
+  j.live = k < t.nlev && p0 + (int)threadIdx.x < p1;
+}
+
+template <typename T, bool FWD, bool SKIP = false>
+__device__ __forceinline__ void ring2_row(const RingJob<T>& j, IluView<T> v, double* x, T* ring,
+                                          unsigned mask) {
+  if (SKIP && !j.live) return;
+  T acc[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) acc[c] = FWD ? j.rhs[c] : (T)0;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int kp = j.kp[s];
+    const T* w = ring + ((unsigned)kp & mask) * 3u;
+    const bool has = kp >= 0;
+    const T x0 = has ? w[0] : (T)0, x1 = has ? w[1] : (T)0, x2 = has ? w[2] : (T)0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T t = j.a[9 * s + 3 * a] * x0 + j.a[9 * s + 3 * a + 1] * x1 +
+                  j.a[9 * s + 3 * a + 2] * x2;
+      acc[a] = FWD ? acc[a] - t : acc[a] + t;
+    }
+  }
+  T out[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T d = j.D[3 * a] * acc[0] + j.D[3 * a + 1] * acc[1] + j.D[3 * a + 2] * acc[2];
+    out[a] = FWD ? d : j.rhs[a] - d;
+  }
+  if (!j.live) return;
+  T* w = ring + ((unsigned)j.pos & mask) * 3u;
+#pragma unroll
+  for (unsigned c = 0; c < 3; ++c) {
+    w[c] = out[c];
+    if (FWD)
+      v.z[c * (unsigned)v.ns + (unsigned)j.pos] = out[c];
+    else
+      x[3u * (unsigned)j.cell + c] = (double)out[c];
+  }
+}
+
+// Rows of level index k beyond the first NT (levels wider than the workgroup).
+template <typename T, int NT, bool FWD>
+__device__ __forceinline__ void ring2_extra(const Topo& t, IluView<T> v, double* x, T* ring,
+                                            unsigned mask, int k) {
+  const int l = FWD ? k : t.nlev - 1 - k;
+  const int p1 = t.level_ptr[l + 1];
+  for (int pos = t.level_ptr[l] + NT + (int)threadIdx.x; pos < p1; pos += NT) {
+    RingJob<T> j;
+    ring2_load<T, FWD>(t, v, pos, j);
+    ring2_row<T, FWD>(j, v, x, ring, mask);
+  }
+}
+
+// WIDE: some level has more rows than the workgroup has threads.
+template <typename T, int NT, bool FWD, bool WIDE, bool SKIP>
+__device__ __forceinline__ void ring2_sweep(const Topo& t, IluView<T> v, double* x, T* ring,
+                                            unsigned mask) {
+  RingJob<T> ja, jb;
+  ring2_fetch<T, FWD, SKIP>(t, v, 0, ja);
+  for (int k = 0; k < t.nlev; k += 2) {
+    ring2_fetch<T, FWD, SKIP>(t, v, k + 1, jb);
+    ring2_row<T, FWD, SKIP>(ja, v, x, ring, mask);
+    if (WIDE) ring2_extra<T, NT, FWD>(t, v, x, ring, mask, k);
+    __syncthreads();
+    if (k + 1 >= t.nlev) break;
+    ring2_fetch<T, FWD, SKIP>(t, v, k + 2, ja);
+    ring2_row<T, FWD, SKIP>(jb, v, x, ring, mask);
+    if (WIDE) ring2_extra<T, NT, FWD>(t, v, x, ring, mask, k + 1);
+    __syncthreads();
+  }
+}
+
+}  // namespace ilu
+}  // namespace opm

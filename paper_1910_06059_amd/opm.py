@@ -87,7 +87,7 @@ EXPORTS = [
     "opm_ensemble_bytes", "opm_ensemble_prepare", "opm_ensemble_launch",
 ]
 
-OPT_SWEEP_MODE, OPT_KRYLOV_CHUNK = 1, 2
+OPT_SWEEP_MODE, OPT_KRYLOV_CHUNK, OPT_SWEEP_KERNEL = 1, 2, 3
 
 _lib = None
 

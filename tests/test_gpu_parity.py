@@ -179,6 +179,31 @@ def test_sweep_modes_bitwise_equal(opm):
     assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sweep_kernels_bitwise_equal(opm, precision):
+    """Every one-workgroup ring-sweep kernel (gather inside the sweep;
+    branch-free prefetch with 512, 256, 128 threads; idle wavefronts
+    skipping) gives bitwise the same result, including levels wider than
+    the workgroup (the 30x30x12 box has up to 360 rows per level)."""
+    for case in (cases.config2(), cases.box_case(30, 30, 12, seed=9)):
+        g = opm.GpuModel(case)
+        y = g.state(cases.random_state(case, 5))
+        acc0 = g.accumulation(g.state(cases.random_state(case, 6)))
+        R, J, _ = g.assemble(y, acc0, DAY)
+        ilu, status = g.ilu0_factor(J, precision)
+        assert int(status.item()) == 0
+        out = []
+        try:
+            for kind in range(1, 7):
+                opm.set_option(opm.OPT_SWEEP_KERNEL, kind)
+                out.append(g.ilu0_apply(ilu, R, precision))
+        finally:
+            opm.set_option(opm.OPT_SWEEP_KERNEL, 0)
+        for kind, x in enumerate(out[1:], start=2):
+            assert torch.equal(x, out[0]), (case.name, precision, kind)
+    assert g.max_level > 256
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_spmv_parity(opm, name):
     case = CASES[name]
