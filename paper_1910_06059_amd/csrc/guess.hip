@@ -36,7 +36,8 @@ constexpr int kTaps = 27;
 constexpr int kLayerW = kTaps * kCh * kCh;        // W[27][cout][cin]
 constexpr int kLayerParams = kLayerW + kCh;       // + bias[cout]
 constexpr int kParams = 3 * kLayerParams;
-constexpr int kChunk = 64;                        // tiles per wave in the weight gradient
+constexpr int kChunk = 16;                        // tiles per wave in the weight gradient
+constexpr int kReduceGroup = 32;                  // waves per stage-1 sum of the partials
 static_assert(kParams == OPM_GUESS_PARAMS, "parameter count");
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
@@ -60,8 +61,11 @@ inline int tiles_of(const Grid& g) { return (g.nbox + 15) / 16; }
 inline size_t al(size_t b) { return (b + 255) / 256 * 256; }
 inline size_t act_bytes(const Grid& g) { return al(sizeof(unsigned short) * (size_t)tiles_of(g) * 16 * kCh); }
 inline int waves_of(const Grid& g) { return (tiles_of(g) + kChunk - 1) / kChunk; }
+inline int groups_of(const Grid& g) { return (waves_of(g) + kReduceGroup - 1) / kReduceGroup; }
+// per-wave partials, then the stage-1 sums of groups of kReduceGroup waves
 inline size_t partial_bytes(const Grid& g) {
-  return al(sizeof(float) * (size_t)waves_of(g) * kLayerParams);
+  return al(sizeof(float) * (size_t)waves_of(g) * kLayerParams) +
+         al(sizeof(float) * (size_t)groups_of(g) * kLayerParams);
 }
 
 // -------------------------------------------------------------- features
@@ -225,54 +229,81 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(Grid g, const unsigned sh
 // dW[t][cout][cin] = sum_cells in[cell + off_t][cin] d_out[cell][cout] as
 // 16x16x16 products whose reduction runs over 16 cells (A = in^T with rows
 // cin, B = d_out with columns cout); bias[cout] = sum_cells d_out[cell][cout].
+// Tiles are the outer loop: a lane's four cells and their d_out values are
+// found once per tile and the 27 tap accumulators stay in registers.
 __global__ __launch_bounds__(256) void k_conv_bwd_weight(Grid g, const unsigned short* in,
                                                          const unsigned short* dout, int ntiles,
                                                          float* partials) {
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int t0 = wave * kChunk;
-  if (t0 >= ntiles) return;
+  if (t0 >= ntiles) return;   // whole wavefront: MFMA needs all lanes
   const int t1 = min(t0 + kChunk, ntiles);
   const int m = lane & 15, kb = lane >> 4;
-  float* P = partials + (size_t)wave * kLayerParams;
+  floatx4 acc[kTaps];
+#pragma unroll
+  for (int t = 0; t < kTaps; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.f;
-  for (int t = 0; t < kTaps; ++t) {
-    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int tile = t0; tile < t1; ++tile) {
-      bf16x4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
+  for (int tile = t0; tile < t1; ++tile) {
+    int ci[4], cj[4], ck[4];
+    bool ok[4];
+    bf16x4 b = {0, 0, 0, 0};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int cell = tile * 16 + 4 * kb + r;
-        if (cell >= g.nbox) continue;
-        const int ci = cell % g.nx, cj = (cell / g.nx) % g.ny, ck = cell / (g.nx * g.ny);
-        const int ii = ci + dx, jj = cj + dy, kk = ck + dz;
-        b[r] = (short)dout[(unsigned)cell * kCh + m];
-        if (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz)
-          a[r] = (short)in[(unsigned)(ii + g.nx * (jj + g.ny * kk)) * kCh + m];
-      }
-      if (t == kTaps / 2) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) bsum += bf2f((unsigned short)b[r]);
-      }
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) {
+      const int cell = tile * 16 + 4 * kb + r;
+      ok[r] = cell < g.nbox;
+      const int c = ok[r] ? cell : 0;
+      ci[r] = c % g.nx;
+      cj[r] = (c / g.nx) % g.ny;
+      ck[r] = c / (g.nx * g.ny);
+      const unsigned short dv = ok[r] ? dout[(unsigned)c * kCh + m] : (unsigned short)0;
+      b[r] = (short)dv;
+      bsum += bf2f(dv);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) P[(t * kCh + m) * kCh + 4 * kb + r] = acc[r];
+    for (int t = 0; t < kTaps; ++t) {
+      const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+      bf16x4 a = {0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ii = ci[r] + dx, jj = cj[r] + dy, kk = ck[r] + dz;
+        if (ok[r] && ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz)
+          a[r] = (short)in[(unsigned)(ii + g.nx * (jj + g.ny * kk)) * kCh + m];
+      }
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+    }
   }
+  float* P = partials + (size_t)wave * kLayerParams;
+#pragma unroll
+  for (int t = 0; t < kTaps; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) P[(t * kCh + m) * kCh + 4 * kb + r] = acc[t][r];
   // lanes m, m+16, m+32, m+48 hold the four k blocks of channel m
   bsum += __shfl_xor(bsum, 16, 64);
   bsum += __shfl_xor(bsum, 32, 64);
   if (kb == 0) P[kLayerW + m] = bsum;
 }
 
-// grad[e] = sum over waves of the partials, in wave order (deterministic).
-__global__ __launch_bounds__(256) void k_reduce_partials(const float* partials, int nwaves,
+// Sum of the per-wave partials in two fixed-order stages: stage 1 adds
+// groups of kReduceGroup waves (grid: parameter blocks x groups), stage 2
+// adds the groups (deterministic).
+
+__global__ __launch_bounds__(256) void k_reduce_stage1(const float* partials, int nwaves,
+                                                       float* stage) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= kLayerParams) return;
+  const int w0 = blockIdx.y * kReduceGroup, w1 = min(w0 + kReduceGroup, nwaves);
+  float s = 0.f;
+  for (int w = w0; w < w1; ++w) s += partials[(size_t)w * kLayerParams + e];
+  stage[(size_t)blockIdx.y * kLayerParams + e] = s;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partials(const float* stage, int ngroups,
                                                          float* grad) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= kLayerParams) return;
   float s = 0.f;
-  for (int w = 0; w < nwaves; ++w) s += partials[(size_t)w * kLayerParams + e];
+  for (int gr = 0; gr < ngroups; ++gr) s += stage[(size_t)gr * kLayerParams + e];
   grad[e] = s;
 }
 
@@ -396,11 +427,14 @@ void conv_launch(const Grid& g, const unsigned short* in, const unsigned short* 
 void backward_launch(const Grid& g, const unsigned short* in, const unsigned short* dout,
                      const unsigned short* wb, const unsigned short* act_in, unsigned short* din,
                      float* grad, float* partials, hipStream_t s) {
-  const int nt = tiles_of(g), nw = waves_of(g);
+  const int nt = tiles_of(g), nw = waves_of(g), ng = groups_of(g);
+  float* stage = partials + al(sizeof(float) * (size_t)nw * kLayerParams) / sizeof(float);
   hipLaunchKernelGGL(k_conv_bwd_weight, dim3((nw + 3) / 4), dim3(256), 0, s, g, in, dout, nt,
                      partials);
-  hipLaunchKernelGGL(k_reduce_partials, dim3((kLayerParams + 255) / 256), dim3(256), 0, s,
-                     partials, nw, grad);
+  hipLaunchKernelGGL(k_reduce_stage1, dim3((kLayerParams + 255) / 256, ng), dim3(256), 0, s,
+                     partials, nw, stage);
+  hipLaunchKernelGGL(k_reduce_partials, dim3((kLayerParams + 255) / 256), dim3(256), 0, s, stage,
+                     ng, grad);
   if (din)
     hipLaunchKernelGGL(k_conv_bwd_data, dim3((nt + 3) / 4), dim3(256), 0, s, g, dout, wb, act_in,
                        din, nt);
