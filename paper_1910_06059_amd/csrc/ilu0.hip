@@ -119,16 +119,37 @@ __global__ __launch_bounds__(kWgThreads) void k_apply_ring(Topo t, IluView<T> v,
   apply_levels_ring<T, kWgThreads>(t, v, r, x, reinterpret_cast<T*>(smem), mask);
 }
 
-// r gathered into z in level order (the right-hand side of the ring sweep).
+// r gathered into z4 in level order (the right-hand side of the record sweep).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gather_rhs(int n, const int32_t* perm, IluView<T> v,
                                                        const double* r, const int32_t* skip) {
   if (skip && *skip != 0) return;
   const int pos = blockIdx.x * kBlock + threadIdx.x;
   if (pos >= n) return;
-  const int cell = perm[pos];
+  const size_t cell = (size_t)perm[pos];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) v.z[(size_t)c * v.ns + pos] = (T)r[3 * (size_t)cell + c];
+  for (int c = 0; c < 3; ++c) v.z4[4 * (size_t)pos + c] = (T)r[3 * cell + c];
+  v.z4[4 * (size_t)pos + 3] = (T)0;
+}
+
+// Sweep records of every row position (after the factorisation): the
+// forward record holds the lower blocks and D^{-1}, the backward one the
+// upper blocks and D^{-1}, each with the neighbour positions and the row.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pack_records(Topo t, IluView<T> v) {
+  const int pos = blockIdx.x * kBlock + threadIdx.x;
+  if (pos >= t.n) return;
+  constexpr size_t kV = 16 / sizeof(T);
+  const size_t ns = (size_t)v.ns, p = (size_t)pos;
+#pragma unroll
+  for (int e = 0; e < kRecValues; ++e) {
+    const size_t a = ((size_t)e / kV * ns + p) * kV + (size_t)e % kV;
+    v.rec_f[a] = e < 27 ? v.lov[e * ns + p] : v.dinv[(e - 27) * ns + p];
+    v.rec_b[a] = e < 27 ? v.upv[e * ns + p] : v.dinv[(e - 27) * ns + p];
+  }
+  const int cell = t.perm[pos];
+  v.idx_f[pos] = int4v{t.lo_pos[3 * p], t.lo_pos[3 * p + 1], t.lo_pos[3 * p + 2], cell};
+  v.idx_b[pos] = int4v{t.up_pos[3 * p], t.up_pos[3 * p + 1], t.up_pos[3 * p + 2], cell};
 }
 
 // Both sweeps by one workgroup of NT threads through the LDS ring with
@@ -189,6 +210,10 @@ int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* stat
       hipLaunchKernelGGL((k_factor_wg<T, false>), dim3(1), dim3(kFacThreads), 0, s, t, J, v,
                          status);
     }
+    // the record sweep's copy of the factors (whenever a ring sweep can run)
+    if (sizeof(T) * 3 * (size_t)ring_rows(pb->sweep_span, pb->max_level) <= kMaxRingBytes)
+      hipLaunchKernelGGL(k_pack_records<T>, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock),
+                         0, s, t, v);
     OPM_TRY_HIP(hipGetLastError());
     return OPM_OK;
   }

@@ -13,6 +13,21 @@ namespace ilu {
 
 __host__ __device__ inline size_t ilu_padded(int n) { return ((size_t)n + 63) / 64 * 64; }
 
+// Sweep records: the 36 values a sweep row needs (its three neighbour
+// blocks, then D^{-1}) as 16-byte chunks, chunk-major: value e of position p
+// at [((e / kV) * ns + p) * kV + e % kV] with kV = 16 / sizeof(T), so one
+// 16-byte load per chunk and lane reads consecutive chunks across lanes.
+constexpr int kRecValues = 36;
+template <typename T>
+struct Vec16 {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+typedef int int4v __attribute__((ext_vector_type(4)));
+
 template <typename T>
 struct IluView {
   int ns;          // SoA stride (n padded to 64)
@@ -21,6 +36,11 @@ struct IluView {
   T* lov;          // [27][ns] A_ik of the lower neighbours, slot-major
   T* upv;          // [27][ns] A_ij of the upper neighbours
   T* z;            // [3][ns] level-ordered sweep scratch
+  T* rec_f;        // forward sweep records (lower blocks, D^{-1})
+  T* rec_b;        // backward sweep records (upper blocks, D^{-1})
+  int4v* idx_f;    // [ns] (lower neighbour positions, row)
+  int4v* idx_b;    // [ns] (upper neighbour positions, row)
+  T* z4;           // [ns][4] level-ordered sweep scratch of the record sweep
 };
 
 template <typename T>
@@ -28,7 +48,8 @@ __host__ __device__ inline size_t view_bytes(int n) {
   const size_t ns = ilu_padded(n);
   size_t b = sizeof(double) * 9 * ns;
   if (sizeof(T) != sizeof(double)) b += sizeof(T) * 9 * ns;
-  return b + sizeof(T) * (27 + 27 + 3) * ns;
+  return b + sizeof(T) * (27 + 27 + 3) * ns + sizeof(T) * (2 * kRecValues + 4) * ns +
+         2 * sizeof(int4v) * ns;
 }
 
 template <typename T>
@@ -49,6 +70,16 @@ __host__ __device__ inline IluView<T> view(const opm_problem* pb, void* ilu) {
   v.upv = (T*)base;
   base += sizeof(T) * 27 * v.ns;
   v.z = (T*)base;
+  base += sizeof(T) * 3 * v.ns;
+  v.rec_f = (T*)base;
+  base += sizeof(T) * kRecValues * v.ns;
+  v.rec_b = (T*)base;
+  base += sizeof(T) * kRecValues * v.ns;
+  v.idx_f = (int4v*)base;
+  base += sizeof(int4v) * v.ns;
+  v.idx_b = (int4v*)base;
+  base += sizeof(int4v) * v.ns;
+  v.z4 = (T*)base;
   return v;
 }
 
@@ -664,9 +695,11 @@ namespace ilu {
 
 // ---------------------------------------------------------------------------
 // Ring sweep with branch-free prefetch.  The forward sweep takes its
-// right-hand side from z in level order (gathered there before the sweep),
+// right-hand side from z4 in level order (gathered there before the sweep),
 // so the data of a row are loads at its own level position only and the
-// next level's loads never wait for an index.  A prefetch clamps the level
+// next level's loads never wait for an index; the row's blocks, D^{-1},
+// neighbour positions and right-hand side come from the sweep records in
+// 16-byte loads (21 per row in FP64, 12 in FP32).  A prefetch clamps the level
 // (past the last level: the last level) and the row (lanes past a level's
 // end: its last row), so every lane issues the same loads on every path and
 // the compiler can wait for exactly the loads a level needs while the next
@@ -687,20 +720,37 @@ struct RingJob {
 
 template <typename T, bool FWD>
 __device__ __forceinline__ void ring2_load(const Topo& t, IluView<T> v, int pos, RingJob<T>& j) {
+  typedef typename Vec16<T>::type V;
+  constexpr unsigned kV = 16 / sizeof(T);
   const unsigned ns = (unsigned)v.ns, up = (unsigned)pos;
-  const T* blk = FWD ? v.lov : v.upv;
-  const int32_t* nb = FWD ? t.lo_pos : t.up_pos;
+  const V* rec = reinterpret_cast<const V*>(FWD ? v.rec_f : v.rec_b);
+  const int4v ix = (FWD ? v.idx_f : v.idx_b)[up];
   j.pos = pos;
   j.live = true;
-  j.cell = FWD ? 0 : t.perm[up];
+  j.kp[0] = ix.x;
+  j.kp[1] = ix.y;
+  j.kp[2] = ix.z;
+  j.cell = ix.w;
+  const V* zr = reinterpret_cast<const V*>(v.z4) + up * (4u / kV);
 #pragma unroll
-  for (unsigned c = 0; c < 3; ++c) j.rhs[c] = v.z[c * ns + up];
+  for (unsigned q = 0; q < 4u / kV; ++q) {
+    const V r = zr[q];
 #pragma unroll
-  for (unsigned s = 0; s < 3; ++s) j.kp[s] = nb[3u * up + s];
+    for (unsigned l = 0; l < kV; ++l)
+      if (q * kV + l < 3u) j.rhs[q * kV + l] = r[l];
+  }
 #pragma unroll
-  for (unsigned e = 0; e < 27; ++e) j.a[e] = blk[e * ns + up];
+  for (unsigned c = 0; c < (unsigned)kRecValues / kV; ++c) {
+    const V w = rec[c * ns + up];
 #pragma unroll
-  for (unsigned e = 0; e < 9; ++e) j.D[e] = v.dinv[e * ns + up];
+    for (unsigned l = 0; l < kV; ++l) {
+      const unsigned e = c * kV + l;
+      if (e < 27u)
+        j.a[e] = w[l];
+      else
+        j.D[e - 27u] = w[l];
+    }
+  }
 }
 
 // SKIP: a wavefront with no row in the level issues no load (a branch that
@@ -746,12 +796,22 @@ __device__ __forceinline__ void ring2_row(const RingJob<T>& j, IluView<T> v, dou
   if (!j.live) return;
   T* w = ring + ((unsigned)j.pos & mask) * 3u;
 #pragma unroll
-  for (unsigned c = 0; c < 3; ++c) {
-    w[c] = out[c];
-    if (FWD)
-      v.z[c * (unsigned)v.ns + (unsigned)j.pos] = out[c];
-    else
-      x[3u * (unsigned)j.cell + c] = (double)out[c];
+  for (unsigned c = 0; c < 3; ++c) w[c] = out[c];
+  if (FWD) {
+    typedef typename Vec16<T>::type V;
+    constexpr unsigned kV = 16 / sizeof(T);
+    const T o4[4] = {out[0], out[1], out[2], (T)0};
+    V* zr = reinterpret_cast<V*>(v.z4) + (unsigned)j.pos * (4u / kV);
+#pragma unroll
+    for (unsigned q = 0; q < 4u / kV; ++q) {
+      V r;
+#pragma unroll
+      for (unsigned l = 0; l < kV; ++l) r[l] = o4[q * kV + l];
+      zr[q] = r;
+    }
+  } else {
+#pragma unroll
+    for (unsigned c = 0; c < 3; ++c) x[3u * (unsigned)j.cell + c] = (double)out[c];
   }
 }
 
