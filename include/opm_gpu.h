@@ -74,10 +74,11 @@ typedef struct opm_fluid {
  * numbered in natural order c = i + nx (j + ny k) restricted to the mask;
  * faces are the (+x, +y, +z) neighbours of each active cell, so
  * face_cells[f][0] < face_cells[f][1].  The level schedule lists rows by
- * level of the lower-triangular dependency graph of ILU(0):
- * level(i) = 1 + max level(lower neighbours), rows of one level in ascending
- * order; it is the order in which ILU(0) factorisation and triangular sweeps
- * may proceed in parallel. */
+ * level: the levels are the hyperplanes i + j + k = const that hold active
+ * cells, in increasing order, rows of one level in ascending order.  Every
+ * lower neighbour of a row lies on the previous level, so this is an order
+ * in which ILU(0) factorisation and triangular sweeps may proceed in
+ * parallel (any such order gives the same factors). */
 typedef struct opm_topology {
   int32_t* cell_box;    /* [n_cells]  box index of each active cell            */
   int32_t* face_cells;  /* [n_faces][2] lower and upper cell                   */

@@ -106,15 +106,22 @@ extern "C" int opm_topology_build(int32_t nx, int32_t ny, int32_t nz, const uint
   }
   t->row_ptr[n] = q;
 
-  // ILU(0) level schedule: level(i) = 1 + max level(k) over lower neighbours
-  std::vector<int32_t> level(n, 0);
-  int32_t nlev = 0;
+  // ILU(0) level schedule: the hyperplanes i + j + k = h that hold active
+  // cells, in increasing h.  Every lower neighbour of a cell lies on h - 1,
+  // i.e. on the previous level, so rows of one level are independent and a
+  // sweep needs the values of two consecutive levels only (on a masked grid
+  // the as-soon-as-possible schedule would put neighbours many levels apart).
+  std::vector<int32_t> level(n, 0), hmap(nx + ny + nz, -1);
   for (int32_t ci = 0; ci < n; ++ci) {
-    int32_t lv = 0;
-    for (int32_t r = t->row_ptr[ci]; r < t->diag_pos[ci]; ++r)
-      lv = std::max(lv, level[t->col_idx[r]] + 1);
-    level[ci] = lv;
-    nlev = std::max(nlev, lv + 1);
+    const int32_t b = t->cell_box[ci];
+    hmap[b % nx + (b / nx) % ny + b / (nx * ny)] = 0;
+  }
+  int32_t nlev = 0;
+  for (auto& h : hmap)
+    if (h == 0) h = nlev++;
+  for (int32_t ci = 0; ci < n; ++ci) {
+    const int32_t b = t->cell_box[ci];
+    level[ci] = hmap[b % nx + (b / nx) % ny + b / (nx * ny)];
   }
   std::vector<int32_t> cnt(nlev + 1, 0);
   for (int32_t ci = 0; ci < n; ++ci) cnt[level[ci] + 1]++;

@@ -103,9 +103,14 @@ def test_topology_matches_oracle(make):
     for l in range(L):
         level[perm[lp[l]:lp[l + 1]]] = l
         assert np.all(np.diff(perm[lp[l]:lp[l + 1]]) > 0)
+    # levels are the non-empty hyperplanes i + j + k in increasing order, and
+    # every lower neighbour lies on the previous level
+    hyper = np.array([b % case.nx + (b // case.nx) % case.ny + b // (case.nx * case.ny)
+                      for b in g["cell_box"]])
+    assert np.array_equal(np.unique(hyper, return_inverse=True)[1], level)
     for i in range(n):
         lower = [ci[q] for q in range(rp[i], rp[i + 1]) if ci[q] < i]
-        assert level[i] == (max(level[k] for k in lower) + 1 if lower else 0)
+        assert all(level[k] == level[i] - 1 for k in lower)
     assert topo.max_level == np.diff(lp).max()
     # sweep index tables
     for pos in range(n):
