@@ -586,8 +586,8 @@ def main():
         import oracle
         m = oracle.Model(case)
         yo = case.initial_state()
-        c_cni, c_wall, c_steps = 0.0, 0.0, 0
-        while c_wall < args.cpu_seconds and c_steps < len(case.report_dt):
+        c_cni, c_wall, c_steps, passes = 0.0, 0.0, 0, 0
+        while c_wall < args.cpu_seconds:
             t1 = time.perf_counter()
             ost, yo, orep = m.advance(yo, dt)
             c_wall += time.perf_counter() - t1
@@ -595,10 +595,14 @@ def main():
                 break
             c_cni += orep.cell_newton_its
             c_steps += 1
+            if c_steps % len(case.report_dt) == 0:   # schedule done: start it again
+                yo = case.initial_state()
+                passes += 1
         line["cpu_baseline"] = {"value": round(c_cni / c_wall, 1), "unit": "cell-Newton-iterations/s",
                                 "cores": 1, "kind": "oracle",
-                                "sample": f"first {c_steps} of the 10-day steps of the same workload "
-                                          f"({c_wall:.1f} s, single-threaded plain C, -O2)"}
+                                "sample": f"{c_steps} 10-day steps of the same workload (its "
+                                          f"{len(case.report_dt)}-step schedule repeated from the "
+                                          f"initial state; {c_wall:.1f} s, single-threaded plain C, -O2)"}
     print(json.dumps(line), flush=True)
 
 
