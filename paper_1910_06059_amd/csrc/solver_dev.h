@@ -396,6 +396,42 @@ __device__ __forceinline__ void apply_levels_wg(const Topo& t, IluView<T> v, con
   wg_sweep<T, NT, false>(t, v, r, x, win);
 }
 
+// Block SpMV with three block rows per wavefront.  Lane l serves row l / 21
+// of the group, block (l % 21) / 3 of that row (and every 7th block after
+// it) and output component l % 3, so the 21 lanes of a row read its blocks
+// (at most 7 on the 7-point stencil) as one contiguous run of doubles and a
+// wavefront reads one contiguous span of the matrix.  The per-block partial
+// sums of an output component sit in lanes l, l+3, ..., l+18 and are added in
+// block order by the lane of block 0, which returns true and the row and
+// component it owns.  Lane 63 and rows past n contribute nothing.  Every lane
+// of the wavefront must call it (cross-lane reads).
+constexpr int kSpmvRowsPerWave = 3;
+
+__device__ __forceinline__ bool spmv_group(int n, const int32_t* row_ptr, const int32_t* col,
+                                           const double* J, const double* x, int group,
+                                           int lane, int& row, int& comp, double& yv) {
+  const int rl = lane / 21, rem = lane - 21 * rl;
+  const int q = rem / 3;
+  comp = rem - 3 * q;
+  row = group * kSpmvRowsPerWave + rl;
+  double v = 0.0;
+  const bool live = lane < 21 * kSpmvRowsPerWave && row < n;
+  if (live) {
+    const int q1 = row_ptr[row + 1];
+    for (int qb = row_ptr[row] + q; qb < q1; qb += 7) {
+      const double* B = J + 9 * (size_t)qb + 3 * comp;
+      const double* xj = x + 3 * (size_t)col[qb];
+      v += B[0] * xj[0] + B[1] * xj[1] + B[2] * xj[2];
+    }
+  }
+  double sum = v;
+#pragma unroll
+  for (int k = 1; k < 7; ++k) sum += __shfl(v, lane + 3 * k, kWave);
+  yv = sum;
+  return live && q == 0;
+}
+
+__host__ __device__ inline int spmv_groups(int n) { return (n + kSpmvRowsPerWave - 1) / kSpmvRowsPerWave; }
 // One block row of y = J x (3 outputs).
 __device__ __forceinline__ void spmv_row(const int32_t* row_ptr, const int32_t* col,
                                          const double* J, const double* x, int i, double* y3) {
