@@ -95,6 +95,8 @@ def lib(path: Optional[str] = None):
         L.ora_norms.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, _dp, _dp]
         L.ora_ilu0.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.ora_ilu0_apply.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.ora_set_ilu_blocks.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.ora_set_ilu_blocks.restype = ctypes.c_int
         L.ora_spmv.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
         L.ora_bicgstab.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, ctypes.c_double,
                                    ctypes.c_int, _dp, _dp]
@@ -218,6 +220,12 @@ class Model:
         self.L.ora_norms(self.h, _d(np.ascontiguousarray(y)), _d(np.ascontiguousarray(R)), dt,
                          _d(cnv), _d(mb))
         return cnv, mb
+
+    def set_ilu_blocks(self, bx: int, by: int, bz: int):
+        """Block ILU0 over boxes of bx x by x bz cells (0, 0, 0: one block)."""
+        st = self.L.ora_set_ilu_blocks(self.h, bx, by, bz)
+        if st != OK:
+            raise ValueError(f"oracle: invalid ILU blocks {(bx, by, bz)}")
 
     def ilu0(self, J):
         F = np.zeros_like(J)

@@ -16,6 +16,8 @@
  *                   cancellation (sum of residuals = accumulation + wells)
  *   Jacobian        central finite differences of the residual
  *   ILU(0)          (LU)_ij = A_ij on every pattern entry; exact LU on 1-D
+ *   block ILU0      LU = A inside subdomains and 0 between them; one box =
+ *                   ILU(0); one-cell boxes = block Jacobi; cut 1-D chain
  *   BiCGStab        dense direct solve (numpy) on tiny grids
  *   Newton          one-cell producer root by bisection, quadratic
  *                   convergence, mass balance per step, mirror symmetry
@@ -135,6 +137,7 @@ struct ora_model {
   int* conn_cell;  /* [nc] */
   double* conn_wi; /* [nc] */
   int* conn_well;  /* [nc] */
+  int blk[3];      /* ILU(0) subdomain box (cells per axis); 0: one block */
 };
 
 int ora_n_cells(const ora_model* m) { return m->n; }
@@ -566,8 +569,32 @@ int ora_dense_solve(int n, double* A, double* b) {
  * Generic IKJ elimination restricted to the sparsity pattern of A: for each
  * row i and each k < i in the row, L_ik = A_ik U_kk^{-1}; then every entry
  * (i, j) with j > k that is also in row k's pattern is updated by -L_ik U_kj. */
+int ora_set_ilu_blocks(ora_model* m, int bx, int by, int bz) {
+  if (!(bx == 0 && by == 0 && bz == 0) && (bx <= 0 || by <= 0 || bz <= 0)) return ORA_EINVAL;
+  m->blk[0] = bx;
+  m->blk[1] = by;
+  m->blk[2] = bz;
+  return ORA_OK;
+}
+
+/* Subdomain of a cell: the box (i / bx, j / by, k / bz) of the lattice. */
+static int same_block(const ora_model* m, int a, int b) {
+  if (m->blk[0] == 0) return 1;
+  const int ba = m->cell_box[a], bb = m->cell_box[b];
+  const int ia = ba % m->nx, ja = (ba / m->nx) % m->ny, ka = ba / (m->nx * m->ny);
+  const int ib = bb % m->nx, jb = (bb / m->nx) % m->ny, kb = bb / (m->nx * m->ny);
+  return ia / m->blk[0] == ib / m->blk[0] && ja / m->blk[1] == jb / m->blk[1] &&
+         ka / m->blk[2] == kb / m->blk[2];
+}
+
 int ora_ilu0(const ora_model* m, const double* J, double* F) {
   memcpy(F, J, sizeof(double) * 9 * m->nnzb);
+  /* block ILU0 of a partitioned grid (sec. 2.5, one block per process):
+   * the factorisation sees the matrix without its couplings between
+   * different subdomains, i.e. the ILU(0) of each subdomain's own matrix */
+  for (int i = 0; i < m->n; ++i)
+    for (int q = m->row_ptr[i]; q < m->row_ptr[i + 1]; ++q)
+      if (!same_block(m, i, m->col_idx[q])) memset(F + 9 * q, 0, sizeof(double) * 9);
   double inv[9], tmp[9];
   for (int i = 0; i < m->n; ++i) {
     for (int q = m->row_ptr[i]; q < m->row_ptr[i + 1]; ++q) {

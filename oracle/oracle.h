@@ -119,6 +119,12 @@ void ora_norms(const ora_model* m, const double* y, const double* R, double dt,
 /* Block ILU(0), generic IKJ form: F [nnzb][3][3] holds L (unit diagonal
  * implied) below and U (with diagonal) on/above the block diagonal. */
 int ora_ilu0(const ora_model* m, const double* J, double* F);
+/* Block ILU0 over a partition of the grid into boxes of bx x by x bz cells
+ * (sec. 2.5: one block per process): ora_ilu0 then factors the matrix
+ * with every block coupling two different subdomains removed (those blocks
+ * of F are zero).  All three 0 restores the single block.  ORA_EINVAL for
+ * other non-positive sizes. */
+int ora_set_ilu_blocks(ora_model* m, int bx, int by, int bz);
 void ora_ilu0_apply(const ora_model* m, const double* F, const double* r, double* x);
 void ora_spmv(const ora_model* m, const double* J, const double* x, double* y);
 /* Right-preconditioned BiCGStab, x0 = 0.  its counts half iterations as 0.5. */

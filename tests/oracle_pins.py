@@ -366,6 +366,113 @@ def pin_bicgstab_dense(lib_path=None):
         assert np.allclose(xo, xd, rtol=1e-10, atol=0)
 
 
+def _sub_of(case, cell_box, blk):
+    """Subdomain box index of each active cell for boxes of blk cells."""
+    nx, ny = case.nx, case.ny
+    i, j, k = cell_box % nx, (cell_box // nx) % ny, cell_box // (nx * ny)
+    return np.stack([i // blk[0], j // blk[1], k // blk[2]], axis=1)
+
+
+def pin_block_ilu0_partition(lib_path=None):
+    """Block ILU0 over a box partition (sec. 2.5, one block per process) is the
+    ILU(0) of the matrix without its couplings between subdomains: the product
+    LU reproduces A on every block of the pattern inside one subdomain, L and
+    U vanish on every block between two subdomains, and the preconditioner
+    solve is the exact solve with that LU (dense numpy).  Boxes of 2 x 3 x 2
+    on a 5 x 4 x 3 grid leave ragged boxes on every axis."""
+    c = _wells_case(5, 4, 3, seed=21)
+    m = _model(c, lib_path)
+    y = cases.random_state(c, seed=22)
+    st, R, J = m.assemble(y, m.accumulation(cases.random_state(c, seed=23)), DAY)
+    blk = (2, 3, 2)
+    m.set_ilu_blocks(*blk)
+    st, F = m.ilu0(J)
+    assert st == 0
+    sub = _sub_of(c, m.geometry()["cell_box"], blk)
+    L, U = _lu_dense(m, F)
+    A = _dense(m, J)
+    P = L @ U
+    rp, ci = m.pattern()
+    n_cross = 0
+    for i in range(m.n):
+        sc = np.abs(A[3 * i:3 * i + 3]).max()
+        for q in range(rp[i], rp[i + 1]):
+            j = ci[q]
+            if (sub[i] == sub[j]).all():
+                blkd = P[3 * i:3 * i + 3, 3 * j:3 * j + 3] - A[3 * i:3 * i + 3, 3 * j:3 * j + 3]
+                assert np.abs(blkd).max() <= 1e-12 * sc
+            else:
+                n_cross += 1
+                assert not F[q].any(), (i, j)
+    assert n_cross > 0
+    r = np.random.default_rng(5).standard_normal((m.n, 3))
+    x = m.ilu0_apply(F, r)
+    xd = np.linalg.solve(P, r.ravel())
+    assert np.abs(x.ravel() - xd).max() <= 1e-10 * np.abs(xd).max()
+
+
+def pin_block_ilu0_special_cases(lib_path=None):
+    """One box covering the grid is the global ILU(0) exactly; one-cell boxes
+    give block Jacobi (x_i = A_ii^{-1} r_i, numpy per cell); a 1-D chain cut
+    in two has no dropped fill inside either half, so the preconditioner is
+    the exact inverse of the matrix without the cut coupling."""
+    c = _wells_case(4, 3, 2, seed=31)
+    m = _model(c, lib_path)
+    y = cases.random_state(c, seed=32)
+    st, R, J = m.assemble(y, m.accumulation(cases.random_state(c, seed=33)), DAY)
+    st, F0 = m.ilu0(J)
+    m.set_ilu_blocks(4, 3, 2)
+    st, F1 = m.ilu0(J)
+    assert np.array_equal(F0, F1)
+    m.set_ilu_blocks(9, 9, 9)
+    st, F1 = m.ilu0(J)
+    assert np.array_equal(F0, F1)
+    m.set_ilu_blocks(1, 1, 1)
+    st, Fj = m.ilu0(J)
+    r = np.random.default_rng(7).standard_normal((m.n, 3))
+    x = m.ilu0_apply(Fj, r)
+    rp, ci = m.pattern()
+    for i in range(m.n):
+        q = [q for q in range(rp[i], rp[i + 1]) if ci[q] == i][0]
+        xi = np.linalg.solve(J[q], r[i])
+        assert np.abs(x[i] - xi).max() <= 1e-12 * np.abs(xi).max()
+    # 1-D chain of 8 cells cut between cells 2 and 3 (boxes of 3 cells)
+    c = cases.box_case(8, 1, 1, seed=2, wells=[
+        Well("I", cases.WELL_RATE_INJ, [(0, 0, 0)], 300 * STB / DAY),
+        Well("P", cases.WELL_BHP_PROD, [(7, 0, 0)], 3000 * PSI)])
+    m = _model(c, lib_path)
+    y = cases.random_state(c, seed=4)
+    st, R, J = m.assemble(y, m.accumulation(cases.random_state(c, seed=8)), DAY)
+    m.set_ilu_blocks(3, 1, 1)
+    st, F = m.ilu0(J)
+    A = _dense(m, J)
+    for a, b in [(2, 3), (5, 6)]:
+        A[3 * a:3 * a + 3, 3 * b:3 * b + 3] = 0.0
+        A[3 * b:3 * b + 3, 3 * a:3 * a + 3] = 0.0
+    x = m.ilu0_apply(F, -R)
+    xd = np.linalg.solve(A, -R.ravel())
+    assert np.abs(x.ravel() - xd).max() <= 1e-10 * np.abs(xd).max()
+
+
+def pin_block_ilu0_newton(lib_path=None):
+    """The preconditioner changes the linear iterations, not the converged
+    Newton state: a report step with column boxes matches the single-block
+    run to the Newton tolerance, and it still conserves mass per component."""
+    c = _wells_case(6, 5, 3, seed=41)
+    m = _model(c, lib_path)
+    opts = oracle.default_opts(c)
+    dt = 10 * DAY
+    st, y0, rep0 = m.advance(c.initial_state(), dt, opts)
+    assert st == 0
+    m.set_ilu_blocks(2, 2, 3)
+    st, y1, rep1 = m.advance(c.initial_state(), dt, opts)
+    assert st == 0
+    assert rep1.lin_its != rep0.lin_its
+    assert np.abs(y1[:, 0] - y0[:, 0]).max() <= 1e-8 * np.abs(y0[:, 0]).max()
+    assert np.abs(y1[:, 1:] - y0[:, 1:]).max() <= 1e-8
+    assert max(abs(e) for e in rep1.mass_err) <= 1e-10
+
+
 # ------------------------------------------------------------------ Newton
 def pin_one_cell_producer(lib_path=None):
     """One cell drained by a BHP producer with immobile water below connate
@@ -484,6 +591,7 @@ ALL_PINS = [
     pin_series_transmissibility, pin_depth_pore_volume, pin_peaceman_worked_value,
     pin_compressibility, pin_darcy_flux_upwind, pin_hydrostatic_column, pin_pressure_block,
     pin_jacobian_fd, pin_conservation, pin_norms, pin_ilu0_pattern, pin_ilu0_exact_1d,
-    pin_bicgstab_dense, pin_one_cell_producer, pin_injector_mass, pin_quadratic_convergence,
+    pin_bicgstab_dense, pin_block_ilu0_partition, pin_block_ilu0_special_cases,
+    pin_block_ilu0_newton, pin_one_cell_producer, pin_injector_mass, pin_quadratic_convergence,
     pin_mass_balance_run, pin_mirror_symmetry,
 ]

@@ -49,6 +49,11 @@ MUTANTS = [
     ("kv_not_scaled", "m->kv[c] = kv_kh * perm_h[b];", "m->kv[c] = perm_h[b];"),
     ("peaceman_radius", "double ro = 0.14 * sqrt(dx * dx + dy * dy);", "double ro = 0.2 * dx;"),
     ("chop_not_applied_to_dp", "y[3 * c] += dp;", "y[3 * c] += 0.9 * dp;"),
+    ("block_couplings_kept", "if (!same_block(m, i, m->col_idx[q])) memset",
+     "if (m->blk[0] < 0 && !same_block(m, i, m->col_idx[q])) memset"),
+    ("block_lower_couplings_only", "if (!same_block(m, i, m->col_idx[q])) memset",
+     "if (m->col_idx[q] < i && !same_block(m, i, m->col_idx[q])) memset"),
+    ("block_axis_swapped", "ka / m->blk[2] == kb / m->blk[2]", "ka / m->blk[1] == kb / m->blk[1]"),
 ]
 
 
