@@ -112,6 +112,47 @@ int opm_topology_count(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask,
 int opm_topology_build(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask,
                        opm_topology* topo);
 
+/* Block ILU0 over a partition of the grid into subdomain boxes (paper
+ * sec. 2.5: a block ILU0 with one block per process; sec. 3.7.2 observes
+ * that the linear iterations barely grow with the number of blocks).  The
+ * box of cell (i, j, k) is (i / bx, j / by, k / bz); boxes without active
+ * cells are dropped and the rest numbered densely in box order.  The
+ * preconditioner is the ILU(0) of the matrix with every block that couples
+ * two different subdomains removed, i.e. each subdomain's own ILU(0); the
+ * matrix products of the solver still use the whole matrix.  The paper keeps
+ * strongly coupled cells in one subdomain: boxes spanning whole columns
+ * (bz = nz) suit layered models, whose vertical transmissibilities are the
+ * largest.  Host arrays, filled by opm_topology_build_blocks. */
+typedef struct opm_ilu_blocks {
+  int32_t bx, by, bz;       /* in: subdomain box, cells per axis (each >= 1; a box
+                               longer than the grid spans the whole axis)        */
+  int32_t* sub_level_ptr;   /* out [n_levels * (n_sub + 1)]: the rows of subdomain
+                               s on level l are the positions
+                               [sub_level_ptr[l (n_sub+1) + s], ... + s + 1)     */
+  int32_t* slot;            /* out [n_cells] by position: index of the row inside
+                               its subdomain, counting the subdomain's rows level
+                               by level                                          */
+  int32_t n_sub;            /* out: subdomains holding active cells              */
+  int32_t max_sub;          /* out: most rows of one subdomain                   */
+  int32_t max_width;        /* out: most rows of one subdomain on one level      */
+} opm_ilu_blocks;
+
+/* Number of nonempty subdomains and of levels of a partition (host): size
+ * sub_level_ptr as n_levels * (n_sub + 1).  OPM_EINVAL for non-positive
+ * sizes. */
+int opm_ilu_blocks_count(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask, int32_t bx,
+                         int32_t by, int32_t bz, int32_t* n_sub, int32_t* n_levels);
+/* opm_topology_build for the block ILU0 of a partition (host, synchronous).
+ * Connectivity and block-CSR pattern are those of opm_topology_build.  The
+ * levels are the local hyperplanes (i mod bx) + (j mod by) + (k mod bz) that
+ * hold active cells; inside a level the rows are grouped by subdomain
+ * (positions ordered by level, subdomain, cell).  The ILU neighbour lists
+ * (lo_*, up_*) hold only neighbours in the same subdomain, so every ILU(0)
+ * factorisation and sweep of the library computes the block ILU0 on such a
+ * topology.  OPM_EINVAL on a NULL array or non-positive box size. */
+int opm_topology_build_blocks(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask,
+                              opm_ilu_blocks* blocks, opm_topology* topo);
+
 /* Transmissibility, pore volume and depth (appendix B; sec. 2.1.4), device:
  * T_ij = t_ij t_ji / (t_ij + t_ji) with half-transmissibilities
  * t = |F| k / (d/2) of the axis-aligned cells, k = perm_h for x/y faces and
@@ -180,6 +221,13 @@ typedef struct opm_problem {
   const double* conn_bhp;       /* [n_conns] BHP target (producers)           */
   opm_fluid fluid;
   int32_t sweep_span;           /* opm_topology.sweep_span                    */
+  /* block ILU0 (topology from opm_topology_build_blocks); n_sub = 0 for the
+   * single-block ILU(0) of opm_topology_build, the rest then unused */
+  int32_t n_sub;                /* opm_ilu_blocks.n_sub                       */
+  int32_t max_sub;              /* opm_ilu_blocks.max_sub                     */
+  int32_t max_width;            /* opm_ilu_blocks.max_width                   */
+  const int32_t* sub_level_ptr; /* [n_levels*(n_sub+1)] device copy          */
+  const int32_t* slot;          /* [n_cells] device copy                      */
 } opm_problem;
 
 /* Library set-up: checks that the current device is a gfx950 (MI355X) and
@@ -503,7 +551,10 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
  * results beyond round-off.  Returns OPM_OK, or OPM_EINVAL for an unknown
  * option or value.
  *   OPM_OPT_SWEEP_MODE: ILU(0) factor/sweep launch shape: -1 automatic,
- *     0 one workgroup walks all levels, 1 one launch per level.
+ *     0 one workgroup walks all levels, 1 one launch per level, 2 (block
+ *     ILU0 topologies; else automatic) one workgroup per subdomain, also
+ *     for a single subdomain.  Automatic picks 2 for a block ILU0 topology
+ *     of two or more subdomains whose subdomain vector fits in LDS.
  *   OPM_OPT_KRYLOV_CHUNK: BiCGStab iterations enqueued between reads of the
  *     convergence state (0 automatic, else >= 1).
  *   OPM_OPT_SWEEP_KERNEL: the one-workgroup LDS-ring sweep: 0 automatic,

@@ -43,6 +43,7 @@ constexpr int kFacThreads = 256;       // threads of the one-workgroup factorisa
 constexpr int kMaxWindowRows = 2048;   // widest level served by the one-workgroup sweep
 constexpr int kMaxFactorWindowRows = 640;
 constexpr size_t kMaxRingBytes = 128 * 1024;   // LDS budget of the sweep ring
+constexpr size_t kMaxBlockLds = 150 * 1024;    // LDS budget of a block-ILU0 workgroup
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pack(Topo t, const double* J, IluView<T> v) {
@@ -136,7 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_rhs(int n, const int32_t* per
 // forward record holds the lower blocks and D^{-1}, the backward one the
 // upper blocks and D^{-1}, each with the neighbour positions and the row.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pack_records(Topo t, IluView<T> v) {
+__global__ __launch_bounds__(kBlock) void k_pack_records(Topo t, IluView<T> v,
+                                                         const int32_t* slot) {
   const int pos = blockIdx.x * kBlock + threadIdx.x;
   if (pos >= t.n) return;
   constexpr size_t kV = 16 / sizeof(T);
@@ -148,8 +150,224 @@ __global__ __launch_bounds__(kBlock) void k_pack_records(Topo t, IluView<T> v) {
     v.rec_b[a] = e < 27 ? v.upv[e * ns + p] : v.dinv[(e - 27) * ns + p];
   }
   const int cell = t.perm[pos];
-  v.idx_f[pos] = int4v{t.lo_pos[3 * p], t.lo_pos[3 * p + 1], t.lo_pos[3 * p + 2], cell};
-  v.idx_b[pos] = int4v{t.up_pos[3 * p], t.up_pos[3 * p + 1], t.up_pos[3 * p + 2], cell};
+  // neighbours by level position, or (block ILU0) by slot in the subdomain
+  auto nb = [&](int kp) { return kp < 0 || slot == nullptr ? kp : slot[kp]; };
+  v.idx_f[pos] = int4v{nb(t.lo_pos[3 * p]), nb(t.lo_pos[3 * p + 1]), nb(t.lo_pos[3 * p + 2]), cell};
+  v.idx_b[pos] = int4v{nb(t.up_pos[3 * p]), nb(t.up_pos[3 * p + 1]), nb(t.up_pos[3 * p + 2]), cell};
+}
+
+// ------------------------------------------------------------ block ILU0
+// One workgroup per subdomain (the blocks of the block ILU0 are independent,
+// so the whole factorisation and each whole preconditioner solve are one
+// launch).  Inside a subdomain the rows go level by level with workgroup
+// barriers.  The rows of subdomain s on level l are the positions
+// [slp[l (nsub+1) + s], slp[l (nsub+1) + s + 1]).
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_factor_blocks(Topo t, const double* J, IluView<T> v,
+                                                       const int32_t* slp, int nsub,
+                                                       int32_t* status) {
+  const int s = blockIdx.x;
+  for (int l = 0; l < t.nlev; ++l) {
+    const int p0 = slp[(size_t)l * (nsub + 1) + s], p1 = slp[(size_t)l * (nsub + 1) + s + 1];
+    for (int pos = p0 + (int)threadIdx.x; pos < p1; pos += NT) {
+      FacJob j;
+      load_fac(t, J, pos, j);
+      double inv[9];
+      // D_k^{-1} of the previous level, written by this workgroup before
+      // the barrier
+      finish_fac<T>(j, pos, v,
+                    [&](int kp, double* Dk) {
+#pragma unroll
+                      for (int e = 0; e < 9; ++e) Dk[e] = v.dinv64[(size_t)e * v.ns + kp];
+                    },
+                    status, inv);
+    }
+    __syncthreads();
+  }
+}
+
+// Sweep data of one row of a subdomain: the record (blocks, D^{-1}) of its
+// level position, the slots of its neighbours and its cell; the forward
+// right-hand side r of its cell, the backward one y from the LDS vector.
+template <typename T>
+struct BlockJob {
+  T a[27];
+  T D[9];
+  T rhs[3];
+  int kp[3];   // neighbour slots (-1 if absent)
+  int cell;
+  int slot;
+  bool live;
+};
+
+template <typename T, bool FWD>
+__device__ __forceinline__ void block_fetch(IluView<T> v, const double* r, const T* zl,
+                                            const int* lp, int nlev, int k, int base,
+                                            BlockJob<T>& j) {
+  typedef typename Vec16<T>::type V;
+  constexpr unsigned kV = 16 / sizeof(T);
+  const int kk = k < nlev ? k : nlev - 1;
+  const int l = FWD ? kk : nlev - 1 - kk;
+  const int p0 = lp[2 * l], p1 = lp[2 * l + 1];
+  j.live = k < nlev && p0 + (int)threadIdx.x < p1;
+  // a wavefront without a row on the level loads nothing (also when the
+  // subdomain has no row there at all, p0 == p1)
+  if (__builtin_amdgcn_readfirstlane(p0 + (int)(threadIdx.x & ~63u)) >= p1) return;
+  const int pos = min(p0 + (int)threadIdx.x, p1 - 1);
+  const unsigned ns = (unsigned)v.ns, up = (unsigned)pos;
+  const int4v ix = (FWD ? v.idx_f : v.idx_b)[up];
+  j.kp[0] = ix.x;
+  j.kp[1] = ix.y;
+  j.kp[2] = ix.z;
+  j.cell = ix.w;
+  j.slot = (FWD ? base : base - (p1 - p0)) + (pos - p0);
+  const V* rec = reinterpret_cast<const V*>(FWD ? v.rec_f : v.rec_b);
+#pragma unroll
+  for (unsigned c = 0; c < (unsigned)kRecValues / kV; ++c) {
+    const V w = rec[c * ns + up];
+#pragma unroll
+    for (unsigned q = 0; q < kV; ++q) {
+      const unsigned e = c * kV + q;
+      if (e < 27u)
+        j.a[e] = w[q];
+      else
+        j.D[e - 27u] = w[q];
+    }
+  }
+  if (FWD) {
+#pragma unroll
+    for (unsigned c = 0; c < 3; ++c) j.rhs[c] = (T)r[3u * (unsigned)j.cell + c];
+  } else {
+#pragma unroll
+    for (unsigned c = 0; c < 3; ++c) j.rhs[c] = zl[3u * (unsigned)j.slot + c];
+  }
+}
+
+// The arithmetic of a sweep row, in the same order as the other sweep
+// kernels (results are bitwise equal).
+template <typename T, bool FWD>
+__device__ __forceinline__ void block_row(const BlockJob<T>& j, T* zl, double* x) {
+  if (!j.live) return;
+  T acc[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) acc[c] = FWD ? j.rhs[c] : (T)0;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int kp = j.kp[s];
+    const bool has = kp >= 0;
+    const T* w = zl + 3u * (unsigned)(has ? kp : 0);
+    const T x0 = has ? w[0] : (T)0, x1 = has ? w[1] : (T)0, x2 = has ? w[2] : (T)0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T t = j.a[9 * s + 3 * a] * x0 + j.a[9 * s + 3 * a + 1] * x1 +
+                  j.a[9 * s + 3 * a + 2] * x2;
+      acc[a] = FWD ? acc[a] - t : acc[a] + t;
+    }
+  }
+  T out[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T d = j.D[3 * a] * acc[0] + j.D[3 * a + 1] * acc[1] + j.D[3 * a + 2] * acc[2];
+    out[a] = FWD ? d : j.rhs[a] - d;
+  }
+  T* w = zl + 3u * (unsigned)j.slot;
+#pragma unroll
+  for (unsigned c = 0; c < 3; ++c) w[c] = out[c];
+  if (!FWD) {
+#pragma unroll
+    for (unsigned c = 0; c < 3; ++c) x[3u * (unsigned)j.cell + c] = (double)out[c];
+  }
+}
+
+// Rows of a level beyond the first NT (subdomains with wider levels).
+template <typename T, int NT, bool FWD>
+__device__ __forceinline__ void block_extra(IluView<T> v, const double* r, T* zl, double* x,
+                                            const int* lp, int nlev, int k, int base) {
+  const int l = FWD ? k : nlev - 1 - k;
+  const int p0 = lp[2 * l], p1 = lp[2 * l + 1];
+  const int b0 = FWD ? base : base - (p1 - p0);
+  for (int pos = p0 + NT + (int)threadIdx.x; pos < p1; pos += NT) {
+    BlockJob<T> j;
+    const unsigned ns = (unsigned)v.ns, up = (unsigned)pos;
+    typedef typename Vec16<T>::type V;
+    constexpr unsigned kV = 16 / sizeof(T);
+    const int4v ix = (FWD ? v.idx_f : v.idx_b)[up];
+    j.kp[0] = ix.x;
+    j.kp[1] = ix.y;
+    j.kp[2] = ix.z;
+    j.cell = ix.w;
+    j.slot = b0 + (pos - p0);
+    j.live = true;
+    const V* rec = reinterpret_cast<const V*>(FWD ? v.rec_f : v.rec_b);
+#pragma unroll
+    for (unsigned c = 0; c < (unsigned)kRecValues / kV; ++c) {
+      const V w = rec[c * ns + up];
+#pragma unroll
+      for (unsigned q = 0; q < kV; ++q) {
+        const unsigned e = c * kV + q;
+        if (e < 27u)
+          j.a[e] = w[q];
+        else
+          j.D[e - 27u] = w[q];
+      }
+    }
+#pragma unroll
+    for (unsigned c = 0; c < 3; ++c)
+      j.rhs[c] = FWD ? (T)r[3u * (unsigned)j.cell + c] : zl[3u * (unsigned)j.slot + c];
+    block_row<T, FWD>(j, zl, x);
+  }
+}
+
+template <typename T, int NT, bool FWD, bool WIDE>
+__device__ __forceinline__ void block_sweep(IluView<T> v, const double* r, T* zl, double* x,
+                                            const int* lp, int nlev, int nrows) {
+  // base: rows of the subdomain before the level (forward), or up to and
+  // including it (backward)
+  auto width = [&](int k) {
+    const int l = FWD ? k : nlev - 1 - k;
+    return lp[2 * l + 1] - lp[2 * l];
+  };
+  int base = FWD ? 0 : nrows;
+  BlockJob<T> ja, jb;
+  block_fetch<T, FWD>(v, r, zl, lp, nlev, 0, base, ja);
+  for (int k = 0; k < nlev; k += 2) {
+    const int b1 = FWD ? base + width(k) : base - width(k);
+    block_fetch<T, FWD>(v, r, zl, lp, nlev, k + 1, b1, jb);
+    block_row<T, FWD>(ja, zl, x);
+    if (WIDE) block_extra<T, NT, FWD>(v, r, zl, x, lp, nlev, k, base);
+    __syncthreads();
+    if (k + 1 >= nlev) break;
+    base = b1;
+    const int b2 = FWD ? base + width(k + 1) : base - width(k + 1);
+    block_fetch<T, FWD>(v, r, zl, lp, nlev, k + 2, b2, ja);
+    block_row<T, FWD>(jb, zl, x);
+    if (WIDE) block_extra<T, NT, FWD>(v, r, zl, x, lp, nlev, k + 1, base);
+    __syncthreads();
+    base = b2;
+  }
+}
+
+// x = M^{-1} r for the block ILU0: forward then backward sweep of one
+// subdomain per workgroup, the subdomain's y and x in LDS (3 values per
+// row, by slot), then the level bounds of the subdomain (2 ints per level).
+template <typename T, int NT, bool WIDE>
+__global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t* slp, int nsub,
+                                                      int nlev, int max_sub, const double* r,
+                                                      double* x, const int32_t* skip) {
+  if (skip && *skip != 0) return;
+  extern __shared__ unsigned char smem[];
+  T* zl = reinterpret_cast<T*>(smem);
+  int* lp = reinterpret_cast<int*>(smem + sizeof(T) * 3 * (size_t)max_sub);
+  const int s = blockIdx.x;
+  for (int l = threadIdx.x; l < nlev; l += NT) {
+    lp[2 * l] = slp[(size_t)l * (nsub + 1) + s];
+    lp[2 * l + 1] = slp[(size_t)l * (nsub + 1) + s + 1];
+  }
+  __syncthreads();
+  int nrows = 0;
+  for (int l = 0; l < nlev; ++l) nrows += lp[2 * l + 1] - lp[2 * l];
+  block_sweep<T, NT, true, WIDE>(v, r, zl, x, lp, nlev, nrows);
+  block_sweep<T, NT, false, WIDE>(v, r, zl, x, lp, nlev, nrows);
 }
 
 // Both sweeps by one workgroup of NT threads through the LDS ring with
@@ -182,7 +400,9 @@ size_t apply_lds(const opm_problem* pb) {
 
 size_t factor_lds(const opm_problem* pb) { return sizeof(double) * 2 * 9 * (size_t)pb->max_level; }
 
-bool g_lds_attr_set[32] = {};
+// one flag per (kernel, precision): slots 0-5 level-window kernels, 12-21
+// (FP64) and 24-33 (FP32) ring sweeps, 40-43 (FP64) and 44-47 (FP32) block ILU0
+bool g_lds_attr_set[48] = {};
 
 template <typename K>
 int allow_lds(K kernel, int slot) {
@@ -194,6 +414,17 @@ int allow_lds(K kernel, int slot) {
   return OPM_OK;
 }
 
+// Threads of a block-ILU0 workgroup: the widest level of a subdomain
+// rounded up to a wavefront, at most 256 (wider levels loop).
+int block_threads(const opm_problem* pb) {
+  return pb->max_width <= 64 ? 64 : pb->max_width <= 128 ? 128 : 256;
+}
+
+template <typename T>
+size_t block_lds(const opm_problem* pb) {
+  return sizeof(T) * 3 * (size_t)pb->max_sub + sizeof(int) * 2 * (size_t)pb->n_levels;
+}
+
 template <typename T>
 int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* status, int mode,
                 hipStream_t s) {
@@ -201,6 +432,25 @@ int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* stat
   Topo t = topo_of(pb);
   hipLaunchKernelGGL(k_pack<T>, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock), 0, s, t, J,
                      v);
+  if (mode == 2) {   // block ILU0: one workgroup per subdomain
+    switch (block_threads(pb)) {
+      case 64:
+        hipLaunchKernelGGL((k_factor_blocks<T, 64>), dim3(pb->n_sub), dim3(64), 0, s, t, J, v,
+                           pb->sub_level_ptr, pb->n_sub, status);
+        break;
+      case 128:
+        hipLaunchKernelGGL((k_factor_blocks<T, 128>), dim3(pb->n_sub), dim3(128), 0, s, t, J, v,
+                           pb->sub_level_ptr, pb->n_sub, status);
+        break;
+      default:
+        hipLaunchKernelGGL((k_factor_blocks<T, 256>), dim3(pb->n_sub), dim3(256), 0, s, t, J, v,
+                           pb->sub_level_ptr, pb->n_sub, status);
+    }
+    hipLaunchKernelGGL(k_pack_records<T>, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock), 0,
+                       s, t, v, pb->slot);
+    OPM_TRY_HIP(hipGetLastError());
+    return OPM_OK;
+  }
   if (mode == 0) {
     if (pb->max_level <= kMaxFactorWindowRows) {
       OPM_TRY(allow_lds(k_factor_wg<T, true>, sizeof(T) == 8 ? 0 : 1));
@@ -213,7 +463,7 @@ int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* stat
     // the record sweep's copy of the factors (whenever a ring sweep can run)
     if (sizeof(T) * 3 * (size_t)ring_rows(pb->sweep_span, pb->max_level) <= kMaxRingBytes)
       hipLaunchKernelGGL(k_pack_records<T>, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock),
-                         0, s, t, v);
+                         0, s, t, v, nullptr);
     OPM_TRY_HIP(hipGetLastError());
     return OPM_OK;
   }
@@ -231,6 +481,30 @@ int apply_impl(const opm_problem* pb, void* ilu, const double* r, double* x, int
                hipStream_t s, const int32_t* skip) {
   IluView<T> v = view<T>(pb, ilu);
   Topo t = topo_of(pb);
+  if (mode == 2) {
+    const size_t lds = block_lds<T>(pb);
+    const int slot = sizeof(T) == 8 ? 40 : 44;
+#define OPM_BLOCKS(NT)                                                                           \
+  do {                                                                                           \
+    if (pb->max_width <= NT) {                                                                   \
+      OPM_TRY(allow_lds(k_apply_blocks<T, NT, false>, slot + (NT == 64 ? 0 : NT == 128 ? 1 : 2))); \
+      hipLaunchKernelGGL((k_apply_blocks<T, NT, false>), dim3(pb->n_sub), dim3(NT), lds, s, v,   \
+                         pb->sub_level_ptr, pb->n_sub, pb->n_levels, pb->max_sub, r, x, skip);   \
+    } else {                                                                                     \
+      OPM_TRY(allow_lds(k_apply_blocks<T, NT, true>, slot + 3));                                 \
+      hipLaunchKernelGGL((k_apply_blocks<T, NT, true>), dim3(pb->n_sub), dim3(NT), lds, s, v,    \
+                         pb->sub_level_ptr, pb->n_sub, pb->n_levels, pb->max_sub, r, x, skip);   \
+    }                                                                                            \
+  } while (0)
+    switch (block_threads(pb)) {
+      case 64: OPM_BLOCKS(64); break;
+      case 128: OPM_BLOCKS(128); break;
+      default: OPM_BLOCKS(256); break;
+    }
+#undef OPM_BLOCKS
+    OPM_TRY_HIP(hipGetLastError());
+    return OPM_OK;
+  }
   if (mode == 0) {
     const int ring = ring_rows(pb->sweep_span, pb->max_level);
     const size_t ring_bytes = sizeof(T) * 3 * (size_t)ring;
@@ -308,17 +582,25 @@ int g_sweep_mode = -1;
 // threads with idle wavefronts skipping their loads)
 int g_sweep_kernel = 0;
 
-int sweep_mode(const opm_problem* pb) {
+// A block-ILU0 topology runs one workgroup per subdomain whenever the
+// subdomain's vector fits in LDS; modes 0 and 1 also serve it (same
+// factors and sweeps, level by level over the whole system).
+int sweep_mode(const opm_problem* pb, int precision) {
   if (g_sweep_mode == 0 || g_sweep_mode == 1) {
     if (g_sweep_mode == 0 && pb->max_level > kMaxWindowRows) return 1;
     return g_sweep_mode;
   }
+  if (pb->n_sub > 0 && pb->sub_level_ptr && pb->slot &&
+      (pb->n_sub > 1 || g_sweep_mode == 2) &&
+      (precision == OPM_PREC_MIXED ? block_lds<float>(pb) : block_lds<double>(pb)) <=
+          kMaxBlockLds)
+    return 2;
   return pb->max_level <= kMaxWindowRows && pb->n_cells <= 200000 ? 0 : 1;
 }
 
 int ilu_factor(const opm_problem* pb, const double* J, void* ilu, int precision, int32_t* status,
                hipStream_t s) {
-  const int mode = sweep_mode(pb);
+  const int mode = sweep_mode(pb, precision);
   if (precision == OPM_PREC_MIXED) return factor_impl<float>(pb, J, ilu, status, mode, s);
   return factor_impl<double>(pb, J, ilu, status, mode, s);
 }
@@ -326,7 +608,7 @@ int ilu_factor(const opm_problem* pb, const double* J, void* ilu, int precision,
 // skip (device, may be null): the sweeps return at once while *skip != 0.
 int ilu_apply(const opm_problem* pb, void* ilu, int precision, const double* r, double* x,
               hipStream_t s, const int32_t* skip) {
-  const int mode = sweep_mode(pb);
+  const int mode = sweep_mode(pb, precision);
   if (precision == OPM_PREC_MIXED) return apply_impl<float>(pb, ilu, r, x, mode, s, skip);
   return apply_impl<double>(pb, ilu, r, x, mode, s, skip);
 }

@@ -18,7 +18,7 @@ namespace opm {
 
 int ilu_apply(const opm_problem* pb, void* ilu, int precision, const double* r, double* x,
               hipStream_t s, const int32_t* skip);
-int sweep_mode(const opm_problem* pb);
+int sweep_mode(const opm_problem* pb, int precision = OPM_PREC_FP64);
 
 namespace {
 
@@ -293,7 +293,7 @@ int g_krylov_chunk = 0;
 
 int chunk_size(const opm_problem* pb) {
   if (g_krylov_chunk > 0) return g_krylov_chunk;
-  return sweep_mode(pb) == 0 ? 6 : 3;
+  return sweep_mode(pb) == 1 ? 3 : 6;
 }
 
 size_t krylov_bytes(const opm_problem* pb) {

@@ -317,7 +317,7 @@ int opm_init(void) {
 int opm_set_option(int option, int value) {
   switch (option) {
     case OPM_OPT_SWEEP_MODE:
-      if (value < -1 || value > 1) return OPM_EINVAL;
+      if (value < -1 || value > 2) return OPM_EINVAL;
       g_sweep_mode = value;
       return OPM_OK;
     case OPM_OPT_KRYLOV_CHUNK:

@@ -40,8 +40,101 @@ extern "C" int opm_topology_count(int32_t nx, int32_t ny, int32_t nz, const uint
   return OPM_OK;
 }
 
+namespace {
+
+// Subdomain boxes of the block ILU0 (paper sec. 2.5: one block per process):
+// box (i / bx, j / by, k / bz); boxes without active cells are dropped and
+// the others numbered densely in box order.  Level of a cell: the local
+// hyperplane (i mod bx) + (j mod by) + (k mod bz), densely numbered over the
+// values that hold cells, so every lower neighbour inside the subdomain lies
+// on the previous level.
+struct Blocking {
+  int bx, by, bz;
+  std::vector<int32_t> sub;   // [n] dense subdomain of each cell
+  int32_t n_sub = 0;
+};
+
+int blocking_of(int nx, int ny, int nz, const uint8_t* mask, int bx, int by, int bz,
+                Blocking& B) {
+  if (bx <= 0 || by <= 0 || bz <= 0) return OPM_EINVAL;
+  // a box longer than the grid is the whole axis
+  bx = std::min(bx, nx);
+  by = std::min(by, ny);
+  bz = std::min(bz, nz);
+  B.bx = bx;
+  B.by = by;
+  B.bz = bz;
+  const long nbx = (nx + bx - 1) / bx, nby = (ny + by - 1) / by, nbz = (nz + bz - 1) / bz;
+  std::vector<int32_t> box_sub(nbx * nby * nbz, -1);
+  B.sub.clear();
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const long b = i + (long)nx * (j + (long)ny * k);
+        if (!active(mask, b)) continue;
+        const long q = i / bx + nbx * (j / by + nby * (k / bz));
+        box_sub[q] = 0;
+      }
+  B.n_sub = 0;
+  for (auto& q : box_sub)
+    if (q == 0) q = B.n_sub++;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const long b = i + (long)nx * (j + (long)ny * k);
+        if (active(mask, b)) B.sub.push_back(box_sub[i / bx + nbx * (j / by + nby * (k / bz))]);
+      }
+  return OPM_OK;
+}
+
+int build(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask, const Blocking* B,
+          opm_ilu_blocks* blk, opm_topology* t);
+
+}  // namespace
+
 extern "C" int opm_topology_build(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask,
                                   opm_topology* t) {
+  return build(nx, ny, nz, mask, nullptr, nullptr, t);
+}
+
+extern "C" int opm_ilu_blocks_count(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask,
+                                    int32_t bx, int32_t by, int32_t bz, int32_t* n_sub,
+                                    int32_t* n_levels) {
+  int32_t n = 0, nf = 0;
+  int st = opm_topology_count(nx, ny, nz, mask, &n, &nf);
+  if (st != OPM_OK) return st;
+  if (!n_sub || !n_levels) return OPM_EINVAL;
+  Blocking B;
+  st = blocking_of(nx, ny, nz, mask, bx, by, bz, B);
+  if (st != OPM_OK) return st;
+  std::vector<char> h((size_t)B.bx + B.by + B.bz, 0);
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i)
+        if (active(mask, i + (long)nx * (j + (long)ny * k))) h[i % B.bx + j % B.by + k % B.bz] = 1;
+  int32_t nl = 0;
+  for (char c : h) nl += c;
+  *n_sub = B.n_sub;
+  *n_levels = nl;
+  return OPM_OK;
+}
+
+extern "C" int opm_topology_build_blocks(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask,
+                                         opm_ilu_blocks* blk, opm_topology* t) {
+  if (!blk || !blk->sub_level_ptr || !blk->slot) return OPM_EINVAL;
+  int32_t n = 0, nf = 0;
+  int st = opm_topology_count(nx, ny, nz, mask, &n, &nf);
+  if (st != OPM_OK) return st;
+  Blocking B;
+  st = blocking_of(nx, ny, nz, mask, blk->bx, blk->by, blk->bz, B);
+  if (st != OPM_OK) return st;
+  return build(nx, ny, nz, mask, &B, blk, t);
+}
+
+namespace {
+
+int build(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask, const Blocking* B,
+          opm_ilu_blocks* blk, opm_topology* t) {
   int32_t n = 0, nf = 0;
   int st = opm_topology_count(nx, ny, nz, mask, &n, &nf);
   if (st != OPM_OK) return st;
@@ -111,48 +204,78 @@ extern "C" int opm_topology_build(int32_t nx, int32_t ny, int32_t nz, const uint
   // i.e. on the previous level, so rows of one level are independent and a
   // sweep needs the values of two consecutive levels only (on a masked grid
   // the as-soon-as-possible schedule would put neighbours many levels apart).
-  std::vector<int32_t> level(n, 0), hmap(nx + ny + nz, -1);
-  for (int32_t ci = 0; ci < n; ++ci) {
-    const int32_t b = t->cell_box[ci];
-    hmap[b % nx + (b / nx) % ny + b / (nx * ny)] = 0;
-  }
+  // With subdomains: the local hyperplanes, and inside a level the rows
+  // grouped by subdomain (positions ordered by level, subdomain, cell).
+  const int hx = B ? B->bx : nx, hy = B ? B->by : ny, hz = B ? B->bz : nz;
+  const int32_t nsub = B ? B->n_sub : 1;
+  auto hyper = [&](int32_t b) { return b % nx % hx + (b / nx) % ny % hy + b / (nx * ny) % hz; };
+  auto sub_of = [&](int32_t ci) { return B ? B->sub[ci] : 0; };
+  std::vector<int32_t> level(n, 0), hmap((size_t)hx + hy + hz, -1);
+  for (int32_t ci = 0; ci < n; ++ci) hmap[hyper(t->cell_box[ci])] = 0;
   int32_t nlev = 0;
   for (auto& h : hmap)
     if (h == 0) h = nlev++;
-  for (int32_t ci = 0; ci < n; ++ci) {
-    const int32_t b = t->cell_box[ci];
-    level[ci] = hmap[b % nx + (b / nx) % ny + b / (nx * ny)];
+  for (int32_t ci = 0; ci < n; ++ci) level[ci] = hmap[hyper(t->cell_box[ci])];
+  // counting sort over the key (level, subdomain)
+  std::vector<int32_t> cnt((size_t)nlev * nsub + 1, 0);
+  for (int32_t ci = 0; ci < n; ++ci) cnt[(size_t)level[ci] * nsub + sub_of(ci) + 1]++;
+  int32_t mw = 0;
+  for (size_t q = 0; q + 1 < cnt.size(); ++q) {
+    mw = std::max(mw, cnt[q + 1]);
+    cnt[q + 1] += cnt[q];
   }
-  std::vector<int32_t> cnt(nlev + 1, 0);
-  for (int32_t ci = 0; ci < n; ++ci) cnt[level[ci] + 1]++;
   int32_t mx = 0;
-  for (int32_t l = 0; l < nlev; ++l) {
-    mx = std::max(mx, cnt[l + 1]);
-    cnt[l + 1] += cnt[l];
+  for (int32_t l = 0; l <= nlev; ++l) t->level_ptr[l] = cnt[(size_t)l * nsub];
+  for (int32_t l = 0; l < nlev; ++l) mx = std::max(mx, t->level_ptr[l + 1] - t->level_ptr[l]);
+  if (B) {
+    for (int32_t l = 0; l < nlev; ++l)
+      for (int32_t sb = 0; sb <= nsub; ++sb)
+        blk->sub_level_ptr[(size_t)l * (nsub + 1) + sb] = cnt[(size_t)l * nsub + sb];
   }
-  for (int32_t l = 0; l <= nlev; ++l) t->level_ptr[l] = cnt[l];
-  for (int32_t ci = 0; ci < n; ++ci) {   // ascending cell order within a level
-    int32_t pos = cnt[level[ci]]++;
+  std::vector<int32_t> start(cnt.begin(), cnt.end() - 1);
+  for (int32_t ci = 0; ci < n; ++ci) {   // ascending cell order within a key
+    int32_t pos = start[(size_t)level[ci] * nsub + sub_of(ci)]++;
     t->perm[pos] = ci;
     t->iperm[ci] = pos;
   }
+  if (B) {
+    // slot: index of a row inside its subdomain (levels ascending)
+    std::vector<int32_t> fill(nsub, 0);
+    int32_t ms = 0;
+    for (int32_t l = 0; l < nlev; ++l)
+      for (int32_t sb = 0; sb < nsub; ++sb) {
+        const int32_t p0 = cnt[(size_t)l * nsub + sb], p1 = cnt[(size_t)l * nsub + sb + 1];
+        for (int32_t pos = p0; pos < p1; ++pos) blk->slot[pos] = fill[sb] + (pos - p0);
+        fill[sb] += p1 - p0;
+        ms = std::max(ms, fill[sb]);
+      }
+    blk->n_sub = nsub;
+    blk->max_sub = ms;
+    blk->max_width = mw;
+  }
+  // neighbour lists of the ILU structure: with subdomains, only neighbours
+  // in the same subdomain (the couplings between subdomains are dropped)
   for (int32_t pos = 0; pos < n; ++pos) {
     int32_t ci = t->perm[pos];
     int32_t s = 0;
-    for (int32_t r = t->row_ptr[ci]; r < t->diag_pos[ci]; ++r, ++s) {
+    for (int32_t r = t->row_ptr[ci]; r < t->diag_pos[ci]; ++r) {
       int32_t kc = t->col_idx[r];
+      if (sub_of(kc) != sub_of(ci)) continue;
       t->lo_blk[3 * pos + s] = r;
       t->lo_pos[3 * pos + s] = t->iperm[kc];
       int32_t tb = -1;   // block (k, i) in row k
       for (int32_t r2 = t->diag_pos[kc] + 1; r2 < t->row_ptr[kc + 1]; ++r2)
         if (t->col_idx[r2] == ci) tb = r2;
       t->lo_tblk[3 * pos + s] = tb;
+      ++s;
     }
     for (; s < 3; ++s) t->lo_blk[3 * pos + s] = t->lo_tblk[3 * pos + s] = t->lo_pos[3 * pos + s] = -1;
     s = 0;
-    for (int32_t r = t->diag_pos[ci] + 1; r < t->row_ptr[ci + 1]; ++r, ++s) {
+    for (int32_t r = t->diag_pos[ci] + 1; r < t->row_ptr[ci + 1]; ++r) {
+      if (sub_of(t->col_idx[r]) != sub_of(ci)) continue;
       t->up_blk[3 * pos + s] = r;
       t->up_pos[3 * pos + s] = t->iperm[t->col_idx[r]];
+      ++s;
     }
     for (; s < 3; ++s) t->up_blk[3 * pos + s] = t->up_pos[3 * pos + s] = -1;
   }
@@ -167,6 +290,8 @@ extern "C" int opm_topology_build(int32_t nx, int32_t ny, int32_t nz, const uint
   t->sweep_span = span;
   return OPM_OK;
 }
+
+}  // namespace
 
 extern "C" int opm_well_groups(int32_t n_cells, int32_t n_conns, const int32_t* conn_cell,
                                int32_t* cell_conn_ptr, int32_t* cell_conn) {

@@ -11,7 +11,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Optional
+from typing import Optional, Sequence
 
 import numpy as np
 import torch
@@ -43,6 +43,11 @@ class Topology(ctypes.Structure):
         ("n_levels", _i32), ("max_level", _i32), ("sweep_span", _i32)]
 
 
+class IluBlocks(ctypes.Structure):
+    _fields_ = [("bx", _i32), ("by", _i32), ("bz", _i32), ("sub_level_ptr", _ip), ("slot", _ip),
+                ("n_sub", _i32), ("max_sub", _i32), ("max_width", _i32)]
+
+
 class Problem(ctypes.Structure):
     _fields_ = [("n_cells", _i32), ("n_faces", _i32), ("nnzb", _i32), ("n_levels", _i32),
                 ("max_level", _i32), ("n_conns", _i32),
@@ -52,7 +57,9 @@ class Problem(ctypes.Structure):
                 ("iperm", _vp), ("lo_blk", _vp), ("lo_tblk", _vp), ("lo_pos", _vp),
                 ("up_blk", _vp), ("up_pos", _vp), ("cell_conn_ptr", _vp), ("cell_conn", _vp),
                 ("conn_kind", _vp), ("conn_phase", _vp), ("conn_wi", _vp), ("conn_rate", _vp),
-                ("conn_bhp", _vp), ("fluid", Fluid), ("sweep_span", _i32)]
+                ("conn_bhp", _vp), ("fluid", Fluid), ("sweep_span", _i32),
+                ("n_sub", _i32), ("max_sub", _i32), ("max_width", _i32),
+                ("sub_level_ptr", _vp), ("slot", _vp)]
 
 
 class SolveReport(ctypes.Structure):
@@ -80,7 +87,8 @@ class NewtonReport(ctypes.Structure):
 
 
 EXPORTS = [
-    "opm_init", "opm_strerror", "opm_topology_count", "opm_topology_build", "opm_geometry",
+    "opm_init", "opm_strerror", "opm_topology_count", "opm_topology_build",
+    "opm_ilu_blocks_count", "opm_topology_build_blocks", "opm_geometry",
     "opm_well_index", "opm_well_groups", "opm_accumulation", "opm_norms_bytes", "opm_assemble",
     "opm_ilu0_bytes", "opm_ilu0_factor", "opm_ilu0_apply", "opm_spmv", "opm_krylov_bytes",
     "opm_bicgstab", "opm_newton_bytes", "opm_newton_step", "opm_advance", "opm_set_option",
@@ -118,6 +126,9 @@ def lib():
         L.opm_set_option.argtypes = [ctypes.c_int, ctypes.c_int]
         L.opm_topology_count.argtypes = [_i32, _i32, _i32, _vp, _ip, _ip]
         L.opm_topology_build.argtypes = [_i32, _i32, _i32, _vp, ctypes.POINTER(Topology)]
+        L.opm_ilu_blocks_count.argtypes = [_i32, _i32, _i32, _vp, _i32, _i32, _i32, _ip, _ip]
+        L.opm_topology_build_blocks.argtypes = [_i32, _i32, _i32, _vp, ctypes.POINTER(IluBlocks),
+                                                ctypes.POINTER(Topology)]
         L.opm_geometry.argtypes = [_i32, _i32, _i32, ctypes.c_double, ctypes.c_double, _vp, _vp,
                                    ctypes.c_double, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
                                    _vp, _vp]
@@ -191,28 +202,57 @@ def default_opts(case=None, precision=PREC_FP64, **kw) -> NewtonOpts:
     return o
 
 
-class GpuModel:
-    """A case laid out on the GPU: topology, geometry and wells on device."""
+def build_topology(nx: int, ny: int, nz: int, mask: np.ndarray,
+                   ilu_blocks: Optional[Sequence[int]] = None):
+    """Host topology (opm_topology_build, or opm_topology_build_blocks for a
+    block ILU0 over subdomain boxes of ilu_blocks = (bx, by, bz) cells).
+    Returns (n, nf, host arrays, Topology, IluBlocks or None)."""
+    L = lib()
+    mask = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
+    n, nf = _i32(), _i32()
+    _check(L.opm_topology_count(nx, ny, nz, mask.ctypes.data, ctypes.byref(n), ctypes.byref(nf)),
+           "opm_topology_count")
+    n, nf = n.value, nf.value
+    nnzb = n + 2 * nf
+    sizes = dict(cell_box=n, face_cells=2 * nf, face_dir=nf, row_ptr=n + 1, col_idx=nnzb,
+                 blk_face=nnzb, diag_pos=n, level_ptr=n + 1, perm=n, iperm=n, lo_blk=3 * n,
+                 lo_tblk=3 * n, lo_pos=3 * n, up_blk=3 * n, up_pos=3 * n)
+    host = {k: np.zeros(max(v, 1), np.int32) for k, v in sizes.items()}
+    topo = Topology(**{k: a.ctypes.data_as(_ip) for k, a in host.items()})
+    if ilu_blocks is None:
+        _check(L.opm_topology_build(nx, ny, nz, mask.ctypes.data, ctypes.byref(topo)),
+               "opm_topology_build")
+        return n, nf, host, topo, None
+    bx, by, bz = (int(b) for b in ilu_blocks)
+    ns, nl = _i32(), _i32()
+    _check(L.opm_ilu_blocks_count(nx, ny, nz, mask.ctypes.data, bx, by, bz, ctypes.byref(ns),
+                                  ctypes.byref(nl)), "opm_ilu_blocks_count")
+    host["sub_level_ptr"] = np.zeros(max(nl.value * (ns.value + 1), 1), np.int32)
+    host["slot"] = np.zeros(max(n, 1), np.int32)
+    blk = IluBlocks(bx=bx, by=by, bz=bz, sub_level_ptr=host["sub_level_ptr"].ctypes.data_as(_ip),
+                    slot=host["slot"].ctypes.data_as(_ip))
+    _check(L.opm_topology_build_blocks(nx, ny, nz, mask.ctypes.data, ctypes.byref(blk),
+                                       ctypes.byref(topo)), "opm_topology_build_blocks")
+    return n, nf, host, topo, blk
 
-    def __init__(self, case: _cases.Case, device: str = "cuda"):
+
+class GpuModel:
+    """A case laid out on the GPU: topology, geometry and wells on device.
+    ilu_blocks = (bx, by, bz) selects the block ILU0 over subdomain boxes of
+    that many cells per axis (one block per subdomain) instead of the
+    single-block ILU(0)."""
+
+    def __init__(self, case: _cases.Case, device: str = "cuda",
+                 ilu_blocks: Optional[Sequence[int]] = None):
         L = lib()
         init()
         self.case = case
         self.dev = torch.device(device)
         nx, ny, nz = case.nx, case.ny, case.nz
-        mask = np.ascontiguousarray(case.mask, dtype=np.uint8).ravel()
-        n, nf = _i32(), _i32()
-        _check(L.opm_topology_count(nx, ny, nz, mask.ctypes.data, ctypes.byref(n),
-                                    ctypes.byref(nf)), "opm_topology_count")
-        n, nf = n.value, nf.value
+        n, nf, host, topo, blk = build_topology(nx, ny, nz, case.mask, ilu_blocks)
         nnzb = n + 2 * nf
-        sizes = dict(cell_box=n, face_cells=2 * nf, face_dir=nf, row_ptr=n + 1, col_idx=nnzb,
-                     blk_face=nnzb, diag_pos=n, level_ptr=n + 1, perm=n, iperm=n, lo_blk=3 * n,
-                     lo_tblk=3 * n, lo_pos=3 * n, up_blk=3 * n, up_pos=3 * n)
-        host = {k: np.zeros(max(v, 1), np.int32) for k, v in sizes.items()}
-        topo = Topology(**{k: a.ctypes.data_as(_ip) for k, a in host.items()})
-        _check(L.opm_topology_build(nx, ny, nz, mask.ctypes.data, ctypes.byref(topo)),
-               "opm_topology_build")
+        self.ilu_blocks = None if ilu_blocks is None else tuple(int(b) for b in ilu_blocks)
+        self.blocks = blk
         self.n, self.nf, self.nnzb = n, nf, nnzb
         self.n_levels, self.max_level = topo.n_levels, topo.max_level
         self.sweep_span = topo.sweep_span
@@ -289,6 +329,10 @@ class GpuModel:
             conn_kind=self.conn_kind.data_ptr(), conn_phase=self.conn_phase.data_ptr(),
             conn_wi=self.conn_wi.data_ptr(), conn_rate=self.conn_rate.data_ptr(),
             conn_bhp=self.conn_bhp.data_ptr(), fluid=fl, sweep_span=topo.sweep_span)
+        if blk is not None:
+            self.pb.n_sub, self.pb.max_sub, self.pb.max_width = blk.n_sub, blk.max_sub, blk.max_width
+            self.pb.sub_level_ptr = d["sub_level_ptr"].data_ptr()
+            self.pb.slot = d["slot"].data_ptr()
         self._work = {}
         torch.cuda.current_stream().synchronize()
 

@@ -143,6 +143,93 @@ def test_topology_levels_are_hyperplanes():
             assert b % 5 + (b // 5) % 4 + b // 20 == l
 
 
+def _subdomains(case, cell_box, blk):
+    """Dense subdomain index of every cell, computed here from the box
+    formula: box (i // bx, j // by, k // bz), nonempty boxes numbered in box
+    order."""
+    nx, ny, nz = case.nx, case.ny, case.nz
+    bx, by, bz = (min(b, e) for b, e in zip(blk, (nx, ny, nz)))
+    i, j, k = cell_box % nx, (cell_box // nx) % ny, cell_box // (nx * ny)
+    nbx, nby = -(-nx // bx), -(-ny // by)
+    box = i // bx + nbx * (j // by + nby * (k // bz))
+    used = np.unique(box)
+    dense = {int(b): q for q, b in enumerate(used)}
+    hyper = i % bx + j % by + k % bz
+    return np.array([dense[int(b)] for b in box]), hyper, len(used)
+
+
+@pytest.mark.parametrize("blk", [(2, 3, 2), (3, 2, 5), (1, 1, 1), (20, 20, 20)])
+@pytest.mark.parametrize("masked", [False, True])
+def test_block_topology(blk, masked):
+    """Block ILU0 topology: same connectivity as the single-block one; the
+    ILU neighbour lists hold exactly the neighbours in the same subdomain;
+    positions ordered by (local hyperplane level, subdomain, cell), each
+    lower neighbour of a row on the previous level; the subdomain ranges
+    and slots index every row once."""
+    opm = _opm()
+    mask = np.random.default_rng(8).random((5, 4, 6)) > 0.3 if masked else None
+    case = cases.box_case(6, 4, 5, seed=3, mask=mask, wells=[])
+    n, nf, h0, t0 = _topology(case)
+    n1, nf1, h, topo, b = opm.build_topology(case.nx, case.ny, case.nz, case.mask, blk)
+    assert (n1, nf1) == (n, nf)
+    for k in ("cell_box", "face_cells", "face_dir", "row_ptr", "col_idx", "blk_face", "diag_pos"):
+        assert np.array_equal(h[k], h0[k]), k
+    sub, hyper, nsub = _subdomains(case, h["cell_box"][:n], blk)
+    assert b.n_sub == nsub
+    levels = np.unique(hyper)
+    lev_of = {int(v): q for q, v in enumerate(levels)}
+    assert topo.n_levels == len(levels)
+    perm, iperm, lp = h["perm"][:n], h["iperm"][:n], h["level_ptr"]
+    key = [(lev_of[int(hyper[c])], sub[c], c) for c in perm]
+    assert key == sorted(key) and np.array_equal(iperm[perm], np.arange(n))
+    for l in range(topo.n_levels):
+        assert all(key[p][0] == l for p in range(lp[l], lp[l + 1]))
+    slp = h["sub_level_ptr"][:topo.n_levels * (nsub + 1)].reshape(topo.n_levels, nsub + 1)
+    slot, counts, widths = h["slot"][:n], np.zeros(nsub, int), []
+    for l in range(topo.n_levels):
+        assert slp[l, 0] == lp[l] and slp[l, nsub] == lp[l + 1]
+        for sb in range(nsub):
+            rows = range(slp[l, sb], slp[l, sb + 1])
+            widths.append(len(rows))
+            for q, p in enumerate(rows):
+                assert sub[perm[p]] == sb and slot[p] == counts[sb] + q
+            counts[sb] += len(rows)
+    assert b.max_sub == counts.max() and b.max_width == max(widths)
+    rp, ci = h["row_ptr"], h["col_idx"]
+    for p in range(n):
+        c = perm[p]
+        lo = [q for q in range(rp[c], rp[c + 1]) if ci[q] < c and sub[ci[q]] == sub[c]]
+        up = [q for q in range(rp[c], rp[c + 1]) if ci[q] > c and sub[ci[q]] == sub[c]]
+        assert list(h["lo_blk"][3 * p:3 * p + len(lo)]) == lo
+        assert list(h["up_blk"][3 * p:3 * p + len(up)]) == up
+        assert (h["lo_blk"][3 * p + len(lo):3 * p + 3] == -1).all()
+        assert (h["up_blk"][3 * p + len(up):3 * p + 3] == -1).all()
+        for s_, q in enumerate(lo):
+            kp = h["lo_pos"][3 * p + s_]
+            assert kp == iperm[ci[q]] and key[kp][0] == key[p][0] - 1
+            assert ci[h["lo_tblk"][3 * p + s_]] == c
+        for s_, q in enumerate(up):
+            assert h["up_pos"][3 * p + s_] == iperm[ci[q]]
+    if blk == (20, 20, 20):
+        for k in ("level_ptr", "perm", "iperm", "lo_blk", "lo_tblk", "lo_pos", "up_blk", "up_pos"):
+            assert np.array_equal(h[k], h0[k]), k
+
+
+def test_block_topology_invalid():
+    opm = _opm()
+    L = opm.lib()
+    ns, nl = ctypes.c_int32(), ctypes.c_int32()
+    for blk in [(0, 1, 1), (1, -2, 1), (1, 1, 0)]:
+        assert L.opm_ilu_blocks_count(3, 3, 3, None, *blk, ctypes.byref(ns), ctypes.byref(nl)) == opm.EINVAL
+        with pytest.raises(opm.OpmError):
+            opm.build_topology(3, 3, 3, np.ones((3, 3, 3), np.uint8), blk)
+    assert L.opm_ilu_blocks_count(3, 3, 3, None, 2, 2, 2, ctypes.byref(ns), ctypes.byref(nl)) == 0
+    assert (ns.value, nl.value) == (8, 4)
+    blk = opm.IluBlocks(bx=2, by=2, bz=2)   # NULL output arrays
+    t = opm.Topology()
+    assert L.opm_topology_build_blocks(3, 3, 3, None, ctypes.byref(blk), ctypes.byref(t)) == opm.EINVAL
+
+
 def test_topology_edge_cases():
     opm = _opm()
     L = opm.lib()
