@@ -561,10 +561,13 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
  *     1 right-hand side gathered inside the sweep, 2-6 right-hand side
  *     gathered into level order first and branch-free prefetch with 512,
  *     256 or 128 threads (2, 3, 4) or with wavefronts that have no row in a
- *     level skipping their loads (5: 512, 6: 256 threads). */
+ *     level skipping their loads (5: 512, 6: 256 threads).
+ *   OPM_OPT_BLOCK_DEPTH: block-ILU0 sweeps, levels whose data is loaded
+ *     while a level is computed: 0 automatic (1), 1 or 2. */
 #define OPM_OPT_SWEEP_MODE 1
 #define OPM_OPT_KRYLOV_CHUNK 2
 #define OPM_OPT_SWEEP_KERNEL 3
+#define OPM_OPT_BLOCK_DEPTH 4
 int opm_set_option(int option, int value);
 
 const char* opm_strerror(int code);

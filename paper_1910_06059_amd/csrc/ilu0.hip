@@ -33,6 +33,7 @@
 namespace opm {
 
 extern int g_sweep_kernel;
+extern int g_block_depth;
 
 namespace {
 
@@ -137,8 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_rhs(int n, const int32_t* per
 // forward record holds the lower blocks and D^{-1}, the backward one the
 // upper blocks and D^{-1}, each with the neighbour positions and the row.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pack_records(Topo t, IluView<T> v,
-                                                         const int32_t* slot) {
+__global__ __launch_bounds__(kBlock) void k_pack_records(Topo t, IluView<T> v) {
   const int pos = blockIdx.x * kBlock + threadIdx.x;
   if (pos >= t.n) return;
   constexpr size_t kV = 16 / sizeof(T);
@@ -150,10 +150,8 @@ __global__ __launch_bounds__(kBlock) void k_pack_records(Topo t, IluView<T> v,
     v.rec_b[a] = e < 27 ? v.upv[e * ns + p] : v.dinv[(e - 27) * ns + p];
   }
   const int cell = t.perm[pos];
-  // neighbours by level position, or (block ILU0) by slot in the subdomain
-  auto nb = [&](int kp) { return kp < 0 || slot == nullptr ? kp : slot[kp]; };
-  v.idx_f[pos] = int4v{nb(t.lo_pos[3 * p]), nb(t.lo_pos[3 * p + 1]), nb(t.lo_pos[3 * p + 2]), cell};
-  v.idx_b[pos] = int4v{nb(t.up_pos[3 * p]), nb(t.up_pos[3 * p + 1]), nb(t.up_pos[3 * p + 2]), cell};
+  v.idx_f[pos] = int4v{t.lo_pos[3 * p], t.lo_pos[3 * p + 1], t.lo_pos[3 * p + 2], cell};
+  v.idx_b[pos] = int4v{t.up_pos[3 * p], t.up_pos[3 * p + 1], t.up_pos[3 * p + 2], cell};
 }
 
 // ------------------------------------------------------------ block ILU0
@@ -165,30 +163,104 @@ __global__ __launch_bounds__(kBlock) void k_pack_records(Topo t, IluView<T> v,
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_factor_blocks(Topo t, const double* J, IluView<T> v,
                                                        const int32_t* slp, int nsub,
-                                                       int32_t* status) {
+                                                       int max_width, int32_t* status) {
+  // inverse pivots of the previous and the current level of the subdomain
+  // (every lower neighbour in the subdomain lies on the previous level)
+  extern __shared__ double fwin[];   // [2][max_width][9]
   const int s = blockIdx.x;
+  auto range = [&](int l, int& p0, int& p1) {
+    p0 = slp[(size_t)l * (nsub + 1) + s];
+    p1 = slp[(size_t)l * (nsub + 1) + s + 1];
+  };
+  int p0, p1;
+  range(0, p0, p1);
+  FacJob next;
+  if (p0 + (int)threadIdx.x < p1) load_fac(t, J, p0 + threadIdx.x, next);
+  int prev0 = 0, prev1 = 0, buf = 0;
   for (int l = 0; l < t.nlev; ++l) {
-    const int p0 = slp[(size_t)l * (nsub + 1) + s], p1 = slp[(size_t)l * (nsub + 1) + s + 1];
-    for (int pos = p0 + (int)threadIdx.x; pos < p1; pos += NT) {
-      FacJob j;
-      load_fac(t, J, pos, j);
+    int q0 = 0, q1 = 0;
+    if (l + 1 < t.nlev) range(l + 1, q0, q1);
+    const FacJob cur = next;
+    // the next level's blocks load while this level is computed
+    if (q0 + (int)threadIdx.x < q1) load_fac(t, J, q0 + threadIdx.x, next);
+    auto finish = [&](const FacJob& j, int pos) {
       double inv[9];
-      // D_k^{-1} of the previous level, written by this workgroup before
-      // the barrier
       finish_fac<T>(j, pos, v,
                     [&](int kp, double* Dk) {
+                      if (kp >= prev0 && kp < prev1) {
+                        const double* w = fwin + ((size_t)(buf ^ 1) * max_width + (kp - prev0)) * 9;
 #pragma unroll
-                      for (int e = 0; e < 9; ++e) Dk[e] = v.dinv64[(size_t)e * v.ns + kp];
+                        for (int e = 0; e < 9; ++e) Dk[e] = w[e];
+                      } else {
+#pragma unroll
+                        for (int e = 0; e < 9; ++e) Dk[e] = v.dinv64[(size_t)e * v.ns + kp];
+                      }
                     },
                     status, inv);
+      double* w = fwin + ((size_t)buf * max_width + (pos - p0)) * 9;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) w[e] = inv[e];
+    };
+    if (p0 + (int)threadIdx.x < p1) finish(cur, p0 + threadIdx.x);
+    // rows of levels wider than the workgroup
+    for (int pos = p0 + NT + (int)threadIdx.x; pos < p1; pos += NT) {
+      FacJob extra;
+      load_fac(t, J, pos, extra);
+      finish(extra, pos);
     }
     __syncthreads();
+    prev0 = p0;
+    prev1 = p1;
+    buf ^= 1;
+    p0 = q0;
+    p1 = q1;
   }
 }
 
-// Sweep data of one row of a subdomain: the record (blocks, D^{-1}) of its
-// level position, the slots of its neighbours and its cell; the forward
-// right-hand side r of its cell, the backward one y from the LDS vector.
+// Sweep records of the block ILU0, straight from the Jacobian (after the
+// pivot recursion): lower blocks and D^{-1}, upper blocks and D^{-1}, the
+// neighbours by slot in the subdomain and the row's cell.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pack_block_records(Topo t, const double* J,
+                                                               IluView<T> v,
+                                                               const int32_t* slot) {
+  const int pos = blockIdx.x * kBlock + threadIdx.x;
+  if (pos >= t.n) return;
+  constexpr size_t kV = 16 / sizeof(T);
+  const size_t ns = (size_t)v.ns, p = (size_t)pos;
+  auto put = [&](T* rec, int e, T val) { rec[((size_t)e / kV * ns + p) * kV + (size_t)e % kV] = val; };
+#pragma unroll
+  for (int sl = 0; sl < 3; ++sl) {
+    const int bl = t.lo_blk[3 * p + sl], bu = t.up_blk[3 * p + sl];
+    const double* Al = J + 9 * (size_t)(bl < 0 ? 0 : bl);
+    const double* Au = J + 9 * (size_t)(bu < 0 ? 0 : bu);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      put(v.rec_f, 9 * sl + e, bl < 0 ? (T)0 : (T)Al[e]);
+      put(v.rec_b, 9 * sl + e, bu < 0 ? (T)0 : (T)Au[e]);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    const T d = v.dinv[(size_t)e * ns + p];
+    put(v.rec_f, 27 + e, d);
+    put(v.rec_b, 27 + e, d);
+  }
+  auto nb = [&](int kp) { return kp < 0 ? kp : slot[kp]; };
+  const int cell = t.perm[pos];
+  v.idx_f[pos] = int4v{nb(t.lo_pos[3 * p]), nb(t.lo_pos[3 * p + 1]), nb(t.lo_pos[3 * p + 2]), cell};
+  v.idx_b[pos] = int4v{nb(t.up_pos[3 * p]), nb(t.up_pos[3 * p + 1]), nb(t.up_pos[3 * p + 2]), cell};
+}
+
+// A sweep of one subdomain is a three-stage pipeline over its levels: the
+// neighbour slots and cells of level k+2 and the records and right-hand
+// sides of level k+1 are loaded while level k is computed.  The right-hand
+// side of the forward sweep is r at the row's cell, so its address needs
+// the index loaded one level earlier; loading the index in the same stage
+// would make the wait for it (the load counter drains in order) also wait
+// for the previous level's data.  No branch separates a load from its use
+// (lanes past a level's end load a clamped row and store nothing), so the
+// compiler never has to assume a load of an earlier level still in flight.
 template <typename T>
 struct BlockJob {
   T a[27];
@@ -200,22 +272,37 @@ struct BlockJob {
   bool live;
 };
 
-template <typename T, bool FWD>
-__device__ __forceinline__ void block_fetch(IluView<T> v, const double* r, const T* zl,
-                                            const int* lp, int nlev, int k, int base,
-                                            BlockJob<T>& j) {
-  typedef typename Vec16<T>::type V;
-  constexpr unsigned kV = 16 / sizeof(T);
+// Level k of the sweep (ascending levels forward, descending backward;
+// past the last one: the last one) and the lane's clamped row position.
+template <bool FWD>
+__device__ __forceinline__ void block_row_pos(const int* lp, int nlev, int k, int& p0, int& p1,
+                                              int& pos) {
   const int kk = k < nlev ? k : nlev - 1;
   const int l = FWD ? kk : nlev - 1 - kk;
-  const int p0 = lp[2 * l], p1 = lp[2 * l + 1];
+  p0 = lp[2 * l];
+  p1 = lp[2 * l + 1];
+  pos = max(min(p0 + (int)threadIdx.x, p1 - 1), 0);
+}
+
+template <typename T, bool FWD>
+__device__ __forceinline__ int4v block_index(IluView<T> v, const int* lp, int nlev, int k) {
+  int p0, p1, pos;
+  block_row_pos<FWD>(lp, nlev, k, p0, p1, pos);
+  return (FWD ? v.idx_f : v.idx_b)[(unsigned)pos];
+}
+
+// base: rows of the subdomain before the level (forward) or up to and
+// including it (backward).
+template <typename T, bool FWD>
+__device__ __forceinline__ void block_data(IluView<T> v, const double* r, const T* zl,
+                                           const int* lp, int nlev, int k, int base, int4v ix,
+                                           BlockJob<T>& j) {
+  typedef typename Vec16<T>::type V;
+  constexpr unsigned kV = 16 / sizeof(T);
+  int p0, p1, pos;
+  block_row_pos<FWD>(lp, nlev, k, p0, p1, pos);
   j.live = k < nlev && p0 + (int)threadIdx.x < p1;
-  // a wavefront without a row on the level loads nothing (also when the
-  // subdomain has no row there at all, p0 == p1)
-  if (__builtin_amdgcn_readfirstlane(p0 + (int)(threadIdx.x & ~63u)) >= p1) return;
-  const int pos = min(p0 + (int)threadIdx.x, p1 - 1);
   const unsigned ns = (unsigned)v.ns, up = (unsigned)pos;
-  const int4v ix = (FWD ? v.idx_f : v.idx_b)[up];
   j.kp[0] = ix.x;
   j.kp[1] = ix.y;
   j.kp[2] = ix.z;
@@ -238,16 +325,23 @@ __device__ __forceinline__ void block_fetch(IluView<T> v, const double* r, const
 #pragma unroll
     for (unsigned c = 0; c < 3; ++c) j.rhs[c] = (T)r[3u * (unsigned)j.cell + c];
   } else {
+    // y of the row (forward result); slots of lanes past the level's end
+    // stay inside the subdomain
+    const unsigned sl = (unsigned)max(j.slot, 0);
 #pragma unroll
-    for (unsigned c = 0; c < 3; ++c) j.rhs[c] = zl[3u * (unsigned)j.slot + c];
+    for (unsigned c = 0; c < 3; ++c) j.rhs[c] = zl[3u * sl + c];
   }
+  // keep every load of the stage here, ahead of the computation of the
+  // current level (the compiler would otherwise sink some of them to their
+  // first use, behind the next stage's loads)
+  asm volatile("" ::: "memory");
 }
 
 // The arithmetic of a sweep row, in the same order as the other sweep
-// kernels (results are bitwise equal).
+// kernels (results are bitwise equal).  Every lane computes; only rows of
+// the level store.
 template <typename T, bool FWD>
 __device__ __forceinline__ void block_row(const BlockJob<T>& j, T* zl, double* x) {
-  if (!j.live) return;
   T acc[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) acc[c] = FWD ? j.rhs[c] : (T)0;
@@ -270,6 +364,7 @@ __device__ __forceinline__ void block_row(const BlockJob<T>& j, T* zl, double* x
     const T d = j.D[3 * a] * acc[0] + j.D[3 * a + 1] * acc[1] + j.D[3 * a + 2] * acc[2];
     out[a] = FWD ? d : j.rhs[a] - d;
   }
+  if (!j.live) return;
   T* w = zl + 3u * (unsigned)j.slot;
 #pragma unroll
   for (unsigned c = 0; c < 3; ++c) w[c] = out[c];
@@ -318,39 +413,62 @@ __device__ __forceinline__ void block_extra(IluView<T> v, const double* r, T* zl
   }
 }
 
-template <typename T, int NT, bool FWD, bool WIDE>
+// DEPTH: levels whose data is in flight while a level is computed.  At the
+// step that computes level s the index stage loads level s + DEPTH + 2 and
+// the data stage loads level s + DEPTH from the index loaded two steps
+// earlier, so no load waits for one issued in the previous step.  The
+// stages rotate through register rings (3 indices, DEPTH + 1 jobs), fully
+// unrolled over a period of P steps so that every ring slot is a register.
+template <typename T, int NT, bool FWD, bool WIDE, int DEPTH>
 __device__ __forceinline__ void block_sweep(IluView<T> v, const double* r, T* zl, double* x,
                                             const int* lp, int nlev, int nrows) {
-  // base: rows of the subdomain before the level (forward), or up to and
-  // including it (backward)
-  auto width = [&](int k) {
+  constexpr int ND = DEPTH + 1, NI = 3;
+  constexpr int P = ND % NI == 0 ? ND : ND * NI;
+  auto next_base = [&](int b, int k) {
     const int l = FWD ? k : nlev - 1 - k;
-    return lp[2 * l + 1] - lp[2 * l];
+    const int w = k < nlev ? lp[2 * l + 1] - lp[2 * l] : 0;
+    return FWD ? b + w : b - w;
   };
-  int base = FWD ? 0 : nrows;
-  BlockJob<T> ja, jb;
-  block_fetch<T, FWD>(v, r, zl, lp, nlev, 0, base, ja);
-  for (int k = 0; k < nlev; k += 2) {
-    const int b1 = FWD ? base + width(k) : base - width(k);
-    block_fetch<T, FWD>(v, r, zl, lp, nlev, k + 1, b1, jb);
-    block_row<T, FWD>(ja, zl, x);
-    if (WIDE) block_extra<T, NT, FWD>(v, r, zl, x, lp, nlev, k, base);
+  int ik = 0;                                 // index stage: next level
+  int dk = 0, db = FWD ? 0 : nrows;           // data stage: next level and its base
+  int ck = 0, cb = db;                        // compute stage
+  auto index = [&]() { return block_index<T, FWD>(v, lp, nlev, ik++); };
+  auto data = [&](int4v ix, BlockJob<T>& j) {
+    block_data<T, FWD>(v, r, zl, lp, nlev, dk, db, ix, j);
+    db = next_base(db, dk++);
+  };
+  auto compute = [&](const BlockJob<T>& j) {
+    block_row<T, FWD>(j, zl, x);
+    if (WIDE) block_extra<T, NT, FWD>(v, r, zl, x, lp, nlev, ck, cb);
+    cb = next_base(cb, ck++);
     __syncthreads();
-    if (k + 1 >= nlev) break;
-    base = b1;
-    const int b2 = FWD ? base + width(k + 1) : base - width(k + 1);
-    block_fetch<T, FWD>(v, r, zl, lp, nlev, k + 2, b2, ja);
-    block_row<T, FWD>(jb, zl, x);
-    if (WIDE) block_extra<T, NT, FWD>(v, r, zl, x, lp, nlev, k + 1, base);
-    __syncthreads();
-    base = b2;
+  };
+  BlockJob<T> jobs[ND];
+  int4v idx[NI];
+  // prologue: data of levels 0 .. DEPTH-1, indices of DEPTH and DEPTH+1
+  // (each index slot is read before it is loaded again)
+#pragma unroll
+  for (int q = 0; q < DEPTH; ++q) {
+    idx[q % NI] = index();
+    data(idx[q % NI], jobs[q % ND]);
+  }
+  idx[DEPTH % NI] = index();
+  idx[(DEPTH + 1) % NI] = index();
+  for (int k = 0; k < nlev; k += P) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      if (k + q >= nlev) break;
+      idx[(q + DEPTH + 2) % NI] = index();
+      data(idx[(q + DEPTH) % NI], jobs[(q + DEPTH) % ND]);
+      compute(jobs[q % ND]);
+    }
   }
 }
 
 // x = M^{-1} r for the block ILU0: forward then backward sweep of one
 // subdomain per workgroup, the subdomain's y and x in LDS (3 values per
 // row, by slot), then the level bounds of the subdomain (2 ints per level).
-template <typename T, int NT, bool WIDE>
+template <typename T, int NT, bool WIDE, int DEPTH>
 __global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t* slp, int nsub,
                                                       int nlev, int max_sub, const double* r,
                                                       double* x, const int32_t* skip) {
@@ -366,8 +484,8 @@ __global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t
   __syncthreads();
   int nrows = 0;
   for (int l = 0; l < nlev; ++l) nrows += lp[2 * l + 1] - lp[2 * l];
-  block_sweep<T, NT, true, WIDE>(v, r, zl, x, lp, nlev, nrows);
-  block_sweep<T, NT, false, WIDE>(v, r, zl, x, lp, nlev, nrows);
+  block_sweep<T, NT, true, WIDE, DEPTH>(v, r, zl, x, lp, nlev, nrows);
+  block_sweep<T, NT, false, WIDE, DEPTH>(v, r, zl, x, lp, nlev, nrows);
 }
 
 // Both sweeps by one workgroup of NT threads through the LDS ring with
@@ -401,8 +519,9 @@ size_t apply_lds(const opm_problem* pb) {
 size_t factor_lds(const opm_problem* pb) { return sizeof(double) * 2 * 9 * (size_t)pb->max_level; }
 
 // one flag per (kernel, precision): slots 0-5 level-window kernels, 12-21
-// (FP64) and 24-33 (FP32) ring sweeps, 40-43 (FP64) and 44-47 (FP32) block ILU0
-bool g_lds_attr_set[48] = {};
+// (FP64) and 24-33 (FP32) ring sweeps, 34-39 block-ILU0 factorisation,
+// 40-51 (FP64) and 52-63 (FP32) block-ILU0 sweeps
+bool g_lds_attr_set[64] = {};
 
 template <typename K>
 int allow_lds(K kernel, int slot) {
@@ -430,27 +549,32 @@ int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* stat
                 hipStream_t s) {
   IluView<T> v = view<T>(pb, ilu);
   Topo t = topo_of(pb);
-  hipLaunchKernelGGL(k_pack<T>, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock), 0, s, t, J,
-                     v);
   if (mode == 2) {   // block ILU0: one workgroup per subdomain
+    const size_t lds = sizeof(double) * 2 * 9 * (size_t)pb->max_width;
+    const int slot = sizeof(T) == 8 ? 34 : 37;
     switch (block_threads(pb)) {
       case 64:
-        hipLaunchKernelGGL((k_factor_blocks<T, 64>), dim3(pb->n_sub), dim3(64), 0, s, t, J, v,
-                           pb->sub_level_ptr, pb->n_sub, status);
+        OPM_TRY(allow_lds(k_factor_blocks<T, 64>, slot));
+        hipLaunchKernelGGL((k_factor_blocks<T, 64>), dim3(pb->n_sub), dim3(64), lds, s, t, J, v,
+                           pb->sub_level_ptr, pb->n_sub, pb->max_width, status);
         break;
       case 128:
-        hipLaunchKernelGGL((k_factor_blocks<T, 128>), dim3(pb->n_sub), dim3(128), 0, s, t, J, v,
-                           pb->sub_level_ptr, pb->n_sub, status);
+        OPM_TRY(allow_lds(k_factor_blocks<T, 128>, slot + 1));
+        hipLaunchKernelGGL((k_factor_blocks<T, 128>), dim3(pb->n_sub), dim3(128), lds, s, t, J,
+                           v, pb->sub_level_ptr, pb->n_sub, pb->max_width, status);
         break;
       default:
-        hipLaunchKernelGGL((k_factor_blocks<T, 256>), dim3(pb->n_sub), dim3(256), 0, s, t, J, v,
-                           pb->sub_level_ptr, pb->n_sub, status);
+        OPM_TRY(allow_lds(k_factor_blocks<T, 256>, slot + 2));
+        hipLaunchKernelGGL((k_factor_blocks<T, 256>), dim3(pb->n_sub), dim3(256), lds, s, t, J,
+                           v, pb->sub_level_ptr, pb->n_sub, pb->max_width, status);
     }
-    hipLaunchKernelGGL(k_pack_records<T>, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock), 0,
-                       s, t, v, pb->slot);
+    hipLaunchKernelGGL(k_pack_block_records<T>, dim3(blocks_for(pb->n_cells, kBlock)),
+                       dim3(kBlock), 0, s, t, J, v, pb->slot);
     OPM_TRY_HIP(hipGetLastError());
     return OPM_OK;
   }
+  hipLaunchKernelGGL(k_pack<T>, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock), 0, s, t, J,
+                     v);
   if (mode == 0) {
     if (pb->max_level <= kMaxFactorWindowRows) {
       OPM_TRY(allow_lds(k_factor_wg<T, true>, sizeof(T) == 8 ? 0 : 1));
@@ -463,7 +587,7 @@ int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* stat
     // the record sweep's copy of the factors (whenever a ring sweep can run)
     if (sizeof(T) * 3 * (size_t)ring_rows(pb->sweep_span, pb->max_level) <= kMaxRingBytes)
       hipLaunchKernelGGL(k_pack_records<T>, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock),
-                         0, s, t, v, nullptr);
+                         0, s, t, v);
     OPM_TRY_HIP(hipGetLastError());
     return OPM_OK;
   }
@@ -483,23 +607,31 @@ int apply_impl(const opm_problem* pb, void* ilu, const double* r, double* x, int
   Topo t = topo_of(pb);
   if (mode == 2) {
     const size_t lds = block_lds<T>(pb);
-    const int slot = sizeof(T) == 8 ? 40 : 44;
-#define OPM_BLOCKS(NT)                                                                           \
-  do {                                                                                           \
-    if (pb->max_width <= NT) {                                                                   \
-      OPM_TRY(allow_lds(k_apply_blocks<T, NT, false>, slot + (NT == 64 ? 0 : NT == 128 ? 1 : 2))); \
-      hipLaunchKernelGGL((k_apply_blocks<T, NT, false>), dim3(pb->n_sub), dim3(NT), lds, s, v,   \
-                         pb->sub_level_ptr, pb->n_sub, pb->n_levels, pb->max_sub, r, x, skip);   \
-    } else {                                                                                     \
-      OPM_TRY(allow_lds(k_apply_blocks<T, NT, true>, slot + 3));                                 \
-      hipLaunchKernelGGL((k_apply_blocks<T, NT, true>), dim3(pb->n_sub), dim3(NT), lds, s, v,    \
-                         pb->sub_level_ptr, pb->n_sub, pb->n_levels, pb->max_sub, r, x, skip);   \
-    }                                                                                            \
+    const int slot = sizeof(T) == 8 ? 40 : 52;
+#define OPM_BLOCKS(NT, D, SL)                                                                 \
+  do {                                                                                        \
+    if (pb->max_width <= NT) {                                                                \
+      OPM_TRY(allow_lds(k_apply_blocks<T, NT, false, D>, slot + SL));                         \
+      hipLaunchKernelGGL((k_apply_blocks<T, NT, false, D>), dim3(pb->n_sub), dim3(NT), lds, s, \
+                         v, pb->sub_level_ptr, pb->n_sub, pb->n_levels, pb->max_sub, r, x,    \
+                         skip);                                                               \
+    } else {                                                                                  \
+      OPM_TRY(allow_lds(k_apply_blocks<T, NT, true, D>, slot + SL + 1));                      \
+      hipLaunchKernelGGL((k_apply_blocks<T, NT, true, D>), dim3(pb->n_sub), dim3(NT), lds, s,  \
+                         v, pb->sub_level_ptr, pb->n_sub, pb->n_levels, pb->max_sub, r, x,    \
+                         skip);                                                               \
+    }                                                                                         \
   } while (0)
-    switch (block_threads(pb)) {
-      case 64: OPM_BLOCKS(64); break;
-      case 128: OPM_BLOCKS(128); break;
-      default: OPM_BLOCKS(256); break;
+    // one level of data in flight (two measured no faster on 9000- to
+    // 500000-cell systems)
+    const int depth = g_block_depth != 0 ? g_block_depth : 1;
+    switch (block_threads(pb) * 4 + depth) {
+      case 64 * 4 + 1: OPM_BLOCKS(64, 1, 0); break;
+      case 128 * 4 + 1: OPM_BLOCKS(128, 1, 2); break;
+      case 256 * 4 + 1: OPM_BLOCKS(256, 1, 4); break;
+      case 64 * 4 + 2: OPM_BLOCKS(64, 2, 6); break;
+      case 128 * 4 + 2: OPM_BLOCKS(128, 2, 8); break;
+      default: OPM_BLOCKS(256, 2, 10); break;
     }
 #undef OPM_BLOCKS
     OPM_TRY_HIP(hipGetLastError());
@@ -581,6 +713,8 @@ int g_sweep_mode = -1;
 // loads, 2-6 branch-free prefetch (512, 256, 128 threads; 512 and 256
 // threads with idle wavefronts skipping their loads)
 int g_sweep_kernel = 0;
+// levels whose data the block-ILU0 sweeps keep in flight: 0 automatic, 1, 2
+int g_block_depth = 0;
 
 // A block-ILU0 topology runs one workgroup per subdomain whenever the
 // subdomain's vector fits in LDS; modes 0 and 1 also serve it (same

@@ -10,6 +10,7 @@
 namespace opm {
 
 extern int g_sweep_mode;
+extern int g_block_depth;
 extern int g_sweep_kernel;
 extern int g_krylov_chunk;
 int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, double dt,
@@ -327,6 +328,10 @@ int opm_set_option(int option, int value) {
     case OPM_OPT_SWEEP_KERNEL:
       if (value < 0 || value > 6) return OPM_EINVAL;
       g_sweep_kernel = value;
+      return OPM_OK;
+    case OPM_OPT_BLOCK_DEPTH:
+      if (value < 0 || value > 2) return OPM_EINVAL;
+      g_block_depth = value;
       return OPM_OK;
     default:
       return OPM_EINVAL;

@@ -60,9 +60,11 @@ def _system(case, blk, seed=1):
     return m, R, J, F
 
 
-def _factor_bytes(g, precision):
+def _pivot_bytes(g, precision):
+    """The inverse pivots lead the ILU buffer: FP64 [9][ns], then with FP32
+    factors their FP32 copy [9][ns]."""
     ns = (g.n + 63) // 64 * 64
-    return 8 * (9 + 54) * ns if precision == 0 else 8 * 9 * ns + 4 * (9 + 54) * ns
+    return 8 * 9 * ns if precision == 0 else 8 * 9 * ns + 4 * 9 * ns
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -96,14 +98,15 @@ def test_block_ilu0_parity(opm, name, precision):
 @pytest.mark.parametrize("name", ["C2_columns", "masked", "box_ragged"])
 def test_block_launch_shapes_bitwise_equal(opm, name, precision):
     """One workgroup per subdomain (automatic), one workgroup for all levels
-    and one launch per level give bitwise equal factors and sweeps."""
+    and one launch per level give bitwise equal inverse pivots and sweeps;
+    so do one and two levels of sweep data in flight."""
     make, blk = CASES[name]
     case = make()
     g = opm.GpuModel(case, ilu_blocks=blk)
     y = g.state(cases.random_state(case, 5))
     acc0 = g.accumulation(g.state(cases.random_state(case, 6)))
     R, J, _ = g.assemble(y, acc0, DAY)
-    nfac = _factor_bytes(g, precision)
+    nfac = _pivot_bytes(g, precision)
     out = []
     try:
         for mode in (-1, 2, 1, 0):
@@ -116,6 +119,13 @@ def test_block_launch_shapes_bitwise_equal(opm, name, precision):
     for mode, (f, x) in zip((2, 1, 0), out[1:]):
         assert torch.equal(f, out[0][0]), (name, precision, mode, "factors")
         assert torch.equal(x, out[0][1]), (name, precision, mode, "sweep")
+    ilu, _ = g.ilu0_factor(J, precision)
+    try:
+        for depth in (1, 2):
+            opm.set_option(opm.OPT_BLOCK_DEPTH, depth)
+            assert torch.equal(g.ilu0_apply(ilu, R, precision), out[0][1]), (name, depth)
+    finally:
+        opm.set_option(opm.OPT_BLOCK_DEPTH, 0)
 
 
 def test_block_wide_subdomain(opm):
