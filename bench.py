@@ -3,11 +3,15 @@
 
 Workload: the 24x25x15 waterflood (9000 active cells, lognormal layered
 permeability, one rate injector over the (0,0) column, four BHP producers),
-FP64 state, block-ILU(0) BiCGStab to 1e-6, Newton to CNV 1e-8 / MB 1e-11.
-One benchmark step is one 10-day implicit time step: every Newton iteration
-assembles the residual and Jacobian by AD, tests convergence, factors
-ILU(0), solves with BiCGStab and applies the chopped update, all in the HIP
-kernels of libopm_gpu.so.  Inputs are resident in HBM before timing starts.
+FP64 state, ILU0-preconditioned BiCGStab to 1e-6, Newton to CNV 1e-8 / MB
+1e-11.  One benchmark step is one 10-day implicit time step: every Newton
+iteration assembles the residual and Jacobian by AD, tests convergence,
+factors the preconditioner, solves with BiCGStab and applies the chopped
+update, all in the HIP kernels of libopm_gpu.so.  Inputs are resident in HBM
+before timing starts.  The preconditioner of `value` is the block ILU0 of
+the paper's parallel runs (sec. 2.5, one block per subdomain; default 42
+column subdomains of 4x4x15 cells, --ilu-blocks); the ILU(0) of the whole
+system is timed on the same workload and reported beside it.
 
 Metric: cell-Newton-iterations per second = sum over timed Newton iterations
 of the active cell count / wall time of the timed steps.
@@ -46,6 +50,16 @@ def sweep_bytes_per_cell(precision: int) -> float:
     return blocks + vectors + index
 
 
+def block_sweep_bytes_per_cell(precision: int) -> float:
+    """Algorithmic bytes of one block-ILU0 preconditioner application per
+    cell: the three lower and three upper off-diagonal blocks and D^{-1}
+    (read in both sweeps) of the sweep records, the two 16-byte neighbour
+    index records, the right-hand side read and the result written (the
+    intermediate vector stays in LDS)."""
+    w = 8 if precision == 0 else 4
+    return (27 + 27 + 2 * 9) * w + 2 * 16 + 24 + 24
+
+
 def spmv_bytes_per_cell(nnzb: int, n: int) -> float:
     """Algorithmic bytes of y = J x per block row: every 3x3 FP64 block and
     its column index once, the row pointer, x once and y once."""
@@ -73,13 +87,37 @@ def factor_bytes_per_cell(precision: int) -> float:
     return pack + recurse
 
 
+def block_factor_bytes_per_cell(precision: int) -> float:
+    """Algorithmic bytes of the block-ILU0 factorisation per cell: the pivot
+    recursion reads the diagonal, the three lower and the three transposed
+    blocks of the row and writes D^{-1} (plus its FP32 copy); the record
+    pass reads the six off-diagonal blocks and D^{-1} and writes the two
+    sweep records and index records."""
+    w = 8 if precision == 0 else 4
+    recurse = 7 * 72 + 72 + (36 if precision else 0)
+    records = 6 * 72 + 9 * w + 2 * 36 * w + 2 * 16
+    return recurse + records
+
+
+def parse_blocks(spec, case):
+    """--ilu-blocks: 'none' (single block), 'BXxBY' (columns over the full
+    depth) or 'BXxBYxBZ'."""
+    if spec is None or spec == "none":
+        return None
+    parts = [int(v) for v in spec.lower().split("x")]
+    if len(parts) == 2:
+        parts.append(case.nz)
+    return tuple(parts)
+
+
 def measured_traffic(kernel_class: str, precision: int):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs (profiles/counters.json, scaled by a plain
     256 MiB copy), or None when there is no record or one of the kernel's
     source files has changed since the counters were taken."""
     import hashlib
-    tags = {("ilu0_apply", 0): "c2_fp64_ilu0_sweep", ("ilu0_apply", 1): "c2_mixed_ilu0_sweep"}
+    tags = {("ilu0_apply", 0): "c2_fp64_ilu0_sweep", ("ilu0_apply", 1): "c2_mixed_ilu0_sweep",
+            ("block_apply", 0): "c2_fp64_block_sweep", ("block_apply", 1): "c2_mixed_block_sweep"}
     tag = tags.get((kernel_class, precision))
     path = os.path.join(ROOT, "profiles", "counters.json")
     if tag is None or not os.path.exists(path):
@@ -351,6 +389,11 @@ def bench_kernels(args):
     yk[:, 0] += 1e4
     R, J, _ = g.assemble(yk, acc0, dt)
     ilu = {p: g.ilu0_factor(J, p)[0] for p in (0, 1)}
+    blk = parse_blocks(args.ilu_blocks, case) or (4, 4, case.nz)
+    gb = opm.GpuModel(case, ilu_blocks=blk)
+    Jb_ = J.clone()   # same cell numbering and pattern: the same Jacobian
+    bilu = {p: gb.ilu0_factor(Jb_, p)[0] for p in (0, 1)}
+    pbb = gb._pbp()
     x = g.zeros_state()
     L = opm.lib()
     pbp = g._pbp()
@@ -394,6 +437,15 @@ def bench_kernels(args):
                      assemble_bytes(n, g.nnzb, g.nf), "k_assemble + k_norms_final"),
         "ilu0_factor_fp64": (lambda: L.opm_ilu0_factor(pbp, sp(J), sp(ilu_tmp[0]), 0, sp(status), st),
                              factor_bytes_per_cell(0) * n, "k_pack + k_factor_level (FP64)"),
+        "block_apply_fp64": (lambda: L.opm_ilu0_apply(pbb, sp(bilu[0]), 0, sp(R), sp(x), st),
+                             block_sweep_bytes_per_cell(0) * n,
+                             f"k_apply_blocks (FP64, {gb.pb.n_sub} subdomains of {blk})"),
+        "block_apply_fp32": (lambda: L.opm_ilu0_apply(pbb, sp(bilu[1]), 1, sp(R), sp(x), st),
+                             block_sweep_bytes_per_cell(1) * n,
+                             f"k_apply_blocks (FP32, {gb.pb.n_sub} subdomains of {blk})"),
+        "block_factor_fp64": (lambda: L.opm_ilu0_factor(pbb, sp(Jb_), sp(ilu_tmp[0]), 0, sp(status), st),
+                              block_factor_bytes_per_cell(0) * n,
+                              "k_factor_blocks + k_pack_block_records (FP64)"),
     }
     if args.kernels:
         keep = set(args.kernels.split(","))
@@ -436,6 +488,9 @@ def main():
     ap.add_argument("--baseline-members", type=int, default=4,
                     help="members timed one by one on the single-system FP64 path (c4-ensemble)")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 FP32 ILU(0) factors")
+    ap.add_argument("--ilu-blocks", default="4x4",
+                    help="block ILU0 subdomain boxes: 'BXxBY' columns over the full depth, "
+                         "'BXxBYxBZ', or 'none' for the single-block ILU(0)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="time budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -469,30 +524,53 @@ def main():
     if args.steps is None:
         args.steps = 30
     case = cases.config2()
-    g = opm.GpuModel(case, device="cuda:0")
     opts = opm.default_opts(case, precision=args.precision)
     dt = case.report_dt[0]
-    y = g.initial_state()
     stream = torch.cuda.current_stream()
+    blocks = parse_blocks(args.ilu_blocks, case)
 
-    for _ in range(args.warmup):
-        st, rep = g.advance(y, dt, opts)
-        if st != opm.OK:
-            raise RuntimeError(f"warm-up step failed: {opm._strerror(st)}")
-    torch.cuda.synchronize()
-    reps = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st, rep = g.advance(y, dt, opts)
-        if st != opm.OK:
-            raise RuntimeError(f"timed step failed: {opm._strerror(st)}")
-        reps.append(rep.as_dict())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    def run(blk):
+        """Warm-up steps, then the timed report steps from the state they
+        leave (inputs resident in HBM)."""
+        g = opm.GpuModel(case, device="cuda:0", ilu_blocks=blk)
+        y = g.initial_state()
+        for _ in range(args.warmup):
+            st, rep = g.advance(y, dt, opts)
+            if st != opm.OK:
+                raise RuntimeError(f"warm-up step failed: {opm._strerror(st)}")
+        torch.cuda.synchronize()
+        reps = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            st, rep = g.advance(y, dt, opts)
+            if st != opm.OK:
+                raise RuntimeError(f"timed step failed: {opm._strerror(st)}")
+            reps.append(rep.as_dict())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return g, y, reps, wall
+
+    g, y, reps, wall = run(blocks)
     cni = sum(r["cell_newton_its"] for r in reps)
     newton = sum(r["newton_its"] for r in reps)
     lin = sum(r["lin_its"] for r in reps)
     value = cni / wall
+    other = None
+    if blocks is not None:   # the single-block ILU(0) on the same workload
+        g1, y1, reps1, wall1 = run(None)
+        c1 = sum(r["cell_newton_its"] for r in reps1)
+        n1 = sum(r["newton_its"] for r in reps1)
+        l1 = sum(r["lin_its"] for r in reps1)
+        yb, ys = y.cpu().numpy(), y1.cpu().numpy()
+        other = {"value": round(c1 / wall1, 1), "ms_per_step": round(1e3 * wall1 / args.steps, 3),
+                 "newton_its": n1, "lin_its_per_newton": round(l1 / max(n1, 1), 2),
+                 "preconditioner": "ILU(0) of the whole system (sec. 2.3.1), one workgroup "
+                                   "walking its 62 hyperplane levels",
+                 "final_state_vs_block": {
+                     "p_rel": float(abs(yb[:, 0] - ys[:, 0]).max() / abs(ys[:, 0]).max()),
+                     "s_abs": float(abs(yb[:, 1:] - ys[:, 1:]).max())},
+                 "speedup_of_block": round(value / (c1 / wall1), 3)}
+        del g1, y1
 
     # ---- dominant kernel: HIP-event timing of repeated launches ------------
     acc0 = g.accumulation(y)
@@ -537,19 +615,26 @@ def main():
     t_asm = timed(lambda: L.opm_assemble(pbp, sp(yk), sp(acc0), dt, sp(Rb), sp(Jb), sp(norms), s),
                   args.kernel_reps)
     n = g.n
-    sweep_b = sweep_bytes_per_cell(args.precision) * n
     spmv_b = spmv_bytes_per_cell(g.nnzb, n) * n
     asm_b = assemble_bytes(n, g.nnzb, g.nf)
+    if blocks is not None:
+        apply_class = "block_apply"
+        apply = {"seconds": t_apply, "bytes": block_sweep_bytes_per_cell(args.precision) * n,
+                 "kernel": f"block-ILU0 forward+backward sweeps (k_apply_blocks, one 64-thread "
+                           f"workgroup per subdomain, {g.pb.n_sub} subdomains)"}
+    else:
+        apply_class = "ilu0_apply"
+        apply = {"seconds": t_apply, "bytes": sweep_bytes_per_cell(args.precision) * n,
+                 "kernel": "ilu0 forward+backward sweeps (k_gather_rhs + k_apply_ring2, "
+                           "one workgroup of 512 threads)"}
     kernels = {
-        "ilu0_apply": {"seconds": t_apply, "bytes": sweep_b,
-                       "kernel": "ilu0 forward+backward sweeps (k_gather_rhs + k_apply_ring2, "
-                                 "one workgroup of 512 threads)"},
+        apply_class: apply,
         "spmv": {"seconds": t_spmv, "bytes": spmv_b, "kernel": "k_spmv"},
         "assemble": {"seconds": t_asm, "bytes": asm_b, "kernel": "k_assemble+k_norms_final"},
     }
     # time share of each kernel class in one Newton iteration of the run
     its_per_newton = lin / max(newton, 1)
-    share = {"ilu0_apply": 2 * its_per_newton * t_apply, "spmv": 2 * its_per_newton * t_spmv,
+    share = {apply_class: 2 * its_per_newton * t_apply, "spmv": 2 * its_per_newton * t_spmv,
              "assemble": t_asm}
     dom = max(share, key=share.get)
     k = kernels[dom]
@@ -560,6 +645,11 @@ def main():
                 "kernel": k["kernel"], "avg_launch_us": round(k["seconds"] * 1e6, 3),
                 "bytes_per_launch": int(k["bytes"])}
 
+    if blocks is not None:
+        precond = (f"block ILU0 (sec. 2.5, one block per subdomain): {g.pb.n_sub} column "
+                   f"subdomains of {blocks[0]}x{blocks[1]}x{blocks[2]} cells")
+    else:
+        precond = "ILU(0) of the whole system (sec. 2.3.1)"
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "cell-Newton-iterations/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -569,7 +659,8 @@ def main():
         "config": {"workload": "24x25x15 waterflood, 9000 cells, 10-day implicit steps",
                    "n_cells": n, "nnzb": g.nnzb, "ilu_levels": g.n_levels,
                    "newton_tol_cnv": case.tol_cnv, "lin_rtol": case.lin_rtol,
-                   "precision": "fp64" if args.precision == 0 else "mixed"},
+                   "precision": "fp64" if args.precision == 0 else "mixed",
+                   "preconditioner": precond},
         "roofline": roofline,
         "breakdown": {
             "newton_its": newton, "lin_its_per_newton": round(its_per_newton, 2),
@@ -581,6 +672,8 @@ def main():
             "kernels_gbs": {kk: round(v["bytes"] / v["seconds"] / 1e9, 1) for kk, v in kernels.items()},
         },
     }
+    if other is not None:
+        line["single_block_ilu0"] = other
 
     if not args.no_cpu:
         import oracle

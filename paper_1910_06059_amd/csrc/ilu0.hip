@@ -218,8 +218,11 @@ __global__ __launch_bounds__(NT) void k_factor_blocks(Topo t, const double* J, I
 }
 
 // Sweep records of the block ILU0, straight from the Jacobian (after the
-// pivot recursion): lower blocks and D^{-1}, upper blocks and D^{-1}, the
-// neighbours by slot in the subdomain and the row's cell.
+// pivot recursion).  Record (row, a) holds row a of the three off-diagonal
+// blocks (lower ones forward, upper ones backward) and row a of D^{-1}: 12
+// values as 16-byte chunks, chunk c of (position p, a) at [(c ns + p) 3 + a]
+// so that the three lanes of a row and consecutive rows read consecutive
+// chunks.  Index records: neighbours by slot in the subdomain, and the cell.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pack_block_records(Topo t, const double* J,
                                                                IluView<T> v,
@@ -228,66 +231,92 @@ __global__ __launch_bounds__(kBlock) void k_pack_block_records(Topo t, const dou
   if (pos >= t.n) return;
   constexpr size_t kV = 16 / sizeof(T);
   const size_t ns = (size_t)v.ns, p = (size_t)pos;
-  auto put = [&](T* rec, int e, T val) { rec[((size_t)e / kV * ns + p) * kV + (size_t)e % kV] = val; };
+  auto put = [&](T* rec, int a, int e, T val) {
+    rec[(((size_t)e / kV * ns + p) * 3 + a) * kV + (size_t)e % kV] = val;
+  };
 #pragma unroll
   for (int sl = 0; sl < 3; ++sl) {
     const int bl = t.lo_blk[3 * p + sl], bu = t.up_blk[3 * p + sl];
     const double* Al = J + 9 * (size_t)(bl < 0 ? 0 : bl);
     const double* Au = J + 9 * (size_t)(bu < 0 ? 0 : bu);
 #pragma unroll
-    for (int e = 0; e < 9; ++e) {
-      put(v.rec_f, 9 * sl + e, bl < 0 ? (T)0 : (T)Al[e]);
-      put(v.rec_b, 9 * sl + e, bu < 0 ? (T)0 : (T)Au[e]);
-    }
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        put(v.rec_f, a, 3 * sl + c, bl < 0 ? (T)0 : (T)Al[3 * a + c]);
+        put(v.rec_b, a, 3 * sl + c, bu < 0 ? (T)0 : (T)Au[3 * a + c]);
+      }
   }
 #pragma unroll
-  for (int e = 0; e < 9; ++e) {
-    const T d = v.dinv[(size_t)e * ns + p];
-    put(v.rec_f, 27 + e, d);
-    put(v.rec_b, 27 + e, d);
-  }
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T d = v.dinv[(size_t)(3 * a + c) * ns + p];
+      put(v.rec_f, a, 9 + c, d);
+      put(v.rec_b, a, 9 + c, d);
+    }
   auto nb = [&](int kp) { return kp < 0 ? kp : slot[kp]; };
   const int cell = t.perm[pos];
   v.idx_f[pos] = int4v{nb(t.lo_pos[3 * p]), nb(t.lo_pos[3 * p + 1]), nb(t.lo_pos[3 * p + 2]), cell};
   v.idx_b[pos] = int4v{nb(t.up_pos[3 * p]), nb(t.up_pos[3 * p + 1]), nb(t.up_pos[3 * p + 2]), cell};
 }
 
-// A sweep of one subdomain is a three-stage pipeline over its levels: the
-// neighbour slots and cells of level k+2 and the records and right-hand
-// sides of level k+1 are loaded while level k is computed.  The right-hand
-// side of the forward sweep is r at the row's cell, so its address needs
-// the index loaded one level earlier; loading the index in the same stage
-// would make the wait for it (the load counter drains in order) also wait
-// for the previous level's data.  No branch separates a load from its use
-// (lanes past a level's end load a clamped row and store nothing), so the
-// compiler never has to assume a load of an earlier level still in flight.
+// Block-ILU0 sweep rows are spread over three lanes, one per equation a:
+// lane a holds row a of the three neighbour blocks and of D^{-1} (12
+// values, the record of (row, a)), computes its partial sum
+//   acc_a = r_a - sum_s A_s[a][.] x_s   (forward; backward with + and 0),
+// takes acc_b of the two other lanes of the row by cross-lane shuffle and
+// finishes with D^{-1}[a][.] acc.  The arithmetic and its order per value
+// are those of the other sweep kernels (bitwise equal results).  A
+// wavefront holds 21 rows (lanes 3q + a, lane 63 idle).
+constexpr int kRowsPerWave = 21;
+
+__device__ __forceinline__ int block_lane_row() {
+  return (int)(threadIdx.x >> 6) * kRowsPerWave + (int)(threadIdx.x & 63u) / 3;
+}
+__device__ __forceinline__ int block_lane_eq() {
+  const int l = (int)(threadIdx.x & 63u);
+  return l < 63 ? l % 3 : 3;
+}
+
 template <typename T>
 struct BlockJob {
-  T a[27];
-  T D[9];
-  T rhs[3];
+  T a[9];      // row a of the three neighbour blocks
+  T d[3];      // row a of D^{-1}
+  T rhs;       // component a of r (forward) or y (backward)
   int kp[3];   // neighbour slots (-1 if absent)
   int cell;
   int slot;
   bool live;
 };
 
+// A sweep of one subdomain is a three-stage pipeline over its levels: the
+// neighbour slots and cells of level k+2 and the records and right-hand
+// sides of level k+1 are loaded while level k is computed.  The right-hand
+// side of the forward sweep is r at the row's cell, so its address needs
+// the index loaded earlier; loading the index in the same stage would make
+// the wait for it (the load counter drains in order) also wait for the
+// previous level's data.  No branch separates a load from its use (lanes
+// past a level's end load a clamped row and store nothing), so the
+// compiler never has to assume a load of an earlier level still in flight.
+
 // Level k of the sweep (ascending levels forward, descending backward;
 // past the last one: the last one) and the lane's clamped row position.
 template <bool FWD>
-__device__ __forceinline__ void block_row_pos(const int* lp, int nlev, int k, int& p0, int& p1,
-                                              int& pos) {
+__device__ __forceinline__ void block_row_pos(const int* lp, int nlev, int k, int row, int& p0,
+                                              int& p1, int& pos) {
   const int kk = k < nlev ? k : nlev - 1;
   const int l = FWD ? kk : nlev - 1 - kk;
   p0 = lp[2 * l];
   p1 = lp[2 * l + 1];
-  pos = max(min(p0 + (int)threadIdx.x, p1 - 1), 0);
+  pos = max(min(p0 + row, p1 - 1), 0);
 }
 
 template <typename T, bool FWD>
-__device__ __forceinline__ int4v block_index(IluView<T> v, const int* lp, int nlev, int k) {
+__device__ __forceinline__ int4v block_index(IluView<T> v, const int* lp, int nlev, int k,
+                                             int row) {
   int p0, p1, pos;
-  block_row_pos<FWD>(lp, nlev, k, p0, p1, pos);
+  block_row_pos<FWD>(lp, nlev, k, row, p0, p1, pos);
   return (FWD ? v.idx_f : v.idx_b)[(unsigned)pos];
 }
 
@@ -295,13 +324,15 @@ __device__ __forceinline__ int4v block_index(IluView<T> v, const int* lp, int nl
 // including it (backward).
 template <typename T, bool FWD>
 __device__ __forceinline__ void block_data(IluView<T> v, const double* r, const T* zl,
-                                           const int* lp, int nlev, int k, int base, int4v ix,
-                                           BlockJob<T>& j) {
+                                           const int* lp, int nlev, int k, int row, int base,
+                                           int4v ix, BlockJob<T>& j) {
   typedef typename Vec16<T>::type V;
-  constexpr unsigned kV = 16 / sizeof(T);
+  constexpr unsigned kV = 16 / sizeof(T), kC = 12 / kV;
+  const int eq = block_lane_eq();
+  const unsigned a = (unsigned)min(eq, 2);
   int p0, p1, pos;
-  block_row_pos<FWD>(lp, nlev, k, p0, p1, pos);
-  j.live = k < nlev && p0 + (int)threadIdx.x < p1;
+  block_row_pos<FWD>(lp, nlev, k, row, p0, p1, pos);
+  j.live = k < nlev && p0 + row < p1 && eq < 3;
   const unsigned ns = (unsigned)v.ns, up = (unsigned)pos;
   j.kp[0] = ix.x;
   j.kp[1] = ix.y;
@@ -310,26 +341,23 @@ __device__ __forceinline__ void block_data(IluView<T> v, const double* r, const 
   j.slot = (FWD ? base : base - (p1 - p0)) + (pos - p0);
   const V* rec = reinterpret_cast<const V*>(FWD ? v.rec_f : v.rec_b);
 #pragma unroll
-  for (unsigned c = 0; c < (unsigned)kRecValues / kV; ++c) {
-    const V w = rec[c * ns + up];
+  for (unsigned c = 0; c < kC; ++c) {
+    const V w = rec[(c * ns + up) * 3u + a];
 #pragma unroll
     for (unsigned q = 0; q < kV; ++q) {
       const unsigned e = c * kV + q;
-      if (e < 27u)
+      if (e < 9u)
         j.a[e] = w[q];
       else
-        j.D[e - 27u] = w[q];
+        j.d[e - 9u] = w[q];
     }
   }
   if (FWD) {
-#pragma unroll
-    for (unsigned c = 0; c < 3; ++c) j.rhs[c] = (T)r[3u * (unsigned)j.cell + c];
+    j.rhs = (T)r[3u * (unsigned)j.cell + a];
   } else {
     // y of the row (forward result); slots of lanes past the level's end
     // stay inside the subdomain
-    const unsigned sl = (unsigned)max(j.slot, 0);
-#pragma unroll
-    for (unsigned c = 0; c < 3; ++c) j.rhs[c] = zl[3u * sl + c];
+    j.rhs = zl[3u * (unsigned)max(j.slot, 0) + a];
   }
   // keep every load of the stage here, ahead of the computation of the
   // current level (the compiler would otherwise sink some of them to their
@@ -337,78 +365,46 @@ __device__ __forceinline__ void block_data(IluView<T> v, const double* r, const 
   asm volatile("" ::: "memory");
 }
 
-// The arithmetic of a sweep row, in the same order as the other sweep
-// kernels (results are bitwise equal).  Every lane computes; only rows of
-// the level store.
+// Every lane computes (the shuffles need all lanes); only rows of the level
+// store.
 template <typename T, bool FWD>
 __device__ __forceinline__ void block_row(const BlockJob<T>& j, T* zl, double* x) {
-  T acc[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) acc[c] = FWD ? j.rhs[c] : (T)0;
+  const int eq = block_lane_eq();
+  const unsigned a = (unsigned)min(eq, 2);
+  T acc = FWD ? j.rhs : (T)0;
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     const int kp = j.kp[s];
     const bool has = kp >= 0;
     const T* w = zl + 3u * (unsigned)(has ? kp : 0);
     const T x0 = has ? w[0] : (T)0, x1 = has ? w[1] : (T)0, x2 = has ? w[2] : (T)0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const T t = j.a[9 * s + 3 * a] * x0 + j.a[9 * s + 3 * a + 1] * x1 +
-                  j.a[9 * s + 3 * a + 2] * x2;
-      acc[a] = FWD ? acc[a] - t : acc[a] + t;
-    }
+    const T t = j.a[3 * s] * x0 + j.a[3 * s + 1] * x1 + j.a[3 * s + 2] * x2;
+    acc = FWD ? acc - t : acc + t;
   }
-  T out[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const T d = j.D[3 * a] * acc[0] + j.D[3 * a + 1] * acc[1] + j.D[3 * a + 2] * acc[2];
-    out[a] = FWD ? d : j.rhs[a] - d;
-  }
+  const int lane0 = (int)(threadIdx.x & 63u) - (int)a;
+  const T acc0 = __shfl(acc, lane0, 64), acc1 = __shfl(acc, lane0 + 1, 64),
+          acc2 = __shfl(acc, lane0 + 2, 64);
+  const T d = j.d[0] * acc0 + j.d[1] * acc1 + j.d[2] * acc2;
+  const T out = FWD ? d : j.rhs - d;
   if (!j.live) return;
-  T* w = zl + 3u * (unsigned)j.slot;
-#pragma unroll
-  for (unsigned c = 0; c < 3; ++c) w[c] = out[c];
-  if (!FWD) {
-#pragma unroll
-    for (unsigned c = 0; c < 3; ++c) x[3u * (unsigned)j.cell + c] = (double)out[c];
-  }
+  zl[3u * (unsigned)j.slot + a] = out;
+  if (!FWD) x[3u * (unsigned)j.cell + a] = (double)out;
 }
 
-// Rows of a level beyond the first NT (subdomains with wider levels).
+// Rows of a level beyond the first NT / 64 * 21 (subdomains with wider
+// levels).
 template <typename T, int NT, bool FWD>
 __device__ __forceinline__ void block_extra(IluView<T> v, const double* r, T* zl, double* x,
                                             const int* lp, int nlev, int k, int base) {
+  constexpr int kRows = NT / 64 * kRowsPerWave;
   const int l = FWD ? k : nlev - 1 - k;
-  const int p0 = lp[2 * l], p1 = lp[2 * l + 1];
-  const int b0 = FWD ? base : base - (p1 - p0);
-  for (int pos = p0 + NT + (int)threadIdx.x; pos < p1; pos += NT) {
+  const int w = lp[2 * l + 1] - lp[2 * l];
+  // uniform trip count: every lane joins the shuffles of every round
+  for (int r0 = kRows; r0 < w; r0 += kRows) {
+    const int row = r0 + block_lane_row();
+    const int4v ix = block_index<T, FWD>(v, lp, nlev, k, row);
     BlockJob<T> j;
-    const unsigned ns = (unsigned)v.ns, up = (unsigned)pos;
-    typedef typename Vec16<T>::type V;
-    constexpr unsigned kV = 16 / sizeof(T);
-    const int4v ix = (FWD ? v.idx_f : v.idx_b)[up];
-    j.kp[0] = ix.x;
-    j.kp[1] = ix.y;
-    j.kp[2] = ix.z;
-    j.cell = ix.w;
-    j.slot = b0 + (pos - p0);
-    j.live = true;
-    const V* rec = reinterpret_cast<const V*>(FWD ? v.rec_f : v.rec_b);
-#pragma unroll
-    for (unsigned c = 0; c < (unsigned)kRecValues / kV; ++c) {
-      const V w = rec[c * ns + up];
-#pragma unroll
-      for (unsigned q = 0; q < kV; ++q) {
-        const unsigned e = c * kV + q;
-        if (e < 27u)
-          j.a[e] = w[q];
-        else
-          j.D[e - 27u] = w[q];
-      }
-    }
-#pragma unroll
-    for (unsigned c = 0; c < 3; ++c)
-      j.rhs[c] = FWD ? (T)r[3u * (unsigned)j.cell + c] : zl[3u * (unsigned)j.slot + c];
+    block_data<T, FWD>(v, r, zl, lp, nlev, k, row, base, ix, j);
     block_row<T, FWD>(j, zl, x);
   }
 }
@@ -424,6 +420,7 @@ __device__ __forceinline__ void block_sweep(IluView<T> v, const double* r, T* zl
                                             const int* lp, int nlev, int nrows) {
   constexpr int ND = DEPTH + 1, NI = 3;
   constexpr int P = ND % NI == 0 ? ND : ND * NI;
+  const int row = block_lane_row();
   auto next_base = [&](int b, int k) {
     const int l = FWD ? k : nlev - 1 - k;
     const int w = k < nlev ? lp[2 * l + 1] - lp[2 * l] : 0;
@@ -432,9 +429,9 @@ __device__ __forceinline__ void block_sweep(IluView<T> v, const double* r, T* zl
   int ik = 0;                                 // index stage: next level
   int dk = 0, db = FWD ? 0 : nrows;           // data stage: next level and its base
   int ck = 0, cb = db;                        // compute stage
-  auto index = [&]() { return block_index<T, FWD>(v, lp, nlev, ik++); };
+  auto index = [&]() { return block_index<T, FWD>(v, lp, nlev, ik++, row); };
   auto data = [&](int4v ix, BlockJob<T>& j) {
-    block_data<T, FWD>(v, r, zl, lp, nlev, dk, db, ix, j);
+    block_data<T, FWD>(v, r, zl, lp, nlev, dk, row, db, ix, j);
     db = next_base(db, dk++);
   };
   auto compute = [&](const BlockJob<T>& j) {
@@ -533,10 +530,18 @@ int allow_lds(K kernel, int slot) {
   return OPM_OK;
 }
 
-// Threads of a block-ILU0 workgroup: the widest level of a subdomain
-// rounded up to a wavefront, at most 256 (wider levels loop).
+// Threads of a block-ILU0 factorisation workgroup (a row per thread) and of
+// a sweep workgroup (21 rows per wavefront): the widest level of a
+// subdomain rounded up to a wavefront, at most 256 (wider levels loop).
 int block_threads(const opm_problem* pb) {
   return pb->max_width <= 64 ? 64 : pb->max_width <= 128 ? 128 : 256;
+}
+int block_sweep_threads(const opm_problem* pb) {
+  const int waves = (pb->max_width + kRowsPerWave - 1) / kRowsPerWave;
+  return waves <= 1 ? 64 : waves <= 2 ? 128 : 256;
+}
+bool block_sweep_wide(const opm_problem* pb) {
+  return pb->max_width > block_sweep_threads(pb) / 64 * kRowsPerWave;
 }
 
 template <typename T>
@@ -610,7 +615,7 @@ int apply_impl(const opm_problem* pb, void* ilu, const double* r, double* x, int
     const int slot = sizeof(T) == 8 ? 40 : 52;
 #define OPM_BLOCKS(NT, D, SL)                                                                 \
   do {                                                                                        \
-    if (pb->max_width <= NT) {                                                                \
+    if (!block_sweep_wide(pb)) {                                                              \
       OPM_TRY(allow_lds(k_apply_blocks<T, NT, false, D>, slot + SL));                         \
       hipLaunchKernelGGL((k_apply_blocks<T, NT, false, D>), dim3(pb->n_sub), dim3(NT), lds, s, \
                          v, pb->sub_level_ptr, pb->n_sub, pb->n_levels, pb->max_sub, r, x,    \
@@ -625,7 +630,7 @@ int apply_impl(const opm_problem* pb, void* ilu, const double* r, double* x, int
     // one level of data in flight (two measured no faster on 9000- to
     // 500000-cell systems)
     const int depth = g_block_depth != 0 ? g_block_depth : 1;
-    switch (block_threads(pb) * 4 + depth) {
+    switch (block_sweep_threads(pb) * 4 + depth) {
       case 64 * 4 + 1: OPM_BLOCKS(64, 1, 0); break;
       case 128 * 4 + 1: OPM_BLOCKS(128, 1, 2); break;
       case 256 * 4 + 1: OPM_BLOCKS(256, 1, 4); break;
