@@ -28,6 +28,7 @@
 //  - one launch per level over many workgroups (large systems).
 // Packing the off-diagonal blocks into level order does not depend on the
 // levels and runs as one wide kernel over all rows.
+#include "krylov_dev.h"
 #include "solver_dev.h"
 
 namespace opm {
@@ -283,11 +284,21 @@ template <typename T>
 struct BlockJob {
   T a[9];      // row a of the three neighbour blocks
   T d[3];      // row a of D^{-1}
-  T rhs;       // component a of r (forward) or y (backward)
+  T rhs;       // backward: component a of y
+  double u[3]; // forward: the vector values the right-hand side is made of
   int kp[3];   // neighbour slots (-1 if absent)
   int cell;
   int slot;
   bool live;
+};
+
+// Forward right-hand side of a sweep: r itself, or (fused with BiCGStab)
+// p = r + beta (p - omega v) or s = r - alpha v, written back for the rows
+// of the level.
+struct BlockRhs {
+  const double* r;
+  kry::Fused f;
+  double beta, omega, alpha;
 };
 
 // A sweep of one subdomain is a three-stage pipeline over its levels: the
@@ -322,8 +333,8 @@ __device__ __forceinline__ int4v block_index(IluView<T> v, const int* lp, int nl
 
 // base: rows of the subdomain before the level (forward) or up to and
 // including it (backward).
-template <typename T, bool FWD>
-__device__ __forceinline__ void block_data(IluView<T> v, const double* r, const T* zl,
+template <typename T, bool FWD, int MODE>
+__device__ __forceinline__ void block_data(IluView<T> v, const BlockRhs& q, const T* zl,
                                            const int* lp, int nlev, int k, int row, int base,
                                            int4v ix, BlockJob<T>& j) {
   typedef typename Vec16<T>::type V;
@@ -353,7 +364,17 @@ __device__ __forceinline__ void block_data(IluView<T> v, const double* r, const 
     }
   }
   if (FWD) {
-    j.rhs = (T)r[3u * (unsigned)j.cell + a];
+    const unsigned i = 3u * (unsigned)j.cell + a;
+    if (MODE == kry::kFuseNone) j.u[0] = q.r[i];
+    if (MODE == kry::kFuseBegin) {
+      j.u[0] = q.f.r[i];
+      j.u[1] = q.f.p[i];
+      j.u[2] = q.f.v[i];
+    }
+    if (MODE == kry::kFuseS) {
+      j.u[0] = q.f.r[i];
+      j.u[1] = q.f.v[i];
+    }
   } else {
     // y of the row (forward result); slots of lanes past the level's end
     // stay inside the subdomain
@@ -367,11 +388,18 @@ __device__ __forceinline__ void block_data(IluView<T> v, const double* r, const 
 
 // Every lane computes (the shuffles need all lanes); only rows of the level
 // store.
-template <typename T, bool FWD>
-__device__ __forceinline__ void block_row(const BlockJob<T>& j, T* zl, double* x) {
+template <typename T, bool FWD, int MODE>
+__device__ __forceinline__ void block_row(const BlockJob<T>& j, T* zl, double* x,
+                                          const BlockRhs& q, double& ss) {
   const int eq = block_lane_eq();
   const unsigned a = (unsigned)min(eq, 2);
-  T acc = FWD ? j.rhs : (T)0;
+  // forward right-hand side (the same expressions as the unfused vector
+  // kernels of the iteration)
+  double u = j.u[0];
+  if (FWD && MODE == kry::kFuseBegin) u = j.u[0] + q.beta * (j.u[1] - q.omega * j.u[2]);
+  if (FWD && MODE == kry::kFuseS) u = j.u[0] - q.alpha * j.u[1];
+  const T rhs = FWD ? (T)u : j.rhs;
+  T acc = FWD ? rhs : (T)0;
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     const int kp = j.kp[s];
@@ -389,13 +417,19 @@ __device__ __forceinline__ void block_row(const BlockJob<T>& j, T* zl, double* x
   if (!j.live) return;
   zl[3u * (unsigned)j.slot + a] = out;
   if (!FWD) x[3u * (unsigned)j.cell + a] = (double)out;
+  if (FWD && MODE == kry::kFuseBegin) q.f.p[3u * (unsigned)j.cell + a] = u;
+  if (FWD && MODE == kry::kFuseS) {
+    q.f.s[3u * (unsigned)j.cell + a] = u;
+    ss += u * u;
+  }
 }
 
 // Rows of a level beyond the first NT / 64 * 21 (subdomains with wider
 // levels).
-template <typename T, int NT, bool FWD>
-__device__ __forceinline__ void block_extra(IluView<T> v, const double* r, T* zl, double* x,
-                                            const int* lp, int nlev, int k, int base) {
+template <typename T, int NT, bool FWD, int MODE>
+__device__ __forceinline__ void block_extra(IluView<T> v, const BlockRhs& q, T* zl, double* x,
+                                            const int* lp, int nlev, int k, int base,
+                                            double& ss) {
   constexpr int kRows = NT / 64 * kRowsPerWave;
   const int l = FWD ? k : nlev - 1 - k;
   const int w = lp[2 * l + 1] - lp[2 * l];
@@ -404,8 +438,8 @@ __device__ __forceinline__ void block_extra(IluView<T> v, const double* r, T* zl
     const int row = r0 + block_lane_row();
     const int4v ix = block_index<T, FWD>(v, lp, nlev, k, row);
     BlockJob<T> j;
-    block_data<T, FWD>(v, r, zl, lp, nlev, k, row, base, ix, j);
-    block_row<T, FWD>(j, zl, x);
+    block_data<T, FWD, MODE>(v, q, zl, lp, nlev, k, row, base, ix, j);
+    block_row<T, FWD, MODE>(j, zl, x, q, ss);
   }
 }
 
@@ -415,9 +449,9 @@ __device__ __forceinline__ void block_extra(IluView<T> v, const double* r, T* zl
 // earlier, so no load waits for one issued in the previous step.  The
 // stages rotate through register rings (3 indices, DEPTH + 1 jobs), fully
 // unrolled over a period of P steps so that every ring slot is a register.
-template <typename T, int NT, bool FWD, bool WIDE, int DEPTH>
-__device__ __forceinline__ void block_sweep(IluView<T> v, const double* r, T* zl, double* x,
-                                            const int* lp, int nlev, int nrows) {
+template <typename T, int NT, bool FWD, bool WIDE, int DEPTH, int MODE>
+__device__ __forceinline__ void block_sweep(IluView<T> v, const BlockRhs& q, T* zl, double* x,
+                                            const int* lp, int nlev, int nrows, double& ss) {
   constexpr int ND = DEPTH + 1, NI = 3;
   constexpr int P = ND % NI == 0 ? ND : ND * NI;
   const int row = block_lane_row();
@@ -431,12 +465,12 @@ __device__ __forceinline__ void block_sweep(IluView<T> v, const double* r, T* zl
   int ck = 0, cb = db;                        // compute stage
   auto index = [&]() { return block_index<T, FWD>(v, lp, nlev, ik++, row); };
   auto data = [&](int4v ix, BlockJob<T>& j) {
-    block_data<T, FWD>(v, r, zl, lp, nlev, dk, row, db, ix, j);
+    block_data<T, FWD, MODE>(v, q, zl, lp, nlev, dk, row, db, ix, j);
     db = next_base(db, dk++);
   };
   auto compute = [&](const BlockJob<T>& j) {
-    block_row<T, FWD>(j, zl, x);
-    if (WIDE) block_extra<T, NT, FWD>(v, r, zl, x, lp, nlev, ck, cb);
+    block_row<T, FWD, MODE>(j, zl, x, q, ss);
+    if (WIDE) block_extra<T, NT, FWD, MODE>(v, q, zl, x, lp, nlev, ck, cb, ss);
     cb = next_base(cb, ck++);
     __syncthreads();
   };
@@ -465,11 +499,30 @@ __device__ __forceinline__ void block_sweep(IluView<T> v, const double* r, T* zl
 // x = M^{-1} r for the block ILU0: forward then backward sweep of one
 // subdomain per workgroup, the subdomain's y and x in LDS (3 values per
 // row, by slot), then the level bounds of the subdomain (2 ints per level).
-template <typename T, int NT, bool WIDE, int DEPTH>
+// MODE (kry::FusedMode): the forward right-hand side is r, or the p or s
+// update of a BiCGStab iteration, preceded by the tests of that iteration
+// (every workgroup evaluates them on the same partials and returns at once
+// if the iteration does not run); with the s update the workgroup's partial
+// of <s, s> goes to f.part_out.
+template <typename T, int NT, bool WIDE, int DEPTH, int MODE>
 __global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t* slp, int nsub,
                                                       int nlev, int max_sub, const double* r,
-                                                      double* x, const int32_t* skip) {
-  if (skip && *skip != 0) return;
+                                                      double* x, const int32_t* skip,
+                                                      kry::Fused f) {
+  __shared__ double red[NT / 64];
+  __shared__ int word;
+  BlockRhs q{r, f, 0.0, 0.0, 0.0};
+  if (MODE == kry::kFuseNone) {
+    if (skip && *skip != 0) return;
+  } else {
+    const int state = kry::read_state(f.sc, &word);
+    if (MODE == kry::kFuseBegin &&
+        !kry::begin_iteration<NT>(*f.sc, state, f.part_a, f.part_b, f.n_part, red, q.beta,
+                                  q.omega))
+      return;
+    if (MODE == kry::kFuseS && !kry::alpha_step<NT>(*f.sc, state, f.part_a, f.n_part, red, q.alpha))
+      return;
+  }
   extern __shared__ unsigned char smem[];
   T* zl = reinterpret_cast<T*>(smem);
   int* lp = reinterpret_cast<int*>(smem + sizeof(T) * 3 * (size_t)max_sub);
@@ -481,8 +534,13 @@ __global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t
   __syncthreads();
   int nrows = 0;
   for (int l = 0; l < nlev; ++l) nrows += lp[2 * l + 1] - lp[2 * l];
-  block_sweep<T, NT, true, WIDE, DEPTH>(v, r, zl, x, lp, nlev, nrows);
-  block_sweep<T, NT, false, WIDE, DEPTH>(v, r, zl, x, lp, nlev, nrows);
+  double ss = 0.0;
+  block_sweep<T, NT, true, WIDE, DEPTH, MODE>(v, q, zl, x, lp, nlev, nrows, ss);
+  if (MODE == kry::kFuseS) {
+    const double tot = block_sum<NT>(ss, red);
+    if (threadIdx.x == 0) f.part_out[blockIdx.x] = tot;
+  }
+  block_sweep<T, NT, false, WIDE, DEPTH, MODE>(v, q, zl, x, lp, nlev, nrows, ss);
 }
 
 // Both sweeps by one workgroup of NT threads through the LDS ring with
@@ -517,14 +575,18 @@ size_t factor_lds(const opm_problem* pb) { return sizeof(double) * 2 * 9 * (size
 
 // one flag per (kernel, precision): slots 0-5 level-window kernels, 12-21
 // (FP64) and 24-33 (FP32) ring sweeps, 34-39 block-ILU0 factorisation,
-// 40-51 (FP64) and 52-63 (FP32) block-ILU0 sweeps
-bool g_lds_attr_set[64] = {};
+// 64-99 (FP64) and 100-135 (FP32) block-ILU0 sweeps (12 per fused mode)
+bool g_lds_attr_set[136] = {};
 
+// Dynamic LDS up to the 160 KB of a workgroup less the kernel's static LDS.
 template <typename K>
 int allow_lds(K kernel, int slot) {
   if (!g_lds_attr_set[slot]) {
+    hipFuncAttributes at;
+    OPM_TRY_HIP(hipFuncGetAttributes(&at, reinterpret_cast<const void*>(kernel)));
     OPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    160 * 1024 - (int)at.sharedSizeBytes));
     g_lds_attr_set[slot] = true;
   }
   return OPM_OK;
@@ -605,43 +667,48 @@ int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* stat
   return OPM_OK;
 }
 
+// One workgroup per subdomain, both sweeps in one launch.
+template <typename T, int MODE>
+int apply_blocks(const opm_problem* pb, IluView<T> v, const double* r, double* x,
+                 const int32_t* skip, const kry::Fused& f, hipStream_t s) {
+  const size_t lds = block_lds<T>(pb);
+  const int slot = (sizeof(T) == 8 ? 64 : 100) + 12 * MODE;
+#define OPM_BLOCKS(NT, D, SL)                                                                    \
+  do {                                                                                           \
+    if (!block_sweep_wide(pb)) {                                                                 \
+      OPM_TRY(allow_lds(k_apply_blocks<T, NT, false, D, MODE>, slot + SL));                      \
+      hipLaunchKernelGGL((k_apply_blocks<T, NT, false, D, MODE>), dim3(pb->n_sub), dim3(NT), lds, \
+                         s, v, pb->sub_level_ptr, pb->n_sub, pb->n_levels, pb->max_sub, r, x,    \
+                         skip, f);                                                               \
+    } else {                                                                                     \
+      OPM_TRY(allow_lds(k_apply_blocks<T, NT, true, D, MODE>, slot + SL + 1));                   \
+      hipLaunchKernelGGL((k_apply_blocks<T, NT, true, D, MODE>), dim3(pb->n_sub), dim3(NT), lds,  \
+                         s, v, pb->sub_level_ptr, pb->n_sub, pb->n_levels, pb->max_sub, r, x,    \
+                         skip, f);                                                               \
+    }                                                                                            \
+  } while (0)
+  // one level of data in flight (two measured no faster on 9000- to
+  // 500000-cell systems; the fused forms only have one)
+  const int depth = MODE == kry::kFuseNone && g_block_depth == 2 ? 2 : 1;
+  switch (block_sweep_threads(pb) * 4 + depth) {
+    case 64 * 4 + 1: OPM_BLOCKS(64, 1, 0); break;
+    case 128 * 4 + 1: OPM_BLOCKS(128, 1, 2); break;
+    case 256 * 4 + 1: OPM_BLOCKS(256, 1, 4); break;
+    case 64 * 4 + 2: OPM_BLOCKS(64, MODE == kry::kFuseNone ? 2 : 1, 6); break;
+    case 128 * 4 + 2: OPM_BLOCKS(128, MODE == kry::kFuseNone ? 2 : 1, 8); break;
+    default: OPM_BLOCKS(256, MODE == kry::kFuseNone ? 2 : 1, 10); break;
+  }
+#undef OPM_BLOCKS
+  OPM_TRY_HIP(hipGetLastError());
+  return OPM_OK;
+}
+
 template <typename T>
 int apply_impl(const opm_problem* pb, void* ilu, const double* r, double* x, int mode,
                hipStream_t s, const int32_t* skip) {
   IluView<T> v = view<T>(pb, ilu);
   Topo t = topo_of(pb);
-  if (mode == 2) {
-    const size_t lds = block_lds<T>(pb);
-    const int slot = sizeof(T) == 8 ? 40 : 52;
-#define OPM_BLOCKS(NT, D, SL)                                                                 \
-  do {                                                                                        \
-    if (!block_sweep_wide(pb)) {                                                              \
-      OPM_TRY(allow_lds(k_apply_blocks<T, NT, false, D>, slot + SL));                         \
-      hipLaunchKernelGGL((k_apply_blocks<T, NT, false, D>), dim3(pb->n_sub), dim3(NT), lds, s, \
-                         v, pb->sub_level_ptr, pb->n_sub, pb->n_levels, pb->max_sub, r, x,    \
-                         skip);                                                               \
-    } else {                                                                                  \
-      OPM_TRY(allow_lds(k_apply_blocks<T, NT, true, D>, slot + SL + 1));                      \
-      hipLaunchKernelGGL((k_apply_blocks<T, NT, true, D>), dim3(pb->n_sub), dim3(NT), lds, s,  \
-                         v, pb->sub_level_ptr, pb->n_sub, pb->n_levels, pb->max_sub, r, x,    \
-                         skip);                                                               \
-    }                                                                                         \
-  } while (0)
-    // one level of data in flight (two measured no faster on 9000- to
-    // 500000-cell systems)
-    const int depth = g_block_depth != 0 ? g_block_depth : 1;
-    switch (block_sweep_threads(pb) * 4 + depth) {
-      case 64 * 4 + 1: OPM_BLOCKS(64, 1, 0); break;
-      case 128 * 4 + 1: OPM_BLOCKS(128, 1, 2); break;
-      case 256 * 4 + 1: OPM_BLOCKS(256, 1, 4); break;
-      case 64 * 4 + 2: OPM_BLOCKS(64, 2, 6); break;
-      case 128 * 4 + 2: OPM_BLOCKS(128, 2, 8); break;
-      default: OPM_BLOCKS(256, 2, 10); break;
-    }
-#undef OPM_BLOCKS
-    OPM_TRY_HIP(hipGetLastError());
-    return OPM_OK;
-  }
+  if (mode == 2) return apply_blocks<T, kry::kFuseNone>(pb, v, r, x, skip, kry::Fused{}, s);
   if (mode == 0) {
     const int ring = ring_rows(pb->sweep_span, pb->max_level);
     const size_t ring_bytes = sizeof(T) * 3 * (size_t)ring;
@@ -742,6 +809,22 @@ int ilu_factor(const opm_problem* pb, const double* J, void* ilu, int precision,
   const int mode = sweep_mode(pb, precision);
   if (precision == OPM_PREC_MIXED) return factor_impl<float>(pb, J, ilu, status, mode, s);
   return factor_impl<double>(pb, J, ilu, status, mode, s);
+}
+
+// Block-ILU0 solve whose forward right-hand side is a BiCGStab vector
+// update (mode: kry::kFuseBegin or kry::kFuseS); only for sweep mode 2.
+int ilu_apply_fused(const opm_problem* pb, void* ilu, int precision, int mode,
+                    const kry::Fused& f, double* x, hipStream_t s) {
+  if (precision == OPM_PREC_MIXED) {
+    IluView<float> v = view<float>(pb, ilu);
+    return mode == kry::kFuseBegin
+               ? apply_blocks<float, kry::kFuseBegin>(pb, v, nullptr, x, nullptr, f, s)
+               : apply_blocks<float, kry::kFuseS>(pb, v, nullptr, x, nullptr, f, s);
+  }
+  IluView<double> v = view<double>(pb, ilu);
+  return mode == kry::kFuseBegin
+             ? apply_blocks<double, kry::kFuseBegin>(pb, v, nullptr, x, nullptr, f, s)
+             : apply_blocks<double, kry::kFuseS>(pb, v, nullptr, x, nullptr, f, s);
 }
 
 // skip (device, may be null): the sweeps return at once while *skip != 0.

@@ -12,24 +12,24 @@
 // between chunks.
 #include <algorithm>
 
+#include "krylov_dev.h"
 #include "solver_dev.h"
 
 namespace opm {
 
 int ilu_apply(const opm_problem* pb, void* ilu, int precision, const double* r, double* x,
               hipStream_t s, const int32_t* skip);
+int ilu_apply_fused(const opm_problem* pb, void* ilu, int precision, int mode,
+                    const kry::Fused& f, double* x, hipStream_t s);
 int sweep_mode(const opm_problem* pb, int precision = OPM_PREC_FP64);
 
 namespace {
 
-constexpr int kMaxGrid = 1024;   // workgroups of the vector kernels
-
-enum State : int32_t { kRunning = 0, kHalfPending = 1, kDone = 2 };
-
-struct Scalars {
-  double rho, rho0, alpha, omega, bnorm, tol, relres, pad;
-  int32_t state, status, its, half, maxit, pad2[3];
-};
+using kry::kDone;
+using kry::kHalfPending;
+using kry::kMaxGrid;
+using kry::kRunning;
+using kry::Scalars;
 
 struct Work {
   double *r, *rh, *p, *v, *ph, *s, *sh, *t;
@@ -59,11 +59,8 @@ Work carve(const opm_problem* pb, void* work) {
   return w;
 }
 
-// Sum of the G partials of a reduction, identical in every workgroup.
 __device__ __forceinline__ double sum_partials(const double* part, int G, double* sh) {
-  double v = 0.0;
-  for (int k = threadIdx.x; k < G; k += kBlock) v += part[k];
-  return block_sum<kBlock>(v, sh);
+  return kry::sum_partials<kBlock>(part, G, sh);
 }
 
 __device__ __forceinline__ void store_partial(double v, double* part, double* sh) {
@@ -130,42 +127,13 @@ __global__ __launch_bounds__(kBlock) void k_init2(Work w, int G, double rtol, in
 // residual of the previous iteration, then p = r + beta (p - omega v).
 __global__ __launch_bounds__(kBlock) void k_begin(int N, Work w, int G) {
   __shared__ double sh[kBlock / kWave];
+  __shared__ int word;
   Scalars& s = *w.sc;
-  const int state = s.state;
-  if (state != kRunning) {
-    if (state == kHalfPending && blockIdx.x == 0 && threadIdx.x == 0) s.state = kDone;
-    return;
-  }
-  const double rr = sum_partials(w.part_rr, G, sh);
-  const double rho = sum_partials(w.part_rhr, G, sh);
-  const int its = s.its;
-  const double rnorm = sqrt(rr);
-  int verdict = kRunning, status = OPM_OK;
-  if (rnorm <= s.tol) {
-    verdict = kDone;
-  } else if (its > 0 && s.omega == 0.0) {
-    verdict = kDone;
-    status = OPM_EBREAKDOWN;
-  } else if (its >= s.maxit) {
-    verdict = kDone;
-    status = OPM_ENOTCONV;
-  } else if (fabs(rho) < 1e-300) {
-    verdict = kDone;
-    status = OPM_EBREAKDOWN;
-  }
-  if (verdict == kDone) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      s.status = status;
-      s.relres = s.bnorm > 0.0 ? rnorm / s.bnorm : 0.0;
-      s.state = kDone;
-    }
-    return;
-  }
-  const double beta = its == 0 ? 0.0 : (rho / s.rho0) * (s.alpha / s.omega);
-  const double om = s.omega;
+  const int state = kry::read_state(w.sc, &word);
+  double beta, om;
+  if (!kry::begin_iteration<kBlock>(s, state, w.part_rr, w.part_rhr, G, sh, beta, om)) return;
   for (int k = blockIdx.x * kBlock + threadIdx.x; k < N; k += gridDim.x * kBlock)
     w.p[k] = w.r[k] + beta * (w.p[k] - om * w.v[k]);
-  if (blockIdx.x == 0 && threadIdx.x == 0) s.rho = rho;
 }
 
 // v = A p^ ; partials of <r^, v>.
@@ -190,17 +158,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_rv(int n, const int32_t* row_pt
 // alpha = rho / <r^, v>; s = r - alpha v; partials of <s, s>.
 __global__ __launch_bounds__(kBlock) void k_s(int N, Work w, int G) {
   __shared__ double sh[kBlock / kWave];
+  __shared__ int word;
   Scalars& sc = *w.sc;
-  if (sc.state != kRunning) return;
-  const double rv = sum_partials(w.part_rv, G, sh);
-  if (rv == 0.0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc.status = OPM_EBREAKDOWN;
-      sc.state = kDone;
-    }
-    return;
-  }
-  const double alpha = sc.rho / rv;
+  const int state = kry::read_state(w.sc, &word);
+  double alpha;
+  if (!kry::alpha_step<kBlock>(sc, state, w.part_rv, G, sh, alpha)) return;
   double ss = 0.0;
   for (int k = blockIdx.x * kBlock + threadIdx.x; k < N; k += gridDim.x * kBlock) {
     const double v = w.r[k] - alpha * w.v[k];
@@ -208,28 +170,31 @@ __global__ __launch_bounds__(kBlock) void k_s(int N, Work w, int G) {
     ss += v * v;
   }
   store_partial(ss, w.part_ss, sh);
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc.alpha = alpha;
 }
 
 // Half-step exit test ||s|| <= tol (one workgroup).
 __global__ __launch_bounds__(kBlock) void k_s_check(Work w, int G) {
   __shared__ double sh[kBlock / kWave];
-  Scalars& sc = *w.sc;
-  if (sc.state != kRunning) return;
-  const double snorm = sqrt(sum_partials(w.part_ss, G, sh));
-  if (threadIdx.x == 0 && snorm <= sc.tol) {
-    sc.half = 1;
-    sc.relres = snorm / sc.bnorm;
-    sc.its += 1;
-    sc.state = kHalfPending;
-  }
+  __shared__ int word;
+  const int state = kry::read_state(w.sc, &word);
+  kry::half_step_check<kBlock>(*w.sc, state, w.part_ss, G, sh);
 }
 
-// t = A s^ ; partials of <t, s> and <t, t>.
+// t = A s^ ; partials of <t, s> and <t, t>.  With CHECK, first the
+// half-step exit test on the nss partials of <s, s> (written by the sweep
+// that computed s).
+template <bool CHECK>
 __global__ __launch_bounds__(kBlock) void k_spmv_t(int n, const int32_t* row_ptr,
-                                                    const int32_t* col, const double* J, Work w) {
+                                                    const int32_t* col, const double* J, Work w,
+                                                    int nss) {
   __shared__ double sh[kBlock / kWave];
-  if (w.sc->state != kRunning) return;
+  __shared__ int word;
+  if (CHECK) {
+    const int state = kry::read_state(w.sc, &word);
+    if (!kry::half_step_check<kBlock>(*w.sc, state, w.part_ss, nss, sh)) return;
+  } else if (w.sc->state != kRunning) {
+    return;
+  }
   double ts = 0.0, tt = 0.0;
   const int lane = threadIdx.x & (kWave - 1), ng = spmv_groups(n);
   for (int g = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; g < ng;
@@ -321,19 +286,33 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
   hipLaunchKernelGGL(k_init2, dim3(1), dim3(kBlock), 0, st, w, G, rtol, maxit);
   OPM_TRY_HIP(hipGetLastError());
   const int chunk = chunk_size(pb);
+  // block ILU0 with one workgroup per subdomain: the p and s updates (and
+  // the tests before them) run inside the preconditioner sweeps
+  const bool fused = sweep_mode(pb, precision) == 2 && pb->n_sub <= kMaxGrid;
+  kry::Fused fb{w.r, w.p, w.v, nullptr, w.part_rr, w.part_rhr, G, nullptr, w.sc};
+  kry::Fused fs{w.r, nullptr, w.v, w.s, w.part_rv, nullptr, Gr, w.part_ss, w.sc};
   Scalars host;
   int launched = 0;
   for (;;) {
     for (int c = 0; c < chunk; ++c) {
-      hipLaunchKernelGGL(k_begin, dim3(G), dim3(kBlock), 0, st, N, w, G);
-      OPM_TRY(ilu_apply(pb, ilu, precision, w.p, w.ph, st, &w.sc->state));
-      hipLaunchKernelGGL(k_spmv_rv, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr, pb->col_idx,
-                         J, w);
-      hipLaunchKernelGGL(k_s, dim3(G), dim3(kBlock), 0, st, N, w, Gr);
-      hipLaunchKernelGGL(k_s_check, dim3(1), dim3(kBlock), 0, st, w, G);
-      OPM_TRY(ilu_apply(pb, ilu, precision, w.s, w.sh, st, &w.sc->state));
-      hipLaunchKernelGGL(k_spmv_t, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr, pb->col_idx, J,
-                         w);
+      if (fused) {
+        OPM_TRY(ilu_apply_fused(pb, ilu, precision, kry::kFuseBegin, fb, w.ph, st));
+        hipLaunchKernelGGL(k_spmv_rv, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
+                           pb->col_idx, J, w);
+        OPM_TRY(ilu_apply_fused(pb, ilu, precision, kry::kFuseS, fs, w.sh, st));
+        hipLaunchKernelGGL(k_spmv_t<true>, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
+                           pb->col_idx, J, w, pb->n_sub);
+      } else {
+        hipLaunchKernelGGL(k_begin, dim3(G), dim3(kBlock), 0, st, N, w, G);
+        OPM_TRY(ilu_apply(pb, ilu, precision, w.p, w.ph, st, &w.sc->state));
+        hipLaunchKernelGGL(k_spmv_rv, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
+                           pb->col_idx, J, w);
+        hipLaunchKernelGGL(k_s, dim3(G), dim3(kBlock), 0, st, N, w, Gr);
+        hipLaunchKernelGGL(k_s_check, dim3(1), dim3(kBlock), 0, st, w, G);
+        OPM_TRY(ilu_apply(pb, ilu, precision, w.s, w.sh, st, &w.sc->state));
+        hipLaunchKernelGGL(k_spmv_t<false>, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
+                           pb->col_idx, J, w, 0);
+      }
       hipLaunchKernelGGL(k_x, dim3(G), dim3(kBlock), 0, st, N, x, w, Gr);
       OPM_TRY_HIP(hipGetLastError());
       ++launched;

@@ -1,0 +1,140 @@
+// Device-side state of the BiCGStab iteration (paper sec. 2.3.1), shared by
+// the Krylov kernels (krylov.hip) and the block-ILU0 sweeps that fuse a
+// vector update of the iteration into their right-hand side (ilu0.hip).
+//
+// Every scalar lives in device memory; every dot product is a two-stage
+// fixed-order reduction whose per-workgroup partials are summed by the
+// consuming kernel itself, in the same order in every workgroup, so all
+// workgroups of a kernel see bit-identical scalars and take the same
+// decisions.  A state word (running / half-step exit / done) lets kernels of
+// an iteration that is no longer needed return at once.
+#pragma once
+
+#include "common.h"
+
+namespace opm {
+namespace kry {
+
+constexpr int kMaxGrid = 1024;   // workgroups of the vector kernels (partials per reduction)
+
+enum State : int32_t { kRunning = 0, kHalfPending = 1, kDone = 2 };
+
+struct Scalars {
+  double rho, rho0, alpha, omega, bnorm, tol, relres, pad;
+  int32_t state, status, its, half, maxit, pad2[3];
+};
+
+// A vector update of the iteration computed by a block-ILU0 sweep for the
+// rows of its subdomain, as the right-hand side of the preconditioner solve.
+enum FusedMode : int { kFuseNone = 0, kFuseBegin = 1, kFuseS = 2 };
+struct Fused {
+  const double* r;          // residual
+  double* p;                // kFuseBegin: search direction, updated in place
+  const double* v;          // A p^
+  double* s;                // kFuseS: s = r - alpha v (out)
+  const double* part_a;     // kFuseBegin: partials of <r,r>; kFuseS: of <r^,v>
+  const double* part_b;     // kFuseBegin: partials of <r^,r>
+  int n_part;               // number of those partials
+  double* part_out;         // kFuseS: partials of <s,s>, one per workgroup
+  Scalars* sc;
+};
+
+// Sum of the G partials of a reduction by NT threads (identical in every
+// workgroup of the same size).
+template <int NT>
+__device__ __forceinline__ double sum_partials(const double* part, int G, double* sh) {
+  double v = 0.0;
+  for (int k = threadIdx.x; k < G; k += NT) v += part[k];
+  return block_sum<NT>(v, sh);
+}
+
+// Start of an iteration: the convergence / iteration-cap / breakdown tests
+// on the residual of the previous iteration.  Returns true if the iteration
+// runs, with beta and omega of p = r + beta (p - omega v).  `state` is the
+// state word as read once for the whole workgroup.
+template <int NT>
+__device__ __forceinline__ bool begin_iteration(Scalars& s, int state, const double* part_rr,
+                                                const double* part_rhr, int G, double* sh,
+                                                double& beta, double& om) {
+  if (state != kRunning) {
+    if (state == kHalfPending && blockIdx.x == 0 && threadIdx.x == 0) s.state = kDone;
+    return false;
+  }
+  const double rr = sum_partials<NT>(part_rr, G, sh);
+  const double rho = sum_partials<NT>(part_rhr, G, sh);
+  const int its = s.its;
+  const double rnorm = sqrt(rr);
+  int verdict = kRunning, status = OPM_OK;
+  if (rnorm <= s.tol) {
+    verdict = kDone;
+  } else if (its > 0 && s.omega == 0.0) {
+    verdict = kDone;
+    status = OPM_EBREAKDOWN;
+  } else if (its >= s.maxit) {
+    verdict = kDone;
+    status = OPM_ENOTCONV;
+  } else if (fabs(rho) < 1e-300) {
+    verdict = kDone;
+    status = OPM_EBREAKDOWN;
+  }
+  if (verdict == kDone) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      s.status = status;
+      s.relres = s.bnorm > 0.0 ? rnorm / s.bnorm : 0.0;
+      s.state = kDone;
+    }
+    return false;
+  }
+  beta = its == 0 ? 0.0 : (rho / s.rho0) * (s.alpha / s.omega);
+  om = s.omega;
+  if (blockIdx.x == 0 && threadIdx.x == 0) s.rho = rho;
+  return true;
+}
+
+// alpha = rho / <r^, v> (breakdown on a zero denominator).  Returns true if
+// the iteration goes on.
+template <int NT>
+__device__ __forceinline__ bool alpha_step(Scalars& sc, int state, const double* part_rv, int G,
+                                           double* sh, double& alpha) {
+  if (state != kRunning) return false;
+  const double rv = sum_partials<NT>(part_rv, G, sh);
+  if (rv == 0.0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc.status = OPM_EBREAKDOWN;
+      sc.state = kDone;
+    }
+    return false;
+  }
+  alpha = sc.rho / rv;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc.alpha = alpha;
+  return true;
+}
+
+// Half-step exit test ||s|| <= tol.  Returns true if the iteration goes on.
+template <int NT>
+__device__ __forceinline__ bool half_step_check(Scalars& sc, int state, const double* part_ss,
+                                                int G, double* sh) {
+  if (state != kRunning) return false;
+  const double snorm = sqrt(sum_partials<NT>(part_ss, G, sh));
+  if (snorm <= sc.tol) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc.half = 1;
+      sc.relres = snorm / sc.bnorm;
+      sc.its += 1;
+      sc.state = kHalfPending;
+    }
+    return false;
+  }
+  return true;
+}
+
+// The state word read once per workgroup (every wavefront of the workgroup
+// takes the same branch even if another workgroup changes the word).
+__device__ __forceinline__ int read_state(const Scalars* sc, int* shared_word) {
+  if (threadIdx.x == 0) *shared_word = sc->state;
+  __syncthreads();
+  return *shared_word;
+}
+
+}  // namespace kry
+}  // namespace opm
