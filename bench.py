@@ -161,7 +161,8 @@ def bench_mixed(args):
     from paper_1910_06059_amd import cases, opm
     steps = args.steps or 10
     case = cases.config3()
-    g = opm.GpuModel(case)
+    blk = parse_blocks(args.ilu_blocks, case)
+    g = opm.GpuModel(case, ilu_blocks=blk)
     dt = case.report_dt[0]
     res = {}
     for prec in (0, 1):
@@ -178,7 +179,9 @@ def bench_mixed(args):
             "steps": steps, "warmup": 1, "higher_is_better": True, "dtype": "f64+f32-ilu",
             "data": "synthetic",
             "config": {"workload": f"46x112x22 masked grid, {g.n} active cells, 10-day steps",
-                       "n_cells": g.n, "ilu_levels": g.n_levels},
+                       "n_cells": g.n, "ilu_levels": g.n_levels,
+                       "preconditioner": "ILU(0) of the whole system" if blk is None else
+                       f"block ILU0, {g.pb.n_sub} column subdomains of {blk[0]}x{blk[1]}x{blk[2]}"},
             "fp64": res[0], "mixed": res[1],
             "mixed_vs_fp64_state": {"p_rel": err_p, "s_abs": err_s}}
     print(json.dumps(line), flush=True)
@@ -281,8 +284,9 @@ def bench_guess(args):
     t0 = time.perf_counter()
     data = []
     gen_newton = 0
+    blk = parse_blocks(args.ilu_blocks, cases.config5(train_seeds[0]))
     for seed in train_seeds:
-        g = opm.GpuModel(cases.config5(seed))
+        g = opm.GpuModel(cases.config5(seed), ilu_blocks=blk)
         states, reps = guess.simulate(g, steps, log=log)
         gen_newton += sum(r["newton_its"] for r in reps)
         g._work.clear()            # training needs the problem and the states only
@@ -307,7 +311,7 @@ def bench_guess(args):
     per_seed = {}
     state_diff = 0.0
     for seed in test_seeds:
-        g = opm.GpuModel(cases.config5(seed))
+        g = opm.GpuModel(cases.config5(seed), ilu_blocks=blk)
         out = {}
         for name, n_ in runs.items():
             r = guess.compare(g, n_, steps, log=log)
@@ -355,7 +359,9 @@ def bench_guess(args):
             "dtype": "f64 (simulator) + bf16/f32 (network)", "data": "synthetic",
             "config": {"workload": f"100x100x50 waterflood, {g.n} cells, 10-day steps, "
                                    f"train seeds {train_seeds[0]}-{train_seeds[-1]}, "
-                                   f"test seeds {test_seeds}"},
+                                   f"test seeds {test_seeds}",
+                       "preconditioner": "ILU(0) of the whole system" if blk is None else
+                       f"block ILU0, {g.pb.n_sub} column subdomains of {blk[0]}x{blk[1]}x{blk[2]}"},
             "runs": tot,
             "speedup_extrapolation": round(pt["wall_s"] / tot["extrapolation"]["wall_s"], 4),
             "newton_its_ratio_learned": round(tot["learned"]["newton_its"] / pt["newton_its"], 4),
@@ -490,7 +496,8 @@ def main():
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 FP32 ILU(0) factors")
     ap.add_argument("--ilu-blocks", default="4x4",
                     help="block ILU0 subdomain boxes: 'BXxBY' columns over the full depth, "
-                         "'BXxBYxBZ', or 'none' for the single-block ILU(0)")
+                         "'BXxBYxBZ', or 'none' for the single-block ILU(0) (c2, c3-mixed, "
+                         "c5-guess, and the block rows of c5-kernels)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="time budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")

@@ -563,11 +563,16 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
  *     256 or 128 threads (2, 3, 4) or with wavefronts that have no row in a
  *     level skipping their loads (5: 512, 6: 256 threads).
  *   OPM_OPT_BLOCK_DEPTH: block-ILU0 sweeps, levels whose data is loaded
- *     while a level is computed: 0 automatic (1), 1 or 2. */
+ *     while a level is computed: 0 automatic (1), 1 or 2.
+ *   OPM_OPT_KRYLOV_GRAPH: 1 (default) replays each chunk of BiCGStab
+ *     iterations after the first chunk of a solve as a HIP graph captured
+ *     once per set of arguments (kept until the process ends, at most 16),
+ *     0 enqueues the kernels one by one. */
 #define OPM_OPT_SWEEP_MODE 1
 #define OPM_OPT_KRYLOV_CHUNK 2
 #define OPM_OPT_SWEEP_KERNEL 3
 #define OPM_OPT_BLOCK_DEPTH 4
+#define OPM_OPT_KRYLOV_GRAPH 5
 int opm_set_option(int option, int value);
 
 const char* opm_strerror(int code);

@@ -224,42 +224,72 @@ __global__ __launch_bounds__(NT) void k_factor_blocks(Topo t, const double* J, I
 // values as 16-byte chunks, chunk c of (position p, a) at [(c ns + p) 3 + a]
 // so that the three lanes of a row and consecutive rows read consecutive
 // chunks.  Index records: neighbours by slot in the subdomain, and the cell.
+// A workgroup packs 32 consecutive positions: their Jacobian rows (at most
+// 7 blocks each, contiguous in J) are read into LDS by 8 lanes per row, then
+// 96 threads write the forward and 96 the backward records, each thread one
+// (position, a) for every chunk, so consecutive threads write consecutive
+// chunks.
+constexpr int kPackRows = 32;
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pack_block_records(Topo t, const double* J,
-                                                               IluView<T> v,
-                                                               const int32_t* slot) {
-  const int pos = blockIdx.x * kBlock + threadIdx.x;
-  if (pos >= t.n) return;
-  constexpr size_t kV = 16 / sizeof(T);
-  const size_t ns = (size_t)v.ns, p = (size_t)pos;
-  auto put = [&](T* rec, int a, int e, T val) {
-    rec[(((size_t)e / kV * ns + p) * 3 + a) * kV + (size_t)e % kV] = val;
-  };
-#pragma unroll
-  for (int sl = 0; sl < 3; ++sl) {
-    const int bl = t.lo_blk[3 * p + sl], bu = t.up_blk[3 * p + sl];
-    const double* Al = J + 9 * (size_t)(bl < 0 ? 0 : bl);
-    const double* Au = J + 9 * (size_t)(bu < 0 ? 0 : bu);
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        put(v.rec_f, a, 3 * sl + c, bl < 0 ? (T)0 : (T)Al[3 * a + c]);
-        put(v.rec_b, a, 3 * sl + c, bu < 0 ? (T)0 : (T)Au[3 * a + c]);
-      }
-  }
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const T d = v.dinv[(size_t)(3 * a + c) * ns + p];
-      put(v.rec_f, a, 9 + c, d);
-      put(v.rec_b, a, 9 + c, d);
+__global__ __launch_bounds__(256) void k_pack_block_records(Topo t, const int32_t* row_ptr,
+                                                            const double* J, IluView<T> v,
+                                                            const int32_t* slot) {
+  typedef typename Vec16<T>::type V;
+  constexpr unsigned kV = 16 / sizeof(T), kC = 12 / kV;
+  __shared__ double rows[kPackRows][64];
+  __shared__ int rbase[kPackRows];
+  const int p0 = blockIdx.x * kPackRows;
+  {
+    const int g = threadIdx.x >> 3, l = threadIdx.x & 7, pos = p0 + g;
+    if (pos < t.n) {
+      const int cell = t.perm[pos];
+      const int b0 = row_ptr[cell], nv = 9 * (row_ptr[cell + 1] - b0);
+      const double* src = J + 9 * (size_t)b0;
+      for (int e = l; e < nv; e += 8) rows[g][e] = src[e];
+      if (l == 0) rbase[g] = b0;
     }
-  auto nb = [&](int kp) { return kp < 0 ? kp : slot[kp]; };
-  const int cell = t.perm[pos];
-  v.idx_f[pos] = int4v{nb(t.lo_pos[3 * p]), nb(t.lo_pos[3 * p + 1]), nb(t.lo_pos[3 * p + 2]), cell};
-  v.idx_b[pos] = int4v{nb(t.up_pos[3 * p]), nb(t.up_pos[3 * p + 1]), nb(t.up_pos[3 * p + 2]), cell};
+  }
+  __syncthreads();
+  const int tid = threadIdx.x;
+  if (tid < 192) {
+    const bool fwd = tid < 96;
+    const int q = fwd ? tid : tid - 96, g = q / 3, a = q % 3, pos = p0 + g;
+    if (pos < t.n) {
+      const size_t ns = (size_t)v.ns, up = (size_t)pos;
+      const int32_t* blk = (fwd ? t.lo_blk : t.up_blk) + 3 * up;
+      int loc[3];
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) loc[sl] = blk[sl] < 0 ? -1 : blk[sl] - rbase[g];
+      V* rec = reinterpret_cast<V*>(fwd ? v.rec_f : v.rec_b);
+#pragma unroll
+      for (unsigned c = 0; c < kC; ++c) {
+        V w;
+#pragma unroll
+        for (unsigned qq = 0; qq < kV; ++qq) {
+          const unsigned e = c * kV + qq;
+          T val;
+          if (e < 9u) {
+            const int sl = (int)e / 3, col = (int)e % 3;
+            val = loc[sl] < 0 ? (T)0 : (T)rows[g][9 * loc[sl] + 3 * a + col];
+          } else {
+            val = v.dinv[(size_t)(3 * a + (int)e - 9) * ns + up];
+          }
+          w[qq] = val;
+        }
+        rec[(c * ns + up) * 3 + a] = w;
+      }
+    }
+  } else if (tid < 192 + kPackRows) {
+    const int pos = p0 + tid - 192;
+    if (pos < t.n) {
+      const size_t p = (size_t)pos;
+      auto nb = [&](int kp) { return kp < 0 ? kp : slot[kp]; };
+      const int cell = t.perm[pos];
+      v.idx_f[pos] = int4v{nb(t.lo_pos[3 * p]), nb(t.lo_pos[3 * p + 1]), nb(t.lo_pos[3 * p + 2]), cell};
+      v.idx_b[pos] = int4v{nb(t.up_pos[3 * p]), nb(t.up_pos[3 * p + 1]), nb(t.up_pos[3 * p + 2]), cell};
+    }
+  }
 }
 
 // Block-ILU0 sweep rows are spread over three lanes, one per equation a:
@@ -449,9 +479,10 @@ __device__ __forceinline__ void block_extra(IluView<T> v, const BlockRhs& q, T* 
 // earlier, so no load waits for one issued in the previous step.  The
 // stages rotate through register rings (3 indices, DEPTH + 1 jobs), fully
 // unrolled over a period of P steps so that every ring slot is a register.
-template <typename T, int NT, bool FWD, bool WIDE, int DEPTH, int MODE>
-__device__ __forceinline__ void block_sweep(IluView<T> v, const BlockRhs& q, T* zl, double* x,
-                                            const int* lp, int nlev, int nrows, double& ss) {
+template <typename T, int NT, bool FWD, bool WIDE, int DEPTH, int MODE, typename Gate>
+__device__ __forceinline__ bool block_sweep(IluView<T> v, BlockRhs& q, T* zl, double* x,
+                                            const int* lp, int nlev, int nrows, double& ss,
+                                            Gate gate) {
   constexpr int ND = DEPTH + 1, NI = 3;
   constexpr int P = ND % NI == 0 ? ND : ND * NI;
   const int row = block_lane_row();
@@ -485,15 +516,19 @@ __device__ __forceinline__ void block_sweep(IluView<T> v, const BlockRhs& q, T* 
   }
   idx[DEPTH % NI] = index();
   idx[(DEPTH + 1) % NI] = index();
+  // with the first levels' loads in flight: the decisions that need the
+  // iteration's scalars (their loads overlap those of the sweep)
+  if (!gate(q)) return false;
   for (int k = 0; k < nlev; k += P) {
 #pragma unroll
-    for (int q = 0; q < P; ++q) {
-      if (k + q >= nlev) break;
-      idx[(q + DEPTH + 2) % NI] = index();
-      data(idx[(q + DEPTH) % NI], jobs[(q + DEPTH) % ND]);
-      compute(jobs[q % ND]);
+    for (int qq = 0; qq < P; ++qq) {
+      if (k + qq >= nlev) break;
+      idx[(qq + DEPTH + 2) % NI] = index();
+      data(idx[(qq + DEPTH) % NI], jobs[(qq + DEPTH) % ND]);
+      compute(jobs[qq % ND]);
     }
   }
+  return true;
 }
 
 // x = M^{-1} r for the block ILU0: forward then backward sweep of one
@@ -511,18 +546,7 @@ __global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t
                                                       kry::Fused f) {
   __shared__ double red[NT / 64];
   __shared__ int word;
-  BlockRhs q{r, f, 0.0, 0.0, 0.0};
-  if (MODE == kry::kFuseNone) {
-    if (skip && *skip != 0) return;
-  } else {
-    const int state = kry::read_state(f.sc, &word);
-    if (MODE == kry::kFuseBegin &&
-        !kry::begin_iteration<NT>(*f.sc, state, f.part_a, f.part_b, f.n_part, red, q.beta,
-                                  q.omega))
-      return;
-    if (MODE == kry::kFuseS && !kry::alpha_step<NT>(*f.sc, state, f.part_a, f.n_part, red, q.alpha))
-      return;
-  }
+  if (MODE == kry::kFuseNone && skip && *skip != 0) return;
   extern __shared__ unsigned char smem[];
   T* zl = reinterpret_cast<T*>(smem);
   int* lp = reinterpret_cast<int*>(smem + sizeof(T) * 3 * (size_t)max_sub);
@@ -531,16 +555,39 @@ __global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t
     lp[2 * l] = slp[(size_t)l * (nsub + 1) + s];
     lp[2 * l + 1] = slp[(size_t)l * (nsub + 1) + s + 1];
   }
+  // the iteration's state word, read once for the workgroup with the table
+  if (MODE != kry::kFuseNone && threadIdx.x == 0) word = f.sc->state;
   __syncthreads();
+  int state = kry::kRunning;
+  if (MODE != kry::kFuseNone) {
+    state = word;
+    if (state != kry::kRunning) {
+      if (MODE == kry::kFuseBegin && state == kry::kHalfPending && blockIdx.x == 0 &&
+          threadIdx.x == 0)
+        f.sc->state = kry::kDone;
+      return;
+    }
+  }
   int nrows = 0;
   for (int l = 0; l < nlev; ++l) nrows += lp[2 * l + 1] - lp[2 * l];
+  BlockRhs q{r, f, 0.0, 0.0, 0.0};
+  // the iteration's tests and scalars (every workgroup on the same partials)
+  auto gate = [&](BlockRhs& qq) -> bool {
+    if (MODE == kry::kFuseBegin)
+      return kry::begin_iteration<NT>(*f.sc, state, f.part_a, f.part_b, f.n_part, red, qq.beta,
+                                      qq.omega);
+    if (MODE == kry::kFuseS)
+      return kry::alpha_step<NT>(*f.sc, state, f.part_a, f.n_part, red, qq.alpha);
+    return true;
+  };
+  auto open = [](BlockRhs&) { return true; };
   double ss = 0.0;
-  block_sweep<T, NT, true, WIDE, DEPTH, MODE>(v, q, zl, x, lp, nlev, nrows, ss);
+  if (!block_sweep<T, NT, true, WIDE, DEPTH, MODE>(v, q, zl, x, lp, nlev, nrows, ss, gate)) return;
   if (MODE == kry::kFuseS) {
     const double tot = block_sum<NT>(ss, red);
     if (threadIdx.x == 0) f.part_out[blockIdx.x] = tot;
   }
-  block_sweep<T, NT, false, WIDE, DEPTH, MODE>(v, q, zl, x, lp, nlev, nrows, ss);
+  block_sweep<T, NT, false, WIDE, DEPTH, MODE>(v, q, zl, x, lp, nlev, nrows, ss, open);
 }
 
 // Both sweeps by one workgroup of NT threads through the LDS ring with
@@ -635,8 +682,8 @@ int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* stat
         hipLaunchKernelGGL((k_factor_blocks<T, 256>), dim3(pb->n_sub), dim3(256), lds, s, t, J,
                            v, pb->sub_level_ptr, pb->n_sub, pb->max_width, status);
     }
-    hipLaunchKernelGGL(k_pack_block_records<T>, dim3(blocks_for(pb->n_cells, kBlock)),
-                       dim3(kBlock), 0, s, t, J, v, pb->slot);
+    hipLaunchKernelGGL(k_pack_block_records<T>, dim3(blocks_for(pb->n_cells, kPackRows)),
+                       dim3(256), 0, s, t, pb->row_ptr, J, v, pb->slot);
     OPM_TRY_HIP(hipGetLastError());
     return OPM_OK;
   }

@@ -13,6 +13,7 @@ extern int g_sweep_mode;
 extern int g_block_depth;
 extern int g_sweep_kernel;
 extern int g_krylov_chunk;
+extern int g_krylov_graph;
 int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, double dt,
                     double* R, double* J, double* norms, hipStream_t s);
 int launch_accumulation(const opm_problem* pb, const double* y, double* acc0, hipStream_t s);
@@ -320,6 +321,10 @@ int opm_set_option(int option, int value) {
     case OPM_OPT_SWEEP_MODE:
       if (value < -1 || value > 2) return OPM_EINVAL;
       g_sweep_mode = value;
+      return OPM_OK;
+    case OPM_OPT_KRYLOV_GRAPH:
+      if (value < 0 || value > 1) return OPM_EINVAL;
+      g_krylov_graph = value;
       return OPM_OK;
     case OPM_OPT_KRYLOV_CHUNK:
       if (value < 0) return OPM_EINVAL;

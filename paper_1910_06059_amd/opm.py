@@ -95,7 +95,7 @@ EXPORTS = [
     "opm_ensemble_bytes", "opm_ensemble_prepare", "opm_ensemble_launch",
 ]
 
-OPT_SWEEP_MODE, OPT_KRYLOV_CHUNK, OPT_SWEEP_KERNEL, OPT_BLOCK_DEPTH = 1, 2, 3, 4
+OPT_SWEEP_MODE, OPT_KRYLOV_CHUNK, OPT_SWEEP_KERNEL, OPT_BLOCK_DEPTH, OPT_KRYLOV_GRAPH = 1, 2, 3, 4, 5
 
 _lib = None
 
