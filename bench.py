@@ -501,6 +501,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="time budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--krylov-graph", type=int, default=1,
+                    help="replay BiCGStab chunks from HIP graphs (1) or enqueue kernel by kernel (0)")
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--kernels", default=None,
                     help="comma-separated subset of the c5-kernels table (spmv, ilu0_apply_fp64, "
@@ -520,6 +522,8 @@ def main():
     from paper_1910_06059_amd import cases, opm
 
     torch.cuda.set_device(0)
+    opm.init()
+    opm.set_option(opm.OPT_KRYLOV_GRAPH, args.krylov_graph)
     if args.workload == "c3-mixed":
         return bench_mixed(args)
     if args.workload == "c4-ensemble":
