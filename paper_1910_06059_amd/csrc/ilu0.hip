@@ -342,55 +342,57 @@ struct BlockRhs {
 // compiler never has to assume a load of an earlier level still in flight.
 
 // Level k of the sweep (ascending levels forward, descending backward;
-// past the last one: the last one) and the lane's clamped row position.
-template <bool FWD>
-__device__ __forceinline__ void block_row_pos(const int* lp, int nlev, int k, int row, int& p0,
-                                              int& p1, int& pos) {
-  const int kk = k < nlev ? k : nlev - 1;
-  const int l = FWD ? kk : nlev - 1 - kk;
-  p0 = lp[2 * l];
-  p1 = lp[2 * l + 1];
-  pos = max(min(p0 + row, p1 - 1), 0);
-}
+// past the last one: the last one), the lane's clamped row position and
+// the row's index record; the data stage reuses the bounds.
+struct BlockStage {
+  int4v ix;
+  int p0, p1, pos;
+  bool in;   // k is a level of the sweep
+};
 
 template <typename T, bool FWD>
-__device__ __forceinline__ int4v block_index(IluView<T> v, const int* lp, int nlev, int k,
-                                             int row) {
-  int p0, p1, pos;
-  block_row_pos<FWD>(lp, nlev, k, row, p0, p1, pos);
-  return (FWD ? v.idx_f : v.idx_b)[(unsigned)pos];
+__device__ __forceinline__ BlockStage block_index(IluView<T> v, const int* lp, int nlev, int k,
+                                                  int row) {
+  BlockStage st;
+  const int kk = k < nlev ? k : nlev - 1;
+  const int l = FWD ? kk : nlev - 1 - kk;
+  st.p0 = lp[2 * l];
+  st.p1 = lp[2 * l + 1];
+  st.pos = max(min(st.p0 + row, st.p1 - 1), 0);
+  st.in = k < nlev;
+  st.ix = (FWD ? v.idx_f : v.idx_b)[(unsigned)st.pos];
+  return st;
 }
 
 // base: rows of the subdomain before the level (forward) or up to and
-// including it (backward).
+// including it (backward).  Missing neighbours (index -1) read the zero row
+// at slot zslot.
 template <typename T, bool FWD, int MODE>
-__device__ __forceinline__ void block_data(IluView<T> v, const BlockRhs& q, const T* zl,
-                                           const int* lp, int nlev, int k, int row, int base,
-                                           int4v ix, BlockJob<T>& j) {
+__device__ __forceinline__ void block_data(IluView<T> v, const BlockRhs& q, const T* zl, int row,
+                                           int base, int zslot, const BlockStage& st,
+                                           BlockJob<T>& j) {
   typedef typename Vec16<T>::type V;
   constexpr unsigned kV = 16 / sizeof(T), kC = 12 / kV;
   const int eq = block_lane_eq();
   const unsigned a = (unsigned)min(eq, 2);
-  int p0, p1, pos;
-  block_row_pos<FWD>(lp, nlev, k, row, p0, p1, pos);
-  j.live = k < nlev && p0 + row < p1 && eq < 3;
-  const unsigned ns = (unsigned)v.ns, up = (unsigned)pos;
-  j.kp[0] = ix.x;
-  j.kp[1] = ix.y;
-  j.kp[2] = ix.z;
-  j.cell = ix.w;
-  j.slot = (FWD ? base : base - (p1 - p0)) + (pos - p0);
+  j.live = st.in && st.p0 + row < st.p1 && eq < 3;
+  const unsigned ns = (unsigned)v.ns, up = (unsigned)st.pos;
+  j.kp[0] = st.ix.x < 0 ? zslot : st.ix.x;
+  j.kp[1] = st.ix.y < 0 ? zslot : st.ix.y;
+  j.kp[2] = st.ix.z < 0 ? zslot : st.ix.z;
+  j.cell = st.ix.w;
+  j.slot = (FWD ? base : base - (st.p1 - st.p0)) + (st.pos - st.p0);
   const V* rec = reinterpret_cast<const V*>(FWD ? v.rec_f : v.rec_b);
 #pragma unroll
   for (unsigned c = 0; c < kC; ++c) {
     const V w = rec[(c * ns + up) * 3u + a];
 #pragma unroll
-    for (unsigned q = 0; q < kV; ++q) {
-      const unsigned e = c * kV + q;
+    for (unsigned qq = 0; qq < kV; ++qq) {
+      const unsigned e = c * kV + qq;
       if (e < 9u)
-        j.a[e] = w[q];
+        j.a[e] = w[qq];
       else
-        j.d[e - 9u] = w[q];
+        j.d[e - 9u] = w[qq];
     }
   }
   if (FWD) {
@@ -412,8 +414,11 @@ __device__ __forceinline__ void block_data(IluView<T> v, const BlockRhs& q, cons
   }
   // keep every load of the stage here, ahead of the computation of the
   // current level (the compiler would otherwise sink some of them to their
-  // first use, behind the next stage's loads)
+  // first use, behind the next stage's loads), and keep the arithmetic on
+  // them after this point (hoisted above the loads it would wait for them
+  // at once)
   asm volatile("" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // Every lane computes (the shuffles need all lanes); only rows of the level
@@ -432,10 +437,10 @@ __device__ __forceinline__ void block_row(const BlockJob<T>& j, T* zl, double* x
   T acc = FWD ? rhs : (T)0;
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
-    const int kp = j.kp[s];
-    const bool has = kp >= 0;
-    const T* w = zl + 3u * (unsigned)(has ? kp : 0);
-    const T x0 = has ? w[0] : (T)0, x1 = has ? w[1] : (T)0, x2 = has ? w[2] : (T)0;
+    // a missing neighbour reads the zero row: x = 0 exactly, as in the
+    // other sweep kernels
+    const T* w = zl + 3u * (unsigned)j.kp[s];
+    const T x0 = w[0], x1 = w[1], x2 = w[2];
     const T t = j.a[3 * s] * x0 + j.a[3 * s + 1] * x1 + j.a[3 * s + 2] * x2;
     acc = FWD ? acc - t : acc + t;
   }
@@ -458,7 +463,7 @@ __device__ __forceinline__ void block_row(const BlockJob<T>& j, T* zl, double* x
 // levels).
 template <typename T, int NT, bool FWD, int MODE>
 __device__ __forceinline__ void block_extra(IluView<T> v, const BlockRhs& q, T* zl, double* x,
-                                            const int* lp, int nlev, int k, int base,
+                                            const int* lp, int nlev, int k, int base, int zslot,
                                             double& ss) {
   constexpr int kRows = NT / 64 * kRowsPerWave;
   const int l = FWD ? k : nlev - 1 - k;
@@ -466,9 +471,9 @@ __device__ __forceinline__ void block_extra(IluView<T> v, const BlockRhs& q, T* 
   // uniform trip count: every lane joins the shuffles of every round
   for (int r0 = kRows; r0 < w; r0 += kRows) {
     const int row = r0 + block_lane_row();
-    const int4v ix = block_index<T, FWD>(v, lp, nlev, k, row);
+    const BlockStage st = block_index<T, FWD>(v, lp, nlev, k, row);
     BlockJob<T> j;
-    block_data<T, FWD, MODE>(v, q, zl, lp, nlev, k, row, base, ix, j);
+    block_data<T, FWD, MODE>(v, q, zl, row, base, zslot, st, j);
     block_row<T, FWD, MODE>(j, zl, x, q, ss);
   }
 }
@@ -481,8 +486,8 @@ __device__ __forceinline__ void block_extra(IluView<T> v, const BlockRhs& q, T* 
 // unrolled over a period of P steps so that every ring slot is a register.
 template <typename T, int NT, bool FWD, bool WIDE, int DEPTH, int MODE, typename Gate>
 __device__ __forceinline__ bool block_sweep(IluView<T> v, BlockRhs& q, T* zl, double* x,
-                                            const int* lp, int nlev, int nrows, double& ss,
-                                            Gate gate) {
+                                            const int* lp, int nlev, int nrows, int zslot,
+                                            double& ss, Gate gate) {
   constexpr int ND = DEPTH + 1, NI = 3;
   constexpr int P = ND % NI == 0 ? ND : ND * NI;
   const int row = block_lane_row();
@@ -495,18 +500,20 @@ __device__ __forceinline__ bool block_sweep(IluView<T> v, BlockRhs& q, T* zl, do
   int dk = 0, db = FWD ? 0 : nrows;           // data stage: next level and its base
   int ck = 0, cb = db;                        // compute stage
   auto index = [&]() { return block_index<T, FWD>(v, lp, nlev, ik++, row); };
-  auto data = [&](int4v ix, BlockJob<T>& j) {
-    block_data<T, FWD, MODE>(v, q, zl, lp, nlev, dk, row, db, ix, j);
-    db = next_base(db, dk++);
+  auto data = [&](const BlockStage& st, BlockJob<T>& j) {
+    block_data<T, FWD, MODE>(v, q, zl, row, db, zslot, st, j);
+    const int w = st.in ? st.p1 - st.p0 : 0;
+    db = FWD ? db + w : db - w;
+    ++dk;
   };
   auto compute = [&](const BlockJob<T>& j) {
     block_row<T, FWD, MODE>(j, zl, x, q, ss);
-    if (WIDE) block_extra<T, NT, FWD, MODE>(v, q, zl, x, lp, nlev, ck, cb, ss);
+    if (WIDE) block_extra<T, NT, FWD, MODE>(v, q, zl, x, lp, nlev, ck, cb, zslot, ss);
     cb = next_base(cb, ck++);
     __syncthreads();
   };
   BlockJob<T> jobs[ND];
-  int4v idx[NI];
+  BlockStage idx[NI];
   // prologue: data of levels 0 .. DEPTH-1, indices of DEPTH and DEPTH+1
   // (each index slot is read before it is loaded again)
 #pragma unroll
@@ -548,13 +555,14 @@ __global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t
   __shared__ int word;
   if (MODE == kry::kFuseNone && skip && *skip != 0) return;
   extern __shared__ unsigned char smem[];
-  T* zl = reinterpret_cast<T*>(smem);
-  int* lp = reinterpret_cast<int*>(smem + sizeof(T) * 3 * (size_t)max_sub);
+  T* zl = reinterpret_cast<T*>(smem);   // [max_sub + 1][3], the last row zero
+  int* lp = reinterpret_cast<int*>(smem + sizeof(T) * 3 * ((size_t)max_sub + 1));
   const int s = blockIdx.x;
   for (int l = threadIdx.x; l < nlev; l += NT) {
     lp[2 * l] = slp[(size_t)l * (nsub + 1) + s];
     lp[2 * l + 1] = slp[(size_t)l * (nsub + 1) + s + 1];
   }
+  if (threadIdx.x < 3) zl[3 * (size_t)max_sub + threadIdx.x] = (T)0;
   // the iteration's state word, read once for the workgroup with the table
   if (MODE != kry::kFuseNone && threadIdx.x == 0) word = f.sc->state;
   __syncthreads();
@@ -582,12 +590,14 @@ __global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t
   };
   auto open = [](BlockRhs&) { return true; };
   double ss = 0.0;
-  if (!block_sweep<T, NT, true, WIDE, DEPTH, MODE>(v, q, zl, x, lp, nlev, nrows, ss, gate)) return;
+  if (!block_sweep<T, NT, true, WIDE, DEPTH, MODE>(v, q, zl, x, lp, nlev, nrows, max_sub, ss,
+                                                   gate))
+    return;
   if (MODE == kry::kFuseS) {
     const double tot = block_sum<NT>(ss, red);
     if (threadIdx.x == 0) f.part_out[blockIdx.x] = tot;
   }
-  block_sweep<T, NT, false, WIDE, DEPTH, MODE>(v, q, zl, x, lp, nlev, nrows, ss, open);
+  block_sweep<T, NT, false, WIDE, DEPTH, MODE>(v, q, zl, x, lp, nlev, nrows, max_sub, ss, open);
 }
 
 // Both sweeps by one workgroup of NT threads through the LDS ring with
@@ -653,9 +663,11 @@ bool block_sweep_wide(const opm_problem* pb) {
   return pb->max_width > block_sweep_threads(pb) / 64 * kRowsPerWave;
 }
 
+// The subdomain's vector (one row per slot and a zero row) and its level
+// bounds.
 template <typename T>
 size_t block_lds(const opm_problem* pb) {
-  return sizeof(T) * 3 * (size_t)pb->max_sub + sizeof(int) * 2 * (size_t)pb->n_levels;
+  return sizeof(T) * 3 * ((size_t)pb->max_sub + 1) + sizeof(int) * 2 * (size_t)pb->n_levels;
 }
 
 template <typename T>
