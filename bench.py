@@ -386,7 +386,8 @@ def bench_kernels(args):
     factorisation, each divided into its algorithmic bytes."""
     import torch
     from paper_1910_06059_amd import cases, opm
-    case = cases.config5(5008)
+    nx, ny, nz = (int(v) for v in args.kernel_grid.lower().split("x"))
+    case = cases.config5(5008, nx, ny, nz)
     g = opm.GpuModel(case)
     dt = case.report_dt[0]
     y = g.initial_state()
@@ -461,12 +462,13 @@ def bench_kernels(args):
         t = timed(fn)
         res[name] = {"kernel": kname, "us": round(t * 1e6, 2), "bytes": int(nbytes),
                      "gbs": round(nbytes / t / 1e9, 1), "frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4)}
-    line = {"metric": "kernel HBM roofline on the 500k-cell system (algorithmic bytes / HIP-event "
+    line = {"metric": f"kernel HBM roofline on the {n}-cell system (algorithmic bytes / HIP-event "
                       "time per launch)", "value": res.get("spmv", {}).get("frac"),
             "unit": "fraction of 8 TB/s (SpMV)", "n_gpus": 1, "steps": reps, "warmup": 3,
             "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": f"100x100x50 system, {n} cells, {g.nnzb} blocks, "
-                                   f"{g.n_levels} ILU levels (max {g.max_level} rows)"},
+            "config": {"workload": f"{nx}x{ny}x{nz} system, {n} cells, {g.nnzb} blocks, "
+                                   f"{g.n_levels} ILU levels (max {g.max_level} rows), block ILU0 "
+                                   f"on {gb.pb.n_sub} subdomains of {blk[0]}x{blk[1]}x{blk[2]}"},
             "kernels": res}
     print(json.dumps(line), flush=True)
 
@@ -504,6 +506,9 @@ def main():
     ap.add_argument("--krylov-graph", type=int, default=1,
                     help="replay BiCGStab chunks from HIP graphs (1) or enqueue kernel by kernel (0)")
     ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--kernel-grid", default="100x100x50",
+                    help="grid of the c5-kernels table (C5: 100x100x50; 200x200x50 is the 2M-cell "
+                         "stand-in)")
     ap.add_argument("--kernels", default=None,
                     help="comma-separated subset of the c5-kernels table (spmv, ilu0_apply_fp64, "
                          "ilu0_apply_fp32, assemble, ilu0_factor_fp64)")
