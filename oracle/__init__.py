@@ -36,7 +36,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("tol_cnv", ctypes.c_double), ("tol_mb", ctypes.c_double),
                 ("ds_max", ctypes.c_double), ("dp_max_rel", ctypes.c_double),
                 ("lin_rtol", ctypes.c_double), ("max_newton", ctypes.c_int),
-                ("lin_maxit", ctypes.c_int), ("max_cuts", ctypes.c_int)]
+                ("lin_maxit", ctypes.c_int), ("max_cuts", ctypes.c_int),
+                ("krylov", ctypes.c_int), ("restart", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -98,6 +99,9 @@ def lib(path: Optional[str] = None):
         L.ora_set_ilu_blocks.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.ora_set_ilu_blocks.restype = ctypes.c_int
         L.ora_spmv.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.ora_gmres.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int,
+                                ctypes.c_int, _dp, _dp]
+        L.ora_gmres.restype = ctypes.c_int
         L.ora_bicgstab.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, ctypes.c_double,
                                    ctypes.c_int, _dp, _dp]
         L.ora_newton_step.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double,
@@ -121,7 +125,7 @@ def _i(a: np.ndarray):
 
 def default_opts(case=None, **kw) -> Opts:
     o = Opts(tol_cnv=1e-8, tol_mb=1e-11, ds_max=0.2, dp_max_rel=0.3, lin_rtol=1e-6,
-             max_newton=20, lin_maxit=500, max_cuts=8)
+             max_newton=20, lin_maxit=500, max_cuts=8, krylov=0, restart=30)
     if case is not None:
         o.tol_cnv, o.tol_mb, o.lin_rtol = case.tol_cnv, case.tol_mb, case.lin_rtol
     for k, v in kw.items():
@@ -248,6 +252,14 @@ class Model:
         rr = ctypes.c_double()
         st = self.L.ora_bicgstab(self.h, _d(J), _d(F), _d(np.ascontiguousarray(b, dtype=np.float64)),
                                  _d(x), rtol, maxit, ctypes.byref(its), ctypes.byref(rr))
+        return st, x, its.value, rr.value
+
+    def gmres(self, J, F, b, rtol=1e-6, maxit=500, restart=30):
+        x = np.zeros((self.n, 3))
+        its = ctypes.c_double()
+        rr = ctypes.c_double()
+        st = self.L.ora_gmres(self.h, _d(J), _d(F), _d(np.ascontiguousarray(b, dtype=np.float64)),
+                              _d(x), rtol, maxit, restart, ctypes.byref(its), ctypes.byref(rr))
         return st, x, its.value, rr.value
 
     def newton_step(self, y, y_prev, dt, opts: Optional[Opts] = None):

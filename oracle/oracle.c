@@ -19,6 +19,8 @@
  *   block ILU0      LU = A inside subdomains and 0 between them; one box =
  *                   ILU(0); one-cell boxes = block Jacobi; cut 1-D chain
  *   BiCGStab        dense direct solve (numpy) on tiny grids
+ *   GMRes           dense direct solve with restarts; one iteration with an
+ *                   exact LU; least-squares minimum over the Krylov space
  *   Newton          one-cell producer root by bisection, quadratic
  *                   convergence, mass balance per step, mirror symmetry
  * Full multi-step runs are not pinned against the paper (it prints no
@@ -726,6 +728,99 @@ done:
   return status;
 }
 
+/* ------------------------------------ restarted GMRes (sec. 2.3.1, GMRes(m))
+ * Saad and Schultz's minimal-residual method, right preconditioned:
+ * x = M^{-1} u with u from the Krylov space of A M^{-1} built from the
+ * residual r0 = b - A x0, each space of at most m vectors (restart length),
+ * orthonormalised by modified Gram-Schmidt; the least-squares problem is
+ * reduced by Givens rotations, whose last entry |g_{j+1}| is the residual
+ * norm of the current iterate.  x0 = 0, stop on |g_{j+1}| <= rtol ||b||,
+ * at the iteration cap, or on an exact (happy) breakdown h_{j+1,j} = 0. */
+int ora_gmres(const ora_model* m, const double* J, const double* F, const double* b, double* x,
+              double rtol, int maxit, int restart, double* its_out, double* relres_out) {
+  const int N = 3 * m->n;
+  if (restart < 1) return ORA_EINVAL;
+  double* V = (double*)malloc(sizeof(double) * (size_t)N * (restart + 1));
+  double* H = (double*)calloc((size_t)(restart + 1) * restart, sizeof(double));
+  double* cs = (double*)malloc(sizeof(double) * restart);
+  double* sn = (double*)malloc(sizeof(double) * restart);
+  double* g = (double*)malloc(sizeof(double) * (restart + 1));
+  double* y = (double*)malloc(sizeof(double) * restart);
+  double* w = (double*)malloc(sizeof(double) * N);
+  double* z = (double*)malloc(sizeof(double) * N);
+  for (int k = 0; k < N; ++k) x[k] = 0.0;
+  const double bnorm = sqrt(dot(N, b, b)), tol = rtol * bnorm;
+  int status = ORA_ENOTCONV, its = 0;
+  double relres = bnorm > 0.0 ? 1.0 : 0.0;
+  if (bnorm == 0.0) { status = ORA_OK; goto done; }
+#define Hm(i, j) H[(size_t)(i) * restart + (j)]
+  while (its < maxit) {
+    /* residual of the current iterate starts the space */
+    ora_spmv(m, J, x, w);
+    for (int k = 0; k < N; ++k) V[k] = b[k] - w[k];
+    const double beta = sqrt(dot(N, V, V));
+    relres = beta / bnorm;
+    if (beta <= tol) { status = ORA_OK; break; }
+    for (int k = 0; k < N; ++k) V[k] /= beta;
+    for (int i = 0; i <= restart; ++i) g[i] = 0.0;
+    g[0] = beta;
+    int k_used = 0, done_cycle = 0;
+    for (int j = 0; j < restart && its < maxit; ++j) {
+      double* vj = V + (size_t)j * N;
+      ora_ilu0_apply(m, F, vj, z);
+      ora_spmv(m, J, z, w);
+      for (int i = 0; i <= j; ++i) {
+        const double* vi = V + (size_t)i * N;
+        const double h = dot(N, w, vi);
+        Hm(i, j) = h;
+        for (int k = 0; k < N; ++k) w[k] -= h * vi[k];
+      }
+      const double hn = sqrt(dot(N, w, w));
+      Hm(j + 1, j) = hn;
+      /* earlier rotations on the new column, then the one that zeroes it */
+      for (int i = 0; i < j; ++i) {
+        const double a = Hm(i, j), c = Hm(i + 1, j);
+        Hm(i, j) = cs[i] * a + sn[i] * c;
+        Hm(i + 1, j) = -sn[i] * a + cs[i] * c;
+      }
+      const double d = hypot(Hm(j, j), Hm(j + 1, j));
+      cs[j] = d > 0.0 ? Hm(j, j) / d : 1.0;
+      sn[j] = d > 0.0 ? Hm(j + 1, j) / d : 0.0;
+      Hm(j, j) = d;
+      Hm(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++its;
+      k_used = j + 1;
+      relres = fabs(g[j + 1]) / bnorm;
+      if (fabs(g[j + 1]) <= tol || hn == 0.0) { done_cycle = 1; break; }
+      double* vn = V + (size_t)(j + 1) * N;
+      for (int k = 0; k < N; ++k) vn[k] = w[k] / hn;
+    }
+    /* y = R^{-1} g over the columns used, x += M^{-1} V y */
+    for (int i = k_used - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int c = i + 1; c < k_used; ++c) t -= Hm(i, c) * y[c];
+      if (Hm(i, i) == 0.0) { status = ORA_EBREAKDOWN; goto done; }
+      y[i] = t / Hm(i, i);
+    }
+    for (int k = 0; k < N; ++k) w[k] = 0.0;
+    for (int i = 0; i < k_used; ++i) {
+      const double* vi = V + (size_t)i * N;
+      for (int k = 0; k < N; ++k) w[k] += y[i] * vi[k];
+    }
+    ora_ilu0_apply(m, F, w, z);
+    for (int k = 0; k < N; ++k) x[k] += z[k];
+    if (done_cycle) { status = ORA_OK; break; }
+  }
+#undef Hm
+done:
+  if (its_out) *its_out = its;
+  if (relres_out) *relres_out = relres;
+  free(V); free(H); free(cs); free(sn); free(g); free(y); free(w); free(z);
+  return status;
+}
+
 /* ------------------------------------------------ Newton (sec. 2.3, eq. linsystem) */
 static int all_finite(int n, const double* a) {
   for (int k = 0; k < n; ++k)
@@ -762,7 +857,9 @@ int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double 
     for (int k = 0; k < N; ++k) b[k] = -R[k];
     double its = 0.0, rr = 0.0;
     t0 = now_s();
-    st = ora_bicgstab(m, J, F, b, dx, o->lin_rtol, o->lin_maxit, &its, &rr);
+    st = o->krylov == 1
+             ? ora_gmres(m, J, F, b, dx, o->lin_rtol, o->lin_maxit, o->restart, &its, &rr)
+             : ora_bicgstab(m, J, F, b, dx, o->lin_rtol, o->lin_maxit, &its, &rr);
     rep->t_krylov += now_s() - t0;
     rep->lin_its += its;
     if (st != ORA_OK) { status = st; break; }

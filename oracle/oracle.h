@@ -64,6 +64,8 @@ typedef struct ora_opts {
   int max_newton;     /* max linear solves per time step                    */
   int lin_maxit;      /* BiCGStab iteration cap                             */
   int max_cuts;       /* time-step halvings allowed per report step         */
+  int krylov;         /* 0 BiCGStab, 1 restarted GMRes                      */
+  int restart;        /* GMRes restart length                               */
 } ora_opts;
 
 typedef struct ora_report {
@@ -128,6 +130,11 @@ int ora_set_ilu_blocks(ora_model* m, int bx, int by, int bz);
 void ora_ilu0_apply(const ora_model* m, const double* F, const double* r, double* x);
 void ora_spmv(const ora_model* m, const double* J, const double* x, double* y);
 /* Right-preconditioned BiCGStab, x0 = 0.  its counts half iterations as 0.5. */
+/* Right-preconditioned restarted GMRes(restart), x0 = 0, modified
+ * Gram-Schmidt, Givens rotations; its counts inner iterations.
+ * ORA_EINVAL for restart < 1. */
+int ora_gmres(const ora_model* m, const double* J, const double* F, const double* b, double* x,
+              double rtol, int maxit, int restart, double* its, double* relres);
 int ora_bicgstab(const ora_model* m, const double* J, const double* F, const double* b,
                  double* x, double rtol, int maxit, double* its, double* relres);
 

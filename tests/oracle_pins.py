@@ -473,6 +473,81 @@ def pin_block_ilu0_newton(lib_path=None):
     assert max(abs(e) for e in rep1.mass_err) <= 1e-10
 
 
+def pin_gmres_dense(lib_path=None):
+    """Restarted GMRes (sec. 2.3.1) against numpy's dense LU on tiny grids
+    (restart 8, so the larger ones restart several times)."""
+    for (nx, ny, nz), seed in [((2, 2, 2), 1), ((3, 3, 3), 2), ((4, 3, 2), 3)]:
+        c = _wells_case(nx, ny, nz, seed)
+        m = _model(c, lib_path)
+        y = cases.random_state(c, seed=seed + 10)
+        st, R, J = m.assemble(y, m.accumulation(cases.random_state(c, seed=seed + 20)), DAY)
+        st, F = m.ilu0(J)
+        st, x, its, rr = m.gmres(J, F, -R, rtol=1e-13, maxit=2000, restart=8)
+        assert st == 0, st
+        xd = np.linalg.solve(_dense(m, J), -R.ravel())
+        err = np.abs(x.ravel() - xd) / (np.abs(xd.reshape(-1, 3)).max(axis=0)[None, :].repeat(m.n, 0).ravel())
+        assert err.max() <= 1e-9, err.max()
+
+
+def pin_gmres_exact_lu(lib_path=None):
+    """With the exact LU of a 1-D chain as preconditioner, A M^{-1} = I and
+    GMRes stops after one iteration with the solution."""
+    c = cases.box_case(7, 1, 1, seed=1, wells=[
+        Well("I", cases.WELL_RATE_INJ, [(0, 0, 0)], 300 * STB / DAY),
+        Well("P", cases.WELL_BHP_PROD, [(6, 0, 0)], 3000 * PSI)])
+    m = _model(c, lib_path)
+    y = cases.random_state(c, seed=4)
+    st, R, J = m.assemble(y, m.accumulation(cases.random_state(c, seed=8)), DAY)
+    st, F = m.ilu0(J)
+    st, x, its, rr = m.gmres(J, F, -R, rtol=1e-10)
+    assert st == 0 and its == 1, (st, its)
+    xd = np.linalg.solve(_dense(m, J), -R.ravel())
+    assert np.abs(x.ravel() - xd).max() <= 1e-9 * np.abs(xd).max()
+
+
+def pin_gmres_minimal_residual(lib_path=None):
+    """Within one cycle, the k-th GMRes iterate has the smallest residual
+    over x = M^{-1} u, u in span{b, (A M^{-1}) b, ..., (A M^{-1})^{k-1} b}:
+    the minimum computed here by numpy least squares over that space (the
+    oracle's SpMV and ILU(0) solve only build the space), and the reported
+    relative residual is the true one."""
+    c = _wells_case(4, 3, 3, seed=5)
+    m = _model(c, lib_path)
+    y = cases.random_state(c, seed=6)
+    st, R, J = m.assemble(y, m.accumulation(cases.random_state(c, seed=7)), DAY)
+    st, F = m.ilu0(J)
+    b = -R
+    bn = np.linalg.norm(b)
+    U = [b.ravel()]
+    for _ in range(5):
+        U.append(m.spmv(J, m.ilu0_apply(F, U[-1].reshape(-1, 3))).ravel())
+    for k in range(1, 6):
+        st, x, its, rr = m.gmres(J, F, b, rtol=1e-14, maxit=k, restart=k)
+        assert its == k
+        res = np.linalg.norm(b.ravel() - m.spmv(J, x).ravel())
+        AU = np.stack([m.spmv(J, m.ilu0_apply(F, u.reshape(-1, 3))).ravel() for u in U[:k]], axis=1)
+        Q, _ = np.linalg.qr(AU)
+        best = np.linalg.norm(b.ravel() - Q @ (Q.T @ b.ravel()))
+        assert abs(res - best) <= 1e-8 * bn, (k, res, best)
+        assert abs(rr - res / bn) <= 1e-8, (k, rr, res / bn)
+
+
+def pin_gmres_newton(lib_path=None):
+    """A report step with GMRes(30) as the linear solver converges to the
+    BiCGStab run's state to the Newton tolerance and conserves mass."""
+    c = _wells_case(6, 5, 3, seed=43)
+    m = _model(c, lib_path)
+    dt = 10 * DAY
+    st, y0, rep0 = m.advance(c.initial_state(), dt, oracle.default_opts(c))
+    assert st == 0
+    st, y1, rep1 = m.advance(c.initial_state(), dt, oracle.default_opts(c, krylov=1, restart=30))
+    assert st == 0
+    assert rep1.lin_its != rep0.lin_its
+    assert np.abs(y1[:, 0] - y0[:, 0]).max() <= 1e-8 * np.abs(y0[:, 0]).max()
+    assert np.abs(y1[:, 1:] - y0[:, 1:]).max() <= 1e-8
+    assert max(abs(e) for e in rep1.mass_err) <= 1e-10
+
+
 # ------------------------------------------------------------------ Newton
 def pin_one_cell_producer(lib_path=None):
     """One cell drained by a BHP producer with immobile water below connate
@@ -592,6 +667,7 @@ ALL_PINS = [
     pin_compressibility, pin_darcy_flux_upwind, pin_hydrostatic_column, pin_pressure_block,
     pin_jacobian_fd, pin_conservation, pin_norms, pin_ilu0_pattern, pin_ilu0_exact_1d,
     pin_bicgstab_dense, pin_block_ilu0_partition, pin_block_ilu0_special_cases,
-    pin_block_ilu0_newton, pin_one_cell_producer, pin_injector_mass, pin_quadratic_convergence,
+    pin_block_ilu0_newton, pin_gmres_dense, pin_gmres_exact_lu, pin_gmres_minimal_residual,
+    pin_gmres_newton, pin_one_cell_producer, pin_injector_mass, pin_quadratic_convergence,
     pin_mass_balance_run, pin_mirror_symmetry,
 ]

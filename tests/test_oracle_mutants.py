@@ -54,6 +54,12 @@ MUTANTS = [
     ("block_lower_couplings_only", "if (!same_block(m, i, m->col_idx[q])) memset",
      "if (m->col_idx[q] < i && !same_block(m, i, m->col_idx[q])) memset"),
     ("block_axis_swapped", "ka / m->blk[2] == kb / m->blk[2]", "ka / m->blk[1] == kb / m->blk[1]"),
+    ("gmres_gram_schmidt_sign", "for (int k = 0; k < N; ++k) w[k] -= h * vi[k];",
+     "for (int k = 0; k < N; ++k) w[k] += h * vi[k];"),
+    ("gmres_givens_sign", "g[j + 1] = -sn[j] * g[j];", "g[j + 1] = sn[j] * g[j];"),
+    ("gmres_rotation_sign", "Hm(i + 1, j) = -sn[i] * a + cs[i] * c;", "Hm(i + 1, j) = sn[i] * a + cs[i] * c;"),
+    ("gmres_update_unpreconditioned", "for (int k = 0; k < N; ++k) x[k] += z[k];",
+     "for (int k = 0; k < N; ++k) x[k] += w[k];"),
 ]
 
 
