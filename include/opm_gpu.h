@@ -47,8 +47,9 @@ extern "C" {
 #define OPM_OK 0
 #define OPM_EINVAL (-1)        /* bad argument or unsupported pattern        */
 #define OPM_ESINGULAR (-2)     /* zero / non-finite 3x3 pivot in ILU(0)       */
-#define OPM_ENOTCONV (-3)      /* Newton or BiCGStab did not converge        */
-#define OPM_EBREAKDOWN (-4)    /* BiCGStab breakdown (rho, <r^,v>, omega, <t,t>) */
+#define OPM_ENOTCONV (-3)      /* Newton or a Krylov solver did not converge */
+#define OPM_EBREAKDOWN (-4)    /* Krylov breakdown (BiCGStab: rho, <r^,v>, omega,
+                                  * <t,t>; GMRes: singular triangular factor) */
 #define OPM_ENONFINITE (-5)    /* NaN or Inf in residual or state            */
 #define OPM_EHIP (-6)          /* a HIP runtime call failed                   */
 
@@ -57,6 +58,10 @@ extern "C" {
 
 #define OPM_PREC_FP64 0        /* ILU(0) factors and sweeps in FP64            */
 #define OPM_PREC_MIXED 1       /* ILU(0) factors stored and swept in FP32      */
+
+#define OPM_KRYLOV_BICGSTAB 0  /* Newton's linear solver: BiCGStab (default)     */
+#define OPM_KRYLOV_GMRES 1     /* Newton's linear solver: restarted GMRes        */
+#define OPM_GMRES_MAX_RESTART 32
 
 /* Fluid and rock-fluid constants (phase order water, oil, gas). */
 typedef struct opm_fluid {
@@ -296,24 +301,54 @@ int opm_bicgstab(const opm_problem* pb, const double* J, const void* ilu, int pr
                  const double* b, double* x, double rtol, int32_t maxit, void* work,
                  opm_solve_report* report, void* stream);
 
+/* Size in bytes of the GMRes workspace (device) for a restart length in
+ * 1..OPM_GMRES_MAX_RESTART (0 for an invalid one): restart + 1 basis
+ * vectors, their restart preconditioned images, one more vector and the
+ * reduction partials. */
+size_t opm_gmres_bytes(const opm_problem* pb, int32_t restart);
+
+/* Restarted GMRes(restart), right preconditioned by the ILU(0) (or block
+ * ILU0) factors in ilu (sec. 2.3.1 names GMRes as the alternative to
+ * BiCGStab).  x0 = 0; every cycle restarts from the true residual
+ * b - A x; orthogonalisation is classical Gram-Schmidt applied twice; the
+ * Hessenberg least-squares problem is reduced with Givens rotations; the
+ * update of a cycle is Z y with z_j = M^{-1} v_j kept from the iterations
+ * (for a linear M equal to M^{-1} V y; with FP32 factors it keeps the
+ * iterate consistent with the minimised residual).  Stops
+ * when the residual norm of the iterate (the rotated right-hand side, or the
+ * true residual at a cycle start) is <= rtol ||b||_2, after maxit
+ * iterations (OPM_ENOTCONV in the report), or on an exact breakdown (a
+ * singular triangular factor: OPM_EBREAKDOWN, x keeps the previous cycles).
+ * b, x: device [n][3] (x is overwritten); work: device, opm_gmres_bytes;
+ * report: HOST (its = inner iterations, rel_res = the residual estimate
+ * above / ||b||); the call synchronises the stream a few times per cycle.
+ * Returns OPM_EINVAL for a bad argument or restart outside
+ * 1..OPM_GMRES_MAX_RESTART, OPM_EHIP on a runtime failure, else OPM_OK
+ * (the solver's own outcome is report->status). */
+int opm_gmres(const opm_problem* pb, const double* J, const void* ilu, int precision,
+              const double* b, double* x, double rtol, int32_t maxit, int32_t restart, void* work,
+              opm_solve_report* report, void* stream);
+
 /* Newton options (sec. 2.3). */
 typedef struct opm_newton_opts {
   double tol_cnv;      /* converged when max CNV <= tol_cnv ...             */
   double tol_mb;       /* ... and max MB <= tol_mb                          */
   double ds_max;       /* Appleyard chop: largest saturation change         */
   double dp_max_rel;   /* Appleyard chop: largest |dp| / |p|                */
-  double lin_rtol;     /* BiCGStab relative tolerance                       */
+  double lin_rtol;     /* Krylov relative tolerance                         */
   int32_t max_newton;  /* linear solves allowed per time step               */
-  int32_t lin_maxit;   /* BiCGStab iteration cap                            */
+  int32_t lin_maxit;   /* Krylov iteration cap                              */
   int32_t precision;   /* OPM_PREC_FP64 or OPM_PREC_MIXED                   */
   int32_t max_cuts;    /* time-step halvings per report step (opm_advance)  */
+  int32_t krylov;      /* OPM_KRYLOV_BICGSTAB or OPM_KRYLOV_GMRES           */
+  int32_t restart;     /* GMRes restart length (1..OPM_GMRES_MAX_RESTART)   */
 } opm_newton_opts;
 
 /* Report of one time step (or of one report step for opm_advance). */
 typedef struct opm_newton_report {
   int32_t status;
   int32_t newton_its;  /* linear solves                                     */
-  int32_t lin_its;     /* BiCGStab iterations (half iterations round up)    */
+  int32_t lin_its;     /* Krylov iterations (BiCGStab half ones round up)   */
   int32_t substeps;    /* accepted substeps (opm_advance)                   */
   int32_t cuts;        /* time-step halvings (opm_advance)                  */
   int32_t pad;
@@ -322,16 +357,25 @@ typedef struct opm_newton_report {
   double t_assemble, t_factor, t_krylov, t_update;   /* s, HIP events     */
 } opm_newton_report;
 
-/* Size in bytes of the Newton workspace (device) for a precision. */
+/* Size in bytes of the Newton workspace (device) for a precision, with
+ * BiCGStab as the linear solver. */
 size_t opm_newton_bytes(const opm_problem* pb, int precision);
+
+/* Size in bytes of the Newton workspace (device) for these options (their
+ * precision, Krylov method and restart length); 0 for invalid options.
+ * Equal to opm_newton_bytes for BiCGStab. */
+size_t opm_newton_work_bytes(const opm_problem* pb, const opm_newton_opts* opts);
 
 /* One implicit Euler step of length dt (sec. 2.3): Newton iterations from
  * the guess in y (device [n][3], in/out) with y_prev the state at the start
  * of the step, each one assemble -> convergence test -> ILU(0) ->
- * BiCGStab -> Appleyard-chopped update, at most max_newton linear solves.
+ * BiCGStab (or GMRes) -> Appleyard-chopped update, at most max_newton
+ * linear solves.
  * No time-step cutting (opm_advance does that).  work: device,
  * opm_newton_bytes.  report: HOST; the call synchronises the stream once per
- * Newton iteration (convergence test) and a few times per linear solve. */
+ * Newton iteration (convergence test) and a few times per linear solve.
+ * With opts->krylov = OPM_KRYLOV_GMRES, work must hold
+ * opm_newton_work_bytes. */
 int opm_newton_step(const opm_problem* pb, double* y, const double* y_prev, double dt,
                     const opm_newton_opts* opts, void* work, opm_newton_report* report,
                     void* stream);
@@ -378,7 +422,8 @@ int opm_ensemble_prepare(const opm_problem* members, double* const* y, int32_t n
 /* One asynchronous launch advancing every member by n_steps report steps.
  * max_level: the largest max_level of the members; reports: device
  * [n_members].  opts->precision is ignored (the workspace's precision is
- * passed explicitly). */
+ * passed explicitly); opts->krylov must be OPM_KRYLOV_BICGSTAB (else
+ * OPM_EINVAL): the members' solver is BiCGStab. */
 int opm_ensemble_launch(const void* work, int32_t n_members, int precision, int32_t max_level,
                         double dt_report, int32_t n_steps, const opm_newton_opts* opts,
                         opm_ensemble_report* reports, void* stream);

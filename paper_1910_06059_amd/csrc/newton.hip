@@ -27,6 +27,10 @@ int spmv(const opm_problem* pb, const double* J, const double* x, double* y, hip
 int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, const double* b,
              double* x, double rtol, int maxit, void* work, opm_solve_report* rep,
              hipStream_t st);
+size_t gmres_bytes(const opm_problem* pb, int restart);
+int gmres(const opm_problem* pb, const double* J, void* ilu, int precision, const double* b,
+          double* x, double rtol, int maxit, int restart, void* work, opm_solve_report* rep,
+          hipStream_t st);
 
 int guess_infer(const opm_problem* pb, const opm_guess_net* net, const double* y_n,
                 const double* y_nm1, double* y_guess, void* work, hipStream_t s,
@@ -51,11 +55,13 @@ struct NewtonWork {
   void* krylov;
 };
 
-size_t newton_bytes(const opm_problem* pb, int precision) {
+// The Krylov workspace is last: its size depends on the method.
+size_t newton_bytes(const opm_problem* pb, int precision, int krylov = OPM_KRYLOV_BICGSTAB,
+                    int restart = 0) {
   const size_t N = 3 * (size_t)pb->n_cells;
+  const size_t kb = krylov == OPM_KRYLOV_GMRES ? gmres_bytes(pb, restart) : krylov_bytes(pb);
   return align256(sizeof(double) * N) * 3 + align256(sizeof(double) * 9 * (size_t)pb->nnzb) +
-         align256(norms_bytes(pb)) + 256 + align256(ilu_bytes(pb, precision)) +
-         align256(krylov_bytes(pb));
+         align256(norms_bytes(pb)) + 256 + align256(ilu_bytes(pb, precision)) + align256(kb);
 }
 
 NewtonWork carve(const opm_problem* pb, int precision, void* work) {
@@ -184,8 +190,12 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
     OPM_TRY(ilu_factor(pb, w.J, w.ilu, o->precision, &w.flags[0], s));
     OPM_TRY_HIP(hipEventRecord(ev.e[2], s));
     opm_solve_report lr;
-    OPM_TRY(bicgstab(pb, w.J, w.ilu, o->precision, w.R, w.d, o->lin_rtol, o->lin_maxit, w.krylov,
-                     &lr, s));
+    if (o->krylov == OPM_KRYLOV_GMRES)
+      OPM_TRY(gmres(pb, w.J, w.ilu, o->precision, w.R, w.d, o->lin_rtol, o->lin_maxit, o->restart,
+                    w.krylov, &lr, s));
+    else
+      OPM_TRY(bicgstab(pb, w.J, w.ilu, o->precision, w.R, w.d, o->lin_rtol, o->lin_maxit,
+                       w.krylov, &lr, s));
     OPM_TRY_HIP(hipEventRecord(ev.e[3], s));
     rep->lin_its += lr.its;
     OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
@@ -414,14 +424,45 @@ int opm_bicgstab(const opm_problem* pb, const double* J, const void* ilu, int pr
                   as_stream(stream));
 }
 
+size_t opm_gmres_bytes(const opm_problem* pb, int32_t restart) {
+  return pb && restart >= 1 && restart <= OPM_GMRES_MAX_RESTART ? gmres_bytes(pb, restart) : 0;
+}
+
+int opm_gmres(const opm_problem* pb, const double* J, const void* ilu, int precision,
+              const double* b, double* x, double rtol, int32_t maxit, int32_t restart, void* work,
+              opm_solve_report* report, void* stream) {
+  if (!valid_problem(pb) || !valid_prec(precision) || !(rtol >= 0.0) || maxit < 0 || !report ||
+      restart < 1 || restart > OPM_GMRES_MAX_RESTART ||
+      (pb->n_cells > 0 && (!J || !ilu || !b || !x || !work)))
+    return OPM_EINVAL;
+  if (pb->n_cells == 0) {
+    memset(report, 0, sizeof(*report));
+    return OPM_OK;
+  }
+  return gmres(pb, J, const_cast<void*>(ilu), precision, b, x, rtol, maxit, restart, work,
+               report, as_stream(stream));
+}
+
 size_t opm_newton_bytes(const opm_problem* pb, int precision) {
   return pb && valid_prec(precision) ? newton_bytes(pb, precision) : 0;
+}
+
+static bool valid_krylov(const opm_newton_opts* o) {
+  return o->krylov == OPM_KRYLOV_BICGSTAB ||
+         (o->krylov == OPM_KRYLOV_GMRES && o->restart >= 1 &&
+          o->restart <= OPM_GMRES_MAX_RESTART);
+}
+
+size_t opm_newton_work_bytes(const opm_problem* pb, const opm_newton_opts* opts) {
+  return pb && opts && valid_prec(opts->precision) && valid_krylov(opts)
+             ? newton_bytes(pb, opts->precision, opts->krylov, opts->restart)
+             : 0;
 }
 
 static bool valid_opts(const opm_newton_opts* o) {
   return o && valid_prec(o->precision) && o->max_newton >= 0 && o->lin_maxit >= 0 &&
          o->max_cuts >= 0 && o->ds_max > 0.0 && o->dp_max_rel > 0.0 && o->lin_rtol >= 0.0 &&
-         o->tol_cnv >= 0.0 && o->tol_mb >= 0.0;
+         o->tol_cnv >= 0.0 && o->tol_mb >= 0.0 && valid_krylov(o);
 }
 
 int opm_newton_step(const opm_problem* pb, double* y, const double* y_prev, double dt,

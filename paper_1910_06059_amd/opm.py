@@ -23,6 +23,8 @@ LIB_PATH = os.path.join(_HERE, "libopm_gpu.so")
 
 OK, EINVAL, ESINGULAR, ENOTCONV, EBREAKDOWN, ENONFINITE, EHIP = 0, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_MIXED = 0, 1
+KRYLOV_BICGSTAB, KRYLOV_GMRES = 0, 1
+GMRES_MAX_RESTART = 32
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -71,7 +73,7 @@ class NewtonOpts(ctypes.Structure):
     _fields_ = [("tol_cnv", ctypes.c_double), ("tol_mb", ctypes.c_double),
                 ("ds_max", ctypes.c_double), ("dp_max_rel", ctypes.c_double),
                 ("lin_rtol", ctypes.c_double), ("max_newton", _i32), ("lin_maxit", _i32),
-                ("precision", _i32), ("max_cuts", _i32)]
+                ("precision", _i32), ("max_cuts", _i32), ("krylov", _i32), ("restart", _i32)]
 
 
 class NewtonReport(ctypes.Structure):
@@ -91,7 +93,8 @@ EXPORTS = [
     "opm_ilu_blocks_count", "opm_topology_build_blocks", "opm_geometry",
     "opm_well_index", "opm_well_groups", "opm_accumulation", "opm_norms_bytes", "opm_assemble",
     "opm_ilu0_bytes", "opm_ilu0_factor", "opm_ilu0_apply", "opm_spmv", "opm_krylov_bytes",
-    "opm_bicgstab", "opm_newton_bytes", "opm_newton_step", "opm_advance", "opm_set_option",
+    "opm_bicgstab", "opm_gmres_bytes", "opm_gmres", "opm_newton_bytes", "opm_newton_work_bytes",
+    "opm_newton_step", "opm_advance", "opm_set_option",
     "opm_ensemble_bytes", "opm_ensemble_prepare", "opm_ensemble_launch",
 ]
 
@@ -150,8 +153,14 @@ def lib():
         L.opm_krylov_bytes.restype = ctypes.c_size_t
         L.opm_bicgstab.argtypes = [P, _vp, _vp, ctypes.c_int, _vp, _vp, ctypes.c_double, _i32,
                                    _vp, ctypes.POINTER(SolveReport), _vp]
+        L.opm_gmres_bytes.argtypes = [P, _i32]
+        L.opm_gmres_bytes.restype = ctypes.c_size_t
+        L.opm_gmres.argtypes = [P, _vp, _vp, ctypes.c_int, _vp, _vp, ctypes.c_double, _i32, _i32,
+                                _vp, ctypes.POINTER(SolveReport), _vp]
         L.opm_newton_bytes.argtypes = [P, ctypes.c_int]
         L.opm_newton_bytes.restype = ctypes.c_size_t
+        L.opm_newton_work_bytes.argtypes = [P, ctypes.POINTER(NewtonOpts)]
+        L.opm_newton_work_bytes.restype = ctypes.c_size_t
         L.opm_newton_step.argtypes = [P, _vp, _vp, ctypes.c_double, ctypes.POINTER(NewtonOpts),
                                       _vp, ctypes.POINTER(NewtonReport), _vp]
         L.opm_advance.argtypes = [P, _vp, ctypes.c_double, ctypes.POINTER(NewtonOpts), _vp, _vp,
@@ -194,7 +203,8 @@ def set_option(option: int, value: int) -> None:
 
 def default_opts(case=None, precision=PREC_FP64, **kw) -> NewtonOpts:
     o = NewtonOpts(tol_cnv=1e-8, tol_mb=1e-11, ds_max=0.2, dp_max_rel=0.3, lin_rtol=1e-6,
-                   max_newton=20, lin_maxit=500, precision=precision, max_cuts=8)
+                   max_newton=20, lin_maxit=500, precision=precision, max_cuts=8,
+                   krylov=KRYLOV_BICGSTAB, restart=30)
     if case is not None:
         o.tol_cnv, o.tol_mb, o.lin_rtol = case.tol_cnv, case.tol_mb, case.lin_rtol
     for k, v in kw.items():
@@ -407,10 +417,25 @@ class GpuModel:
                               maxit, _ptr(work), ctypes.byref(rep), _stream()), "opm_bicgstab")
         return x, rep
 
+    def gmres(self, J, ilu, b, rtol=1e-6, maxit=500, restart=30, precision=PREC_FP64):
+        L = lib()
+        x = self.zeros_state()
+        work = self.workspace("gmres", L.opm_gmres_bytes(self._pbp(), restart))
+        rep = SolveReport()
+        _check(L.opm_gmres(self._pbp(), _ptr(J), _ptr(ilu), precision, _ptr(b), _ptr(x), rtol,
+                           maxit, restart, _ptr(work), ctypes.byref(rep), _stream()), "opm_gmres")
+        return x, rep
+
+    def newton_work(self, o: NewtonOpts) -> torch.Tensor:
+        nbytes = lib().opm_newton_work_bytes(self._pbp(), ctypes.byref(o))
+        if nbytes == 0:
+            raise OpmError(EINVAL, "opm_newton_work_bytes")
+        return self.workspace(f"newton{o.precision}", nbytes)
+
     def newton_step(self, y, y_prev, dt, opts: Optional[NewtonOpts] = None):
         L = lib()
         o = opts or default_opts(self.case)
-        work = self.workspace(f"newton{o.precision}", L.opm_newton_bytes(self._pbp(), o.precision))
+        work = self.newton_work(o)
         rep = NewtonReport()
         st = L.opm_newton_step(self._pbp(), _ptr(y), _ptr(y_prev), dt, ctypes.byref(o),
                                _ptr(work), ctypes.byref(rep), _stream())
@@ -421,7 +446,7 @@ class GpuModel:
     def advance(self, y, dt, opts: Optional[NewtonOpts] = None):
         L = lib()
         o = opts or default_opts(self.case)
-        work = self.workspace(f"newton{o.precision}", L.opm_newton_bytes(self._pbp(), o.precision))
+        work = self.newton_work(o)
         ysave = self.workspace("ysave", 24 * self.n).view(torch.float64)[:3 * self.n].view(self.n, 3)
         rep = NewtonReport()
         st = L.opm_advance(self._pbp(), _ptr(y), dt, ctypes.byref(o), _ptr(work), _ptr(ysave),
@@ -489,7 +514,7 @@ class GpuModel:
         """opm_advance_guess: (status, report, guess_used)."""
         L = _guess_lib()
         o = opts or default_opts(self.case)
-        work = self.workspace(f"newton{o.precision}", L.opm_newton_bytes(self._pbp(), o.precision))
+        work = self.newton_work(o)
         ysave = self.workspace("ysave", 24 * self.n).view(torch.float64)[:3 * self.n].view(self.n, 3)
         rep = NewtonReport()
         used = _i32()

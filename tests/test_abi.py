@@ -263,3 +263,34 @@ def test_invalid_problem_rejected_without_gpu():
     pb.nnzb = 6   # consistent sizes but null device arrays
     assert L.opm_assemble(ctypes.byref(pb), R, R, 1.0, R, R, None, None) == opm.EINVAL
     assert L.opm_newton_bytes(None, 0) == 0
+
+
+def test_gmres_sizes_and_option_checks_without_gpu():
+    """GMRes workspace sizes and the Krylov option checks are host-only."""
+    opm = _opm()
+    L = opm.lib()
+    pb = opm.Problem()
+    pb.n_cells, pb.n_faces, pb.nnzb = 4, 1, 6
+    assert L.opm_gmres_bytes(None, 30) == 0
+    for bad in (0, -1, opm.GMRES_MAX_RESTART + 1):
+        assert L.opm_gmres_bytes(ctypes.byref(pb), bad) == 0
+    # restart + 1 basis vectors of 3 n (padded to 32 doubles) at least
+    for m in (1, 8, opm.GMRES_MAX_RESTART):
+        assert L.opm_gmres_bytes(ctypes.byref(pb), m) >= 8 * 32 * (m + 1)
+    assert L.opm_gmres_bytes(ctypes.byref(pb), 8) < L.opm_gmres_bytes(ctypes.byref(pb), 9)
+    o = opm.default_opts()
+    assert o.krylov == opm.KRYLOV_BICGSTAB
+    assert L.opm_newton_work_bytes(ctypes.byref(pb), ctypes.byref(o)) == \
+        L.opm_newton_bytes(ctypes.byref(pb), o.precision)
+    o.krylov = opm.KRYLOV_GMRES
+    assert L.opm_newton_work_bytes(ctypes.byref(pb), ctypes.byref(o)) > \
+        L.opm_newton_bytes(ctypes.byref(pb), o.precision)
+    for krylov, restart in ((opm.KRYLOV_GMRES, 0), (opm.KRYLOV_GMRES, 33), (2, 30)):
+        o.krylov, o.restart = krylov, restart
+        assert L.opm_newton_work_bytes(ctypes.byref(pb), ctypes.byref(o)) == 0
+    # a solve with restart out of range or null buffers is rejected before any device work
+    rep = opm.SolveReport()
+    R = ctypes.c_void_p(1)
+    for restart in (0, 33):
+        assert L.opm_gmres(ctypes.byref(pb), R, R, 0, R, R, 1e-6, 10, restart, R,
+                           ctypes.byref(rep), None) == opm.EINVAL
