@@ -25,6 +25,7 @@ Also printed on the same JSON line:
                 of the same workload, on this machine's host cores.
 """
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -97,6 +98,24 @@ def block_factor_bytes_per_cell(precision: int) -> float:
     recurse = 7 * 72 + 72 + (36 if precision else 0)
     records = 6 * 72 + 9 * w + 2 * 36 * w + 2 * 16
     return recurse + records
+
+
+def gmres_cycle_bytes(n: int, nnzb: int, m: int, apply_bytes: float) -> float:
+    """Bytes of one GMRes(m) call of one cycle as designed (x0 = 0, m
+    iterations): x = 0 and ||b|| (b read, x written); the cycle-start
+    residual SpMV (plus b read), its norm (v_0 read) and scaling (v_0 read
+    and written); per iteration j the preconditioner solve (apply_bytes), the
+    SpMV, then classical Gram-Schmidt applied twice, which reads the basis
+    v_0 .. v_j three times (projections with w read; first update with w
+    read and written; second update and norm with w read and written), and
+    the next basis vector (w read, v_{j+1} written); the cycle ends with
+    x += Z y (z_0 .. z_{m-1} read, x read and written)."""
+    N8 = 24.0 * n
+    spmv = spmv_bytes_per_cell(nnzb, n) * n
+    total = 2 * N8 + (spmv + N8) + N8 + 2 * N8 + (m + 2) * N8
+    for j in range(m):
+        total += apply_bytes + spmv + 3 * (j + 1) * N8 + 7 * N8
+    return total
 
 
 def parse_blocks(spec, case):
@@ -454,6 +473,17 @@ def bench_kernels(args):
                               block_factor_bytes_per_cell(0) * n,
                               "k_factor_blocks + k_pack_block_records (FP64)"),
     }
+    # one GMRes(m) cycle with the FP64 block ILU0 (rtol 0: exactly m iterations)
+    m = args.restart
+    gwork = torch.empty(L.opm_gmres_bytes(pbb, m), dtype=torch.uint8, device=g.dev)
+    grep = opm.SolveReport()
+    xg = g.zeros_state()
+    kern["gmres_cycle"] = (
+        lambda: L.opm_gmres(pbb, sp(Jb_), sp(bilu[0]), 0, sp(R), sp(xg), 0.0, m, m, sp(gwork),
+                            ctypes.byref(grep), st),
+        gmres_cycle_bytes(n, g.nnzb, m, block_sweep_bytes_per_cell(0) * n),
+        f"one GMRes({m}) cycle: {m} x (k_apply_blocks + k_gm_spmv + k_gm_dots + k_gm_cgs1 + "
+        "k_gm_cgs2 + k_gm_rotate) + start and finish kernels (FP64 block ILU0)")
     if args.kernels:
         keep = set(args.kernels.split(","))
         kern = {k: v for k, v in kern.items() if k in keep}
@@ -462,6 +492,9 @@ def bench_kernels(args):
         t = timed(fn)
         res[name] = {"kernel": kname, "us": round(t * 1e6, 2), "bytes": int(nbytes),
                      "gbs": round(nbytes / t / 1e9, 1), "frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4)}
+        if name == "gmres_cycle":
+            assert grep.its == m and grep.status == opm.ENOTCONV, (grep.its, grep.status)
+            res[name]["us_per_iteration"] = round(t * 1e6 / m, 2)
     line = {"metric": f"kernel HBM roofline on the {n}-cell system (algorithmic bytes / HIP-event "
                       "time per launch)", "value": res.get("spmv", {}).get("frac"),
             "unit": "fraction of 8 TB/s (SpMV)", "n_gpus": 1, "steps": reps, "warmup": 3,
@@ -505,6 +538,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--krylov-graph", type=int, default=1,
                     help="replay BiCGStab chunks from HIP graphs (1) or enqueue kernel by kernel (0)")
+    ap.add_argument("--krylov", choices=["bicgstab", "gmres"], default="bicgstab",
+                    help="Newton's linear solver (c2)")
+    ap.add_argument("--restart", type=int, default=30, help="GMRes restart length")
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--kernel-grid", default="100x100x50",
                     help="grid of the c5-kernels table (C5: 100x100x50; 200x200x50 is the 2M-cell "
@@ -541,6 +577,8 @@ def main():
         args.steps = 30
     case = cases.config2()
     opts = opm.default_opts(case, precision=args.precision)
+    if args.krylov == "gmres":
+        opts.krylov, opts.restart = opm.KRYLOV_GMRES, args.restart
     dt = case.report_dt[0]
     stream = torch.cuda.current_stream()
     blocks = parse_blocks(args.ilu_blocks, case)
@@ -676,6 +714,7 @@ def main():
                    "n_cells": n, "nnzb": g.nnzb, "ilu_levels": g.n_levels,
                    "newton_tol_cnv": case.tol_cnv, "lin_rtol": case.lin_rtol,
                    "precision": "fp64" if args.precision == 0 else "mixed",
+                   "krylov": "BiCGStab" if args.krylov == "bicgstab" else f"GMRes({args.restart})",
                    "preconditioner": precond},
         "roofline": roofline,
         "breakdown": {
