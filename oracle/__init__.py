@@ -29,7 +29,9 @@ _u8p = ctypes.POINTER(ctypes.c_uint8)
 class Fluid(ctypes.Structure):
     _fields_ = [("rho_s", ctypes.c_double * 3), ("c", ctypes.c_double * 3),
                 ("p_ref", ctypes.c_double), ("mu", ctypes.c_double * 3),
-                ("swc", ctypes.c_double), ("n_corey", ctypes.c_double), ("g", ctypes.c_double)]
+                ("swc", ctypes.c_double), ("n_corey", ctypes.c_double), ("g", ctypes.c_double),
+                ("rs_c", ctypes.c_double), ("bo_r", ctypes.c_double), ("muo_r", ctypes.c_double),
+                ("eps_switch", ctypes.c_double), ("live", ctypes.c_int), ("pad", ctypes.c_int)]
 
 
 class Opts(ctypes.Structure):
@@ -109,6 +111,9 @@ def lib(path: Optional[str] = None):
         L.ora_advance.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.POINTER(Opts),
                                   ctypes.POINTER(Report)]
         L.ora_dense_solve.argtypes = [ctypes.c_int, _dp, _dp]
+        L.ora_set_meaning.argtypes = [ctypes.c_void_p, _u8p]
+        L.ora_set_meaning.restype = ctypes.c_int
+        L.ora_get_meaning.argtypes = [ctypes.c_void_p, _u8p]
         _libs[key] = L
     return _libs[key]
 
@@ -140,7 +145,10 @@ class Model:
         L = lib(lib_path)
         f = case.fluid
         self.fluid = Fluid((ctypes.c_double * 3)(*f.rho_s), (ctypes.c_double * 3)(*f.c), f.p_ref,
-                           (ctypes.c_double * 3)(*f.mu), f.swc, f.n_corey, f.g)
+                           (ctypes.c_double * 3)(*f.mu), f.swc, f.n_corey, f.g,
+                           getattr(f, "rs_c", 0.0), getattr(f, "bo_r", 0.0),
+                           getattr(f, "muo_r", 0.0), getattr(f, "eps_switch", 0.0),
+                           int(getattr(f, "live", False)), 0)
         dz = np.ascontiguousarray(case.dz, dtype=np.float64)
         perm = np.ascontiguousarray(case.perm_h, dtype=np.float64).ravel()
         poro = np.ascontiguousarray(case.poro, dtype=np.float64).ravel()
@@ -165,6 +173,8 @@ class Model:
         self.nf = L.ora_n_faces(self.h)
         self.nnzb = L.ora_nnzb(self.h)
         self.nc = L.ora_n_conns(self.h)
+        if hasattr(case, "initial_meaning"):
+            self.set_meaning(case.initial_meaning())
 
     def __del__(self):
         try:
@@ -195,6 +205,19 @@ class Model:
         well = np.zeros(max(self.nc, 1), np.int32)
         self.L.ora_conns(self.h, _i(cell), _d(wi), _i(well))
         return cell[:self.nc], wi[:self.nc], well[:self.nc]
+
+    # ---- state: meaning of the third variable per cell (0 s_g, 1 r_go)
+    def set_meaning(self, mean):
+        mean = np.ascontiguousarray(mean, dtype=np.uint8)
+        assert mean.shape == (self.n,)
+        st = self.L.ora_set_meaning(self.h, mean.ctypes.data_as(_u8p))
+        if st != OK:
+            raise ValueError("oracle: invalid variable meaning")
+
+    def meaning(self) -> np.ndarray:
+        out = np.zeros(max(self.n, 1), np.uint8)
+        self.L.ora_get_meaning(self.h, out.ctypes.data_as(_u8p))
+        return out[:self.n]
 
     # ---- path steps
     def accumulation(self, y):
@@ -278,14 +301,23 @@ class Model:
         return st, y, rep
 
     def run(self, y0=None, n_steps=None, opts=None):
-        """Advance over the case's report schedule; returns states after each report step."""
-        y = self.case.initial_state() if y0 is None else np.array(y0, dtype=np.float64)
+        """Advance over the case's report schedule; returns states after each
+        report step (their variable meanings in ``self.run_meanings``).
+        Without y0 the run starts from the case's initial state and meaning."""
+        if y0 is None:
+            y = self.case.initial_state()
+            if hasattr(self.case, "initial_meaning"):
+                self.set_meaning(self.case.initial_meaning())
+        else:
+            y = np.array(y0, dtype=np.float64)
         states, reps = [], []
+        self.run_meanings = []
         for dt in self.case.report_dt[:n_steps]:
             st, y, rep = self.advance(y, dt, opts)
             if st != OK:
                 raise RuntimeError(f"oracle advance failed with status {st}")
             states.append(y.copy())
+            self.run_meanings.append(self.meaning().copy())
             reps.append(rep.as_dict())
         return states, reps
 

@@ -140,6 +140,7 @@ struct ora_model {
   double* conn_wi; /* [nc] */
   int* conn_well;  /* [nc] */
   int blk[3];      /* ILU(0) subdomain box (cells per axis); 0: one block */
+  unsigned char* mean;   /* [n] meaning of the third variable: 0 s_g, 1 r_go */
 };
 
 int ora_n_cells(const ora_model* m) { return m->n; }
@@ -153,6 +154,7 @@ void ora_destroy(ora_model* m) {
   free(m->pv); free(m->depth); free(m->face); free(m->trans); free(m->row_ptr);
   free(m->col_idx); free(m->well_kind); free(m->well_phase); free(m->well_target);
   free(m->well_beg); free(m->conn_cell); free(m->conn_wi); free(m->conn_well);
+  free(m->mean);
   free(m);
 }
 
@@ -196,6 +198,7 @@ ora_model* ora_create(int nx, int ny, int nz, double dx, double dy, const double
   for (int b = 0; b < nb; ++b) m->box_cell[b] = (mask == NULL || mask[b]) ? n++ : -1;
   m->n = n;
   m->cell_box = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+  m->mean = (unsigned char*)calloc((size_t)n + 1, 1);
   for (int b = 0; b < nb; ++b)
     if (m->box_cell[b] >= 0) m->cell_box[m->box_cell[b]] = b;
 
@@ -343,18 +346,32 @@ typedef struct {
   dual b[3];    /* shrinkage / expansion factors */
   dual rho[3];  /* reservoir densities */
   dual lam[3];  /* mobilities k_r / mu */
+  dual r;       /* dissolved gas-oil ratio r_go (0 for dead oil) */
 } props;
 
-static void cell_props(const ora_fluid* f, const double* y, int off, props* P) {
+/* Properties of one cell from its (p, s_w, x) and the meaning of x (sec.
+ * 2.1.1, eq. primaryVariableMeaning): x = s_g (free gas present; for live
+ * oil the oil is then saturated, r_go = r_s(p)) or x = r_go (no free gas,
+ * s_g = 0).  Live oil (sec. 2.1.6): r_s(p) = rs_c p; dissolved gas swells
+ * the oil, b_o = exp(c_o (p - p_ref)) / (1 + bo_r r), thins it,
+ * mu_o = mu_o / (1 + muo_r r), and adds its surface mass to the oil
+ * density, rho_o = b_o (rho_oS + r rho_gS). */
+static void cell_props(const ora_fluid* f, const double* y, int off, int mean, props* P) {
   P->p = dvar(y[0], off + 0);
   dual sw = dvar(y[1], off + 1);
-  dual sg = dvar(y[2], off + 2);
+  dual x = dvar(y[2], off + 2);
+  dual sg = (f->live && mean == 1) ? dconst(0.0) : x;
+  P->r = !f->live ? dconst(0.0) : (mean == 1 ? x : dscale(P->p, f->rs_c));
   dual so = dsub(dsub(dconst(1.0), sw), sg);   /* s_w + s_o + s_g = 1 */
   P->s[0] = sw; P->s[1] = so; P->s[2] = sg;
   for (int a = 0; a < 3; ++a) {
     /* constant compressibility: (1/b) db/dp = c with b(p_ref) = 1 */
     P->b[a] = dexp(dscale(dsub(P->p, dconst(f->p_ref)), f->c[a]));
     P->rho[a] = dscale(P->b[a], f->rho_s[a]);   /* rho = b rho_S */
+  }
+  if (f->live) {
+    P->b[1] = ddiv(P->b[1], dadd(dconst(1.0), dscale(P->r, f->bo_r)));
+    P->rho[1] = dmul(P->b[1], dadd(dconst(f->rho_s[1]), dscale(P->r, f->rho_s[2])));
   }
   /* Corey two-phase curves with residuals 0 except connate water */
   double den = 1.0 - f->swc;
@@ -375,21 +392,50 @@ static void cell_props(const ora_fluid* f, const double* y, int off, props* P) {
   else
     kro = krow;
   P->lam[0] = ddiv(krw, dconst(f->mu[0]));
-  P->lam[1] = ddiv(kro, dconst(f->mu[1]));
+  P->lam[1] = f->live
+                  ? ddiv(kro, ddiv(dconst(f->mu[1]), dadd(dconst(1.0), dscale(P->r, f->muo_r))))
+                  : ddiv(kro, dconst(f->mu[1]));
   P->lam[2] = ddiv(krg, dconst(f->mu[2]));
 }
 
-void ora_accumulation(const ora_model* m, const double* y, double* acc) {
+/* Surface volume per pore volume of component a: b_a s_a, plus the gas
+ * dissolved in the oil, r b_o s_o, for the gas component. */
+static dual component_acc(const props* P, int a) {
+  dual A = dmul(P->b[a], P->s[a]);
+  if (a == 2) A = dadd(A, dmul(P->r, dmul(P->b[1], P->s[1])));
+  return A;
+}
+
+int ora_set_meaning(ora_model* m, const unsigned char* mean) {
+  for (int c = 0; c < m->n; ++c) {
+    const unsigned char v = mean ? mean[c] : 0;
+    if (v > 1 || (v == 1 && !m->fl.live)) return ORA_EINVAL;
+  }
+  for (int c = 0; c < m->n; ++c) m->mean[c] = mean ? mean[c] : 0;
+  return ORA_OK;
+}
+
+void ora_get_meaning(const ora_model* m, unsigned char* mean) {
+  memcpy(mean, m->mean, (size_t)m->n);
+}
+
+static void accumulation_of(const ora_model* m, const unsigned char* mean, const double* y,
+                            double* acc) {
   for (int c = 0; c < m->n; ++c) {
     props P;
-    cell_props(&m->fl, y + 3 * c, 0, &P);
-    for (int a = 0; a < 3; ++a) acc[3 * c + a] = P.b[a].v * P.s[a].v;
+    cell_props(&m->fl, y + 3 * c, 0, mean[c], &P);
+    for (int a = 0; a < 3; ++a) acc[3 * c + a] = component_acc(&P, a).v;
   }
+}
+
+void ora_accumulation(const ora_model* m, const double* y, double* acc) {
+  accumulation_of(m, m->mean, y, acc);
 }
 
 /* Well term of one connection as duals in slots 0-2 (sec. 2.2.1):
  * rate injector: fixed surface rate split over connections by WI share;
- * BHP producer: q_alpha = b_alpha lambda_alpha WI (p - p_bhp)^+ . */
+ * BHP producer: q_alpha = b_alpha lambda_alpha WI (p - p_bhp)^+, and for
+ * live oil the gas dissolved in the produced oil, r b_o lambda_o WI (.)^+ . */
 static void conn_rates(const ora_model* m, int q, const double* y, dual out[3]) {
   int w = m->conn_well[q];
   int c = m->conn_cell[q];
@@ -400,11 +446,13 @@ static void conn_rates(const ora_model* m, int q, const double* y, dual out[3]) 
     out[m->well_phase[w]] = dconst(-m->well_target[w] * m->conn_wi[q] / wsum);
   } else {
     props P;
-    cell_props(&m->fl, y + 3 * c, 0, &P);
+    cell_props(&m->fl, y + 3 * c, 0, m->mean[c], &P);
     dual dp = dsub(P.p, dconst(m->well_target[w]));
     if (dp.v > 0.0) {
       for (int a = 0; a < 3; ++a)
         out[a] = dmul(dscale(dmul(P.b[a], P.lam[a]), m->conn_wi[q]), dp);
+      if (m->fl.live)
+        out[2] = dadd(out[2], dmul(dscale(dmul(P.r, dmul(P.b[1], P.lam[1])), m->conn_wi[q]), dp));
     }
   }
 }
@@ -431,10 +479,10 @@ int ora_assemble(const ora_model* m, const double* y, const double* acc0, double
   /* accumulation: PV/dt (A - A0) */
   for (int c = 0; c < m->n; ++c) {
     props P;
-    cell_props(f, y + 3 * c, 0, &P);
+    cell_props(f, y + 3 * c, 0, m->mean[c], &P);
     int dblk = J ? find_block(m, c, c) : -1;
     for (int a = 0; a < 3; ++a) {
-      dual A = dmul(P.b[a], P.s[a]);
+      dual A = component_acc(&P, a);
       dual r = dscale(dsub(A, dconst(acc0[3 * c + a])), m->pv[c] / dt);
       R[3 * c + a] += r.v;
       if (J) add_block(J, dblk, a, r.d, 1.0);
@@ -444,8 +492,8 @@ int ora_assemble(const ora_model* m, const double* y, const double* acc0, double
   for (int fc = 0; fc < m->nf; ++fc) {
     int i = m->face[2 * fc], j = m->face[2 * fc + 1];
     props Pi, Pj;
-    cell_props(f, y + 3 * i, 0, &Pi);
-    cell_props(f, y + 3 * j, 3, &Pj);
+    cell_props(f, y + 3 * i, 0, m->mean[i], &Pi);
+    cell_props(f, y + 3 * j, 3, m->mean[j], &Pj);
     double T = m->trans[fc];
     dual dzij = dconst(m->depth[i] - m->depth[j]);
     int bii = -1, bij = -1, bjj = -1, bji = -1;
@@ -453,11 +501,19 @@ int ora_assemble(const ora_model* m, const double* y, const double* acc0, double
       bii = find_block(m, i, i); bij = find_block(m, i, j);
       bjj = find_block(m, j, j); bji = find_block(m, j, i);
     }
+    /* phase potentials and upwind cells; component a = phase a, plus for
+     * gas the gas dissolved in the oil phase, carried with the oil */
+    dual dphi[3];
+    const props* U[3];
     for (int a = 0; a < 3; ++a) {
       dual rho_avg = dscale(dadd(Pi.rho[a], Pj.rho[a]), 0.5);
-      dual dphi = dsub(dsub(Pi.p, Pj.p), dmul(dscale(rho_avg, f->g), dzij));
-      const props* U = (dphi.v >= 0.0) ? &Pi : &Pj;
-      dual F = dmul(dmul(U->b[a], U->lam[a]), dscale(dphi, T));
+      dphi[a] = dsub(dsub(Pi.p, Pj.p), dmul(dscale(rho_avg, f->g), dzij));
+      U[a] = (dphi[a].v >= 0.0) ? &Pi : &Pj;
+    }
+    for (int a = 0; a < 3; ++a) {
+      dual F = dmul(dmul(U[a]->b[a], U[a]->lam[a]), dscale(dphi[a], T));
+      if (a == 2 && f->live)
+        F = dadd(F, dmul(dmul(U[1]->r, dmul(U[1]->b[1], U[1]->lam[1])), dscale(dphi[1], T)));
       R[3 * i + a] += F.v;
       R[3 * j + a] -= F.v;
       if (J) {
@@ -491,7 +547,7 @@ void ora_norms(const ora_model* m, const double* y, const double* R, double dt, 
   for (int a = 0; a < 3; ++a) cnv[a] = 0.0;
   for (int c = 0; c < m->n; ++c) {
     props P;
-    cell_props(&m->fl, y + 3 * c, 0, &P);
+    cell_props(&m->fl, y + 3 * c, 0, m->mean[c], &P);
     pvsum += m->pv[c];
     for (int a = 0; a < 3; ++a) {
       double v = dt * fabs(R[3 * c + a]) / (P.b[a].v * m->pv[c]);
@@ -828,6 +884,28 @@ static int all_finite(int n, const double* a) {
   return 1;
 }
 
+/* Variable switch of one cell after an update (eq. primaryVariableMeaning,
+ * with a threshold against oscillation): free gas gone (s_g < -eps) ->
+ * x = r_go = r_s(p), the oil saturated at the switch; dissolved gas above
+ * saturation (r_go > r_s(p) (1 + eps)) -> x = s_g = 0, free gas appears from
+ * the next iteration on; a negative r_go is set to 0. */
+static void switch_variable(const ora_fluid* f, double* yc, unsigned char* mean) {
+  const double rs = f->rs_c * yc[0];
+  if (*mean == 0) {
+    if (yc[2] < -f->eps_switch) {
+      *mean = 1;
+      yc[2] = rs;
+    }
+  } else {
+    if (yc[2] > rs * (1.0 + f->eps_switch)) {
+      *mean = 0;
+      yc[2] = 0.0;
+    } else if (yc[2] < 0.0) {
+      yc[2] = 0.0;
+    }
+  }
+}
+
 int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double dt,
                     const ora_opts* o, ora_report* rep) {
   const int n = m->n, N = 3 * n;
@@ -865,21 +943,25 @@ int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double 
     if (st != ORA_OK) { status = st; break; }
     t0 = now_s();
     /* Appleyard-type chop: bound |dp| by dp_max_rel |p|, scale the saturation
-     * update of a cell so that its largest component is at most ds_max. */
+     * update of a cell so that its largest component is at most ds_max (the
+     * third variable counts only where it is s_g; a change of r_go is not
+     * chopped).  Then, for live oil, the variable switch. */
     for (int c = 0; c < n; ++c) {
       double dp = dx[3 * c], lim = o->dp_max_rel * fabs(y[3 * c]);
       if (dp > lim) dp = lim;
       if (dp < -lim) dp = -lim;
-      double dsw = dx[3 * c + 1], dsg = dx[3 * c + 2];
-      double mx = fmax(fabs(dsw), fabs(dsg));
+      const int is_sg = !m->fl.live || m->mean[c] == 0;
+      double dsw = dx[3 * c + 1], dx3 = dx[3 * c + 2];
+      double mx = is_sg ? fmax(fabs(dsw), fabs(dx3)) : fabs(dsw);
       if (mx > o->ds_max) {
         double sc = o->ds_max / mx;
         dsw *= sc;
-        dsg *= sc;
+        if (is_sg) dx3 *= sc;
       }
       y[3 * c] += dp;
       y[3 * c + 1] += dsw;
-      y[3 * c + 2] += dsg;
+      y[3 * c + 2] += dx3;
+      if (m->fl.live) switch_variable(&m->fl, y + 3 * c, &m->mean[c]);
     }
     rep->t_update += now_s() - t0;
     rep->newton_its++;
@@ -891,13 +973,14 @@ int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double 
   return status;
 }
 
-static void mass_error(const ora_model* m, const double* y_old, const double* y_new, double dt,
-                       double err[3]) {
+/* y_old with its meaning mean_old; y_new with the model's current one. */
+static void mass_error(const ora_model* m, const double* y_old, const unsigned char* mean_old,
+                       const double* y_new, double dt, double err[3]) {
   const int n = m->n;
   double* a0 = (double*)malloc(sizeof(double) * 3 * n);
   double* a1 = (double*)malloc(sizeof(double) * 3 * n);
   double* q = (double*)malloc(sizeof(double) * 3 * n);
-  ora_accumulation(m, y_old, a0);
+  accumulation_of(m, mean_old, y_old, a0);
   ora_accumulation(m, y_new, a1);
   ora_well_rates(m, y_new, q);
   for (int a = 0; a < 3; ++a) {
@@ -907,7 +990,7 @@ static void mass_error(const ora_model* m, const double* y_old, const double* y_
       M1 += m->pv[c] * a1[3 * c + a];
       Q += q[3 * c + a];
       props P;
-      cell_props(&m->fl, y_new + 3 * c, 0, &P);
+      cell_props(&m->fl, y_new + 3 * c, 0, m->mean[c], &P);
       bsum += P.b[a].v;
       pvs += m->pv[c];
     }
@@ -920,7 +1003,9 @@ int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts*
                 ora_report* rep) {
   const int N = 3 * m->n;
   double* yn = (double*)malloc(sizeof(double) * N);
+  unsigned char* mn = (unsigned char*)malloc((size_t)m->n + 1);
   memcpy(yn, y, sizeof(double) * N);
+  memcpy(mn, m->mean, (size_t)m->n);
   memset(rep, 0, sizeof(*rep));
   double t = 0.0, dt_try = dt_report;
   int status = ORA_OK;
@@ -937,17 +1022,19 @@ int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts*
     rep->t_update += r1.t_update;
     if (st == ORA_OK) {
       double e[3];
-      mass_error(m, yn, y, dt, e);
+      mass_error(m, yn, mn, y, dt, e);
       for (int a = 0; a < 3; ++a) {
         if (e[a] > rep->mass_err[a]) rep->mass_err[a] = e[a];
         rep->cnv[a] = r1.cnv[a];
         rep->mb[a] = r1.mb[a];
       }
       memcpy(yn, y, sizeof(double) * N);
+      memcpy(mn, m->mean, (size_t)m->n);
       t += dt;
       rep->substeps++;
     } else {
       memcpy(y, yn, sizeof(double) * N);
+      memcpy(m->mean, mn, (size_t)m->n);
       dt_try = 0.5 * dt;
       rep->cuts++;
       if (rep->cuts > o->max_cuts) { status = st; break; }
@@ -955,5 +1042,6 @@ int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts*
   }
   rep->status = status;
   free(yn);
+  free(mn);
   return status;
 }

@@ -22,7 +22,9 @@
  *   transmissibility    appendix B
  *
  * Units are SI throughout.  Phase / component order is (water, oil, gas);
- * the primary variables per cell are (p_o, s_w, s_g).  Cell numbering is the
+ * the primary variables per cell are (p_o, s_w, x) with x = s_g, or, for live
+ * oil in a cell without free gas, x = r_go (the meaning of x is a per-cell
+ * state held by the model, eq. primaryVariableMeaning).  Cell numbering is the
  * natural order of active cells, c = i + nx*(j + ny*k) restricted to the mask.
  *
  * Parity status of each function (what pins it) is listed in the header of
@@ -53,6 +55,13 @@ typedef struct ora_fluid {
   double swc;        /* connate water saturation                           */
   double n_corey;    /* Corey exponent of every two-phase curve            */
   double g;          /* gravitational acceleration [m/s^2]                 */
+  /* live oil (sec. 2.1.6: gas dissolved in the oleic phase; dry gas) */
+  double rs_c;       /* saturated gas-oil ratio r_s(p) = rs_c p [1/Pa]      */
+  double bo_r;       /* swelling: b_o = exp(c_o (p - p_ref)) / (1 + bo_r r) */
+  double muo_r;      /* thinning: mu_o = mu_o / (1 + muo_r r)               */
+  double eps_switch; /* threshold of the variable switch (s_g, relative r)  */
+  int live;          /* 0 dead oil (x = s_g everywhere), 1 live oil         */
+  int pad;
 } ora_fluid;
 
 typedef struct ora_opts {
@@ -106,7 +115,16 @@ void ora_pattern(const ora_model* m, int* row_ptr, int* col_idx);
 /* Well connections: active cell, well index, owning well [n_conns]. */
 void ora_conns(const ora_model* m, int* cell, double* wi, int* well);
 
-/* A_alpha = b_alpha s_alpha per cell (m_phi = 1): acc [n][3]. */
+/* The per-cell meaning of the third variable (0: s_g, 1: r_go), the state
+ * that goes with y: every function below reads the model's current meaning;
+ * ora_newton_step / ora_advance update it with y.  Set from `mean` [n] (NULL:
+ * every cell 0); dead oil requires all 0.  ORA_EINVAL for a value other
+ * than 0 or 1, or 1 with a dead-oil fluid. */
+int ora_set_meaning(ora_model* m, const unsigned char* mean);
+void ora_get_meaning(const ora_model* m, unsigned char* mean);
+
+/* A_alpha = b_alpha s_alpha per cell (m_phi = 1), plus r_go b_o s_o in the
+ * gas component for live oil: acc [n][3]. */
 void ora_accumulation(const ora_model* m, const double* y, double* acc);
 /* Surface well rates q [n][3] (outflux positive) at state y. */
 void ora_well_rates(const ora_model* m, const double* y, double* q);

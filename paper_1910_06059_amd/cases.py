@@ -46,6 +46,14 @@ class Fluid:
     swc: float = 0.12
     n_corey: float = 2.0
     g: float = G
+    # live oil (gas dissolved in the oil; dry gas): saturated gas-oil ratio
+    # r_s(p) = rs_c p, oil swelling b_o / (1 + bo_r r) and thinning
+    # mu_o / (1 + muo_r r), switching threshold eps_switch
+    live: bool = False
+    rs_c: float = 0.0
+    bo_r: float = 0.0
+    muo_r: float = 0.0
+    eps_switch: float = 1e-6
 
 
 @dataclasses.dataclass
@@ -76,6 +84,7 @@ class Case:
     p_init: float = 4800.0 * PSI
     sw_init: float = 0.12
     sg_init: float = 0.0
+    r_init: Optional[float] = None   # live oil: initial dissolved ratio (x = r_go, no free gas)
     report_dt: List[float] = dataclasses.field(default_factory=list)   # s
     tol_cnv: float = 1e-8
     tol_mb: float = 1e-11
@@ -96,8 +105,13 @@ class Case:
         y = np.empty((n, 3), dtype=np.float64)
         y[:, 0] = self.p_init
         y[:, 1] = self.sw_init
-        y[:, 2] = self.sg_init
+        y[:, 2] = self.sg_init if self.r_init is None else self.r_init
         return y
+
+    def initial_meaning(self) -> np.ndarray:
+        """[n_active] meaning of the third variable: 0 s_g, 1 r_go (the
+        initial state has no free gas when r_init is given)."""
+        return np.full(self.n_active, 0 if self.r_init is None else 1, dtype=np.uint8)
 
     def box_index(self, i: int, j: int, k: int) -> int:
         return i + self.nx * (j + self.ny * k)
@@ -251,13 +265,43 @@ def config5(seed: int = 5008, nx: int = 100, ny: int = 100, nz: int = 50) -> Cas
                 report_dt=[10 * DAY] * 25, seed=seed)
 
 
+def live_fluid(p_bubble: float = 3000.0 * PSI, r_bubble: float = 5.0) -> Fluid:
+    """Live oil whose saturated gas-oil ratio reaches r_bubble (sm3/sm3) at
+    the bubble point p_bubble (r_s(p) = r_bubble p / p_bubble); the oil
+    swells by 10 % and thins by 25 % at r_bubble."""
+    return Fluid(live=True, rs_c=r_bubble / p_bubble, bo_r=0.1 / r_bubble,
+                 muo_r=0.25 / r_bubble)
+
+
+def config_live(seed: int = 6, nx: int = 12, ny: int = 12, nz: int = 5) -> Case:
+    """Live-oil depletion with phase appearance (SPE9-like behaviour): oil
+    undersaturated at 3600 psi with a bubble point of 3000 psi (r_go = 5
+    sm3/sm3 everywhere, no free gas), a water injector in one corner column
+    and a producer held at 2500 psi, below the bubble point, in the opposite
+    column, so that free gas appears around the producer; 20 steps of 15
+    days."""
+    rng = np.random.default_rng(seed)
+    perm = lognormal_perm(rng, (nz, ny, nx), 100.0, 1.0)
+    poro = np.full((nz, ny, nx), 0.25)
+    p_b = 3000.0 * PSI
+    fluid = live_fluid(p_b, 5.0)
+    wells = [
+        Well("INJ", WELL_RATE_INJ, [(0, 0, k) for k in range(nz)], 300 * STB / DAY, phase=W),
+        Well("PROD", WELL_BHP_PROD, [(nx - 1, ny - 1, k) for k in range(nz)], 2500.0 * PSI),
+    ]
+    return Case(f"C6_live_{nx}x{ny}x{nz}", nx, ny, nz, 300 * FT, 300 * FT, np.full(nz, 20.0 * FT),
+                perm, poro, _full_mask(nz, ny, nx), fluid=fluid, wells=wells,
+                p_init=3600.0 * PSI, sw_init=0.12, r_init=fluid.rs_c * p_b,
+                report_dt=[15 * DAY] * 20, seed=seed)
+
+
 def box_case(nx: int, ny: int, nz: int, *, seed: int = 0, dx: float = 300 * FT,
              dy: float = 300 * FT, dz: Sequence[float] | float = 20 * FT,
              median_md: float = 100.0, sigma_ln: float = 1.0, poro: float = 0.3,
              wells: Optional[List[Well]] = None, mask: Optional[np.ndarray] = None,
              report_dt: Optional[List[float]] = None, fluid: Optional[Fluid] = None,
              p_init: float = 4800.0 * PSI, sw_init: float = 0.12, sg_init: float = 0.0,
-             name: Optional[str] = None) -> Case:
+             r_init: Optional[float] = None, name: Optional[str] = None) -> Case:
     """Small seeded box with configurable wells (tests and smoke runs)."""
     rng = np.random.default_rng(seed)
     perm = lognormal_perm(rng, (nz, ny, nx), median_md, sigma_ln)
@@ -271,7 +315,7 @@ def box_case(nx: int, ny: int, nz: int, *, seed: int = 0, dx: float = 300 * FT,
         mask = _full_mask(nz, ny, nx)
     return Case(name or f"box_{nx}x{ny}x{nz}_s{seed}", nx, ny, nz, dx, dy, dzv, perm,
                 np.full((nz, ny, nx), poro), mask, fluid=fluid or Fluid(), wells=wells,
-                p_init=p_init, sw_init=sw_init, sg_init=sg_init,
+                p_init=p_init, sw_init=sw_init, sg_init=sg_init, r_init=r_init,
                 report_dt=report_dt if report_dt is not None else [5 * DAY] * 3, seed=seed)
 
 

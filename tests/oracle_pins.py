@@ -662,6 +662,248 @@ def pin_mirror_symmetry(lib_path=None):
     assert Y[..., 1].max() > 0.121   # water actually moved
 
 
+# ------------------------------------------------------------ live oil
+# Live oil (sec. 2.1.6: gas dissolved in the oleic phase, dry gas) with the
+# per-cell meaning of the third variable (eq. primaryVariableMeaning):
+# x = s_g where free gas is present (the oil then saturated, r = r_s(p)),
+# x = r_go where it is not (s_g = 0).
+def _live_case(nx, ny, nz, seed, wells=None, g=cases.G, **kw):
+    fl = cases.live_fluid()
+    fl.g = g
+    if wells is None:
+        wells = [Well("I", cases.WELL_RATE_INJ, [(0, 0, k) for k in range(nz)], 300 * STB / DAY,
+                      phase=cases.W),
+                 Well("P", cases.WELL_BHP_PROD, [(nx - 1, ny - 1, nz - 1)], 2500 * PSI)]
+    kw.setdefault("dz", [6.0 + 3 * k for k in range(nz)])
+    return cases.box_case(nx, ny, nz, seed=seed, wells=wells, fluid=fl, **kw)
+
+
+def _live_state(c, seed, mean=None):
+    """A state with mixed meanings away from kinks: free-gas cells with
+    s_g in [0.03, 0.2], undersaturated cells with r in [0.3, 0.9] r_s(p)."""
+    rng = np.random.default_rng(seed)
+    n = c.n_active
+    if mean is None:
+        mean = rng.integers(0, 2, n).astype(np.uint8)
+    y = np.empty((n, 3))
+    y[:, 0] = rng.uniform(2800, 3200, n) * PSI
+    y[:, 1] = rng.uniform(0.15, 0.5, n)
+    rs = c.fluid.rs_c * y[:, 0]
+    y[:, 2] = np.where(mean == 0, rng.uniform(0.03, 0.2, n), rng.uniform(0.3, 0.9, n) * rs)
+    return y, mean
+
+
+def pin_live_dead_limit(lib_path=None):
+    """Live oil with no dissolution (r_s = 0) and every cell in the s_g
+    meaning is dead oil: residual and Jacobian equal the dead-oil ones
+    exactly, whatever the swelling and thinning coefficients."""
+    base = _wells_case(3, 3, 2, seed=7)
+    live = _wells_case(3, 3, 2, seed=7)
+    live.fluid = cases.Fluid(live=True, rs_c=0.0, bo_r=0.7, muo_r=0.3)
+    md, ml = _model(base, lib_path), _model(live, lib_path)
+    y = cases.random_state(base, seed=11)
+    acc0 = md.accumulation(cases.random_state(base, seed=12))
+    assert np.array_equal(ml.accumulation(y), md.accumulation(y))
+    st, Rd, Jd = md.assemble(y, acc0, 2 * DAY)
+    st, Rl, Jl = ml.assemble(y, acc0, 2 * DAY)
+    assert np.array_equal(Rd, Rl) and np.array_equal(Jd, Jl)
+
+
+def pin_live_switch_continuity(lib_path=None):
+    """At the switching point (no free gas, oil exactly saturated) a cell can
+    be written in either meaning: (s_g = 0) or (r = r_s(p)).  The residual
+    is the same, and by the chain rule (r = r_s(p) = rs_c p in the s_g
+    meaning) the Jacobian columns satisfy d/dp|_sg = d/dp|_r + rs_c d/dr and
+    d/ds_w|_sg = d/ds_w|_r, for the cell's own block and its neighbours'."""
+    c = _live_case(3, 3, 2, seed=4)
+    m = _model(c, lib_path)
+    y, mean = _live_state(c, seed=5)
+    y0, mean0 = _live_state(c, seed=6)
+    m.set_meaning(mean0)
+    acc0 = m.accumulation(y0)
+    S = np.array([1, 4, 7, 10, 16])           # cells put at the switching point
+    ya, ma = y.copy(), mean.copy()
+    ya[S, 2], ma[S] = 0.0, 0                  # s_g = 0
+    yb, mb = y.copy(), mean.copy()
+    yb[S, 2], mb[S] = c.fluid.rs_c * y[S, 0], 1   # r = r_s(p)
+    m.set_meaning(ma)
+    st, Ra, Ja = m.assemble(ya, acc0, 2 * DAY)
+    m.set_meaning(mb)
+    st, Rb, Jb = m.assemble(yb, acc0, 2 * DAY)
+    scale = np.abs(Ra).max(axis=0) + 1e-300
+    assert np.all(np.abs(Ra - Rb) <= 1e-13 * scale), np.abs(Ra - Rb).max(axis=0) / scale
+    Da, Db = _dense(m, Ja), _dense(m, Jb)
+    colscale = np.abs(Da).max(axis=0) + 1e-300
+    for cidx in S:
+        cp, cw, cx = 3 * cidx, 3 * cidx + 1, 3 * cidx + 2
+        lhs = Da[:, cp]
+        rhs = Db[:, cp] + c.fluid.rs_c * Db[:, cx]
+        assert np.all(np.abs(lhs - rhs) <= 1e-11 * colscale[cp]), np.abs(lhs - rhs).max()
+        assert np.all(np.abs(Da[:, cw] - Db[:, cw]) <= 1e-11 * colscale[cw])
+
+
+def pin_live_jacobian_fd(lib_path=None):
+    """Forward-mode AD Jacobian against central finite differences on a
+    live-oil state with both meanings present (the derivative of r_s(p)
+    enters through p in the s_g meaning)."""
+    c = _live_case(3, 3, 2, seed=7)
+    m = _model(c, lib_path)
+    y0, mean0 = _live_state(c, seed=12)
+    m.set_meaning(mean0)
+    acc0 = m.accumulation(y0)
+    y, mean = _live_state(c, seed=11)
+    m.set_meaning(mean)
+    dt = 2 * DAY
+    st, R, J = m.assemble(y, acc0, dt)
+    D = _dense(m, J)
+    FD = np.zeros_like(D)
+    for cidx in range(m.n):
+        for v in range(3):
+            h = 1e-7 * (abs(y[cidx, v]) + (1e5 if v == 0 else 0.0)) if v != 1 else 1e-7
+            yp, ym = y.copy(), y.copy()
+            yp[cidx, v] += h
+            ym[cidx, v] -= h
+            Rp = m.assemble(yp, acc0, dt, jacobian=False)[1].ravel()
+            Rm = m.assemble(ym, acc0, dt, jacobian=False)[1].ravel()
+            FD[:, 3 * cidx + v] = (Rp - Rm) / (2 * h)
+    colscale = np.abs(D).max(axis=0) + 1e-300
+    err = np.abs(D - FD) / colscale[None, :]
+    assert err.max() <= 1e-6, err.max()
+
+
+def pin_live_conservation(lib_path=None):
+    """Flux cancellation with dissolved gas: the residuals sum to the change
+    of surface volume in place (free plus dissolved gas) plus the well terms."""
+    c = _live_case(4, 3, 3, seed=3)
+    m = _model(c, lib_path)
+    y0, mean0 = _live_state(c, seed=6)
+    m.set_meaning(mean0)
+    a0 = m.accumulation(y0)
+    y, mean = _live_state(c, seed=5)
+    m.set_meaning(mean)
+    dt = 5 * DAY
+    st, R, _ = m.assemble(y, a0, dt, jacobian=False)
+    pv = m.geometry()["pore_vol"]
+    acc_term = pv[:, None] / dt * (m.accumulation(y) - a0)
+    q = m.well_rates(y)
+    lhs = R.sum(axis=0)
+    rhs = acc_term.sum(axis=0) + q.sum(axis=0)
+    scale = np.abs(acc_term).sum(axis=0) + np.abs(q).sum(axis=0)
+    assert np.all(np.abs(lhs - rhs) <= 1e-12 * scale), (lhs, rhs)
+
+
+def pin_live_closed_cell(lib_path=None):
+    """One closed cell without free gas that loses stock-tank oil at a fixed
+    surface rate Q (a negative-rate source of the oil component only) keeps
+    all its gas: the gas in place is the dissolved gas r N_o, so after a step
+    r = N_g / (N_o - Q dt) with N_g = r0 N_o.  Also the definition of the
+    swelling at p_ref: b_o = 1 / (1 + bo_r r)."""
+    Q = 0.02 * STB / DAY
+    wells = [Well("X", cases.WELL_RATE_INJ, [(0, 0, 0)], -Q, phase=cases.O)]
+    c = _live_case(1, 1, 1, seed=1, wells=wells, dx=20.0, dy=20.0, dz=2.0)
+    m = _model(c, lib_path)
+    r0 = 4.0
+    y = np.array([[3600 * PSI, c.fluid.swc, r0]])
+    m.set_meaning(np.array([1], np.uint8))
+    acc = m.accumulation(y)[0]
+    assert abs(acc[2] - r0 * acc[1]) <= 1e-14 * acc[2]     # gas in place = r N_o
+    pv = m.geometry()["pore_vol"][0]
+    dt = 2 * DAY
+    o = oracle.default_opts(c, tol_cnv=1e-12, tol_mb=1e-14)
+    st, y1, rep = m.newton_step(y, y, dt, o)
+    assert st == 0 and m.meaning()[0] == 1, (st, m.meaning())
+    No = pv * acc[1]
+    r1 = r0 * No / (No - Q * dt)
+    assert abs(y1[0, 2] - r1) <= 1e-9 * r1, (y1[0, 2], r1)
+    assert y1[0, 0] < y[0, 0]
+    yr = np.array([[c.fluid.p_ref, c.fluid.swc, 2.5]])
+    so = 1.0 - c.fluid.swc
+    assert abs(m.accumulation(yr)[0, 1] / so - 1.0 / (1.0 + c.fluid.bo_r * 2.5)) <= 1e-15
+
+
+def pin_live_dissolved_moves_with_oil(lib_path=None):
+    """The dissolved gas travels with the oil phase: between two cells
+    without free gas its flux is r of the oil's upwind cell times the oil
+    flux, also when gas and oil potentials point opposite ways (a column
+    whose pressure step lies between the oil and gas heads); a producer of
+    undersaturated oil produces gas at r times its oil rate."""
+    wells = [Well("P", cases.WELL_BHP_PROD, [(0, 0, 1)], 2500 * PSI)]
+    c = _live_case(1, 1, 2, seed=2, wells=wells, dx=30.0, dy=30.0, dz=[10.0, 10.0])
+    m = _model(c, lib_path)
+    m.set_meaning(np.array([1, 1], np.uint8))
+    fl = c.fluid
+    p_top = 3400 * PSI
+    rho_mid = 0.5 * (fl.rho_s[1] + fl.rho_s[2] * 3.0)   # between the gas and oil densities
+    y = np.array([[p_top, 0.3, 3.0], [p_top + fl.g * rho_mid * 10.0, 0.3, 4.5]])
+    st, R, _ = m.assemble(y, m.accumulation(y), DAY)
+    q = m.well_rates(y)
+    F = R - q     # the accumulation term is zero (acc0 = A(y)): fluxes only
+    assert F[0, 1] > 0                          # oil flows down, from the top cell
+    assert abs(F[0, 2] - 3.0 * F[0, 1]) <= 1e-12 * abs(F[0, 2]), (F[0], 3.0)
+    assert q[1, 1] > 0 and abs(q[1, 2] - 4.5 * q[1, 1]) <= 1e-14 * q[1, 2]
+
+
+def pin_live_hydrostatic_column(lib_path=None):
+    """A column of undersaturated live oil at rest: the discrete hydrostatic
+    profile uses the oil's mass per reservoir volume, which holds the
+    stock-tank oil and the dissolved gas, rho_o = b_o (rho_oS + r rho_gS)
+    (b_o read from the accumulation A_o = b_o s_o); no flux through any face."""
+    dz = np.array([10.0, 20.0, 5.0, 15.0])
+    c = _live_case(1, 1, 4, seed=3, wells=[], dx=30.0, dy=30.0, dz=dz)
+    m = _model(c, lib_path)
+    fl = c.fluid
+    r = 4.0
+    m.set_meaning(np.ones(4, np.uint8))
+    so = 1.0 - fl.swc
+
+    def rho(p):
+        bo = m.accumulation(np.array([[p, fl.swc] + [r]] * 4))[0, 1] / so
+        return bo * (fl.rho_s[1] + r * fl.rho_s[2])
+
+    zc = np.cumsum(dz) - dz / 2
+    p = [3500 * PSI]
+    for k in range(3):
+        hk = zc[k + 1] - zc[k]
+        f = lambda q, pk=p[-1]: q - pk - fl.g * 0.5 * (rho(pk) + rho(q)) * hk
+        p.append(brentq(f, p[-1], p[-1] + 1e7, xtol=1e-12, rtol=1e-15))
+    y = np.array([[pk, fl.swc, r] for pk in p])
+    st, R, _ = m.assemble(y, m.accumulation(y), DAY)
+    T = m.geometry()["trans"]
+    scale = T.max() * fl.g * rho(p[0]) * 20.0 / fl.mu[1]
+    assert np.all(np.abs(R) <= 1e-12 * scale), (np.abs(R).max(), scale)
+
+
+def pin_live_depletion_1d(lib_path=None):
+    """Horizontal 1-D depletion below the bubble point (producer at one end
+    at 2500 psi, bubble point 3000 psi, oil undersaturated at r_init): every
+    converged state is valid (no free gas below -eps, no dissolved gas above
+    r_s(p) (1 + eps)); cells without free gas keep r = r_init (the oil that
+    reaches them carries r_init, no free gas reaches them upstream of the
+    gas); free gas forms a contiguous zone at the producer end, only where
+    the pressure is below the bubble point; each step conserves mass."""
+    nx = 20
+    wells = [Well("P", cases.WELL_BHP_PROD, [(nx - 1, 0, 0)], 2500 * PSI)]
+    fl = cases.live_fluid()
+    c = cases.box_case(nx, 1, 1, seed=8, wells=wells, fluid=fl, dz=10.0, p_init=3300 * PSI,
+                       r_init=fl.rs_c * 3000 * PSI, report_dt=[5 * DAY] * 6, sigma_ln=0.0)
+    m = _model(c, lib_path)
+    states, reps = m.run()
+    eps = fl.eps_switch
+    r_init = c.r_init
+    for y, mean, rep in zip(states, m.run_meanings, reps):
+        assert max(rep["mass_err"]) <= 1e-10, rep["mass_err"]
+        free = mean == 0
+        rs = fl.rs_c * y[:, 0]
+        assert np.all(y[free, 2] >= -eps)
+        assert np.all(y[~free, 2] <= rs[~free] * (1 + eps))
+        assert np.all(np.abs(y[~free, 2] - r_init) <= 1e-8 * r_init), np.abs(y[~free, 2] - r_init).max()
+        if free.any():
+            first = int(np.argmax(free))
+            assert np.all(free[first:]), mean     # contiguous up to the producer
+            assert np.all(y[free, 0] < 3000 * PSI * (1 + eps))
+    assert (m.run_meanings[-1] == 0).sum() >= 2
+
+
 ALL_PINS = [
     pin_series_transmissibility, pin_depth_pore_volume, pin_peaceman_worked_value,
     pin_compressibility, pin_darcy_flux_upwind, pin_hydrostatic_column, pin_pressure_block,
@@ -669,5 +911,7 @@ ALL_PINS = [
     pin_bicgstab_dense, pin_block_ilu0_partition, pin_block_ilu0_special_cases,
     pin_block_ilu0_newton, pin_gmres_dense, pin_gmres_exact_lu, pin_gmres_minimal_residual,
     pin_gmres_newton, pin_one_cell_producer, pin_injector_mass, pin_quadratic_convergence,
-    pin_mass_balance_run, pin_mirror_symmetry,
+    pin_mass_balance_run, pin_mirror_symmetry, pin_live_dead_limit, pin_live_switch_continuity,
+    pin_live_jacobian_fd, pin_live_conservation, pin_live_closed_cell,
+    pin_live_dissolved_moves_with_oil, pin_live_hydrostatic_column, pin_live_depletion_1d,
 ]

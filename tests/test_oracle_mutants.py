@@ -19,7 +19,7 @@ MUTANTS = [
     ("gravity_sign", "dsub(dsub(Pi.p, Pj.p), dmul(dscale(rho_avg, f->g), dzij))",
      "dadd(dsub(Pi.p, Pj.p), dmul(dscale(rho_avg, f->g), dzij))"),
     ("density_not_averaged", "dscale(dadd(Pi.rho[a], Pj.rho[a]), 0.5)", "Pi.rho[a]"),
-    ("upwind_reversed", "(dphi.v >= 0.0) ? &Pi : &Pj", "(dphi.v >= 0.0) ? &Pj : &Pi"),
+    ("upwind_reversed", "(dphi[a].v >= 0.0) ? &Pi : &Pj", "(dphi[a].v >= 0.0) ? &Pj : &Pi"),
     ("flux_not_antisymmetric", "R[3 * j + a] -= F.v;", "R[3 * j + a] += F.v;"),
     ("offdiag_block_sign", "add_block(J, bij, a, F.d + 3, 1.0);", "add_block(J, bij, a, F.d + 3, -1.0);"),
     ("neighbour_block_swapped", "add_block(J, bji, a, F.d, -1.0);", "add_block(J, bji, a, F.d + 3, -1.0);"),
@@ -60,6 +60,24 @@ MUTANTS = [
     ("gmres_rotation_sign", "Hm(i + 1, j) = -sn[i] * a + cs[i] * c;", "Hm(i + 1, j) = sn[i] * a + cs[i] * c;"),
     ("gmres_update_unpreconditioned", "for (int k = 0; k < N; ++k) x[k] += z[k];",
      "for (int k = 0; k < N; ++k) x[k] += w[k];"),
+    # live oil
+    ("live_dissolved_gas_not_stored", "if (a == 2) A = dadd(A, dmul(P->r, dmul(P->b[1], P->s[1])));",
+     "if (a == 2) A = dadd(A, dconst(0.0));"),
+    ("live_dissolved_gas_gas_upwind",
+     "F = dadd(F, dmul(dmul(U[1]->r, dmul(U[1]->b[1], U[1]->lam[1])), dscale(dphi[1], T)));",
+     "F = dadd(F, dmul(dmul(U[2]->r, dmul(U[2]->b[1], U[2]->lam[1])), dscale(dphi[1], T)));"),
+    ("live_rs_derivative_dropped", "(mean == 1 ? x : dscale(P->p, f->rs_c))",
+     "(mean == 1 ? x : dconst(P->p.v * f->rs_c))"),
+    ("live_oil_density_without_gas",
+     "P->rho[1] = dmul(P->b[1], dadd(dconst(f->rho_s[1]), dscale(P->r, f->rho_s[2])));",
+     "P->rho[1] = dscale(P->b[1], f->rho_s[1]);"),
+    ("live_swelling_inverted", "P->b[1] = ddiv(P->b[1], dadd(dconst(1.0), dscale(P->r, f->bo_r)));",
+     "P->b[1] = dmul(P->b[1], dadd(dconst(1.0), dscale(P->r, f->bo_r)));"),
+    ("live_producer_without_dissolved_gas", "      if (m->fl.live)\n        out[2] = dadd(out[2],",
+     "      if (0)\n        out[2] = dadd(out[2],"),
+    ("live_gas_never_appears", "if (yc[2] > rs * (1.0 + f->eps_switch)) {", "if (0) {"),
+    ("live_free_gas_in_undersaturated_cell", "dual sg = (f->live && mean == 1) ? dconst(0.0) : x;",
+     "dual sg = x;"),
 ]
 
 
