@@ -72,6 +72,16 @@ typedef struct opm_fluid {
   double swc;        /* connate water saturation of the Corey curves        */
   double n_corey;    /* Corey exponent of every two-phase curve (>= 1)      */
   double g;          /* gravitational acceleration [m/s^2], depth positive down */
+  /* Live oil (sec. 2.1.6: gas dissolved in the oleic phase; dry gas).  With
+   * live = 0 the oil is dead and the fields below are unused. */
+  double rs_c;       /* saturated gas-oil ratio r_s(p) = rs_c p [1/Pa]      */
+  double bo_r;       /* swelling: b_o = exp(c_o (p - p_ref)) / (1 + bo_r r) */
+  double muo_r;      /* thinning: mu_o = mu_o / (1 + muo_r r); the oil
+                        density is rho_o = b_o (rho_oS + r rho_gS)          */
+  double eps_switch; /* threshold of the variable switch: free gas below
+                        -eps_switch, dissolved gas above r_s (1 + eps_switch) */
+  int32_t live;      /* 0 dead oil, 1 live oil                               */
+  int32_t pad;
 } opm_fluid;
 
 /* Connectivity of a masked nx*ny*nz Cartesian box (host arrays, filled by
@@ -233,6 +243,13 @@ typedef struct opm_problem {
   int32_t max_width;            /* opm_ilu_blocks.max_width                   */
   const int32_t* sub_level_ptr; /* [n_levels*(n_sub+1)] device copy          */
   const int32_t* slot;          /* [n_cells] device copy                      */
+  /* Meaning of the third primary variable per cell (sec. 2.1.1, eq.
+   * primaryVariableMeaning): 0 x = s_g (free gas present; live oil then
+   * saturated, r_go = r_s(p)), 1 x = r_go (live oil without free gas,
+   * s_g = 0).  Device [n_cells], part of the state that goes with y:
+   * opm_newton_step / opm_advance update it in place.  NULL for dead oil
+   * (every cell 0); required (non-NULL) for live oil. */
+  uint8_t* meaning;
 } opm_problem;
 
 /* Library set-up: checks that the current device is a gfx950 (MI355X) and
@@ -250,7 +267,11 @@ int opm_accumulation(const opm_problem* pb, const double* y, double* acc0, void*
 size_t opm_norms_bytes(const opm_problem* pb);
 
 /* Residual and Jacobian by forward-mode AD (sec. 2.4.1-2.4.2; eqs.
- * materialbalance, flux1, head, gwseg, wellinflow).  y, acc0: [n][3]; R:
+ * materialbalance, flux1, head, gwseg, wellinflow).  With live oil the gas
+ * component also holds the gas dissolved in the oil (r b_o s_o in the
+ * accumulation, r (b_o lambda_o) T dPhi_o upwinded with the oil phase in the
+ * flux, r times the oil rate in a producer), and the third Jacobian column
+ * of a cell is d/ds_g or d/dr_go by its meaning.  y, acc0: [n][3]; R:
  * [n][3] out; J: [nnzb][3][3] out (may be NULL for the residual only).
  * norms (may be NULL): device buffer of opm_norms_bytes; its first 8
  * doubles receive CNV_w, CNV_o, CNV_g, MB_w, MB_o, MB_g, max CNV, max MB,
@@ -368,7 +389,9 @@ size_t opm_newton_work_bytes(const opm_problem* pb, const opm_newton_opts* opts)
 
 /* One implicit Euler step of length dt (sec. 2.3): Newton iterations from
  * the guess in y (device [n][3], in/out) with y_prev the state at the start
- * of the step, each one assemble -> convergence test -> ILU(0) ->
+ * of the step (with live oil, pb->meaning at entry describes both y_prev
+ * and y, and is updated by the variable switch after each Newton update),
+ * each one assemble -> convergence test -> ILU(0) ->
  * BiCGStab (or GMRes) -> Appleyard-chopped update, at most max_newton
  * linear solves.
  * No time-step cutting (opm_advance does that).  work: device,
@@ -383,7 +406,9 @@ int opm_newton_step(const opm_problem* pb, double* y, const double* y_prev, doub
 /* Advance y (device, in/out) over a report step of length dt: substeps with
  * halving on failure (sec. 2.3 time-step cutting), at most max_cuts halvings;
  * after a cut the shorter substep length is kept for the rest of the report
- * step.  y_save: device [n][3] scratch for the last accepted state. */
+ * step.  y_save: device [n][3] scratch for the last accepted state; with
+ * live oil the variable meanings (pb->meaning) are saved and restored with
+ * it, in the Newton workspace. */
 int opm_advance(const opm_problem* pb, double* y, double dt, const opm_newton_opts* opts,
                 void* work, double* y_save, opm_newton_report* report, void* stream);
 
@@ -415,7 +440,8 @@ size_t opm_ensemble_bytes(const opm_problem* members, int32_t n_members, int pre
  * their states y[m] (host array of device pointers [n_cells_m][3], updated in
  * place by the launches).  Host, synchronous (copies a member table to the
  * device).  OPM_EINVAL if the widest ILU(0) level of a member does not fit
- * the kernel's LDS window. */
+ * the kernel's LDS window, or if a member's fluid is live oil (the ensemble
+ * kernel is dead oil only). */
 int opm_ensemble_prepare(const opm_problem* members, double* const* y, int32_t n_members,
                          int precision, void* work, size_t work_bytes);
 
@@ -529,7 +555,7 @@ int opm_guess_train_step(const opm_problem* pb, const opm_guess_net* net, const 
  * never taken).  work: the
  * Newton workspace (opm_newton_bytes, any precision).  chosen (host): 1 if
  * y_guess was taken; cnv (host [2]): max CNV at y_prev and at y_guess.
- * Synchronises the stream. */
+ * Synchronises the stream.  Dead oil only (OPM_EINVAL for live oil). */
 int opm_guess_select(const opm_problem* pb, double* y, const double* y_prev,
                      const double* y_guess, double dt, void* work, int32_t* chosen, double* cnv,
                      void* stream);
@@ -542,7 +568,7 @@ int opm_guess_select(const opm_problem* pb, double* y, const double* y_prev,
  * cut starts from the previous state.  net may be NULL (then it is
  * opm_advance).  guess_work: opm_guess_work_bytes; y_guess: device [n][3]
  * scratch; guess_used (host): 0 previous state, 1 learned guess,
- * 2 extrapolation. */
+ * 2 extrapolation.  With a net, dead oil only (OPM_EINVAL for live oil). */
 int opm_advance_guess(const opm_problem* pb, double* y, const double* y_nm1, double dt,
                       const opm_newton_opts* opts, const opm_guess_net* net, void* guess_work,
                       double* y_guess, void* work, double* y_save, opm_newton_report* report,

@@ -19,13 +19,14 @@ namespace {
 
 using namespace asmdev;
 
+template <bool LIVE>
 __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a) {
   __shared__ double sh[kBlock / kWave];
   const int i = blockIdx.x * kBlock + threadIdx.x;
   double part[kNormStride];
 #pragma unroll
   for (int k = 0; k < kNormStride; ++k) part[k] = 0.0;
-  if (i < a.n) assemble_row(a, i, a.dt, part);
+  if (i < a.n) assemble_row<LIVE>(a, i, a.dt, part);
   if (a.partials) {
     double out[kNormStride];
 #pragma unroll
@@ -77,13 +78,14 @@ __global__ __launch_bounds__(kBlock) void k_norms_final(const double* partials, 
   }
 }
 
+template <bool LIVE>
 __global__ __launch_bounds__(kBlock) void k_accumulation(int n, opm_fluid f, const double* y,
-                                                          double* acc) {
+                                                          const uint8_t* meaning, double* acc) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   FaceProps P;
   CellAcc A;
-  properties(f, y[3 * i], y[3 * i + 1], y[3 * i + 2], P, &A);
+  properties<LIVE>(f, y[3 * i], y[3 * i + 1], y[3 * i + 2], LIVE ? meaning[i] : 0, P, &A);
 #pragma unroll
   for (int c = 0; c < 3; ++c) acc[3 * i + c] = A.A[c].v;
 }
@@ -112,10 +114,14 @@ int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, 
   a.conn_rate = pb->conn_rate;
   a.conn_bhp = pb->conn_bhp;
   a.fluid = pb->fluid;
+  a.meaning = pb->meaning;
   a.R = R;
   a.J = J;
   a.partials = norms ? norms + 8 : nullptr;
-  hipLaunchKernelGGL(k_assemble, dim3(nblk), dim3(kBlock), 0, s, a);
+  if (pb->fluid.live)
+    hipLaunchKernelGGL(k_assemble<true>, dim3(nblk), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_assemble<false>, dim3(nblk), dim3(kBlock), 0, s, a);
   OPM_TRY_HIP(hipGetLastError());
   if (norms) {
     hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(kBlock), 0, s, norms + 8, nblk, pb->n_cells,
@@ -126,8 +132,13 @@ int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, 
 }
 
 int launch_accumulation(const opm_problem* pb, const double* y, double* acc0, hipStream_t s) {
-  hipLaunchKernelGGL(k_accumulation, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock), 0, s,
-                     pb->n_cells, pb->fluid, y, acc0);
+  const dim3 grid(blocks_for(pb->n_cells, kBlock));
+  if (pb->fluid.live)
+    hipLaunchKernelGGL(k_accumulation<true>, grid, dim3(kBlock), 0, s, pb->n_cells, pb->fluid, y,
+                       pb->meaning, acc0);
+  else
+    hipLaunchKernelGGL(k_accumulation<false>, grid, dim3(kBlock), 0, s, pb->n_cells, pb->fluid, y,
+                       pb->meaning, acc0);
   OPM_TRY_HIP(hipGetLastError());
   return OPM_OK;
 }

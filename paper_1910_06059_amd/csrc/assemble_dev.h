@@ -136,9 +136,18 @@ __device__ __forceinline__ D6 lift(const D3& a, int side) {
 // ------------------------------------------------------ cell properties
 struct FaceProps {
   double p;
-  double rho[3], drho[3];   // density and d rho / dp (rho depends on p only)
+  D3 rho[3];                // densities (live oil: with its dissolved gas)
   D3 mob[3];                // b_alpha * lambda_alpha
+  D3 rmob;                  // r b_o lambda_o: dissolved gas carried by the oil (live oil)
 };
+
+__device__ __forceinline__ D3 sel(bool c, const D3& x, const D3& y) {
+  D3 r;
+  r.v = c ? x.v : y.v;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r.d[k] = c ? x.d[k] : y.d[k];
+  return r;
+}
 
 // Element-wise select (keeps both operands in registers; a reference picked
 // at run time would force them to memory).
@@ -147,34 +156,42 @@ __device__ __forceinline__ FaceProps pick(bool c, const FaceProps& x, const Face
   r.p = c ? x.p : y.p;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    r.rho[a] = c ? x.rho[a] : y.rho[a];
-    r.drho[a] = c ? x.drho[a] : y.drho[a];
-    r.mob[a].v = c ? x.mob[a].v : y.mob[a].v;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) r.mob[a].d[k] = c ? x.mob[a].d[k] : y.mob[a].d[k];
+    r.rho[a] = sel(c, x.rho[a], y.rho[a]);
+    r.mob[a] = sel(c, x.mob[a], y.mob[a]);
   }
+  r.rmob = sel(c, x.rmob, y.rmob);
   return r;
 }
 
 struct CellAcc {
-  D3 A[3];                  // b_alpha s_alpha
+  D3 A[3];                  // b_alpha s_alpha (+ r b_o s_o for gas, live oil)
   double b[3];
 };
 
 // b = exp(c (p - p_ref)); rho = rho_S b; Corey curves with the segregation
-// model for three-phase oil; mob = b k_r / mu.
+// model for three-phase oil; mob = b k_r / mu.  The third variable x is s_g,
+// or, for live oil in a cell without free gas (mean = 1), r_go with s_g = 0
+// (eq. primaryVariableMeaning).  Live oil (sec. 2.1.6): r = r_s(p) = rs_c p
+// where free gas is present, b_o /= (1 + bo_r r), mu_o /= (1 + muo_r r),
+// rho_o = b_o (rho_oS + r rho_gS).
+template <bool LIVE>
 __device__ __forceinline__ void properties(const opm_fluid& f, double p_v, double sw_v,
-                                           double sg_v, FaceProps& P, CellAcc* acc) {
+                                           double x_v, int mean, FaceProps& P, CellAcc* acc) {
   D3 p = cst<3>(p_v);
   p.d[0] = 1.0;
   D3 sw = cst<3>(sw_v);
   sw.d[1] = 1.0;
-  D3 sg = cst<3>(sg_v);
-  sg.d[2] = 1.0;
+  D3 x = cst<3>(x_v);
+  x.d[2] = 1.0;
+  const bool undersat = LIVE && mean == 1;
+  const D3 sg = undersat ? cst<3>(0.0) : x;
+  D3 r = cst<3>(0.0);
+  if (LIVE) r = sel(undersat, x, p * f.rs_c);
   D3 so = (cst<3>(1.0) - sw) - sg;
   D3 b[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) b[a] = dexp((p - cst<3>(f.p_ref)) * f.c[a]);
+  if (LIVE) b[1] = quot(b[1], cst<3>(1.0) + r * f.bo_r);
   const double den = 1.0 - f.swc;
   D3 krw = dpow(clamp01((sw - cst<3>(f.swc)) / den), f.n_corey);
   D3 krg = dpow(clamp01(sg / den), f.n_corey);
@@ -187,9 +204,14 @@ __device__ __forceinline__ void properties(const opm_fluid& f, double p_v, doubl
   const D3 kr[3] = {krw, kro, krg};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    P.rho[a] = f.rho_s[a] * b[a].v;
-    P.drho[a] = f.rho_s[a] * b[a].d[0];
+    P.rho[a] = b[a] * f.rho_s[a];
     P.mob[a] = b[a] * (kr[a] / f.mu[a]);
+  }
+  P.rmob = cst<3>(0.0);
+  if (LIVE) {
+    P.rho[1] = b[1] * (cst<3>(f.rho_s[1]) + r * f.rho_s[2]);
+    P.mob[1] = b[1] * ((kro * (cst<3>(1.0) + r * f.muo_r)) / f.mu[1]);
+    P.rmob = r * P.mob[1];
   }
   if (acc) {
     const D3 s[3] = {sw, so, sg};
@@ -198,26 +220,38 @@ __device__ __forceinline__ void properties(const opm_fluid& f, double p_v, doubl
       acc->A[a] = b[a] * s[a];
       acc->b[a] = b[a].v;
     }
+    if (LIVE) acc->A[2] = acc->A[2] + r * (b[1] * so);
   }
 }
 
-// Flux of component a from lower cell L to upper cell H through a face of
-// transmissibility T: (b lambda)_U T dPhi with dPhi = p_L - p_H -
-// g (rho_L + rho_H)/2 (z_L - z_H), U = L if dPhi >= 0 else H.
-__device__ __forceinline__ D6 face_flux(const FaceProps& L, const FaceProps& H, int a, double dz,
-                                        double T, double g) {
+// Potential difference of phase a from lower cell L to upper cell H:
+// dPhi = p_L - p_H - g (rho_L + rho_H)/2 (z_L - z_H).
+__device__ __forceinline__ D6 potential(const FaceProps& L, const FaceProps& H, int a, double dz,
+                                        double g) {
   D6 pl = cst<6>(L.p);
   pl.d[0] = 1.0;
   D6 ph = cst<6>(H.p);
   ph.d[3] = 1.0;
-  D6 rl = cst<6>(L.rho[a]);
-  rl.d[0] = L.drho[a];
-  D6 rh = cst<6>(H.rho[a]);
-  rh.d[3] = H.drho[a];
-  D6 rho_avg = (rl + rh) * 0.5;
-  D6 dphi = (pl - ph) - (rho_avg * g) * dz;
+  D6 rho_avg = (lift(L.rho[a], 0) + lift(H.rho[a], 1)) * 0.5;
+  return (pl - ph) - (rho_avg * g) * dz;
+}
+
+// Flux of component a from lower cell L to upper cell H through a face of
+// transmissibility T: (b lambda)_U T dPhi, U = L if dPhi >= 0 else H; for
+// live oil the gas component adds the dissolved gas, (r b_o lambda_o)_Uo T
+// dPhi_o with the oil phase's potential and upwind cell.
+template <bool LIVE>
+__device__ __forceinline__ D6 face_flux(const FaceProps& L, const FaceProps& H, int a, double dz,
+                                        double T, double g) {
+  const D6 dphi = potential(L, H, a, dz, g);
   D6 mob = dphi.v >= 0.0 ? lift(L.mob[a], 0) : lift(H.mob[a], 1);
-  return mob * (dphi * T);
+  D6 F = mob * (dphi * T);
+  if (LIVE && a == 2) {
+    const D6 dphio = potential(L, H, 1, dz, g);
+    D6 rm = dphio.v >= 0.0 ? lift(L.rmob, 0) : lift(H.rmob, 1);
+    F = F + rm * (dphio * T);
+  }
+  return F;
 }
 
 struct AsmArgs {
@@ -239,6 +273,7 @@ struct AsmArgs {
   const double* conn_rate;
   const double* conn_bhp;
   opm_fluid fluid;
+  const uint8_t* meaning;   // [n] meaning of the third variable (live oil)
   double* R;
   double* J;
   double* partials;   // [gridDim.x][kNormStride] or null
@@ -246,13 +281,15 @@ struct AsmArgs {
 
 // Residual and Jacobian block row of cell i (one lane): writes R_i, the
 // blocks J_i* (if a.J) and the cell's contributions to the CNV/MB norms:
-// part = (dt|R_a|/(b_a PV) for a = w,o,g; R_a; b_a; PV).
+// part = (dt|R_a|/(b_a PV) for a = w,o,g; R_a; b_a; PV).  LIVE: live oil
+// with the cells' variable meanings in a.meaning.
+template <bool LIVE>
 __device__ __forceinline__ void assemble_row(const AsmArgs& a, int i, double dt,
                                              double part[kNormStride]) {
   const double yi0 = a.y[3 * i], yi1 = a.y[3 * i + 1], yi2 = a.y[3 * i + 2];
   FaceProps Pi;
   CellAcc Ai;
-  properties(a.fluid, yi0, yi1, yi2, Pi, &Ai);
+  properties<LIVE>(a.fluid, yi0, yi1, yi2, LIVE ? a.meaning[i] : 0, Pi, &Ai);
   const double pv = a.pv[i];
   const double zi = a.depth[i];
   D3 r[3];
@@ -267,7 +304,8 @@ __device__ __forceinline__ void assemble_row(const AsmArgs& a, int i, double dt,
       continue;
     }
     FaceProps Pj;
-    properties(a.fluid, a.y[3 * j], a.y[3 * j + 1], a.y[3 * j + 2], Pj, nullptr);
+    properties<LIVE>(a.fluid, a.y[3 * j], a.y[3 * j + 1], a.y[3 * j + 2],
+                     LIVE ? a.meaning[j] : 0, Pj, nullptr);
     const double T = a.trans[a.blk_face[q]];
     const double zj = a.depth[j];
     const bool lower = i < j;
@@ -277,7 +315,7 @@ __device__ __forceinline__ void assemble_row(const AsmArgs& a, int i, double dt,
     double blk[9];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      D6 F = face_flux(L, H, c, dz, T, a.fluid.g);
+      D6 F = face_flux<LIVE>(L, H, c, dz, T, a.fluid.g);
       if (lower) {
         r[c].v += F.v;
 #pragma unroll
@@ -301,7 +339,8 @@ __device__ __forceinline__ void assemble_row(const AsmArgs& a, int i, double dt,
     }
   }
   // wells of this cell (sec. 2.2.1): fixed-rate injector source or BHP
-  // producer q = b lambda WI (p - p_bhp)^+
+  // producer q = b lambda WI (p - p_bhp)^+ (live oil: plus r times the oil
+  // rate in the gas component)
   for (int t = a.cell_conn_ptr[i]; t < a.cell_conn_ptr[i + 1]; ++t) {
     const int k = a.cell_conn[t];
     if (a.conn_kind[k] == OPM_WELL_RATE_INJ) {
@@ -315,6 +354,7 @@ __device__ __forceinline__ void assemble_row(const AsmArgs& a, int i, double dt,
       if (dp.v > 0.0) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) r[c] = r[c] + (Pi.mob[c] * a.conn_wi[k]) * dp;
+        if (LIVE) r[2] = r[2] + (Pi.rmob * a.conn_wi[k]) * dp;
       }
     }
   }

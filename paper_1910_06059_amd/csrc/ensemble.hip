@@ -192,8 +192,8 @@ __device__ int wg_newton(const EnsMember& M, const Topo& tp, IluView<T> iv, doub
   for (int i = tid; i < n; i += NT) {
     FaceProps P;
     CellAcc A;
-    asmdev::properties(M.pb.fluid, M.y_save[3 * i], M.y_save[3 * i + 1], M.y_save[3 * i + 2],
-                       P, &A);
+    asmdev::properties<false>(M.pb.fluid, M.y_save[3 * i], M.y_save[3 * i + 1],
+                              M.y_save[3 * i + 2], 0, P, &A);
 #pragma unroll
     for (int c = 0; c < 3; ++c) M.acc0[3 * i + c] = A.A[c].v;
   }
@@ -217,6 +217,7 @@ __device__ int wg_newton(const EnsMember& M, const Topo& tp, IluView<T> iv, doub
   a.conn_rate = M.pb.conn_rate;
   a.conn_bhp = M.pb.conn_bhp;
   a.fluid = M.pb.fluid;
+  a.meaning = nullptr;   // dead oil only (opm_ensemble_prepare rejects live oil)
   a.R = M.R;
   a.J = M.J;
   a.partials = nullptr;
@@ -224,7 +225,7 @@ __device__ int wg_newton(const EnsMember& M, const Topo& tp, IluView<T> iv, doub
     double cmax[3] = {0.0, 0.0, 0.0}, sums[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int i = tid; i < n; i += NT) {
       double part[kNormStride];
-      asmdev::assemble_row(a, i, h, part);
+      asmdev::assemble_row<false>(a, i, h, part);
 #pragma unroll
       for (int c = 0; c < 3; ++c) cmax[c] = nan_max(cmax[c], part[c]);
 #pragma unroll
@@ -458,7 +459,8 @@ int opm_ensemble_prepare(const opm_problem* members, double* const* y, int32_t n
   int max_level = 0;
   for (int m = 0; m < n_members; ++m) {
     const opm_problem& pb = members[m];
-    if (pb.n_cells <= 0 || pb.nnzb != pb.n_cells + 2 * pb.n_faces || pb.n_levels <= 0 || !y[m])
+    if (pb.n_cells <= 0 || pb.nnzb != pb.n_cells + 2 * pb.n_faces || pb.n_levels <= 0 || !y[m] ||
+        pb.fluid.live != 0)
       return OPM_EINVAL;
     max_level = std::max(max_level, (int)pb.max_level);
   }

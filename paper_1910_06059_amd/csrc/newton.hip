@@ -51,6 +51,7 @@ struct NewtonWork {
   double* d;
   double* norms;
   int32_t* flags;   // [0] factor status, [1] non-finite update
+  uint8_t* mean_save;   // [n] variable meanings of the last accepted state (live oil)
   void* ilu;
   void* krylov;
 };
@@ -61,7 +62,8 @@ size_t newton_bytes(const opm_problem* pb, int precision, int krylov = OPM_KRYLO
   const size_t N = 3 * (size_t)pb->n_cells;
   const size_t kb = krylov == OPM_KRYLOV_GMRES ? gmres_bytes(pb, restart) : krylov_bytes(pb);
   return align256(sizeof(double) * N) * 3 + align256(sizeof(double) * 9 * (size_t)pb->nnzb) +
-         align256(norms_bytes(pb)) + 256 + align256(ilu_bytes(pb, precision)) + align256(kb);
+         align256(norms_bytes(pb)) + 256 + align256((size_t)pb->n_cells) +
+         align256(ilu_bytes(pb, precision)) + align256(kb);
 }
 
 NewtonWork carve(const opm_problem* pb, int precision, void* work) {
@@ -80,6 +82,8 @@ NewtonWork carve(const opm_problem* pb, int precision, void* work) {
   c += align256(norms_bytes(pb));
   w.flags = (int32_t*)c;
   c += 256;
+  w.mean_save = (uint8_t*)c;
+  c += align256((size_t)pb->n_cells);
   w.ilu = c;
   c += align256(ilu_bytes(pb, precision));
   w.krylov = c;
@@ -92,25 +96,47 @@ __global__ void k_clear_flags(int32_t* flags) {
 
 // y <- y - chop(d) where J d = R (so -d is the Newton update): |dp| is
 // bounded by dp_max_rel |p|; the saturation part is scaled so that its
-// largest component is at most ds_max.
+// largest component is at most ds_max (the third variable counts only where
+// it is s_g: a change of r_go is not chopped).  With live oil (meaning
+// non-null) the variable switch follows (eq. primaryVariableMeaning, with a
+// threshold against oscillation, sec. 2.3): free gas below -eps -> x =
+// r_go = r_s(p); dissolved gas above r_s(p) (1 + eps) -> x = s_g = 0; a
+// negative r_go is set to 0.
 __global__ __launch_bounds__(kBlock) void k_update(int n, double* y, const double* d,
                                                     double ds_max, double dp_max_rel,
+                                                    uint8_t* meaning, double rs_c, double eps,
                                                     int32_t* flags) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
+  const int mean = meaning ? meaning[i] : 0;
   const double p = y[3 * i];
   double dp = -d[3 * i];
   const double lim = dp_max_rel * fabs(p);
   if (dp > lim) dp = lim;
   if (dp < -lim) dp = -lim;
-  double dsw = -d[3 * i + 1], dsg = -d[3 * i + 2];
-  const double mx = fmax(fabs(dsw), fabs(dsg));
+  double dsw = -d[3 * i + 1], dx = -d[3 * i + 2];
+  const double mx = mean == 0 ? fmax(fabs(dsw), fabs(dx)) : fabs(dsw);
   if (mx > ds_max) {
     const double sc = ds_max / mx;
     dsw *= sc;
-    dsg *= sc;
+    if (mean == 0) dx *= sc;
   }
-  const double y0 = p + dp, y1 = y[3 * i + 1] + dsw, y2 = y[3 * i + 2] + dsg;
+  const double y0 = p + dp, y1 = y[3 * i + 1] + dsw;
+  double y2 = y[3 * i + 2] + dx;
+  if (meaning) {
+    const double rs = rs_c * y0;
+    if (mean == 0) {
+      if (y2 < -eps) {
+        meaning[i] = 1;
+        y2 = rs;
+      }
+    } else if (y2 > rs * (1.0 + eps)) {
+      meaning[i] = 0;
+      y2 = 0.0;
+    } else if (y2 < 0.0) {
+      y2 = 0.0;
+    }
+  }
   y[3 * i] = y0;
   y[3 * i + 1] = y1;
   y[3 * i + 2] = y2;
@@ -147,7 +173,10 @@ bool valid_problem(const opm_problem* pb) {
          pb->cell_conn_ptr && (pb->n_conns == 0 || (pb->cell_conn && pb->conn_kind &&
                                                      pb->conn_phase && pb->conn_wi &&
                                                      pb->conn_rate && pb->conn_bhp)) &&
-         pb->n_levels > 0 && pb->level_ptr_h[pb->n_levels] == pb->n_cells;
+         pb->n_levels > 0 && pb->level_ptr_h[pb->n_levels] == pb->n_cells &&
+         (pb->fluid.live == 0 || (pb->fluid.live == 1 && pb->meaning && pb->fluid.rs_c >= 0.0 &&
+                                  pb->fluid.bo_r >= 0.0 && pb->fluid.muo_r >= 0.0 &&
+                                  pb->fluid.eps_switch >= 0.0));
 }
 
 bool valid_prec(int p) { return p == OPM_PREC_FP64 || p == OPM_PREC_MIXED; }
@@ -210,8 +239,10 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
       status = lr.status;
       break;
     }
+    uint8_t* mean = pb->fluid.live ? pb->meaning : nullptr;
     hipLaunchKernelGGL(k_update, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, n, y, w.d,
-                       o->ds_max, o->dp_max_rel, w.flags);
+                       o->ds_max, o->dp_max_rel, mean, pb->fluid.rs_c, pb->fluid.eps_switch,
+                       w.flags);
     OPM_TRY_HIP(hipGetLastError());
     OPM_TRY_HIP(hipEventRecord(ev.e[4], s));
     OPM_TRY_HIP(hipEventSynchronize(ev.e[4]));
@@ -263,7 +294,12 @@ int advance(const opm_problem* pb, double* y, const double* y_nm1, double dt,
   const size_t bytes = sizeof(double) * 3 * (size_t)pb->n_cells;
   memset(report, 0, sizeof(*report));
   if (guess_used) *guess_used = 0;
+  // live oil: the variable meanings are saved and restored with the state
+  uint8_t* mean_save = pb->fluid.live ? carve(pb, opts->precision, work).mean_save : nullptr;
+  const size_t mbytes = (size_t)pb->n_cells;
   OPM_TRY_HIP(hipMemcpyAsync(y_save, y, bytes, hipMemcpyDeviceToDevice, s));
+  if (mean_save)
+    OPM_TRY_HIP(hipMemcpyAsync(mean_save, pb->meaning, mbytes, hipMemcpyDeviceToDevice, s));
   double t = 0.0, dt_try = dt;
   int status = OPM_OK;
   bool first = true;
@@ -292,10 +328,14 @@ int advance(const opm_problem* pb, double* y, const double* y_nm1, double dt,
         report->mb[c] = r1.mb[c];
       }
       OPM_TRY_HIP(hipMemcpyAsync(y_save, y, bytes, hipMemcpyDeviceToDevice, s));
+      if (mean_save)
+        OPM_TRY_HIP(hipMemcpyAsync(mean_save, pb->meaning, mbytes, hipMemcpyDeviceToDevice, s));
       t += h;
       report->substeps++;
     } else {
       OPM_TRY_HIP(hipMemcpyAsync(y, y_save, bytes, hipMemcpyDeviceToDevice, s));
+      if (mean_save)
+        OPM_TRY_HIP(hipMemcpyAsync(pb->meaning, mean_save, mbytes, hipMemcpyDeviceToDevice, s));
       dt_try = 0.5 * h;
       report->cuts++;
       if (report->cuts > opts->max_cuts) {
@@ -487,7 +527,7 @@ int opm_guess_select(const opm_problem* pb, double* y, const double* y_prev,
                      const double* y_guess, double dt, void* work, int32_t* chosen, double* cnv,
                      void* stream) {
   if (!valid_problem(pb) || pb->n_cells == 0 || !(dt > 0.0) || !y || !y_prev || !y_guess ||
-      !work)
+      !work || pb->fluid.live != 0)
     return OPM_EINVAL;
   return guess_select(pb, y, y_prev, &y_guess, 1, dt, work, chosen, cnv, as_stream(stream));
 }
@@ -499,7 +539,8 @@ int opm_advance_guess(const opm_problem* pb, double* y, const double* y_nm1, dou
   if (!valid_problem(pb) || pb->n_cells == 0 || !valid_opts(opts) || !(dt > 0.0) || !y ||
       !y_save || !work || !report)
     return OPM_EINVAL;
-  if (net && (!y_nm1 || !guess_work || !y_guess || opm_guess_work_bytes(pb, net) == 0))
+  if (net && (!y_nm1 || !guess_work || !y_guess || opm_guess_work_bytes(pb, net) == 0 ||
+              pb->fluid.live != 0))
     return OPM_EINVAL;
   return advance(pb, y, y_nm1, dt, opts, net, guess_work, y_guess, work, y_save, report,
                  guess_used, as_stream(stream));

@@ -35,7 +35,9 @@ _dp = ctypes.POINTER(ctypes.c_double)
 class Fluid(ctypes.Structure):
     _fields_ = [("rho_s", ctypes.c_double * 3), ("c", ctypes.c_double * 3),
                 ("p_ref", ctypes.c_double), ("mu", ctypes.c_double * 3),
-                ("swc", ctypes.c_double), ("n_corey", ctypes.c_double), ("g", ctypes.c_double)]
+                ("swc", ctypes.c_double), ("n_corey", ctypes.c_double), ("g", ctypes.c_double),
+                ("rs_c", ctypes.c_double), ("bo_r", ctypes.c_double), ("muo_r", ctypes.c_double),
+                ("eps_switch", ctypes.c_double), ("live", _i32), ("pad", _i32)]
 
 
 class Topology(ctypes.Structure):
@@ -61,7 +63,7 @@ class Problem(ctypes.Structure):
                 ("conn_kind", _vp), ("conn_phase", _vp), ("conn_wi", _vp), ("conn_rate", _vp),
                 ("conn_bhp", _vp), ("fluid", Fluid), ("sweep_span", _i32),
                 ("n_sub", _i32), ("max_sub", _i32), ("max_width", _i32),
-                ("sub_level_ptr", _vp), ("slot", _vp)]
+                ("sub_level_ptr", _vp), ("slot", _vp), ("meaning", _vp)]
 
 
 class SolveReport(ctypes.Structure):
@@ -324,7 +326,8 @@ class GpuModel:
         self.cell_conn = torch.from_numpy(cc).to(self.dev)
         f = case.fluid
         fl = Fluid((ctypes.c_double * 3)(*f.rho_s), (ctypes.c_double * 3)(*f.c), f.p_ref,
-                   (ctypes.c_double * 3)(*f.mu), f.swc, f.n_corey, f.g)
+                   (ctypes.c_double * 3)(*f.mu), f.swc, f.n_corey, f.g, f.rs_c, f.bo_r, f.muo_r,
+                   f.eps_switch, int(f.live), 0)
         self.pb = Problem(
             n_cells=n, n_faces=nf, nnzb=nnzb, n_levels=self.n_levels, max_level=self.max_level,
             n_conns=nc, trans=self.trans.data_ptr(), pore_vol=self.pore_vol.data_ptr(),
@@ -343,6 +346,11 @@ class GpuModel:
             self.pb.n_sub, self.pb.max_sub, self.pb.max_width = blk.n_sub, blk.max_sub, blk.max_width
             self.pb.sub_level_ptr = d["sub_level_ptr"].data_ptr()
             self.pb.slot = d["slot"].data_ptr()
+        # meaning of the third variable per cell (0 s_g, 1 r_go): live oil only
+        self.live = bool(f.live)
+        self.meaning_t = torch.from_numpy(case.initial_meaning()).to(self.dev)
+        if self.live:
+            self.pb.meaning = self.meaning_t.data_ptr()
         self._work = {}
         torch.cuda.current_stream().synchronize()
 
@@ -357,7 +365,21 @@ class GpuModel:
         return torch.as_tensor(np.ascontiguousarray(y, dtype=np.float64)).to(self.dev).contiguous()
 
     def initial_state(self) -> torch.Tensor:
+        """The case's initial state; also resets the variable meanings to the
+        case's initial ones (live oil)."""
+        self.set_meaning(self.case.initial_meaning())
         return self.state(self.case.initial_state())
+
+    def set_meaning(self, mean) -> None:
+        """Meaning of the third variable per cell (0 s_g, 1 r_go), the state
+        that goes with y for live oil."""
+        m = torch.as_tensor(np.ascontiguousarray(mean, dtype=np.uint8))
+        if m.shape != (self.n,) or (not self.live and bool(m.any())):
+            raise ValueError("meaning: one 0/1 value per cell, all 0 for dead oil")
+        self.meaning_t.copy_(m.to(self.dev))
+
+    def meaning(self) -> np.ndarray:
+        return self.meaning_t.cpu().numpy().copy()
 
     def pattern(self):
         return (self.host["row_ptr"][:self.n + 1].copy(), self.host["col_idx"][:self.nnzb].copy())
@@ -456,15 +478,19 @@ class GpuModel:
         return st, rep
 
     def run(self, y=None, n_steps=None, opts=None, keep_states=True):
-        """Advance over the case's report schedule (raises on a failed step)."""
+        """Advance over the case's report schedule (raises on a failed step);
+        with live oil the meanings after each step are in ``run_meanings``."""
         y = self.initial_state() if y is None else y
         states, reps = [], []
+        self.run_meanings = []
         for dt in self.case.report_dt[:n_steps]:
             st, rep = self.advance(y, dt, opts)
             if st != OK:
                 raise OpmError(st, "opm_advance")
             if keep_states:
                 states.append(y.detach().cpu().numpy().copy())
+                if self.live:
+                    self.run_meanings.append(self.meaning())
             reps.append(rep.as_dict())
         return y, states, reps
 
