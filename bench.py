@@ -403,6 +403,7 @@ def bench_kernels(args):
     repeated launches (on the launch stream) of the BSR SpMV, the ILU(0)
     application with FP64 and FP32 factors, the assembly and the ILU(0)
     factorisation, each divided into its algorithmic bytes."""
+    import numpy as np
     import torch
     from paper_1910_06059_amd import cases, opm
     nx, ny, nz = (int(v) for v in args.kernel_grid.lower().split("x"))
@@ -473,6 +474,27 @@ def bench_kernels(args):
                               block_factor_bytes_per_cell(0) * n,
                               "k_factor_blocks + k_pack_block_records (FP64)"),
     }
+    # assembly with live oil on the same grid: a seeded state, half of the
+    # cells with free gas (x = s_g), half undersaturated (x = r_go < r_s(p))
+    case_l = cases.config5(5008, nx, ny, nz)
+    case_l.fluid = cases.live_fluid()
+    gl = opm.GpuModel(case_l)
+    rng = np.random.default_rng(7)
+    mean_l = rng.integers(0, 2, gl.n).astype(np.uint8)
+    yl = np.empty((gl.n, 3))
+    yl[:, 0] = 3000 * cases.PSI + rng.uniform(-200, 200, gl.n) * cases.PSI
+    yl[:, 1] = rng.uniform(0.15, 0.4, gl.n)
+    yl[:, 2] = np.where(mean_l == 0, rng.uniform(0.02, 0.2, gl.n),
+                        rng.uniform(0.3, 0.9, gl.n) * case_l.fluid.rs_c * yl[:, 0])
+    gl.set_meaning(mean_l)
+    yl_t = gl.state(yl)
+    acc_l = gl.accumulation(yl_t)
+    Rl, Jl = torch.empty_like(R), torch.empty_like(J)
+    norms_l = torch.zeros(L.opm_norms_bytes(gl._pbp()) // 8, dtype=torch.float64, device=g.dev)
+    pbl = gl._pbp()
+    kern["assemble_live"] = (
+        lambda: L.opm_assemble(pbl, sp(yl_t), sp(acc_l), dt, sp(Rl), sp(Jl), sp(norms_l), st),
+        assemble_bytes(n, g.nnzb, g.nf) + n, "k_assemble<live> + k_norms_final (live oil)")
     # one GMRes(m) cycle with the FP64 block ILU0 (rtol 0: exactly m iterations)
     m = args.restart
     gwork = torch.empty(L.opm_gmres_bytes(pbb, m), dtype=torch.uint8, device=g.dev)
@@ -513,8 +535,9 @@ def main():
                     help="timed report steps (default: 30 for c2, 10 for c3, 20 for c4)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c3-mixed", "c4-ensemble", "c5-guess", "c5-kernels"],
-                    help="c2: the headline metric line; c3-mixed: FP32 ILU(0) vs FP64 on the "
+                    choices=["c2", "c3-mixed", "c4-ensemble", "c5-guess", "c5-kernels", "c6-live"],
+                    help="c2: the headline metric line; c6-live: the same line on a 24x25x15 "
+                         "live-oil depletion with phase appearance; c3-mixed: FP32 ILU(0) vs FP64 on the "
                          "masked 45k-cell grid; c4-ensemble: 64 members in one launch; "
                          "c5-guess: learned Newton guess on the 500k-cell waterflood; "
                          "c5-kernels: per-kernel HBM roofline at 500k cells")
@@ -575,7 +598,14 @@ def main():
         return bench_kernels(args)
     if args.steps is None:
         args.steps = 30
-    case = cases.config2()
+    live = args.workload == "c6-live"
+    if live:
+        case = cases.config_live(nx=24, ny=25, nz=15)
+        workload = ("24x25x15 live-oil depletion (bubble point 3000 psi, producer at 2500 psi: "
+                    "free gas appears), 9000 cells, 15-day implicit steps")
+    else:
+        case = cases.config2()
+        workload = "24x25x15 waterflood, 9000 cells, 10-day implicit steps"
     opts = opm.default_opts(case, precision=args.precision)
     if args.krylov == "gmres":
         opts.krylov, opts.restart = opm.KRYLOV_GMRES, args.restart
@@ -695,7 +725,7 @@ def main():
     achieved = k["bytes"] / k["seconds"] / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic(dom, args.precision),
+                "traffic": None if live else measured_traffic(dom, args.precision),
                 "kernel": k["kernel"], "avg_launch_us": round(k["seconds"] * 1e6, 3),
                 "bytes_per_launch": int(k["bytes"])}
 
@@ -710,7 +740,7 @@ def main():
         "ms_per_step": round(1e3 * wall / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == 0 else "f64+f32-ilu",
         "data": "synthetic",
-        "config": {"workload": "24x25x15 waterflood, 9000 cells, 10-day implicit steps",
+        "config": {"workload": workload,
                    "n_cells": n, "nnzb": g.nnzb, "ilu_levels": g.n_levels,
                    "newton_tol_cnv": case.tol_cnv, "lin_rtol": case.lin_rtol,
                    "precision": "fp64" if args.precision == 0 else "mixed",
@@ -729,11 +759,14 @@ def main():
     }
     if other is not None:
         line["single_block_ilu0"] = other
+    if live:
+        line["live_oil"] = {"free_gas_cells_at_end": int((g.meaning() == 0).sum()), "n_cells": n}
 
     if not args.no_cpu:
         import oracle
         m = oracle.Model(case)
         yo = case.initial_state()
+        m.set_meaning(case.initial_meaning())
         c_cni, c_wall, c_steps, passes = 0.0, 0.0, 0, 0
         while c_wall < args.cpu_seconds:
             t1 = time.perf_counter()
@@ -745,10 +778,11 @@ def main():
             c_steps += 1
             if c_steps % len(case.report_dt) == 0:   # schedule done: start it again
                 yo = case.initial_state()
+                m.set_meaning(case.initial_meaning())
                 passes += 1
         line["cpu_baseline"] = {"value": round(c_cni / c_wall, 1), "unit": "cell-Newton-iterations/s",
                                 "cores": 1, "kind": "oracle",
-                                "sample": f"{c_steps} 10-day steps of the same workload (its "
+                                "sample": f"{c_steps} {round(dt / 86400)}-day steps of the same workload (its "
                                           f"{len(case.report_dt)}-step schedule repeated from the "
                                           f"initial state; {c_wall:.1f} s, single-threaded plain C, -O2)"}
     print(json.dumps(line), flush=True)
