@@ -111,6 +111,17 @@ def lib(path: Optional[str] = None):
         L.ora_advance.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.POINTER(Opts),
                                   ctypes.POINTER(Report)]
         L.ora_dense_solve.argtypes = [ctypes.c_int, _dp, _dp]
+        L.ora_set_standard_wells.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.ora_set_standard_wells.restype = ctypes.c_int
+        L.ora_get_well_state.argtypes = [ctypes.c_void_p, _dp]
+        L.ora_set_well_state.argtypes = [ctypes.c_void_p, _dp]
+        L.ora_well_storage_start.argtypes = [ctypes.c_void_p]
+        L.ora_well_system.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, _dp, _dp, _dp, _dp]
+        L.ora_well_system.restype = ctypes.c_int
+        L.ora_schur_solve.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                      ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      _dp, _dp]
+        L.ora_schur_solve.restype = ctypes.c_int
         L.ora_set_meaning.argtypes = [ctypes.c_void_p, _u8p]
         L.ora_set_meaning.restype = ctypes.c_int
         L.ora_get_meaning.argtypes = [ctypes.c_void_p, _u8p]
@@ -175,6 +186,14 @@ class Model:
         self.nc = L.ora_n_conns(self.h)
         if hasattr(case, "initial_meaning"):
             self.set_meaning(case.initial_meaning())
+        self.nw = nw
+        self.std_wells = bool(getattr(case, "standard_wells", False))
+        if self.std_wells:
+            vol, x0 = case.standard_well_init()
+            st = L.ora_set_standard_wells(self.h, _d(np.ascontiguousarray(vol, dtype=np.float64)),
+                                          _d(np.ascontiguousarray(x0, dtype=np.float64)))
+            if st != OK:
+                raise ValueError("oracle: invalid standard wells")
 
     def __del__(self):
         try:
@@ -218,6 +237,38 @@ class Model:
         out = np.zeros(max(self.n, 1), np.uint8)
         self.L.ora_get_meaning(self.h, out.ctypes.data_as(_u8p))
         return out[:self.n]
+
+    # ---- standard wells (well unknowns Q_t, F_w, F_g, p_bhp per well)
+    def well_state(self) -> np.ndarray:
+        x = np.zeros((max(self.nw, 1), 4))
+        self.L.ora_get_well_state(self.h, _d(x))
+        return x[:self.nw]
+
+    def set_well_state(self, x):
+        self.L.ora_set_well_state(self.h, _d(np.ascontiguousarray(x, dtype=np.float64)))
+
+    def well_storage_start(self):
+        self.L.ora_well_storage_start(self.h)
+
+    def well_system(self, y, dt):
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        Rw = np.zeros((self.nw, 4))
+        B = np.zeros((max(self.nc, 1), 4, 3))
+        C = np.zeros((max(self.nc, 1), 3, 4))
+        D = np.zeros((self.nw, 4, 4))
+        st = self.L.ora_well_system(self.h, _d(y), dt, _d(Rw), _d(B), _d(C), _d(D))
+        return st, Rw, B[:self.nc], C[:self.nc], D
+
+    def schur_solve(self, J, F, B, C, D, Rr, Rw, rtol=1e-10, maxit=500, krylov=0, restart=30):
+        xr = np.zeros((self.n, 3))
+        xw = np.zeros((self.nw, 4))
+        its = ctypes.c_double()
+        rr = ctypes.c_double()
+        f = lambda a: _d(np.ascontiguousarray(a, dtype=np.float64))
+        st = self.L.ora_schur_solve(self.h, f(J), f(F), f(B), f(C), f(D), f(Rr), f(Rw), _d(xr),
+                                    _d(xw), rtol, maxit, krylov, restart, ctypes.byref(its),
+                                    ctypes.byref(rr))
+        return st, xr, xw, its.value
 
     # ---- path steps
     def accumulation(self, y):
@@ -308,16 +359,21 @@ class Model:
             y = self.case.initial_state()
             if hasattr(self.case, "initial_meaning"):
                 self.set_meaning(self.case.initial_meaning())
+            if self.std_wells:
+                self.set_well_state(self.case.standard_well_init()[1])
         else:
             y = np.array(y0, dtype=np.float64)
         states, reps = [], []
         self.run_meanings = []
+        self.run_well_states = []
         for dt in self.case.report_dt[:n_steps]:
             st, y, rep = self.advance(y, dt, opts)
             if st != OK:
                 raise RuntimeError(f"oracle advance failed with status {st}")
             states.append(y.copy())
             self.run_meanings.append(self.meaning().copy())
+            if self.std_wells:
+                self.run_well_states.append(self.well_state().copy())
             reps.append(rep.as_dict())
         return states, reps
 

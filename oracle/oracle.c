@@ -42,9 +42,10 @@ static double now_s(void) {
 
 /* ------------------------------------------- forward-mode AD (sec. 2.4.1)
  * A value paired with a fixed number of partial derivatives; every operation
- * applies the chain rule.  Slots 0-2 are d/d(p, s_w, s_g) of the first cell
- * of a connection, slots 3-5 those of the second cell. */
-#define ND 6
+ * applies the chain rule.  Slots 0-2 are d/d(p, s_w, x) of the first cell
+ * of a connection, slots 3-5 those of the second cell; for a standard-well
+ * connection slots 3-6 are d/d(Q_t, F_w, F_g, p_bhp) of the well. */
+#define ND 7
 typedef struct {
   double v;
   double d[ND];
@@ -141,6 +142,10 @@ struct ora_model {
   int* conn_well;  /* [nc] */
   int blk[3];      /* ILU(0) subdomain box (cells per axis); 0: one block */
   unsigned char* mean;   /* [n] meaning of the third variable: 0 s_g, 1 r_go */
+  int std_wells;         /* 1: standard well model with well unknowns */
+  double* well_vol;      /* [nw] wellbore volume V_w */
+  double* wx;            /* [nw][4] well state (Q_t, F_w, F_g, p_bhp) */
+  double* wA0;           /* [nw][3] wellbore storage at the start of the step */
 };
 
 int ora_n_cells(const ora_model* m) { return m->n; }
@@ -155,6 +160,7 @@ void ora_destroy(ora_model* m) {
   free(m->col_idx); free(m->well_kind); free(m->well_phase); free(m->well_target);
   free(m->well_beg); free(m->conn_cell); free(m->conn_wi); free(m->conn_well);
   free(m->mean);
+  free(m->well_vol); free(m->wx); free(m->wA0);
   free(m);
 }
 
@@ -432,6 +438,9 @@ void ora_accumulation(const ora_model* m, const double* y, double* acc) {
   accumulation_of(m, m->mean, y, acc);
 }
 
+static void std_conn_rate(const ora_model* m, int q, const double* y, const double* wx,
+                          dual out[3]);
+
 /* Well term of one connection as duals in slots 0-2 (sec. 2.2.1):
  * rate injector: fixed surface rate split over connections by WI share;
  * BHP producer: q_alpha = b_alpha lambda_alpha WI (p - p_bhp)^+, and for
@@ -461,7 +470,10 @@ void ora_well_rates(const ora_model* m, const double* y, double* qout) {
   memset(qout, 0, sizeof(double) * 3 * m->n);
   for (int q = 0; q < m->nc; ++q) {
     dual r[3];
-    conn_rates(m, q, y, r);
+    if (m->std_wells)
+      std_conn_rate(m, q, y, m->wx, r);
+    else
+      conn_rates(m, q, y, r);
     for (int a = 0; a < 3; ++a) qout[3 * m->conn_cell[q] + a] += r[a].v;
   }
 }
@@ -528,7 +540,10 @@ int ora_assemble(const ora_model* m, const double* y, const double* acc0, double
   for (int q = 0; q < m->nc; ++q) {
     int c = m->conn_cell[q];
     dual r[3];
-    conn_rates(m, q, y, r);
+    if (m->std_wells)
+      std_conn_rate(m, q, y, m->wx, r);
+    else
+      conn_rates(m, q, y, r);
     int dblk = J ? find_block(m, c, c) : -1;
     for (int a = 0; a < 3; ++a) {
       R[3 * c + a] += r[a].v;
@@ -719,6 +734,236 @@ void ora_spmv(const ora_model* m, const double* J, const double* x, double* y) {
   }
 }
 
+
+/* ---------------------------------------------- standard wells (sec. 2.2.1)
+ * Each well has the unknowns x_w = (Q_t, F_w, F_g, p_bhp) (eq.
+ * weighted_total_rate): the weighted total surface rate (production
+ * positive), the weighted water and gas fractions of the wellbore fluid and
+ * the bottom-hole pressure, with weights g = (1, 1, 0.01); the component
+ * surface rates are Q_a = F_a Q_t / g_a with F_o = 1 - F_w - F_g.  The
+ * wellbore fluid holds mix_a = (F_a / g_a) / sum_b F_b / (g_b b_b(p_bhp))
+ * surface volume of component a per reservoir volume (b at p_bhp, no gas
+ * dissolved in the wellbore). */
+static const double kWellG[3] = {1.0, 1.0, 0.01};
+
+typedef struct {
+  dual Qt, F[3], pb;
+  dual mix[3];
+} wellvars;
+
+static void well_vars(const ora_fluid* f, const double* xw, wellvars* W) {
+  W->Qt = dvar(xw[0], 3);
+  W->F[0] = dvar(xw[1], 4);
+  W->F[2] = dvar(xw[2], 5);
+  W->F[1] = dsub(dsub(dconst(1.0), W->F[0]), W->F[2]);
+  W->pb = dvar(xw[3], 6);
+  dual S = dconst(0.0);
+  for (int a = 0; a < 3; ++a) {
+    dual b = dexp(dscale(dsub(W->pb, dconst(f->p_ref)), f->c[a]));
+    S = dadd(S, ddiv(dscale(W->F[a], 1.0 / kWellG[a]), b));
+  }
+  for (int a = 0; a < 3; ++a) W->mix[a] = ddiv(dscale(W->F[a], 1.0 / kWellG[a]), S);
+}
+
+/* Surface rate of each component through connection q (production
+ * positive; eq. wellinflow with h_w,j = 0): a producing connection
+ * (p_j > p_bhp) carries the cell's phases, q_a = WI b_a lambda_a (p_j -
+ * p_bhp) (live oil: plus r b_o lambda_o for gas); an injecting one carries
+ * the wellbore fluid at the cell's total mobility, q_a = WI lambda_t (p_j -
+ * p_bhp) mix_a.  Slots 0-2: the cell's variables; 3-6: the well's. */
+static void std_conn_rate(const ora_model* m, int q, const double* y, const double* wx,
+                          dual out[3]) {
+  const int c = m->conn_cell[q], w = m->conn_well[q];
+  props P;
+  cell_props(&m->fl, y + 3 * c, 0, m->mean[c], &P);
+  wellvars W;
+  well_vars(&m->fl, wx + 4 * w, &W);
+  dual dp = dsub(P.p, W.pb);
+  const double wi = m->conn_wi[q];
+  if (dp.v > 0.0) {
+    for (int a = 0; a < 3; ++a) out[a] = dmul(dscale(dmul(P.b[a], P.lam[a]), wi), dp);
+    if (m->fl.live)
+      out[2] = dadd(out[2], dmul(dscale(dmul(P.r, dmul(P.b[1], P.lam[1])), wi), dp));
+  } else {
+    dual lt = dadd(dadd(P.lam[0], P.lam[1]), P.lam[2]);
+    for (int a = 0; a < 3; ++a) out[a] = dmul(dmul(dscale(lt, wi), dp), W.mix[a]);
+  }
+}
+
+int ora_set_standard_wells(ora_model* m, const double* well_vol, const double* x0) {
+  if (m->nw == 0) return ORA_EINVAL;
+  for (int w = 0; w < m->nw; ++w)
+    if (!(well_vol[w] >= 0.0)) return ORA_EINVAL;
+  free(m->well_vol); free(m->wx); free(m->wA0);
+  m->well_vol = (double*)malloc(sizeof(double) * m->nw);
+  m->wx = (double*)malloc(sizeof(double) * 4 * m->nw);
+  m->wA0 = (double*)calloc(3 * (size_t)m->nw, sizeof(double));
+  memcpy(m->well_vol, well_vol, sizeof(double) * m->nw);
+  memcpy(m->wx, x0, sizeof(double) * 4 * m->nw);
+  m->std_wells = 1;
+  return ORA_OK;
+}
+
+void ora_get_well_state(const ora_model* m, double* x) {
+  if (m->std_wells) memcpy(x, m->wx, sizeof(double) * 4 * m->nw);
+}
+
+void ora_set_well_state(ora_model* m, const double* x) {
+  if (m->std_wells) memcpy(m->wx, x, sizeof(double) * 4 * m->nw);
+}
+
+/* Wellbore storage A_a,w = V_w mix_a of a well state: A [nw][3]. */
+static void well_storage(const ora_model* m, const double* wx, double* A) {
+  for (int w = 0; w < m->nw; ++w) {
+    wellvars W;
+    well_vars(&m->fl, wx + 4 * w, &W);
+    for (int a = 0; a < 3; ++a) A[3 * w + a] = m->well_vol[w] * W.mix[a].v;
+  }
+}
+
+void ora_well_storage_start(ora_model* m) {
+  if (m->std_wells) well_storage(m, m->wx, m->wA0);
+}
+
+/* Well equations at (y, model well state) and their coupling blocks:
+ * component conservation with wellbore storage (eq. conseq-swell),
+ * R_a,w = V_w (mix_a - mix_a^0)/dt + Q_a - sum_j q_a,j, and the control
+ * (eq. well-control-bhp / -rate): p_bhp - target for a BHP producer,
+ * Q_a + target for an injector of component a at the surface rate target.
+ * Rw [nw][4]; B [nc][4][3] = dRw/dx_cell; C [nc][3][4] = d(cell residual
+ * (+q))/dx_w; D [nw][4][4] = dRw/dx_w. */
+int ora_well_system(const ora_model* m, const double* y, double dt, double* Rw, double* B,
+                    double* C, double* D) {
+  if (!m->std_wells) return ORA_EINVAL;
+  memset(B, 0, sizeof(double) * 12 * m->nc);
+  memset(C, 0, sizeof(double) * 12 * m->nc);
+  for (int w = 0; w < m->nw; ++w) {
+    wellvars W;
+    well_vars(&m->fl, m->wx + 4 * w, &W);
+    dual R[4];
+    for (int a = 0; a < 3; ++a) {
+      dual st = dscale(dsub(W.mix[a], dconst(m->wA0[3 * w + a] /
+                                             (m->well_vol[w] > 0.0 ? m->well_vol[w] : 1.0))),
+                       m->well_vol[w] / dt);
+      R[a] = dadd(st, dscale(dmul(W.F[a], W.Qt), 1.0 / kWellG[a]));
+    }
+    for (int q = m->well_beg[w]; q < m->well_beg[w + 1]; ++q) {
+      dual qr[3];
+      std_conn_rate(m, q, y, m->wx, qr);
+      for (int a = 0; a < 3; ++a) {
+        R[a] = dsub(R[a], qr[a]);
+        for (int v = 0; v < 3; ++v) B[12 * q + 3 * a + v] = -qr[a].d[v];
+        for (int k = 0; k < 4; ++k) C[12 * q + 4 * a + k] = qr[a].d[3 + k];
+      }
+    }
+    if (m->well_kind[w] == ORA_WELL_BHP_PROD) {
+      R[3] = dsub(W.pb, dconst(m->well_target[w]));
+    } else {
+      const int ph = m->well_phase[w];
+      R[3] = dadd(dscale(dmul(W.F[ph], W.Qt), 1.0 / kWellG[ph]), dconst(m->well_target[w]));
+    }
+    for (int e = 0; e < 4; ++e) {
+      Rw[4 * w + e] = R[e].v;
+      for (int k = 0; k < 4; ++k) D[16 * w + 4 * e + k] = R[e].d[3 + k];
+    }
+  }
+  return ORA_OK;
+}
+
+/* The Krylov operator: the reservoir matrix, with standard wells their
+ * Schur complement (eq. wellequation), y = A x - sum_w C_w D_w^{-1} B_w x. */
+typedef struct {
+  const ora_model* m;
+  const double* J;
+  const double* B;      /* NULL without standard wells */
+  const double* C;
+  const double* Dinv;   /* [nw][4][4] */
+} oper;
+
+static void op_apply(const oper* op, const double* x, double* y) {
+  const ora_model* m = op->m;
+  ora_spmv(m, op->J, x, y);
+  if (!op->B) return;
+  for (int w = 0; w < m->nw; ++w) {
+    double t[4] = {0, 0, 0, 0}, u[4] = {0, 0, 0, 0};
+    for (int q = m->well_beg[w]; q < m->well_beg[w + 1]; ++q) {
+      const int c = m->conn_cell[q];
+      for (int e = 0; e < 4; ++e)
+        for (int v = 0; v < 3; ++v) t[e] += op->B[12 * q + 3 * e + v] * x[3 * c + v];
+    }
+    for (int e = 0; e < 4; ++e)
+      for (int k = 0; k < 4; ++k) u[e] += op->Dinv[16 * w + 4 * e + k] * t[k];
+    for (int q = m->well_beg[w]; q < m->well_beg[w + 1]; ++q) {
+      const int c = m->conn_cell[q];
+      for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 4; ++k) y[3 * c + a] -= op->C[12 * q + 4 * a + k] * u[k];
+    }
+  }
+}
+
+static int inv4(const double* A, double* X) {
+  for (int k = 0; k < 4; ++k) {
+    double M[16], e[4] = {0, 0, 0, 0};
+    memcpy(M, A, sizeof(M));
+    e[k] = 1.0;
+    if (ora_dense_solve(4, M, e) != ORA_OK) return ORA_ESINGULAR;
+    for (int r = 0; r < 4; ++r) X[4 * r + k] = e[r];
+  }
+  return ORA_OK;
+}
+
+static int bicgstab_op(const oper* op, const double* F, const double* b, double* x, double rtol,
+                       int maxit, double* its_out, double* relres_out);
+static int gmres_op(const oper* op, const double* F, const double* b, double* x, double rtol,
+                    int maxit, int restart, double* its_out, double* relres_out);
+
+int ora_schur_solve(const ora_model* m, const double* J, const double* F, const double* B,
+                    const double* C, const double* D, const double* Rr, const double* Rw,
+                    double* xr, double* xw, double rtol, int maxit, int krylov, int restart,
+                    double* its, double* relres) {
+  const int N = 3 * m->n;
+  double* Dinv = (double*)malloc(sizeof(double) * 16 * (m->nw + 1));
+  double* b = (double*)malloc(sizeof(double) * N);
+  int st = ORA_OK;
+  for (int w = 0; w < m->nw && st == ORA_OK; ++w) st = inv4(D + 16 * w, Dinv + 16 * w);
+  if (st != ORA_OK) goto out;
+  /* b = R_r - sum_w C_w D_w^{-1} R_w */
+  memcpy(b, Rr, sizeof(double) * N);
+  for (int w = 0; w < m->nw; ++w) {
+    double u[4] = {0, 0, 0, 0};
+    for (int e = 0; e < 4; ++e)
+      for (int k = 0; k < 4; ++k) u[e] += Dinv[16 * w + 4 * e + k] * Rw[4 * w + k];
+    for (int q = m->well_beg[w]; q < m->well_beg[w + 1]; ++q) {
+      const int c = m->conn_cell[q];
+      for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 4; ++k) b[3 * c + a] -= C[12 * q + 4 * a + k] * u[k];
+    }
+  }
+  {
+    oper op = {m, J, B, C, Dinv};
+    st = krylov == 1 ? gmres_op(&op, F, b, xr, rtol, maxit, restart, its, relres)
+                     : bicgstab_op(&op, F, b, xr, rtol, maxit, its, relres);
+  }
+  /* x_w = D_w^{-1} (R_w - B_w x_r) */
+  for (int w = 0; w < m->nw; ++w) {
+    double t[4];
+    for (int e = 0; e < 4; ++e) t[e] = Rw[4 * w + e];
+    for (int q = m->well_beg[w]; q < m->well_beg[w + 1]; ++q) {
+      const int c = m->conn_cell[q];
+      for (int e = 0; e < 4; ++e)
+        for (int v = 0; v < 3; ++v) t[e] -= B[12 * q + 3 * e + v] * xr[3 * c + v];
+    }
+    for (int e = 0; e < 4; ++e) {
+      xw[4 * w + e] = 0.0;
+      for (int k = 0; k < 4; ++k) xw[4 * w + e] += Dinv[16 * w + 4 * e + k] * t[k];
+    }
+  }
+out:
+  free(Dinv);
+  free(b);
+  return st;
+}
+
 /* ----------------------------------------------- BiCGStab (sec. 2.3.1)
  * van der Vorst's stabilised BiCG with right preconditioning M = LU,
  * x0 = 0, stopping on the 2-norm of the residual relative to ||b||. */
@@ -730,6 +975,13 @@ static double dot(int n, const double* a, const double* b) {
 
 int ora_bicgstab(const ora_model* m, const double* J, const double* F, const double* b, double* x,
                  double rtol, int maxit, double* its_out, double* relres_out) {
+  oper op = {m, J, NULL, NULL, NULL};
+  return bicgstab_op(&op, F, b, x, rtol, maxit, its_out, relres_out);
+}
+
+static int bicgstab_op(const oper* op, const double* F, const double* b, double* x, double rtol,
+                       int maxit, double* its_out, double* relres_out) {
+  const ora_model* m = op->m;
   const int N = 3 * m->n;
   double* r = (double*)malloc(sizeof(double) * N);
   double* rh = (double*)malloc(sizeof(double) * N);
@@ -751,7 +1003,7 @@ int ora_bicgstab(const ora_model* m, const double* J, const double* F, const dou
     double beta = (rho / rho0) * (alpha / omega);
     for (int k = 0; k < N; ++k) p[k] = r[k] + beta * (p[k] - omega * v[k]);
     ora_ilu0_apply(m, F, p, ph);
-    ora_spmv(m, J, ph, v);
+    op_apply(op, ph, v);
     double rv = dot(N, rh, v);
     if (rv == 0.0) { status = ORA_EBREAKDOWN; break; }
     alpha = rho / rv;
@@ -763,7 +1015,7 @@ int ora_bicgstab(const ora_model* m, const double* J, const double* F, const dou
       break;
     }
     ora_ilu0_apply(m, F, s, sh);
-    ora_spmv(m, J, sh, t);
+    op_apply(op, sh, t);
     double tt = dot(N, t, t);
     if (tt == 0.0) { status = ORA_EBREAKDOWN; break; }
     omega = dot(N, t, s) / tt;
@@ -794,6 +1046,13 @@ done:
  * at the iteration cap, or on an exact (happy) breakdown h_{j+1,j} = 0. */
 int ora_gmres(const ora_model* m, const double* J, const double* F, const double* b, double* x,
               double rtol, int maxit, int restart, double* its_out, double* relres_out) {
+  oper op = {m, J, NULL, NULL, NULL};
+  return gmres_op(&op, F, b, x, rtol, maxit, restart, its_out, relres_out);
+}
+
+static int gmres_op(const oper* op, const double* F, const double* b, double* x, double rtol,
+                    int maxit, int restart, double* its_out, double* relres_out) {
+  const ora_model* m = op->m;
   const int N = 3 * m->n;
   if (restart < 1) return ORA_EINVAL;
   double* V = (double*)malloc(sizeof(double) * (size_t)N * (restart + 1));
@@ -812,7 +1071,7 @@ int ora_gmres(const ora_model* m, const double* J, const double* F, const double
 #define Hm(i, j) H[(size_t)(i) * restart + (j)]
   while (its < maxit) {
     /* residual of the current iterate starts the space */
-    ora_spmv(m, J, x, w);
+    op_apply(op, x, w);
     for (int k = 0; k < N; ++k) V[k] = b[k] - w[k];
     const double beta = sqrt(dot(N, V, V));
     relres = beta / bnorm;
@@ -824,7 +1083,7 @@ int ora_gmres(const ora_model* m, const double* J, const double* F, const double
     for (int j = 0; j < restart && its < maxit; ++j) {
       double* vj = V + (size_t)j * N;
       ora_ilu0_apply(m, F, vj, z);
-      ora_spmv(m, J, z, w);
+      op_apply(op, z, w);
       for (int i = 0; i <= j; ++i) {
         const double* vi = V + (size_t)i * N;
         const double h = dot(N, w, vi);
@@ -915,17 +1174,37 @@ int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double 
   double* F = (double*)malloc(sizeof(double) * 9 * m->nnzb);
   double* b = (double*)malloc(sizeof(double) * N);
   double* dx = (double*)malloc(sizeof(double) * N);
+  const int nw = m->std_wells ? m->nw : 0, nc = m->std_wells ? m->nc : 0;
+  double* Rw = (double*)malloc(sizeof(double) * (4 * nw + 1));
+  double* bw = (double*)malloc(sizeof(double) * (4 * nw + 1));
+  double* dxw = (double*)malloc(sizeof(double) * (4 * nw + 1));
+  double* Bw = (double*)malloc(sizeof(double) * (12 * nc + 1));
+  double* Cw = (double*)malloc(sizeof(double) * (12 * nc + 1));
+  double* Dw = (double*)malloc(sizeof(double) * (16 * nw + 1));
   memset(rep, 0, sizeof(*rep));
   ora_accumulation(m, y_prev, acc0);
+  if (m->std_wells) well_storage(m, m->wx, m->wA0);   /* the well state at entry is the old one */
   int status = ORA_ENOTCONV;
   for (int it = 0;; ++it) {
     double t0 = now_s();
     int st = ora_assemble(m, y, acc0, dt, R, J);
+    if (st == ORA_OK && m->std_wells) st = ora_well_system(m, y, dt, Rw, Bw, Cw, Dw);
     rep->t_assemble += now_s() - t0;
     if (st != ORA_OK) { status = st; break; }
     ora_norms(m, y, R, dt, rep->cnv, rep->mb);
     double cmax = fmax(rep->cnv[0], fmax(rep->cnv[1], rep->cnv[2]));
     double mmax = fmax(rep->mb[0], fmax(rep->mb[1], rep->mb[2]));
+    /* wells: component residuals in saturation units of the perforated pore
+     * volume, the control relative to its target */
+    for (int w = 0; w < nw; ++w) {
+      double vref = 0.0;
+      for (int q = m->well_beg[w]; q < m->well_beg[w + 1]; ++q) vref += m->pv[m->conn_cell[q]];
+      for (int a = 0; a < 3; ++a) {
+        const double bw_a = exp(m->fl.c[a] * (m->wx[4 * w + 3] - m->fl.p_ref));
+        cmax = fmax(cmax, dt * fabs(Rw[4 * w + a]) / (bw_a * vref));
+      }
+      cmax = fmax(cmax, fabs(Rw[4 * w + 3]) / fabs(m->well_target[w]));
+    }
     if (cmax <= o->tol_cnv && mmax <= o->tol_mb) { status = ORA_OK; break; }
     if (it >= o->max_newton) { status = ORA_ENOTCONV; break; }
     t0 = now_s();
@@ -933,11 +1212,16 @@ int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double 
     rep->t_factor += now_s() - t0;
     if (st != ORA_OK) { status = st; break; }
     for (int k = 0; k < N; ++k) b[k] = -R[k];
+    for (int k = 0; k < 4 * nw; ++k) bw[k] = -Rw[k];
     double its = 0.0, rr = 0.0;
     t0 = now_s();
-    st = o->krylov == 1
-             ? ora_gmres(m, J, F, b, dx, o->lin_rtol, o->lin_maxit, o->restart, &its, &rr)
-             : ora_bicgstab(m, J, F, b, dx, o->lin_rtol, o->lin_maxit, &its, &rr);
+    if (m->std_wells)
+      st = ora_schur_solve(m, J, F, Bw, Cw, Dw, b, bw, dx, dxw, o->lin_rtol, o->lin_maxit,
+                           o->krylov, o->restart, &its, &rr);
+    else
+      st = o->krylov == 1
+               ? ora_gmres(m, J, F, b, dx, o->lin_rtol, o->lin_maxit, o->restart, &its, &rr)
+               : ora_bicgstab(m, J, F, b, dx, o->lin_rtol, o->lin_maxit, &its, &rr);
     rep->t_krylov += now_s() - t0;
     rep->lin_its += its;
     if (st != ORA_OK) { status = st; break; }
@@ -963,6 +1247,29 @@ int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double 
       y[3 * c + 2] += dx3;
       if (m->fl.live) switch_variable(&m->fl, y + 3 * c, &m->mean[c]);
     }
+    /* well unknowns: |dp_bhp| <= dp_max_rel p_bhp, the fraction pair scaled
+     * to at most ds_max, fractions kept in [0, 1] with F_w + F_g <= 1 */
+    for (int w = 0; w < nw; ++w) {
+      double* x = m->wx + 4 * w;
+      double dpb = dxw[4 * w + 3], lim = o->dp_max_rel * fabs(x[3]);
+      if (dpb > lim) dpb = lim;
+      if (dpb < -lim) dpb = -lim;
+      double dfw = dxw[4 * w + 1], dfg = dxw[4 * w + 2];
+      double mx = fmax(fabs(dfw), fabs(dfg));
+      if (mx > o->ds_max) {
+        dfw *= o->ds_max / mx;
+        dfg *= o->ds_max / mx;
+      }
+      x[0] += dxw[4 * w];
+      x[1] = fmin(fmax(x[1] + dfw, 0.0), 1.0);
+      x[2] = fmin(fmax(x[2] + dfg, 0.0), 1.0);
+      if (x[1] + x[2] > 1.0) {
+        const double sc = 1.0 / (x[1] + x[2]);
+        x[1] *= sc;
+        x[2] *= sc;
+      }
+      x[3] += dpb;
+    }
     rep->t_update += now_s() - t0;
     rep->newton_its++;
     rep->cell_newton_its += (double)n;
@@ -970,25 +1277,43 @@ int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double 
   }
   rep->status = status;
   free(acc0); free(R); free(J); free(F); free(b); free(dx);
+  free(Rw); free(bw); free(dxw); free(Bw); free(Cw); free(Dw);
   return status;
 }
 
-/* y_old with its meaning mean_old; y_new with the model's current one. */
+/* y_old with its meaning mean_old (and well state wx_old); y_new with the
+ * model's current ones.  With standard wells the surface volume in place
+ * includes the wellbore and the outflow is the wells' surface rates. */
 static void mass_error(const ora_model* m, const double* y_old, const unsigned char* mean_old,
-                       const double* y_new, double dt, double err[3]) {
+                       const double* wx_old, const double* y_new, double dt, double err[3]) {
   const int n = m->n;
   double* a0 = (double*)malloc(sizeof(double) * 3 * n);
   double* a1 = (double*)malloc(sizeof(double) * 3 * n);
   double* q = (double*)malloc(sizeof(double) * 3 * n);
+  double* w0 = (double*)calloc(3 * (size_t)m->nw + 3, sizeof(double));
+  double* w1 = (double*)calloc(3 * (size_t)m->nw + 3, sizeof(double));
   accumulation_of(m, mean_old, y_old, a0);
   ora_accumulation(m, y_new, a1);
   ora_well_rates(m, y_new, q);
+  if (m->std_wells) {
+    well_storage(m, wx_old, w0);
+    well_storage(m, m->wx, w1);
+  }
   for (int a = 0; a < 3; ++a) {
     double M0 = 0.0, M1 = 0.0, Q = 0.0, bsum = 0.0, pvs = 0.0;
+    if (m->std_wells) {
+      for (int w = 0; w < m->nw; ++w) {
+        M0 += w0[3 * w + a];
+        M1 += w1[3 * w + a];
+        const double* x = m->wx + 4 * w;
+        const double Fa = a == 0 ? x[1] : (a == 2 ? x[2] : 1.0 - x[1] - x[2]);
+        Q += Fa * x[0] / kWellG[a];   /* Q_a = F_a Q_t / g_a */
+      }
+    }
     for (int c = 0; c < n; ++c) {
       M0 += m->pv[c] * a0[3 * c + a];
       M1 += m->pv[c] * a1[3 * c + a];
-      Q += q[3 * c + a];
+      if (!m->std_wells) Q += q[3 * c + a];
       props P;
       cell_props(&m->fl, y_new + 3 * c, 0, m->mean[c], &P);
       bsum += P.b[a].v;
@@ -996,7 +1321,7 @@ static void mass_error(const ora_model* m, const double* y_old, const unsigned c
     }
     err[a] = fabs(M1 - M0 + dt * Q) / ((bsum / n) * pvs);
   }
-  free(a0); free(a1); free(q);
+  free(a0); free(a1); free(q); free(w0); free(w1);
 }
 
 int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts* o,
@@ -1004,8 +1329,11 @@ int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts*
   const int N = 3 * m->n;
   double* yn = (double*)malloc(sizeof(double) * N);
   unsigned char* mn = (unsigned char*)malloc((size_t)m->n + 1);
+  const size_t wbytes = m->std_wells ? sizeof(double) * 4 * m->nw : 0;
+  double* wn = (double*)malloc(wbytes + sizeof(double));
   memcpy(yn, y, sizeof(double) * N);
   memcpy(mn, m->mean, (size_t)m->n);
+  if (wbytes) memcpy(wn, m->wx, wbytes);
   memset(rep, 0, sizeof(*rep));
   double t = 0.0, dt_try = dt_report;
   int status = ORA_OK;
@@ -1022,7 +1350,7 @@ int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts*
     rep->t_update += r1.t_update;
     if (st == ORA_OK) {
       double e[3];
-      mass_error(m, yn, mn, y, dt, e);
+      mass_error(m, yn, mn, wn, y, dt, e);
       for (int a = 0; a < 3; ++a) {
         if (e[a] > rep->mass_err[a]) rep->mass_err[a] = e[a];
         rep->cnv[a] = r1.cnv[a];
@@ -1030,11 +1358,13 @@ int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts*
       }
       memcpy(yn, y, sizeof(double) * N);
       memcpy(mn, m->mean, (size_t)m->n);
+      if (wbytes) memcpy(wn, m->wx, wbytes);
       t += dt;
       rep->substeps++;
     } else {
       memcpy(y, yn, sizeof(double) * N);
       memcpy(m->mean, mn, (size_t)m->n);
+      if (wbytes) memcpy(m->wx, wn, wbytes);
       dt_try = 0.5 * dt;
       rep->cuts++;
       if (rep->cuts > o->max_cuts) { status = st; break; }
@@ -1043,5 +1373,6 @@ int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts*
   rep->status = status;
   free(yn);
   free(mn);
+  free(wn);
   return status;
 }

@@ -163,6 +163,37 @@ int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double 
 /* Advance y over one report step of length dt with halving on failure. */
 int ora_advance(const ora_model* m, double* y, double dt, const ora_opts* o, ora_report* rep);
 
+/* Standard well model (sec. 2.2.1): every well of the model gets the
+ * unknowns x_w = (Q_t, F_w, F_g, p_bhp) (weighted total surface rate,
+ * production positive; weighted water and gas fractions of the wellbore
+ * fluid; bottom-hole pressure) with weights g = (1, 1, 0.01), component
+ * conservation with wellbore storage (volume well_vol [nw]) and its control
+ * (BHP producer: p_bhp = target; rate injector of component a:
+ * Q_a = -target); connection rates by eq. wellinflow with h_w,j = 0.  x0:
+ * [nw][4] initial well state.  The well state is held by the model like the
+ * variable meaning; ora_newton_step / ora_advance solve the coupled system
+ * by the Schur complement (eq. wellequation). */
+int ora_set_standard_wells(ora_model* m, const double* well_vol, const double* x0);
+void ora_get_well_state(const ora_model* m, double* x);
+void ora_set_well_state(ora_model* m, const double* x);
+/* Record the wellbore storage of the current well state as the storage at
+ * the start of a step (ora_newton_step does it at entry). */
+void ora_well_storage_start(ora_model* m);
+/* Well equations at y and the model's well state: Rw [nw][4] (water, oil,
+ * gas conservation, control), B [nc][4][3] = dRw/d(cell variables of the
+ * connection), C [nc][3][4] = d(cell residual)/dx_w, D [nw][4][4] =
+ * dRw/dx_w.  ORA_EINVAL without standard wells. */
+int ora_well_system(const ora_model* m, const double* y, double dt, double* Rw, double* B,
+                    double* C, double* D);
+/* Solve [[A C] [B D]] [x_r; x_w] = [Rr; Rw] by the Schur complement: the
+ * Krylov method (0 BiCGStab, 1 GMRes(restart)) on (A - sum C D^-1 B) x_r =
+ * Rr - sum C D^-1 Rw with the ILU(0) factors F of A as preconditioner, then
+ * x_w = D^-1 (Rw - B x_r). */
+int ora_schur_solve(const ora_model* m, const double* J, const double* F, const double* B,
+                    const double* C, const double* D, const double* Rr, const double* Rw,
+                    double* xr, double* xw, double rtol, int maxit, int krylov, int restart,
+                    double* its, double* relres);
+
 /* Dense LU with partial pivoting: solves A x = b in place (A [n][n] row-major
  * is overwritten).  Returns ORA_ESINGULAR on a zero pivot. */
 int ora_dense_solve(int n, double* A, double* b);

@@ -85,6 +85,7 @@ class Case:
     sw_init: float = 0.12
     sg_init: float = 0.0
     r_init: Optional[float] = None   # live oil: initial dissolved ratio (x = r_go, no free gas)
+    standard_wells: bool = False     # wells with their own unknowns (Q_t, F_w, F_g, p_bhp)
     report_dt: List[float] = dataclasses.field(default_factory=list)   # s
     tol_cnv: float = 1e-8
     tol_mb: float = 1e-11
@@ -107,6 +108,22 @@ class Case:
         y[:, 1] = self.sw_init
         y[:, 2] = self.sg_init if self.r_init is None else self.r_init
         return y
+
+    def standard_well_init(self):
+        """Wellbore volumes (pi r_w^2 times the perforated thickness) and the
+        initial well states [nw][4] = (Q_t, F_w, F_g, p_bhp): no flow (Q_t = 0);
+        a producer's wellbore holds oil (F_w = F_g = 0) at its target BHP; an
+        injector's holds its injected component at the initial pressure."""
+        vol = np.array([math.pi * w.rw ** 2 * sum(float(self.dz[k]) for (_, _, k) in w.cells)
+                        for w in self.wells])
+        x0 = np.zeros((len(self.wells), 4))
+        for n, w in enumerate(self.wells):
+            if w.kind == WELL_BHP_PROD:
+                x0[n] = (0.0, 0.0, 0.0, w.target)
+            else:
+                x0[n] = (0.0, 1.0 if w.phase == W else 0.0, 1.0 if w.phase == GAS else 0.0,
+                         self.p_init)
+        return vol, x0
 
     def initial_meaning(self) -> np.ndarray:
         """[n_active] meaning of the third variable: 0 s_g, 1 r_go (the

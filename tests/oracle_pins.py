@@ -904,6 +904,164 @@ def pin_live_depletion_1d(lib_path=None):
     assert (m.run_meanings[-1] == 0).sum() >= 2
 
 
+# ------------------------------------------------------- standard wells
+# Standard well model (sec. 2.2.1): per well x_w = (Q_t, F_w, F_g, p_bhp),
+# component conservation with wellbore storage and a control equation,
+# eliminated from the linear system by the Schur complement (eq.
+# wellequation).
+def _std_case(vol_scale=1.0):
+    wells = [Well("I", cases.WELL_RATE_INJ, [(0, 0, k) for k in range(2)], 400 * STB / DAY,
+                  phase=cases.W),
+             Well("P", cases.WELL_BHP_PROD, [(2, 2, 0), (2, 2, 1)], 3000 * PSI)]
+    c = cases.box_case(3, 3, 2, seed=7, wells=wells, dz=[6.0, 9.0])
+    c.standard_wells = True
+    return c
+
+
+def _std_state(c, m, seed):
+    """A random reservoir state and a well state with both wells flowing."""
+    y = cases.random_state(c, seed=seed)
+    rng = np.random.default_rng(seed)
+    x = m.well_state().copy()
+    x[0] = (-2e-4 * rng.uniform(0.5, 1.5), 1.0 - 0.05 * rng.uniform(), 0.01 * rng.uniform(),
+            y[:, 0].mean() + 300 * PSI)
+    x[1] = (3e-4 * rng.uniform(0.5, 1.5), 0.2 * rng.uniform(), 0.05 * rng.uniform(),
+            y[:, 0].mean() - 300 * PSI)
+    return y, x
+
+
+def _full_system(m, J, B, C, D):
+    """The coupled matrix [[A C] [B D]] (cells first, then 4 per well)."""
+    A = _dense(m, J)
+    n3, nw = 3 * m.n, m.nw
+    M = np.zeros((n3 + 4 * nw, n3 + 4 * nw))
+    M[:n3, :n3] = A
+    cell, _, well = m.conns()
+    for q in range(m.nc):
+        c, w = cell[q], well[q]
+        M[3 * c:3 * c + 3, n3 + 4 * w:n3 + 4 * w + 4] += C[q]
+        M[n3 + 4 * w:n3 + 4 * w + 4, 3 * c:3 * c + 3] += B[q]
+    for w in range(nw):
+        M[n3 + 4 * w:n3 + 4 * w + 4, n3 + 4 * w:n3 + 4 * w + 4] = D[w]
+    return M
+
+
+def pin_std_schur_dense(lib_path=None):
+    """The Schur-complement solve (eq. wellequation: Krylov on A - C D^-1 B,
+    then x_w = D^-1 (R_w - B x_r)) equals numpy's dense solve of the whole
+    coupled system, for BiCGStab and GMRes."""
+    c = _std_case()
+    m = _model(c, lib_path)
+    y, x = _std_state(c, m, seed=3)
+    m.set_well_state(x)
+    m.well_storage_start()
+    acc0 = m.accumulation(cases.random_state(c, seed=4))
+    st, R, J = m.assemble(y, acc0, 2 * DAY)
+    st, Rw, B, C, D = m.well_system(y, 2 * DAY)
+    assert st == 0
+    st, F = m.ilu0(J)
+    M = _full_system(m, J, B, C, D)
+    rhs = np.concatenate([R.ravel(), Rw.ravel()])
+    xd = np.linalg.solve(M, rhs)
+    for krylov in (0, 1):
+        st, xr, xw, its = m.schur_solve(J, F, B, C, D, R, Rw, rtol=1e-13, maxit=500,
+                                        krylov=krylov, restart=10)
+        assert st == 0
+        got = np.concatenate([xr.ravel(), xw.ravel()])
+        scale = np.abs(xd).max()
+        assert np.abs(got[:3 * m.n] - xd[:3 * m.n]).max() <= 1e-8 * np.abs(xd[:3 * m.n]).max()
+        for k in range(4 * m.nw):   # each well unknown against its own scale
+            ref = xd[3 * m.n + k]
+            assert abs(got[3 * m.n + k] - ref) <= 1e-8 * (abs(ref) + 1e-12 * scale), (k, got[3 * m.n + k], ref)
+
+
+def pin_std_jacobian_fd(lib_path=None):
+    """The coupling blocks against central finite differences: the cell
+    residual's derivatives w.r.t. the well unknowns (C), the well residual's
+    w.r.t. the cell variables (B) and the well unknowns (D), and the cell
+    block diagonal with the connection terms."""
+    c = _std_case()
+    m = _model(c, lib_path)
+    y, x = _std_state(c, m, seed=5)
+    m.set_well_state(x)
+    m.well_storage_start()
+    acc0 = m.accumulation(cases.random_state(c, seed=6))
+    dt = 2 * DAY
+    st, R, J = m.assemble(y, acc0, dt)
+    st, Rw, B, C, D = m.well_system(y, dt)
+    M = _full_system(m, J, B, C, D)
+
+    def resid(yv, xv):
+        m.set_well_state(xv)
+        r = m.assemble(yv, acc0, dt, jacobian=False)[1].ravel()
+        rw = m.well_system(yv, dt)[1].ravel()
+        m.set_well_state(x)
+        return np.concatenate([r, rw])
+
+    n3 = 3 * m.n
+    FD = np.zeros_like(M)
+    for k in range(n3 + 4 * m.nw):
+        yp, ym, xp, xm = y.copy(), y.copy(), x.copy(), x.copy()
+        if k < n3:
+            ci, v = divmod(k, 3)
+            h = 1e-7 * (abs(y[ci, 0]) + 1e5) if v == 0 else 1e-7
+            yp[ci, v] += h
+            ym[ci, v] -= h
+        else:   # well unknowns: larger steps (their columns are small next to R)
+            w, e = divmod(k - n3, 4)
+            h = 1e-5 * (abs(x[w, e]) + (1e5 if e == 3 else 1e-6))
+            xp[w, e] += h
+            xm[w, e] -= h
+        FD[:, k] = (resid(yp, xp) - resid(ym, xm)) / (2 * h)
+    colscale = np.abs(M).max(axis=0) + 1e-300
+    err = np.abs(M - FD) / colscale[None, :]
+    assert err[:, :n3].max() <= 1e-6, err[:, :n3].max()
+    assert err[:, n3:].max() <= 1e-4, err[:, n3:].max()
+
+
+def pin_std_simplified_limit(lib_path=None):
+    """Single-connection wells with a vanishing wellbore volume reduce to
+    the simplified wells: a BHP producer's connection then carries exactly
+    b lambda WI (p - p_bhp)^+, a rate injector's exactly its target; the
+    converged states of a 3-step run agree to the Newton tolerance.  (With
+    no volume at all the wellbore composition of a well at rest is
+    undetermined, one reason for the storage term.)"""
+    base = cases.config1()
+    ref = _model(base, lib_path)
+    states_ref, _ = ref.run(n_steps=3)
+    c = cases.config1()
+    c.standard_wells = True
+    m = _model(c, lib_path)
+    vol, x0 = c.standard_well_init()
+    st = m.L.ora_set_standard_wells(m.h, oracle._d(vol * 1e-9), oracle._d(x0))
+    assert st == 0
+    states, _ = m.run(n_steps=3)
+    states_std = states
+    for a, b in zip(states_std, states_ref):
+        assert np.abs(a[:, 0] - b[:, 0]).max() <= 1e-7 * np.abs(b[:, 0]).max()
+        assert np.abs(a[:, 1:] - b[:, 1:]).max() <= 1e-7
+
+
+def pin_std_controls_and_storage(lib_path=None):
+    """Over a run with multi-connection wells and a large wellbore: the rate
+    injector's water rate Q_w = F_w Q_t (g_w = 1) equals its target, its
+    wellbore holds water only (F_w = 1, F_g = 0), the producer sits at its
+    BHP, and every step conserves the surface volume of each component
+    counting the wellbore (storage V_w mix_a) and the surface rates Q_a."""
+    c = _std_case()
+    m = _model(c, lib_path)
+    vol, x0 = c.standard_well_init()
+    st = m.L.ora_set_standard_wells(m.h, oracle._d(vol * 2000.0), oracle._d(x0))
+    assert st == 0
+    c.report_dt = [2 * DAY] * 4
+    states, reps = m.run()
+    for r, x in zip(reps, m.run_well_states):
+        assert max(r["mass_err"]) <= 1e-10, r["mass_err"]
+        assert abs(x[0, 1] * x[0, 0] + 400 * STB / DAY) <= 1e-9 * 400 * STB / DAY
+        assert x[0, 1] == 1.0 and x[0, 2] == 0.0
+        assert abs(x[1, 3] - 3000 * PSI) <= 1e-6 * 3000 * PSI
+
+
 ALL_PINS = [
     pin_series_transmissibility, pin_depth_pore_volume, pin_peaceman_worked_value,
     pin_compressibility, pin_darcy_flux_upwind, pin_hydrostatic_column, pin_pressure_block,
@@ -914,4 +1072,6 @@ ALL_PINS = [
     pin_mass_balance_run, pin_mirror_symmetry, pin_live_dead_limit, pin_live_switch_continuity,
     pin_live_jacobian_fd, pin_live_conservation, pin_live_closed_cell,
     pin_live_dissolved_moves_with_oil, pin_live_hydrostatic_column, pin_live_depletion_1d,
+    pin_std_schur_dense, pin_std_jacobian_fd, pin_std_simplified_limit,
+    pin_std_controls_and_storage,
 ]

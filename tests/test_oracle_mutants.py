@@ -78,6 +78,26 @@ MUTANTS = [
     ("live_gas_never_appears", "if (yc[2] > rs * (1.0 + f->eps_switch)) {", "if (0) {"),
     ("live_free_gas_in_undersaturated_cell", "dual sg = (f->live && mean == 1) ? dconst(0.0) : x;",
      "dual sg = x;"),
+    # standard wells and the Schur complement
+    ("std_schur_operator_sign", "y[3 * c + a] -= op->C[12 * q + 4 * a + k] * u[k];",
+     "y[3 * c + a] += op->C[12 * q + 4 * a + k] * u[k];"),
+    ("std_schur_rhs_missing", "b[3 * c + a] -= C[12 * q + 4 * a + k] * u[k];",
+     "b[3 * c + a] -= 0.0 * C[12 * q + 4 * a + k] * u[k];"),
+    ("std_well_recovery_sign", "t[e] -= B[12 * q + 3 * e + v] * xr[3 * c + v];",
+     "t[e] += B[12 * q + 3 * e + v] * xr[3 * c + v];"),
+    ("std_injection_uses_cell_phases",
+     "    for (int a = 0; a < 3; ++a) out[a] = dmul(dmul(dscale(lt, wi), dp), W.mix[a]);",
+     "    for (int a = 0; a < 3; ++a) out[a] = dmul(dscale(dmul(P.b[a], P.lam[a]), wi), dp);"),
+    ("std_storage_dropped", "R[a] = dadd(st, dscale(dmul(W.F[a], W.Qt), 1.0 / kWellG[a]));",
+     "R[a] = dadd(dscale(st, 0.0), dscale(dmul(W.F[a], W.Qt), 1.0 / kWellG[a]));"),
+    ("std_B_sign", "B[12 * q + 3 * a + v] = -qr[a].d[v];", "B[12 * q + 3 * a + v] = qr[a].d[v];"),
+    ("std_C_wrong_slots", "C[12 * q + 4 * a + k] = qr[a].d[3 + k];",
+     "C[12 * q + 4 * a + k] = qr[a].d[k];"),
+    ("std_bhp_control_sign", "R[3] = dsub(W.pb, dconst(m->well_target[w]));",
+     "R[3] = dadd(W.pb, dconst(m->well_target[w]));"),
+    ("std_rate_control_sign",
+     "R[3] = dadd(dscale(dmul(W.F[ph], W.Qt), 1.0 / kWellG[ph]), dconst(m->well_target[w]));",
+     "R[3] = dsub(dscale(dmul(W.F[ph], W.Qt), 1.0 / kWellG[ph]), dconst(m->well_target[w]));"),
 ]
 
 
