@@ -250,6 +250,33 @@ typedef struct opm_problem {
    * opm_newton_step / opm_advance update it in place.  NULL for dead oil
    * (every cell 0); required (non-NULL) for live oil. */
   uint8_t* meaning;
+  /* Standard well model (sec. 2.2.1), enabled by n_wells > 0: each well has
+   * the unknowns x_w = (Q_t, F_w, F_g, p_bhp) -- weighted total surface
+   * rate (production positive), weighted water and gas fractions of the
+   * wellbore fluid (weights g = (1, 1, 0.01), Q_a = F_a Q_t / g_a,
+   * F_o = 1 - F_w - F_g) and bottom-hole pressure -- with component
+   * conservation including wellbore storage V_w mix_a (eq. conseq-swell;
+   * mix_a = (F_a / g_a) / sum_b F_b / (g_b b_b(p_bhp))) and its control
+   * (eq. well-control-bhp: p_bhp = target; eq. well-control-rate: Q_a =
+   * -target for an injector of component a).  A producing connection
+   * carries the cell's phases, q_a = WI b_a lambda_a (p - p_bhp) (plus
+   * r b_o lambda_o for gas with live oil), an injecting one the wellbore
+   * fluid at the cell's total mobility, q_a = WI lambda_t (p - p_bhp) mix_a
+   * (eq. wellinflow, h_w,j = 0).  The Newton step eliminates the well
+   * unknowns by the Schur complement (eq. wellequation).  With n_wells = 0
+   * the wells are the fixed sources / BHP sinks described by conn_kind.
+   * Connections are numbered well by well. */
+  int32_t n_wells;
+  int32_t pad_w;
+  const int32_t* well_conn_ptr; /* [n_wells+1] connections of each well      */
+  const int32_t* conn_cell;     /* [n_conns] cell of each connection          */
+  const int32_t* conn_well;     /* [n_conns] well of each connection          */
+  const int32_t* well_kind;     /* [n_wells] OPM_WELL_*                       */
+  const int32_t* well_phase;    /* [n_wells] controlled component (injectors) */
+  const double* well_target;    /* [n_wells] BHP [Pa] or surface rate [m3/s]  */
+  const double* well_vol;       /* [n_wells] wellbore volume V_w [m3]         */
+  double* well_state;           /* [n_wells][4] device, in/out: the state of
+                                   the well unknowns that goes with y         */
 } opm_problem;
 
 /* Library set-up: checks that the current device is a gfx950 (MI355X) and
@@ -378,6 +405,24 @@ typedef struct opm_newton_report {
   double t_assemble, t_factor, t_krylov, t_update;   /* s, HIP events     */
 } opm_newton_report;
 
+/* Size in bytes of the device workspace of opm_assemble_wells (0 without
+ * standard wells). */
+size_t opm_wells_bytes(const opm_problem* pb);
+
+/* The coupled linearization with standard wells (sec. 2.2.1, eq.
+ * wellequation): the reservoir residual R [n][3] and Jacobian J
+ * [nnzb][3][3] as opm_assemble (the connection terms now from the well
+ * unknowns in pb->well_state), the well residuals Rw [n_wells][4] (water,
+ * oil, gas conservation with wellbore storage relative to the well state
+ * well_state0 at the start of the step, then the control), and the coupling
+ * blocks B [n_conns][4][3] = dRw/d(cell variables of the connection), C
+ * [n_conns][3][4] = d(cell residual)/d(well unknowns), D [n_wells][4][4] =
+ * dRw/d(well unknowns).  All device; work: opm_wells_bytes.  Synchronises;
+ * OPM_ESINGULAR when a D is singular, OPM_EINVAL without standard wells. */
+int opm_assemble_wells(const opm_problem* pb, const double* y, const double* acc0,
+                       const double* well_state0, double dt, double* R, double* J, double* Rw,
+                       double* B, double* C, double* D, void* work, void* stream);
+
 /* Size in bytes of the Newton workspace (device) for a precision, with
  * BiCGStab as the linear solver. */
 size_t opm_newton_bytes(const opm_problem* pb, int precision);
@@ -398,7 +443,16 @@ size_t opm_newton_work_bytes(const opm_problem* pb, const opm_newton_opts* opts)
  * opm_newton_bytes.  report: HOST; the call synchronises the stream once per
  * Newton iteration (convergence test) and a few times per linear solve.
  * With opts->krylov = OPM_KRYLOV_GMRES, work must hold
- * opm_newton_work_bytes. */
+ * opm_newton_work_bytes.  With standard wells (pb->n_wells > 0) each
+ * iteration also assembles the well equations, solves the reservoir system
+ * with BiCGStab on the Schur complement (A - sum C D^-1 B) (the ILU(0) of A
+ * as preconditioner; GMRes is refused with OPM_EINVAL), recovers the well
+ * update and updates pb->well_state (|dp_bhp| <= dp_max_rel p_bhp, the
+ * fraction pair scaled to ds_max and kept in [0, 1]); convergence also
+ * requires every well's component residuals (dt |R_a,w| / (b_a(p_bhp)
+ * PV_perforated)) and its control residual relative to its target to be
+ * below tol_cnv.  pb->well_state at entry is the state at the start of the
+ * step (its wellbore storage). */
 int opm_newton_step(const opm_problem* pb, double* y, const double* y_prev, double dt,
                     const opm_newton_opts* opts, void* work, opm_newton_report* report,
                     void* stream);
@@ -407,8 +461,9 @@ int opm_newton_step(const opm_problem* pb, double* y, const double* y_prev, doub
  * halving on failure (sec. 2.3 time-step cutting), at most max_cuts halvings;
  * after a cut the shorter substep length is kept for the rest of the report
  * step.  y_save: device [n][3] scratch for the last accepted state; with
- * live oil the variable meanings (pb->meaning) are saved and restored with
- * it, in the Newton workspace. */
+ * live oil the variable meanings (pb->meaning), with standard wells the well
+ * state (pb->well_state), are saved and restored with it, in the Newton
+ * workspace. */
 int opm_advance(const opm_problem* pb, double* y, double dt, const opm_newton_opts* opts,
                 void* work, double* y_save, opm_newton_report* report, void* stream);
 

@@ -92,8 +92,10 @@ __global__ __launch_bounds__(kBlock) void k_accumulation(int n, opm_fluid f, con
 
 }  // namespace
 
+// Cw (standard wells, with J): [n_conns][3][4] derivatives of the cell
+// residuals w.r.t. the well unknowns.
 int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, double dt,
-                    double* R, double* J, double* norms, hipStream_t s) {
+                    double* R, double* J, double* norms, hipStream_t s, double* Cw) {
   const int nblk = blocks_for(pb->n_cells, kBlock);
   AsmArgs a;
   a.n = pb->n_cells;
@@ -115,6 +117,10 @@ int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, 
   a.conn_bhp = pb->conn_bhp;
   a.fluid = pb->fluid;
   a.meaning = pb->meaning;
+  a.n_wells = pb->n_wells;
+  a.conn_well = pb->conn_well;
+  a.well_state = pb->well_state;
+  a.Cw = Cw;
   a.R = R;
   a.J = J;
   a.partials = norms ? norms + 8 : nullptr;

@@ -139,6 +139,7 @@ struct FaceProps {
   D3 rho[3];                // densities (live oil: with its dissolved gas)
   D3 mob[3];                // b_alpha * lambda_alpha
   D3 rmob;                  // r b_o lambda_o: dissolved gas carried by the oil (live oil)
+  D3 lamt;                  // total mobility sum_alpha lambda_alpha (well injection)
 };
 
 __device__ __forceinline__ D3 sel(bool c, const D3& x, const D3& y) {
@@ -160,6 +161,7 @@ __device__ __forceinline__ FaceProps pick(bool c, const FaceProps& x, const Face
     r.mob[a] = sel(c, x.mob[a], y.mob[a]);
   }
   r.rmob = sel(c, x.rmob, y.rmob);
+  r.lamt = sel(c, x.lamt, y.lamt);
   return r;
 }
 
@@ -208,11 +210,14 @@ __device__ __forceinline__ void properties(const opm_fluid& f, double p_v, doubl
     P.mob[a] = b[a] * (kr[a] / f.mu[a]);
   }
   P.rmob = cst<3>(0.0);
+  D3 lam_o = kro / f.mu[1];
   if (LIVE) {
     P.rho[1] = b[1] * (cst<3>(f.rho_s[1]) + r * f.rho_s[2]);
-    P.mob[1] = b[1] * ((kro * (cst<3>(1.0) + r * f.muo_r)) / f.mu[1]);
+    lam_o = (kro * (cst<3>(1.0) + r * f.muo_r)) / f.mu[1];
+    P.mob[1] = b[1] * lam_o;
     P.rmob = r * P.mob[1];
   }
+  P.lamt = (krw / f.mu[0] + lam_o) + krg / f.mu[2];
   if (acc) {
     const D3 s[3] = {sw, so, sg};
 #pragma unroll
@@ -254,6 +259,73 @@ __device__ __forceinline__ D6 face_flux(const FaceProps& L, const FaceProps& H, 
   return F;
 }
 
+// ------------------------------------------------- standard wells (sec. 2.2.1)
+using D7 = Dual<7>;
+
+// Weights of the weighted total rate and fractions (eq. weighted_total_rate).
+constexpr double kWellG0 = 1.0, kWellG1 = 1.0, kWellG2 = 0.01;
+__device__ __forceinline__ double well_g(int a) { return a == 0 ? kWellG0 : (a == 1 ? kWellG1 : kWellG2); }
+
+// The well unknowns as duals in slots 3-6 (Q_t, F_w, F_g, p_bhp) and the
+// wellbore fluid's surface volume per reservoir volume of each component,
+// mix_a = (F_a / g_a) / sum_b F_b / (g_b b_b(p_bhp)), F_o = 1 - F_w - F_g.
+struct WellVars {
+  D7 Qt, F[3], pb, mix[3];
+};
+
+__device__ __forceinline__ WellVars well_vars(const opm_fluid& f, const double* x) {
+  WellVars W;
+  W.Qt = cst<7>(x[0]);
+  W.Qt.d[3] = 1.0;
+  W.F[0] = cst<7>(x[1]);
+  W.F[0].d[4] = 1.0;
+  W.F[2] = cst<7>(x[2]);
+  W.F[2].d[5] = 1.0;
+  W.F[1] = (cst<7>(1.0) - W.F[0]) - W.F[2];
+  W.pb = cst<7>(x[3]);
+  W.pb.d[6] = 1.0;
+  D7 S = cst<7>(0.0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const D7 b = dexp((W.pb - cst<7>(f.p_ref)) * f.c[a]);
+    S = S + quot(W.F[a] * (1.0 / well_g(a)), b);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) W.mix[a] = quot(W.F[a] * (1.0 / well_g(a)), S);
+  return W;
+}
+
+// A cell dual (slots 0-2) in the connection's slots.
+__device__ __forceinline__ D7 lift7(const D3& a) {
+  D7 r = cst<7>(a.v);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r.d[k] = a.d[k];
+  return r;
+}
+
+// Surface rate of each component through a standard-well connection
+// (production positive; eq. wellinflow with h_w,j = 0): producing (p > p_bhp)
+// the cell's phases, q_a = WI b_a lambda_a (p - p_bhp) (+ r b_o lambda_o for
+// gas, live oil); injecting the wellbore fluid at the cell's total
+// mobility, q_a = WI lambda_t (p - p_bhp) mix_a.  Slots 0-2: the cell's
+// variables; 3-6: the well's.
+template <bool LIVE>
+__device__ __forceinline__ void std_conn_rate(const FaceProps& P, const WellVars& W, double wi,
+                                              D7 q[3]) {
+  D7 pc = cst<7>(P.p);
+  pc.d[0] = 1.0;
+  const D7 dp = pc - W.pb;
+  if (dp.v > 0.0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q[a] = (lift7(P.mob[a]) * wi) * dp;
+    if (LIVE) q[2] = q[2] + (lift7(P.rmob) * wi) * dp;
+  } else {
+    const D7 lt = (lift7(P.lamt) * wi) * dp;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q[a] = lt * W.mix[a];
+  }
+}
+
 struct AsmArgs {
   int n;
   const double* y;
@@ -274,6 +346,10 @@ struct AsmArgs {
   const double* conn_bhp;
   opm_fluid fluid;
   const uint8_t* meaning;   // [n] meaning of the third variable (live oil)
+  int n_wells;              // > 0: standard wells (the connection terms below)
+  const int32_t* conn_well;
+  const double* well_state; // [n_wells][4]
+  double* Cw;               // [n_conns][3][4] out: d(cell residual)/d(well unknowns)
   double* R;
   double* J;
   double* partials;   // [gridDim.x][kNormStride] or null
@@ -343,6 +419,22 @@ __device__ __forceinline__ void assemble_row(const AsmArgs& a, int i, double dt,
   // rate in the gas component)
   for (int t = a.cell_conn_ptr[i]; t < a.cell_conn_ptr[i + 1]; ++t) {
     const int k = a.cell_conn[t];
+    if (a.n_wells > 0) {   // standard well: the connection rate from the well unknowns
+      const WellVars W = well_vars(a.fluid, a.well_state + 4 * a.conn_well[k]);
+      D7 q[3];
+      std_conn_rate<LIVE>(Pi, W, a.conn_wi[k], q);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        r[c].v += q[c].v;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) r[c].d[v] += q[c].d[v];
+        if (a.Cw) {
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) a.Cw[12 * (size_t)k + 4 * c + kk] = q[c].d[3 + kk];
+        }
+      }
+      continue;
+    }
     if (a.conn_kind[k] == OPM_WELL_RATE_INJ) {
       const int ph = a.conn_phase[k];
 #pragma unroll

@@ -218,6 +218,10 @@ __device__ int wg_newton(const EnsMember& M, const Topo& tp, IluView<T> iv, doub
   a.conn_bhp = M.pb.conn_bhp;
   a.fluid = M.pb.fluid;
   a.meaning = nullptr;   // dead oil only (opm_ensemble_prepare rejects live oil)
+  a.n_wells = 0;         // and the simplified wells only
+  a.conn_well = nullptr;
+  a.well_state = nullptr;
+  a.Cw = nullptr;
   a.R = M.R;
   a.J = M.J;
   a.partials = nullptr;
@@ -460,7 +464,7 @@ int opm_ensemble_prepare(const opm_problem* members, double* const* y, int32_t n
   for (int m = 0; m < n_members; ++m) {
     const opm_problem& pb = members[m];
     if (pb.n_cells <= 0 || pb.nnzb != pb.n_cells + 2 * pb.n_faces || pb.n_levels <= 0 || !y[m] ||
-        pb.fluid.live != 0)
+        pb.fluid.live != 0 || pb.n_wells != 0)
       return OPM_EINVAL;
     max_level = std::max(max_level, (int)pb.max_level);
   }

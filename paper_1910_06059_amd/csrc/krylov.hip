@@ -138,9 +138,11 @@ __global__ __launch_bounds__(kBlock) void k_begin(int N, Work w, int G) {
     w.p[k] = w.r[k] + beta * (w.p[k] - om * w.v[k]);
 }
 
-// v = A p^ ; partials of <r^, v>.
+// v = A p^ (with standard wells the Schur-complement operator, wc) ;
+// partials of <r^, v>.
 __global__ __launch_bounds__(kBlock) void k_spmv_rv(int n, const int32_t* row_ptr,
-                                                     const int32_t* col, const double* J, Work w) {
+                                                     const int32_t* col, const double* J, Work w,
+                                                     WellCorr wc) {
   __shared__ double sh[kBlock / kWave];
   if (w.sc->state != kRunning) return;
   double acc = 0.0;
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_rv(int n, const int32_t* row_pt
        g += gridDim.x * (kBlock / kWave)) {
     int row, comp;
     double yv;
-    if (spmv_group(n, row_ptr, col, J, w.ph, g, lane, row, comp, yv)) {
+    if (spmv_group(n, row_ptr, col, J, w.ph, g, lane, row, comp, yv, wc)) {
       w.v[3 * row + comp] = yv;
       acc += w.rh[3 * row + comp] * yv;
     }
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_s_check(Work w, int G) {
 template <bool CHECK>
 __global__ __launch_bounds__(kBlock) void k_spmv_t(int n, const int32_t* row_ptr,
                                                     const int32_t* col, const double* J, Work w,
-                                                    int nss) {
+                                                    int nss, WellCorr wc) {
   __shared__ double sh[kBlock / kWave];
   __shared__ int word;
   if (CHECK) {
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_t(int n, const int32_t* row_ptr
        g += gridDim.x * (kBlock / kWave)) {
     int row, comp;
     double yv;
-    if (spmv_group(n, row_ptr, col, J, w.sh, g, lane, row, comp, yv)) {
+    if (spmv_group(n, row_ptr, col, J, w.sh, g, lane, row, comp, yv, wc)) {
       w.t[3 * row + comp] = yv;
       ts += yv * w.s[3 * row + comp];
       tt += yv * yv;
@@ -302,6 +304,7 @@ struct ChunkKey {
   const void* work;
   hipStream_t st;
   int precision, chunk, device, sweep_mode, sweep_kernel, block_depth;
+  WellSchur ws;   // standard wells (all zero without)
 };
 struct ChunkGraph {
   ChunkKey key;
@@ -329,9 +332,10 @@ int capture_stream(int device, hipStream_t* out) {
 }  // namespace
 
 // Enqueue the whole solve; returns after reading the final scalars.
+// ws (may be null): standard wells, solved through their Schur complement.
 int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, const double* b,
              double* x, double rtol, int maxit, void* work, opm_solve_report* rep,
-             hipStream_t st) {
+             hipStream_t st, const WellSchur* ws) {
   const int n = pb->n_cells, N = 3 * n;
   Work w = carve(pb, work);
   const int G = vec_grid(N), Gr = std::min(kMaxGrid, std::max(1, spmv_blocks(n)));
@@ -346,25 +350,30 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
   kry::Fused fs{w.r, nullptr, w.v, w.s, w.part_rv, nullptr, Gr, w.part_ss, w.sc};
   Scalars host;
   int launched = 0;
+  const WellCorr wc = ws ? ws->wc() : WellCorr{nullptr, nullptr, nullptr};
   auto enqueue_chunk = [&](hipStream_t st) -> int {
     for (int c = 0; c < chunk; ++c) {
       if (fused) {
         OPM_TRY(ilu_apply_fused(pb, ilu, precision, kry::kFuseBegin, fb, w.ph, st));
+        if (ws) OPM_TRY(well_op(*ws, w.ph, &w.sc->state, st));
         hipLaunchKernelGGL(k_spmv_rv, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
-                           pb->col_idx, J, w);
+                           pb->col_idx, J, w, wc);
         OPM_TRY(ilu_apply_fused(pb, ilu, precision, kry::kFuseS, fs, w.sh, st));
+        if (ws) OPM_TRY(well_op(*ws, w.sh, &w.sc->state, st));
         hipLaunchKernelGGL(k_spmv_t<true>, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
-                           pb->col_idx, J, w, pb->n_sub);
+                           pb->col_idx, J, w, pb->n_sub, wc);
       } else {
         hipLaunchKernelGGL(k_begin, dim3(G), dim3(kBlock), 0, st, N, w, G);
         OPM_TRY(ilu_apply(pb, ilu, precision, w.p, w.ph, st, &w.sc->state));
+        if (ws) OPM_TRY(well_op(*ws, w.ph, &w.sc->state, st));
         hipLaunchKernelGGL(k_spmv_rv, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
-                           pb->col_idx, J, w);
+                           pb->col_idx, J, w, wc);
         hipLaunchKernelGGL(k_s, dim3(G), dim3(kBlock), 0, st, N, w, Gr);
         hipLaunchKernelGGL(k_s_check, dim3(1), dim3(kBlock), 0, st, w, G);
         OPM_TRY(ilu_apply(pb, ilu, precision, w.s, w.sh, st, &w.sc->state));
+        if (ws) OPM_TRY(well_op(*ws, w.sh, &w.sc->state, st));
         hipLaunchKernelGGL(k_spmv_t<false>, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
-                           pb->col_idx, J, w, 0);
+                           pb->col_idx, J, w, 0, wc);
       }
       hipLaunchKernelGGL(k_x, dim3(G), dim3(kBlock), 0, st, N, x, w, Gr);
       OPM_TRY_HIP(hipGetLastError());
@@ -384,6 +393,7 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
     key.chunk = chunk;
     OPM_TRY_HIP(hipGetDevice(&key.device));
     key.sweep_mode = g_sweep_mode;
+    if (ws) std::memcpy(&key.ws, ws, sizeof *ws);   // ws is built zero-filled (padding too)
     key.sweep_kernel = g_sweep_kernel;
     key.block_depth = g_block_depth;
   }

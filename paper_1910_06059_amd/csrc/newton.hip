@@ -4,8 +4,10 @@
 // C-ABI entry points of the library.
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "common.h"
+#include "wells_dev.h"
 
 namespace opm {
 
@@ -15,7 +17,7 @@ extern int g_sweep_kernel;
 extern int g_krylov_chunk;
 extern int g_krylov_graph;
 int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, double dt,
-                    double* R, double* J, double* norms, hipStream_t s);
+                    double* R, double* J, double* norms, hipStream_t s, double* Cw = nullptr);
 int launch_accumulation(const opm_problem* pb, const double* y, double* acc0, hipStream_t s);
 size_t ilu_bytes(const opm_problem* pb, int precision);
 int ilu_factor(const opm_problem* pb, const double* J, void* ilu, int precision, int32_t* status,
@@ -26,7 +28,7 @@ size_t krylov_bytes(const opm_problem* pb);
 int spmv(const opm_problem* pb, const double* J, const double* x, double* y, hipStream_t s);
 int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, const double* b,
              double* x, double rtol, int maxit, void* work, opm_solve_report* rep,
-             hipStream_t st);
+             hipStream_t st, const WellSchur* ws = nullptr);
 size_t gmres_bytes(const opm_problem* pb, int restart);
 int gmres(const opm_problem* pb, const double* J, void* ilu, int precision, const double* b,
           double* x, double rtol, int maxit, int restart, void* work, opm_solve_report* rep,
@@ -52,6 +54,7 @@ struct NewtonWork {
   double* norms;
   int32_t* flags;   // [0] factor status, [1] non-finite update
   uint8_t* mean_save;   // [n] variable meanings of the last accepted state (live oil)
+  WellWork wells;       // standard wells (unset without)
   void* ilu;
   void* krylov;
 };
@@ -63,7 +66,7 @@ size_t newton_bytes(const opm_problem* pb, int precision, int krylov = OPM_KRYLO
   const size_t kb = krylov == OPM_KRYLOV_GMRES ? gmres_bytes(pb, restart) : krylov_bytes(pb);
   return align256(sizeof(double) * N) * 3 + align256(sizeof(double) * 9 * (size_t)pb->nnzb) +
          align256(norms_bytes(pb)) + 256 + align256((size_t)pb->n_cells) +
-         align256(ilu_bytes(pb, precision)) + align256(kb);
+         align256(wells_bytes(pb)) + align256(ilu_bytes(pb, precision)) + align256(kb);
 }
 
 NewtonWork carve(const opm_problem* pb, int precision, void* work) {
@@ -84,6 +87,9 @@ NewtonWork carve(const opm_problem* pb, int precision, void* work) {
   c += 256;
   w.mean_save = (uint8_t*)c;
   c += align256((size_t)pb->n_cells);
+  std::memset(&w.wells, 0, sizeof w.wells);
+  if (pb->n_wells > 0) w.wells = wells_carve(pb, c);
+  c += align256(wells_bytes(pb));
   w.ilu = c;
   c += align256(ilu_bytes(pb, precision));
   w.krylov = c;
@@ -176,7 +182,11 @@ bool valid_problem(const opm_problem* pb) {
          pb->n_levels > 0 && pb->level_ptr_h[pb->n_levels] == pb->n_cells &&
          (pb->fluid.live == 0 || (pb->fluid.live == 1 && pb->meaning && pb->fluid.rs_c >= 0.0 &&
                                   pb->fluid.bo_r >= 0.0 && pb->fluid.muo_r >= 0.0 &&
-                                  pb->fluid.eps_switch >= 0.0));
+                                  pb->fluid.eps_switch >= 0.0)) &&
+         (pb->n_wells == 0 ||
+          (pb->n_wells > 0 && pb->n_conns > 0 && pb->well_conn_ptr && pb->conn_cell &&
+           pb->conn_well && pb->well_kind && pb->well_phase && pb->well_target && pb->well_vol &&
+           pb->well_state));
 }
 
 bool valid_prec(int p) { return p == OPM_PREC_FP64 || p == OPM_PREC_MIXED; }
@@ -189,26 +199,45 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
   memset(rep, 0, sizeof(*rep));
   OPM_TRY(launch_accumulation(pb, y_prev, w.acc0, s));
   hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, w.flags);
+  // standard wells: the well state at entry is the one at the start of the
+  // step (its wellbore storage)
+  const bool std_wells = pb->n_wells > 0;
+  const WellWork& ww = w.wells;
+  if (std_wells) OPM_TRY(well_storage0(pb, pb->well_state, ww.A0, s));
+  WellSchur ws;
+  std::memset(&ws, 0, sizeof ws);
+  if (std_wells) ws = well_schur(pb, ww);
+  std::vector<double> wn(std_wells ? pb->n_wells : 0);
   int status = OPM_ENOTCONV;
   for (int it = 0;; ++it) {
     OPM_TRY_HIP(hipEventRecord(ev.e[0], s));
-    OPM_TRY(launch_assemble(pb, y, w.acc0, dt, w.R, w.J, w.norms, s));
+    OPM_TRY(launch_assemble(pb, y, w.acc0, dt, w.R, w.J, w.norms, s, std_wells ? ww.C : nullptr));
+    if (std_wells) OPM_TRY(well_system(pb, y, dt, ww, w.flags, s));
     OPM_TRY_HIP(hipEventRecord(ev.e[1], s));
     double nrm[8];
     int32_t flags[4];
     OPM_TRY_HIP(hipMemcpyAsync(nrm, w.norms, sizeof(nrm), hipMemcpyDeviceToHost, s));
     OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    if (std_wells)
+      OPM_TRY_HIP(hipMemcpyAsync(wn.data(), ww.wn, sizeof(double) * wn.size(),
+                                 hipMemcpyDeviceToHost, s));
     OPM_TRY_HIP(hipStreamSynchronize(s));
     rep->t_assemble += elapsed(ev.e[0], ev.e[1]);
     for (int c = 0; c < 3; ++c) {
       rep->cnv[c] = nrm[c];
       rep->mb[c] = nrm[3 + c];
     }
-    if (flags[1] || !std::isfinite(nrm[6]) || !std::isfinite(nrm[7])) {
+    double cmax = nrm[6];
+    for (double v : wn) cmax = std::isnan(v) ? v : std::fmax(cmax, v);
+    if (flags[1] || !std::isfinite(cmax) || !std::isfinite(nrm[7])) {
       status = OPM_ENONFINITE;
       break;
     }
-    if (nrm[6] <= o->tol_cnv && nrm[7] <= o->tol_mb) {
+    if (flags[0] != 0) {   // a singular well matrix D
+      status = flags[0];
+      break;
+    }
+    if (cmax <= o->tol_cnv && nrm[7] <= o->tol_mb) {
       status = OPM_OK;
       break;
     }
@@ -219,12 +248,13 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
     OPM_TRY(ilu_factor(pb, w.J, w.ilu, o->precision, &w.flags[0], s));
     OPM_TRY_HIP(hipEventRecord(ev.e[2], s));
     opm_solve_report lr;
+    if (std_wells) OPM_TRY(well_rhs(pb, ww, w.R, s));   // R_r - sum C D^-1 R_w
     if (o->krylov == OPM_KRYLOV_GMRES)
       OPM_TRY(gmres(pb, w.J, w.ilu, o->precision, w.R, w.d, o->lin_rtol, o->lin_maxit, o->restart,
                     w.krylov, &lr, s));
     else
       OPM_TRY(bicgstab(pb, w.J, w.ilu, o->precision, w.R, w.d, o->lin_rtol, o->lin_maxit,
-                       w.krylov, &lr, s));
+                       w.krylov, &lr, s, std_wells ? &ws : nullptr));
     OPM_TRY_HIP(hipEventRecord(ev.e[3], s));
     rep->lin_its += lr.its;
     OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
@@ -239,6 +269,8 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
       status = lr.status;
       break;
     }
+    if (std_wells)
+      OPM_TRY(well_update(pb, ww, w.d, o->ds_max, o->dp_max_rel, w.flags, s));
     uint8_t* mean = pb->fluid.live ? pb->meaning : nullptr;
     hipLaunchKernelGGL(k_update, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, n, y, w.d,
                        o->ds_max, o->dp_max_rel, mean, pb->fluid.rs_c, pb->fluid.eps_switch,
@@ -297,9 +329,14 @@ int advance(const opm_problem* pb, double* y, const double* y_nm1, double dt,
   // live oil: the variable meanings are saved and restored with the state
   uint8_t* mean_save = pb->fluid.live ? carve(pb, opts->precision, work).mean_save : nullptr;
   const size_t mbytes = (size_t)pb->n_cells;
+  // standard wells: the well state likewise
+  double* wsave = pb->n_wells > 0 ? carve(pb, opts->precision, work).wells.save : nullptr;
+  const size_t wbytes = sizeof(double) * 4 * (size_t)pb->n_wells;
   OPM_TRY_HIP(hipMemcpyAsync(y_save, y, bytes, hipMemcpyDeviceToDevice, s));
   if (mean_save)
     OPM_TRY_HIP(hipMemcpyAsync(mean_save, pb->meaning, mbytes, hipMemcpyDeviceToDevice, s));
+  if (wsave)
+    OPM_TRY_HIP(hipMemcpyAsync(wsave, pb->well_state, wbytes, hipMemcpyDeviceToDevice, s));
   double t = 0.0, dt_try = dt;
   int status = OPM_OK;
   bool first = true;
@@ -330,12 +367,16 @@ int advance(const opm_problem* pb, double* y, const double* y_nm1, double dt,
       OPM_TRY_HIP(hipMemcpyAsync(y_save, y, bytes, hipMemcpyDeviceToDevice, s));
       if (mean_save)
         OPM_TRY_HIP(hipMemcpyAsync(mean_save, pb->meaning, mbytes, hipMemcpyDeviceToDevice, s));
+      if (wsave)
+        OPM_TRY_HIP(hipMemcpyAsync(wsave, pb->well_state, wbytes, hipMemcpyDeviceToDevice, s));
       t += h;
       report->substeps++;
     } else {
       OPM_TRY_HIP(hipMemcpyAsync(y, y_save, bytes, hipMemcpyDeviceToDevice, s));
       if (mean_save)
         OPM_TRY_HIP(hipMemcpyAsync(pb->meaning, mean_save, mbytes, hipMemcpyDeviceToDevice, s));
+      if (wsave)
+        OPM_TRY_HIP(hipMemcpyAsync(pb->well_state, wsave, wbytes, hipMemcpyDeviceToDevice, s));
       dt_try = 0.5 * h;
       report->cuts++;
       if (report->cuts > opts->max_cuts) {
@@ -483,6 +524,33 @@ int opm_gmres(const opm_problem* pb, const double* J, const void* ilu, int preci
                report, as_stream(stream));
 }
 
+size_t opm_wells_bytes(const opm_problem* pb) {
+  return pb && pb->n_wells > 0 ? wells_bytes(pb) : 0;
+}
+
+int opm_assemble_wells(const opm_problem* pb, const double* y, const double* acc0,
+                       const double* well_state0, double dt, double* R, double* J, double* Rw,
+                       double* B, double* C, double* D, void* work, void* stream) {
+  if (!valid_problem(pb) || pb->n_cells == 0 || pb->n_wells <= 0 || !y || !acc0 ||
+      !well_state0 || !(dt > 0.0) || !R || !J || !Rw || !B || !C || !D || !work)
+    return OPM_EINVAL;
+  hipStream_t s = as_stream(stream);
+  WellWork ww = wells_carve(pb, work);
+  ww.Rw = Rw;
+  ww.B = B;
+  ww.C = C;
+  ww.D = D;
+  int32_t* flags = (int32_t*)ww.save;   // scratch for the status word
+  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, flags);
+  OPM_TRY(well_storage0(pb, well_state0, ww.A0, s));
+  OPM_TRY(launch_assemble(pb, y, acc0, dt, R, J, nullptr, s, C));
+  OPM_TRY(well_system(pb, y, dt, ww, flags, s));
+  int32_t f = 0;
+  OPM_TRY_HIP(hipMemcpyAsync(&f, flags, sizeof f, hipMemcpyDeviceToHost, s));
+  OPM_TRY_HIP(hipStreamSynchronize(s));
+  return f;
+}
+
 size_t opm_newton_bytes(const opm_problem* pb, int precision) {
   return pb && valid_prec(precision) ? newton_bytes(pb, precision) : 0;
 }
@@ -505,11 +573,16 @@ static bool valid_opts(const opm_newton_opts* o) {
          o->tol_cnv >= 0.0 && o->tol_mb >= 0.0 && valid_krylov(o);
 }
 
+// Standard wells are solved with BiCGStab only.
+static bool valid_wells_opts(const opm_problem* pb, const opm_newton_opts* o) {
+  return pb->n_wells == 0 || o->krylov == OPM_KRYLOV_BICGSTAB;
+}
+
 int opm_newton_step(const opm_problem* pb, double* y, const double* y_prev, double dt,
                     const opm_newton_opts* opts, void* work, opm_newton_report* report,
                     void* stream) {
   if (!valid_problem(pb) || pb->n_cells == 0 || !valid_opts(opts) || !(dt > 0.0) || !y ||
-      !y_prev || !work || !report)
+      !y_prev || !work || !report || !valid_wells_opts(pb, opts))
     return OPM_EINVAL;
   return newton_step(pb, y, y_prev, dt, opts, work, report, as_stream(stream));
 }
@@ -517,7 +590,7 @@ int opm_newton_step(const opm_problem* pb, double* y, const double* y_prev, doub
 int opm_advance(const opm_problem* pb, double* y, double dt, const opm_newton_opts* opts,
                 void* work, double* y_save, opm_newton_report* report, void* stream) {
   if (!valid_problem(pb) || pb->n_cells == 0 || !valid_opts(opts) || !(dt > 0.0) || !y ||
-      !y_save || !work || !report)
+      !y_save || !work || !report || !valid_wells_opts(pb, opts))
     return OPM_EINVAL;
   return advance(pb, y, nullptr, dt, opts, nullptr, nullptr, nullptr, work, y_save, report,
                  nullptr, as_stream(stream));
@@ -527,7 +600,7 @@ int opm_guess_select(const opm_problem* pb, double* y, const double* y_prev,
                      const double* y_guess, double dt, void* work, int32_t* chosen, double* cnv,
                      void* stream) {
   if (!valid_problem(pb) || pb->n_cells == 0 || !(dt > 0.0) || !y || !y_prev || !y_guess ||
-      !work || pb->fluid.live != 0)
+      !work || pb->fluid.live != 0 || pb->n_wells != 0)
     return OPM_EINVAL;
   return guess_select(pb, y, y_prev, &y_guess, 1, dt, work, chosen, cnv, as_stream(stream));
 }
@@ -539,8 +612,9 @@ int opm_advance_guess(const opm_problem* pb, double* y, const double* y_nm1, dou
   if (!valid_problem(pb) || pb->n_cells == 0 || !valid_opts(opts) || !(dt > 0.0) || !y ||
       !y_save || !work || !report)
     return OPM_EINVAL;
-  if (net && (!y_nm1 || !guess_work || !y_guess || opm_guess_work_bytes(pb, net) == 0 ||
-              pb->fluid.live != 0))
+  if (!valid_wells_opts(pb, opts) ||
+      (net && (!y_nm1 || !guess_work || !y_guess || opm_guess_work_bytes(pb, net) == 0 ||
+               pb->fluid.live != 0 || pb->n_wells != 0)))
     return OPM_EINVAL;
   return advance(pb, y, y_nm1, dt, opts, net, guess_work, y_guess, work, y_save, report,
                  guess_used, as_stream(stream));

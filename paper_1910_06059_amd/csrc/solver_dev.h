@@ -7,6 +7,7 @@
 #pragma once
 
 #include "common.h"
+#include "wells_dev.h"
 
 namespace opm {
 namespace ilu {
@@ -404,12 +405,16 @@ __device__ __forceinline__ void apply_levels_wg(const Topo& t, IluView<T> v, con
 // sums of an output component sit in lanes l, l+3, ..., l+18 and are added in
 // block order by the lane of block 0, which returns true and the row and
 // component it owns.  Lane 63 and rows past n contribute nothing.  Every lane
-// of the wavefront must call it (cross-lane reads).
+// of the wavefront must call it (cross-lane reads).  With standard wells
+// (wc.corr non-null) the owning lane subtracts the well corrections of its
+// cell's connections: the Schur-complement operator.
 constexpr int kSpmvRowsPerWave = 3;
 
 __device__ __forceinline__ bool spmv_group(int n, const int32_t* row_ptr, const int32_t* col,
                                            const double* J, const double* x, int group,
-                                           int lane, int& row, int& comp, double& yv) {
+                                           int lane, int& row, int& comp, double& yv,
+                                           const WellCorr& wc = WellCorr{nullptr, nullptr,
+                                                                         nullptr}) {
   const int rl = lane / 21, rem = lane - 21 * rl;
   const int q = rem / 3;
   comp = rem - 3 * q;
@@ -427,6 +432,8 @@ __device__ __forceinline__ bool spmv_group(int n, const int32_t* row_ptr, const 
   double sum = v;
 #pragma unroll
   for (int k = 1; k < 7; ++k) sum += __shfl(v, lane + 3 * k, kWave);
+  if (wc.corr && live && q == 0)
+    for (int t = wc.ccp[row]; t < wc.ccp[row + 1]; ++t) sum -= wc.corr[3 * (size_t)wc.cc[t] + comp];
   yv = sum;
   return live && q == 0;
 }

@@ -63,7 +63,10 @@ class Problem(ctypes.Structure):
                 ("conn_kind", _vp), ("conn_phase", _vp), ("conn_wi", _vp), ("conn_rate", _vp),
                 ("conn_bhp", _vp), ("fluid", Fluid), ("sweep_span", _i32),
                 ("n_sub", _i32), ("max_sub", _i32), ("max_width", _i32),
-                ("sub_level_ptr", _vp), ("slot", _vp), ("meaning", _vp)]
+                ("sub_level_ptr", _vp), ("slot", _vp), ("meaning", _vp),
+                ("n_wells", _i32), ("pad_w", _i32), ("well_conn_ptr", _vp), ("conn_cell", _vp),
+                ("conn_well", _vp), ("well_kind", _vp), ("well_phase", _vp), ("well_target", _vp),
+                ("well_vol", _vp), ("well_state", _vp)]
 
 
 class SolveReport(ctypes.Structure):
@@ -96,7 +99,7 @@ EXPORTS = [
     "opm_well_index", "opm_well_groups", "opm_accumulation", "opm_norms_bytes", "opm_assemble",
     "opm_ilu0_bytes", "opm_ilu0_factor", "opm_ilu0_apply", "opm_spmv", "opm_krylov_bytes",
     "opm_bicgstab", "opm_gmres_bytes", "opm_gmres", "opm_newton_bytes", "opm_newton_work_bytes",
-    "opm_newton_step", "opm_advance", "opm_set_option",
+    "opm_newton_step", "opm_advance", "opm_set_option", "opm_wells_bytes", "opm_assemble_wells",
     "opm_ensemble_bytes", "opm_ensemble_prepare", "opm_ensemble_launch",
 ]
 
@@ -163,6 +166,10 @@ def lib():
         L.opm_newton_bytes.restype = ctypes.c_size_t
         L.opm_newton_work_bytes.argtypes = [P, ctypes.POINTER(NewtonOpts)]
         L.opm_newton_work_bytes.restype = ctypes.c_size_t
+        L.opm_wells_bytes.argtypes = [P]
+        L.opm_wells_bytes.restype = ctypes.c_size_t
+        L.opm_assemble_wells.argtypes = [P, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp,
+                                         _vp, _vp, _vp, _vp]
         L.opm_newton_step.argtypes = [P, _vp, _vp, ctypes.c_double, ctypes.POINTER(NewtonOpts),
                                       _vp, ctypes.POINTER(NewtonReport), _vp]
         L.opm_advance.argtypes = [P, _vp, ctypes.c_double, ctypes.POINTER(NewtonOpts), _vp, _vp,
@@ -351,6 +358,25 @@ class GpuModel:
         self.meaning_t = torch.from_numpy(case.initial_meaning()).to(self.dev)
         if self.live:
             self.pb.meaning = self.meaning_t.data_ptr()
+        # standard wells: well unknowns (Q_t, F_w, F_g, p_bhp) per well
+        self.nw = nw
+        self.std_wells = bool(getattr(case, "standard_wells", False))
+        if self.std_wells:
+            vol, x0 = case.standard_well_init()
+            wcp = np.zeros(nw + 1, np.int32)
+            wcp[1:] = np.cumsum([len(w.cells) for w in wells])
+            self.well_conn_ptr = torch.from_numpy(wcp).to(self.dev)
+            self.well_vol = torch.tensor(vol, **f64)
+            self.well_state_t = torch.tensor(x0, **f64).contiguous()
+            self.pb.n_wells = nw
+            self.pb.well_conn_ptr = self.well_conn_ptr.data_ptr()
+            self.pb.conn_cell = self.conn_cell.data_ptr()
+            self.pb.conn_well = self.conn_well.data_ptr()
+            self.pb.well_kind = self.well_kind.data_ptr()
+            self.pb.well_phase = self.well_phase.data_ptr()
+            self.pb.well_target = self.well_target.data_ptr()
+            self.pb.well_vol = self.well_vol.data_ptr()
+            self.pb.well_state = self.well_state_t.data_ptr()
         self._work = {}
         torch.cuda.current_stream().synchronize()
 
@@ -366,9 +392,35 @@ class GpuModel:
 
     def initial_state(self) -> torch.Tensor:
         """The case's initial state; also resets the variable meanings to the
-        case's initial ones (live oil)."""
+        case's initial ones (live oil) and the well unknowns (standard wells)."""
         self.set_meaning(self.case.initial_meaning())
+        if self.std_wells:
+            self.set_well_state(self.case.standard_well_init()[1])
         return self.state(self.case.initial_state())
+
+    def set_well_state(self, x) -> None:
+        """Well unknowns [n_wells][4] = (Q_t, F_w, F_g, p_bhp) (standard wells)."""
+        self.well_state_t.copy_(torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)))
+
+    def well_state(self) -> np.ndarray:
+        return self.well_state_t.cpu().numpy().copy()
+
+    def assemble_wells(self, y, acc0, well_state0, dt):
+        """opm_assemble_wells: (R, J, Rw, B, C, D) on the device."""
+        L = lib()
+        R = self.zeros_state()
+        J = torch.zeros((self.nnzb, 3, 3), dtype=torch.float64, device=self.dev)
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        Rw = torch.zeros((self.nw, 4), **f64)
+        B = torch.zeros((max(self.nc, 1), 4, 3), **f64)
+        C = torch.zeros((max(self.nc, 1), 3, 4), **f64)
+        D = torch.zeros((self.nw, 4, 4), **f64)
+        x0 = torch.as_tensor(np.ascontiguousarray(well_state0, dtype=np.float64)).to(self.dev)
+        work = self.workspace("wells", L.opm_wells_bytes(self._pbp()))
+        _check(L.opm_assemble_wells(self._pbp(), _ptr(y), _ptr(acc0), _ptr(x0), dt, _ptr(R),
+                                    _ptr(J), _ptr(Rw), _ptr(B), _ptr(C), _ptr(D), _ptr(work),
+                                    _stream()), "opm_assemble_wells")
+        return R, J, Rw, B[:self.nc], C[:self.nc], D
 
     def set_meaning(self, mean) -> None:
         """Meaning of the third variable per cell (0 s_g, 1 r_go), the state
@@ -483,6 +535,7 @@ class GpuModel:
         y = self.initial_state() if y is None else y
         states, reps = [], []
         self.run_meanings = []
+        self.run_well_states = []
         for dt in self.case.report_dt[:n_steps]:
             st, rep = self.advance(y, dt, opts)
             if st != OK:
@@ -491,6 +544,8 @@ class GpuModel:
                 states.append(y.detach().cpu().numpy().copy())
                 if self.live:
                     self.run_meanings.append(self.meaning())
+                if self.std_wells:
+                    self.run_well_states.append(self.well_state())
             reps.append(rep.as_dict())
         return y, states, reps
 

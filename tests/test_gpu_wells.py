@@ -1,0 +1,186 @@
+"""Standard wells (well unknowns, Schur complement) on the GPU, through the C
+ABI, against the oracle's standard-well model.
+
+Tolerances: the coupled linearization (R, J, R_w, B, C, D) to 1e-11 of the
+largest entry of the same column (D: of the same row); converged reservoir
+states to 1e-6 (relative pressure, absolute saturations) and well states to
+1e-6 (relative BHP and rate, absolute fractions) after every report step,
+the parity bar of the path.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1910_06059_amd import cases
+from paper_1910_06059_amd.cases import DAY, PSI, STB, Well
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def opm():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_1910_06059_amd import opm as _opm
+    _opm.init()
+    return _opm
+
+
+def _box():
+    wells = [Well("I", cases.WELL_RATE_INJ, [(0, 0, 0), (0, 0, 1)], 400 * STB / DAY,
+                  phase=cases.W),
+             Well("P", cases.WELL_BHP_PROD, [(3, 2, 0), (3, 2, 1)], 3000 * PSI)]
+    c = cases.box_case(4, 3, 2, seed=7, wells=wells, dz=[6.0, 9.0])
+    c.standard_wells = True
+    return c
+
+
+def _c1():
+    c = cases.config1()
+    c.standard_wells = True
+    return c
+
+
+def _c6():
+    c = cases.config_live()
+    c.standard_wells = True
+    return c
+
+
+def _masked():
+    c = cases.box_case(9, 7, 4, seed=5, mask=cases.masked_mask(
+        np.random.default_rng(8), (4, 7, 9), 150), wells=[])
+    act = np.argwhere(c.mask)
+    k, j, i = act[0]
+    k2, j2, i2 = act[-1]
+    c.wells = [Well("I", cases.WELL_RATE_INJ, [(int(i), int(j), int(k))], 300 * STB / DAY),
+               Well("P", cases.WELL_BHP_PROD, [(int(i2), int(j2), int(k2))], 3000 * PSI)]
+    c.standard_wells = True
+    return c
+
+
+CASES = {"box": _box, "C1": _c1, "C6_live": _c6, "masked": _masked}
+
+
+def _well_state(c, m, y, seed):
+    rng = np.random.default_rng(seed)
+    x = m.well_state().copy()
+    pm = y[:, 0].mean()
+    for w, well in enumerate(c.wells):
+        if well.kind == cases.WELL_BHP_PROD:
+            x[w] = (3e-4 * rng.uniform(0.5, 1.5), 0.2 * rng.uniform(), 0.05 * rng.uniform(),
+                    pm - 300 * PSI)
+        else:
+            x[w] = (-2e-4 * rng.uniform(0.5, 1.5), x[w, 1], x[w, 2], pm + 300 * PSI)
+    return x
+
+
+def _state(c, seed):
+    if c.fluid.live:
+        rng = np.random.default_rng(seed)
+        n = c.n_active
+        y = np.empty((n, 3))
+        y[:, 0] = rng.uniform(3300, 3700, n) * PSI
+        y[:, 1] = rng.uniform(0.15, 0.5, n)
+        y[:, 2] = rng.uniform(0.3, 0.9, n) * c.fluid.rs_c * y[:, 0]   # undersaturated
+        return y
+    return cases.random_state(c, seed=seed)
+
+
+def _cols(A):
+    return np.abs(A).max(axis=0) + 1e-300
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_wells_linearization_parity(opm, name):
+    c = CASES[name]()
+    g = opm.GpuModel(c)
+    m = oracle.Model(c)
+    y = _state(c, 3)
+    y0 = _state(c, 4)
+    x0 = m.well_state().copy()
+    x = _well_state(c, m, y, 5)
+    acc0 = m.accumulation(y0)
+    m.set_well_state(x0)
+    m.well_storage_start()
+    m.set_well_state(x)
+    st, R, J = m.assemble(y, acc0, 2 * DAY)
+    st, Rw, B, C, D = m.well_system(y, 2 * DAY)
+    assert st == 0
+    g.set_well_state(x)
+    Rg, Jg, Rwg, Bg, Cg, Dg = (t.cpu().numpy() for t in g.assemble_wells(
+        g.state(y), g.state(acc0), x0, 2 * DAY))
+    assert (np.abs(Rg - R) / _cols(R)).max() <= 1e-11
+    Jf = J.reshape(-1, 9)
+    assert (np.abs(Jg.reshape(-1, 9) - Jf) / _cols(Jf)).max() <= 1e-11
+    assert (np.abs(Rwg - Rw) / _cols(Rw)).max() <= 1e-11
+    Bf, Cf = B.reshape(-1, 12), C.reshape(-1, 12)
+    assert (np.abs(Bg.reshape(-1, 12) - Bf) / _cols(Bf)).max() <= 1e-11
+    assert (np.abs(Cg.reshape(-1, 12) - Cf) / _cols(Cf)).max() <= 1e-11
+    for w in range(m.nw):   # D row by row (rows have different units)
+        rs = np.abs(D[w]).max(axis=1, keepdims=True) + 1e-300
+        assert (np.abs(Dg[w] - D[w]) / rs).max() <= 1e-11
+
+
+def _compare_run(c, gstates, gwells, ostates, owells, what):
+    for s, (yg, xg, yo, xo) in enumerate(zip(gstates, gwells, ostates, owells)):
+        ep = np.abs(yg[:, 0] - yo[:, 0]).max() / np.abs(yo[:, 0]).max()
+        es = np.abs(yg[:, 1:] - yo[:, 1:]).max() if not c.fluid.live else \
+            np.abs(yg[:, 1] - yo[:, 1]).max()
+        assert ep <= 1e-6 and es <= 1e-6, f"{what} step {s}: p {ep:.2e} s {es:.2e}"
+        eb = np.abs(xg[:, 3] - xo[:, 3]).max() / np.abs(xo[:, 3]).max()
+        eq = np.abs(xg[:, 0] - xo[:, 0]).max() / (np.abs(xo[:, 0]).max() + 1e-300)
+        ef = np.abs(xg[:, 1:3] - xo[:, 1:3]).max()
+        assert eb <= 1e-6 and eq <= 1e-6 and ef <= 1e-6, \
+            f"{what} step {s} wells: bhp {eb:.2e} Q_t {eq:.2e} F {ef:.2e}"
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_wells_run_c1(opm, precision):
+    c = _c1()
+    g = opm.GpuModel(c)
+    m = oracle.Model(c)
+    ostates, oreps = m.run()
+    y, gstates, greps = g.run(opts=opm.default_opts(c, precision=precision))
+    _compare_run(c, gstates, g.run_well_states, ostates, m.run_well_states, "C1")
+    # the gas injector holds its surface rate (g_g = 0.01: Q_g = F_g Q_t / 0.01)
+    x = g.run_well_states[-1]
+    assert abs(x[0, 2] * x[0, 0] / 0.01 + c.wells[0].target) <= 1e-8 * c.wells[0].target
+    for rg, ro in zip(greps, oreps):
+        assert abs(rg["newton_its"] - ro["newton_its"]) <= 1
+
+
+@pytest.mark.parametrize("blk", [None, (4, 4, 5)], ids=["single", "blocks"])
+def test_wells_run_c6_live(opm, blk):
+    """Multi-connection standard wells with live oil (free gas appears at
+    the producer), single and block ILU0 (the fused block path)."""
+    c = _c6()
+    g = opm.GpuModel(c, ilu_blocks=blk)
+    m = oracle.Model(c)
+    ostates, oreps = m.run(n_steps=10)
+    y, gstates, greps = g.run(n_steps=10)
+    for s, (yg, mg, yo, mo) in enumerate(zip(gstates, g.run_meanings, ostates, m.run_meanings)):
+        rs = c.fluid.rs_c
+        sg_g, sg_o = np.where(mg == 0, yg[:, 2], 0.0), np.where(mo == 0, yo[:, 2], 0.0)
+        r_g = np.where(mg == 0, rs * yg[:, 0], yg[:, 2])
+        r_o = np.where(mo == 0, rs * yo[:, 0], yo[:, 2])
+        assert np.abs(sg_g - sg_o).max() <= 1e-6 and \
+            np.abs(r_g - r_o).max() <= 1e-6 * np.abs(r_o).max(), f"step {s}"
+    _compare_run(c, gstates, g.run_well_states, ostates, m.run_well_states, "C6")
+
+
+def test_wells_rejections(opm):
+    import ctypes
+    c = _c1()
+    g = opm.GpuModel(c)
+    y = g.initial_state()
+    o = opm.default_opts(c, krylov=opm.KRYLOV_GMRES)
+    with pytest.raises(opm.OpmError):   # GMRes with standard wells: OPM_EINVAL
+        g.newton_step(y, g.initial_state(), DAY, o)
+    L = opm._ensemble_lib()
+    members = (opm.Problem * 1)(g.pb)
+    ys = (ctypes.c_void_p * 1)(y.data_ptr())
+    nb = L.opm_ensemble_bytes(members, 1, 0)
+    ens = torch.empty(max(nb, 256), dtype=torch.uint8, device=g.dev)
+    assert L.opm_ensemble_prepare(members, ys, 1, 0, ens.data_ptr(), nb) == opm.EINVAL
