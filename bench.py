@@ -564,6 +564,9 @@ def main():
     ap.add_argument("--krylov", choices=["bicgstab", "gmres"], default="bicgstab",
                     help="Newton's linear solver (c2)")
     ap.add_argument("--restart", type=int, default=30, help="GMRes restart length")
+    ap.add_argument("--wells", choices=["simplified", "standard"], default="simplified",
+                    help="c2 / c6-live: fixed-source wells, or standard wells with their own "
+                         "unknowns solved by the Schur complement")
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--kernel-grid", default="100x100x50",
                     help="grid of the c5-kernels table (C5: 100x100x50; 200x200x50 is the 2M-cell "
@@ -606,6 +609,8 @@ def main():
     else:
         case = cases.config2()
         workload = "24x25x15 waterflood, 9000 cells, 10-day implicit steps"
+    if args.wells == "standard":
+        case.standard_wells = True
     opts = opm.default_opts(case, precision=args.precision)
     if args.krylov == "gmres":
         opts.krylov, opts.restart = opm.KRYLOV_GMRES, args.restart
@@ -745,6 +750,8 @@ def main():
                    "newton_tol_cnv": case.tol_cnv, "lin_rtol": case.lin_rtol,
                    "precision": "fp64" if args.precision == 0 else "mixed",
                    "krylov": "BiCGStab" if args.krylov == "bicgstab" else f"GMRes({args.restart})",
+                   "wells": ("standard wells (Q_t, F_w, F_g, p_bhp per well; Schur complement)"
+                             if args.wells == "standard" else "fixed sources / BHP sinks"),
                    "preconditioner": precond},
         "roofline": roofline,
         "breakdown": {
@@ -767,6 +774,8 @@ def main():
         m = oracle.Model(case)
         yo = case.initial_state()
         m.set_meaning(case.initial_meaning())
+        if case.standard_wells:
+            m.set_well_state(case.standard_well_init()[1])
         c_cni, c_wall, c_steps, passes = 0.0, 0.0, 0, 0
         while c_wall < args.cpu_seconds:
             t1 = time.perf_counter()
@@ -779,6 +788,8 @@ def main():
             if c_steps % len(case.report_dt) == 0:   # schedule done: start it again
                 yo = case.initial_state()
                 m.set_meaning(case.initial_meaning())
+                if case.standard_wells:
+                    m.set_well_state(case.standard_well_init()[1])
                 passes += 1
         line["cpu_baseline"] = {"value": round(c_cni / c_wall, 1), "unit": "cell-Newton-iterations/s",
                                 "cores": 1, "kind": "oracle",
