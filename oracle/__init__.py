@@ -39,7 +39,8 @@ class Opts(ctypes.Structure):
                 ("ds_max", ctypes.c_double), ("dp_max_rel", ctypes.c_double),
                 ("lin_rtol", ctypes.c_double), ("max_newton", ctypes.c_int),
                 ("lin_maxit", ctypes.c_int), ("max_cuts", ctypes.c_int),
-                ("krylov", ctypes.c_int), ("restart", ctypes.c_int)]
+                ("krylov", ctypes.c_int), ("restart", ctypes.c_int),
+                ("precond", ctypes.c_int), ("pad", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -122,6 +123,20 @@ def lib(path: Optional[str] = None):
                                       ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       _dp, _dp]
         L.ora_schur_solve.restype = ctypes.c_int
+        vp = ctypes.c_void_p
+        L.ora_cpr_setup.argtypes = [vp, _dp, ctypes.POINTER(vp)]
+        L.ora_cpr_setup.restype = ctypes.c_int
+        L.ora_cpr_destroy.argtypes = [vp]
+        L.ora_cpr_levels.argtypes = [vp]
+        L.ora_cpr_levels.restype = ctypes.c_int
+        L.ora_cpr_level_size.argtypes = [vp, ctypes.c_int, _ip, _ip]
+        L.ora_cpr_level.argtypes = [vp, ctypes.c_int, _ip, _ip, _dp, _ip]
+        L.ora_cpr_weights.argtypes = [vp, _dp]
+        L.ora_cpr_vcycle.argtypes = [vp, _dp, _dp]
+        L.ora_cpr_apply.argtypes = [vp, vp, _dp, _dp, _dp, _dp]
+        L.ora_bicgstab_cpr.argtypes = [vp, _dp, _dp, vp, _dp, _dp, ctypes.c_double, ctypes.c_int,
+                                       _dp, _dp]
+        L.ora_bicgstab_cpr.restype = ctypes.c_int
         L.ora_set_meaning.argtypes = [ctypes.c_void_p, _u8p]
         L.ora_set_meaning.restype = ctypes.c_int
         L.ora_get_meaning.argtypes = [ctypes.c_void_p, _u8p]
@@ -141,7 +156,7 @@ def _i(a: np.ndarray):
 
 def default_opts(case=None, **kw) -> Opts:
     o = Opts(tol_cnv=1e-8, tol_mb=1e-11, ds_max=0.2, dp_max_rel=0.3, lin_rtol=1e-6,
-             max_newton=20, lin_maxit=500, max_cuts=8, krylov=0, restart=30)
+             max_newton=20, lin_maxit=500, max_cuts=8, krylov=0, restart=30, precond=0)
     if case is not None:
         o.tol_cnv, o.tol_mb, o.lin_rtol = case.tol_cnv, case.tol_mb, case.lin_rtol
     for k, v in kw.items():
@@ -224,6 +239,10 @@ class Model:
         well = np.zeros(max(self.nc, 1), np.int32)
         self.L.ora_conns(self.h, _i(cell), _d(wi), _i(well))
         return cell[:self.nc], wi[:self.nc], well[:self.nc]
+
+    # ---- CPR-AMG (two-stage preconditioner with an aggregation AMG)
+    def cpr(self, J) -> "Cpr":
+        return Cpr(self, J)
 
     # ---- state: meaning of the third variable per cell (0 s_g, 1 r_go)
     def set_meaning(self, mean):
@@ -376,6 +395,67 @@ class Model:
                 self.run_well_states.append(self.well_state().copy())
             reps.append(rep.as_dict())
         return states, reps
+
+
+class Cpr:
+    """The oracle's CPR-AMG hierarchy for one Jacobian (owns the C handle)."""
+
+    def __init__(self, model: Model, J):
+        self.m = model
+        self.L = model.L
+        self.J = np.ascontiguousarray(J, dtype=np.float64)
+        h = ctypes.c_void_p()
+        st = self.L.ora_cpr_setup(model.h, _d(self.J), ctypes.byref(h))
+        if st != OK:
+            raise ValueError(f"oracle: CPR setup failed ({st})")
+        self.h = h
+        self.nl = self.L.ora_cpr_levels(h)
+
+    def __del__(self):
+        try:
+            self.L.ora_cpr_destroy(self.h)
+        except Exception:
+            pass
+
+    def level(self, l):
+        """(rp, ci, a, agg) of level l (agg None on the coarsest)."""
+        n, nnz = ctypes.c_int(), ctypes.c_int()
+        self.L.ora_cpr_level_size(self.h, l, ctypes.byref(n), ctypes.byref(nnz))
+        n, nnz = n.value, nnz.value
+        rp = np.zeros(n + 1, np.int32)
+        ci = np.zeros(max(nnz, 1), np.int32)
+        a = np.zeros(max(nnz, 1))
+        agg = np.zeros(max(n, 1), np.int32)
+        last = l == self.nl - 1
+        self.L.ora_cpr_level(self.h, l, _i(rp), _i(ci), _d(a),
+                             ctypes.cast(None, _ip) if last else _i(agg))
+        return rp, ci[:nnz], a[:nnz], (None if last else agg[:n])
+
+    def weights(self):
+        w = np.zeros((self.m.n, 3))
+        self.L.ora_cpr_weights(self.h, _d(w))
+        return w
+
+    def vcycle(self, b):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros(self.m.n)
+        self.L.ora_cpr_vcycle(self.h, _d(b), _d(x))
+        return x
+
+    def apply(self, F, r):
+        z = np.zeros((self.m.n, 3))
+        self.L.ora_cpr_apply(self.m.h, self.h, _d(self.J), _d(np.ascontiguousarray(F)),
+                             _d(np.ascontiguousarray(r, dtype=np.float64)), _d(z))
+        return z
+
+    def bicgstab(self, F, b, rtol=1e-6, maxit=500):
+        x = np.zeros((self.m.n, 3))
+        its = ctypes.c_double()
+        rr = ctypes.c_double()
+        st = self.L.ora_bicgstab_cpr(self.m.h, _d(self.J), _d(np.ascontiguousarray(F)), self.h,
+                                     _d(np.ascontiguousarray(b, dtype=np.float64)), _d(x), rtol,
+                                     maxit, ctypes.byref(its), ctypes.byref(rr))
+        return st, x, its.value, rr.value
 
 
 def dense_solve(A: np.ndarray, b: np.ndarray, lib_path: Optional[str] = None) -> np.ndarray:

@@ -735,6 +735,244 @@ void ora_spmv(const ora_model* m, const double* J, const double* x, double* y) {
 }
 
 
+
+/* -------------------------------------------------- CPR-AMG (sec. 2.3.1)
+ * Two-stage constrained-pressure-residual preconditioner.  Stage 1: the
+ * quasi-IMPES weights w_i solve D_i^T w_i = e_p (D_i the diagonal block of
+ * row i), the pressure system is (A_p)_ij = w_i^T A_ij e_p, and one V(1,1)
+ * cycle of an aggregation AMG approximates A_p^{-1} (w^T r).  Stage 2: the
+ * (block-)ILU(0) of the whole system on the remaining residual,
+ * z = x1 + M_ILU^{-1} (r - A x1), x1 = e_p (pressure correction).
+ * AMG: unsmoothed aggregation with geometric 2x2x2 aggregates of the
+ * level's lattice (coarse unknown = a coarse box holding at least one
+ * unknown, natural order), Galerkin coarse matrices A_c = P^T A P with the
+ * piecewise-constant P, damped Jacobi (omega = 2/3) before and after the
+ * coarse correction, dense LU on the coarsest level (<= 64 unknowns or
+ * no further coarsening). */
+#define ORA_AMG_MAX 12
+#define ORA_AMG_COARSE 64
+static const double kJacobiOmega = 2.0 / 3.0;
+
+struct ora_cpr {
+  int nl;
+  int n[ORA_AMG_MAX];
+  int dims[ORA_AMG_MAX][3];
+  int* box[ORA_AMG_MAX];    /* lattice box of each unknown */
+  int* rp[ORA_AMG_MAX];
+  int* ci[ORA_AMG_MAX];
+  double* a[ORA_AMG_MAX];
+  int* agg[ORA_AMG_MAX];    /* unknown of level l -> unknown of level l + 1 */
+  double* w;                /* [n][3] */
+};
+
+static void cpr_free(ora_cpr* c);
+void ora_cpr_destroy(ora_cpr* c) {
+  if (c) cpr_free(c);
+}
+
+static void cpr_free(ora_cpr* c) {
+  for (int l = 0; l < ORA_AMG_MAX; ++l) {
+    free(c->box[l]); free(c->rp[l]); free(c->ci[l]); free(c->a[l]); free(c->agg[l]);
+  }
+  free(c->w);
+  free(c);
+}
+
+/* Coarse matrix of level l + 1: sum of the level-l entries between the
+ * aggregates (sparse accumulation row by row, columns ascending). */
+static void galerkin(ora_cpr* c, int l) {
+  const int nf = c->n[l], nc = c->n[l + 1];
+  int* cnt = (int*)calloc((size_t)nc + 1, sizeof(int));
+  int* mark = (int*)malloc(sizeof(int) * nc);
+  double* acc = (double*)calloc((size_t)nc, sizeof(double));
+  for (int J = 0; J < nc; ++J) mark[J] = -1;
+  /* children of each coarse unknown */
+  int* chp = (int*)calloc((size_t)nc + 1, sizeof(int));
+  int* ch = (int*)malloc(sizeof(int) * (nf + 1));
+  for (int i = 0; i < nf; ++i) chp[c->agg[l][i] + 1]++;
+  for (int I = 0; I < nc; ++I) chp[I + 1] += chp[I];
+  int* fill = (int*)malloc(sizeof(int) * (nc + 1));
+  memcpy(fill, chp, sizeof(int) * nc);
+  for (int i = 0; i < nf; ++i) ch[fill[c->agg[l][i]]++] = i;
+  /* pass 1: row lengths */
+  for (int I = 0; I < nc; ++I) {
+    for (int t = chp[I]; t < chp[I + 1]; ++t) {
+      const int i = ch[t];
+      for (int q = c->rp[l][i]; q < c->rp[l][i + 1]; ++q) {
+        const int J = c->agg[l][c->ci[l][q]];
+        if (mark[J] != I) { mark[J] = I; cnt[I + 1]++; }
+      }
+    }
+  }
+  for (int I = 0; I < nc; ++I) cnt[I + 1] += cnt[I];
+  c->rp[l + 1] = cnt;
+  c->ci[l + 1] = (int*)malloc(sizeof(int) * (cnt[nc] + 1));
+  c->a[l + 1] = (double*)malloc(sizeof(double) * (cnt[nc] + 1));
+  for (int J = 0; J < nc; ++J) mark[J] = -1;
+  for (int I = 0; I < nc; ++I) {
+    int len = 0;
+    int* cols = c->ci[l + 1] + cnt[I];
+    for (int t = chp[I]; t < chp[I + 1]; ++t) {
+      const int i = ch[t];
+      for (int q = c->rp[l][i]; q < c->rp[l][i + 1]; ++q) {
+        const int J = c->agg[l][c->ci[l][q]];
+        if (mark[J] != I) { mark[J] = I; cols[len++] = J; acc[J] = 0.0; }
+        acc[J] += c->a[l][q];
+      }
+    }
+    for (int u = 1; u < len; ++u) {   /* columns ascending */
+      int v = cols[u], r = u - 1;
+      while (r >= 0 && cols[r] > v) { cols[r + 1] = cols[r]; --r; }
+      cols[r + 1] = v;
+    }
+    for (int u = 0; u < len; ++u) c->a[l + 1][cnt[I] + u] = acc[cols[u]];
+  }
+  free(mark); free(acc); free(chp); free(ch); free(fill);
+}
+
+/* Build the hierarchy for the Jacobian J (weights, A_p and coarse levels). */
+int ora_cpr_setup(const ora_model* m, const double* J, ora_cpr** out) {
+  ora_cpr* c = (ora_cpr*)calloc(1, sizeof(ora_cpr));
+  const int n = m->n;
+  c->w = (double*)malloc(sizeof(double) * 3 * (n + 1));
+  /* quasi-IMPES weights: D_i^T w_i = e_p */
+  for (int i = 0; i < n; ++i) {
+    const double* Dg = J + 9 * find_block(m, i, i);
+    double T[9] = {Dg[0], Dg[3], Dg[6], Dg[1], Dg[4], Dg[7], Dg[2], Dg[5], Dg[8]};
+    double e[3] = {1.0, 0.0, 0.0};
+    if (ora_dense_solve(3, T, e) != ORA_OK) { cpr_free(c); return ORA_ESINGULAR; }
+    for (int a = 0; a < 3; ++a) c->w[3 * i + a] = e[a];
+  }
+  /* level 0: the pressure system on the block pattern */
+  c->n[0] = n;
+  c->dims[0][0] = m->nx; c->dims[0][1] = m->ny; c->dims[0][2] = m->nz;
+  c->rp[0] = (int*)malloc(sizeof(int) * (n + 1));
+  memcpy(c->rp[0], m->row_ptr, sizeof(int) * (n + 1));
+  c->ci[0] = (int*)malloc(sizeof(int) * (m->nnzb + 1));
+  memcpy(c->ci[0], m->col_idx, sizeof(int) * m->nnzb);
+  c->a[0] = (double*)malloc(sizeof(double) * (m->nnzb + 1));
+  c->box[0] = (int*)malloc(sizeof(int) * (n + 1));
+  memcpy(c->box[0], m->cell_box, sizeof(int) * n);
+  for (int i = 0; i < n; ++i)
+    for (int q = m->row_ptr[i]; q < m->row_ptr[i + 1]; ++q) {
+      double v = 0.0;
+      for (int a = 0; a < 3; ++a) v += c->w[3 * i + a] * J[9 * q + 3 * a];
+      c->a[0][q] = v;
+    }
+  /* coarse levels: 2x2x2 boxes of the level's lattice */
+  int l = 0;
+  while (c->n[l] > ORA_AMG_COARSE && l + 1 < ORA_AMG_MAX) {
+    const int* d = c->dims[l];
+    if (d[0] == 1 && d[1] == 1 && d[2] == 1) break;
+    int cd[3] = {(d[0] + 1) / 2, (d[1] + 1) / 2, (d[2] + 1) / 2};
+    const int nb = cd[0] * cd[1] * cd[2];
+    int* idx = (int*)malloc(sizeof(int) * nb);
+    for (int b = 0; b < nb; ++b) idx[b] = -1;
+    int* parent = (int*)malloc(sizeof(int) * (c->n[l] + 1));
+    for (int i = 0; i < c->n[l]; ++i) {
+      const int b = c->box[l][i];
+      const int x = b % d[0], y = (b / d[0]) % d[1], z = b / (d[0] * d[1]);
+      parent[i] = x / 2 + cd[0] * (y / 2 + cd[1] * (z / 2));
+      idx[parent[i]] = 0;
+    }
+    int nc = 0;
+    for (int b = 0; b < nb; ++b)
+      if (idx[b] >= 0) idx[b] = nc++;
+    c->agg[l] = (int*)malloc(sizeof(int) * (c->n[l] + 1));
+    for (int i = 0; i < c->n[l]; ++i) c->agg[l][i] = idx[parent[i]];
+    c->box[l + 1] = (int*)malloc(sizeof(int) * (nc + 1));
+    for (int b = 0; b < nb; ++b)
+      if (idx[b] >= 0) c->box[l + 1][idx[b]] = b;
+    c->n[l + 1] = nc;
+    memcpy(c->dims[l + 1], cd, sizeof(cd));
+    free(idx); free(parent);
+    galerkin(c, l);
+    ++l;
+  }
+  c->nl = l + 1;
+  *out = c;
+  return ORA_OK;
+}
+
+static void csr_mv(const ora_cpr* c, int l, const double* x, double* y) {
+  for (int i = 0; i < c->n[l]; ++i) {
+    double s = 0.0;
+    for (int q = c->rp[l][i]; q < c->rp[l][i + 1]; ++q) s += c->a[l][q] * x[c->ci[l][q]];
+    y[i] = s;
+  }
+}
+
+static double csr_diag(const ora_cpr* c, int l, int i) {
+  for (int q = c->rp[l][i]; q < c->rp[l][i + 1]; ++q)
+    if (c->ci[l][q] == i) return c->a[l][q];
+  return 0.0;
+}
+
+/* x = V(1,1)-cycle approximation of A_l^{-1} b (x starts at zero). */
+static void vcycle(const ora_cpr* c, int l, const double* b, double* x) {
+  const int n = c->n[l];
+  if (l == c->nl - 1) {   /* coarsest: dense LU */
+    double* A = (double*)calloc((size_t)n * n + 1, sizeof(double));
+    for (int i = 0; i < n; ++i) {
+      for (int q = c->rp[l][i]; q < c->rp[l][i + 1]; ++q) A[(size_t)i * n + c->ci[l][q]] = c->a[l][q];
+      x[i] = b[i];
+    }
+    ora_dense_solve(n, A, x);
+    free(A);
+    return;
+  }
+  const int nc = c->n[l + 1];
+  double* r = (double*)malloc(sizeof(double) * (n + 1));
+  double* bc = (double*)calloc((size_t)nc + 1, sizeof(double));
+  double* xc = (double*)calloc((size_t)nc + 1, sizeof(double));
+  for (int i = 0; i < n; ++i) x[i] = kJacobiOmega * b[i] / csr_diag(c, l, i);   /* pre-smooth */
+  csr_mv(c, l, x, r);
+  for (int i = 0; i < n; ++i) bc[c->agg[l][i]] += b[i] - r[i];   /* restrict the residual */
+  vcycle(c, l + 1, bc, xc);
+  for (int i = 0; i < n; ++i) x[i] += xc[c->agg[l][i]];   /* prolong */
+  csr_mv(c, l, x, r);
+  for (int i = 0; i < n; ++i) x[i] += kJacobiOmega * (b[i] - r[i]) / csr_diag(c, l, i);   /* post-smooth */
+  free(r); free(bc); free(xc);
+}
+
+int ora_cpr_levels(const ora_cpr* c) { return c->nl; }
+
+void ora_cpr_level_size(const ora_cpr* c, int l, int* n, int* nnz) {
+  *n = c->n[l];
+  *nnz = c->rp[l][c->n[l]];
+}
+
+void ora_cpr_level(const ora_cpr* c, int l, int* rp, int* ci, double* a, int* agg) {
+  memcpy(rp, c->rp[l], sizeof(int) * (c->n[l] + 1));
+  memcpy(ci, c->ci[l], sizeof(int) * c->rp[l][c->n[l]]);
+  memcpy(a, c->a[l], sizeof(double) * c->rp[l][c->n[l]]);
+  if (agg && l + 1 < c->nl) memcpy(agg, c->agg[l], sizeof(int) * c->n[l]);
+}
+
+void ora_cpr_weights(const ora_cpr* c, double* w) { memcpy(w, c->w, sizeof(double) * 3 * c->n[0]); }
+
+void ora_cpr_vcycle(const ora_cpr* c, const double* b, double* x) { vcycle(c, 0, b, x); }
+
+/* z = CPR(r): pressure stage then (block-)ILU(0) stage on the rest. */
+static void cpr_apply(const ora_model* m, const ora_cpr* c, const double* J, const double* F,
+                      const double* r, double* z) {
+  const int n = m->n;
+  double* bp = (double*)malloc(sizeof(double) * (n + 1));
+  double* xp = (double*)malloc(sizeof(double) * (n + 1));
+  double* x1 = (double*)calloc(3 * (size_t)n + 1, sizeof(double));
+  double* r2 = (double*)malloc(sizeof(double) * (3 * n + 1));
+  double* z2 = (double*)malloc(sizeof(double) * (3 * n + 1));
+  for (int i = 0; i < n; ++i)
+    bp[i] = c->w[3 * i] * r[3 * i] + c->w[3 * i + 1] * r[3 * i + 1] + c->w[3 * i + 2] * r[3 * i + 2];
+  vcycle(c, 0, bp, xp);
+  for (int i = 0; i < n; ++i) x1[3 * i] = xp[i];
+  ora_spmv(m, J, x1, r2);
+  for (int k = 0; k < 3 * n; ++k) r2[k] = r[k] - r2[k];
+  ora_ilu0_apply(m, F, r2, z2);
+  for (int k = 0; k < 3 * n; ++k) z[k] = x1[k] + z2[k];
+  free(bp); free(xp); free(x1); free(r2); free(z2);
+}
+
 /* ---------------------------------------------- standard wells (sec. 2.2.1)
  * Each well has the unknowns x_w = (Q_t, F_w, F_g, p_bhp) (eq.
  * weighted_total_rate): the weighted total surface rate (production
@@ -878,7 +1116,16 @@ typedef struct {
   const double* B;      /* NULL without standard wells */
   const double* C;
   const double* Dinv;   /* [nw][4][4] */
+  const ora_cpr* cpr;   /* NULL: the (block-)ILU(0) preconditioner alone */
 } oper;
+
+/* The preconditioner: (block-)ILU(0), or CPR with it as second stage. */
+static void prec_apply(const oper* op, const double* F, const double* r, double* z) {
+  if (op->cpr)
+    cpr_apply(op->m, op->cpr, op->J, F, r, z);
+  else
+    ora_ilu0_apply(op->m, F, r, z);
+}
 
 static void op_apply(const oper* op, const double* x, double* y) {
   const ora_model* m = op->m;
@@ -914,13 +1161,39 @@ static int inv4(const double* A, double* X) {
 
 static int bicgstab_op(const oper* op, const double* F, const double* b, double* x, double rtol,
                        int maxit, double* its_out, double* relres_out);
+
+void ora_cpr_apply(const ora_model* m, const ora_cpr* c, const double* J, const double* F,
+                   const double* r, double* z) {
+  cpr_apply(m, c, J, F, r, z);
+}
+
+int ora_bicgstab_cpr(const ora_model* m, const double* J, const double* F, const ora_cpr* c,
+                     const double* b, double* x, double rtol, int maxit, double* its,
+                     double* relres) {
+  oper op = {m, J, NULL, NULL, NULL, c};
+  return bicgstab_op(&op, F, b, x, rtol, maxit, its, relres);
+}
+
 static int gmres_op(const oper* op, const double* F, const double* b, double* x, double rtol,
                     int maxit, int restart, double* its_out, double* relres_out);
+
+static int schur_solve(const ora_model* m, const double* J, const double* F, const double* B,
+                       const double* C, const double* D, const double* Rr, const double* Rw,
+                       double* xr, double* xw, double rtol, int maxit, int krylov, int restart,
+                       double* its, double* relres, const ora_cpr* cpr);
 
 int ora_schur_solve(const ora_model* m, const double* J, const double* F, const double* B,
                     const double* C, const double* D, const double* Rr, const double* Rw,
                     double* xr, double* xw, double rtol, int maxit, int krylov, int restart,
                     double* its, double* relres) {
+  return schur_solve(m, J, F, B, C, D, Rr, Rw, xr, xw, rtol, maxit, krylov, restart, its, relres,
+                     NULL);
+}
+
+static int schur_solve(const ora_model* m, const double* J, const double* F, const double* B,
+                       const double* C, const double* D, const double* Rr, const double* Rw,
+                       double* xr, double* xw, double rtol, int maxit, int krylov, int restart,
+                       double* its, double* relres, const ora_cpr* cpr) {
   const int N = 3 * m->n;
   double* Dinv = (double*)malloc(sizeof(double) * 16 * (m->nw + 1));
   double* b = (double*)malloc(sizeof(double) * N);
@@ -940,7 +1213,7 @@ int ora_schur_solve(const ora_model* m, const double* J, const double* F, const 
     }
   }
   {
-    oper op = {m, J, B, C, Dinv};
+    oper op = {m, J, B, C, Dinv, cpr};
     st = krylov == 1 ? gmres_op(&op, F, b, xr, rtol, maxit, restart, its, relres)
                      : bicgstab_op(&op, F, b, xr, rtol, maxit, its, relres);
   }
@@ -975,7 +1248,7 @@ static double dot(int n, const double* a, const double* b) {
 
 int ora_bicgstab(const ora_model* m, const double* J, const double* F, const double* b, double* x,
                  double rtol, int maxit, double* its_out, double* relres_out) {
-  oper op = {m, J, NULL, NULL, NULL};
+  oper op = {m, J, NULL, NULL, NULL, NULL};
   return bicgstab_op(&op, F, b, x, rtol, maxit, its_out, relres_out);
 }
 
@@ -1002,7 +1275,7 @@ static int bicgstab_op(const oper* op, const double* F, const double* b, double*
     if (fabs(rho) < 1e-300) { status = ORA_EBREAKDOWN; break; }
     double beta = (rho / rho0) * (alpha / omega);
     for (int k = 0; k < N; ++k) p[k] = r[k] + beta * (p[k] - omega * v[k]);
-    ora_ilu0_apply(m, F, p, ph);
+    prec_apply(op, F, p, ph);
     op_apply(op, ph, v);
     double rv = dot(N, rh, v);
     if (rv == 0.0) { status = ORA_EBREAKDOWN; break; }
@@ -1014,7 +1287,7 @@ static int bicgstab_op(const oper* op, const double* F, const double* b, double*
       its = it - 0.5; relres = snorm / bnorm; status = ORA_OK;
       break;
     }
-    ora_ilu0_apply(m, F, s, sh);
+    prec_apply(op, F, s, sh);
     op_apply(op, sh, t);
     double tt = dot(N, t, t);
     if (tt == 0.0) { status = ORA_EBREAKDOWN; break; }
@@ -1046,7 +1319,7 @@ done:
  * at the iteration cap, or on an exact (happy) breakdown h_{j+1,j} = 0. */
 int ora_gmres(const ora_model* m, const double* J, const double* F, const double* b, double* x,
               double rtol, int maxit, int restart, double* its_out, double* relres_out) {
-  oper op = {m, J, NULL, NULL, NULL};
+  oper op = {m, J, NULL, NULL, NULL, NULL};
   return gmres_op(&op, F, b, x, rtol, maxit, restart, its_out, relres_out);
 }
 
@@ -1082,7 +1355,7 @@ static int gmres_op(const oper* op, const double* F, const double* b, double* x,
     int k_used = 0, done_cycle = 0;
     for (int j = 0; j < restart && its < maxit; ++j) {
       double* vj = V + (size_t)j * N;
-      ora_ilu0_apply(m, F, vj, z);
+      prec_apply(op, F, vj, z);
       op_apply(op, z, w);
       for (int i = 0; i <= j; ++i) {
         const double* vi = V + (size_t)i * N;
@@ -1124,7 +1397,7 @@ static int gmres_op(const oper* op, const double* F, const double* b, double* x,
       const double* vi = V + (size_t)i * N;
       for (int k = 0; k < N; ++k) w[k] += y[i] * vi[k];
     }
-    ora_ilu0_apply(m, F, w, z);
+    prec_apply(op, F, w, z);
     for (int k = 0; k < N; ++k) x[k] += z[k];
     if (done_cycle) { status = ORA_OK; break; }
   }
@@ -1214,14 +1487,19 @@ int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double 
     for (int k = 0; k < N; ++k) b[k] = -R[k];
     for (int k = 0; k < 4 * nw; ++k) bw[k] = -Rw[k];
     double its = 0.0, rr = 0.0;
+    ora_cpr* cpr = NULL;
+    if (o->precond == 1 && (st = ora_cpr_setup(m, J, &cpr)) != ORA_OK) { status = st; break; }
     t0 = now_s();
-    if (m->std_wells)
-      st = ora_schur_solve(m, J, F, Bw, Cw, Dw, b, bw, dx, dxw, o->lin_rtol, o->lin_maxit,
-                           o->krylov, o->restart, &its, &rr);
-    else
+    if (m->std_wells) {
+      st = schur_solve(m, J, F, Bw, Cw, Dw, b, bw, dx, dxw, o->lin_rtol, o->lin_maxit, o->krylov,
+                       o->restart, &its, &rr, cpr);
+    } else {
+      oper op = {m, J, NULL, NULL, NULL, cpr};
       st = o->krylov == 1
-               ? ora_gmres(m, J, F, b, dx, o->lin_rtol, o->lin_maxit, o->restart, &its, &rr)
-               : ora_bicgstab(m, J, F, b, dx, o->lin_rtol, o->lin_maxit, &its, &rr);
+               ? gmres_op(&op, F, b, dx, o->lin_rtol, o->lin_maxit, o->restart, &its, &rr)
+               : bicgstab_op(&op, F, b, dx, o->lin_rtol, o->lin_maxit, &its, &rr);
+    }
+    ora_cpr_destroy(cpr);
     rep->t_krylov += now_s() - t0;
     rep->lin_its += its;
     if (st != ORA_OK) { status = st; break; }

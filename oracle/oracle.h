@@ -75,6 +75,8 @@ typedef struct ora_opts {
   int max_cuts;       /* time-step halvings allowed per report step         */
   int krylov;         /* 0 BiCGStab, 1 restarted GMRes                      */
   int restart;        /* GMRes restart length                               */
+  int precond;        /* 0 (block-)ILU(0), 1 CPR-AMG with it as stage two   */
+  int pad;
 } ora_opts;
 
 typedef struct ora_report {
@@ -193,6 +195,33 @@ int ora_schur_solve(const ora_model* m, const double* J, const double* F, const 
                     const double* C, const double* D, const double* Rr, const double* Rw,
                     double* xr, double* xw, double rtol, int maxit, int krylov, int restart,
                     double* its, double* relres);
+
+/* CPR-AMG (sec. 2.3.1): the two-stage constrained-pressure-residual
+ * preconditioner with an aggregation AMG for the pressure stage.  Setup for
+ * a Jacobian J: quasi-IMPES weights (D_i^T w_i = e_p, D_i the diagonal
+ * block), pressure matrix (A_p)_ij = w_i^T A_ij e_p on the block pattern,
+ * coarse levels by geometric 2x2x2 aggregation of each level's lattice with
+ * Galerkin matrices P^T A P (P piecewise constant) down to <= 64 unknowns.
+ * Application: one V(1,1) cycle (damped Jacobi, omega = 2/3; dense LU on the
+ * coarsest level) on w^T r, x1 = e_p x_p, then z = x1 + M_ILU^{-1}(r - A x1)
+ * with the (block-)ILU(0) factors F of A. */
+typedef struct ora_cpr ora_cpr;
+int ora_cpr_setup(const ora_model* m, const double* J, ora_cpr** out);
+void ora_cpr_destroy(ora_cpr* c);
+int ora_cpr_levels(const ora_cpr* c);
+void ora_cpr_level_size(const ora_cpr* c, int l, int* n, int* nnz);
+/* Level l's CSR matrix (rp [n+1], ci / a [nnz]) and, for l < levels - 1,
+ * its aggregation map agg [n] (may be NULL). */
+void ora_cpr_level(const ora_cpr* c, int l, int* rp, int* ci, double* a, int* agg);
+void ora_cpr_weights(const ora_cpr* c, double* w);
+/* x = one V(1,1) cycle on A_p x = b (x starts at zero). */
+void ora_cpr_vcycle(const ora_cpr* c, const double* b, double* x);
+void ora_cpr_apply(const ora_model* m, const ora_cpr* c, const double* J, const double* F,
+                   const double* r, double* z);
+/* Right-preconditioned BiCGStab with CPR (second stage: the factors F). */
+int ora_bicgstab_cpr(const ora_model* m, const double* J, const double* F, const ora_cpr* c,
+                     const double* b, double* x, double rtol, int maxit, double* its,
+                     double* relres);
 
 /* Dense LU with partial pivoting: solves A x = b in place (A [n][n] row-major
  * is overwritten).  Returns ORA_ESINGULAR on a zero pivot. */

@@ -1062,6 +1062,192 @@ def pin_std_controls_and_storage(lib_path=None):
         assert abs(x[1, 3] - 3000 * PSI) <= 1e-6 * 3000 * PSI
 
 
+# ---------------------------------------------------------------- CPR-AMG
+# Two-stage CPR preconditioner (sec. 2.3.1) with an aggregation AMG for the
+# pressure stage.
+def _cpr_system(case, lib_path, seed=1):
+    m = _model(case, lib_path)
+    y = cases.random_state(case, seed=seed)
+    st, R, J = m.assemble(y, m.accumulation(cases.random_state(case, seed=seed + 1)), 2 * DAY)
+    st, F = m.ilu0(J)
+    assert st == 0
+    return m, R, J, F
+
+
+def pin_cpr_weights_decouple(lib_path=None):
+    """Quasi-IMPES weights decouple the pressure in each cell's diagonal
+    block: w_i^T D_i = (1, 0, 0), and the pressure matrix holds w_i^T A_ij
+    applied to the pressure unit vector."""
+    c = _wells_case(3, 3, 2, seed=7)
+    m = _model(c, lib_path)
+    y = cases.random_state(c, seed=11)
+    st, R, J = m.assemble(y, m.accumulation(cases.random_state(c, seed=12)), 2 * DAY)
+    cp = m.cpr(J)
+    w = cp.weights()
+    rp, ci = m.pattern()
+    for i in range(m.n):
+        q = rp[i] + list(ci[rp[i]:rp[i + 1]]).index(i)
+        row = w[i] @ J[q]
+        tol = 1e-12 * 3 * np.abs(w[i]).max() * np.abs(J[q]).max()   # rounding of w^T D
+        assert abs(row[0] - 1.0) <= tol and np.all(np.abs(row[1:]) <= tol), (row, tol)
+    rp0, ci0, a0, _ = cp.level(0)
+    Ap = np.array([w[i] @ J[q][:, 0] for i in range(m.n) for q in range(rp[i], rp[i + 1])])
+    assert np.array_equal(rp0, rp) and np.array_equal(ci0, ci)
+    assert np.abs(a0 - Ap).max() <= 1e-12 * np.abs(Ap).max()
+
+
+def pin_cpr_galerkin_hierarchy(lib_path=None):
+    """Each coarse level is the Galerkin product P^T A P with the piecewise
+    constant P of geometric 2x2x2 aggregates of the level's lattice (coarse
+    unknowns numbered in natural order of the occupied coarse boxes),
+    rebuilt here from the cell coordinates and numpy."""
+    c = cases.box_case(9, 7, 5, seed=5, mask=cases.masked_mask(
+        np.random.default_rng(8), (5, 7, 9), 200), wells=[])
+    m = _model(c, lib_path)
+    y = cases.random_state(c, seed=3)
+    st, R, J = m.assemble(y, m.accumulation(cases.random_state(c, seed=4)), 2 * DAY)
+    cp = m.cpr(J)
+    assert cp.nl >= 2
+    boxes = m.geometry()["cell_box"]
+    dims = (c.nx, c.ny, c.nz)
+    for l in range(cp.nl - 1):
+        rp, ci, a, agg = cp.level(l)
+        n = len(rp) - 1
+        A = np.zeros((n, n))
+        for i in range(n):
+            A[i, ci[rp[i]:rp[i + 1]]] = a[rp[i]:rp[i + 1]]
+        cd = tuple((d + 1) // 2 for d in dims)
+        parent = [(b % dims[0]) // 2 + cd[0] * (((b // dims[0]) % dims[1]) // 2 +
+                                                 cd[1] * ((b // (dims[0] * dims[1])) // 2))
+                  for b in boxes]
+        occupied = sorted(set(parent))
+        index = {b: k for k, b in enumerate(occupied)}
+        want = np.array([index[b] for b in parent])
+        assert np.array_equal(agg, want)
+        P = np.zeros((n, len(occupied)))
+        P[np.arange(n), want] = 1.0
+        rpc, cic, ac, _ = cp.level(l + 1)
+        Ac = np.zeros((len(occupied), len(occupied)))
+        for I in range(len(occupied)):
+            Ac[I, cic[rpc[I]:rpc[I + 1]]] = ac[rpc[I]:rpc[I + 1]]
+        G = P.T @ A @ P
+        assert np.abs(Ac - G).max() <= 1e-12 * np.abs(G).max()
+        boxes, dims = occupied, cd
+    assert len(cp.level(cp.nl - 1)[0]) - 1 <= 64 or dims == (1, 1, 1)
+
+
+def pin_cpr_exact_second_stage(lib_path=None):
+    """With an exact second stage (ILU(0) of a 1-D chain is its LU), CPR is
+    the exact inverse whatever the pressure stage gives: z = x1 + A^{-1}(r -
+    A x1) = A^{-1} r; BiCGStab with CPR stops after half an iteration."""
+    c = cases.box_case(7, 1, 1, seed=3)
+    m, R, J, F = _cpr_system(c, lib_path)
+    cp = m.cpr(J)
+    z = cp.apply(F, -R)
+    xd = np.linalg.solve(_dense(m, J), -R.ravel()).reshape(-1, 3)
+    assert np.abs(z - xd).max() <= 1e-9 * np.abs(xd).max()
+    st, x, its, rr = cp.bicgstab(F, -R, rtol=1e-10)
+    assert st == 0 and its == 0.5
+
+
+def pin_cpr_vcycle_converges(lib_path=None):
+    """The V(1,1) cycle as a stationary iteration on the pressure system of a
+    heterogeneous 9000-cell system reduces the residual every cycle, below a
+    quarter after ten."""
+    c = cases.config2()
+    m, R, J, F = _cpr_system(c, lib_path)
+    cp = m.cpr(J)
+    rp, ci, a, _ = cp.level(0)
+    n = m.n
+
+    def Ap(x):
+        return np.array([a[rp[i]:rp[i + 1]] @ x[ci[rp[i]:rp[i + 1]]] for i in range(n)])
+
+    b = np.random.default_rng(0).standard_normal(n)
+    x = np.zeros(n)
+    prev = 1.0
+    for _ in range(10):
+        x = x + cp.vcycle(b - Ap(x))
+        rel = np.linalg.norm(b - Ap(x)) / np.linalg.norm(b)
+        assert rel < prev
+        prev = rel
+    assert prev <= 0.25, prev
+
+
+def pin_cpr_two_grid(lib_path=None):
+    """On a two-level hierarchy (108 cells, 18 coarse unknowns solved
+    exactly) the cycle is a Galerkin coarse-grid correction between two
+    damped Jacobi sweeps (omega = 2/3): undoing the post-sweep gives an
+    iterate x_mid whose difference from the pre-sweep omega D^-1 b lies in
+    range(P) and whose residual is orthogonal to range(P), P^T (b - A x_mid)
+    = 0.  Checked on a near-elliptic pressure system (a very long step)."""
+    wells = [Well("P", cases.WELL_BHP_PROD, [(5, 5, 2)], 3000 * PSI)]
+    c = cases.box_case(6, 6, 3, seed=4, wells=wells)
+    m = _model(c, lib_path)
+    y = cases.random_state(c, seed=2)
+    st, R, J = m.assemble(y, m.accumulation(y), 1e5 * DAY)
+    cp = m.cpr(J)
+    assert cp.nl == 2
+    rp, ci, a, agg = cp.level(0)
+    n = m.n
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, ci[rp[i]:rp[i + 1]]] = a[rp[i]:rp[i + 1]]
+    P = np.zeros((n, agg.max() + 1))
+    P[np.arange(n), agg] = 1.0
+    d = np.diag(A)
+    om = 2.0 / 3.0
+    b = np.random.default_rng(1).standard_normal(n)
+    x = cp.vcycle(b)
+    S = np.eye(n) - om * (A / d[:, None])
+    x_mid = np.linalg.solve(S, x - om * b / d)
+    x_pre = om * b / d
+    coef = np.linalg.lstsq(P, x_mid - x_pre, rcond=None)[0]
+    assert np.abs(P @ coef - (x_mid - x_pre)).max() <= 1e-9 * np.abs(x_mid).max()
+    orth = P.T @ (b - A @ x_mid)
+    assert np.abs(orth).max() <= 1e-9 * np.abs(P.T @ b).max(), np.abs(orth).max()
+
+
+def pin_cpr_fewer_iterations(lib_path=None):
+    """CPR reduces the linear iterations against the ILU(0) alone on the
+    Newton system of the 9000-cell waterflood's first step, and both solve
+    it to the tolerance."""
+    c = cases.config2()
+    m = _model(c, lib_path)
+    y0 = c.initial_state()
+    st, R, J = m.assemble(y0, m.accumulation(y0), c.report_dt[0])
+    y1 = y0.copy()
+    st, F = m.ilu0(J)
+    st, x, its_ilu, _ = m.bicgstab(J, F, -R, rtol=1e-6)
+    assert st == 0
+    # a system off equilibrium: one Newton update in
+    y1 = y0 + x
+    st, R, J = m.assemble(y1, m.accumulation(y0), c.report_dt[0])
+    st, F = m.ilu0(J)
+    st, x, its_ilu, _ = m.bicgstab(J, F, -R, rtol=1e-6)
+    cp = m.cpr(J)
+    st2, x2, its_cpr, _ = cp.bicgstab(F, -R, rtol=1e-6)
+    assert st == 0 and st2 == 0
+    assert its_cpr < its_ilu, (its_cpr, its_ilu)
+    res = -R - m.spmv(J, x2)
+    assert np.linalg.norm(res) <= 1e-6 * np.linalg.norm(R) * 1.0001
+
+
+def pin_cpr_newton(lib_path=None):
+    """The preconditioner changes the linear iterations, not the Newton
+    state: a report step with CPR matches the ILU(0) one to the Newton
+    tolerance and conserves mass."""
+    c = cases.config1()
+    m = _model(c, lib_path)
+    st, ya, ra = m.advance(c.initial_state(), c.report_dt[0])
+    st2, yb, rb = m.advance(c.initial_state(), c.report_dt[0],
+                            oracle.default_opts(c, precond=1))
+    assert st == 0 and st2 == 0
+    assert np.abs(ya[:, 0] - yb[:, 0]).max() <= 1e-8 * np.abs(ya[:, 0]).max()
+    assert np.abs(ya[:, 1:] - yb[:, 1:]).max() <= 1e-8
+    assert max(rb.mass_err) <= 1e-10
+
+
 ALL_PINS = [
     pin_series_transmissibility, pin_depth_pore_volume, pin_peaceman_worked_value,
     pin_compressibility, pin_darcy_flux_upwind, pin_hydrostatic_column, pin_pressure_block,
@@ -1073,5 +1259,8 @@ ALL_PINS = [
     pin_live_jacobian_fd, pin_live_conservation, pin_live_closed_cell,
     pin_live_dissolved_moves_with_oil, pin_live_hydrostatic_column, pin_live_depletion_1d,
     pin_std_schur_dense, pin_std_jacobian_fd, pin_std_simplified_limit,
-    pin_std_controls_and_storage,
+    pin_std_controls_and_storage, pin_cpr_weights_decouple, pin_cpr_galerkin_hierarchy,
+    pin_cpr_exact_second_stage, pin_cpr_vcycle_converges, pin_cpr_two_grid,
+    pin_cpr_fewer_iterations,
+    pin_cpr_newton,
 ]

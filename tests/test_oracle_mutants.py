@@ -95,6 +95,21 @@ MUTANTS = [
      "C[12 * q + 4 * a + k] = qr[a].d[k];"),
     ("std_bhp_control_sign", "R[3] = dsub(W.pb, dconst(m->well_target[w]));",
      "R[3] = dadd(W.pb, dconst(m->well_target[w]));"),
+    # CPR-AMG
+    ("cpr_weights_not_transposed",
+     "double T[9] = {Dg[0], Dg[3], Dg[6], Dg[1], Dg[4], Dg[7], Dg[2], Dg[5], Dg[8]};",
+     "double T[9] = {Dg[0], Dg[1], Dg[2], Dg[3], Dg[4], Dg[5], Dg[6], Dg[7], Dg[8]};"),
+    ("cpr_pressure_column_wrong", "for (int a = 0; a < 3; ++a) v += c->w[3 * i + a] * J[9 * q + 3 * a];",
+     "for (int a = 0; a < 3; ++a) v += c->w[3 * i + a] * J[9 * q + 3 * a + 1];"),
+    ("cpr_restrict_rhs_not_residual", "bc[c->agg[l][i]] += b[i] - r[i];",
+     "bc[c->agg[l][i]] += b[i];"),
+    ("cpr_prolongation_dropped", "x[i] += xc[c->agg[l][i]];   /* prolong */",
+     "x[i] += 0.0 * xc[c->agg[l][i]];   /* prolong */"),
+    ("cpr_post_smooth_sign", "x[i] += kJacobiOmega * (b[i] - r[i]) / csr_diag(c, l, i);",
+     "x[i] -= kJacobiOmega * (b[i] - r[i]) / csr_diag(c, l, i);"),
+    ("cpr_second_stage_on_r", "for (int k = 0; k < 3 * n; ++k) r2[k] = r[k] - r2[k];",
+     "for (int k = 0; k < 3 * n; ++k) r2[k] = r[k];"),
+    ("cpr_galerkin_drops_entries", "acc[J] += c->a[l][q];", "acc[J] = c->a[l][q];"),
     ("std_rate_control_sign",
      "R[3] = dadd(dscale(dmul(W.F[ph], W.Qt), 1.0 / kWellG[ph]), dconst(m->well_target[w]));",
      "R[3] = dsub(dscale(dmul(W.F[ph], W.Qt), 1.0 / kWellG[ph]), dconst(m->well_target[w]));"),
