@@ -118,6 +118,45 @@ def gmres_cycle_bytes(n: int, nnzb: int, m: int, apply_bytes: float) -> float:
     return total
 
 
+def cpr_apply_bytes(levels, n: int, nnzb: int, apply_bytes: float) -> float:
+    """Bytes of one CPR application as designed: b_0 = w^T r (w and r read,
+    b_0 written); per level above the coarsest the pre-smoothing (b, D read,
+    x written), the restricted residual (the level's CSR values, columns and
+    row pointers, b and x read, child lists read, the coarse b written), the
+    prolongation (aggregate map and coarse solution read, x read and
+    written) and the post-smoothing (CSR, D, b, x read, y written); the
+    coarsest level's inverse read; the second-stage residual (the pressure
+    column of J with its columns and row pointers, x_p, r read, r2 written);
+    the ILU(0) solve (apply_bytes); z_p += x_p."""
+    total = 56.0 * n
+    for l in range(len(levels) - 1):
+        nl, nnz = levels[l]
+        nc = levels[l + 1][0]
+        csr = 12.0 * nnz + 4.0 * (nl + 1)
+        total += 24.0 * nl                                # pre-smoothing
+        total += csr + 16.0 * nl + 4.0 * (nl + nc + 1) + 8.0 * nc   # restriction
+        total += 4.0 * nl + 8.0 * nc + 16.0 * nl          # prolongation
+        total += csr + 32.0 * nl                          # post-smoothing
+    nc = levels[-1][0]
+    total += 8.0 * nc * nc + 16.0 * nc
+    total += 28.0 * nnzb + 4.0 * (n + 1) + 8.0 * n + 48.0 * n   # second-stage residual
+    return total + apply_bytes + 24.0 * n
+
+
+def cpr_setup_bytes(levels, n: int, nnzb: int) -> float:
+    """Bytes of one CPR setup as designed: the diagonal blocks and the
+    pressure column of every block of J read with the pattern, weights,
+    level-0 values and diagonal written; per coarse level its gather lists
+    and the finer values read, its values and diagonal written; the
+    coarsest matrix read and its inverse written."""
+    total = 72.0 * n + 24.0 * nnzb + 4.0 * (n + 1) + 4.0 * n + 24.0 * n + 8.0 * nnzb + 8.0 * n
+    for l in range(1, len(levels)):
+        nl, nnz = levels[l]
+        total += 12.0 * levels[l - 1][1] + 4.0 * (nnz + 1) + 8.0 * nnz + 4.0 * nl + 8.0 * nl
+    nc, nnzc = levels[-1]
+    return total + 12.0 * nnzc + 8.0 * nc * nc
+
+
 def parse_blocks(spec, case):
     """--ilu-blocks: 'none' (single block), 'BXxBY' (columns over the full
     depth) or 'BXxBYxBZ'."""
@@ -506,6 +545,18 @@ def bench_kernels(args):
         gmres_cycle_bytes(n, g.nnzb, m, block_sweep_bytes_per_cell(0) * n),
         f"one GMRes({m}) cycle: {m} x (k_apply_blocks + k_gm_spmv + k_gm_dots + k_gm_cgs1 + "
         "k_gm_cgs2 + k_gm_rotate) + start and finish kernels (FP64 block ILU0)")
+    # CPR-AMG on the same system (FP64 block ILU0 as its second stage)
+    cpr_k, cpr_st = gb.cpr_setup(Jb_)
+    lv = gb.amg_levels()
+    kern["cpr_setup"] = (
+        lambda: L.opm_cpr_setup(pbb, sp(Jb_), sp(cpr_k), sp(cpr_st), st),
+        cpr_setup_bytes(lv, n, g.nnzb),
+        f"k_cpr_weights + {len(lv) - 1} x (k_cpr_galerkin + k_cpr_diag) + k_cpr_inverse")
+    kern["cpr_apply"] = (
+        lambda: L.opm_cpr_apply(pbb, sp(Jb_), sp(bilu[0]), 0, sp(cpr_k), sp(R), sp(x), st),
+        cpr_apply_bytes(lv, n, g.nnzb, block_sweep_bytes_per_cell(0) * n),
+        f"V(1,1) cycle over {len(lv)} levels ({'/'.join(str(a) for a, _ in lv)} unknowns) + "
+        "k_cpr_r2 + k_apply_blocks (FP64) + k_cpr_add")
     if args.kernels:
         keep = set(args.kernels.split(","))
         kern = {k: v for k, v in kern.items() if k in keep}
@@ -564,6 +615,9 @@ def main():
     ap.add_argument("--krylov", choices=["bicgstab", "gmres"], default="bicgstab",
                     help="Newton's linear solver (c2)")
     ap.add_argument("--restart", type=int, default=30, help="GMRes restart length")
+    ap.add_argument("--precond", choices=["ilu0", "cpr"], default="ilu0",
+                    help="Newton's preconditioner: the (block-)ILU(0), or CPR-AMG with it as "
+                         "the second stage")
     ap.add_argument("--wells", choices=["simplified", "standard"], default="simplified",
                     help="c2 / c6-live: fixed-source wells, or standard wells with their own "
                          "unknowns solved by the Schur complement")
@@ -614,6 +668,8 @@ def main():
     opts = opm.default_opts(case, precision=args.precision)
     if args.krylov == "gmres":
         opts.krylov, opts.restart = opm.KRYLOV_GMRES, args.restart
+    if args.precond == "cpr":
+        opts.precond = opm.PRECOND_CPR
     dt = case.report_dt[0]
     stream = torch.cuda.current_stream()
     blocks = parse_blocks(args.ilu_blocks, case)
@@ -739,6 +795,11 @@ def main():
                    f"subdomains of {blocks[0]}x{blocks[1]}x{blocks[2]} cells")
     else:
         precond = "ILU(0) of the whole system (sec. 2.3.1)"
+    if args.precond == "cpr":
+        lv = g.amg_levels()
+        precond = (f"CPR-AMG (sec. 2.3.1): quasi-IMPES pressure system, one V(1,1) cycle of a "
+                   f"{len(lv)}-level aggregation AMG (unknowns per level "
+                   f"{'/'.join(str(a) for a, _ in lv)}), then as the second stage " + precond)
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "cell-Newton-iterations/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -776,10 +837,12 @@ def main():
         m.set_meaning(case.initial_meaning())
         if case.standard_wells:
             m.set_well_state(case.standard_well_init()[1])
+        oopts = oracle.default_opts(case, krylov=int(opts.krylov), restart=int(opts.restart),
+                                    precond=int(opts.precond))
         c_cni, c_wall, c_steps, passes = 0.0, 0.0, 0, 0
         while c_wall < args.cpu_seconds:
             t1 = time.perf_counter()
-            ost, yo, orep = m.advance(yo, dt)
+            ost, yo, orep = m.advance(yo, dt, oopts)
             c_wall += time.perf_counter() - t1
             if ost != 0:
                 break

@@ -62,6 +62,8 @@ extern "C" {
 #define OPM_KRYLOV_BICGSTAB 0  /* Newton's linear solver: BiCGStab (default)     */
 #define OPM_KRYLOV_GMRES 1     /* Newton's linear solver: restarted GMRes        */
 #define OPM_GMRES_MAX_RESTART 32
+#define OPM_PRECOND_ILU0 0     /* the (block-)ILU(0) preconditioner            */
+#define OPM_PRECOND_CPR 1      /* CPR-AMG, the (block-)ILU(0) as second stage */
 
 /* Fluid and rock-fluid constants (phase order water, oil, gas). */
 typedef struct opm_fluid {
@@ -204,6 +206,51 @@ int opm_well_index(int32_t nx, int32_t ny, double dx, double dy, const double* d
 int opm_well_groups(int32_t n_cells, int32_t n_conns, const int32_t* conn_cell,
                     int32_t* cell_conn_ptr, int32_t* cell_conn);
 
+/* CPR-AMG hierarchy (sec. 2.3.1: the two-stage CPR preconditioner with an
+ * AMG for the pressure system).  Level 0 is the pressure system on the
+ * cells (the block pattern, row_ptr / col_idx / diag_pos of the problem);
+ * level l + 1 aggregates the unknowns of level l in geometric 2x2x2 boxes of
+ * level l's lattice (its coarse unknowns: the occupied coarse boxes in
+ * natural order), down to at most OPM_AMG_COARSE unknowns (OPM_EINVAL if
+ * OPM_AMG_MAX_LEVELS levels do not get there).  Filled on the
+ * host by opm_amg_build (host arrays), then the same struct with device
+ * copies is referenced from opm_problem.amg.  Arrays of level l (l >= 1
+ * for row_ptr / col / dpos; l < n_levels - 1 for agg / child_ptr / child;
+ * l >= 1 for gmap_ptr / gmap):
+ *   row_ptr [n+1], col [nnz]: CSR pattern, columns ascending;
+ *   dpos [n]: position of each row's diagonal entry;
+ *   agg [n_l]: the unknown of level l + 1 that holds each unknown;
+ *   child_ptr [n_{l+1}+1], child [n_l]: the unknowns of each aggregate,
+ *     ascending;
+ *   gmap_ptr [nnz_l + 1], gmap [nnz_{l-1}]: the level l-1 entries whose sum
+ *     is each entry of level l (the Galerkin product P^T A P with the
+ *     piecewise-constant P), in the order children, then row entries. */
+#define OPM_AMG_MAX_LEVELS 12
+#define OPM_AMG_COARSE 64
+typedef struct opm_amg {
+  int32_t n_levels;
+  int32_t n[OPM_AMG_MAX_LEVELS];
+  int32_t nnz[OPM_AMG_MAX_LEVELS];
+  int32_t* row_ptr[OPM_AMG_MAX_LEVELS];
+  int32_t* col[OPM_AMG_MAX_LEVELS];
+  int32_t* dpos[OPM_AMG_MAX_LEVELS];
+  int32_t* agg[OPM_AMG_MAX_LEVELS];
+  int32_t* child_ptr[OPM_AMG_MAX_LEVELS];
+  int32_t* child[OPM_AMG_MAX_LEVELS];
+  int32_t* gmap_ptr[OPM_AMG_MAX_LEVELS];
+  int32_t* gmap[OPM_AMG_MAX_LEVELS];
+} opm_amg;
+
+/* Sizes of the hierarchy of a topology (n_levels, n[], nnz[] of out; the
+ * pointers untouched).  row_ptr / col_idx: the block pattern of
+ * opm_topology_build (host). */
+int opm_amg_count(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask, int32_t n_cells,
+                  const int32_t* row_ptr, const int32_t* col_idx, opm_amg* out);
+/* Fill the arrays of out (host, sized from opm_amg_count; level 0's
+ * row_ptr / col / dpos pointers are not used). */
+int opm_amg_build(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask, int32_t n_cells,
+                  const int32_t* row_ptr, const int32_t* col_idx, opm_amg* out);
+
 /* The discrete problem handed to the path (device pointers unless noted).
  * Well connections must be grouped by cell: cell_conn_ptr[n_cells+1] gives
  * the connections of cell i as conn ids cell_conn[cell_conn_ptr[i] ..]. */
@@ -277,6 +324,9 @@ typedef struct opm_problem {
   const double* well_vol;       /* [n_wells] wellbore volume V_w [m3]         */
   double* well_state;           /* [n_wells][4] device, in/out: the state of
                                    the well unknowns that goes with y         */
+  /* CPR-AMG hierarchy (host struct holding device arrays), or NULL: needed
+   * for opm_newton_opts.precond = OPM_PRECOND_CPR and opm_cpr_*. */
+  const opm_amg* amg;
 } opm_problem;
 
 /* Library set-up: checks that the current device is a gfx950 (MI355X) and
@@ -390,7 +440,43 @@ typedef struct opm_newton_opts {
   int32_t max_cuts;    /* time-step halvings per report step (opm_advance)  */
   int32_t krylov;      /* OPM_KRYLOV_BICGSTAB or OPM_KRYLOV_GMRES           */
   int32_t restart;     /* GMRes restart length (1..OPM_GMRES_MAX_RESTART)   */
+  int32_t precond;     /* OPM_PRECOND_ILU0 or OPM_PRECOND_CPR (BiCGStab)    */
+  int32_t pad;
 } opm_newton_opts;
+
+/* CPR-AMG preconditioner (sec. 2.3.1, the two-stage CPR preconditioner):
+ * stage 1 solves the quasi-IMPES pressure system approximately by one
+ * V(1,1) cycle of the aggregation AMG of opm_problem.amg (damped Jacobi,
+ * omega = 2/3; the coarsest level by its inverse), stage 2 applies the
+ * (block-)ILU(0) of the whole system to what is left:
+ *   w_i: D_i^T w_i = e_p (D_i the diagonal block of row i);
+ *   (A_p)_ij = w_i^T A_ij e_p; coarse levels A_{l+1} = P_l^T A_l P_l;
+ *   z = x1 + M_ILU^{-1} (r - A x1), x1 = e_p V(A_p, w^T r).
+ * All buffers are device memory; the workspace cpr holds opm_cpr_bytes
+ * bytes and is owned by the caller.  Every call needs pb->amg (OPM_EINVAL
+ * without); nothing is allocated. */
+size_t opm_cpr_bytes(const opm_problem* pb);
+/* Weights, pressure matrices and coarsest inverse for the Jacobian J
+ * ([nnzb][3][3]); *status (device) is set to OPM_ESINGULAR on a singular
+ * diagonal block or coarsest matrix and left alone otherwise. */
+int opm_cpr_setup(const opm_problem* pb, const double* J, void* cpr, int32_t* status,
+                  void* stream);
+/* x = V(1,1)-cycle approximation of A_p^{-1} b (b, x: [n_cells]). */
+int opm_cpr_vcycle(const opm_problem* pb, const void* cpr, const double* b, double* x,
+                   void* stream);
+/* z = CPR(r) (r, z: [n_cells][3], distinct) with the ILU(0) factors ilu of
+ * the same J in the given precision. */
+int opm_cpr_apply(const opm_problem* pb, const double* J, const void* ilu, int precision,
+                  const void* cpr, const double* r, double* z, void* stream);
+/* Copies out level `level`'s matrix values (a: [amg->nnz[level]], the
+ * level's CSR order; level 0 on the block pattern) and the weights (w:
+ * [n_cells][3]); either may be NULL. */
+int opm_cpr_values(const opm_problem* pb, const void* cpr, int32_t level, double* a,
+                   double* w, void* stream);
+/* opm_bicgstab with CPR (set up for J) as the preconditioner. */
+int opm_bicgstab_cpr(const opm_problem* pb, const double* J, const void* ilu, int precision,
+                     const void* cpr, const double* b, double* x, double rtol, int32_t maxit,
+                     void* work, opm_solve_report* report, void* stream);
 
 /* Report of one time step (or of one report step for opm_advance). */
 typedef struct opm_newton_report {

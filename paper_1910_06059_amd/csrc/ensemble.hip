@@ -527,7 +527,8 @@ int opm_ensemble_launch_config(const void* work, int32_t n_members, int precisio
                                opm_ensemble_report* reports, void* stream) {
   if (!work || n_members <= 0 || !opts || !reports || n_steps < 0 || !(dt_report > 0.0) ||
       max_level <= 0 || opts->max_newton < 0 || opts->lin_maxit < 0 || opts->max_cuts < 0 ||
-      opts->krylov != OPM_KRYLOV_BICGSTAB || !cfg || !valid_config(*cfg, max_level) ||
+      opts->krylov != OPM_KRYLOV_BICGSTAB || opts->precond != OPM_PRECOND_ILU0 || !cfg ||
+      !valid_config(*cfg, max_level) ||
       cfg->sweep_bytes <= 0)
     return OPM_EINVAL;
   const EnsMember* tab = table_of(const_cast<void*>(work));
@@ -560,7 +561,7 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
                           opm_ensemble_config* best, double* seconds, int32_t* n_tried,
                           void* stream) {
   if (!members || n_members <= 0 || !work || !opts || !best || !(dt_report > 0.0) ||
-      opts->krylov != OPM_KRYLOV_BICGSTAB ||
+      opts->krylov != OPM_KRYLOV_BICGSTAB || opts->precond != OPM_PRECOND_ILU0 ||
       (precision != OPM_PREC_FP64 && precision != OPM_PREC_MIXED))
     return OPM_EINVAL;
   hipStream_t s = as_stream(stream);

@@ -33,6 +33,7 @@
 // chunks and reads the state between chunks.
 #include <algorithm>
 
+#include "cpr_dev.h"
 #include "solver_dev.h"
 
 namespace opm {
@@ -473,9 +474,10 @@ size_t gmres_bytes(const opm_problem* pb, int restart) {
   return gm_bytes(pb->n_cells, std::min(std::max(restart, 1), kMaxRestart));
 }
 
+// cpr (may be null): CPR-AMG set up for J, with ilu as its second stage.
 int gmres(const opm_problem* pb, const double* J, void* ilu, int precision, const double* b,
           double* x, double rtol, int maxit, int restart, void* work, opm_solve_report* rep,
-          hipStream_t st) {
+          hipStream_t st, const CprWork* cpr) {
   if (restart < 1 || restart > kMaxRestart || maxit < 0) return OPM_EINVAL;
   const int n = pb->n_cells, N = 3 * n, m = restart;
   GmWork w = gm_carve(n, m, work);
@@ -496,7 +498,11 @@ int gmres(const opm_problem* pb, const double* J, void* ilu, int precision, cons
     for (int j0 = 0; j0 < m; j0 += chunk) {
       for (int j = j0; j < std::min(m, j0 + chunk); ++j) {
         double* zj = w.Z + (size_t)j * w.Np;
-        OPM_TRY(ilu_apply(pb, ilu, precision, w.V + (size_t)j * w.Np, zj, st, &w.sc->state));
+        const double* vj = w.V + (size_t)j * w.Np;
+        if (cpr)
+          OPM_TRY(cpr_apply(pb, J, ilu, precision, *cpr, vj, zj, st, &w.sc->state));
+        else
+          OPM_TRY(ilu_apply(pb, ilu, precision, vj, zj, st, &w.sc->state));
         hipLaunchKernelGGL(k_gm_spmv<false>, dim3(Gs), dim3(kBlock), 0, st, n, pb->row_ptr,
                            pb->col_idx, J, zj, nullptr, w.w, w.sc, (int)kGmRunning);
         if (j < 4)

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <vector>
 
+#include "cpr_dev.h"
 #include "krylov_dev.h"
 #include "solver_dev.h"
 
@@ -304,7 +305,8 @@ struct ChunkKey {
   const void* work;
   hipStream_t st;
   int precision, chunk, device, sweep_mode, sweep_kernel, block_depth;
-  WellSchur ws;   // standard wells (all zero without)
+  WellSchur ws;              // standard wells (all zero without)
+  const double* cpr_base;    // CPR workspace (null without)
 };
 struct ChunkGraph {
   ChunkKey key;
@@ -333,9 +335,10 @@ int capture_stream(int device, hipStream_t* out) {
 
 // Enqueue the whole solve; returns after reading the final scalars.
 // ws (may be null): standard wells, solved through their Schur complement.
+// cpr (may be null): CPR-AMG set up for J, with ilu as its second stage.
 int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, const double* b,
              double* x, double rtol, int maxit, void* work, opm_solve_report* rep,
-             hipStream_t st, const WellSchur* ws) {
+             hipStream_t st, const WellSchur* ws, const CprWork* cpr) {
   const int n = pb->n_cells, N = 3 * n;
   Work w = carve(pb, work);
   const int G = vec_grid(N), Gr = std::min(kMaxGrid, std::max(1, spmv_blocks(n)));
@@ -345,12 +348,16 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
   const int chunk = chunk_size(pb);
   // block ILU0 with one workgroup per subdomain: the p and s updates (and
   // the tests before them) run inside the preconditioner sweeps
-  const bool fused = sweep_mode(pb, precision) == 2 && pb->n_sub <= kMaxGrid;
+  const bool fused = sweep_mode(pb, precision) == 2 && pb->n_sub <= kMaxGrid && !cpr;
   kry::Fused fb{w.r, w.p, w.v, nullptr, w.part_rr, w.part_rhr, G, nullptr, w.sc};
   kry::Fused fs{w.r, nullptr, w.v, w.s, w.part_rv, nullptr, Gr, w.part_ss, w.sc};
   Scalars host;
   int launched = 0;
   const WellCorr wc = ws ? ws->wc() : WellCorr{nullptr, nullptr, nullptr};
+  auto prec = [&](const double* r, double* z, hipStream_t st) -> int {
+    return cpr ? cpr_apply(pb, J, ilu, precision, *cpr, r, z, st, &w.sc->state)
+               : ilu_apply(pb, ilu, precision, r, z, st, &w.sc->state);
+  };
   auto enqueue_chunk = [&](hipStream_t st) -> int {
     for (int c = 0; c < chunk; ++c) {
       if (fused) {
@@ -364,13 +371,13 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
                            pb->col_idx, J, w, pb->n_sub, wc);
       } else {
         hipLaunchKernelGGL(k_begin, dim3(G), dim3(kBlock), 0, st, N, w, G);
-        OPM_TRY(ilu_apply(pb, ilu, precision, w.p, w.ph, st, &w.sc->state));
+        OPM_TRY(prec(w.p, w.ph, st));
         if (ws) OPM_TRY(well_op(*ws, w.ph, &w.sc->state, st));
         hipLaunchKernelGGL(k_spmv_rv, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
                            pb->col_idx, J, w, wc);
         hipLaunchKernelGGL(k_s, dim3(G), dim3(kBlock), 0, st, N, w, Gr);
         hipLaunchKernelGGL(k_s_check, dim3(1), dim3(kBlock), 0, st, w, G);
-        OPM_TRY(ilu_apply(pb, ilu, precision, w.s, w.sh, st, &w.sc->state));
+        OPM_TRY(prec(w.s, w.sh, st));
         if (ws) OPM_TRY(well_op(*ws, w.sh, &w.sc->state, st));
         hipLaunchKernelGGL(k_spmv_t<false>, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
                            pb->col_idx, J, w, 0, wc);
@@ -394,6 +401,7 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
     OPM_TRY_HIP(hipGetDevice(&key.device));
     key.sweep_mode = g_sweep_mode;
     if (ws) std::memcpy(&key.ws, ws, sizeof *ws);   // ws is built zero-filled (padding too)
+    key.cpr_base = cpr ? cpr->w : nullptr;
     key.sweep_kernel = g_sweep_kernel;
     key.block_depth = g_block_depth;
   }

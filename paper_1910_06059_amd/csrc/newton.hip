@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "common.h"
+#include "cpr_dev.h"
 #include "wells_dev.h"
 
 namespace opm {
@@ -28,11 +29,11 @@ size_t krylov_bytes(const opm_problem* pb);
 int spmv(const opm_problem* pb, const double* J, const double* x, double* y, hipStream_t s);
 int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, const double* b,
              double* x, double rtol, int maxit, void* work, opm_solve_report* rep,
-             hipStream_t st, const WellSchur* ws = nullptr);
+             hipStream_t st, const WellSchur* ws = nullptr, const CprWork* cpr = nullptr);
 size_t gmres_bytes(const opm_problem* pb, int restart);
 int gmres(const opm_problem* pb, const double* J, void* ilu, int precision, const double* b,
           double* x, double rtol, int maxit, int restart, void* work, opm_solve_report* rep,
-          hipStream_t st);
+          hipStream_t st, const CprWork* cpr = nullptr);
 
 int guess_infer(const opm_problem* pb, const opm_guess_net* net, const double* y_n,
                 const double* y_nm1, double* y_guess, void* work, hipStream_t s,
@@ -55,6 +56,7 @@ struct NewtonWork {
   int32_t* flags;   // [0] factor status, [1] non-finite update
   uint8_t* mean_save;   // [n] variable meanings of the last accepted state (live oil)
   WellWork wells;       // standard wells (unset without)
+  void* cpr;            // CPR-AMG workspace (problems with a hierarchy)
   void* ilu;
   void* krylov;
 };
@@ -66,7 +68,8 @@ size_t newton_bytes(const opm_problem* pb, int precision, int krylov = OPM_KRYLO
   const size_t kb = krylov == OPM_KRYLOV_GMRES ? gmres_bytes(pb, restart) : krylov_bytes(pb);
   return align256(sizeof(double) * N) * 3 + align256(sizeof(double) * 9 * (size_t)pb->nnzb) +
          align256(norms_bytes(pb)) + 256 + align256((size_t)pb->n_cells) +
-         align256(wells_bytes(pb)) + align256(ilu_bytes(pb, precision)) + align256(kb);
+         align256(wells_bytes(pb)) + align256(cpr_bytes(pb)) + align256(ilu_bytes(pb, precision)) +
+         align256(kb);
 }
 
 NewtonWork carve(const opm_problem* pb, int precision, void* work) {
@@ -90,6 +93,8 @@ NewtonWork carve(const opm_problem* pb, int precision, void* work) {
   std::memset(&w.wells, 0, sizeof w.wells);
   if (pb->n_wells > 0) w.wells = wells_carve(pb, c);
   c += align256(wells_bytes(pb));
+  w.cpr = c;
+  c += align256(cpr_bytes(pb));
   w.ilu = c;
   c += align256(ilu_bytes(pb, precision));
   w.krylov = c;
@@ -208,6 +213,10 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
   std::memset(&ws, 0, sizeof ws);
   if (std_wells) ws = well_schur(pb, ww);
   std::vector<double> wn(std_wells ? pb->n_wells : 0);
+  const bool use_cpr = o->precond == OPM_PRECOND_CPR;
+  CprWork cw;
+  std::memset(&cw, 0, sizeof cw);
+  if (use_cpr) cw = cpr_carve(pb, w.cpr);
   int status = OPM_ENOTCONV;
   for (int it = 0;; ++it) {
     OPM_TRY_HIP(hipEventRecord(ev.e[0], s));
@@ -246,15 +255,16 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
       break;
     }
     OPM_TRY(ilu_factor(pb, w.J, w.ilu, o->precision, &w.flags[0], s));
+    if (use_cpr) OPM_TRY(cpr_setup(pb, w.J, cw, &w.flags[0], s));
     OPM_TRY_HIP(hipEventRecord(ev.e[2], s));
     opm_solve_report lr;
     if (std_wells) OPM_TRY(well_rhs(pb, ww, w.R, s));   // R_r - sum C D^-1 R_w
     if (o->krylov == OPM_KRYLOV_GMRES)
       OPM_TRY(gmres(pb, w.J, w.ilu, o->precision, w.R, w.d, o->lin_rtol, o->lin_maxit, o->restart,
-                    w.krylov, &lr, s));
+                    w.krylov, &lr, s, use_cpr ? &cw : nullptr));
     else
       OPM_TRY(bicgstab(pb, w.J, w.ilu, o->precision, w.R, w.d, o->lin_rtol, o->lin_maxit,
-                       w.krylov, &lr, s, std_wells ? &ws : nullptr));
+                       w.krylov, &lr, s, std_wells ? &ws : nullptr, use_cpr ? &cw : nullptr));
     OPM_TRY_HIP(hipEventRecord(ev.e[3], s));
     rep->lin_its += lr.its;
     OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
@@ -570,12 +580,92 @@ size_t opm_newton_work_bytes(const opm_problem* pb, const opm_newton_opts* opts)
 static bool valid_opts(const opm_newton_opts* o) {
   return o && valid_prec(o->precision) && o->max_newton >= 0 && o->lin_maxit >= 0 &&
          o->max_cuts >= 0 && o->ds_max > 0.0 && o->dp_max_rel > 0.0 && o->lin_rtol >= 0.0 &&
-         o->tol_cnv >= 0.0 && o->tol_mb >= 0.0 && valid_krylov(o);
+         o->tol_cnv >= 0.0 && o->tol_mb >= 0.0 && valid_krylov(o) &&
+         (o->precond == OPM_PRECOND_ILU0 || o->precond == OPM_PRECOND_CPR);
 }
 
-// Standard wells are solved with BiCGStab only.
+// The CPR hierarchy referenced by the problem fits it: level 0 is the block
+// pattern, the coarsest level has at most OPM_AMG_COARSE unknowns and every
+// array a level needs is there.
+static bool valid_amg(const opm_problem* pb) {
+  const opm_amg* g = pb->amg;
+  if (!g || g->n_levels < 1 || g->n_levels > OPM_AMG_MAX_LEVELS || g->n[0] != pb->n_cells ||
+      g->nnz[0] != pb->nnzb || g->n[g->n_levels - 1] > OPM_AMG_COARSE ||
+      g->n[g->n_levels - 1] < 1)
+    return false;
+  for (int l = 0; l < g->n_levels; ++l) {
+    if (l >= 1 && (!g->row_ptr[l] || !g->col[l] || !g->dpos[l] || !g->gmap_ptr[l] ||
+                   !g->gmap[l] || g->n[l] < 1 || g->nnz[l] < g->n[l]))
+      return false;
+    if (l + 1 < g->n_levels && (!g->agg[l] || !g->child_ptr[l] || !g->child[l])) return false;
+  }
+  return true;
+}
+
+// Standard wells are solved with BiCGStab only; CPR needs the hierarchy.
 static bool valid_wells_opts(const opm_problem* pb, const opm_newton_opts* o) {
-  return pb->n_wells == 0 || o->krylov == OPM_KRYLOV_BICGSTAB;
+  return (pb->n_wells == 0 || o->krylov == OPM_KRYLOV_BICGSTAB) &&
+         (o->precond == OPM_PRECOND_ILU0 || valid_amg(pb));
+}
+
+size_t opm_cpr_bytes(const opm_problem* pb) {
+  return pb && pb->n_cells > 0 && valid_amg(pb) ? cpr_bytes(pb) : 0;
+}
+
+int opm_cpr_setup(const opm_problem* pb, const double* J, void* cpr, int32_t* status,
+                  void* stream) {
+  if (!valid_problem(pb) || pb->n_cells == 0 || !valid_amg(pb) || !J || !cpr || !status)
+    return OPM_EINVAL;
+  return cpr_setup(pb, J, cpr_carve(pb, cpr), status, as_stream(stream));
+}
+
+int opm_cpr_vcycle(const opm_problem* pb, const void* cpr, const double* b, double* x,
+                   void* stream) {
+  if (!valid_problem(pb) || pb->n_cells == 0 || !valid_amg(pb) || !cpr || !b || !x)
+    return OPM_EINVAL;
+  hipStream_t s = as_stream(stream);
+  const CprWork w = cpr_carve(pb, const_cast<void*>(cpr));
+  const size_t bytes = sizeof(double) * pb->n_cells;
+  OPM_TRY_HIP(hipMemcpyAsync(w.b[0], b, bytes, hipMemcpyDeviceToDevice, s));
+  OPM_TRY(cpr_vcycle(pb, w, s, nullptr));
+  OPM_TRY_HIP(hipMemcpyAsync(x, w.y[0], bytes, hipMemcpyDeviceToDevice, s));
+  return OPM_OK;
+}
+
+int opm_cpr_apply(const opm_problem* pb, const double* J, const void* ilu, int precision,
+                  const void* cpr, const double* r, double* z, void* stream) {
+  if (!valid_problem(pb) || pb->n_cells == 0 || !valid_amg(pb) || !valid_prec(precision) || !J ||
+      !ilu || !cpr || !r || !z || r == z)
+    return OPM_EINVAL;
+  return cpr_apply(pb, J, const_cast<void*>(ilu), precision,
+                   cpr_carve(pb, const_cast<void*>(cpr)), r, z, as_stream(stream), nullptr);
+}
+
+int opm_cpr_values(const opm_problem* pb, const void* cpr, int32_t level, double* a,
+                   double* w, void* stream) {
+  if (!valid_problem(pb) || pb->n_cells == 0 || !valid_amg(pb) || !cpr || level < 0 ||
+      level >= pb->amg->n_levels)
+    return OPM_EINVAL;
+  hipStream_t s = as_stream(stream);
+  const CprWork cw = cpr_carve(pb, const_cast<void*>(cpr));
+  if (a)
+    OPM_TRY_HIP(hipMemcpyAsync(a, cw.a[level], sizeof(double) * pb->amg->nnz[level],
+                               hipMemcpyDeviceToDevice, s));
+  if (w)
+    OPM_TRY_HIP(hipMemcpyAsync(w, cw.w, sizeof(double) * 3 * pb->n_cells,
+                               hipMemcpyDeviceToDevice, s));
+  return OPM_OK;
+}
+
+int opm_bicgstab_cpr(const opm_problem* pb, const double* J, const void* ilu, int precision,
+                     const void* cpr, const double* b, double* x, double rtol, int32_t maxit,
+                     void* work, opm_solve_report* report, void* stream) {
+  if (!valid_problem(pb) || pb->n_cells == 0 || !valid_amg(pb) || !valid_prec(precision) ||
+      !(rtol >= 0.0) || maxit < 0 || !report || !J || !ilu || !cpr || !b || !x || !work)
+    return OPM_EINVAL;
+  const CprWork cw = cpr_carve(pb, const_cast<void*>(cpr));
+  return bicgstab(pb, J, const_cast<void*>(ilu), precision, b, x, rtol, maxit, work, report,
+                  as_stream(stream), nullptr, &cw);
 }
 
 int opm_newton_step(const opm_problem* pb, double* y, const double* y_prev, double dt,

@@ -306,3 +306,151 @@ extern "C" int opm_well_groups(int32_t n_cells, int32_t n_conns, const int32_t* 
   for (int32_t k = 0; k < n_conns; ++k) cell_conn[cnt[conn_cell[k]]++] = k;
   return OPM_OK;
 }
+
+// ---------------------------------------------------------------- CPR-AMG
+// The aggregation hierarchy of the CPR pressure stage: geometric 2x2x2
+// aggregates of each level's lattice, the coarse patterns, and the gather
+// maps of the Galerkin products.  Built level by level; count and build run
+// the same construction (count keeps only the sizes).
+namespace {
+
+struct AmgLevel {
+  int dims[3];
+  std::vector<int> box;                // lattice box of each unknown
+  std::vector<int32_t> row_ptr, col, dpos;
+  std::vector<int32_t> agg, child_ptr, child;   // to the next level
+  std::vector<int32_t> gmap_ptr, gmap;           // from the previous level
+};
+
+int amg_hierarchy(int nx, int ny, int nz, const uint8_t* mask, int n, const int32_t* row_ptr,
+                  const int32_t* col_idx, std::vector<AmgLevel>& L) {
+  L.clear();
+  L.emplace_back();
+  AmgLevel& l0 = L.back();
+  l0.dims[0] = nx;
+  l0.dims[1] = ny;
+  l0.dims[2] = nz;
+  l0.box.reserve(n);
+  for (long b = 0; b < (long)nx * ny * nz; ++b)
+    if (active(mask, b)) l0.box.push_back((int)b);
+  if ((int)l0.box.size() != n) return OPM_EINVAL;
+  l0.row_ptr.assign(row_ptr, row_ptr + n + 1);
+  l0.col.assign(col_idx, col_idx + row_ptr[n]);
+  while ((int)L.back().box.size() > OPM_AMG_COARSE && (int)L.size() < OPM_AMG_MAX_LEVELS) {
+    AmgLevel& f = L.back();
+    const int* d = f.dims;
+    if (d[0] == 1 && d[1] == 1 && d[2] == 1) break;
+    const int cd[3] = {(d[0] + 1) / 2, (d[1] + 1) / 2, (d[2] + 1) / 2};
+    const long nbc = (long)cd[0] * cd[1] * cd[2];
+    const int nf = (int)f.box.size();
+    std::vector<int> idx(nbc, -1), parent(nf);
+    for (int i = 0; i < nf; ++i) {
+      const int b = f.box[i];
+      const int x = b % d[0], y = (b / d[0]) % d[1], z = b / (d[0] * d[1]);
+      parent[i] = x / 2 + cd[0] * (y / 2 + cd[1] * (z / 2));
+      idx[parent[i]] = 0;
+    }
+    AmgLevel c;
+    int nc = 0;
+    for (long b = 0; b < nbc; ++b)
+      if (idx[b] >= 0) {
+        idx[b] = nc++;
+        c.box.push_back((int)b);
+      }
+    std::memcpy(c.dims, cd, sizeof cd);
+    f.agg.resize(nf);
+    for (int i = 0; i < nf; ++i) f.agg[i] = idx[parent[i]];
+    f.child_ptr.assign(nc + 1, 0);
+    for (int i = 0; i < nf; ++i) f.child_ptr[f.agg[i] + 1]++;
+    for (int I = 0; I < nc; ++I) f.child_ptr[I + 1] += f.child_ptr[I];
+    f.child.resize(nf);
+    {
+      std::vector<int32_t> fill(f.child_ptr.begin(), f.child_ptr.end() - 1);
+      for (int i = 0; i < nf; ++i) f.child[fill[f.agg[i]]++] = i;
+    }
+    // coarse rows: the aggregates of the children's columns, ascending; each
+    // coarse entry gathers its fine entries in the order children, entries
+    c.row_ptr.assign(nc + 1, 0);
+    std::vector<std::vector<int32_t>> members;
+    for (int I = 0; I < nc; ++I) {
+      std::vector<std::pair<int32_t, int32_t>> e;   // (coarse column, fine entry)
+      for (int t = f.child_ptr[I]; t < f.child_ptr[I + 1]; ++t) {
+        const int i = f.child[t];
+        for (int q = f.row_ptr[i]; q < f.row_ptr[i + 1]; ++q) e.push_back({f.agg[f.col[q]], q});
+      }
+      std::stable_sort(e.begin(), e.end(),
+                       [](const std::pair<int32_t, int32_t>& a,
+                          const std::pair<int32_t, int32_t>& b) { return a.first < b.first; });
+      for (size_t u = 0; u < e.size(); ++u) {
+        if (u == 0 || e[u].first != e[u - 1].first) {
+          c.col.push_back(e[u].first);
+          members.emplace_back();
+        }
+        members.back().push_back(e[u].second);
+      }
+      c.row_ptr[I + 1] = (int32_t)c.col.size();
+    }
+    c.gmap_ptr.assign(members.size() + 1, 0);
+    for (size_t k = 0; k < members.size(); ++k) {
+      c.gmap_ptr[k + 1] = c.gmap_ptr[k] + (int32_t)members[k].size();
+      c.gmap.insert(c.gmap.end(), members[k].begin(), members[k].end());
+    }
+    c.dpos.resize(nc);
+    for (int I = 0; I < nc; ++I)
+      for (int q = c.row_ptr[I]; q < c.row_ptr[I + 1]; ++q)
+        if (c.col[q] == I) c.dpos[I] = q;
+    L.push_back(std::move(c));
+  }
+  // the coarsest level is solved by its dense inverse
+  if ((int)L.back().box.size() > OPM_AMG_COARSE) return OPM_EINVAL;
+  return OPM_OK;
+}
+
+int amg_fill(int nx, int ny, int nz, const uint8_t* mask, int n, const int32_t* row_ptr,
+             const int32_t* col_idx, opm_amg* out, bool arrays) {
+  if (nx <= 0 || ny <= 0 || nz <= 0 || n <= 0 || !row_ptr || !col_idx || !out) return OPM_EINVAL;
+  std::vector<AmgLevel> L;
+  const int st = amg_hierarchy(nx, ny, nz, mask, n, row_ptr, col_idx, L);
+  if (st != OPM_OK) return st;
+  out->n_levels = (int32_t)L.size();
+  for (size_t l = 0; l < L.size(); ++l) {
+    out->n[l] = (int32_t)L[l].box.size();
+    out->nnz[l] = (int32_t)L[l].col.size();
+  }
+  if (!arrays) return OPM_OK;
+  auto put = [](int32_t* dst, const std::vector<int32_t>& v) {
+    if (!v.empty()) std::memcpy(dst, v.data(), sizeof(int32_t) * v.size());
+  };
+  for (size_t l = 0; l < L.size(); ++l) {
+    if (l >= 1) {
+      if (!out->row_ptr[l] || !out->col[l] || !out->dpos[l] || !out->gmap_ptr[l] || !out->gmap[l])
+        return OPM_EINVAL;
+      put(out->row_ptr[l], L[l].row_ptr);
+      put(out->col[l], L[l].col);
+      put(out->dpos[l], L[l].dpos);
+      put(out->gmap_ptr[l], L[l].gmap_ptr);
+      put(out->gmap[l], L[l].gmap);
+    }
+    if (l + 1 < L.size()) {
+      if (!out->agg[l] || !out->child_ptr[l] || !out->child[l]) return OPM_EINVAL;
+      put(out->agg[l], L[l].agg);
+      put(out->child_ptr[l], L[l].child_ptr);
+      put(out->child[l], L[l].child);
+    }
+  }
+  return OPM_OK;
+}
+
+}  // namespace
+
+extern "C" int opm_amg_count(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask,
+                             int32_t n_cells, const int32_t* row_ptr, const int32_t* col_idx,
+                             opm_amg* out) {
+  return amg_fill(nx, ny, nz, mask, n_cells, row_ptr, col_idx, out, false);
+}
+
+extern "C" int opm_amg_build(int32_t nx, int32_t ny, int32_t nz, const uint8_t* mask,
+                             int32_t n_cells, const int32_t* row_ptr, const int32_t* col_idx,
+                             opm_amg* out) {
+  return amg_fill(nx, ny, nz, mask, n_cells, row_ptr, col_idx, out, true);
+}

@@ -25,6 +25,7 @@ OK, EINVAL, ESINGULAR, ENOTCONV, EBREAKDOWN, ENONFINITE, EHIP = 0, -1, -2, -3, -
 PREC_FP64, PREC_MIXED = 0, 1
 KRYLOV_BICGSTAB, KRYLOV_GMRES = 0, 1
 GMRES_MAX_RESTART = 32
+PRECOND_ILU0, PRECOND_CPR = 0, 1
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -66,7 +67,17 @@ class Problem(ctypes.Structure):
                 ("sub_level_ptr", _vp), ("slot", _vp), ("meaning", _vp),
                 ("n_wells", _i32), ("pad_w", _i32), ("well_conn_ptr", _vp), ("conn_cell", _vp),
                 ("conn_well", _vp), ("well_kind", _vp), ("well_phase", _vp), ("well_target", _vp),
-                ("well_vol", _vp), ("well_state", _vp)]
+                ("well_vol", _vp), ("well_state", _vp), ("amg", _vp)]
+
+
+AMG_MAX_LEVELS, AMG_COARSE = 12, 64
+
+
+class Amg(ctypes.Structure):
+    _fields_ = [("n_levels", _i32), ("n", _i32 * AMG_MAX_LEVELS),
+                ("nnz", _i32 * AMG_MAX_LEVELS)] + [
+        (name, _vp * AMG_MAX_LEVELS) for name in (
+            "row_ptr", "col", "dpos", "agg", "child_ptr", "child", "gmap_ptr", "gmap")]
 
 
 class SolveReport(ctypes.Structure):
@@ -78,7 +89,8 @@ class NewtonOpts(ctypes.Structure):
     _fields_ = [("tol_cnv", ctypes.c_double), ("tol_mb", ctypes.c_double),
                 ("ds_max", ctypes.c_double), ("dp_max_rel", ctypes.c_double),
                 ("lin_rtol", ctypes.c_double), ("max_newton", _i32), ("lin_maxit", _i32),
-                ("precision", _i32), ("max_cuts", _i32), ("krylov", _i32), ("restart", _i32)]
+                ("precision", _i32), ("max_cuts", _i32), ("krylov", _i32), ("restart", _i32),
+                ("precond", _i32), ("pad", _i32)]
 
 
 class NewtonReport(ctypes.Structure):
@@ -101,6 +113,8 @@ EXPORTS = [
     "opm_bicgstab", "opm_gmres_bytes", "opm_gmres", "opm_newton_bytes", "opm_newton_work_bytes",
     "opm_newton_step", "opm_advance", "opm_set_option", "opm_wells_bytes", "opm_assemble_wells",
     "opm_ensemble_bytes", "opm_ensemble_prepare", "opm_ensemble_launch",
+    "opm_amg_count", "opm_amg_build", "opm_cpr_bytes", "opm_cpr_setup", "opm_cpr_vcycle",
+    "opm_cpr_apply", "opm_cpr_values", "opm_bicgstab_cpr",
 ]
 
 OPT_SWEEP_MODE, OPT_KRYLOV_CHUNK, OPT_SWEEP_KERNEL, OPT_BLOCK_DEPTH, OPT_KRYLOV_GRAPH = 1, 2, 3, 4, 5
@@ -174,6 +188,17 @@ def lib():
                                       _vp, ctypes.POINTER(NewtonReport), _vp]
         L.opm_advance.argtypes = [P, _vp, ctypes.c_double, ctypes.POINTER(NewtonOpts), _vp, _vp,
                                   ctypes.POINTER(NewtonReport), _vp]
+        A = ctypes.POINTER(Amg)
+        L.opm_amg_count.argtypes = [_i32, _i32, _i32, _vp, _i32, _vp, _vp, A]
+        L.opm_amg_build.argtypes = [_i32, _i32, _i32, _vp, _i32, _vp, _vp, A]
+        L.opm_cpr_bytes.argtypes = [P]
+        L.opm_cpr_bytes.restype = ctypes.c_size_t
+        L.opm_cpr_setup.argtypes = [P, _vp, _vp, _vp, _vp]
+        L.opm_cpr_vcycle.argtypes = [P, _vp, _vp, _vp, _vp]
+        L.opm_cpr_apply.argtypes = [P, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]
+        L.opm_cpr_values.argtypes = [P, _vp, _i32, _vp, _vp, _vp]
+        L.opm_bicgstab_cpr.argtypes = [P, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, ctypes.c_double,
+                                       _i32, _vp, ctypes.POINTER(SolveReport), _vp]
         _lib = L
     return _lib
 
@@ -213,7 +238,7 @@ def set_option(option: int, value: int) -> None:
 def default_opts(case=None, precision=PREC_FP64, **kw) -> NewtonOpts:
     o = NewtonOpts(tol_cnv=1e-8, tol_mb=1e-11, ds_max=0.2, dp_max_rel=0.3, lin_rtol=1e-6,
                    max_newton=20, lin_maxit=500, precision=precision, max_cuts=8,
-                   krylov=KRYLOV_BICGSTAB, restart=30)
+                   krylov=KRYLOV_BICGSTAB, restart=30, precond=PRECOND_ILU0)
     if case is not None:
         o.tol_cnv, o.tol_mb, o.lin_rtol = case.tol_cnv, case.tol_mb, case.lin_rtol
     for k, v in kw.items():
@@ -255,14 +280,44 @@ def build_topology(nx: int, ny: int, nz: int, mask: np.ndarray,
     return n, nf, host, topo, blk
 
 
+def amg_hierarchy(nx: int, ny: int, nz: int, mask: np.ndarray, n: int, row_ptr: np.ndarray,
+                  col_idx: np.ndarray):
+    """opm_amg_count + opm_amg_build (host only): the Amg struct (host
+    pointers) and its arrays {(name, level): int32 array}."""
+    L = lib()
+    mask = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    g = Amg()
+    _check(L.opm_amg_count(nx, ny, nz, mask.ctypes.data, n, rp.ctypes.data, ci.ctypes.data,
+                           ctypes.byref(g)), "opm_amg_count")
+    nl = g.n_levels
+    arrays = {}
+    for l in range(nl):
+        nl_, nnz = g.n[l], g.nnz[l]
+        if l >= 1:
+            for k, size in (("row_ptr", nl_ + 1), ("col", nnz), ("dpos", nl_),
+                            ("gmap_ptr", nnz + 1), ("gmap", g.nnz[l - 1])):
+                arrays[k, l] = np.zeros(size, np.int32)
+        if l + 1 < nl:
+            for k, size in (("agg", nl_), ("child_ptr", g.n[l + 1] + 1), ("child", nl_)):
+                arrays[k, l] = np.zeros(size, np.int32)
+    for (k, l), a in arrays.items():
+        getattr(g, k)[l] = a.ctypes.data
+    _check(L.opm_amg_build(nx, ny, nz, mask.ctypes.data, n, rp.ctypes.data, ci.ctypes.data,
+                           ctypes.byref(g)), "opm_amg_build")
+    return g, arrays
+
+
 class GpuModel:
     """A case laid out on the GPU: topology, geometry and wells on device.
     ilu_blocks = (bx, by, bz) selects the block ILU0 over subdomain boxes of
     that many cells per axis (one block per subdomain) instead of the
-    single-block ILU(0)."""
+    single-block ILU(0).  amg builds the CPR-AMG hierarchy (needed for
+    precond = PRECOND_CPR)."""
 
     def __init__(self, case: _cases.Case, device: str = "cuda",
-                 ilu_blocks: Optional[Sequence[int]] = None):
+                 ilu_blocks: Optional[Sequence[int]] = None, amg: bool = True):
         L = lib()
         init()
         self.case = case
@@ -378,7 +433,73 @@ class GpuModel:
             self.pb.well_vol = self.well_vol.data_ptr()
             self.pb.well_state = self.well_state_t.data_ptr()
         self._work = {}
+        self.amg = self._build_amg(host) if amg else None
+        if amg:
+            self.pb.amg = ctypes.addressof(self.amg)
         torch.cuda.current_stream().synchronize()
+
+    def _build_amg(self, host):
+        """The CPR-AMG hierarchy (opm_amg_build on the host, arrays copied to
+        the device); the struct handed to the library holds device pointers."""
+        c = self.case
+        g, arrays = amg_hierarchy(c.nx, c.ny, c.nz, c.mask, self.n, host["row_ptr"],
+                                  host["col_idx"])
+        self.amg_host = arrays
+        self.amg_dev = {key: torch.from_numpy(a).to(self.dev) for key, a in arrays.items()}
+        d = Amg()
+        d.n_levels = g.n_levels
+        for l in range(g.n_levels):
+            d.n[l], d.nnz[l] = g.n[l], g.nnz[l]
+        for (k, l), t in self.amg_dev.items():
+            getattr(d, k)[l] = t.data_ptr()
+        return d
+
+    def amg_levels(self):
+        """(n, nnz) per level of the CPR hierarchy."""
+        return [(self.amg.n[l], self.amg.nnz[l]) for l in range(self.amg.n_levels)]
+
+    def cpr_setup(self, J):
+        """opm_cpr_setup: the CPR workspace for the Jacobian J, and the
+        device status word."""
+        L = lib()
+        nb = L.opm_cpr_bytes(self._pbp())
+        if nb == 0:
+            raise OpmError(EINVAL, "opm_cpr_bytes")
+        cpr = torch.zeros(nb, dtype=torch.uint8, device=self.dev)
+        status = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        _check(L.opm_cpr_setup(self._pbp(), _ptr(J), _ptr(cpr), _ptr(status), _stream()),
+               "opm_cpr_setup")
+        return cpr, status
+
+    def cpr_values(self, cpr, level):
+        """(level matrix values, weights [n][3]) of a set-up CPR workspace."""
+        a = torch.zeros(self.amg.nnz[level], dtype=torch.float64, device=self.dev)
+        w = self.zeros_state()
+        _check(lib().opm_cpr_values(self._pbp(), _ptr(cpr), level, _ptr(a), _ptr(w), _stream()),
+               "opm_cpr_values")
+        return a, w
+
+    def cpr_vcycle(self, cpr, b):
+        x = torch.zeros(self.n, dtype=torch.float64, device=self.dev)
+        _check(lib().opm_cpr_vcycle(self._pbp(), _ptr(cpr), _ptr(b), _ptr(x), _stream()),
+               "opm_cpr_vcycle")
+        return x
+
+    def cpr_apply(self, J, ilu, cpr, r, precision=PREC_FP64):
+        z = self.zeros_state()
+        _check(lib().opm_cpr_apply(self._pbp(), _ptr(J), _ptr(ilu), precision, _ptr(cpr), _ptr(r),
+                                   _ptr(z), _stream()), "opm_cpr_apply")
+        return z
+
+    def bicgstab_cpr(self, J, ilu, cpr, b, rtol=1e-6, maxit=500, precision=PREC_FP64):
+        L = lib()
+        x = self.zeros_state()
+        work = self.workspace("krylov", L.opm_krylov_bytes(self._pbp()))
+        rep = SolveReport()
+        _check(L.opm_bicgstab_cpr(self._pbp(), _ptr(J), _ptr(ilu), precision, _ptr(cpr), _ptr(b),
+                                  _ptr(x), rtol, maxit, _ptr(work), ctypes.byref(rep), _stream()),
+               "opm_bicgstab_cpr")
+        return x, rep
 
     # ------------------------------------------------------------ helpers
     def _pbp(self):
