@@ -119,26 +119,27 @@ def gmres_cycle_bytes(n: int, nnzb: int, m: int, apply_bytes: float) -> float:
 
 
 def cpr_apply_bytes(levels, n: int, nnzb: int, apply_bytes: float) -> float:
-    """Bytes of one CPR application as designed: b_0 = w^T r (w and r read,
-    b_0 written); per level above the coarsest the pre-smoothing (b, D read,
-    x written), the restricted residual (the level's CSR values, columns and
-    row pointers, b and x read, child lists read, the coarse b written), the
-    prolongation (aggregate map and coarse solution read, x read and
-    written) and the post-smoothing (CSR, D, b, x read, y written); the
-    coarsest level's inverse read; the second-stage residual (the pressure
-    column of J with its columns and row pointers, x_p, r read, r2 written);
-    the ILU(0) solve (apply_bytes); z_p += x_p."""
-    total = 56.0 * n
-    for l in range(len(levels) - 1):
+    """Bytes of one CPR application as designed (one kernel per level down
+    and up): down at level 0 the CSR values, columns and row pointers, the
+    diagonal, the weights and r read, b_0 and the residual written; down at
+    level l the CSR, the diagonal, the child lists and the finer residual
+    read, b_l and the residual written; the coarsest level's child lists,
+    finer residual and inverse read, its solution written; up at level l the
+    CSR, the diagonal, b_l, the aggregate map and the coarser solution read,
+    the level's solution written; the second-stage residual (the compact
+    pressure column of J with its columns and row pointers, x_p and r read,
+    r2 written); the ILU(0) solve (apply_bytes); z_p += x_p."""
+    L = len(levels)
+    total = 0.0
+    for l in range(L - 1):
         nl, nnz = levels[l]
-        nc = levels[l + 1][0]
-        csr = 12.0 * nnz + 4.0 * (nl + 1)
-        total += 24.0 * nl                                # pre-smoothing
-        total += csr + 16.0 * nl + 4.0 * (nl + nc + 1) + 8.0 * nc   # restriction
-        total += 4.0 * nl + 8.0 * nc + 16.0 * nl          # prolongation
-        total += csr + 32.0 * nl                          # post-smoothing
+        csr = 12.0 * nnz + 4.0 * (nl + 1) + 8.0 * nl
+        src = 48.0 * nl if l == 0 else 4.0 * (nl + 1) + 12.0 * levels[l - 1][0]
+        total += csr + src + 16.0 * nl                                  # down
+        total += csr + 8.0 * nl + 4.0 * nl + 8.0 * levels[l + 1][0] + 8.0 * nl   # up
     nc = levels[-1][0]
-    total += 8.0 * nc * nc + 16.0 * nc
+    src = 48.0 * nc if L == 1 else 4.0 * (nc + 1) + 12.0 * levels[-2][0]
+    total += src + 8.0 * nc * nc + 8.0 * nc
     total += 28.0 * nnzb + 4.0 * (n + 1) + 8.0 * n + 48.0 * n   # second-stage residual
     return total + apply_bytes + 24.0 * n
 
@@ -146,10 +147,12 @@ def cpr_apply_bytes(levels, n: int, nnzb: int, apply_bytes: float) -> float:
 def cpr_setup_bytes(levels, n: int, nnzb: int) -> float:
     """Bytes of one CPR setup as designed: the diagonal blocks and the
     pressure column of every block of J read with the pattern, weights,
-    level-0 values and diagonal written; per coarse level its gather lists
-    and the finer values read, its values and diagonal written; the
-    coarsest matrix read and its inverse written."""
-    total = 72.0 * n + 24.0 * nnzb + 4.0 * (n + 1) + 4.0 * n + 24.0 * n + 8.0 * nnzb + 8.0 * n
+    level-0 values and diagonal and the compact pressure column written;
+    per coarse level its gather lists and the finer values read, its values
+    and diagonal written; the coarsest matrix read and its inverse
+    written."""
+    total = (72.0 * n + 24.0 * nnzb + 4.0 * (n + 1) + 4.0 * n + 24.0 * n + 8.0 * nnzb + 8.0 * n +
+             24.0 * nnzb)
     for l in range(1, len(levels)):
         nl, nnz = levels[l]
         total += 12.0 * levels[l - 1][1] + 4.0 * (nnz + 1) + 8.0 * nnz + 4.0 * nl + 8.0 * nl
@@ -555,8 +558,22 @@ def bench_kernels(args):
     kern["cpr_apply"] = (
         lambda: L.opm_cpr_apply(pbb, sp(Jb_), sp(bilu[0]), 0, sp(cpr_k), sp(R), sp(x), st),
         cpr_apply_bytes(lv, n, g.nnzb, block_sweep_bytes_per_cell(0) * n),
-        f"V(1,1) cycle over {len(lv)} levels ({'/'.join(str(a) for a, _ in lv)} unknowns) + "
-        "k_cpr_r2 + k_apply_blocks (FP64) + k_cpr_add")
+        f"V(1,1) cycle over {len(lv)} levels ({'/'.join(str(a) for a, _ in lv)} unknowns: "
+        f"{len(lv) - 1} x k_cpr_down + k_cpr_coarse + {len(lv) - 1} x k_cpr_up) + k_cpr_r2 + "
+        "k_apply_blocks (FP64) + k_cpr_add")
+    # a whole linear solve (BiCGStab to 1e-6) with either preconditioner: the
+    # iterations CPR saves against its dearer application
+    kwork = torch.empty(L.opm_krylov_bytes(pbb), dtype=torch.uint8, device=g.dev)
+    srep = {"ilu0": opm.SolveReport(), "cpr": opm.SolveReport()}
+    xs = g.zeros_state()
+    kern["solve_block_ilu0"] = (
+        lambda: L.opm_bicgstab(pbb, sp(Jb_), sp(bilu[0]), 0, sp(R), sp(xs), 1e-6, 1000,
+                               sp(kwork), ctypes.byref(srep["ilu0"]), st),
+        0, "BiCGStab to 1e-6 with the FP64 block ILU0 (whole solve)")
+    kern["solve_cpr"] = (
+        lambda: L.opm_bicgstab_cpr(pbb, sp(Jb_), sp(bilu[0]), 0, sp(cpr_k), sp(R), sp(xs), 1e-6,
+                                   1000, sp(kwork), ctypes.byref(srep["cpr"]), st),
+        0, "BiCGStab to 1e-6 with CPR-AMG + FP64 block ILU0 (whole solve)")
     if args.kernels:
         keep = set(args.kernels.split(","))
         kern = {k: v for k, v in kern.items() if k in keep}
@@ -565,6 +582,11 @@ def bench_kernels(args):
         t = timed(fn)
         res[name] = {"kernel": kname, "us": round(t * 1e6, 2), "bytes": int(nbytes),
                      "gbs": round(nbytes / t / 1e9, 1), "frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4)}
+        if name.startswith("solve_"):
+            rp_ = srep["ilu0" if name == "solve_block_ilu0" else "cpr"]
+            res[name] = {"kernel": kname, "us": round(t * 1e6, 2), "its": rp_.its,
+                         "half": rp_.half, "status": rp_.status}
+            continue
         if name == "gmres_cycle":
             assert grep.its == m and grep.status == opm.ENOTCONV, (grep.its, grep.status)
             res[name]["us_per_iteration"] = round(t * 1e6 / m, 2)

@@ -625,10 +625,9 @@ int opm_cpr_vcycle(const opm_problem* pb, const void* cpr, const double* b, doub
     return OPM_EINVAL;
   hipStream_t s = as_stream(stream);
   const CprWork w = cpr_carve(pb, const_cast<void*>(cpr));
-  const size_t bytes = sizeof(double) * pb->n_cells;
-  OPM_TRY_HIP(hipMemcpyAsync(w.b[0], b, bytes, hipMemcpyDeviceToDevice, s));
-  OPM_TRY(cpr_vcycle(pb, w, s, nullptr));
-  OPM_TRY_HIP(hipMemcpyAsync(x, w.y[0], bytes, hipMemcpyDeviceToDevice, s));
+  OPM_TRY(cpr_vcycle(pb, w, nullptr, b, s, nullptr));
+  OPM_TRY_HIP(hipMemcpyAsync(x, w.y[0], sizeof(double) * pb->n_cells, hipMemcpyDeviceToDevice,
+                             s));
   return OPM_OK;
 }
 
