@@ -224,3 +224,49 @@ def test_cpr_rejections(opm):
         g.newton_step(y, g.initial_state(), DAY, opm.default_opts(c, precond=opm.PRECOND_CPR))
     with pytest.raises(opm.OpmError):
         g.newton_step(y, g.initial_state(), DAY, opm.default_opts(c, precond=2))
+
+
+def test_cpr_full_size_c5(opm):
+    """The 500k-cell system at full size: every level's matrix and the
+    weights against the oracle's, the V-cycle and z = CPR(r) with the
+    single-block ILU(0) against the oracle's, and BiCGStab with CPR and the
+    block ILU0 on 4x4x50 columns (the benchmark's launch configuration)
+    solving to the tolerance on the oracle's operator."""
+    c = cases.config5(seed=5008)
+    m = oracle.Model(c)
+    y = cases.random_state(c, seed=9)
+    st, R, J = m.assemble(y, m.accumulation(cases.random_state(c, seed=10)), c.report_dt[0])
+    assert st == 0
+    cp = m.cpr(J)
+    g = opm.GpuModel(c)
+    Jd = _dev(g, J)
+    cpr, status = g.cpr_setup(Jd)
+    assert int(status.item()) == 0
+    assert g.amg.n_levels == cp.nl == 6
+    for l in range(cp.nl):
+        a_g, w_g = g.cpr_values(cpr, l)
+        rp, ci, a_o, _ = cp.level(l)
+        rowmax = np.maximum.reduceat(np.abs(a_o), rp[:-1]) + 1e-300
+        err = np.abs(a_g.cpu().numpy() - a_o) / np.repeat(rowmax, np.diff(rp))
+        assert err.max() <= 1e-13, f"level {l}"
+    w_o = cp.weights()
+    assert (np.abs(w_g.cpu().numpy() - w_o) / np.abs(w_o).max(axis=1, keepdims=True)).max() <= 1e-13
+    b = np.random.default_rng(9).standard_normal(m.n)
+    x_o = cp.vcycle(b)
+    x_g = g.cpr_vcycle(cpr, _dev(g, b)).cpu().numpy()
+    assert np.abs(x_g - x_o).max() <= 1e-8 * np.abs(x_o).max()
+    st, F = m.ilu0(J)
+    assert st == 0
+    ilu, st = g.ilu0_factor(Jd)
+    z_o = cp.apply(F, R)
+    z_g = g.cpr_apply(Jd, ilu, cpr, _dev(g, R)).cpu().numpy()
+    assert (np.abs(z_g - z_o) / (np.abs(z_o).max(axis=0) + 1e-300)).max() <= 1e-8
+    del ilu, F
+    gb = opm.GpuModel(c, ilu_blocks=(4, 4, 50))
+    Jb = _dev(gb, J)
+    cprb, _ = gb.cpr_setup(Jb)
+    bilu, _ = gb.ilu0_factor(Jb)
+    x, rep = gb.bicgstab_cpr(Jb, bilu, cprb, _dev(gb, -R), rtol=1e-6)
+    assert rep.status == 0
+    res = -R - m.spmv(J, x.cpu().numpy())
+    assert np.linalg.norm(res) <= 1.01e-6 * np.linalg.norm(R)
