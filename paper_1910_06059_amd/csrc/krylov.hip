@@ -66,8 +66,9 @@ __device__ __forceinline__ double sum_partials(const double* part, int G, double
   return kry::sum_partials<kBlock>(part, G, sh);
 }
 
+template <int NT = kBlock>
 __device__ __forceinline__ void store_partial(double v, double* part, double* sh) {
-  const double s = block_sum<kBlock>(v, sh);
+  const double s = block_sum<NT>(v, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -141,15 +142,16 @@ __global__ __launch_bounds__(kBlock) void k_begin(int N, Work w, int G) {
 
 // v = A p^ (with standard wells the Schur-complement operator, wc) ;
 // partials of <r^, v>.
-__global__ __launch_bounds__(kBlock) void k_spmv_rv(int n, const int32_t* row_ptr,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_spmv_rv(int n, const int32_t* row_ptr,
                                                      const int32_t* col, const double* J, Work w,
                                                      WellCorr wc) {
-  __shared__ double sh[kBlock / kWave];
+  __shared__ double sh[NT / kWave];
   if (w.sc->state != kRunning) return;
   double acc = 0.0;
   const int lane = threadIdx.x & (kWave - 1), ng = spmv_groups(n);
-  for (int g = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; g < ng;
-       g += gridDim.x * (kBlock / kWave)) {
+  for (int g = blockIdx.x * (NT / kWave) + threadIdx.x / kWave; g < ng;
+       g += gridDim.x * (NT / kWave)) {
     int row, comp;
     double yv;
     if (spmv_group(n, row_ptr, col, J, w.ph, g, lane, row, comp, yv, wc)) {
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_rv(int n, const int32_t* row_pt
       acc += w.rh[3 * row + comp] * yv;
     }
   }
-  store_partial(acc, w.part_rv, sh);
+  store_partial<NT>(acc, w.part_rv, sh);
 }
 
 // alpha = rho / <r^, v>; s = r - alpha v; partials of <s, s>.
@@ -188,22 +190,22 @@ __global__ __launch_bounds__(kBlock) void k_s_check(Work w, int G) {
 // t = A s^ ; partials of <t, s> and <t, t>.  With CHECK, first the
 // half-step exit test on the nss partials of <s, s> (written by the sweep
 // that computed s).
-template <bool CHECK>
-__global__ __launch_bounds__(kBlock) void k_spmv_t(int n, const int32_t* row_ptr,
+template <bool CHECK, int NT>
+__global__ __launch_bounds__(NT) void k_spmv_t(int n, const int32_t* row_ptr,
                                                     const int32_t* col, const double* J, Work w,
                                                     int nss, WellCorr wc) {
-  __shared__ double sh[kBlock / kWave];
+  __shared__ double sh[NT / kWave];
   __shared__ int word;
   if (CHECK) {
     const int state = kry::read_state(w.sc, &word);
-    if (!kry::half_step_check<kBlock>(*w.sc, state, w.part_ss, nss, sh)) return;
+    if (!kry::half_step_check<NT>(*w.sc, state, w.part_ss, nss, sh)) return;
   } else if (w.sc->state != kRunning) {
     return;
   }
   double ts = 0.0, tt = 0.0;
   const int lane = threadIdx.x & (kWave - 1), ng = spmv_groups(n);
-  for (int g = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; g < ng;
-       g += gridDim.x * (kBlock / kWave)) {
+  for (int g = blockIdx.x * (NT / kWave) + threadIdx.x / kWave; g < ng;
+       g += gridDim.x * (NT / kWave)) {
     int row, comp;
     double yv;
     if (spmv_group(n, row_ptr, col, J, w.sh, g, lane, row, comp, yv, wc)) {
@@ -212,8 +214,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_t(int n, const int32_t* row_ptr
       tt += yv * yv;
     }
   }
-  store_partial(ts, w.part_ts, sh);
-  store_partial(tt, w.part_tt, sh);
+  store_partial<NT>(ts, w.part_ts, sh);
+  store_partial<NT>(tt, w.part_tt, sh);
 }
 
 // omega = <t,s>/<t,t>; x += alpha p^ + omega s^; r = s - omega t; partials of
@@ -358,29 +360,52 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
     return cpr ? cpr_apply(pb, J, ilu, precision, *cpr, r, z, st, &w.sc->state)
                : ilu_apply(pb, ilu, precision, r, z, st, &w.sc->state);
   };
+  // With the grid capped at kMaxGrid workgroups (large systems) the two
+  // SpMVs with reductions run 512-thread workgroups, twice the resident
+  // waves of 256-thread ones over the same number of partial sums.
+  const bool wide = spmv_blocks(n) > kMaxGrid;
+  auto spmv_rv = [&](hipStream_t st) {
+    if (wide)
+      hipLaunchKernelGGL(k_spmv_rv<2 * kBlock>, dim3(Gr), dim3(2 * kBlock), 0, st, n,
+                         pb->row_ptr, pb->col_idx, J, w, wc);
+    else
+      hipLaunchKernelGGL(k_spmv_rv<kBlock>, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
+                         pb->col_idx, J, w, wc);
+  };
+  auto spmv_t = [&](hipStream_t st, bool check) {
+    const int nss = check ? pb->n_sub : 0;
+    if (wide && check)
+      hipLaunchKernelGGL((k_spmv_t<true, 2 * kBlock>), dim3(Gr), dim3(2 * kBlock), 0, st, n,
+                         pb->row_ptr, pb->col_idx, J, w, nss, wc);
+    else if (wide)
+      hipLaunchKernelGGL((k_spmv_t<false, 2 * kBlock>), dim3(Gr), dim3(2 * kBlock), 0, st, n,
+                         pb->row_ptr, pb->col_idx, J, w, nss, wc);
+    else if (check)
+      hipLaunchKernelGGL((k_spmv_t<true, kBlock>), dim3(Gr), dim3(kBlock), 0, st, n,
+                         pb->row_ptr, pb->col_idx, J, w, nss, wc);
+    else
+      hipLaunchKernelGGL((k_spmv_t<false, kBlock>), dim3(Gr), dim3(kBlock), 0, st, n,
+                         pb->row_ptr, pb->col_idx, J, w, nss, wc);
+  };
   auto enqueue_chunk = [&](hipStream_t st) -> int {
     for (int c = 0; c < chunk; ++c) {
       if (fused) {
         OPM_TRY(ilu_apply_fused(pb, ilu, precision, kry::kFuseBegin, fb, w.ph, st));
         if (ws) OPM_TRY(well_op(*ws, w.ph, &w.sc->state, st));
-        hipLaunchKernelGGL(k_spmv_rv, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
-                           pb->col_idx, J, w, wc);
+        spmv_rv(st);
         OPM_TRY(ilu_apply_fused(pb, ilu, precision, kry::kFuseS, fs, w.sh, st));
         if (ws) OPM_TRY(well_op(*ws, w.sh, &w.sc->state, st));
-        hipLaunchKernelGGL(k_spmv_t<true>, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
-                           pb->col_idx, J, w, pb->n_sub, wc);
+        spmv_t(st, true);
       } else {
         hipLaunchKernelGGL(k_begin, dim3(G), dim3(kBlock), 0, st, N, w, G);
         OPM_TRY(prec(w.p, w.ph, st));
         if (ws) OPM_TRY(well_op(*ws, w.ph, &w.sc->state, st));
-        hipLaunchKernelGGL(k_spmv_rv, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
-                           pb->col_idx, J, w, wc);
+        spmv_rv(st);
         hipLaunchKernelGGL(k_s, dim3(G), dim3(kBlock), 0, st, N, w, Gr);
         hipLaunchKernelGGL(k_s_check, dim3(1), dim3(kBlock), 0, st, w, G);
         OPM_TRY(prec(w.s, w.sh, st));
         if (ws) OPM_TRY(well_op(*ws, w.sh, &w.sc->state, st));
-        hipLaunchKernelGGL(k_spmv_t<false>, dim3(Gr), dim3(kBlock), 0, st, n, pb->row_ptr,
-                           pb->col_idx, J, w, 0, wc);
+        spmv_t(st, false);
       }
       hipLaunchKernelGGL(k_x, dim3(G), dim3(kBlock), 0, st, N, x, w, Gr);
       OPM_TRY_HIP(hipGetLastError());
