@@ -432,11 +432,14 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
   }
   for (int pass = 0;; ++pass) {
     hipGraphExec_t exec = nullptr;
-    // the first chunk of a solve runs eagerly (it also sets the kernels'
-    // LDS attributes outside any capture)
-    if (g_krylov_graph == 1 && pass > 0) {
+    if (g_krylov_graph == 1)
       for (auto& cg : g_chunk_graphs)
         if (same_key(cg.key, key)) exec = cg.exec;
+    // a chunk with no graph yet runs eagerly the first time (which also sets
+    // the kernels' LDS attributes outside any capture) and is captured the
+    // next time; once captured, every chunk of every solve with the same
+    // arguments is a replay
+    if (g_krylov_graph == 1 && (exec || pass > 0)) {
       if (!exec) {
         hipGraph_t graph;
         hipStream_t cs;
