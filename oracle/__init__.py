@@ -112,7 +112,9 @@ def lib(path: Optional[str] = None):
         L.ora_advance.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.POINTER(Opts),
                                   ctypes.POINTER(Report)]
         L.ora_dense_solve.argtypes = [ctypes.c_int, _dp, _dp]
-        L.ora_set_standard_wells.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.ora_set_standard_wells.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.ora_get_well_ctrl.argtypes = [ctypes.c_void_p, _ip]
+        L.ora_set_well_ctrl.argtypes = [ctypes.c_void_p, _ip]
         L.ora_set_standard_wells.restype = ctypes.c_int
         L.ora_get_well_state.argtypes = [ctypes.c_void_p, _dp]
         L.ora_set_well_state.argtypes = [ctypes.c_void_p, _dp]
@@ -205,8 +207,10 @@ class Model:
         self.std_wells = bool(getattr(case, "standard_wells", False))
         if self.std_wells:
             vol, x0 = case.standard_well_init()
+            lim = np.ascontiguousarray(case.standard_well_limits(), dtype=np.float64)
             st = L.ora_set_standard_wells(self.h, _d(np.ascontiguousarray(vol, dtype=np.float64)),
-                                          _d(np.ascontiguousarray(x0, dtype=np.float64)))
+                                          _d(np.ascontiguousarray(x0, dtype=np.float64)),
+                                          _d(lim))
             if st != OK:
                 raise ValueError("oracle: invalid standard wells")
 
@@ -265,6 +269,15 @@ class Model:
 
     def set_well_state(self, x):
         self.L.ora_set_well_state(self.h, _d(np.ascontiguousarray(x, dtype=np.float64)))
+
+    def well_ctrl(self) -> np.ndarray:
+        """Active control per well: 0 its own, 1 its limit."""
+        c = np.zeros(max(self.nw, 1), np.int32)
+        self.L.ora_get_well_ctrl(self.h, _i(c))
+        return c[:self.nw]
+
+    def set_well_ctrl(self, c):
+        self.L.ora_set_well_ctrl(self.h, _i(np.ascontiguousarray(c, dtype=np.int32)))
 
     def well_storage_start(self):
         self.L.ora_well_storage_start(self.h)
@@ -380,11 +393,13 @@ class Model:
                 self.set_meaning(self.case.initial_meaning())
             if self.std_wells:
                 self.set_well_state(self.case.standard_well_init()[1])
+                self.set_well_ctrl(np.zeros(self.nw, np.int32))
         else:
             y = np.array(y0, dtype=np.float64)
         states, reps = [], []
         self.run_meanings = []
         self.run_well_states = []
+        self.run_well_ctrls = []
         for dt in self.case.report_dt[:n_steps]:
             st, y, rep = self.advance(y, dt, opts)
             if st != OK:
@@ -393,6 +408,7 @@ class Model:
             self.run_meanings.append(self.meaning().copy())
             if self.std_wells:
                 self.run_well_states.append(self.well_state().copy())
+                self.run_well_ctrls.append(self.well_ctrl().copy())
             reps.append(rep.as_dict())
         return states, reps
 

@@ -145,6 +145,8 @@ struct ora_model {
   int std_wells;         /* 1: standard well model with well unknowns */
   double* well_vol;      /* [nw] wellbore volume V_w */
   double* wx;            /* [nw][4] well state (Q_t, F_w, F_g, p_bhp) */
+  double* well_limit;    /* [nw] limit of the other control, 0 = none */
+  int* wctrl;            /* [nw] active control: 0 the well's own, 1 its limit */
   double* wA0;           /* [nw][3] wellbore storage at the start of the step */
 };
 
@@ -160,7 +162,7 @@ void ora_destroy(ora_model* m) {
   free(m->col_idx); free(m->well_kind); free(m->well_phase); free(m->well_target);
   free(m->well_beg); free(m->conn_cell); free(m->conn_wi); free(m->conn_well);
   free(m->mean);
-  free(m->well_vol); free(m->wx); free(m->wA0);
+  free(m->well_vol); free(m->wx); free(m->wA0); free(m->well_limit); free(m->wctrl);
   free(m);
 }
 
@@ -1028,18 +1030,66 @@ static void std_conn_rate(const ora_model* m, int q, const double* y, const doub
   }
 }
 
-int ora_set_standard_wells(ora_model* m, const double* well_vol, const double* x0) {
+int ora_set_standard_wells(ora_model* m, const double* well_vol, const double* x0,
+                           const double* limits) {
   if (m->nw == 0) return ORA_EINVAL;
   for (int w = 0; w < m->nw; ++w)
-    if (!(well_vol[w] >= 0.0)) return ORA_EINVAL;
-  free(m->well_vol); free(m->wx); free(m->wA0);
+    if (!(well_vol[w] >= 0.0) || (limits && !(limits[w] >= 0.0))) return ORA_EINVAL;
+  free(m->well_vol); free(m->wx); free(m->wA0); free(m->well_limit); free(m->wctrl);
   m->well_vol = (double*)malloc(sizeof(double) * m->nw);
   m->wx = (double*)malloc(sizeof(double) * 4 * m->nw);
   m->wA0 = (double*)calloc(3 * (size_t)m->nw, sizeof(double));
+  m->well_limit = (double*)calloc((size_t)m->nw, sizeof(double));
+  m->wctrl = (int*)calloc((size_t)m->nw, sizeof(int));
   memcpy(m->well_vol, well_vol, sizeof(double) * m->nw);
   memcpy(m->wx, x0, sizeof(double) * 4 * m->nw);
+  if (limits) memcpy(m->well_limit, limits, sizeof(double) * m->nw);
   m->std_wells = 1;
   return ORA_OK;
+}
+
+void ora_get_well_ctrl(const ora_model* m, int* ctrl) {
+  if (m->std_wells) memcpy(ctrl, m->wctrl, sizeof(int) * m->nw);
+}
+
+void ora_set_well_ctrl(ora_model* m, const int* ctrl) {
+  if (m->std_wells)
+    for (int w = 0; w < m->nw; ++w) m->wctrl[w] = ctrl[w] != 0 && m->well_limit[w] > 0.0;
+}
+
+/* Control switching (sec. 2.2.1 names BHP and rate controls; the rule is a
+ * reading): a well with a limit runs on its own control (BHP for a
+ * producer, the surface rate of one component for an injector) until the
+ * limit is exceeded (a producer's oil surface rate above it, an injector's
+ * BHP above it), then on the limit (Q_o = limit, p_bhp = limit) until its
+ * own control binds again (the producer's BHP below its target, the
+ * injector's rate above its target).  Checked on the well state after
+ * every Newton update. */
+static double well_frac(const double* x, int a) {
+  return a == 0 ? x[1] : a == 2 ? x[2] : 1.0 - x[1] - x[2];
+}
+
+static void well_switch(const ora_model* m) {
+  for (int w = 0; w < m->nw; ++w) {
+    if (!(m->well_limit[w] > 0.0)) continue;
+    const double* x = m->wx + 4 * w;
+    int* c = m->wctrl + w;
+    if (m->well_kind[w] == ORA_WELL_BHP_PROD) {
+      const double qo = well_frac(x, 1) * x[0] / kWellG[1];
+      if (*c == 0 && qo > m->well_limit[w]) *c = 1;
+      else if (*c == 1 && x[3] < m->well_target[w]) *c = 0;
+    } else {
+      const int ph = m->well_phase[w];
+      const double inj = -well_frac(x, ph) * x[0] / kWellG[ph];
+      if (*c == 0 && x[3] > m->well_limit[w]) *c = 1;
+      else if (*c == 1 && inj > m->well_target[w]) *c = 0;
+    }
+  }
+}
+
+/* The target of the active control. */
+static double active_target(const ora_model* m, int w) {
+  return m->wctrl[w] ? m->well_limit[w] : m->well_target[w];
 }
 
 void ora_get_well_state(const ora_model* m, double* x) {
@@ -1094,11 +1144,15 @@ int ora_well_system(const ora_model* m, const double* y, double dt, double* Rw, 
         for (int k = 0; k < 4; ++k) C[12 * q + 4 * a + k] = qr[a].d[3 + k];
       }
     }
-    if (m->well_kind[w] == ORA_WELL_BHP_PROD) {
+    if (m->well_kind[w] == ORA_WELL_BHP_PROD && m->wctrl[w] == 0) {
       R[3] = dsub(W.pb, dconst(m->well_target[w]));
-    } else {
+    } else if (m->well_kind[w] == ORA_WELL_BHP_PROD) {   /* oil surface rate at the limit */
+      R[3] = dsub(dscale(dmul(W.F[1], W.Qt), 1.0 / kWellG[1]), dconst(m->well_limit[w]));
+    } else if (m->wctrl[w] == 0) {
       const int ph = m->well_phase[w];
       R[3] = dadd(dscale(dmul(W.F[ph], W.Qt), 1.0 / kWellG[ph]), dconst(m->well_target[w]));
+    } else {   /* injector at its BHP limit */
+      R[3] = dsub(W.pb, dconst(m->well_limit[w]));
     }
     for (int e = 0; e < 4; ++e) {
       Rw[4 * w + e] = R[e].v;
@@ -1476,7 +1530,7 @@ int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double 
         const double bw_a = exp(m->fl.c[a] * (m->wx[4 * w + 3] - m->fl.p_ref));
         cmax = fmax(cmax, dt * fabs(Rw[4 * w + a]) / (bw_a * vref));
       }
-      cmax = fmax(cmax, fabs(Rw[4 * w + 3]) / fabs(m->well_target[w]));
+      cmax = fmax(cmax, fabs(Rw[4 * w + 3]) / fabs(active_target(m, w)));
     }
     if (cmax <= o->tol_cnv && mmax <= o->tol_mb) { status = ORA_OK; break; }
     if (it >= o->max_newton) { status = ORA_ENOTCONV; break; }
@@ -1548,6 +1602,7 @@ int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double 
       }
       x[3] += dpb;
     }
+    if (nw > 0) well_switch(m);
     rep->t_update += now_s() - t0;
     rep->newton_its++;
     rep->cell_newton_its += (double)n;
@@ -1609,9 +1664,12 @@ int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts*
   unsigned char* mn = (unsigned char*)malloc((size_t)m->n + 1);
   const size_t wbytes = m->std_wells ? sizeof(double) * 4 * m->nw : 0;
   double* wn = (double*)malloc(wbytes + sizeof(double));
+  const size_t cbytes = m->std_wells ? sizeof(int) * m->nw : 0;
+  int* cn = (int*)malloc(cbytes + sizeof(int));
   memcpy(yn, y, sizeof(double) * N);
   memcpy(mn, m->mean, (size_t)m->n);
   if (wbytes) memcpy(wn, m->wx, wbytes);
+  if (cbytes) memcpy(cn, m->wctrl, cbytes);
   memset(rep, 0, sizeof(*rep));
   double t = 0.0, dt_try = dt_report;
   int status = ORA_OK;
@@ -1637,12 +1695,14 @@ int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts*
       memcpy(yn, y, sizeof(double) * N);
       memcpy(mn, m->mean, (size_t)m->n);
       if (wbytes) memcpy(wn, m->wx, wbytes);
+      if (cbytes) memcpy(cn, m->wctrl, cbytes);
       t += dt;
       rep->substeps++;
     } else {
       memcpy(y, yn, sizeof(double) * N);
       memcpy(m->mean, mn, (size_t)m->n);
       if (wbytes) memcpy(m->wx, wn, wbytes);
+      if (cbytes) memcpy(m->wctrl, cn, cbytes);
       dt_try = 0.5 * dt;
       rep->cuts++;
       if (rep->cuts > o->max_cuts) { status = st; break; }
@@ -1652,5 +1712,6 @@ int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts*
   free(yn);
   free(mn);
   free(wn);
+  free(cn);
   return status;
 }

@@ -175,7 +175,15 @@ int ora_advance(const ora_model* m, double* y, double dt, const ora_opts* o, ora
  * [nw][4] initial well state.  The well state is held by the model like the
  * variable meaning; ora_newton_step / ora_advance solve the coupled system
  * by the Schur complement (eq. wellequation). */
-int ora_set_standard_wells(ora_model* m, const double* well_vol, const double* x0);
+int ora_set_standard_wells(ora_model* m, const double* well_vol, const double* x0,
+                           const double* limits);
+/* limits [nw] (may be NULL = none): the other control of each well, 0 =
+ * none: an injector's maximum BHP, a BHP producer's maximum oil surface
+ * rate.  The active control (0 the well's own, 1 its limit) switches after
+ * each Newton update when the inactive constraint is violated, and is held
+ * by the model with the well state (restored on a time-step cut). */
+void ora_get_well_ctrl(const ora_model* m, int* ctrl);
+void ora_set_well_ctrl(ora_model* m, const int* ctrl);
 void ora_get_well_state(const ora_model* m, double* x);
 void ora_set_well_state(ora_model* m, const double* x);
 /* Record the wellbore storage of the current well state as the storage at

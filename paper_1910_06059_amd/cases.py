@@ -64,6 +64,9 @@ class Well:
     target: float                   # surface rate [m^3/s] (injector) or BHP [Pa]
     phase: int = W                  # injected component (injectors only)
     rw: float = 0.25 * FT           # wellbore radius [m]
+    # standard wells: the limit of the other control, 0 = none (an injector's
+    # maximum BHP [Pa]; a BHP producer's maximum oil surface rate [m^3/s])
+    limit: float = 0.0
 
 
 @dataclasses.dataclass
@@ -124,6 +127,10 @@ class Case:
                 x0[n] = (0.0, 1.0 if w.phase == W else 0.0, 1.0 if w.phase == GAS else 0.0,
                          self.p_init)
         return vol, x0
+
+    def standard_well_limits(self) -> np.ndarray:
+        """[nw] limits of the standard wells' other controls (0 = none)."""
+        return np.array([float(w.limit) for w in self.wells])
 
     def initial_meaning(self) -> np.ndarray:
         """[n_active] meaning of the third variable: 0 s_g, 1 r_go (the

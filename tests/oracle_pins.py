@@ -1033,7 +1033,7 @@ def pin_std_simplified_limit(lib_path=None):
     c.standard_wells = True
     m = _model(c, lib_path)
     vol, x0 = c.standard_well_init()
-    st = m.L.ora_set_standard_wells(m.h, oracle._d(vol * 1e-9), oracle._d(x0))
+    st = m.L.ora_set_standard_wells(m.h, oracle._d(vol * 1e-9), oracle._d(x0), None)
     assert st == 0
     states, _ = m.run(n_steps=3)
     states_std = states
@@ -1051,7 +1051,7 @@ def pin_std_controls_and_storage(lib_path=None):
     c = _std_case()
     m = _model(c, lib_path)
     vol, x0 = c.standard_well_init()
-    st = m.L.ora_set_standard_wells(m.h, oracle._d(vol * 2000.0), oracle._d(x0))
+    st = m.L.ora_set_standard_wells(m.h, oracle._d(vol * 2000.0), oracle._d(x0), None)
     assert st == 0
     c.report_dt = [2 * DAY] * 4
     states, reps = m.run()
@@ -1060,6 +1060,62 @@ def pin_std_controls_and_storage(lib_path=None):
         assert abs(x[0, 1] * x[0, 0] + 400 * STB / DAY) <= 1e-9 * 400 * STB / DAY
         assert x[0, 1] == 1.0 and x[0, 2] == 0.0
         assert abs(x[1, 3] - 3000 * PSI) <= 1e-6 * 3000 * PSI
+
+
+def _switch_case(inj_limit_psi, prod_limit_stb):
+    c = cases.config1()
+    c.standard_wells = True
+    c.wells[0].limit = inj_limit_psi * PSI
+    c.wells[1].limit = prod_limit_stb * STB / DAY
+    return c
+
+
+def _oil_rate(x):
+    return (1.0 - x[1] - x[2]) * x[0]   # g_o = 1
+
+
+def pin_std_control_switching(lib_path=None):
+    """Two-constraint wells: a limit that never binds changes nothing (the
+    same bits as no limit); once a limit binds the well holds it with
+    equality (the gas injector at its BHP limit, injecting less than its
+    target; the producer at its oil-rate limit, above its BHP target), and at
+    every report step the inactive constraint is satisfied, through a switch
+    back from the rate limit to the BHP target as the reservoir depletes;
+    every step conserves mass."""
+    c0 = cases.config1()
+    c0.standard_wells = True
+    m0 = _model(c0, lib_path)
+    s0, _ = m0.run(n_steps=3)
+    m1 = _model(_switch_case(1e6, 1e6), lib_path)
+    s1, _ = m1.run(n_steps=3)
+    for a, b in zip(s0, s1):
+        assert np.array_equal(a, b)
+    assert all(not c.any() for c in m1.run_well_ctrls)
+    # both limits bind from the first step
+    c = _switch_case(7000, 1500)
+    m = _model(c, lib_path)
+    states, reps = m.run()
+    inj_t, pmin = c.wells[0].target, c.wells[1].target
+    for r, x, ctrl in zip(reps, m.run_well_states, m.run_well_ctrls):
+        assert max(r["mass_err"]) <= 1e-9, r["mass_err"]
+        assert list(ctrl) == [1, 1]
+        assert abs(x[0, 3] - 7000 * PSI) <= 1e-7 * 7000 * PSI
+        assert 0.0 < -x[0, 2] * x[0, 0] / 0.01 < inj_t
+        assert abs(_oil_rate(x[1]) - 1500 * STB / DAY) <= 1e-7 * 1500 * STB / DAY
+        assert x[1, 3] > pmin
+    # the producer starts on its rate limit and returns to its BHP target
+    c = _switch_case(4900, 2500)
+    m = _model(c, lib_path)
+    states, reps = m.run()
+    hist = [int(ctrl[1]) for ctrl in m.run_well_ctrls]
+    assert hist[0] == 1 and hist[-1] == 0 and hist == sorted(hist, reverse=True), hist
+    lim = 2500 * STB / DAY
+    for r, x, h in zip(reps, m.run_well_states, hist):
+        assert max(r["mass_err"]) <= 1e-9, r["mass_err"]
+        if h == 1:
+            assert abs(_oil_rate(x[1]) - lim) <= 1e-7 * lim and x[1, 3] >= pmin
+        else:
+            assert abs(x[1, 3] - pmin) <= 1e-7 * pmin and _oil_rate(x[1]) <= lim
 
 
 # ---------------------------------------------------------------- CPR-AMG
@@ -1259,7 +1315,8 @@ ALL_PINS = [
     pin_live_jacobian_fd, pin_live_conservation, pin_live_closed_cell,
     pin_live_dissolved_moves_with_oil, pin_live_hydrostatic_column, pin_live_depletion_1d,
     pin_std_schur_dense, pin_std_jacobian_fd, pin_std_simplified_limit,
-    pin_std_controls_and_storage, pin_cpr_weights_decouple, pin_cpr_galerkin_hierarchy,
+    pin_std_controls_and_storage, pin_std_control_switching, pin_cpr_weights_decouple,
+    pin_cpr_galerkin_hierarchy,
     pin_cpr_exact_second_stage, pin_cpr_vcycle_converges, pin_cpr_two_grid,
     pin_cpr_fewer_iterations,
     pin_cpr_newton,

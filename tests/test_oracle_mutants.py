@@ -113,6 +113,15 @@ MUTANTS = [
     ("std_rate_control_sign",
      "R[3] = dadd(dscale(dmul(W.F[ph], W.Qt), 1.0 / kWellG[ph]), dconst(m->well_target[w]));",
      "R[3] = dsub(dscale(dmul(W.F[ph], W.Qt), 1.0 / kWellG[ph]), dconst(m->well_target[w]));"),
+    ("std_switch_rate_compare", "if (*c == 0 && qo > m->well_limit[w]) *c = 1;",
+     "if (*c == 0 && qo < m->well_limit[w]) *c = 1;"),
+    ("std_switch_back_reversed", "else if (*c == 1 && x[3] < m->well_target[w]) *c = 0;",
+     "else if (*c == 1 && x[3] > m->well_target[w]) *c = 0;"),
+    ("std_rate_limit_wrong_phase",
+     "R[3] = dsub(dscale(dmul(W.F[1], W.Qt), 1.0 / kWellG[1]), dconst(m->well_limit[w]));",
+     "R[3] = dsub(dscale(dmul(W.F[0], W.Qt), 1.0 / kWellG[0]), dconst(m->well_limit[w]));"),
+    ("std_injector_limit_uses_target", "R[3] = dsub(W.pb, dconst(m->well_limit[w]));",
+     "R[3] = dsub(W.pb, dconst(m->well_target[w]));"),
 ]
 
 
