@@ -327,6 +327,19 @@ typedef struct opm_problem {
   /* CPR-AMG hierarchy (host struct holding device arrays), or NULL: needed
    * for opm_newton_opts.precond = OPM_PRECOND_CPR and opm_cpr_*. */
   const opm_amg* amg;
+  /* Control limits of standard wells (sec. 2.2.1 BHP and rate controls),
+   * or NULL for none.  well_limit [n_wells] (device): the other control of
+   * each well, 0 = none: an injector's maximum BHP [Pa], a BHP producer's
+   * maximum oil surface rate [m3/s].  well_ctrl [n_wells] (device, in/out,
+   * part of the state with well_state; required with well_limit): the
+   * active control, 0 the well's own, 1 its limit (control equation
+   * p_bhp - limit, resp. Q_o - limit).  After each Newton update a well on
+   * its own control moves to its limit when the limit is exceeded, and one
+   * on its limit moves back when its own control binds again (a producer's
+   * BHP below its target, an injector's rate above its target);
+   * opm_advance restores the controls with the well state on a cut. */
+  const double* well_limit;
+  int32_t* well_ctrl;
 } opm_problem;
 
 /* Library set-up: checks that the current device is a gfx950 (MI355X) and

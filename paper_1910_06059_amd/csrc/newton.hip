@@ -191,7 +191,7 @@ bool valid_problem(const opm_problem* pb) {
          (pb->n_wells == 0 ||
           (pb->n_wells > 0 && pb->n_conns > 0 && pb->well_conn_ptr && pb->conn_cell &&
            pb->conn_well && pb->well_kind && pb->well_phase && pb->well_target && pb->well_vol &&
-           pb->well_state));
+           pb->well_state && (!pb->well_limit || pb->well_ctrl)));
 }
 
 bool valid_prec(int p) { return p == OPM_PREC_FP64 || p == OPM_PREC_MIXED; }
@@ -342,11 +342,17 @@ int advance(const opm_problem* pb, double* y, const double* y_nm1, double dt,
   // standard wells: the well state likewise
   double* wsave = pb->n_wells > 0 ? carve(pb, opts->precision, work).wells.save : nullptr;
   const size_t wbytes = sizeof(double) * 4 * (size_t)pb->n_wells;
+  // and the wells' active controls
+  int32_t* csave = pb->n_wells > 0 && pb->well_limit
+                       ? carve(pb, opts->precision, work).wells.save_ctrl : nullptr;
+  const size_t cbytes = sizeof(int32_t) * (size_t)pb->n_wells;
   OPM_TRY_HIP(hipMemcpyAsync(y_save, y, bytes, hipMemcpyDeviceToDevice, s));
   if (mean_save)
     OPM_TRY_HIP(hipMemcpyAsync(mean_save, pb->meaning, mbytes, hipMemcpyDeviceToDevice, s));
   if (wsave)
     OPM_TRY_HIP(hipMemcpyAsync(wsave, pb->well_state, wbytes, hipMemcpyDeviceToDevice, s));
+  if (csave)
+    OPM_TRY_HIP(hipMemcpyAsync(csave, pb->well_ctrl, cbytes, hipMemcpyDeviceToDevice, s));
   double t = 0.0, dt_try = dt;
   int status = OPM_OK;
   bool first = true;
@@ -379,6 +385,8 @@ int advance(const opm_problem* pb, double* y, const double* y_nm1, double dt,
         OPM_TRY_HIP(hipMemcpyAsync(mean_save, pb->meaning, mbytes, hipMemcpyDeviceToDevice, s));
       if (wsave)
         OPM_TRY_HIP(hipMemcpyAsync(wsave, pb->well_state, wbytes, hipMemcpyDeviceToDevice, s));
+      if (csave)
+        OPM_TRY_HIP(hipMemcpyAsync(csave, pb->well_ctrl, cbytes, hipMemcpyDeviceToDevice, s));
       t += h;
       report->substeps++;
     } else {
@@ -387,6 +395,8 @@ int advance(const opm_problem* pb, double* y, const double* y_nm1, double dt,
         OPM_TRY_HIP(hipMemcpyAsync(pb->meaning, mean_save, mbytes, hipMemcpyDeviceToDevice, s));
       if (wsave)
         OPM_TRY_HIP(hipMemcpyAsync(pb->well_state, wsave, wbytes, hipMemcpyDeviceToDevice, s));
+      if (csave)
+        OPM_TRY_HIP(hipMemcpyAsync(pb->well_ctrl, csave, cbytes, hipMemcpyDeviceToDevice, s));
       dt_try = 0.5 * h;
       report->cuts++;
       if (report->cuts > opts->max_cuts) {

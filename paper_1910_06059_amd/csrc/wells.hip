@@ -6,7 +6,8 @@
 // are component conservation with wellbore storage (eq. conseq-swell),
 // R_a,w = (V_w mix_a - A0_a,w) / dt + Q_a - sum_j q_a,j, and its control
 // (eq. well-control-bhp: p_bhp - target; eq. well-control-rate: Q_a +
-// target for an injector of component a).  Connection rates and the
+// target for an injector of component a; on a well's limit: p_bhp - limit
+// for an injector, Q_o - limit for a producer).  Connection rates and the
 // wellbore fluid are those of the assembly (assemble_dev.h), so the cell
 // rows (with their blocks C = d(cell residual)/dx_w) and the well rows
 // (B = dR_w/d(cell variables), D = dR_w/dx_w) come from one definition.
@@ -42,13 +43,23 @@ struct WellArgs {
   double* well_state;
   const double* pore_vol;
   const uint8_t* meaning;
+  const double* well_limit;   // null: no limits
+  int32_t* well_ctrl;
   opm_fluid fluid;
 };
 
 WellArgs well_args(const opm_problem* pb) {
+  const bool lim = pb->well_limit != nullptr;
   return WellArgs{pb->n_wells,    pb->well_conn_ptr, pb->conn_cell,   pb->conn_wi,
                   pb->well_kind,  pb->well_phase,    pb->well_target, pb->well_vol,
-                  pb->well_state, pb->pore_vol,      pb->meaning,     pb->fluid};
+                  pb->well_state, pb->pore_vol,      pb->meaning,
+                  lim ? pb->well_limit : nullptr,    lim ? pb->well_ctrl : nullptr,
+                  pb->fluid};
+}
+
+// Active control of well w: 0 its own, 1 its limit.
+__device__ __forceinline__ int well_ctrl(const WellArgs& a, int w) {
+  return a.well_ctrl ? a.well_ctrl[w] : 0;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -145,12 +156,17 @@ __global__ __launch_bounds__(kWellThreads) void k_well_system(WellArgs a, const 
 #pragma unroll
     for (int k = 0; k < 4; ++k) R[e].d[3 + k] -= s[e][1 + k];
   }
-  const double target = a.well_target[w];
-  if (a.well_kind[w] == OPM_WELL_BHP_PROD) {
+  const int ctrl = well_ctrl(a, w);
+  const double target = ctrl ? a.well_limit[w] : a.well_target[w];
+  if (a.well_kind[w] == OPM_WELL_BHP_PROD && ctrl == 0) {
     R[3] = W.pb - cst<7>(target);
-  } else {
+  } else if (a.well_kind[w] == OPM_WELL_BHP_PROD) {   // oil surface rate at the limit
+    R[3] = W.F[1] * W.Qt * (1.0 / well_g(1)) - cst<7>(target);
+  } else if (ctrl == 0) {
     const int ph = a.well_phase[w];
     R[3] = W.F[ph] * W.Qt * (1.0 / well_g(ph)) + cst<7>(target);
+  } else {   // injector at its BHP limit
+    R[3] = W.pb - cst<7>(target);
   }
   double Dw[16];
   for (int e = 0; e < 4; ++e) {
@@ -239,10 +255,16 @@ __global__ __launch_bounds__(kBlock) void k_sub_corr(int n, const int32_t* ccp, 
 // Well unknowns after the reservoir solve: d_w = D^{-1} (R_w - B d_r), and
 // x_w -= d_w with |d p_bhp| <= dp_max_rel |p_bhp|, the fraction pair
 // scaled to at most ds_max, fractions kept in [0, 1] with F_w + F_g <= 1.
-__global__ __launch_bounds__(kWellThreads) void k_well_update(WellSchur ws, const double* Rw,
-                                                               const double* d, double* wx,
-                                                               double ds_max, double dp_max_rel,
-                                                               int32_t* flags) {
+// Then the control switch of a well with a limit (sec. 2.2.1 names BHP and
+// rate controls; the rule is a reading): on its own control it moves to
+// the limit when the limit is exceeded (a producer's oil surface rate, an
+// injector's BHP above it), on the limit back to its own control when that
+// binds again (the producer's BHP below its target, the injector's rate
+// above its target).
+__global__ __launch_bounds__(kWellThreads) void k_well_update(WellSchur ws, WellArgs a,
+                                                               const double* Rw, const double* d,
+                                                               double* wx, double ds_max,
+                                                               double dp_max_rel, int32_t* flags) {
   const int w = blockIdx.x;
   double t[4], u[4];
   sum_bx(ws.well_conn_ptr, ws.conn_cell, ws.B, d, w, t);
@@ -270,6 +292,23 @@ __global__ __launch_bounds__(kWellThreads) void k_well_update(WellSchur ws, cons
   }
   x[3] += dpb;
   if (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2]) || !isfinite(x[3])) flags[1] = 1;
+  if (a.well_ctrl && a.well_limit[w] > 0.0) {
+    const int c = a.well_ctrl[w];
+    const double limit = a.well_limit[w], target = a.well_target[w];
+    int next = c;
+    if (a.well_kind[w] == OPM_WELL_BHP_PROD) {
+      const double qo = (1.0 - x[1] - x[2]) * x[0] / well_g(1);
+      if (c == 0 && qo > limit) next = 1;
+      else if (c == 1 && x[3] < target) next = 0;
+    } else {
+      const int ph = a.well_phase[w];
+      const double f = ph == 0 ? x[1] : ph == 2 ? x[2] : 1.0 - x[1] - x[2];
+      const double inj = -f * x[0] / well_g(ph);
+      if (c == 0 && x[3] > limit) next = 1;
+      else if (c == 1 && inj > target) next = 0;
+    }
+    a.well_ctrl[w] = next;
+  }
 }
 
 inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
@@ -280,7 +319,8 @@ size_t wells_bytes(const opm_problem* pb) {
   if (pb->n_wells <= 0) return 0;
   const size_t nw = pb->n_wells, nc = pb->n_conns;
   return al256(8 * 4 * nw) + 2 * al256(8 * 12 * nc) + 2 * al256(8 * 16 * nw) +
-         al256(8 * 3 * nc) + al256(8 * 3 * nw) + al256(8 * nw) + al256(8 * 4 * nw);
+         al256(8 * 3 * nc) + al256(8 * 3 * nw) + al256(8 * nw) + al256(8 * 4 * nw) +
+         al256(4 * nw);
 }
 
 WellWork wells_carve(const opm_problem* pb, void* p) {
@@ -304,6 +344,8 @@ WellWork wells_carve(const opm_problem* pb, void* p) {
   w.wn = (double*)c;
   c += al256(8 * nw);
   w.save = (double*)c;
+  c += al256(8 * 4 * nw);
+  w.save_ctrl = (int32_t*)c;
   return w;
 }
 
@@ -359,7 +401,8 @@ int well_op(const WellSchur& ws, const double* x, const int32_t* skip, hipStream
 int well_update(const opm_problem* pb, const WellWork& ww, const double* d, double ds_max,
                 double dp_max_rel, int32_t* flags, hipStream_t s) {
   hipLaunchKernelGGL(k_well_update, dim3(pb->n_wells), dim3(kWellThreads), 0, s,
-                     well_schur(pb, ww), ww.Rw, d, pb->well_state, ds_max, dp_max_rel, flags);
+                     well_schur(pb, ww), well_args(pb), ww.Rw, d, pb->well_state, ds_max,
+                     dp_max_rel, flags);
   OPM_TRY_HIP(hipGetLastError());
   return OPM_OK;
 }

@@ -41,6 +41,7 @@ int well_op(const WellSchur& ws, const double* x, const int32_t* skip, hipStream
 // [nw][3], the wells' convergence measures [nw] and a saved state [nw][4].
 struct WellWork {
   double *Rw, *B, *C, *D, *Dinv, *corr, *A0, *wn, *save;
+  int32_t* save_ctrl;   // the active controls saved with the well state
 };
 size_t wells_bytes(const opm_problem* pb);
 WellWork wells_carve(const opm_problem* pb, void* p);

@@ -67,7 +67,8 @@ class Problem(ctypes.Structure):
                 ("sub_level_ptr", _vp), ("slot", _vp), ("meaning", _vp),
                 ("n_wells", _i32), ("pad_w", _i32), ("well_conn_ptr", _vp), ("conn_cell", _vp),
                 ("conn_well", _vp), ("well_kind", _vp), ("well_phase", _vp), ("well_target", _vp),
-                ("well_vol", _vp), ("well_state", _vp), ("amg", _vp)]
+                ("well_vol", _vp), ("well_state", _vp), ("amg", _vp), ("well_limit", _vp),
+                ("well_ctrl", _vp)]
 
 
 AMG_MAX_LEVELS, AMG_COARSE = 12, 64
@@ -432,6 +433,13 @@ class GpuModel:
             self.pb.well_target = self.well_target.data_ptr()
             self.pb.well_vol = self.well_vol.data_ptr()
             self.pb.well_state = self.well_state_t.data_ptr()
+            # control limits (zero = none) and the active controls
+            lim = case.standard_well_limits()
+            self.well_ctrl_t = torch.zeros(max(nw, 1), dtype=torch.int32, device=self.dev)
+            if (lim > 0).any():
+                self.well_limit = torch.tensor(lim, **f64)
+                self.pb.well_limit = self.well_limit.data_ptr()
+                self.pb.well_ctrl = self.well_ctrl_t.data_ptr()
         self._work = {}
         self.amg = self._build_amg(host) if amg else None
         if amg:
@@ -517,6 +525,7 @@ class GpuModel:
         self.set_meaning(self.case.initial_meaning())
         if self.std_wells:
             self.set_well_state(self.case.standard_well_init()[1])
+            self.well_ctrl_t.zero_()
         return self.state(self.case.initial_state())
 
     def set_well_state(self, x) -> None:
@@ -525,6 +534,13 @@ class GpuModel:
 
     def well_state(self) -> np.ndarray:
         return self.well_state_t.cpu().numpy().copy()
+
+    def well_ctrl(self) -> np.ndarray:
+        """Active control per standard well: 0 its own, 1 its limit."""
+        return self.well_ctrl_t.cpu().numpy()[:self.nw].copy()
+
+    def set_well_ctrl(self, c) -> None:
+        self.well_ctrl_t[:self.nw].copy_(torch.as_tensor(np.ascontiguousarray(c, dtype=np.int32)))
 
     def assemble_wells(self, y, acc0, well_state0, dt):
         """opm_assemble_wells: (R, J, Rw, B, C, D) on the device."""
@@ -657,6 +673,7 @@ class GpuModel:
         states, reps = [], []
         self.run_meanings = []
         self.run_well_states = []
+        self.run_well_ctrls = []
         for dt in self.case.report_dt[:n_steps]:
             st, rep = self.advance(y, dt, opts)
             if st != OK:
@@ -667,6 +684,7 @@ class GpuModel:
                     self.run_meanings.append(self.meaning())
                 if self.std_wells:
                     self.run_well_states.append(self.well_state())
+                    self.run_well_ctrls.append(self.well_ctrl())
             reps.append(rep.as_dict())
         return y, states, reps
 

@@ -184,3 +184,38 @@ def test_wells_rejections(opm):
     nb = L.opm_ensemble_bytes(members, 1, 0)
     ens = torch.empty(max(nb, 256), dtype=torch.uint8, device=g.dev)
     assert L.opm_ensemble_prepare(members, ys, 1, 0, ens.data_ptr(), nb) == opm.EINVAL
+
+
+def _limits(c, inj_psi, prod_stb):
+    c.wells[0].limit = inj_psi * PSI
+    c.wells[1].limit = prod_stb * STB / DAY
+    return c
+
+
+@pytest.mark.parametrize("name,inj,prod", [("C1_both_limits", 7000, 1500),
+                                           ("C1_switch_back", 4900, 2500),
+                                           ("C6_live", 3500, 2500)])
+def test_wells_control_switching(opm, name, inj, prod):
+    """Wells with limits on their other control: the active controls after
+    every report step equal the oracle's (both limits binding; a producer
+    that returns from its oil-rate limit to its BHP target; live oil), and
+    the reservoir and well states match to 1e-6."""
+    c = _limits(_c6() if name == "C6_live" else _c1(), inj, prod)
+    g = opm.GpuModel(c)
+    m = oracle.Model(c)
+    n = 10
+    ostates, oreps = m.run(n_steps=n)
+    y, gstates, greps = g.run(n_steps=n)
+    for s, (cg, co) in enumerate(zip(g.run_well_ctrls, m.run_well_ctrls)):
+        assert list(cg) == list(co), f"step {s}: controls {cg} against {co}"
+    hist = [int(cc[1]) for cc in m.run_well_ctrls]
+    assert hist[0] == 1 and (name == "C1_both_limits" or hist[-1] == 0)
+    if c.fluid.live:
+        for s, (yg, yo) in enumerate(zip(gstates, ostates)):
+            assert np.abs(yg[:, 0] - yo[:, 0]).max() <= 1e-6 * np.abs(yo[:, 0]).max(), s
+        for xg, xo in zip(g.run_well_states, m.run_well_states):
+            assert np.abs(xg[:, 3] - xo[:, 3]).max() <= 1e-6 * np.abs(xo[:, 3]).max()
+    else:
+        _compare_run(c, gstates, g.run_well_states, ostates, m.run_well_states, name)
+    for rg, ro in zip(greps, oreps):
+        assert abs(rg["newton_its"] - ro["newton_its"]) <= 1
