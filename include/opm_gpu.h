@@ -544,13 +544,13 @@ size_t opm_newton_work_bytes(const opm_problem* pb, const opm_newton_opts* opts)
  * With opts->krylov = OPM_KRYLOV_GMRES, work must hold
  * opm_newton_work_bytes.  With standard wells (pb->n_wells > 0) each
  * iteration also assembles the well equations, solves the reservoir system
- * with BiCGStab on the Schur complement (A - sum C D^-1 B) (the ILU(0) of A
- * as preconditioner; GMRes is refused with OPM_EINVAL), recovers the well
- * update and updates pb->well_state (|dp_bhp| <= dp_max_rel p_bhp, the
- * fraction pair scaled to ds_max and kept in [0, 1]); convergence also
- * requires every well's component residuals (dt |R_a,w| / (b_a(p_bhp)
- * PV_perforated)) and its control residual relative to its target to be
- * below tol_cnv.  pb->well_state at entry is the state at the start of the
+ * with the chosen Krylov method on the Schur complement (A - sum C D^-1 B)
+ * (the preconditioner built from A alone), recovers the well update and
+ * updates pb->well_state (|dp_bhp| <= dp_max_rel p_bhp, the fraction pair
+ * scaled to ds_max and kept in [0, 1]) and, with limits, pb->well_ctrl;
+ * convergence also requires every well's component residuals
+ * (dt |R_a,w| / (b_a(p_bhp) PV_perforated)) and its control residual
+ * relative to its active target to be below tol_cnv.  pb->well_state at entry is the state at the start of the
  * step (its wellbore storage). */
 int opm_newton_step(const opm_problem* pb, double* y, const double* y_prev, double dt,
                     const opm_newton_opts* opts, void* work, opm_newton_report* report,

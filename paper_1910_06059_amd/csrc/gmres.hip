@@ -187,7 +187,7 @@ template <bool RES>
 __global__ __launch_bounds__(kBlock) void k_gm_spmv(int n, const int32_t* row_ptr,
                                                      const int32_t* col, const double* J,
                                                      const double* x, const double* b, double* y,
-                                                     const GmScalars* sc, int want) {
+                                                     const GmScalars* sc, int want, WellCorr wc) {
   __shared__ int word;
   const int st = read_state(sc, &word);
   if (RES ? st == kGmDone : st != want) return;
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_spmv(int n, const int32_t* row_pt
   if (group >= ilu::spmv_groups(n)) return;   // whole wavefront
   int row, comp;
   double yv;
-  if (ilu::spmv_group(n, row_ptr, col, J, x, group, lane, row, comp, yv))
+  if (ilu::spmv_group(n, row_ptr, col, J, x, group, lane, row, comp, yv, wc))
     y[3 * row + comp] = RES ? b[3 * row + comp] - yv : yv;
 }
 
@@ -475,9 +475,11 @@ size_t gmres_bytes(const opm_problem* pb, int restart) {
 }
 
 // cpr (may be null): CPR-AMG set up for J, with ilu as its second stage.
+// ws (may be null): standard wells, solved through their Schur complement
+// (the operator subtracts sum_w C_w D_w^{-1} B_w of its argument).
 int gmres(const opm_problem* pb, const double* J, void* ilu, int precision, const double* b,
           double* x, double rtol, int maxit, int restart, void* work, opm_solve_report* rep,
-          hipStream_t st, const CprWork* cpr) {
+          hipStream_t st, const CprWork* cpr, const WellSchur* ws) {
   if (restart < 1 || restart > kMaxRestart || maxit < 0) return OPM_EINVAL;
   const int n = pb->n_cells, N = 3 * n, m = restart;
   GmWork w = gm_carve(n, m, work);
@@ -488,9 +490,11 @@ int gmres(const opm_problem* pb, const double* J, void* ilu, int precision, cons
   OPM_TRY_HIP(hipGetLastError());
   const int chunk = 6;
   GmHostView v{};
+  const WellCorr wc = ws ? ws->wc() : WellCorr{nullptr, nullptr, nullptr};
   for (int cycle = 0;; ++cycle) {
+    if (ws) OPM_TRY(well_op(*ws, x, nullptr, st));
     hipLaunchKernelGGL(k_gm_spmv<true>, dim3(Gs), dim3(kBlock), 0, st, n, pb->row_ptr,
-                       pb->col_idx, J, x, b, w.V, w.sc, 0);
+                       pb->col_idx, J, x, b, w.V, w.sc, 0, wc);
     hipLaunchKernelGGL(k_gm_norm0, dim3(G), dim3(kGmBlock), 0, st, N, w);
     hipLaunchKernelGGL(k_gm_start, dim3(1), dim3(kGmBlock), 0, st, w, G);
     hipLaunchKernelGGL(k_gm_scale0, dim3(G), dim3(kGmBlock), 0, st, N, w);
@@ -503,8 +507,9 @@ int gmres(const opm_problem* pb, const double* J, void* ilu, int precision, cons
           OPM_TRY(cpr_apply(pb, J, ilu, precision, *cpr, vj, zj, st, &w.sc->state));
         else
           OPM_TRY(ilu_apply(pb, ilu, precision, vj, zj, st, &w.sc->state));
+        if (ws) OPM_TRY(well_op(*ws, zj, &w.sc->state, st));
         hipLaunchKernelGGL(k_gm_spmv<false>, dim3(Gs), dim3(kBlock), 0, st, n, pb->row_ptr,
-                           pb->col_idx, J, zj, nullptr, w.w, w.sc, (int)kGmRunning);
+                           pb->col_idx, J, zj, nullptr, w.w, w.sc, (int)kGmRunning, wc);
         if (j < 4)
           launch_projections<4>(w, j, N, G, st);
         else if (j < 8)

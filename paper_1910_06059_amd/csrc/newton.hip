@@ -33,7 +33,7 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
 size_t gmres_bytes(const opm_problem* pb, int restart);
 int gmres(const opm_problem* pb, const double* J, void* ilu, int precision, const double* b,
           double* x, double rtol, int maxit, int restart, void* work, opm_solve_report* rep,
-          hipStream_t st, const CprWork* cpr = nullptr);
+          hipStream_t st, const CprWork* cpr = nullptr, const WellSchur* ws = nullptr);
 
 int guess_infer(const opm_problem* pb, const opm_guess_net* net, const double* y_n,
                 const double* y_nm1, double* y_guess, void* work, hipStream_t s,
@@ -261,7 +261,7 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
     if (std_wells) OPM_TRY(well_rhs(pb, ww, w.R, s));   // R_r - sum C D^-1 R_w
     if (o->krylov == OPM_KRYLOV_GMRES)
       OPM_TRY(gmres(pb, w.J, w.ilu, o->precision, w.R, w.d, o->lin_rtol, o->lin_maxit, o->restart,
-                    w.krylov, &lr, s, use_cpr ? &cw : nullptr));
+                    w.krylov, &lr, s, use_cpr ? &cw : nullptr, std_wells ? &ws : nullptr));
     else
       OPM_TRY(bicgstab(pb, w.J, w.ilu, o->precision, w.R, w.d, o->lin_rtol, o->lin_maxit,
                        w.krylov, &lr, s, std_wells ? &ws : nullptr, use_cpr ? &cw : nullptr));
@@ -612,10 +612,9 @@ static bool valid_amg(const opm_problem* pb) {
   return true;
 }
 
-// Standard wells are solved with BiCGStab only; CPR needs the hierarchy.
+// CPR needs the hierarchy.
 static bool valid_wells_opts(const opm_problem* pb, const opm_newton_opts* o) {
-  return (pb->n_wells == 0 || o->krylov == OPM_KRYLOV_BICGSTAB) &&
-         (o->precond == OPM_PRECOND_ILU0 || valid_amg(pb));
+  return o->precond == OPM_PRECOND_ILU0 || valid_amg(pb);
 }
 
 size_t opm_cpr_bytes(const opm_problem* pb) {
