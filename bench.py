@@ -608,8 +608,10 @@ def main():
                     help="timed report steps (default: 30 for c2, 10 for c3, 20 for c4)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c3-mixed", "c4-ensemble", "c5-guess", "c5-kernels", "c6-live"],
-                    help="c2: the headline metric line; c6-live: the same line on a 24x25x15 "
+                    choices=["c2", "c3-mixed", "c4-ensemble", "c5", "c5-guess", "c5-kernels",
+                             "c6-live"],
+                    help="c2: the headline metric line; c5: the same line on the 500k-cell "
+                         "waterflood (100x100x50); c6-live: the same line on a 24x25x15 "
                          "live-oil depletion with phase appearance; c3-mixed: FP32 ILU(0) vs FP64 on the "
                          "masked 45k-cell grid; c4-ensemble: 64 members in one launch; "
                          "c5-guess: learned Newton guess on the 500k-cell waterflood; "
@@ -678,7 +680,11 @@ def main():
     if args.steps is None:
         args.steps = 30
     live = args.workload == "c6-live"
-    if live:
+    if args.workload == "c5":
+        case = cases.config5(seed=5008)
+        workload = ("100x100x50 waterflood, 500000 cells (4 injectors, 5 producers), 10-day "
+                    "implicit steps")
+    elif live:
         case = cases.config_live(nx=24, ny=25, nz=15)
         workload = ("24x25x15 live-oil depletion (bubble point 3000 psi, producer at 2500 psi: "
                     "free gas appears), 9000 cells, 15-day implicit steps")
@@ -808,7 +814,7 @@ def main():
     achieved = k["bytes"] / k["seconds"] / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": None if live else measured_traffic(dom, args.precision),
+                "traffic": measured_traffic(dom, args.precision) if args.workload == "c2" else None,
                 "kernel": k["kernel"], "avg_launch_us": round(k["seconds"] * 1e6, 3),
                 "bytes_per_launch": int(k["bytes"])}
 
