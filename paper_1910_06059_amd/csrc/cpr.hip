@@ -345,27 +345,30 @@ __global__ __launch_bounds__(kBlock) void k_cpr_up(int n, const int32_t* row_ptr
 }
 
 // Second-stage residual r2 = r - A x1 with x1 = (x_p, 0, 0) per cell, from
-// the compact pressure column of J: 21 lanes per row (entry, component),
-// three rows per wavefront, summed in entry order.
+// the compact pressure column of J: seven lanes per row (one entry each,
+// its three values in one 24-byte run), summed in entry order.
 __global__ __launch_bounds__(kBlock) void k_cpr_r2(int n, const int32_t* row_ptr,
                                                     const int32_t* col, const double* jp,
                                                     const double* r, const double* xp,
                                                     double* r2, const int32_t* skip) {
   if (skip && *skip != 0) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-  const int rl = lane / 21, rem = lane - 21 * rl;
-  const int k = rem / 3, c = rem - 3 * k;
-  const int i = wave * 3 + rl;
-  const bool live = lane < 63 && i < n;
-  double p = 0.0;
-  if (live)
-    for (int q = row_ptr[i] + k; q < row_ptr[i + 1]; q += kRowLanes)
-      p += jp[3 * (size_t)q + c] * xp[col[q]];
-  double t = 0.0;
-#pragma unroll
-  for (int k2 = 0; k2 < kRowLanes; ++k2) t += __shfl(p, lane + 3 * k2, kWave);
-  if (live && k == 0) r2[3 * i + c] = r[3 * i + c] - t;
+  const RowLane rl = row_lane(n);
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+  if (rl.live)
+    for (int q = row_ptr[rl.row] + rl.k; q < row_ptr[rl.row + 1]; q += kRowLanes) {
+      const double* B = jp + 3 * (size_t)q;
+      const double xj = xp[col[q]];
+      p0 += B[0] * xj;
+      p1 += B[1] * xj;
+      p2 += B[2] * xj;
+    }
+  const double t0 = row_sum(p0), t1 = row_sum(p1), t2 = row_sum(p2);
+  if (rl.live && rl.k == 0) {
+    const int i = rl.row;
+    r2[3 * i] = r[3 * i] - t0;
+    r2[3 * i + 1] = r[3 * i + 1] - t1;
+    r2[3 * i + 2] = r[3 * i + 2] - t2;
+  }
 }
 
 // z += x1.
@@ -497,8 +500,8 @@ int cpr_apply(const opm_problem* pb, const double* J, void* ilu, int precision, 
   (void)J;
   const int n = pb->n_cells;
   OPM_TRY(cpr_vcycle(pb, w, r, nullptr, s, skip));
-  hipLaunchKernelGGL(k_cpr_r2, dim3(blocks_for(n, 3 * (kBlock / kWave))), dim3(kBlock), 0, s, n,
-                     pb->row_ptr, pb->col_idx, w.jp, r, w.y[0], w.r2, skip);
+  hipLaunchKernelGGL(k_cpr_r2, dim3(row_blocks(n)), dim3(kBlock), 0, s, n, pb->row_ptr,
+                     pb->col_idx, w.jp, r, w.y[0], w.r2, skip);
   OPM_TRY_HIP(hipGetLastError());
   OPM_TRY(ilu_apply(pb, ilu, precision, w.r2, z, s, skip));
   hipLaunchKernelGGL(k_cpr_add, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, n, w.y[0], z,
