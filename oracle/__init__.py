@@ -31,7 +31,8 @@ class Fluid(ctypes.Structure):
                 ("p_ref", ctypes.c_double), ("mu", ctypes.c_double * 3),
                 ("swc", ctypes.c_double), ("n_corey", ctypes.c_double), ("g", ctypes.c_double),
                 ("rs_c", ctypes.c_double), ("bo_r", ctypes.c_double), ("muo_r", ctypes.c_double),
-                ("eps_switch", ctypes.c_double), ("live", ctypes.c_int), ("pad", ctypes.c_int)]
+                ("eps_switch", ctypes.c_double), ("live", ctypes.c_int), ("pad", ctypes.c_int),
+                ("rv_c", ctypes.c_double)]
 
 
 class Opts(ctypes.Structure):
@@ -176,7 +177,7 @@ class Model:
                            (ctypes.c_double * 3)(*f.mu), f.swc, f.n_corey, f.g,
                            getattr(f, "rs_c", 0.0), getattr(f, "bo_r", 0.0),
                            getattr(f, "muo_r", 0.0), getattr(f, "eps_switch", 0.0),
-                           int(getattr(f, "live", False)), 0)
+                           int(getattr(f, "live", False)), 0, getattr(f, "rv_c", 0.0))
         dz = np.ascontiguousarray(case.dz, dtype=np.float64)
         perm = np.ascontiguousarray(case.perm_h, dtype=np.float64).ravel()
         poro = np.ascontiguousarray(case.poro, dtype=np.float64).ravel()

@@ -355,12 +355,17 @@ typedef struct {
   dual rho[3];  /* reservoir densities */
   dual lam[3];  /* mobilities k_r / mu */
   dual r;       /* dissolved gas-oil ratio r_go (0 for dead oil) */
+  dual rv;      /* vaporised oil-gas ratio r_og (0 without wet gas) */
+  int wet;      /* wet gas: the oil component includes r_og b_g s_g */
 } props;
 
 /* Properties of one cell from its (p, s_w, x) and the meaning of x (sec.
  * 2.1.1, eq. primaryVariableMeaning): x = s_g (free gas present; for live
  * oil the oil is then saturated, r_go = r_s(p)) or x = r_go (no free gas,
- * s_g = 0).  Live oil (sec. 2.1.6): r_s(p) = rs_c p; dissolved gas swells
+ * s_g = 0) or, with wet gas, x = r_og (no oil, s_g = 1 - s_w).  Wet gas
+ * (sec. 2.1.6): r_v(p) = rv_c p, saturated where gas and oil coexist; the
+ * vaporised oil adds to the gas density, rho_g = b_g (rho_gS + r_og rho_oS)
+ * (b_g and mu_g unchanged).  Live oil (sec. 2.1.6): r_s(p) = rs_c p; dissolved gas swells
  * the oil, b_o = exp(c_o (p - p_ref)) / (1 + bo_r r), thins it,
  * mu_o = mu_o / (1 + muo_r r), and adds its surface mass to the oil
  * density, rho_o = b_o (rho_oS + r rho_gS). */
@@ -368,8 +373,14 @@ static void cell_props(const ora_fluid* f, const double* y, int off, int mean, p
   P->p = dvar(y[0], off + 0);
   dual sw = dvar(y[1], off + 1);
   dual x = dvar(y[2], off + 2);
-  dual sg = (f->live && mean == 1) ? dconst(0.0) : x;
+  const int wet = f->live && f->rv_c > 0.0;
+  /* meaning 2 (wet gas): no oil, s_g = 1 - s_w, x = r_og */
+  dual sg = (f->live && mean == 1) ? dconst(0.0)
+            : (wet && mean == 2)    ? dsub(dconst(1.0), sw)
+                                    : x;
   P->r = !f->live ? dconst(0.0) : (mean == 1 ? x : dscale(P->p, f->rs_c));
+  P->rv = !wet ? dconst(0.0) : (mean == 2 ? x : dscale(P->p, f->rv_c));
+  P->wet = wet;
   dual so = dsub(dsub(dconst(1.0), sw), sg);   /* s_w + s_o + s_g = 1 */
   P->s[0] = sw; P->s[1] = so; P->s[2] = sg;
   for (int a = 0; a < 3; ++a) {
@@ -381,6 +392,8 @@ static void cell_props(const ora_fluid* f, const double* y, int off, int mean, p
     P->b[1] = ddiv(P->b[1], dadd(dconst(1.0), dscale(P->r, f->bo_r)));
     P->rho[1] = dmul(P->b[1], dadd(dconst(f->rho_s[1]), dscale(P->r, f->rho_s[2])));
   }
+  /* wet gas: the gas density holds the vaporised oil */
+  if (wet) P->rho[2] = dmul(P->b[2], dadd(dconst(f->rho_s[2]), dscale(P->rv, f->rho_s[1])));
   /* Corey two-phase curves with residuals 0 except connate water */
   double den = 1.0 - f->swc;
   dual swn = dclamp01(ddiv(dsub(sw, dconst(f->swc)), dconst(den)));
@@ -407,17 +420,19 @@ static void cell_props(const ora_fluid* f, const double* y, int off, int mean, p
 }
 
 /* Surface volume per pore volume of component a: b_a s_a, plus the gas
- * dissolved in the oil, r b_o s_o, for the gas component. */
+ * dissolved in the oil, r b_o s_o, for the gas component and the oil
+ * vaporised in the gas, r_v b_g s_g, for the oil component (wet gas). */
 static dual component_acc(const props* P, int a) {
   dual A = dmul(P->b[a], P->s[a]);
   if (a == 2) A = dadd(A, dmul(P->r, dmul(P->b[1], P->s[1])));
+  if (a == 1 && P->wet) A = dadd(A, dmul(P->rv, dmul(P->b[2], P->s[2])));
   return A;
 }
 
 int ora_set_meaning(ora_model* m, const unsigned char* mean) {
   for (int c = 0; c < m->n; ++c) {
     const unsigned char v = mean ? mean[c] : 0;
-    if (v > 1 || (v == 1 && !m->fl.live)) return ORA_EINVAL;
+    if (v > 2 || (v >= 1 && !m->fl.live) || (v == 2 && !(m->fl.rv_c > 0.0))) return ORA_EINVAL;
   }
   for (int c = 0; c < m->n; ++c) m->mean[c] = mean ? mean[c] : 0;
   return ORA_OK;
@@ -464,6 +479,8 @@ static void conn_rates(const ora_model* m, int q, const double* y, dual out[3]) 
         out[a] = dmul(dscale(dmul(P.b[a], P.lam[a]), m->conn_wi[q]), dp);
       if (m->fl.live)
         out[2] = dadd(out[2], dmul(dscale(dmul(P.r, dmul(P.b[1], P.lam[1])), m->conn_wi[q]), dp));
+      if (m->fl.live && m->fl.rv_c > 0.0)
+        out[1] = dadd(out[1], dmul(dscale(dmul(P.rv, dmul(P.b[2], P.lam[2])), m->conn_wi[q]), dp));
     }
   }
 }
@@ -528,6 +545,9 @@ int ora_assemble(const ora_model* m, const double* y, const double* acc0, double
       dual F = dmul(dmul(U[a]->b[a], U[a]->lam[a]), dscale(dphi[a], T));
       if (a == 2 && f->live)
         F = dadd(F, dmul(dmul(U[1]->r, dmul(U[1]->b[1], U[1]->lam[1])), dscale(dphi[1], T)));
+      /* wet gas: the oil vaporised in the gas moves with the gas phase */
+      if (a == 1 && f->live && f->rv_c > 0.0)
+        F = dadd(F, dmul(dmul(U[2]->rv, dmul(U[2]->b[2], U[2]->lam[2])), dscale(dphi[2], T)));
       R[3 * i + a] += F.v;
       R[3 * j + a] -= F.v;
       if (J) {
@@ -1024,6 +1044,8 @@ static void std_conn_rate(const ora_model* m, int q, const double* y, const doub
     for (int a = 0; a < 3; ++a) out[a] = dmul(dscale(dmul(P.b[a], P.lam[a]), wi), dp);
     if (m->fl.live)
       out[2] = dadd(out[2], dmul(dscale(dmul(P.r, dmul(P.b[1], P.lam[1])), wi), dp));
+    if (m->fl.live && m->fl.rv_c > 0.0)
+      out[1] = dadd(out[1], dmul(dscale(dmul(P.rv, dmul(P.b[2], P.lam[2])), wi), dp));
   } else {
     dual lt = dadd(dadd(P.lam[0], P.lam[1]), P.lam[2]);
     for (int a = 0; a < 3; ++a) out[a] = dmul(dmul(dscale(lt, wi), dp), W.mix[a]);
@@ -1474,18 +1496,34 @@ static int all_finite(int n, const double* a) {
  * with a threshold against oscillation): free gas gone (s_g < -eps) ->
  * x = r_go = r_s(p), the oil saturated at the switch; dissolved gas above
  * saturation (r_go > r_s(p) (1 + eps)) -> x = s_g = 0, free gas appears from
- * the next iteration on; a negative r_go is set to 0. */
+ * the next iteration on; a negative r_go is set to 0.  Wet gas: oil gone
+ * (s_o < -eps) -> x = r_og = r_v(p); vaporised oil above saturation
+ * (r_og > r_v(p) (1 + eps)) -> x = s_g = 1 - s_w (oil appears from the
+ * next iteration on); a negative r_og is set to 0. */
 static void switch_variable(const ora_fluid* f, double* yc, unsigned char* mean) {
   const double rs = f->rs_c * yc[0];
+  const double rv = f->rv_c * yc[0];
   if (*mean == 0) {
     if (yc[2] < -f->eps_switch) {
       *mean = 1;
       yc[2] = rs;
+    } else if (f->rv_c > 0.0 && 1.0 - yc[1] - yc[2] < -f->eps_switch) {
+      /* wet gas: the oil is gone (s_o < -eps) -> x = r_og = r_v(p) */
+      *mean = 2;
+      yc[2] = rv;
     }
-  } else {
+  } else if (*mean == 1) {
     if (yc[2] > rs * (1.0 + f->eps_switch)) {
       *mean = 0;
       yc[2] = 0.0;
+    } else if (yc[2] < 0.0) {
+      yc[2] = 0.0;
+    }
+  } else {
+    /* vaporised oil above saturation -> oil appears: x = s_g = 1 - s_w */
+    if (yc[2] > rv * (1.0 + f->eps_switch)) {
+      *mean = 0;
+      yc[2] = 1.0 - yc[1];
     } else if (yc[2] < 0.0) {
       yc[2] = 0.0;
     }

@@ -62,6 +62,9 @@ typedef struct ora_fluid {
   double eps_switch; /* threshold of the variable switch (s_g, relative r)  */
   int live;          /* 0 dead oil (x = s_g everywhere), 1 live oil         */
   int pad;
+  /* wet gas (sec. 2.1.6: oil vaporised in the gaseous phase; live oil
+   * only): saturated oil-gas ratio r_v(p) = rv_c p [1/Pa], 0 = dry gas */
+  double rv_c;
 } ora_fluid;
 
 typedef struct ora_opts {

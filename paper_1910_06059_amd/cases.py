@@ -54,6 +54,9 @@ class Fluid:
     bo_r: float = 0.0
     muo_r: float = 0.0
     eps_switch: float = 1e-6
+    # wet gas (oil vaporised in the gas, live oil only): saturated oil-gas
+    # ratio r_v(p) = rv_c p; 0 = dry gas
+    rv_c: float = 0.0
 
 
 @dataclasses.dataclass

@@ -1118,6 +1118,101 @@ def pin_std_control_switching(lib_path=None):
             assert abs(x[1, 3] - pmin) <= 1e-7 * pmin and _oil_rate(x[1]) <= lim
 
 
+# ------------------------------------------------------------- wet gas
+# Oil vaporised in the gas (sec. 2.1.6) with the third meaning x = r_og.
+def _wet_fluid(rv_at_bubble=0.05):
+    fl = cases.live_fluid()
+    fl.rv_c = rv_at_bubble / (3000 * PSI)
+    return fl
+
+
+def _wet_state(c, seed):
+    rng = np.random.default_rng(seed)
+    n = c.n_active
+    mean = rng.integers(0, 3, n).astype(np.uint8)
+    y = np.empty((n, 3))
+    y[:, 0] = rng.uniform(2800, 3200, n) * PSI
+    y[:, 1] = rng.uniform(0.15, 0.4, n)
+    rs, rv = c.fluid.rs_c * y[:, 0], c.fluid.rv_c * y[:, 0]
+    y[:, 2] = np.where(mean == 0, rng.uniform(0.05, 0.3, n),
+                       np.where(mean == 1, rng.uniform(0.3, 0.9, n) * rs,
+                                rng.uniform(0.3, 0.9, n) * rv))
+    return y, mean
+
+
+def pin_wet_jacobian_fd(lib_path=None):
+    """With all three meanings present (s_g, r_go, r_og) and both well
+    kinds, every Jacobian column matches central differences of the
+    residual."""
+    wells = [Well("I", cases.WELL_RATE_INJ, [(0, 0, 0)], 1e4 * 0.0283168 / DAY, phase=cases.GAS),
+             Well("P", cases.WELL_BHP_PROD, [(3, 1, 0)], 2500 * PSI)]
+    c = cases.box_case(4, 2, 2, seed=3, fluid=_wet_fluid(), wells=wells)
+    m = _model(c, lib_path)
+    y, mean = _wet_state(c, 1)
+    assert set(mean) == {0, 1, 2}
+    m.set_meaning(mean)
+    acc0 = m.accumulation(y * 1.01)
+    st, R, J = m.assemble(y, acc0, DAY)
+    rp, ci = m.pattern()
+    scale = np.abs(J).max()
+    for c_ in range(m.n):
+        for v in range(3):
+            h = 1e-6 * max(abs(y[c_, v]), 1e-3)
+            yp, ym = y.copy(), y.copy()
+            yp[c_, v] += h
+            ym[c_, v] -= h
+            fd = (m.assemble(yp, acc0, DAY)[1] - m.assemble(ym, acc0, DAY)[1]) / (2 * h)
+            for i in range(m.n):
+                q = [q for q in range(rp[i], rp[i + 1]) if ci[q] == c_]
+                an = J[q[0]][:, v] if q else np.zeros(3)
+                assert np.abs(fd[i] - an).max() <= 1e-6 * np.abs(fd).max() + 1e-12 * scale
+
+
+def pin_wet_dew_point_continuity(lib_path=None):
+    """A cell at its dew point written either way (x = s_g = 1 - s_w with
+    the gas saturated, or x = r_og = r_v(p) with no oil) gives the same
+    residual."""
+    c = cases.box_case(3, 2, 1, seed=4, fluid=_wet_fluid(), wells=[])
+    m = _model(c, lib_path)
+    y, mean = _wet_state(c, 2)
+    mean[:] = 0
+    y[:, 2] = 0.1
+    k = 2
+    ya, yb = y.copy(), y.copy()
+    ya[k, 2] = 1.0 - ya[k, 1]                  # s_o = 0, meaning 0
+    yb[k, 2] = c.fluid.rv_c * yb[k, 0]          # meaning 2 at saturation
+    mb = mean.copy()
+    mb[k] = 2
+    acc = None
+    m.set_meaning(mean)
+    acc = m.accumulation(y)
+    Ra = m.assemble(ya, acc, DAY)[1]
+    m.set_meaning(mb)
+    Rb = m.assemble(yb, acc, DAY)[1]
+    assert np.abs(Ra - Rb).max() <= 1e-12 * np.abs(Ra).max()
+
+
+def pin_wet_oil_moves_with_gas(lib_path=None):
+    """Between two oil-free cells (x = r_og) the oil component moves only
+    in the gas, upwinded with it: the oil flux is r_og of the upwind cell
+    times the gas flux, in either direction, and the two cells' fluxes
+    cancel."""
+    c = cases.box_case(2, 1, 1, seed=5, fluid=_wet_fluid(), wells=[])
+    m = _model(c, lib_path)
+    m.set_meaning(np.array([2, 2], np.uint8))
+    for hi in (0, 1):
+        y = np.empty((2, 3))
+        y[:, 0] = 3000 * PSI
+        y[hi, 0] = 3100 * PSI
+        y[:, 1] = 0.2
+        y[:, 2] = [0.6 * c.fluid.rv_c * y[0, 0], 0.3 * c.fluid.rv_c * y[1, 0]]
+        acc = m.accumulation(y)
+        R = m.assemble(y, acc, DAY)[1]   # accumulation terms vanish: fluxes only
+        assert abs(R[0, 1] + R[1, 1]) <= 1e-12 * abs(R[0, 1])
+        assert abs(R[0, 2] + R[1, 2]) <= 1e-12 * abs(R[0, 2])
+        assert abs(R[0, 1] - y[hi, 2] * R[0, 2]) <= 1e-12 * abs(R[0, 1])
+
+
 # ---------------------------------------------------------------- CPR-AMG
 # Two-stage CPR preconditioner (sec. 2.3.1) with an aggregation AMG for the
 # pressure stage.
@@ -1315,7 +1410,8 @@ ALL_PINS = [
     pin_live_jacobian_fd, pin_live_conservation, pin_live_closed_cell,
     pin_live_dissolved_moves_with_oil, pin_live_hydrostatic_column, pin_live_depletion_1d,
     pin_std_schur_dense, pin_std_jacobian_fd, pin_std_simplified_limit,
-    pin_std_controls_and_storage, pin_std_control_switching, pin_cpr_weights_decouple,
+    pin_std_controls_and_storage, pin_std_control_switching, pin_wet_jacobian_fd,
+    pin_wet_dew_point_continuity, pin_wet_oil_moves_with_gas, pin_cpr_weights_decouple,
     pin_cpr_galerkin_hierarchy,
     pin_cpr_exact_second_stage, pin_cpr_vcycle_converges, pin_cpr_two_grid,
     pin_cpr_fewer_iterations,

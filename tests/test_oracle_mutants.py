@@ -122,6 +122,11 @@ MUTANTS = [
      "R[3] = dsub(dscale(dmul(W.F[0], W.Qt), 1.0 / kWellG[0]), dconst(m->well_limit[w]));"),
     ("std_injector_limit_uses_target", "R[3] = dsub(W.pb, dconst(m->well_limit[w]));",
      "R[3] = dsub(W.pb, dconst(m->well_target[w]));"),
+    ("wet_vaporised_oil_not_upwinded",
+     "F = dadd(F, dmul(dmul(U[2]->rv, dmul(U[2]->b[2], U[2]->lam[2])), dscale(dphi[2], T)));",
+     "F = dadd(F, dmul(dmul(Pi.rv, dmul(U[2]->b[2], U[2]->lam[2])), dscale(dphi[2], T)));"),
+    ("wet_oil_free_gas_saturation", "            : (wet && mean == 2)    ? dsub(dconst(1.0), sw)",
+     "            : (wet && mean == 2)    ? x"),
 ]
 
 
