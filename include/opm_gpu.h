@@ -84,6 +84,12 @@ typedef struct opm_fluid {
                         -eps_switch, dissolved gas above r_s (1 + eps_switch) */
   int32_t live;      /* 0 dead oil, 1 live oil                               */
   int32_t pad;
+  /* wet gas (sec. 2.1.6: oil vaporised in the gas; live oil only): the
+   * saturated oil-gas ratio r_v(p) = rv_c p [1/Pa]; 0 = dry gas.  With
+   * rv_c > 0 a cell's meaning may also be 2: no oil, s_g = 1 - s_w and
+   * x = r_og (switched to when s_o < -eps_switch, back to x = s_g when
+   * r_og > r_v(p) (1 + eps_switch)). */
+  double rv_c;
 } opm_fluid;
 
 /* Connectivity of a masked nx*ny*nz Cartesian box (host arrays, filled by

@@ -139,6 +139,7 @@ struct FaceProps {
   D3 rho[3];                // densities (live oil: with its dissolved gas)
   D3 mob[3];                // b_alpha * lambda_alpha
   D3 rmob;                  // r b_o lambda_o: dissolved gas carried by the oil (live oil)
+  D3 vmob;                  // r_og b_g lambda_g: oil carried by the gas (wet gas)
   D3 lamt;                  // total mobility sum_alpha lambda_alpha (well injection)
 };
 
@@ -161,6 +162,7 @@ __device__ __forceinline__ FaceProps pick(bool c, const FaceProps& x, const Face
     r.mob[a] = sel(c, x.mob[a], y.mob[a]);
   }
   r.rmob = sel(c, x.rmob, y.rmob);
+  r.vmob = sel(c, x.vmob, y.vmob);
   r.lamt = sel(c, x.lamt, y.lamt);
   return r;
 }
@@ -186,9 +188,14 @@ __device__ __forceinline__ void properties(const opm_fluid& f, double p_v, doubl
   D3 x = cst<3>(x_v);
   x.d[2] = 1.0;
   const bool undersat = LIVE && mean == 1;
-  const D3 sg = undersat ? cst<3>(0.0) : x;
+  // wet gas: meaning 2 = no oil, s_g = 1 - s_w, x = r_og
+  const bool wet = LIVE && f.rv_c > 0.0;
+  const bool oilfree = wet && mean == 2;
+  const D3 sg = undersat ? cst<3>(0.0) : (oilfree ? cst<3>(1.0) - sw : x);
   D3 r = cst<3>(0.0);
   if (LIVE) r = sel(undersat, x, p * f.rs_c);
+  D3 rv = cst<3>(0.0);
+  if (wet) rv = sel(oilfree, x, p * f.rv_c);
   D3 so = (cst<3>(1.0) - sw) - sg;
   D3 b[3];
 #pragma unroll
@@ -217,6 +224,11 @@ __device__ __forceinline__ void properties(const opm_fluid& f, double p_v, doubl
     P.mob[1] = b[1] * lam_o;
     P.rmob = r * P.mob[1];
   }
+  P.vmob = cst<3>(0.0);
+  if (wet) {
+    P.rho[2] = b[2] * (cst<3>(f.rho_s[2]) + rv * f.rho_s[1]);
+    P.vmob = rv * P.mob[2];
+  }
   P.lamt = (krw / f.mu[0] + lam_o) + krg / f.mu[2];
   if (acc) {
     const D3 s[3] = {sw, so, sg};
@@ -226,6 +238,7 @@ __device__ __forceinline__ void properties(const opm_fluid& f, double p_v, doubl
       acc->b[a] = b[a].v;
     }
     if (LIVE) acc->A[2] = acc->A[2] + r * (b[1] * so);
+    if (wet) acc->A[1] = acc->A[1] + rv * (b[2] * sg);
   }
 }
 
@@ -255,6 +268,14 @@ __device__ __forceinline__ D6 face_flux(const FaceProps& L, const FaceProps& H, 
     const D6 dphio = potential(L, H, 1, dz, g);
     D6 rm = dphio.v >= 0.0 ? lift(L.rmob, 0) : lift(H.rmob, 1);
     F = F + rm * (dphio * T);
+  }
+  // wet gas: the oil component adds the vaporised oil, (r_og b_g lambda_g)_Ug
+  // T dPhi_g with the gas phase's potential and upwind cell (zero mobilities
+  // without wet gas)
+  if (LIVE && a == 1) {
+    const D6 dphig = potential(L, H, 2, dz, g);
+    D6 vm = dphig.v >= 0.0 ? lift(L.vmob, 0) : lift(H.vmob, 1);
+    F = F + vm * (dphig * T);
   }
   return F;
 }
@@ -319,6 +340,7 @@ __device__ __forceinline__ void std_conn_rate(const FaceProps& P, const WellVars
 #pragma unroll
     for (int a = 0; a < 3; ++a) q[a] = (lift7(P.mob[a]) * wi) * dp;
     if (LIVE) q[2] = q[2] + (lift7(P.rmob) * wi) * dp;
+    if (LIVE) q[1] = q[1] + (lift7(P.vmob) * wi) * dp;
   } else {
     const D7 lt = (lift7(P.lamt) * wi) * dp;
 #pragma unroll
@@ -447,6 +469,7 @@ __device__ __forceinline__ void assemble_row(const AsmArgs& a, int i, double dt,
 #pragma unroll
         for (int c = 0; c < 3; ++c) r[c] = r[c] + (Pi.mob[c] * a.conn_wi[k]) * dp;
         if (LIVE) r[2] = r[2] + (Pi.rmob * a.conn_wi[k]) * dp;
+        if (LIVE) r[1] = r[1] + (Pi.vmob * a.conn_wi[k]) * dp;
       }
     }
   }

@@ -112,11 +112,13 @@ __global__ void k_clear_flags(int32_t* flags) {
 // non-null) the variable switch follows (eq. primaryVariableMeaning, with a
 // threshold against oscillation, sec. 2.3): free gas below -eps -> x =
 // r_go = r_s(p); dissolved gas above r_s(p) (1 + eps) -> x = s_g = 0; a
-// negative r_go is set to 0.
+// negative r_go is set to 0.  Wet gas (rv_c > 0): oil below -eps (s_o =
+// 1 - s_w - s_g) -> x = r_og = r_v(p); vaporised oil above r_v(p) (1 + eps)
+// -> x = s_g = 1 - s_w; a negative r_og is set to 0.
 __global__ __launch_bounds__(kBlock) void k_update(int n, double* y, const double* d,
                                                     double ds_max, double dp_max_rel,
-                                                    uint8_t* meaning, double rs_c, double eps,
-                                                    int32_t* flags) {
+                                                    uint8_t* meaning, double rs_c, double rv_c,
+                                                    double eps, int32_t* flags) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int mean = meaning ? meaning[i] : 0;
@@ -135,15 +137,25 @@ __global__ __launch_bounds__(kBlock) void k_update(int n, double* y, const doubl
   const double y0 = p + dp, y1 = y[3 * i + 1] + dsw;
   double y2 = y[3 * i + 2] + dx;
   if (meaning) {
-    const double rs = rs_c * y0;
+    const double rs = rs_c * y0, rv = rv_c * y0;
     if (mean == 0) {
       if (y2 < -eps) {
         meaning[i] = 1;
         y2 = rs;
+      } else if (rv_c > 0.0 && 1.0 - y1 - y2 < -eps) {
+        meaning[i] = 2;
+        y2 = rv;
       }
-    } else if (y2 > rs * (1.0 + eps)) {
+    } else if (mean == 1) {
+      if (y2 > rs * (1.0 + eps)) {
+        meaning[i] = 0;
+        y2 = 0.0;
+      } else if (y2 < 0.0) {
+        y2 = 0.0;
+      }
+    } else if (y2 > rv * (1.0 + eps)) {
       meaning[i] = 0;
-      y2 = 0.0;
+      y2 = 1.0 - y1;
     } else if (y2 < 0.0) {
       y2 = 0.0;
     }
@@ -187,7 +199,7 @@ bool valid_problem(const opm_problem* pb) {
          pb->n_levels > 0 && pb->level_ptr_h[pb->n_levels] == pb->n_cells &&
          (pb->fluid.live == 0 || (pb->fluid.live == 1 && pb->meaning && pb->fluid.rs_c >= 0.0 &&
                                   pb->fluid.bo_r >= 0.0 && pb->fluid.muo_r >= 0.0 &&
-                                  pb->fluid.eps_switch >= 0.0)) &&
+                                  pb->fluid.eps_switch >= 0.0 && pb->fluid.rv_c >= 0.0)) &&
          (pb->n_wells == 0 ||
           (pb->n_wells > 0 && pb->n_conns > 0 && pb->well_conn_ptr && pb->conn_cell &&
            pb->conn_well && pb->well_kind && pb->well_phase && pb->well_target && pb->well_vol &&
@@ -283,7 +295,8 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
       OPM_TRY(well_update(pb, ww, w.d, o->ds_max, o->dp_max_rel, w.flags, s));
     uint8_t* mean = pb->fluid.live ? pb->meaning : nullptr;
     hipLaunchKernelGGL(k_update, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, n, y, w.d,
-                       o->ds_max, o->dp_max_rel, mean, pb->fluid.rs_c, pb->fluid.eps_switch,
+                       o->ds_max, o->dp_max_rel, mean, pb->fluid.rs_c, pb->fluid.rv_c,
+                       pb->fluid.eps_switch,
                        w.flags);
     OPM_TRY_HIP(hipGetLastError());
     OPM_TRY_HIP(hipEventRecord(ev.e[4], s));

@@ -38,7 +38,8 @@ class Fluid(ctypes.Structure):
                 ("p_ref", ctypes.c_double), ("mu", ctypes.c_double * 3),
                 ("swc", ctypes.c_double), ("n_corey", ctypes.c_double), ("g", ctypes.c_double),
                 ("rs_c", ctypes.c_double), ("bo_r", ctypes.c_double), ("muo_r", ctypes.c_double),
-                ("eps_switch", ctypes.c_double), ("live", _i32), ("pad", _i32)]
+                ("eps_switch", ctypes.c_double), ("live", _i32), ("pad", _i32),
+                ("rv_c", ctypes.c_double)]
 
 
 class Topology(ctypes.Structure):
@@ -390,7 +391,7 @@ class GpuModel:
         f = case.fluid
         fl = Fluid((ctypes.c_double * 3)(*f.rho_s), (ctypes.c_double * 3)(*f.c), f.p_ref,
                    (ctypes.c_double * 3)(*f.mu), f.swc, f.n_corey, f.g, f.rs_c, f.bo_r, f.muo_r,
-                   f.eps_switch, int(f.live), 0)
+                   f.eps_switch, int(f.live), 0, float(getattr(f, "rv_c", 0.0)))
         self.pb = Problem(
             n_cells=n, n_faces=nf, nnzb=nnzb, n_levels=self.n_levels, max_level=self.max_level,
             n_conns=nc, trans=self.trans.data_ptr(), pore_vol=self.pore_vol.data_ptr(),
@@ -563,8 +564,11 @@ class GpuModel:
         """Meaning of the third variable per cell (0 s_g, 1 r_go), the state
         that goes with y for live oil."""
         m = torch.as_tensor(np.ascontiguousarray(mean, dtype=np.uint8))
-        if m.shape != (self.n,) or (not self.live and bool(m.any())):
-            raise ValueError("meaning: one 0/1 value per cell, all 0 for dead oil")
+        wet = self.live and self.case.fluid.rv_c > 0.0
+        if (m.shape != (self.n,) or (not self.live and bool(m.any())) or
+                bool((m > (2 if wet else 1)).any())):
+            raise ValueError("meaning: one value per cell (0 s_g, 1 r_go, 2 r_og with wet gas), "
+                             "all 0 for dead oil")
         self.meaning_t.copy_(m.to(self.dev))
 
     def meaning(self) -> np.ndarray:

@@ -173,3 +173,83 @@ def test_live_restrictions(opm):
     nb = L.opm_ensemble_bytes(members, 1, 0)
     ens = torch.empty(max(nb, 256), dtype=torch.uint8, device=g.dev)
     assert L.opm_ensemble_prepare(members, ys, 1, 0, ens.data_ptr(), nb) == opm.EINVAL
+
+
+# ------------------------------------------------------------- wet gas
+def _wet_case(name):
+    fl = cases.live_fluid()
+    fl.rv_c = 0.05 / (3000 * PSI)
+    if name == "C6_wet":
+        c = cases.config_live()
+        c.fluid = fl
+        return c
+    c = _live_box(*((5, 4, 3, 3) if name == "box" else (9, 7, 4, 5)), masked=name == "masked")
+    c.fluid = fl
+    return c
+
+
+def _wet_state(c, seed):
+    rng = np.random.default_rng(seed)
+    n = c.n_active
+    mean = rng.integers(0, 3, n).astype(np.uint8)
+    y = np.empty((n, 3))
+    y[:, 0] = rng.uniform(2800, 3200, n) * PSI
+    y[:, 1] = rng.uniform(0.15, 0.4, n)
+    rs, rv = c.fluid.rs_c * y[:, 0], c.fluid.rv_c * y[:, 0]
+    y[:, 2] = np.where(mean == 0, rng.uniform(0.05, 0.3, n),
+                       np.where(mean == 1, rng.uniform(0.3, 0.9, n) * rs,
+                                rng.uniform(0.3, 0.9, n) * rv))
+    return y, mean
+
+
+@pytest.mark.parametrize("name", ["box", "masked", "C6_wet"])
+def test_wet_assembly_parity(opm, name):
+    """Wet gas (oil vaporised in the gas): accumulation, residual, Jacobian
+    and norms with all three meanings against the oracle, at the live-oil
+    tolerances."""
+    c = _wet_case(name)
+    g = opm.GpuModel(c)
+    m = oracle.Model(c)
+    y0, mean0 = _wet_state(c, seed=11)
+    y, mean = _wet_state(c, seed=12)
+    m.set_meaning(mean0)
+    g.set_meaning(mean0)
+    a_o = m.accumulation(y0)
+    a_g = g.accumulation(g.state(y0)).cpu().numpy()
+    assert np.abs(a_g - a_o).max() <= 1e-14 * np.abs(a_o).max()
+    m.set_meaning(mean)
+    g.set_meaning(mean)
+    st, R, J = m.assemble(y, a_o, 2 * DAY)
+    Rg, Jg, norms = g.assemble(g.state(y), g.state(a_o), 2 * DAY)
+    Rg, Jg = Rg.cpu().numpy(), Jg.cpu().numpy()
+    assert (np.abs(Rg - R) / (np.abs(R).max(axis=0) + 1e-300)).max() <= 1e-11
+    Jf, Jgf = J.reshape(-1, 9), Jg.reshape(-1, 9)
+    assert (np.abs(Jgf - Jf) / _colscale(Jf)).max() <= 1e-11
+    cnv, mb = m.norms(y, R, 2 * DAY)
+    ng = norms.cpu().numpy()
+    assert np.allclose(ng[:3], cnv, rtol=1e-9, atol=0)
+
+
+def test_wet_newton_iterates(opm):
+    """Two Newton iterations from a state with all three meanings (linear
+    solves to 1e-12): the iterates, meanings and switches equal the
+    oracle's."""
+    c = _wet_case("C6_wet")
+    g = opm.GpuModel(c)
+    m = oracle.Model(c)
+    y, mean = _wet_state(c, seed=21)
+    m.set_meaning(mean)
+    g.set_meaning(mean)
+    o_o = oracle.default_opts(c, max_newton=2, lin_rtol=1e-12)
+    o_g = opm.default_opts(c, max_newton=2, lin_rtol=1e-12)
+    st_o, yo, rep_o = m.newton_step(y, y, DAY, o_o)
+    yg = g.state(y)
+    st_g, rep_g = g.newton_step(yg, g.state(y), DAY, o_g)
+    assert st_o == st_g and rep_o.newton_its == rep_g.newton_its == 2
+    mg, mo = g.meaning(), m.meaning()
+    assert np.array_equal(mg, mo)
+    yg = yg.cpu().numpy()
+    assert np.abs(yg[:, 0] - yo[:, 0]).max() <= 1e-8 * np.abs(yo[:, 0]).max()
+    assert np.abs(yg[:, 1] - yo[:, 1]).max() <= 1e-8
+    x_scale = np.where(mo == 0, 1.0, np.abs(yo[:, 2]).max())
+    assert (np.abs(yg[:, 2] - yo[:, 2]) / x_scale).max() <= 1e-8
