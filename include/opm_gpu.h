@@ -299,7 +299,8 @@ typedef struct opm_problem {
   /* Meaning of the third primary variable per cell (sec. 2.1.1, eq.
    * primaryVariableMeaning): 0 x = s_g (free gas present; live oil then
    * saturated, r_go = r_s(p)), 1 x = r_go (live oil without free gas,
-   * s_g = 0).  Device [n_cells], part of the state that goes with y:
+   * s_g = 0), 2 x = r_og (wet gas, opm_fluid.rv_c > 0: no oil,
+   * s_g = 1 - s_w).  Device [n_cells], part of the state that goes with y:
    * opm_newton_step / opm_advance update it in place.  NULL for dead oil
    * (every cell 0); required (non-NULL) for live oil. */
   uint8_t* meaning;
@@ -367,7 +368,9 @@ size_t opm_norms_bytes(const opm_problem* pb);
  * component also holds the gas dissolved in the oil (r b_o s_o in the
  * accumulation, r (b_o lambda_o) T dPhi_o upwinded with the oil phase in the
  * flux, r times the oil rate in a producer), and the third Jacobian column
- * of a cell is d/ds_g or d/dr_go by its meaning.  y, acc0: [n][3]; R:
+ * of a cell is d/ds_g, d/dr_go or d/dr_og by its meaning (wet gas adds
+ * r_og b_g s_g to the oil accumulation and r_og (b_g lambda_g) T dPhi_g,
+ * upwinded with the gas phase, to the oil flux).  y, acc0: [n][3]; R:
  * [n][3] out; J: [nnzb][3][3] out (may be NULL for the residual only).
  * norms (may be NULL): device buffer of opm_norms_bytes; its first 8
  * doubles receive CNV_w, CNV_o, CNV_g, MB_w, MB_o, MB_g, max CNV, max MB,

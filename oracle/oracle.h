@@ -120,11 +120,12 @@ void ora_pattern(const ora_model* m, int* row_ptr, int* col_idx);
 /* Well connections: active cell, well index, owning well [n_conns]. */
 void ora_conns(const ora_model* m, int* cell, double* wi, int* well);
 
-/* The per-cell meaning of the third variable (0: s_g, 1: r_go), the state
- * that goes with y: every function below reads the model's current meaning;
- * ora_newton_step / ora_advance update it with y.  Set from `mean` [n] (NULL:
- * every cell 0); dead oil requires all 0.  ORA_EINVAL for a value other
- * than 0 or 1, or 1 with a dead-oil fluid. */
+/* The per-cell meaning of the third variable (0: s_g, 1: r_go, 2: r_og
+ * with wet gas), the state that goes with y: every function below reads
+ * the model's current meaning; ora_newton_step / ora_advance update it with
+ * y.  Set from `mean` [n] (NULL: every cell 0); dead oil requires all 0.
+ * ORA_EINVAL for a value above 2, 1 or 2 with a dead-oil fluid, or 2
+ * without wet gas (rv_c = 0). */
 int ora_set_meaning(ora_model* m, const unsigned char* mean);
 void ora_get_meaning(const ora_model* m, unsigned char* mean);
 

@@ -174,8 +174,12 @@ struct CellAcc {
 
 // b = exp(c (p - p_ref)); rho = rho_S b; Corey curves with the segregation
 // model for three-phase oil; mob = b k_r / mu.  The third variable x is s_g,
-// or, for live oil in a cell without free gas (mean = 1), r_go with s_g = 0
-// (eq. primaryVariableMeaning).  Live oil (sec. 2.1.6): r = r_s(p) = rs_c p
+// or, for live oil in a cell without free gas (mean = 1), r_go with s_g = 0,
+// or, with wet gas in a cell without oil (mean = 2), r_og with s_g = 1 - s_w
+// (eq. primaryVariableMeaning).  Wet gas (sec. 2.1.6): r_og = r_v(p) =
+// rv_c p where oil is present, rho_g = b_g (rho_gS + r_og rho_oS), and the
+// oil component adds r_og b_g s_g (accumulation) and r_og b_g lambda_g
+// (vmob, carried with the gas).  Live oil (sec. 2.1.6): r = r_s(p) = rs_c p
 // where free gas is present, b_o /= (1 + bo_r r), mu_o /= (1 + muo_r r),
 // rho_o = b_o (rho_oS + r rho_gS).
 template <bool LIVE>
