@@ -322,6 +322,22 @@ def config_live(seed: int = 6, nx: int = 12, ny: int = 12, nz: int = 5) -> Case:
                 report_dt=[15 * DAY] * 20, seed=seed)
 
 
+
+def config_wet(rv_bubble: float = 0.01) -> Case:
+    """Wet-gas variant of the live-oil case: the corner injector puts 2
+    MMscf/day of dry gas into the undersaturated oil, whose gas phase holds
+    up to r_v(p) = rv_bubble p / 3000 psi of vaporised oil; twelve 30-day
+    steps, over which the oil around the injector is vaporised away (cells
+    switch to x = r_og)."""
+    c = config_live()
+    c.name = "C6_wet"
+    c.fluid.rv_c = rv_bubble / (3000.0 * PSI)
+    c.wells[0].phase = GAS
+    c.wells[0].target = 2e6 * 0.0283168 / DAY
+    c.report_dt = [30 * DAY] * 12
+    return c
+
+
 def box_case(nx: int, ny: int, nz: int, *, seed: int = 0, dx: float = 300 * FT,
              dy: float = 300 * FT, dz: Sequence[float] | float = 20 * FT,
              median_md: float = 100.0, sigma_ln: float = 1.0, poro: float = 0.3,

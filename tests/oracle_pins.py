@@ -1213,6 +1213,35 @@ def pin_wet_oil_moves_with_gas(lib_path=None):
         assert abs(R[0, 1] - y[hi, 2] * R[0, 2]) <= 1e-12 * abs(R[0, 1])
 
 
+def pin_wet_vaporisation_run(lib_path=None):
+    """Dry gas injected into undersaturated oil with wet gas: every report
+    step converges and conserves each component; the states stay valid (no
+    negative oil in any meaning, r_og of an oil-free cell at most r_v(p),
+    r_go of a gas-free cell at most r_s(p)); oil-free cells appear next to
+    the injector and their number never falls."""
+    c = cases.config_wet()
+    m = _model(c, lib_path)
+    states, reps = m.run()
+    eps = c.fluid.eps_switch
+    counts = []
+    for y, mean, r in zip(states, m.run_meanings, reps):
+        assert max(r["mass_err"]) <= 1e-10, r["mass_err"]
+        sg = np.where(mean == 0, y[:, 2], np.where(mean == 2, 1.0 - y[:, 1], 0.0))
+        so = 1.0 - y[:, 1] - sg
+        assert so.min() >= -eps and sg.min() >= -eps
+        rv, rs = c.fluid.rv_c * y[:, 0], c.fluid.rs_c * y[:, 0]
+        assert np.all(y[mean == 2, 2] <= rv[mean == 2] * (1 + eps))
+        assert np.all(y[mean == 1, 2] <= rs[mean == 1] * (1 + eps))
+        counts.append(int((mean == 2).sum()))
+    assert counts[-1] > 0 and counts == sorted(counts), counts
+    inj = c.wells[0].cells[0]
+    k = np.flatnonzero(m.run_meanings[-1] == 2)
+    i0 = c.box_index(*inj)
+    boxes = np.flatnonzero(c.mask.ravel())[k]
+    ii, jj = boxes % c.nx, (boxes // c.nx) % c.ny
+    assert np.hypot(ii - inj[0], jj - inj[1]).max() <= 0.5 * np.hypot(c.nx, c.ny), (ii, jj, i0)
+
+
 # ---------------------------------------------------------------- CPR-AMG
 # Two-stage CPR preconditioner (sec. 2.3.1) with an aggregation AMG for the
 # pressure stage.
@@ -1411,7 +1440,8 @@ ALL_PINS = [
     pin_live_dissolved_moves_with_oil, pin_live_hydrostatic_column, pin_live_depletion_1d,
     pin_std_schur_dense, pin_std_jacobian_fd, pin_std_simplified_limit,
     pin_std_controls_and_storage, pin_std_control_switching, pin_wet_jacobian_fd,
-    pin_wet_dew_point_continuity, pin_wet_oil_moves_with_gas, pin_cpr_weights_decouple,
+    pin_wet_dew_point_continuity, pin_wet_oil_moves_with_gas, pin_wet_vaporisation_run,
+    pin_cpr_weights_decouple,
     pin_cpr_galerkin_hierarchy,
     pin_cpr_exact_second_stage, pin_cpr_vcycle_converges, pin_cpr_two_grid,
     pin_cpr_fewer_iterations,

@@ -253,3 +253,39 @@ def test_wet_newton_iterates(opm):
     assert np.abs(yg[:, 1] - yo[:, 1]).max() <= 1e-8
     x_scale = np.where(mo == 0, 1.0, np.abs(yo[:, 2]).max())
     assert (np.abs(yg[:, 2] - yo[:, 2]) / x_scale).max() <= 1e-8
+
+
+def _wet_physical(c, y, mean):
+    sg = np.where(mean == 0, y[:, 2], np.where(mean == 2, 1.0 - y[:, 1], 0.0))
+    r = np.where(mean == 1, y[:, 2], c.fluid.rs_c * y[:, 0])
+    rv = np.where(mean == 2, y[:, 2], c.fluid.rv_c * y[:, 0])
+    return sg, 1.0 - y[:, 1] - sg, r, rv
+
+
+@pytest.mark.parametrize("blk", [None, (4, 4, 5)], ids=["single", "blocks"])
+def test_wet_run(opm, blk):
+    """Dry gas into undersaturated oil with wet gas, twelve 30-day steps:
+    after each the pressure, saturations and both ratios match the oracle's
+    run to 1e-6 (ratios relative to their largest value), the meanings
+    agree away from the switching points, and oil-free cells have
+    appeared."""
+    c = cases.config_wet()
+    g = opm.GpuModel(c, ilu_blocks=blk)
+    m = oracle.Model(c)
+    ostates, oreps = m.run()
+    y, gstates, greps = g.run()
+    for s, (yg, mg, yo, mo) in enumerate(zip(gstates, g.run_meanings, ostates, m.run_meanings)):
+        sgg, sog, rg, rvg = _wet_physical(c, yg, mg)
+        sgo, soo, ro, rvo = _wet_physical(c, yo, mo)
+        assert np.abs(yg[:, 0] - yo[:, 0]).max() <= 1e-6 * np.abs(yo[:, 0]).max(), s
+        assert np.abs(yg[:, 1] - yo[:, 1]).max() <= 1e-6, s
+        assert np.abs(sgg - sgo).max() <= 1e-6 and np.abs(sog - soo).max() <= 1e-6, s
+        assert np.abs(rg - ro).max() <= 1e-6 * np.abs(ro).max(), s
+        assert np.abs(rvg - rvo).max() <= 1e-6 * np.abs(rvo).max(), s
+        differ = mg != mo
+        border = ((np.abs(sgo) <= 1e-4) | (np.abs(soo) <= 1e-4)) & \
+                 ((np.abs(sgg) <= 1e-4) | (np.abs(sog) <= 1e-4))
+        assert np.all(border[differ]), f"step {s}: meanings differ away from a switching point"
+    assert (g.run_meanings[-1] == 2).sum() > 0
+    for rg_, ro_ in zip(greps, oreps):
+        assert abs(rg_["newton_its"] - ro_["newton_its"]) <= 1

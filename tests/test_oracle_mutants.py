@@ -76,8 +76,8 @@ MUTANTS = [
     ("live_producer_without_dissolved_gas", "      if (m->fl.live)\n        out[2] = dadd(out[2],",
      "      if (0)\n        out[2] = dadd(out[2],"),
     ("live_gas_never_appears", "if (yc[2] > rs * (1.0 + f->eps_switch)) {", "if (0) {"),
-    ("live_free_gas_in_undersaturated_cell", "dual sg = (f->live && mean == 1) ? dconst(0.0) : x;",
-     "dual sg = x;"),
+    ("live_free_gas_in_undersaturated_cell", "dual sg = (f->live && mean == 1) ? dconst(0.0)",
+     "dual sg = (f->live && mean == 1) ? x"),
     # standard wells and the Schur complement
     ("std_schur_operator_sign", "y[3 * c + a] -= op->C[12 * q + 4 * a + k] * u[k];",
      "y[3 * c + a] += op->C[12 * q + 4 * a + k] * u[k];"),
