@@ -19,14 +19,14 @@ namespace {
 
 using namespace asmdev;
 
-template <bool LIVE>
+template <bool LIVE, bool WET = false>
 __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a) {
   __shared__ double sh[kBlock / kWave];
   const int i = blockIdx.x * kBlock + threadIdx.x;
   double part[kNormStride];
 #pragma unroll
   for (int k = 0; k < kNormStride; ++k) part[k] = 0.0;
-  if (i < a.n) assemble_row<LIVE>(a, i, a.dt, part);
+  if (i < a.n) assemble_row<LIVE, WET>(a, i, a.dt, part);
   if (a.partials) {
     double out[kNormStride];
 #pragma unroll
@@ -78,14 +78,14 @@ __global__ __launch_bounds__(kBlock) void k_norms_final(const double* partials, 
   }
 }
 
-template <bool LIVE>
+template <bool LIVE, bool WET = false>
 __global__ __launch_bounds__(kBlock) void k_accumulation(int n, opm_fluid f, const double* y,
                                                           const uint8_t* meaning, double* acc) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   FaceProps P;
   CellAcc A;
-  properties<LIVE>(f, y[3 * i], y[3 * i + 1], y[3 * i + 2], LIVE ? meaning[i] : 0, P, &A);
+  properties<LIVE, WET>(f, y[3 * i], y[3 * i + 1], y[3 * i + 2], LIVE ? meaning[i] : 0, P, &A);
 #pragma unroll
   for (int c = 0; c < 3; ++c) acc[3 * i + c] = A.A[c].v;
 }
@@ -124,7 +124,9 @@ int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, 
   a.R = R;
   a.J = J;
   a.partials = norms ? norms + 8 : nullptr;
-  if (pb->fluid.live)
+  if (pb->fluid.live && pb->fluid.rv_c > 0.0)   // wet gas
+    hipLaunchKernelGGL((k_assemble<true, true>), dim3(nblk), dim3(kBlock), 0, s, a);
+  else if (pb->fluid.live)
     hipLaunchKernelGGL(k_assemble<true>, dim3(nblk), dim3(kBlock), 0, s, a);
   else
     hipLaunchKernelGGL(k_assemble<false>, dim3(nblk), dim3(kBlock), 0, s, a);
@@ -139,7 +141,10 @@ int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, 
 
 int launch_accumulation(const opm_problem* pb, const double* y, double* acc0, hipStream_t s) {
   const dim3 grid(blocks_for(pb->n_cells, kBlock));
-  if (pb->fluid.live)
+  if (pb->fluid.live && pb->fluid.rv_c > 0.0)
+    hipLaunchKernelGGL((k_accumulation<true, true>), grid, dim3(kBlock), 0, s, pb->n_cells, pb->fluid, y,
+                       pb->meaning, acc0);
+  else if (pb->fluid.live)
     hipLaunchKernelGGL(k_accumulation<true>, grid, dim3(kBlock), 0, s, pb->n_cells, pb->fluid, y,
                        pb->meaning, acc0);
   else

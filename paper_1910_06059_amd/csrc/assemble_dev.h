@@ -182,7 +182,7 @@ struct CellAcc {
 // (vmob, carried with the gas).  Live oil (sec. 2.1.6): r = r_s(p) = rs_c p
 // where free gas is present, b_o /= (1 + bo_r r), mu_o /= (1 + muo_r r),
 // rho_o = b_o (rho_oS + r rho_gS).
-template <bool LIVE>
+template <bool LIVE, bool WET = false>
 __device__ __forceinline__ void properties(const opm_fluid& f, double p_v, double sw_v,
                                            double x_v, int mean, FaceProps& P, CellAcc* acc) {
   D3 p = cst<3>(p_v);
@@ -193,7 +193,7 @@ __device__ __forceinline__ void properties(const opm_fluid& f, double p_v, doubl
   x.d[2] = 1.0;
   const bool undersat = LIVE && mean == 1;
   // wet gas: meaning 2 = no oil, s_g = 1 - s_w, x = r_og
-  const bool wet = LIVE && f.rv_c > 0.0;
+  const bool wet = LIVE && WET;   // wet gas (the caller's kernel is picked by rv_c > 0)
   const bool oilfree = wet && mean == 2;
   const D3 sg = undersat ? cst<3>(0.0) : (oilfree ? cst<3>(1.0) - sw : x);
   D3 r = cst<3>(0.0);
@@ -262,7 +262,7 @@ __device__ __forceinline__ D6 potential(const FaceProps& L, const FaceProps& H, 
 // transmissibility T: (b lambda)_U T dPhi, U = L if dPhi >= 0 else H; for
 // live oil the gas component adds the dissolved gas, (r b_o lambda_o)_Uo T
 // dPhi_o with the oil phase's potential and upwind cell.
-template <bool LIVE>
+template <bool LIVE, bool WET = false>
 __device__ __forceinline__ D6 face_flux(const FaceProps& L, const FaceProps& H, int a, double dz,
                                         double T, double g) {
   const D6 dphi = potential(L, H, a, dz, g);
@@ -274,9 +274,8 @@ __device__ __forceinline__ D6 face_flux(const FaceProps& L, const FaceProps& H, 
     F = F + rm * (dphio * T);
   }
   // wet gas: the oil component adds the vaporised oil, (r_og b_g lambda_g)_Ug
-  // T dPhi_g with the gas phase's potential and upwind cell (zero mobilities
-  // without wet gas)
-  if (LIVE && a == 1) {
+  // T dPhi_g with the gas phase's potential and upwind cell
+  if (LIVE && WET && a == 1) {
     const D6 dphig = potential(L, H, 2, dz, g);
     D6 vm = dphig.v >= 0.0 ? lift(L.vmob, 0) : lift(H.vmob, 1);
     F = F + vm * (dphig * T);
@@ -334,7 +333,7 @@ __device__ __forceinline__ D7 lift7(const D3& a) {
 // gas, live oil); injecting the wellbore fluid at the cell's total
 // mobility, q_a = WI lambda_t (p - p_bhp) mix_a.  Slots 0-2: the cell's
 // variables; 3-6: the well's.
-template <bool LIVE>
+template <bool LIVE, bool WET = false>
 __device__ __forceinline__ void std_conn_rate(const FaceProps& P, const WellVars& W, double wi,
                                               D7 q[3]) {
   D7 pc = cst<7>(P.p);
@@ -344,7 +343,7 @@ __device__ __forceinline__ void std_conn_rate(const FaceProps& P, const WellVars
 #pragma unroll
     for (int a = 0; a < 3; ++a) q[a] = (lift7(P.mob[a]) * wi) * dp;
     if (LIVE) q[2] = q[2] + (lift7(P.rmob) * wi) * dp;
-    if (LIVE) q[1] = q[1] + (lift7(P.vmob) * wi) * dp;
+    if (LIVE && WET) q[1] = q[1] + (lift7(P.vmob) * wi) * dp;
   } else {
     const D7 lt = (lift7(P.lamt) * wi) * dp;
 #pragma unroll
@@ -385,13 +384,13 @@ struct AsmArgs {
 // blocks J_i* (if a.J) and the cell's contributions to the CNV/MB norms:
 // part = (dt|R_a|/(b_a PV) for a = w,o,g; R_a; b_a; PV).  LIVE: live oil
 // with the cells' variable meanings in a.meaning.
-template <bool LIVE>
+template <bool LIVE, bool WET = false>
 __device__ __forceinline__ void assemble_row(const AsmArgs& a, int i, double dt,
                                              double part[kNormStride]) {
   const double yi0 = a.y[3 * i], yi1 = a.y[3 * i + 1], yi2 = a.y[3 * i + 2];
   FaceProps Pi;
   CellAcc Ai;
-  properties<LIVE>(a.fluid, yi0, yi1, yi2, LIVE ? a.meaning[i] : 0, Pi, &Ai);
+  properties<LIVE, WET>(a.fluid, yi0, yi1, yi2, LIVE ? a.meaning[i] : 0, Pi, &Ai);
   const double pv = a.pv[i];
   const double zi = a.depth[i];
   D3 r[3];
@@ -406,7 +405,7 @@ __device__ __forceinline__ void assemble_row(const AsmArgs& a, int i, double dt,
       continue;
     }
     FaceProps Pj;
-    properties<LIVE>(a.fluid, a.y[3 * j], a.y[3 * j + 1], a.y[3 * j + 2],
+    properties<LIVE, WET>(a.fluid, a.y[3 * j], a.y[3 * j + 1], a.y[3 * j + 2],
                      LIVE ? a.meaning[j] : 0, Pj, nullptr);
     const double T = a.trans[a.blk_face[q]];
     const double zj = a.depth[j];
@@ -417,7 +416,7 @@ __device__ __forceinline__ void assemble_row(const AsmArgs& a, int i, double dt,
     double blk[9];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      D6 F = face_flux<LIVE>(L, H, c, dz, T, a.fluid.g);
+      D6 F = face_flux<LIVE, WET>(L, H, c, dz, T, a.fluid.g);
       if (lower) {
         r[c].v += F.v;
 #pragma unroll
@@ -448,7 +447,7 @@ __device__ __forceinline__ void assemble_row(const AsmArgs& a, int i, double dt,
     if (a.n_wells > 0) {   // standard well: the connection rate from the well unknowns
       const WellVars W = well_vars(a.fluid, a.well_state + 4 * a.conn_well[k]);
       D7 q[3];
-      std_conn_rate<LIVE>(Pi, W, a.conn_wi[k], q);
+      std_conn_rate<LIVE, WET>(Pi, W, a.conn_wi[k], q);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         r[c].v += q[c].v;
@@ -473,7 +472,7 @@ __device__ __forceinline__ void assemble_row(const AsmArgs& a, int i, double dt,
 #pragma unroll
         for (int c = 0; c < 3; ++c) r[c] = r[c] + (Pi.mob[c] * a.conn_wi[k]) * dp;
         if (LIVE) r[2] = r[2] + (Pi.rmob * a.conn_wi[k]) * dp;
-        if (LIVE) r[1] = r[1] + (Pi.vmob * a.conn_wi[k]) * dp;
+        if (LIVE && WET) r[1] = r[1] + (Pi.vmob * a.conn_wi[k]) * dp;
       }
     }
   }

@@ -112,7 +112,7 @@ __device__ bool inv4(const double* Din, double* X) {
 // Well equations, B and D (and D^{-1}), and the well's convergence measure
 // wn: max over components of dt |R_a| / (b_a(p_bhp) V_perf) (V_perf the pore
 // volume of the perforated cells) and |R_c| / |target|.
-template <bool LIVE>
+template <bool LIVE, bool WET = false>
 __global__ __launch_bounds__(kWellThreads) void k_well_system(WellArgs a, const double* y,
                                                                const double* A0, double dt,
                                                                double* Rw, double* B, double* D,
@@ -125,10 +125,10 @@ __global__ __launch_bounds__(kWellThreads) void k_well_system(WellArgs a, const 
   for (int q = a.well_conn_ptr[w] + lane; q < a.well_conn_ptr[w + 1]; q += kWellThreads) {
     const int c = a.conn_cell[q];
     FaceProps P;
-    properties<LIVE>(a.fluid, y[3 * c], y[3 * c + 1], y[3 * c + 2], LIVE ? a.meaning[c] : 0, P,
+    properties<LIVE, WET>(a.fluid, y[3 * c], y[3 * c + 1], y[3 * c + 2], LIVE ? a.meaning[c] : 0, P,
                      nullptr);
     D7 qr[3];
-    std_conn_rate<LIVE>(P, W, a.conn_wi[q], qr);
+    std_conn_rate<LIVE, WET>(P, W, a.conn_wi[q], qr);
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
       s[e][0] += qr[e].v;
@@ -373,7 +373,10 @@ int well_storage0(const opm_problem* pb, const double* wx, double* A0, hipStream
 
 int well_system(const opm_problem* pb, const double* y, double dt, const WellWork& ww,
                 int32_t* flags, hipStream_t s) {
-  if (pb->fluid.live)
+  if (pb->fluid.live && pb->fluid.rv_c > 0.0)   // wet gas
+    hipLaunchKernelGGL((k_well_system<true, true>), dim3(pb->n_wells), dim3(kWellThreads), 0, s,
+                       well_args(pb), y, ww.A0, dt, ww.Rw, ww.B, ww.D, ww.Dinv, ww.wn, flags);
+  else if (pb->fluid.live)
     hipLaunchKernelGGL(k_well_system<true>, dim3(pb->n_wells), dim3(kWellThreads), 0, s,
                        well_args(pb), y, ww.A0, dt, ww.Rw, ww.B, ww.D, ww.Dinv, ww.wn, flags);
   else
