@@ -42,6 +42,8 @@ def _masked():
 
 
 CASES = {
+    "one_cell": lambda: cases.box_case(1, 1, 1, seed=2, wells=[]),
+    "column": lambda: cases.box_case(1, 1, 7, seed=2, wells=[]),   # one column, one level
     "tiny": lambda: cases.box_case(4, 3, 2, seed=7, wells=[]),   # one level
     "box": lambda: cases.box_case(11, 9, 5, seed=3, wells=[]),
     "masked": _masked,
