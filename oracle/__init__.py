@@ -112,6 +112,8 @@ def lib(path: Optional[str] = None):
                                       ctypes.POINTER(Opts), ctypes.POINTER(Report)]
         L.ora_advance.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.POINTER(Opts),
                                   ctypes.POINTER(Report)]
+        L.ora_advance_log.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.POINTER(Opts),
+                                      ctypes.POINTER(Report), _dp, _ip, ctypes.c_int, _ip]
         L.ora_dense_solve.argtypes = [ctypes.c_int, _dp, _dp]
         L.ora_set_standard_wells.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
         L.ora_get_well_ctrl.argtypes = [ctypes.c_void_p, _ip]
@@ -383,6 +385,20 @@ class Model:
         o = opts or default_opts(self.case)
         st = self.L.ora_advance(self.h, _d(y), dt, ctypes.byref(o), ctypes.byref(rep))
         return st, y, rep
+
+    def advance_log(self, y, dt, opts: Optional[Opts] = None, cap: int = 4096):
+        """advance() that also returns every attempted substep: (status, y,
+        report, lengths [k], Newton statuses [k])."""
+        y = np.array(y, dtype=np.float64, order="C")
+        rep = Report()
+        o = opts or default_opts(self.case)
+        dts = np.zeros(cap)
+        sts = np.zeros(cap, np.int32)
+        n = ctypes.c_int()
+        st = self.L.ora_advance_log(self.h, _d(y), dt, ctypes.byref(o), ctypes.byref(rep), _d(dts),
+                                    _i(sts), cap, ctypes.byref(n))
+        k = min(n.value, cap)
+        return st, y, rep, dts[:k], sts[:k]
 
     def run(self, y0=None, n_steps=None, opts=None):
         """Advance over the case's report schedule; returns states after each

@@ -1697,6 +1697,16 @@ static void mass_error(const ora_model* m, const double* y_old, const unsigned c
 
 int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts* o,
                 ora_report* rep) {
+  return ora_advance_log(m, y, dt_report, o, rep, NULL, NULL, 0, NULL);
+}
+
+/* Time-step cutting (sec. 2.3): a step whose Newton loop fails is retried
+ * from the last accepted state (y, meanings, well state, controls) with half
+ * the length, and the shorter length is kept for the rest of the report
+ * step.  Each attempt's length and status go to dt_log / st_log (up to
+ * log_cap entries; n_log receives the number of attempts). */
+int ora_advance_log(const ora_model* m, double* y, double dt_report, const ora_opts* o,
+                    ora_report* rep, double* dt_log, int* st_log, int log_cap, int* n_log) {
   const int N = 3 * m->n;
   double* yn = (double*)malloc(sizeof(double) * N);
   unsigned char* mn = (unsigned char*)malloc((size_t)m->n + 1);
@@ -1710,11 +1720,16 @@ int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts*
   if (cbytes) memcpy(cn, m->wctrl, cbytes);
   memset(rep, 0, sizeof(*rep));
   double t = 0.0, dt_try = dt_report;
-  int status = ORA_OK;
+  int status = ORA_OK, attempts = 0;
   while (dt_report - t > 1e-9 * dt_report) {
     double dt = fmin(dt_try, dt_report - t);
     ora_report r1;
     int st = ora_newton_step(m, y, yn, dt, o, &r1);
+    if (dt_log && attempts < log_cap) {
+      dt_log[attempts] = dt;
+      st_log[attempts] = st;
+    }
+    attempts++;
     rep->newton_its += r1.newton_its;
     rep->lin_its += r1.lin_its;
     rep->cell_newton_its += r1.cell_newton_its;
@@ -1747,6 +1762,7 @@ int ora_advance(const ora_model* m, double* y, double dt_report, const ora_opts*
     }
   }
   rep->status = status;
+  if (n_log) *n_log = attempts;
   free(yn);
   free(mn);
   free(wn);

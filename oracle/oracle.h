@@ -168,6 +168,10 @@ int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double 
                     const ora_opts* o, ora_report* rep);
 /* Advance y over one report step of length dt with halving on failure. */
 int ora_advance(const ora_model* m, double* y, double dt, const ora_opts* o, ora_report* rep);
+/* The same, recording every attempted substep: its length dt_log[k] and the
+ * Newton step's status st_log[k] for k < min(*n_log, log_cap). */
+int ora_advance_log(const ora_model* m, double* y, double dt, const ora_opts* o, ora_report* rep,
+                    double* dt_log, int* st_log, int log_cap, int* n_log);
 
 /* Standard well model (sec. 2.2.1): every well of the model gets the
  * unknowns x_w = (Q_t, F_w, F_g, p_bhp) (weighted total surface rate,

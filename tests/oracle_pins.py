@@ -1428,6 +1428,76 @@ def pin_cpr_newton(lib_path=None):
     assert max(rb.mass_err) <= 1e-10
 
 
+# ------------------------------------------------------ time-step cutting
+def _held_state(m):
+    """The state a model holds beside y: meanings, well state, controls."""
+    if m.std_wells:
+        return m.meaning().copy(), m.well_state().copy(), m.well_ctrl().copy()
+    return m.meaning().copy(), None, None
+
+
+def _set_held_state(m, held):
+    mean, wx, ctrl = held
+    m.set_meaning(mean)
+    if wx is not None:
+        m.set_well_state(wx)
+        m.set_well_ctrl(ctrl)
+
+
+def pin_time_step_cut(lib_path=None):
+    """Sec. 2.3 cuts the time step when the Newton loop fails; the reading
+    halves the length, keeps the shorter length for the rest of the report
+    step and retries from the last accepted state (y, the variable meanings,
+    the well state and the active controls, bit for bit).  A tight Newton
+    cap forces cuts on dead oil (C1), on live oil whose gas comes out of
+    solution (the meanings switch inside rejected attempts) and on C1 with
+    standard wells whose limits bind (the controls switch inside rejected
+    attempts).  Checked: every attempt's length follows the rule; each
+    rejected attempt is a Newton step that really fails from the accepted
+    state; and an uninterrupted sequence of Newton steps over the accepted
+    lengths, on a second model, reproduces the report step's y, meanings,
+    well state and controls exactly."""
+    live = cases.config_live()
+    runs = [(cases.config1(), [30 * DAY] * 2, 7),
+            (live, list(live.report_dt[:2]), 3),
+            (_switch_case(7000, 1500), [30 * DAY] * 2, 7)]
+    for case, lengths, max_newton in runs:
+        opts = oracle.default_opts(case, max_newton=max_newton)
+        m = _model(case, lib_path)           # report steps with cuts
+        u = _model(case, lib_path)           # accepted substeps only
+        probe = _model(case, lib_path)       # rejected attempts, from the accepted state
+        y = case.initial_state()
+        yu = y.copy()
+        cuts = 0
+        for D in lengths:
+            st, y, rep, dts, sts = m.advance_log(y, D, opts)
+            assert st == 0 and len(dts) == rep.substeps + rep.cuts
+            t, prev_failed, prev = 0.0, False, D
+            for dt, s in zip(dts, sts):
+                # exact halving after a rejection; otherwise the kept length,
+                # both capped by what is left of the report step
+                want = min(0.5 * prev if prev_failed else prev, D - t)
+                assert dt == want, (case.name, dt, want)
+                held = _held_state(u)
+                if s == 0:
+                    su, yu, _ = u.newton_step(yu, yu, dt, opts)
+                    assert su == 0
+                    t += dt
+                else:
+                    _set_held_state(probe, held)
+                    sp, _, _ = probe.newton_step(yu, yu, dt, opts)
+                    assert sp != 0
+                    cuts += 1
+                prev_failed, prev = s != 0, dt
+            assert t == D
+            assert np.array_equal(y, yu), case.name
+            hm, hu = _held_state(m), _held_state(u)
+            assert np.array_equal(hm[0], hu[0])
+            if hm[1] is not None:
+                assert np.array_equal(hm[1], hu[1]) and np.array_equal(hm[2], hu[2])
+        assert cuts >= 1, case.name
+
+
 ALL_PINS = [
     pin_series_transmissibility, pin_depth_pore_volume, pin_peaceman_worked_value,
     pin_compressibility, pin_darcy_flux_upwind, pin_hydrostatic_column, pin_pressure_block,
@@ -1445,5 +1515,5 @@ ALL_PINS = [
     pin_cpr_galerkin_hierarchy,
     pin_cpr_exact_second_stage, pin_cpr_vcycle_converges, pin_cpr_two_grid,
     pin_cpr_fewer_iterations,
-    pin_cpr_newton,
+    pin_cpr_newton, pin_time_step_cut,
 ]

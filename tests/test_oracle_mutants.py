@@ -127,6 +127,15 @@ MUTANTS = [
      "F = dadd(F, dmul(dmul(Pi.rv, dmul(U[2]->b[2], U[2]->lam[2])), dscale(dphi[2], T)));"),
     ("wet_oil_free_gas_saturation", "            : (wet && mean == 2)    ? dsub(dconst(1.0), sw)",
      "            : (wet && mean == 2)    ? x"),
+    # time-step cutting
+    ("cut_quarter_length", "dt_try = 0.5 * dt;", "dt_try = 0.25 * dt;"),
+    ("cut_state_not_restored", "      memcpy(y, yn, sizeof(double) * N);\n      memcpy(m->mean, mn",
+     "      memcpy(m->mean, mn"),
+    ("cut_meanings_not_restored", "      memcpy(m->mean, mn, (size_t)m->n);\n      if (wbytes)",
+     "      if (wbytes)"),
+    ("cut_well_state_not_restored", "if (wbytes) memcpy(m->wx, wn, wbytes);", ""),
+    ("cut_controls_not_restored", "if (cbytes) memcpy(m->wctrl, cn, cbytes);", ""),
+    ("cut_length_not_kept", "      t += dt;\n", "      t += dt;\n      dt_try = dt_report;\n"),
 ]
 
 
