@@ -26,8 +26,21 @@
  *    col_idx[q], with row_ptr/col_idx the block-CSR pattern of opm_topology.
  *  - "device" pointers are HIP device memory owned by the caller (the Python
  *    binding passes torch CUDA tensors); "host" pointers are host memory.
- *    The library keeps no pointer after a call returns and never allocates
- *    device memory: every buffer, workspaces included, comes from the caller.
+ *    Every buffer, workspaces included, comes from the caller: the library
+ *    never allocates device memory for data.  It keeps no pointer to caller
+ *    memory after a call returns, with one exception: opm_bicgstab (and the
+ *    Newton entry points that call it) caches up to 16 instantiated HIP
+ *    graphs of a chunk of its iterations, keyed by every launch argument
+ *    (the opm_problem by value, the buffers' device addresses, the stream,
+ *    the precision, the launch options, the device) and a hash of the host
+ *    arrays whose contents shape the launches (level_ptr_h and the CPR
+ *    hierarchy's sizes); a graph is replayed only for a call with the same
+ *    key, evicted oldest first, and released at process exit.  Capturing
+ *    needs a non-null stream, so the library creates one capture stream per
+ *    device (default priority) on first use.  A mutex serialises the cache
+ *    and the capture streams between host threads; OPM_OPT_KRYLOV_GRAPH = 0
+ *    turns the cache off.  The graph runtime's own objects aside, nothing
+ *    else persists between calls.
  *  - stream is a hipStream_t (NULL = default stream).  Calls are asynchronous
  *    on that stream unless their comment says that they synchronise.
  *  - Every entry point returns an int status: OPM_OK (0) or a negative code;
@@ -771,8 +784,10 @@ int opm_ensemble_launch_config(const void* work, int32_t n_members, int precisio
 /* Autotuner: times one report step of length dt_report of the whole
  * ensemble for every valid shape (threads 256/128 x ring off/on x factor
  * window on/off), restoring the members' states before each trial and at
- * the end, then configures the workspace with the fastest shape and returns
- * it in best.  seconds (host, optional, >= 8 entries) receives the trial
+ * the end, then configures the workspace with the fastest shape among the
+ * trials in which every member completed the step (status OPM_OK) and
+ * returns it in best; OPM_ENOTCONV (the workspace keeps the last trial's shape) if no trial
+ * completed.  seconds (host, optional, >= 8 entries) receives the trial
  * times in trial order, n_tried (host, optional) their number.  Host,
  * synchronous; results of later launches do not depend on the shape beyond
  * the order of summation in reductions. */

@@ -585,7 +585,8 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
   hipEvent_t e0, e1;
   OPM_TRY_HIP(hipEventCreate(&e0));
   OPM_TRY_HIP(hipEventCreate(&e1));
-  int tried = 0;
+  int tried = 0, passed = 0;
+  std::vector<opm_ensemble_report> trial(n_members);
   double best_t = INFINITY;
   opm_ensemble_config best_c{};
   int status = OPM_OK;
@@ -610,7 +611,18 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (seconds) seconds[tried] = ms * 1e-3;
         ++tried;
-        if (ms * 1e-3 < best_t) {
+        // a trial in which a member failed (or ran out of cuts) stopped
+        // early: its time says nothing about the shape, so it cannot win
+        if (hipMemcpy(trial.data(), reps, sizeof(opm_ensemble_report) * (size_t)n_members,
+                      hipMemcpyDeviceToHost) != hipSuccess) {
+          status = OPM_EHIP;
+          break;
+        }
+        bool complete = true;
+        for (const opm_ensemble_report& r : trial)
+          complete = complete && r.status == OPM_OK && r.steps_done >= 1;
+        if (complete) ++passed;
+        if (complete && ms * 1e-3 < best_t) {
           best_t = ms * 1e-3;
           best_c = c;
         }
@@ -621,6 +633,8 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
   if (status == OPM_OK && hipStreamSynchronize(s) != hipSuccess) status = OPM_EHIP;
   if (status != OPM_OK) return status;
   if (tried == 0) return OPM_EINVAL;
+  if (n_tried) *n_tried = tried;
+  if (passed == 0) return OPM_ENOTCONV;
   OPM_TRY(opm_ensemble_configure(members, n_members, precision, work, &best_c));
   *best = best_c;
   if (n_tried) *n_tried = tried;

@@ -12,6 +12,7 @@
 // between chunks.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "cpr_dev.h"
@@ -298,9 +299,15 @@ namespace {
 // options and the device), kept until the process ends or evicted oldest
 // first.  A chunk only launches kernels (no memset, no copy), and every
 // kernel reads the iteration's state from device memory, so a replay is
-// the same work as enqueuing the chunk again.
+// the same work as enqueuing the chunk again.  Besides the arguments
+// themselves, enqueuing reads two host arrays whose contents set launch
+// ranges baked into the graph: the level schedule (per-level launches of
+// the ILU(0) of large systems) and the CPR hierarchy's level sizes; their
+// contents enter the key through a hash, so a new schedule or hierarchy at
+// a reused host address does not replay a stale graph.
 struct ChunkKey {
   opm_problem pb;
+  uint64_t host_hash;        // FNV-1a of level_ptr_h[0..n_levels] and *pb.amg
   const double* J;
   const void* ilu;
   const double* x;
@@ -316,6 +323,23 @@ struct ChunkGraph {
 };
 std::vector<ChunkGraph> g_chunk_graphs;
 constexpr size_t kMaxChunkGraphs = 16;
+// Guards the graph cache and the capture streams: calls from several host
+// threads look up, capture and evict one at a time.
+std::mutex g_graph_mutex;
+
+uint64_t fnv1a(uint64_t h, const void* data, size_t bytes) {
+  const unsigned char* c = static_cast<const unsigned char*>(data);
+  for (size_t k = 0; k < bytes; ++k) h = (h ^ c[k]) * 1099511628211ull;
+  return h;
+}
+
+uint64_t host_schedule_hash(const opm_problem* pb) {
+  uint64_t h = 1469598103934665603ull;
+  if (pb->level_ptr_h)
+    h = fnv1a(h, pb->level_ptr_h, sizeof(int32_t) * ((size_t)pb->n_levels + 1));
+  if (pb->amg) h = fnv1a(h, pb->amg, sizeof(opm_amg));
+  return h;
+}
 
 bool same_key(const ChunkKey& a, const ChunkKey& b) { return std::memcmp(&a, &b, sizeof a) == 0; }
 
@@ -416,6 +440,7 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
   std::memset(&key, 0, sizeof key);
   if (g_krylov_graph == 1) {
     key.pb = *pb;
+    key.host_hash = host_schedule_hash(pb);
     key.J = J;
     key.ilu = ilu;
     key.x = x;
@@ -432,9 +457,12 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
   }
   for (int pass = 0;; ++pass) {
     hipGraphExec_t exec = nullptr;
-    if (g_krylov_graph == 1)
+    std::unique_lock<std::mutex> lock(g_graph_mutex, std::defer_lock);
+    if (g_krylov_graph == 1) {
+      lock.lock();
       for (auto& cg : g_chunk_graphs)
         if (same_key(cg.key, key)) exec = cg.exec;
+    }
     // a chunk with no graph yet runs eagerly the first time (which also sets
     // the kernels' LDS attributes outside any capture) and is captured the
     // next time; once captured, every chunk of every solve with the same
@@ -460,8 +488,10 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
       }
       OPM_TRY_HIP(hipGraphLaunch(exec, st));
     } else {
+      if (lock.owns_lock()) lock.unlock();
       OPM_TRY(enqueue_chunk(st));
     }
+    if (lock.owns_lock()) lock.unlock();
     launched += chunk;
     // a final begin turns a pending half-step exit into done and performs the
     // convergence test of the last full iteration
