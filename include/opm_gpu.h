@@ -394,6 +394,20 @@ size_t opm_norms_bytes(const opm_problem* pb);
 int opm_assemble(const opm_problem* pb, const double* y, const double* acc0, double dt,
                  double* R, double* J, double* norms, void* stream);
 
+/* opm_assemble for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with the per-workgroup partials of the
+ * norms kept in a static device array of the library (5 MiB per GPU, held
+ * until the process ends) instead of the caller's buffer.  norms (may be
+ * NULL): device, 8 doubles, the same values as opm_assemble's first 8.
+ * Supports at most 16,777,216 cells: larger problems return OPM_EINVAL
+ * before any device work.  The call allocates nothing (the array's address
+ * is resolved by opm_init, or by the first call on a device).  Every call on
+ * a GPU shares that GPU's array, so calls that overlap on one GPU (several
+ * streams or host threads) race and must be serialised by the caller. */
+int opm_assemble_noalloc(const opm_problem* pb, const double* y, const double* acc0, double dt,
+                         double* R, double* J, double* norms, void* stream);
+
 /* Size in bytes of the ILU(0) factor storage for a precision
  * (OPM_PREC_FP64 or OPM_PREC_MIXED). */
 size_t opm_ilu0_bytes(const opm_problem* pb, int precision);

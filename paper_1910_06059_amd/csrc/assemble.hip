@@ -12,10 +12,24 @@
 // for that code (assemble_dev.h), so the two evaluations are bitwise equal
 // and u_ij = -u_ji holds exactly.  The CNV / MB norms are reduced in the same
 // pass.
+#include <mutex>
+
 #include "assemble_dev.h"
 
 namespace opm {
+
+// Scratch of the allocation-free assembly (opm_assemble_noalloc): the
+// per-workgroup partials of the CNV/MB norms, kNormStride doubles for each
+// of at most kScratchBlocks workgroups (5 MiB; every GPU the library runs
+// on holds one copy until the process ends).  Host code never names the
+// array: it uses the device address resolved once per device below.
+constexpr int kScratchBlocks = 65536;
+static __device__ __align__(256) double scratch[(size_t)kScratchBlocks * kNormStride];
+
 namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kScratchDevices] = {};
 
 using namespace asmdev;
 
@@ -92,10 +106,55 @@ __global__ __launch_bounds__(kBlock) void k_accumulation(int n, opm_fluid f, con
 
 }  // namespace
 
+// Resolve the device address of the scratch array on `device` (which must
+// be current); called by opm_init, and by the allocation-free entry point
+// on its first call on a device.
+int assemble_scratch_setup(int device) {
+  if (device < 0 || device >= kScratchDevices) return OPM_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[device]) return OPM_OK;
+  void* ptr = nullptr;
+  OPM_TRY_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) return OPM_EHIP;
+  g_scratch_ptr[device] = static_cast<double*>(ptr);
+  return OPM_OK;
+}
+
+long assemble_noalloc_max_cells() { return (long)kScratchBlocks * kBlock; }
+
+int launch_assemble_parts(const opm_problem* pb, const double* y, const double* acc0, double dt,
+                          double* R, double* J, double* norms, double* partials, hipStream_t s,
+                          double* Cw);
+
+// Assembly with the norms' partials in the library's scratch array: norms
+// receives only the 8 results.  The array is shared by every call on the
+// device, so calls that overlap on one GPU race.
+int launch_assemble_noalloc(const opm_problem* pb, const double* y, const double* acc0, double dt,
+                            double* R, double* J, double* norms, hipStream_t s) {
+  if ((long)pb->n_cells > assemble_noalloc_max_cells()) return OPM_EINVAL;
+  int dev = 0;
+  OPM_TRY_HIP(hipGetDevice(&dev));
+  OPM_TRY(assemble_scratch_setup(dev));
+  double* part = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    part = g_scratch_ptr[dev];
+  }
+  return launch_assemble_parts(pb, y, acc0, dt, R, J, norms, norms ? part : nullptr, s, nullptr);
+}
+
 // Cw (standard wells, with J): [n_conns][3][4] derivatives of the cell
 // residuals w.r.t. the well unknowns.
 int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, double dt,
                     double* R, double* J, double* norms, hipStream_t s, double* Cw) {
+  return launch_assemble_parts(pb, y, acc0, dt, R, J, norms, norms ? norms + 8 : nullptr, s, Cw);
+}
+
+// norms: the 8 results (or null); partials: kNormStride doubles per
+// workgroup of the assembly (null without norms).
+int launch_assemble_parts(const opm_problem* pb, const double* y, const double* acc0, double dt,
+                          double* R, double* J, double* norms, double* partials, hipStream_t s,
+                          double* Cw) {
   const int nblk = blocks_for(pb->n_cells, kBlock);
   AsmArgs a;
   a.n = pb->n_cells;
@@ -123,7 +182,7 @@ int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, 
   a.Cw = Cw;
   a.R = R;
   a.J = J;
-  a.partials = norms ? norms + 8 : nullptr;
+  a.partials = norms ? partials : nullptr;
   if (pb->fluid.live && pb->fluid.rv_c > 0.0)   // wet gas
     hipLaunchKernelGGL((k_assemble<true, true>), dim3(nblk), dim3(kBlock), 0, s, a);
   else if (pb->fluid.live)
@@ -132,7 +191,7 @@ int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, 
     hipLaunchKernelGGL(k_assemble<false>, dim3(nblk), dim3(kBlock), 0, s, a);
   OPM_TRY_HIP(hipGetLastError());
   if (norms) {
-    hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(kBlock), 0, s, norms + 8, nblk, pb->n_cells,
+    hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(kBlock), 0, s, a.partials, nblk, pb->n_cells,
                        dt, norms);
     OPM_TRY_HIP(hipGetLastError());
   }

@@ -19,6 +19,10 @@ extern int g_krylov_chunk;
 extern int g_krylov_graph;
 int launch_assemble(const opm_problem* pb, const double* y, const double* acc0, double dt,
                     double* R, double* J, double* norms, hipStream_t s, double* Cw = nullptr);
+int launch_assemble_noalloc(const opm_problem* pb, const double* y, const double* acc0, double dt,
+                            double* R, double* J, double* norms, hipStream_t s);
+int assemble_scratch_setup(int device);
+long assemble_noalloc_max_cells();
 int launch_accumulation(const opm_problem* pb, const double* y, double* acc0, hipStream_t s);
 size_t ilu_bytes(const opm_problem* pb, int precision);
 int ilu_factor(const opm_problem* pb, const double* J, void* ilu, int precision, int32_t* status,
@@ -437,7 +441,7 @@ int opm_init(void) {
   OPM_TRY_HIP(hipGetDeviceProperties(&prop, dev));
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return OPM_EHIP;
   (void)events();
-  return OPM_OK;
+  return assemble_scratch_setup(dev);
 }
 
 int opm_set_option(int option, int value) {
@@ -494,6 +498,15 @@ int opm_assemble(const opm_problem* pb, const double* y, const double* acc0, dou
     return OPM_EINVAL;
   if (pb->n_cells == 0) return OPM_OK;
   return launch_assemble(pb, y, acc0, dt, R, J, norms, as_stream(stream));
+}
+
+int opm_assemble_noalloc(const opm_problem* pb, const double* y, const double* acc0, double dt,
+                         double* R, double* J, double* norms, void* stream) {
+  if (pb && (long)pb->n_cells > assemble_noalloc_max_cells()) return OPM_EINVAL;
+  if (!valid_problem(pb) || !(dt > 0.0) || (pb->n_cells > 0 && (!y || !acc0 || !R)))
+    return OPM_EINVAL;
+  if (pb->n_cells == 0) return OPM_OK;
+  return launch_assemble_noalloc(pb, y, acc0, dt, R, J, norms, as_stream(stream));
 }
 
 size_t opm_ilu0_bytes(const opm_problem* pb, int precision) {

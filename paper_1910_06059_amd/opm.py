@@ -111,6 +111,7 @@ EXPORTS = [
     "opm_init", "opm_strerror", "opm_topology_count", "opm_topology_build",
     "opm_ilu_blocks_count", "opm_topology_build_blocks", "opm_geometry",
     "opm_well_index", "opm_well_groups", "opm_accumulation", "opm_norms_bytes", "opm_assemble",
+    "opm_assemble_noalloc",
     "opm_ilu0_bytes", "opm_ilu0_factor", "opm_ilu0_apply", "opm_spmv", "opm_krylov_bytes",
     "opm_bicgstab", "opm_gmres_bytes", "opm_gmres", "opm_newton_bytes", "opm_newton_work_bytes",
     "opm_newton_step", "opm_advance", "opm_set_option", "opm_wells_bytes", "opm_assemble_wells",
@@ -165,6 +166,7 @@ def lib():
         L.opm_norms_bytes.argtypes = [P]
         L.opm_norms_bytes.restype = ctypes.c_size_t
         L.opm_assemble.argtypes = [P, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp]
+        L.opm_assemble_noalloc.argtypes = [P, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp]
         L.opm_ilu0_bytes.argtypes = [P, ctypes.c_int]
         L.opm_ilu0_bytes.restype = ctypes.c_size_t
         L.opm_ilu0_factor.argtypes = [P, _vp, _vp, ctypes.c_int, _vp, _vp]
@@ -602,6 +604,12 @@ class GpuModel:
         _check(L.opm_assemble(self._pbp(), _ptr(y), _ptr(acc0), dt, _ptr(R), _ptr(J), _ptr(nb),
                               _stream()), "opm_assemble")
         return R, J, (nb[:8] if norms else None)
+
+    def assemble_noalloc(self, y, acc0, dt, R, J, norms):
+        """opm_assemble_noalloc into caller-given tensors (J and norms may be
+        None); returns the status code."""
+        return lib().opm_assemble_noalloc(self._pbp(), _ptr(y), _ptr(acc0), dt, _ptr(R), _ptr(J),
+                                          _ptr(norms), _stream())
 
     def ilu0_factor(self, J, precision=PREC_FP64):
         L = lib()
