@@ -503,7 +503,7 @@ def bench_kernels(args):
         "ilu0_apply_fp32": (lambda: L.opm_ilu0_apply(pbp, sp(ilu[1]), 1, sp(R), sp(x), st),
                             sweep_bytes_per_cell(1) * n, "k_fwd_level + k_bwd_level (FP32)"),
         "assemble": (lambda: L.opm_assemble(pbp, sp(yk), sp(acc0), dt, sp(Rb), sp(Jb), sp(norms), st),
-                     assemble_bytes(n, g.nnzb, g.nf), "k_assemble + k_norms_final"),
+                     assemble_bytes(n, g.nnzb, g.nf), "k_assemble_tiled + k_norms_final"),
         "ilu0_factor_fp64": (lambda: L.opm_ilu0_factor(pbp, sp(J), sp(ilu_tmp[0]), 0, sp(status), st),
                              factor_bytes_per_cell(0) * n, "k_pack + k_factor_level (FP64)"),
         "block_apply_fp64": (lambda: L.opm_ilu0_apply(pbb, sp(bilu[0]), 0, sp(R), sp(x), st),
@@ -807,7 +807,7 @@ def main():
     kernels = {
         apply_class: apply,
         "spmv": {"seconds": t_spmv, "bytes": spmv_b, "kernel": "k_spmv"},
-        "assemble": {"seconds": t_asm, "bytes": asm_b, "kernel": "k_assemble+k_norms_final"},
+        "assemble": {"seconds": t_asm, "bytes": asm_b, "kernel": "k_assemble_tiled+k_norms_final"},
     }
     # time share of each kernel class in one Newton iteration of the run
     its_per_newton = lin / max(newton, 1)

@@ -360,6 +360,15 @@ typedef struct opm_problem {
    * opm_advance restores the controls with the well state on a cut. */
   const double* well_limit;
   int32_t* well_ctrl;
+  /* The lattice of the cells (sec. 2.4.2 localisation): box dims and
+   * box_cell [nx*ny*nz] (device), the active-cell index of each box cell in
+   * natural order i + nx (j + ny k), -1 for an inactive one.  With box_cell
+   * set, the dead-oil assembly with fixed-source wells runs on lattice
+   * tiles whose cell properties and face fluxes are staged in LDS; NULL
+   * (or live oil, or standard wells) selects the row-per-lane assembly.
+   * Both give the same residual and Jacobian up to rounding. */
+  int32_t nx, ny, nz, pad_l;
+  const int32_t* box_cell;
 } opm_problem;
 
 /* Library set-up: checks that the current device is a gfx950 (MI355X) and
@@ -830,12 +839,16 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
  *   OPM_OPT_KRYLOV_GRAPH: 1 (default) replays each chunk of BiCGStab
  *     iterations after the first chunk of a solve as a HIP graph captured
  *     once per set of arguments (kept until the process ends, at most 16),
- *     0 enqueues the kernels one by one. */
+ *     0 enqueues the kernels one by one.
+ *   OPM_OPT_ASSEMBLY: 1 (default) the LDS-tiled assembly where the problem
+ *     allows it (box_cell set, dead oil, fixed-source wells), 0 always the
+ *     row-per-lane assembly. */
 #define OPM_OPT_SWEEP_MODE 1
 #define OPM_OPT_KRYLOV_CHUNK 2
 #define OPM_OPT_SWEEP_KERNEL 3
 #define OPM_OPT_BLOCK_DEPTH 4
 #define OPM_OPT_KRYLOV_GRAPH 5
+#define OPM_OPT_ASSEMBLY 6
 int opm_set_option(int option, int value);
 
 const char* opm_strerror(int code);

@@ -23,6 +23,9 @@ int launch_assemble_noalloc(const opm_problem* pb, const double* y, const double
                             double* R, double* J, double* norms, hipStream_t s);
 int assemble_scratch_setup(int device);
 long assemble_noalloc_max_cells();
+long assemble_workgroups(const opm_problem* pb, const double* Cw);
+long assemble_max_workgroups(const opm_problem* pb);
+extern int g_assembly_kernel;
 int launch_accumulation(const opm_problem* pb, const double* y, double* acc0, hipStream_t s);
 size_t ilu_bytes(const opm_problem* pb, int precision);
 int ilu_factor(const opm_problem* pb, const double* J, void* ilu, int precision, int32_t* status,
@@ -47,8 +50,10 @@ namespace {
 
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+// partials for whichever assembly kernel runs (the option may change
+// between sizing and use)
 size_t norms_bytes(const opm_problem* pb) {
-  return sizeof(double) * (8 + (size_t)kNormStride * blocks_for(pb->n_cells, kBlock));
+  return sizeof(double) * (8 + (size_t)kNormStride * assemble_max_workgroups(pb));
 }
 
 struct NewtonWork {
@@ -454,6 +459,10 @@ int opm_set_option(int option, int value) {
       if (value < 0 || value > 1) return OPM_EINVAL;
       g_krylov_graph = value;
       return OPM_OK;
+    case OPM_OPT_ASSEMBLY:
+      if (value < 0 || value > 1) return OPM_EINVAL;
+      g_assembly_kernel = value;
+      return OPM_OK;
     case OPM_OPT_KRYLOV_CHUNK:
       if (value < 0) return OPM_EINVAL;
       g_krylov_chunk = value;
@@ -502,7 +511,9 @@ int opm_assemble(const opm_problem* pb, const double* y, const double* acc0, dou
 
 int opm_assemble_noalloc(const opm_problem* pb, const double* y, const double* acc0, double dt,
                          double* R, double* J, double* norms, void* stream) {
-  if (pb && (long)pb->n_cells > assemble_noalloc_max_cells()) return OPM_EINVAL;
+  if (pb && ((long)pb->n_cells > assemble_noalloc_max_cells() ||
+             assemble_workgroups(pb, nullptr) > assemble_noalloc_max_cells() / kBlock))
+    return OPM_EINVAL;
   if (!valid_problem(pb) || !(dt > 0.0) || (pb->n_cells > 0 && (!y || !acc0 || !R)))
     return OPM_EINVAL;
   if (pb->n_cells == 0) return OPM_OK;

@@ -69,7 +69,8 @@ class Problem(ctypes.Structure):
                 ("n_wells", _i32), ("pad_w", _i32), ("well_conn_ptr", _vp), ("conn_cell", _vp),
                 ("conn_well", _vp), ("well_kind", _vp), ("well_phase", _vp), ("well_target", _vp),
                 ("well_vol", _vp), ("well_state", _vp), ("amg", _vp), ("well_limit", _vp),
-                ("well_ctrl", _vp)]
+                ("well_ctrl", _vp), ("nx", _i32), ("ny", _i32), ("nz", _i32), ("pad_l", _i32),
+                ("box_cell", _vp)]
 
 
 AMG_MAX_LEVELS, AMG_COARSE = 12, 64
@@ -121,6 +122,7 @@ EXPORTS = [
 ]
 
 OPT_SWEEP_MODE, OPT_KRYLOV_CHUNK, OPT_SWEEP_KERNEL, OPT_BLOCK_DEPTH, OPT_KRYLOV_GRAPH = 1, 2, 3, 4, 5
+OPT_ASSEMBLY = 6
 
 _lib = None
 
@@ -408,6 +410,10 @@ class GpuModel:
             conn_kind=self.conn_kind.data_ptr(), conn_phase=self.conn_phase.data_ptr(),
             conn_wi=self.conn_wi.data_ptr(), conn_rate=self.conn_rate.data_ptr(),
             conn_bhp=self.conn_bhp.data_ptr(), fluid=fl, sweep_span=topo.sweep_span)
+        # the lattice, for the LDS-tiled assembly
+        self.box_cell_t = torch.from_numpy(box_cell.astype(np.int32)).to(self.dev)
+        self.pb.nx, self.pb.ny, self.pb.nz = nx, ny, nz
+        self.pb.box_cell = self.box_cell_t.data_ptr()
         if blk is not None:
             self.pb.n_sub, self.pb.max_sub, self.pb.max_width = blk.n_sub, blk.max_sub, blk.max_width
             self.pb.sub_level_ptr = d["sub_level_ptr"].data_ptr()
