@@ -75,6 +75,32 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+_BASELINE_PATH = os.path.join(_HERE, "liboracle_omp.so")
+
+
+def build_baseline(path: Optional[str] = None) -> str:
+    """Compile the same sources as the CPU baseline: -O3 -march=native for
+    the host it runs on, OpenMP over the cells of the accumulation, the
+    faces of the flux evaluation and the rows of the Jacobian product, and
+    no floating-point contraction, so that it computes the plain build's
+    bits with any number of threads."""
+    out = path or _BASELINE_PATH
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O3", "-march=native", "-ffp-contract=off", "-fopenmp", "-std=c11",
+           "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", tmp] + _SOURCES + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def set_threads(n: int, lib_path: Optional[str] = None) -> int:
+    """Threads of an OpenMP build (the plain build stays at one); returns the
+    number the library will use."""
+    L = lib(lib_path)
+    L.ora_set_threads(int(n))
+    return int(L.ora_threads())
+
+
 def lib(path: Optional[str] = None):
     """Load the oracle library (``path`` selects another build of the same
     sources, e.g. a deliberately mutated copy used by the pin tests)."""
@@ -115,6 +141,8 @@ def lib(path: Optional[str] = None):
         L.ora_advance_log.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.POINTER(Opts),
                                       ctypes.POINTER(Report), _dp, _ip, ctypes.c_int, _ip]
         L.ora_dense_solve.argtypes = [ctypes.c_int, _dp, _dp]
+        L.ora_set_threads.argtypes = [ctypes.c_int]
+        L.ora_threads.restype = ctypes.c_int
         L.ora_set_standard_wells.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
         L.ora_get_well_ctrl.argtypes = [ctypes.c_void_p, _ip]
         L.ora_set_well_ctrl.argtypes = [ctypes.c_void_p, _ip]

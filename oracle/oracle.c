@@ -33,6 +33,28 @@
 #include <string.h>
 #include <time.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the OpenMP build (the CPU baseline); the plain build used by
+ * the tests is single-threaded and ignores this. */
+void ora_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int ora_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------ timing */
 static double now_s(void) {
   struct timespec ts;
@@ -507,7 +529,9 @@ int ora_assemble(const ora_model* m, const double* y, const double* acc0, double
   const ora_fluid* f = &m->fl;
   memset(R, 0, sizeof(double) * 3 * m->n);
   if (J) memset(J, 0, sizeof(double) * 9 * m->nnzb);
-  /* accumulation: PV/dt (A - A0) */
+  /* accumulation: PV/dt (A - A0); cells are independent (the OpenMP build
+   * of the CPU baseline runs them in parallel, same arithmetic) */
+#pragma omp parallel for schedule(static)
   for (int c = 0; c < m->n; ++c) {
     props P;
     cell_props(f, y + 3 * c, 0, m->mean[c], &P);
@@ -519,7 +543,13 @@ int ora_assemble(const ora_model* m, const double* y, const double* acc0, double
       if (J) add_block(J, dblk, a, r.d, 1.0);
     }
   }
-  /* connection fluxes, each face once; u_ij = -u_ji exactly */
+  /* connection fluxes, each face once; u_ij = -u_ji exactly.  The fluxes
+   * of all faces are evaluated first (faces are independent: the OpenMP
+   * build runs them in parallel) and then added in face order, so the sums
+   * are the same with any number of threads. */
+  dual* flux = (dual*)malloc(sizeof(dual) * 3 * (size_t)(m->nf > 0 ? m->nf : 1));
+  if (!flux) return ORA_EINVAL;
+#pragma omp parallel for schedule(static)
   for (int fc = 0; fc < m->nf; ++fc) {
     int i = m->face[2 * fc], j = m->face[2 * fc + 1];
     props Pi, Pj;
@@ -527,11 +557,6 @@ int ora_assemble(const ora_model* m, const double* y, const double* acc0, double
     cell_props(f, y + 3 * j, 3, m->mean[j], &Pj);
     double T = m->trans[fc];
     dual dzij = dconst(m->depth[i] - m->depth[j]);
-    int bii = -1, bij = -1, bjj = -1, bji = -1;
-    if (J) {
-      bii = find_block(m, i, i); bij = find_block(m, i, j);
-      bjj = find_block(m, j, j); bji = find_block(m, j, i);
-    }
     /* phase potentials and upwind cells; component a = phase a, plus for
      * gas the gas dissolved in the oil phase, carried with the oil */
     dual dphi[3];
@@ -548,6 +573,18 @@ int ora_assemble(const ora_model* m, const double* y, const double* acc0, double
       /* wet gas: the oil vaporised in the gas moves with the gas phase */
       if (a == 1 && f->live && f->rv_c > 0.0)
         F = dadd(F, dmul(dmul(U[2]->rv, dmul(U[2]->b[2], U[2]->lam[2])), dscale(dphi[2], T)));
+      flux[3 * fc + a] = F;
+    }
+  }
+  for (int fc = 0; fc < m->nf; ++fc) {
+    int i = m->face[2 * fc], j = m->face[2 * fc + 1];
+    int bii = -1, bij = -1, bjj = -1, bji = -1;
+    if (J) {
+      bii = find_block(m, i, i); bij = find_block(m, i, j);
+      bjj = find_block(m, j, j); bji = find_block(m, j, i);
+    }
+    for (int a = 0; a < 3; ++a) {
+      dual F = flux[3 * fc + a];
       R[3 * i + a] += F.v;
       R[3 * j + a] -= F.v;
       if (J) {
@@ -558,6 +595,7 @@ int ora_assemble(const ora_model* m, const double* y, const double* acc0, double
       }
     }
   }
+  free(flux);
   /* wells: q_alpha (outflux positive) */
   for (int q = 0; q < m->nc; ++q) {
     int c = m->conn_cell[q];
@@ -745,6 +783,7 @@ void ora_ilu0_apply(const ora_model* m, const double* F, const double* r, double
 }
 
 void ora_spmv(const ora_model* m, const double* J, const double* x, double* y) {
+#pragma omp parallel for schedule(static)
   for (int i = 0; i < m->n; ++i) {
     double t[3] = {0, 0, 0};
     for (int q = m->row_ptr[i]; q < m->row_ptr[i + 1]; ++q) {

@@ -168,6 +168,12 @@ int ora_newton_step(const ora_model* m, double* y, const double* y_prev, double 
                     const ora_opts* o, ora_report* rep);
 /* Advance y over one report step of length dt with halving on failure. */
 int ora_advance(const ora_model* m, double* y, double dt, const ora_opts* o, ora_report* rep);
+/* Threads of the OpenMP build of these sources (the CPU baseline: cells of
+ * the accumulation, faces of the flux evaluation and rows of the product
+ * with J in parallel, every sum in the serial order, so the results are the
+ * serial build's bits); the plain build is single-threaded. */
+void ora_set_threads(int n);
+int ora_threads(void);
 /* The same, recording every attempted substep: its length dt_log[k] and the
  * Newton step's status st_log[k] for k < min(*n_log, log_cap). */
 int ora_advance_log(const ora_model* m, double* y, double dt, const ora_opts* o, ora_report* rep,

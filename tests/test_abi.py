@@ -294,3 +294,29 @@ def test_gmres_sizes_and_option_checks_without_gpu():
     for restart in (0, 33):
         assert L.opm_gmres(ctypes.byref(pb), R, R, 0, R, R, 1e-6, 10, restart, R,
                            ctypes.byref(rep), None) == opm.EINVAL
+
+
+def test_oracle_baseline_build_same_bits(tmp_path):
+    """The CPU baseline is the oracle's own sources built with -O3
+    -march=native and OpenMP: with one thread and with four it computes the
+    plain test build's bits (assembly of the 9000-cell case and a Newton
+    step of C1)."""
+    import oracle
+    from paper_1910_06059_amd import cases
+    so = oracle.build_baseline(str(tmp_path / "liboracle_omp.so"))
+    c2 = cases.config2()
+    y = cases.random_state(c2, seed=3)
+    y0 = cases.random_state(c2, seed=4)
+    plain = oracle.Model(c2)
+    _, R0, J0 = plain.assemble(y, plain.accumulation(y0), 86400.0)
+    c1 = cases.config1()
+    _, ys0, _ = oracle.Model(c1).newton_step(c1.initial_state(), c1.initial_state(),
+                                              c1.report_dt[0])
+    for threads in (1, 4):
+        assert oracle.set_threads(threads, so) == threads
+        omp = oracle.Model(c2, lib_path=so)
+        _, R1, J1 = omp.assemble(y, omp.accumulation(y0), 86400.0)
+        assert np.array_equal(R0, R1) and np.array_equal(J0, J1)
+        _, ys1, _ = oracle.Model(c1, lib_path=so).newton_step(c1.initial_state(),
+                                                              c1.initial_state(), c1.report_dt[0])
+        assert np.array_equal(ys0, ys1)
