@@ -13,8 +13,10 @@ nx*ny*nz box, ReLU after layers 1 and 2.  Arrays are channels-last
 (dx+1) reading the box cell (x+dx, y+dy, z+dz); the parameter vector holds
 W_0, b_0, W_1, b_1, W_2, b_2.  The predicted step is the last step
 y_n - y_{n-1} (a skip connection: linear extrapolation) plus the network's
-correction; training minimises the mean squared error of the three output
-channels against the scaled correction with Adam (Kingma and Ba, 2015).
+correction of the two saturations (output channels 1 and 2; the pressure
+keeps the extrapolation and output channel 0 is unused); training minimises
+the mean squared error of the two saturation outputs against the scaled
+correction with Adam (Kingma and Ba, 2015).
 """
 from __future__ import annotations
 
@@ -164,16 +166,18 @@ def away_from_wells(feats_box: np.ndarray, cell_box: np.ndarray) -> np.ndarray:
 
 def loss_and_dout(out: np.ndarray, tgt: np.ndarray, cell_box: np.ndarray, rounded: bool = True,
                   free=None):
-    """Squared error of the three outputs summed over the active cells in
-    `free` (all if None) and divided by 3 n_cells, and dL/d out as a box
-    (BF16 when rounded)."""
+    """Squared error of the two saturation outputs (channels 1 and 2; the
+    pressure output, channel 0, is neither trained nor used) summed over the
+    active cells in `free` (all if None) and divided by 2 n_cells, and dL/d out
+    as a box (BF16 when rounded)."""
     n = tgt.shape[0]
     o = out.reshape(-1, out.shape[3])[np.asarray(cell_box), :3]
     e = o - tgt
+    e[:, 0] = 0.0
     if free is not None:
         e = np.where(np.asarray(free)[:, None], e, 0.0)
-    loss = float(np.sum(e * e) / (3.0 * n))
-    g = 2.0 * e / (3.0 * n)
+    loss = float(np.sum(e * e) / (2.0 * n))
+    g = 2.0 * e / (2.0 * n)
     if rounded:
         g = bf16(g)
     return loss, to_box(g, cell_box, out.shape[:3])
@@ -245,9 +249,10 @@ def features(case, y_n, y_nm1, cell_box, conn_cell, conn_wi, conn_well, rounded:
 
 def apply_guess(y_n: np.ndarray, y_nm1: np.ndarray, out: np.ndarray,
                 cell_box: np.ndarray, free=None) -> np.ndarray:
-    """y_n + (y_n - y_{n-1}) + correction (dp in units of 100 psi, ds in
-    units of 0.1), the correction only in cells of `free` (all if None) and
-    only where finite; saturations clamped to [0, 1], s_g lowered so that
+    """y_n + (y_n - y_{n-1}), plus the network's correction of the two
+    saturations (in units of 0.1; the pressure keeps the extrapolation), the
+    correction only in cells of `free` (all if None) and only where all three
+    outputs are finite; saturations clamped to [0, 1], s_g lowered so that
     s_w + s_g <= 1."""
     y_n = np.asarray(y_n, dtype=np.float64)
     e = y_n + (y_n - np.asarray(y_nm1, dtype=np.float64))
@@ -256,7 +261,7 @@ def apply_guess(y_n: np.ndarray, y_nm1: np.ndarray, out: np.ndarray,
     if free is not None:
         ok &= np.asarray(free)
     o = np.where(ok[:, None], o, 0.0)
-    p = e[:, 0] + DPS * o[:, 0]
+    p = e[:, 0]
     sw = np.clip(e[:, 1] + DSS * o[:, 1], 0.0, 1.0)
     sg = np.clip(e[:, 2] + DSS * o[:, 2], 0.0, 1.0)
     sg = np.where(sw + sg > 1.0, 1.0 - sw, sg)

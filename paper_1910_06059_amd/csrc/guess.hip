@@ -3,7 +3,9 @@
 // the last two states, the log-permeability and the well terms of each cell
 // to a predicted state change over one report step: the last change
 // y_n - y_{n-1} (a skip connection, linear extrapolation) plus the network's
-// correction away from wells.  The paper always starts
+// correction of the saturations away from wells (the pressure keeps the
+// extrapolation: an error of a few psi in the slightly compressible system
+// raises the CNV far above the extrapolation's).  The paper always starts
 // Newton from the previous state (sec. 2.3); here the prediction replaces
 // that start only when its CNV is lower, and the convergence test is left
 // as it is, so converged states do not depend on the network.
@@ -308,11 +310,11 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const float* stage, int
 }
 
 // -------------------------------------------------------------- training
-// Squared error of the three outputs against the scaled correction of the
-// step to the extrapolated one, (y_next - y_n) - (y_n - y_{n-1})
-// (dp / 100 psi, ds / 0.1), summed over active cells away from wells and
-// divided by 3 n_cells; d_out = dL/d out in BF16 (channels 0-2, zero near
-// wells).
+// Squared error of the two saturation outputs against the scaled correction
+// of the step to the extrapolated one, (y_next - y_n) - (y_n - y_{n-1})
+// (ds / 0.1), summed over active cells away from wells and divided by
+// 2 n_cells; d_out = dL/d out in BF16 (channels 1-2; channel 0, the unused
+// pressure output, and cells near wells get zero).
 __global__ __launch_bounds__(kBlock) void k_loss(Grid g, int n, const int32_t* cell_box,
                                                  const unsigned short* feats, const float* out,
                                                  const double* yn, const double* ynm1,
@@ -328,11 +330,12 @@ __global__ __launch_bounds__(kBlock) void k_loss(Grid g, int n, const int32_t* c
     for (int k = 0; k < 3; ++k)
       tgt[k] = ((ynext[3 * c + k] - yn[3 * c + k]) - (yn[3 * c + k] - ynm1[3 * c + k])) /
                (k == 0 ? kDPS : kDSS);
+    dout[b * kCh] = 0;   // the pressure output is neither trained nor used
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 1; k < 3; ++k) {
       const double e = (double)out[b * kCh + k] - tgt[k];
       se += e * e;
-      dout[b * kCh + k] = f2bf((float)(2.0 * e / (3.0 * n)));
+      dout[b * kCh + k] = f2bf((float)(2.0 * e / (2.0 * n)));
     }
   }
   const double s = block_sum<kBlock>(se, sh);
@@ -345,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_loss_final(const double* partials, i
   double v = 0.0;
   for (int k = threadIdx.x; k < nblk; k += kBlock) v += partials[k];
   v = block_sum<kBlock>(v, sh);
-  if (threadIdx.x == 0) *loss = v / (3.0 * n);
+  if (threadIdx.x == 0) *loss = v / (2.0 * n);
 }
 
 // Adam (Kingma and Ba) on the FP32 master parameters; step is 1-based.
@@ -377,10 +380,12 @@ __global__ __launch_bounds__(256) void k_pack_weights(const float* master, unsig
   wb[(size_t)layer * kLayerW + (t * kCh + ci) * kCh + co] = v;
 }
 
-// y_guess = y_n + (y_n - y_{n-1}) + correction (the skip connection is
-// applied in FP64); the correction is used only away from wells and only if
-// finite, and not at all when out is null (the extrapolation alone);
-// saturations clamped to [0, 1] with s_w + s_g <= 1 (s_g reduced first).
+// y_guess = y_n + (y_n - y_{n-1}) + the correction of the two saturations
+// (the skip connection is applied in FP64; the pressure keeps the
+// extrapolation, output 0 is unused); the correction is used only away from
+// wells and only if all three outputs are finite, and not at all when out is
+// null (the extrapolation alone); saturations clamped to [0, 1] with
+// s_w + s_g <= 1 (s_g reduced first).
 __global__ __launch_bounds__(kBlock) void k_guess_apply(Grid g, int n, const int32_t* cell_box,
                                                         const unsigned short* feats,
                                                         const double* yn, const double* ynm1,
@@ -396,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_guess_apply(Grid g, int n, const int
     o2 = out[b * kCh + 2];
     ok = isfinite(o0) && isfinite(o1) && isfinite(o2) && !near_well(g, feats, (int)b);
   }
-  const double p = yn[3 * c] + (yn[3 * c] - ynm1[3 * c]) + (ok ? kDPS * (double)o0 : 0.0);
+  const double p = yn[3 * c] + (yn[3 * c] - ynm1[3 * c]);
   double sw = yn[3 * c + 1] + (yn[3 * c + 1] - ynm1[3 * c + 1]) + (ok ? kDSS * (double)o1 : 0.0);
   double sg = yn[3 * c + 2] + (yn[3 * c + 2] - ynm1[3 * c + 2]) + (ok ? kDSS * (double)o2 : 0.0);
   sw = fmin(fmax(sw, 0.0), 1.0);

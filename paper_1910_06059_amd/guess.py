@@ -76,17 +76,18 @@ def train(net: "opm.GuessNet", data: Sequence[Tuple["opm.GpuModel", List[torch.T
 
 
 def compare(model: "opm.GpuModel", net: Optional["opm.GuessNet"], n_steps: Optional[int] = None,
-            opts=None, log: Optional[Callable[[str], None]] = None) -> dict:
+            opts=None, log: Optional[Callable[[str], None]] = None, keep: int = 0) -> dict:
     """Advance the case from its initial state, each report step after the
     first started from the learned guess (net given) or every step from the
     previous state (net None); the first step has no previous change and
     always starts from the previous state.
     Returns per-step Newton and linear iterations, wall time and the start
     taken (0 previous state, 1 learned guess, 2 its extrapolation path
-    alone), and the final state (host)."""
+    alone), the final state (host) and the states after the first `keep`
+    report steps (host copies, taken outside the timed region)."""
     y = model.initial_state()
     y_nm1 = y.clone()
-    out = {"newton": [], "lin": [], "wall": [], "used": [], "cuts": []}
+    out = {"newton": [], "lin": [], "wall": [], "used": [], "cuts": [], "states": []}
     for k, dt in enumerate(model.case.report_dt[:n_steps]):
         prev = y.clone()
         torch.cuda.synchronize()
@@ -103,6 +104,8 @@ def compare(model: "opm.GpuModel", net: Optional["opm.GuessNet"], n_steps: Optio
         out["wall"].append(wall)
         out["used"].append(used)
         out["cuts"].append(rep.cuts)
+        if k < keep:
+            out["states"].append(y.cpu().numpy())
         if log:
             log(f"{model.case.name} {'guess' if net is not None else 'prev '} step {k}: "
                 f"newton {rep.newton_its} lin {rep.lin_its} used {used} {wall:.3f}s")

@@ -142,25 +142,30 @@ def pin_adam_closed_forms():
 
 
 def pin_loss_closed_form():
-    """A constant error e in every output gives loss e^2 and dL/dout = 2e/(3n);
-    with cells left out the sum shrinks but the divisor stays 3n."""
+    """A constant error e in every output gives loss e^2 over the two
+    saturation outputs and dL/dout = 2e/(2n) there, zero for the unused
+    pressure output whatever its error; with cells left out the sum shrinks
+    but the divisor stays 2n."""
     rng = _rng(8)
     shape = (2, 2, 3)
     cell_box = np.array([0, 2, 3, 5, 7, 11])
     tgt = rng.standard_normal((6, 3))
     e = 0.25
-    out = cn.to_box(tgt + e, cell_box, shape)
+    o = tgt + e
+    o[:, 0] += 7.0                      # the pressure output does not count
+    out = cn.to_box(o, cell_box, shape)
     loss, d = cn.loss_and_dout(out, tgt, cell_box, rounded=False)
     assert abs(loss - e * e) <= 1e-15
     dd = d.reshape(-1, cn.CH)
-    assert np.allclose(dd[cell_box, :3], 2 * e / 18.0, rtol=1e-15, atol=0)
-    assert not np.any(dd[:, 3:]) and not np.any(np.delete(dd, cell_box, axis=0))
+    assert np.allclose(dd[cell_box, 1:3], 2 * e / 12.0, rtol=1e-15, atol=0)
+    assert not np.any(dd[:, 0]) and not np.any(dd[:, 3:])
+    assert not np.any(np.delete(dd, cell_box, axis=0))
     # cells outside `free` contribute nothing but the count stays n
     free = np.array([True, False, True, True, False, True])
     loss2, d2 = cn.loss_and_dout(out, tgt, cell_box, rounded=False, free=free)
     assert abs(loss2 - e * e * 4.0 / 6.0) <= 1e-15
     dd2 = d2.reshape(-1, cn.CH)
-    assert not np.any(dd2[cell_box[~free]]) and np.allclose(dd2[cell_box[free], :3], 2 * e / 18.0)
+    assert not np.any(dd2[cell_box[~free]]) and np.allclose(dd2[cell_box[free], 1:3], 2 * e / 12.0)
 
 
 def _feature_case():
@@ -201,9 +206,10 @@ def pin_features_worked_values():
 
 
 def pin_apply_guess_special_cases():
-    """The guess is y_n + (y_n - y_{n-1}) + correction (dp per 100 psi, ds
-    per 0.1); saturations clamped, s_g lowered to keep s_w + s_g <= 1, a
-    non-finite correction dropped (the extrapolation remains)."""
+    """The guess is y_n + (y_n - y_{n-1}) plus the saturation correction (ds
+    per 0.1; the pressure output is ignored, the pressure is extrapolated);
+    saturations clamped, s_g lowered to keep s_w + s_g <= 1, a non-finite
+    output dropping the whole correction (the extrapolation remains)."""
     y_n = np.array([[1e7, 0.5, 0.2], [2e7, 0.1, 0.1], [3e7, 0.9, 0.05], [4e7, 0.3, 0.3]])
     y_nm1 = np.array([[1e7 - 50 * PSI, 0.45, 0.2], [2e7, 0.1, 0.1], [3e7, 0.8, 0.05],
                       [4e7 + 10 * PSI, 0.3, 0.35]])
@@ -213,8 +219,8 @@ def pin_apply_guess_special_cases():
     out[0, 0, 2, :3] = [0.0, 2.0, 1.0]
     out[0, 0, 3, :3] = [np.nan, 1.0, 1.0]
     g = cn.apply_guess(y_n, y_nm1, out, np.arange(4))
-    assert np.allclose(g[0], [1e7 + 150 * PSI, 0.65, 0.15], rtol=1e-15, atol=1e-15)
-    assert np.allclose(g[1], [2e7 - 200 * PSI, 0.0, 1.0], rtol=1e-15)
+    assert np.allclose(g[0], [1e7 + 50 * PSI, 0.65, 0.15], rtol=1e-15, atol=1e-15)
+    assert np.allclose(g[1], [2e7, 0.0, 1.0], rtol=1e-15)
     assert np.allclose(g[2], [3e7, 1.0, 0.0], rtol=1e-15)
     assert np.allclose(g[3], [4e7 - 10 * PSI, 0.3, 0.25], rtol=1e-15, atol=1e-15)
     # cells outside `free` (well cells) keep the extrapolation
@@ -246,8 +252,9 @@ def pin_targets_round_trip():
     y_nm1 = y_n - step
     t = cn.targets(y_n, y_nm1, y_next)
     out = cn.to_box(t, np.arange(n), (1, 1, n))
-    assert np.allclose(cn.apply_guess(y_n, y_nm1, out, np.arange(n)), y_next, rtol=1e-12,
-                       atol=1e-12)
+    got = cn.apply_guess(y_n, y_nm1, out, np.arange(n))
+    assert np.allclose(got[:, 1:], y_next[:, 1:], rtol=1e-12, atol=1e-12)
+    assert np.array_equal(got[:, 0], y_n[:, 0] + (y_n[:, 0] - y_nm1[:, 0]))
 
 
 def pin_forward_identity_network():
@@ -342,7 +349,22 @@ _orig_apply = cn.apply_guess
 def _mut_apply_noclamp(y_n, y_nm1, out, cell_box):
     o = out.reshape(-1, out.shape[3])[np.asarray(cell_box), :3]
     e = 2 * np.asarray(y_n) - np.asarray(y_nm1)
-    return e + np.stack([cn.DPS * o[:, 0], cn.DSS * o[:, 1], cn.DSS * o[:, 2]], axis=1)
+    return e + np.stack([0.0 * o[:, 0], cn.DSS * o[:, 1], cn.DSS * o[:, 2]], axis=1)
+
+
+def _mut_apply_pressure_corrected(y_n, y_nm1, out, cell_box):
+    g = _orig_apply(y_n, y_nm1, out, cell_box)
+    o = out.reshape(-1, out.shape[3])[np.asarray(cell_box), 0]
+    g[:, 0] += cn.DPS * np.where(np.isfinite(o), o, 0.0)
+    return g
+
+
+def _mut_loss_trains_pressure(out, tgt, cell_box, rounded=True, free=None):
+    loss, d = _orig_loss(out, tgt, cell_box, rounded, free)
+    o = out.reshape(-1, out.shape[3])[np.asarray(cell_box), 0]
+    dd = d.reshape(-1, d.shape[3]).copy()
+    dd[np.asarray(cell_box), 0] = 2.0 * (o - tgt[:, 0]) / (2.0 * tgt.shape[0])
+    return loss, dd.reshape(d.shape)
 
 
 def _mut_apply_noskip(y_n, y_nm1, out, cell_box):
@@ -365,6 +387,8 @@ MUTANTS = {
     "backward_without_relu_mask": ("backward", _mut_backward_nomask),
     "loss_mean_over_n": ("loss_and_dout", _mut_loss_over_n),
     "guess_without_clamp": ("apply_guess", _mut_apply_noclamp),
+    "guess_corrects_pressure": ("apply_guess", _mut_apply_pressure_corrected),
+    "loss_trains_pressure": ("loss_and_dout", _mut_loss_trains_pressure),
     "guess_without_skip": ("apply_guess", _mut_apply_noskip),
     "targets_without_skip": ("targets", _mut_targets_noskip),
     "saturation_scale": ("DSS", 1.0),
