@@ -292,22 +292,44 @@ __global__ __launch_bounds__(256) void k_pack_block_records(Topo t, const int32_
   }
 }
 
-// Block-ILU0 sweep rows are spread over three lanes, one per equation a:
-// lane a holds row a of the three neighbour blocks and of D^{-1} (12
-// values, the record of (row, a)), computes its partial sum
+// Block-ILU0 sweep rows are spread over a quad of lanes, lane a < 3 per
+// equation a: lane a holds row a of the three neighbour blocks and of
+// D^{-1} (12 values, the record of (row, a)), computes its partial sum
 //   acc_a = r_a - sum_s A_s[a][.] x_s   (forward; backward with + and 0),
-// takes acc_b of the two other lanes of the row by cross-lane shuffle and
-// finishes with D^{-1}[a][.] acc.  The arithmetic and its order per value
-// are those of the other sweep kernels (bitwise equal results).  A
-// wavefront holds 21 rows (lanes 3q + a, lane 63 idle).
-constexpr int kRowsPerWave = 21;
+// takes acc_b of the two other lanes of the quad by DPP quad permutation
+// and finishes with D^{-1}[a][.] acc.  The arithmetic and its order per
+// value are those of the other sweep kernels (bitwise equal results).  A
+// wavefront holds 16 rows (lanes 4q + a; lane 4q + 3 repeats lane 4q + 2's
+// work and stores nothing), the widest level of a 4x4 column.  Records,
+// right-hand sides and the index are read with buffer loads (one 32-bit
+// offset per level, chunk offsets in scalar registers).
+constexpr int kRowsPerWave = 16;
+// Word 3 of a raw buffer resource on gfx9 (32-bit data format, no swizzle).
+constexpr int kBufferWord3 = 0x00020000;
+// A value in LDS (address space 3: 32-bit addresses).
+template <typename T>
+using Lds = __attribute__((address_space(3))) T;
 
 __device__ __forceinline__ int block_lane_row() {
-  return (int)(threadIdx.x >> 6) * kRowsPerWave + (int)(threadIdx.x & 63u) / 3;
+  return (int)(threadIdx.x >> 6) * kRowsPerWave + (int)(threadIdx.x & 63u) / 4;
 }
-__device__ __forceinline__ int block_lane_eq() {
-  const int l = (int)(threadIdx.x & 63u);
-  return l < 63 ? l % 3 : 3;
+__device__ __forceinline__ int block_lane_eq() { return (int)(threadIdx.x & 3u); }
+
+// Value of lane K of the lane's quad (DPP quad permutation: a VALU move, no
+// LDS round trip).
+template <int K>
+__device__ __forceinline__ double quad_lane(double x) {
+  constexpr int ctrl = K | (K << 2) | (K << 4) | (K << 6);
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, ctrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+template <int K>
+__device__ __forceinline__ float quad_lane(float x) {
+  constexpr int ctrl = K | (K << 2) | (K << 4) | (K << 6);
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), ctrl, 0xf, 0xf, false));
 }
 
 template <typename T>
@@ -368,7 +390,7 @@ __device__ __forceinline__ BlockStage block_index(IluView<T> v, const int* lp, i
 // including it (backward).  Missing neighbours (index -1) read the zero row
 // at slot zslot.
 template <typename T, bool FWD, int MODE>
-__device__ __forceinline__ void block_data(IluView<T> v, const BlockRhs& q, const T* zl, int row,
+__device__ __forceinline__ void block_data(IluView<T> v, const BlockRhs& q, const Lds<T>* zl, int row,
                                            int base, int zslot, const BlockStage& st,
                                            BlockJob<T>& j) {
   typedef typename Vec16<T>::type V;
@@ -382,10 +404,16 @@ __device__ __forceinline__ void block_data(IluView<T> v, const BlockRhs& q, cons
   j.kp[2] = st.ix.z < 0 ? zslot : st.ix.z;
   j.cell = st.ix.w;
   j.slot = (FWD ? base : base - (st.p1 - st.p0)) + (st.pos - st.p0);
-  const V* rec = reinterpret_cast<const V*>(FWD ? v.rec_f : v.rec_b);
+  // buffer loads: one 32-bit lane offset per level, the chunk offsets in
+  // scalar registers (no 64-bit address arithmetic per load); reads past
+  // the records return zero
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(FWD ? v.rec_f : v.rec_b), (short)0, (int)(kC * ns * 48u), kBufferWord3);
+  const int voff = (int)((up * 3u + a) * 16u);
 #pragma unroll
   for (unsigned c = 0; c < kC; ++c) {
-    const V w = rec[(c * ns + up) * 3u + a];
+    const V w = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(
+                                          rs, voff, (int)(c * ns * 48u), 0));
 #pragma unroll
     for (unsigned qq = 0; qq < kV; ++qq) {
       const unsigned e = c * kV + qq;
@@ -396,16 +424,21 @@ __device__ __forceinline__ void block_data(IluView<T> v, const BlockRhs& q, cons
     }
   }
   if (FWD) {
-    const unsigned i = 3u * (unsigned)j.cell + a;
-    if (MODE == kry::kFuseNone) j.u[0] = q.r[i];
+    const int off = (int)((3u * (unsigned)j.cell + a) * 8u);
+    auto ld = [&](const double* base) {
+      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)base, (short)0, 0x7fffffff, kBufferWord3);
+      return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    };
+    if (MODE == kry::kFuseNone) j.u[0] = ld(q.r);
     if (MODE == kry::kFuseBegin) {
-      j.u[0] = q.f.r[i];
-      j.u[1] = q.f.p[i];
-      j.u[2] = q.f.v[i];
+      j.u[0] = ld(q.f.r);
+      j.u[1] = ld(q.f.p);
+      j.u[2] = ld(q.f.v);
     }
     if (MODE == kry::kFuseS) {
-      j.u[0] = q.f.r[i];
-      j.u[1] = q.f.v[i];
+      j.u[0] = ld(q.f.r);
+      j.u[1] = ld(q.f.v);
     }
   } else {
     // y of the row (forward result); slots of lanes past the level's end
@@ -424,7 +457,7 @@ __device__ __forceinline__ void block_data(IluView<T> v, const BlockRhs& q, cons
 // Every lane computes (the shuffles need all lanes); only rows of the level
 // store.
 template <typename T, bool FWD, int MODE>
-__device__ __forceinline__ void block_row(const BlockJob<T>& j, T* zl, double* x,
+__device__ __forceinline__ void block_row(const BlockJob<T>& j, Lds<T>* zl, double* x,
                                           const BlockRhs& q, double& ss) {
   const int eq = block_lane_eq();
   const unsigned a = (unsigned)min(eq, 2);
@@ -439,14 +472,12 @@ __device__ __forceinline__ void block_row(const BlockJob<T>& j, T* zl, double* x
   for (int s = 0; s < 3; ++s) {
     // a missing neighbour reads the zero row: x = 0 exactly, as in the
     // other sweep kernels
-    const T* w = zl + 3u * (unsigned)j.kp[s];
+    const Lds<T>* w = zl + 3u * (unsigned)j.kp[s];
     const T x0 = w[0], x1 = w[1], x2 = w[2];
     const T t = j.a[3 * s] * x0 + j.a[3 * s + 1] * x1 + j.a[3 * s + 2] * x2;
     acc = FWD ? acc - t : acc + t;
   }
-  const int lane0 = (int)(threadIdx.x & 63u) - (int)a;
-  const T acc0 = __shfl(acc, lane0, 64), acc1 = __shfl(acc, lane0 + 1, 64),
-          acc2 = __shfl(acc, lane0 + 2, 64);
+  const T acc0 = quad_lane<0>(acc), acc1 = quad_lane<1>(acc), acc2 = quad_lane<2>(acc);
   const T d = j.d[0] * acc0 + j.d[1] * acc1 + j.d[2] * acc2;
   const T out = FWD ? d : j.rhs - d;
   if (!j.live) return;
@@ -459,10 +490,10 @@ __device__ __forceinline__ void block_row(const BlockJob<T>& j, T* zl, double* x
   }
 }
 
-// Rows of a level beyond the first NT / 64 * 21 (subdomains with wider
+// Rows of a level beyond the first NT / 64 * 16 (subdomains with wider
 // levels).
 template <typename T, int NT, bool FWD, int MODE>
-__device__ __forceinline__ void block_extra(IluView<T> v, const BlockRhs& q, T* zl, double* x,
+__device__ __forceinline__ void block_extra(IluView<T> v, const BlockRhs& q, Lds<T>* zl, double* x,
                                             const int* lp, int nlev, int k, int base, int zslot,
                                             double& ss) {
   constexpr int kRows = NT / 64 * kRowsPerWave;
@@ -485,7 +516,7 @@ __device__ __forceinline__ void block_extra(IluView<T> v, const BlockRhs& q, T* 
 // stages rotate through register rings (3 indices, DEPTH + 1 jobs), fully
 // unrolled over a period of P steps so that every ring slot is a register.
 template <typename T, int NT, bool FWD, bool WIDE, int DEPTH, int MODE, typename Gate>
-__device__ __forceinline__ bool block_sweep(IluView<T> v, BlockRhs& q, T* zl, double* x,
+__device__ __forceinline__ bool block_sweep(IluView<T> v, BlockRhs& q, Lds<T>* zl, double* x,
                                             const int* lp, int nlev, int nrows, int zslot,
                                             double& ss, Gate gate) {
   constexpr int ND = DEPTH + 1, NI = 3;
@@ -555,7 +586,9 @@ __global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t
   __shared__ int word;
   if (MODE == kry::kFuseNone && skip && *skip != 0) return;
   extern __shared__ unsigned char smem[];
-  T* zl = reinterpret_cast<T*>(smem);   // [max_sub + 1][3], the last row zero
+  // [max_sub + 1][3], the last row zero; an LDS-qualified pointer keeps the
+  // address arithmetic in 32 bits
+  Lds<T>* zl = (Lds<T>*)reinterpret_cast<T*>(smem);
   int* lp = reinterpret_cast<int*>(smem + sizeof(T) * 3 * ((size_t)max_sub + 1));
   const int s = blockIdx.x;
   for (int l = threadIdx.x; l < nlev; l += NT) {
