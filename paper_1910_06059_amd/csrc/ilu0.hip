@@ -683,7 +683,7 @@ int allow_lds(K kernel, int slot) {
 }
 
 // Threads of a block-ILU0 factorisation workgroup (a row per thread) and of
-// a sweep workgroup (21 rows per wavefront): the widest level of a
+// a sweep workgroup (16 rows per wavefront): the widest level of a
 // subdomain rounded up to a wavefront, at most 256 (wider levels loop).
 int block_threads(const opm_problem* pb) {
   return pb->max_width <= 64 ? 64 : pb->max_width <= 128 ? 128 : 256;
