@@ -10,10 +10,10 @@
 // that start only when its CNV is lower, and the convergence test is left
 // as it is, so converged states do not depend on the network.
 //
-// Convolutions are implicit GEMMs on the BF16 matrix cores
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulation): one wavefront owns 16
-// consecutive box cells x 16 output channels and accumulates 27 tap
-// products of 16x16x16 (the 16 input channels are the reduction).
+// Convolutions are implicit GEMMs on the BF16 matrix cores of gfx950
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation): one wavefront owns 16
+// consecutive box cells x 16 output channels and accumulates 14 products of
+// 16x16x32, each reducing over the 16 input channels of two taps.
 // Activations and their gradients are stored channels-last in BF16
 // ([box cell][16], rounded to nearest even); weights exist as an FP32 master
 // copy (updated by Adam) and as BF16 operand copies in the two layouts that
@@ -43,7 +43,19 @@ constexpr int kReduceGroup = 32;                  // waves per stage-1 sum of th
 static_assert(kParams == OPM_GUESS_PARAMS, "parameter count");
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short short8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f32_16x16x32_bf16 (gfx950): D[16][16] += A[16][32] B[32][16] in
+// FP32; lane l holds A[l % 16][k] and B[k][l % 16] for the eight k of lane
+// group l / 16, and D[4 (l / 16) + r][l % 16].  A product sums over k, so
+// any assignment of the (tap, channel) or cell pairs to k that A and B
+// share gives the same sum.
+__device__ __forceinline__ floatx4 mfma32(const short8& a, const short8& b, const floatx4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
 
 __device__ __forceinline__ unsigned short f2bf(float f) {   // round to nearest even
   unsigned u = __float_as_uint(f);
@@ -150,22 +162,23 @@ __device__ __forceinline__ bool near_well(const Grid& g, const unsigned short* f
 // ---------------------------------------------------- convolution (MFMA)
 // Tap t covers the offset (t % 3 - 1, t / 3 % 3 - 1, t / 9 - 1) in (x, y, z).
 //
-// MFMA 16x16x16 operand layout (64 lanes, m = lane % 16, kb = lane / 16):
-// A: lane holds A[m][4kb .. 4kb+3]; B: lane holds B[4kb .. 4kb+3][m];
-// D: lane holds D[4kb + r][m], r = 0..3.
-//
-// conv_tile: A rows are the 16 cells of the tile, A columns the input
-// channels of the cell at the tap offset (mirrored when FLIP); B = wt[t] as
-// [n][k] rows of 16.
+// conv_tile: one 16x16x32 product per pair of taps: A rows are the 16 cells
+// of the tile, A columns the 16 input channels of the cell at each of the
+// two tap offsets (mirrored when FLIP); B the two taps' weights wt[t] as
+// [n][k] rows of 16.  Lane group kb takes tap t + kb / 2 and channels
+// 8 (kb % 2) .. + 7 in both operands; the 27th tap pairs with zeros.
 template <bool FLIP>
 __device__ __forceinline__ floatx4 conv_tile(const Grid& g, const unsigned short* in,
                                              const unsigned short* wt, int tile, int lane) {
   const int m = lane & 15, kb = lane >> 4;
+  const int half = kb >> 1, c8 = (kb & 1) * 8;
   const int cell = tile * 16 + m;
   const bool valid = cell < g.nbox;
   const int ci = cell % g.nx, cj = (cell / g.nx) % g.ny, ck = cell / (g.nx * g.ny);
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int t = 0; t < kTaps; ++t) {
+#pragma unroll
+  for (int t2 = 0; t2 < kTaps; t2 += 2) {
+    const int t = t2 + half;
     int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
     if (FLIP) {
       dx = -dx;
@@ -173,13 +186,16 @@ __device__ __forceinline__ floatx4 conv_tile(const Grid& g, const unsigned short
       dz = -dz;
     }
     const int ii = ci + dx, jj = cj + dy, kk = ck + dz;
-    bf16x4 a = {0, 0, 0, 0};
-    if (valid && ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz) {
-      const unsigned nb = (unsigned)(ii + g.nx * (jj + g.ny * kk));
-      a = *reinterpret_cast<const bf16x4*>(in + nb * kCh + 4 * kb);
+    short8 a = {0, 0, 0, 0, 0, 0, 0, 0};
+    short8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (t < kTaps) {
+      if (valid && ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz) {
+        const unsigned nb = (unsigned)(ii + g.nx * (jj + g.ny * kk));
+        a = *reinterpret_cast<const short8*>(in + nb * kCh + c8);
+      }
+      b = *reinterpret_cast<const short8*>(wt + (t * kCh + m) * kCh + c8);
     }
-    const bf16x4 b = *reinterpret_cast<const bf16x4*>(wt + (t * kCh + m) * kCh + 4 * kb);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    acc = mfma32(a, b, acc);
   }
   return acc;
 }
@@ -229,10 +245,12 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(Grid g, const unsigned sh
 
 // Weight-gradient partials of one wave over kChunk tiles:
 // dW[t][cout][cin] = sum_cells in[cell + off_t][cin] d_out[cell][cout] as
-// 16x16x16 products whose reduction runs over 16 cells (A = in^T with rows
-// cin, B = d_out with columns cout); bias[cout] = sum_cells d_out[cell][cout].
-// Tiles are the outer loop: a lane's four cells and their d_out values are
-// found once per tile and the 27 tap accumulators stay in registers.
+// 16x16x32 products whose reduction runs over 32 cells, two tiles (A =
+// in^T with rows cin, B = d_out with columns cout; lane group kb takes
+// cells 8 kb .. 8 kb + 7 of the pair in both operands); bias[cout] =
+// sum_cells d_out[cell][cout].  Tile pairs are the outer loop: a lane's
+// eight cells and their d_out values are found once per pair and the 27 tap
+// accumulators stay in registers.
 __global__ __launch_bounds__(256) void k_conv_bwd_weight(Grid g, const unsigned short* in,
                                                          const unsigned short* dout, int ntiles,
                                                          float* partials) {
@@ -246,14 +264,14 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight(Grid g, const unsigned 
 #pragma unroll
   for (int t = 0; t < kTaps; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.f;
-  for (int tile = t0; tile < t1; ++tile) {
-    int ci[4], cj[4], ck[4];
-    bool ok[4];
-    bf16x4 b = {0, 0, 0, 0};
+  for (int tile = t0; tile < t1; tile += 2) {
+    int ci[8], cj[8], ck[8];
+    bool ok[8];
+    short8 b = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int cell = tile * 16 + 4 * kb + r;
-      ok[r] = cell < g.nbox;
+    for (int r = 0; r < 8; ++r) {
+      const int cell = tile * 16 + 8 * kb + r;
+      ok[r] = cell < g.nbox && cell < t1 * 16;
       const int c = ok[r] ? cell : 0;
       ci[r] = c % g.nx;
       cj[r] = (c / g.nx) % g.ny;
@@ -265,14 +283,14 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight(Grid g, const unsigned 
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) {
       const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-      bf16x4 a = {0, 0, 0, 0};
+      short8 a = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < 8; ++r) {
         const int ii = ci[r] + dx, jj = cj[r] + dy, kk = ck[r] + dz;
         if (ok[r] && ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz)
           a[r] = (short)in[(unsigned)(ii + g.nx * (jj + g.ny * kk)) * kCh + m];
       }
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      acc[t] = mfma32(a, b, acc[t]);
     }
   }
   float* P = partials + (size_t)wave * kLayerParams;
@@ -280,7 +298,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight(Grid g, const unsigned 
   for (int t = 0; t < kTaps; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) P[(t * kCh + m) * kCh + 4 * kb + r] = acc[t][r];
-  // lanes m, m+16, m+32, m+48 hold the four k blocks of channel m
+  // lanes m, m+16, m+32, m+48 hold the four cell groups of channel m
   bsum += __shfl_xor(bsum, 16, 64);
   bsum += __shfl_xor(bsum, 32, 64);
   if (kb == 0) P[kLayerW + m] = bsum;
