@@ -369,6 +369,13 @@ typedef struct opm_problem {
    * Both give the same residual and Jacobian up to rounding. */
   int32_t nx, ny, nz, pad_l;
   const int32_t* box_cell;
+  /* cell_box [n_cells] (device): the box index of each active cell (the
+   * inverse of box_cell).  With both maps, the ILU(0) sweeps of a system
+   * too large for one workgroup run plane by plane in one launch each: one
+   * workgroup per z-plane walks the plane's diagonals i + j, and a row waits
+   * only for the value of its neighbour in the plane below (forward) or
+   * above (backward).  NULL: one launch per level. */
+  const int32_t* cell_box;
 } opm_problem;
 
 /* Library set-up: checks that the current device is a gfx950 (MI355X) and
@@ -842,13 +849,23 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
  *     0 enqueues the kernels one by one.
  *   OPM_OPT_ASSEMBLY: 1 (default) the LDS-tiled assembly where the problem
  *     allows it (box_cell set, dead oil, fixed-source wells), 0 always the
- *     row-per-lane assembly. */
+ *     row-per-lane assembly.
+ *   OPM_OPT_PLANE_SWEEP: sweeps of the ILU(0) of a large system (sweep mode
+ *     1): 1 (default) plane-pipelined where box_cell and cell_box are set
+ *     (one workgroup per z-plane), 0 one launch per level.
+ *   OPM_OPT_PLANE_SPIN: re-reads a plane sweep makes of a value of the
+ *     neighbouring plane that is not yet written before it gives up
+ *     (default 262144; 0 gives up at once, to exercise the failure path): a
+ *     sweep that gives up returns NaN, so the Krylov solver reports
+ *     non-finite values instead of hanging. */
 #define OPM_OPT_SWEEP_MODE 1
 #define OPM_OPT_KRYLOV_CHUNK 2
 #define OPM_OPT_SWEEP_KERNEL 3
 #define OPM_OPT_BLOCK_DEPTH 4
 #define OPM_OPT_KRYLOV_GRAPH 5
 #define OPM_OPT_ASSEMBLY 6
+#define OPM_OPT_PLANE_SWEEP 7
+#define OPM_OPT_PLANE_SPIN 8
 int opm_set_option(int option, int value);
 
 const char* opm_strerror(int code);

@@ -35,6 +35,8 @@ namespace opm {
 
 extern int g_sweep_kernel;
 extern int g_block_depth;
+extern int g_plane_sweep;
+extern int g_plane_spin;
 
 namespace {
 
@@ -703,6 +705,312 @@ size_t block_lds(const opm_problem* pb) {
   return sizeof(T) * 3 * ((size_t)pb->max_sub + 1) + sizeof(int) * 2 * (size_t)pb->n_levels;
 }
 
+// ---------------------------------------------- plane-pipelined sweeps
+// The ILU(0) of a system too large for one workgroup, on a Cartesian
+// lattice: the rows of z-plane k on diagonal d = i + j form one contiguous
+// range of the level schedule (level i + j + k lists its rows in natural
+// order, so by plane), their lower neighbours are the same plane's diagonal
+// d - 1 and plane k - 1's diagonal d.  One workgroup per plane walks its
+// diagonals in order with the previous diagonal's results in an LDS ring;
+// the values another plane reads go through a vector that is filled with a
+// marker before the sweep (a signalling-NaN bit pattern, which no
+// arithmetic result has), are written through to the device's coherence
+// point and are read from there until they no longer hold the marker.  So a
+// plane never waits for a whole step of its neighbour, only for the values
+// it needs, and needs no counters, fences or completion waits.  The
+// backward sweep mirrors the forward one downwards.  Workgroups are
+// dispatched in index order and only wait on lower indices, so they cannot
+// deadlock; the wait is bounded all the same, and a wait that gives up
+// raises an abort word that every workgroup honours: the solve then returns
+// NaN (the Krylov solver reports it) instead of hanging.  The row arithmetic
+// is solve_row's, so the results equal the per-level launches' bit for bit.
+constexpr int kPlaneThreads = 256;
+typedef int int2v __attribute__((ext_vector_type(2)));
+
+struct PlaneTab {
+  int2v* rng;       // [nz][D] (first position, end position) of plane k on diagonal d
+  int32_t* abort_w;
+  void* xb;         // [3][ns] the backward sweep's results by position (T)
+  int nx, ny, nz, D, W;
+  unsigned spin;    // polls of a wait before it gives up (0: at once)
+};
+
+inline bool plane_capable(const opm_problem* pb) {
+  return pb->box_cell && pb->cell_box && pb->nx > 0 && pb->ny > 0 && pb->nz > 0 &&
+         std::min(pb->nx, pb->ny) <= kPlaneThreads && pb->nz <= 4096 &&
+         pb->nx + pb->ny - 1 <= 4096;
+}
+inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+// sized for FP64 (the FP32 factors use half of the vector)
+inline size_t plane_bytes(const opm_problem* pb) {
+  if (!plane_capable(pb)) return 0;
+  const size_t D = (size_t)pb->nx + pb->ny - 1;
+  return al256(sizeof(int2v) * D * pb->nz) + 256 +
+         al256(sizeof(double) * 3 * ilu_padded(pb->n_cells));
+}
+template <typename T>
+PlaneTab plane_tab(const opm_problem* pb, void* ilu) {
+  PlaneTab p;
+  char* base = (char*)ilu + al256(view_bytes<T>(pb->n_cells));
+  p.nx = pb->nx;
+  p.ny = pb->ny;
+  p.nz = pb->nz;
+  p.D = pb->nx + pb->ny - 1;
+  p.W = std::min(pb->nx, pb->ny);
+  p.rng = (int2v*)base;
+  base += al256(sizeof(int2v) * (size_t)p.D * p.nz);
+  p.abort_w = (int32_t*)base;
+  p.xb = base + 256;
+  p.spin = (unsigned)g_plane_spin;
+  return p;
+}
+
+__global__ __launch_bounds__(256) void k_plane_init(PlaneTab p) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e < p.D * p.nz) p.rng[e] = int2v{0x7fffffff, -1};
+}
+
+__global__ __launch_bounds__(256) void k_plane_fill(Topo t, const int32_t* cell_box, PlaneTab p) {
+  const int pos = blockIdx.x * 256 + threadIdx.x;
+  if (pos >= t.n) return;
+  const int box = cell_box[t.perm[pos]];
+  const int i = box % p.nx, j = (box / p.nx) % p.ny, k = box / (p.nx * p.ny);
+  int* e = reinterpret_cast<int*>(p.rng + (size_t)k * p.D + i + j);
+  atomicMin(e, pos);
+  atomicMax(e + 1, pos + 1);
+}
+
+// the marker of a value not yet written (signalling NaNs: arithmetic
+// returns quiet ones)
+__device__ __forceinline__ void unset_value(double& v) {
+  v = __builtin_bit_cast(double, 0x7FF4A5A5A5A5A5A5ull);
+}
+__device__ __forceinline__ void unset_value(float& v) { v = __builtin_bit_cast(float, 0x7FA5A5A5u); }
+__device__ __forceinline__ bool is_unset(double v) {
+  return __builtin_bit_cast(unsigned long long, v) == 0x7FF4A5A5A5A5A5A5ull;
+}
+__device__ __forceinline__ bool is_unset(float v) {
+  return __builtin_bit_cast(unsigned, v) == 0x7FA5A5A5u;
+}
+
+// Before a pair of sweeps: both exchange vectors hold the marker, no abort.
+template <typename T>
+__global__ __launch_bounds__(256) void k_plane_reset(IluView<T> v, PlaneTab p,
+                                                      const int32_t* skip) {
+  if (skip && *skip != 0) return;
+  T u;
+  unset_value(u);
+  const unsigned n = 3u * (unsigned)v.ns;
+  T* xb = static_cast<T*>(p.xb);
+  for (unsigned e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+    v.z[e] = u;
+    xb[e] = u;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p.abort_w = 0;
+}
+
+__device__ __forceinline__ double coherent_load(const double* p) {
+  return __builtin_bit_cast(double, __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ float coherent_load(const float* p) {
+  return __builtin_bit_cast(float, __hip_atomic_load(reinterpret_cast<const unsigned*>(p),
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+// written through to the device's coherence point
+__device__ __forceinline__ void coherent_store(double* p, double x) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __builtin_bit_cast(unsigned long long, x),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void coherent_store(float* p, float x) {
+  __hip_atomic_store(reinterpret_cast<unsigned*>(p), __builtin_bit_cast(unsigned, x), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A row of a plane step: its sweep data, and the value of its off-plane
+// neighbour (loaded with the data; re-read at use while it holds the marker).
+template <typename T>
+struct PlaneJob {
+  SweepJob<T> j;
+  T xo[3];
+  int ko;     // the off-plane neighbour's position (-1: none)
+  int have;   // the lane has a row in this step
+  int pos;
+};
+
+// FWD: plane k = blockIdx.x walks d = 0 .. D-1 and reads plane k - 1's
+// forward results; backward: plane k = nz - 1 - blockIdx.x walks d = D-1 ..
+// 0 and reads plane k + 1's backward results (every workgroup waits on a
+// lower index).  The rows of steps s + 1 and s + 2 are in flight while step
+// s is solved (a ring of three jobs, the loop unrolled over its period);
+// every lane loads (lanes without a row at a valid position) so that the
+// loads stay in straight-line code whose waits count only what they need.
+template <typename T, bool FWD>
+__global__ __launch_bounds__(kPlaneThreads) void k_sweep_planes(Topo t, IluView<T> v, PlaneTab p,
+                                                                const double* r, double* x,
+                                                                const int32_t* skip) {
+  if (skip && *skip != 0) return;
+  extern __shared__ unsigned char smem_planes[];
+  T* ring = reinterpret_cast<T*>(smem_planes);                      // [2][W][3]
+  int2v* rl = reinterpret_cast<int2v*>(ring + 2 * 3 * (size_t)p.W);   // [D] the plane's rows per step
+  // fail[s % 3]: a lane of step s gave up.  Read by every wave after the
+  // step's barrier; the slot of step s + 1 is cleared before it (no wave
+  // still reads it: they all passed the barrier of step s - 1 after their
+  // last read of step s - 2).
+  __shared__ int fail[3];
+  __shared__ int go;
+  const int k = FWD ? (int)blockIdx.x : p.nz - 1 - (int)blockIdx.x;
+  const unsigned ns = (unsigned)v.ns;
+  const int tid = (int)threadIdx.x;
+  // the vector the neighbouring planes exchange: forward results in z,
+  // backward results in xb
+  T* xch = FWD ? v.z : static_cast<T*>(p.xb);
+  const int2v none = int2v{0, 0};
+  for (int s = tid; s < p.D; s += kPlaneThreads) {
+    const int2v e = p.rng[(size_t)k * p.D + (FWD ? s : p.D - 1 - s)];
+    rl[s] = e.x < e.y ? e : none;
+  }
+  if (tid == 0) {
+    // a backward sweep after a forward sweep that gave up does not start
+    go = FWD || __hip_atomic_load(p.abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    fail[0] = 0;
+  }
+  __syncthreads();
+  if (go == 0) {
+    // the forward sweep gave up: this plane's solution is NaN, not a stale value
+    for (int s = 0; s < p.D; ++s)
+      for (int q = rl[s].x + tid; q < rl[s].y; q += kPlaneThreads) {
+        const int cell = t.perm[q];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) x[3 * cell + c] = __builtin_nan("");
+      }
+    return;
+  }
+  auto range = [&](int s) { return s < p.D ? rl[s] : none; };
+  // rows rg of a step whose in-plane neighbours are the rows prg
+  auto fetch = [&](PlaneJob<T>& J, const int2v& rg, const int2v& prg) {
+    const int cnt = rg.y - rg.x;
+    J.have = tid < cnt;
+    J.pos = J.have ? rg.x + tid : 0;
+    const unsigned up = (unsigned)J.pos;
+    SweepJob<T>& j = J.j;
+    j.cell = t.perm[up];
+#pragma unroll
+    for (unsigned q = 0; q < 3; ++q) j.kp[q] = FWD ? t.lo_pos[3u * up + q] : t.up_pos[3u * up + q];
+#pragma unroll
+    for (unsigned e = 0; e < 27; ++e) j.a[e] = FWD ? v.lov[e * ns + up] : v.upv[e * ns + up];
+#pragma unroll
+    for (unsigned e = 0; e < 9; ++e) j.D[e] = v.dinv[e * ns + up];
+    if (!FWD) {
+#pragma unroll
+      for (unsigned c = 0; c < 3; ++c) j.rhs[c] = v.z[c * ns + up];
+    }
+    // the off-plane neighbour: the one listed that is not on the previous
+    // diagonal of this plane
+    int ko = -1;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int kp = j.kp[q];
+      ko = kp >= 0 && (kp < prg.x || kp >= prg.y) ? kp : ko;
+    }
+    J.ko = J.have ? ko : -1;
+    const unsigned uo = (unsigned)max(J.ko, 0);
+#pragma unroll
+    for (unsigned c = 0; c < 3; ++c) J.xo[c] = coherent_load(xch + c * ns + uo);
+    if (FWD) {
+#pragma unroll
+      for (unsigned c = 0; c < 3; ++c) j.rhs[c] = (T)r[3u * (unsigned)j.cell + c];
+    }
+  };
+  PlaneJob<T> jobs[3];
+  int2v rgs[3];
+  rgs[0] = range(0);
+  rgs[1] = range(1);
+  rgs[2] = none;
+  int2v prv = none;
+  fetch(jobs[0], rgs[0], none);
+  fetch(jobs[1], rgs[1], rgs[0]);
+  auto step = [&](PlaneJob<T>& J, const int2v& rg, int s) {
+    // the off-plane value: re-read until written (bounded)
+    auto unset3 = [&]() {
+      return J.ko >= 0 && (is_unset(J.xo[0]) || is_unset(J.xo[1]) || is_unset(J.xo[2]));
+    };
+    bool gave_up = J.ko >= 0 && p.spin == 0;
+    if (unset3() && !gave_up) {
+      for (unsigned it = 0;; ++it) {
+        if (it == p.spin) {
+          gave_up = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        const unsigned uo = (unsigned)J.ko;
+#pragma unroll
+        for (unsigned c = 0; c < 3; ++c) J.xo[c] = coherent_load(xch + c * ns + uo);
+        if (!unset3()) break;
+        if ((it & 63) == 63 &&
+            __hip_atomic_load(p.abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          gave_up = true;
+          break;
+        }
+      }
+    }
+    if (gave_up) {
+      __hip_atomic_store(p.abort_w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      fail[s % 3] = 1;
+    }
+    T out[3];
+    solve_row<T, FWD>(J.j, [&](int kp, T* xv) {
+      if (kp >= prv.x && kp < prv.y) {
+        const T* w = ring + (unsigned)(((s + 1) & 1) * p.W + (kp - prv.x)) * 3u;
+        xv[0] = w[0];
+        xv[1] = w[1];
+        xv[2] = w[2];
+      } else {   // the off-plane neighbour (the only other lower one)
+        xv[0] = J.xo[0];
+        xv[1] = J.xo[1];
+        xv[2] = J.xo[2];
+      }
+    }, out);
+    if (J.have) {
+      const unsigned pos = (unsigned)J.pos;
+      T* w = ring + (unsigned)((s & 1) * p.W + (J.pos - rg.x)) * 3u;
+#pragma unroll
+      for (unsigned c = 0; c < 3; ++c) {
+        w[c] = out[c];
+        coherent_store(xch + c * ns + pos, out[c]);
+        if (!FWD) x[3u * (unsigned)J.j.cell + c] = (double)out[c];
+      }
+    }
+    if (tid == 0) fail[(s + 1) % 3] = 0;
+    __syncthreads();
+    prv = rg;
+    return fail[s % 3] == 0;
+  };
+  bool ok = true;
+  for (int s0 = 0; ok && s0 < p.D; s0 += 3) {
+#pragma unroll
+    for (int qq = 0; qq < 3; ++qq) {
+      const int s = s0 + qq;
+      if (s >= p.D) break;
+      rgs[(qq + 2) % 3] = range(s + 2);
+      fetch(jobs[(qq + 2) % 3], rgs[(qq + 2) % 3], rgs[(qq + 1) % 3]);
+      if (!step(jobs[qq], rgs[qq], s)) {
+        ok = false;
+        break;
+      }
+    }
+  }
+  if (!FWD && !ok) {
+    // a sweep that gave up: its plane's solution is NaN, not a stale value
+    for (int s = 0; s < p.D; ++s)
+      for (int q = rl[s].x + tid; q < rl[s].y; q += kPlaneThreads) {
+        const int cell = t.perm[q];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) x[3 * cell + c] = __builtin_nan("");
+      }
+  }
+}
+
 template <typename T>
 int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* status, int mode,
                 hipStream_t s) {
@@ -754,6 +1062,13 @@ int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* stat
     const int p0 = pb->level_ptr_h[l], p1 = pb->level_ptr_h[l + 1];
     hipLaunchKernelGGL(k_factor_level<T>, dim3(blocks_for(p1 - p0, kBlock)), dim3(kBlock), 0, s,
                        t, J, v, p0, p1, status);
+  }
+  if (plane_capable(pb)) {   // the plane table of the sweeps
+    const PlaneTab pt = plane_tab<T>(pb, ilu);
+    hipLaunchKernelGGL(k_plane_init, dim3(blocks_for((long)pt.D * pt.nz, 256)), dim3(256), 0, s,
+                       pt);
+    hipLaunchKernelGGL(k_plane_fill, dim3(blocks_for(pb->n_cells, 256)), dim3(256), 0, s, t,
+                       pb->cell_box, pt);
   }
   OPM_TRY_HIP(hipGetLastError());
   return OPM_OK;
@@ -848,6 +1163,18 @@ int apply_impl(const opm_problem* pb, void* ilu, const double* r, double* x, int
     OPM_TRY_HIP(hipGetLastError());
     return OPM_OK;
   }
+  if (g_plane_sweep > 0 && plane_capable(pb)) {
+    const PlaneTab pt = plane_tab<T>(pb, ilu);
+    const size_t lds = sizeof(T) * 2 * 3 * (size_t)pt.W + sizeof(int2v) * (size_t)pt.D;
+    hipLaunchKernelGGL(k_plane_reset<T>, dim3(blocks_for(3 * (long)v.ns, 256 * 8)), dim3(256), 0,
+                       s, v, pt, skip);
+    hipLaunchKernelGGL((k_sweep_planes<T, true>), dim3(pt.nz), dim3(kPlaneThreads), lds, s, t, v,
+                       pt, r, x, skip);
+    hipLaunchKernelGGL((k_sweep_planes<T, false>), dim3(pt.nz), dim3(kPlaneThreads), lds, s, t,
+                       v, pt, r, x, skip);
+    OPM_TRY_HIP(hipGetLastError());
+    return OPM_OK;
+  }
   for (int l = 0; l < pb->n_levels; ++l) {
     const int p0 = pb->level_ptr_h[l], p1 = pb->level_ptr_h[l + 1];
     hipLaunchKernelGGL(k_fwd_level<T>, dim3(blocks_for(p1 - p0, kBlock)), dim3(kBlock), 0, s, t,
@@ -865,9 +1192,17 @@ int apply_impl(const opm_problem* pb, void* ilu, const double* r, double* x, int
 }  // namespace
 
 size_t ilu_bytes(const opm_problem* pb, int precision) {
-  return precision == OPM_PREC_MIXED ? view_bytes<float>(pb->n_cells)
-                                     : view_bytes<double>(pb->n_cells);
+  const size_t v = precision == OPM_PREC_MIXED ? view_bytes<float>(pb->n_cells)
+                                               : view_bytes<double>(pb->n_cells);
+  const size_t pl = plane_bytes(pb);
+  return pl ? al256(v) + pl : v;
 }
+
+// Sweeps of mode 1 on a lattice: 1 plane-pipelined (default), 0 one launch
+// per level (OPM_OPT_PLANE_SWEEP).
+int g_plane_sweep = 1;
+// Polls of a plane sweep's wait before it gives up (OPM_OPT_PLANE_SPIN).
+int g_plane_spin = 1 << 18;
 
 // Sweep shape: one workgroup when the widest level fits the LDS window and
 // the system is small enough for one compute unit, else one launch per

@@ -270,6 +270,8 @@ int g_krylov_chunk = 0;
 int g_krylov_graph = 1;
 extern int g_sweep_mode;
 extern int g_sweep_kernel;
+extern int g_plane_sweep;
+extern int g_plane_spin;
 extern int g_block_depth;
 
 int chunk_size(const opm_problem* pb) {
@@ -313,7 +315,7 @@ struct ChunkKey {
   const double* x;
   const void* work;
   hipStream_t st;
-  int precision, chunk, device, sweep_mode, sweep_kernel, block_depth;
+  int precision, chunk, device, sweep_mode, sweep_kernel, block_depth, plane_sweep, plane_spin;
   WellSchur ws;              // standard wells (all zero without)
   const double* cpr_base;    // CPR workspace (null without)
 };
@@ -454,6 +456,8 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
     key.cpr_base = cpr ? cpr->w : nullptr;
     key.sweep_kernel = g_sweep_kernel;
     key.block_depth = g_block_depth;
+    key.plane_sweep = g_plane_sweep;
+    key.plane_spin = g_plane_spin;
   }
   for (int pass = 0;; ++pass) {
     hipGraphExec_t exec = nullptr;

@@ -70,7 +70,7 @@ class Problem(ctypes.Structure):
                 ("conn_well", _vp), ("well_kind", _vp), ("well_phase", _vp), ("well_target", _vp),
                 ("well_vol", _vp), ("well_state", _vp), ("amg", _vp), ("well_limit", _vp),
                 ("well_ctrl", _vp), ("nx", _i32), ("ny", _i32), ("nz", _i32), ("pad_l", _i32),
-                ("box_cell", _vp)]
+                ("box_cell", _vp), ("cell_box", _vp)]
 
 
 AMG_MAX_LEVELS, AMG_COARSE = 12, 64
@@ -122,7 +122,7 @@ EXPORTS = [
 ]
 
 OPT_SWEEP_MODE, OPT_KRYLOV_CHUNK, OPT_SWEEP_KERNEL, OPT_BLOCK_DEPTH, OPT_KRYLOV_GRAPH = 1, 2, 3, 4, 5
-OPT_ASSEMBLY = 6
+OPT_ASSEMBLY, OPT_PLANE_SWEEP, OPT_PLANE_SPIN = 6, 7, 8
 
 _lib = None
 
@@ -414,6 +414,7 @@ class GpuModel:
         self.box_cell_t = torch.from_numpy(box_cell.astype(np.int32)).to(self.dev)
         self.pb.nx, self.pb.ny, self.pb.nz = nx, ny, nz
         self.pb.box_cell = self.box_cell_t.data_ptr()
+        self.pb.cell_box = d["cell_box"].data_ptr()
         if blk is not None:
             self.pb.n_sub, self.pb.max_sub, self.pb.max_width = blk.n_sub, blk.max_sub, blk.max_width
             self.pb.sub_level_ptr = d["sub_level_ptr"].data_ptr()

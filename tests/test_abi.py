@@ -42,6 +42,8 @@ def test_strerror_and_options():
     assert L.opm_set_option(opm.OPT_SWEEP_MODE, 7) == opm.EINVAL
     assert L.opm_set_option(999, 0) == opm.EINVAL
     assert L.opm_set_option(opm.OPT_SWEEP_MODE, -1) == opm.OK
+    assert L.opm_set_option(opm.OPT_PLANE_SWEEP, 2) == opm.EINVAL
+    assert L.opm_set_option(opm.OPT_PLANE_SPIN, -1) == opm.EINVAL
 
 
 def _topology(case):

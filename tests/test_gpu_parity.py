@@ -408,3 +408,67 @@ def test_full_size_c5_sampled(opm):
     assert rep.status == 0
     res = -Ro - m.spmv(Jo, x.cpu().numpy())
     assert np.linalg.norm(res) <= 1.01e-6 * np.linalg.norm(Ro)
+
+
+def _plane_systems():
+    masked = cases.box_case(19, 13, 6, seed=6, mask=cases.masked_mask(
+        np.random.default_rng(9), (6, 13, 19), 900), wells=[])
+    return [cases.config2(), masked, cases.box_case(30, 30, 12, seed=9),
+            cases.box_case(7, 40, 5, seed=4), cases.box_case(1, 1, 9, seed=2)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_plane_sweep_bitwise_equal(opm, precision):
+    """The plane-pipelined sweeps (one workgroup per z-plane, the
+    values exchanged between planes through marked vectors) give the
+    per-level launches' bits: the same row arithmetic in the same order, on
+    full, masked, tall and one-column grids."""
+    for case in _plane_systems():
+        print(f"plane sweep: {case.name} precision {precision}", flush=True)
+        g = opm.GpuModel(case)
+        y = g.state(cases.random_state(case, 5))
+        acc0 = g.accumulation(g.state(cases.random_state(case, 6)))
+        R, J, _ = g.assemble(y, acc0, DAY)
+        opm.set_option(opm.OPT_SWEEP_MODE, 1)
+        try:
+            ilu, status = g.ilu0_factor(J, precision)
+            assert int(status.item()) == 0
+            xs = []
+            for planes in (0, 1):
+                opm.set_option(opm.OPT_PLANE_SWEEP, planes)
+                xs.append(g.ilu0_apply(ilu, R, precision))
+            # repeated applications reset the exchange vectors
+            for _ in range(3):
+                xs.append(g.ilu0_apply(ilu, R, precision))
+        finally:
+            opm.set_option(opm.OPT_SWEEP_MODE, -1)
+            opm.set_option(opm.OPT_PLANE_SWEEP, 1)
+        assert torch.isfinite(xs[0]).all()
+        for q, xq in enumerate(xs[1:]):
+            assert torch.equal(xs[0], xq), (case.name, q)
+
+
+def test_plane_sweep_gives_up_with_nan(opm):
+    """A plane sweep whose wait gives up (forced from the host: a spin limit
+    of zero polls) returns NaN for every row instead of hanging, and
+    BiCGStab reports it; the next solve with the normal limit is exact
+    again."""
+    case = cases.box_case(12, 10, 6, seed=3)
+    g = opm.GpuModel(case)
+    y = g.state(cases.random_state(case, 5))
+    acc0 = g.accumulation(g.state(cases.random_state(case, 6)))
+    R, J, _ = g.assemble(y, acc0, DAY)
+    opm.set_option(opm.OPT_SWEEP_MODE, 1)
+    try:
+        ilu, status = g.ilu0_factor(J)
+        ref = g.ilu0_apply(ilu, R)
+        opm.set_option(opm.OPT_PLANE_SPIN, 0)
+        bad = g.ilu0_apply(ilu, R)
+        assert torch.isnan(bad).all()
+        x, rep = g.bicgstab(J, ilu, -R, rtol=1e-6)
+        assert rep.status != 0
+        opm.set_option(opm.OPT_PLANE_SPIN, 1 << 18)
+        assert torch.equal(g.ilu0_apply(ilu, R), ref)
+    finally:
+        opm.set_option(opm.OPT_PLANE_SPIN, 1 << 18)
+        opm.set_option(opm.OPT_SWEEP_MODE, -1)
