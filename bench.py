@@ -270,17 +270,50 @@ def bench_mixed(args):
     print(json.dumps(line), flush=True)
 
 
+def c4_oracle_errors(ens, member_cases, dt):
+    """Max pressure (relative) and saturation (absolute) differences of the
+    three largest members after one report step from the oracle's states at
+    4000 sampled cells each (tests/golden/c4_largest.npz, written by
+    tests/golden/make_golden.py from the oracle alone).  Runs one untimed
+    launch from the initial states."""
+    import numpy as np
+    import torch
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                        "c4_largest.npz")
+    if not os.path.exists(path):
+        return None
+    d = np.load(path)
+    for t, m in zip(ens.y, ens.members):
+        t.copy_(m.initial_state())
+    ens.launch(dt, 1)
+    torch.cuda.synchronize()
+    states = ens.states()
+    ep = es = 0.0
+    for m in (int(v) for v in d["members"]):
+        idx = d[f"m{m}_idx"]
+        yo = np.stack([d[f"m{m}_p"][0], d[f"m{m}_sw"][0], d[f"m{m}_sg"][0]], axis=1)
+        y = states[m][idx]
+        ep = max(ep, float(np.abs(y[:, 0] - yo[:, 0]).max() / np.abs(yo[:, 0]).max()))
+        es = max(es, float(np.abs(y[:, 1:] - yo[:, 1:]).max()))
+    return {"p_rel": ep, "s_abs": es, "members": [int(v) for v in d["members"]],
+            "report_steps": 1, "cells_per_member": int(len(d[f"m{int(d['members'][0])}_idx"]))}
+
+
 def bench_ensemble(args):
     """64 members (uneven grids 20..60 x 20..60 x 20..30) advanced 20 report
     steps of 15 days in one persistent launch (replayed from a captured
-    graph, launch shape picked by the autotuner beforehand), against the
-    single-system FP64 GPU path run member by member on a sample of members."""
+    graph, launch shape picked by the autotuner beforehand: with the members
+    built on a block-ILU0 topology of whole-column subdomains, as many
+    workgroups as the device has compute units, shared out in proportion to
+    the members' rows), against the single-system FP64 GPU path run member by
+    member on a sample of members, and against one workgroup per member."""
     import torch
     from paper_1910_06059_amd import cases, opm
     steps = args.steps or 20
     nm = args.members
     member_cases = [cases.config4_member(m) for m in range(nm)]
     dt = member_cases[0].report_dt[0]
+    split = None if args.member_split == "none" else tuple(int(v) for v in args.member_split.split("x"))
     # warm-up: load the kernels on a two-member ensemble
     warm = opm.Ensemble([cases.box_case(4, 4, 3, seed=1), cases.box_case(3, 5, 2, seed=2)],
                         precision=opm.PREC_MIXED)
@@ -288,7 +321,7 @@ def bench_ensemble(args):
     torch.cuda.synchronize()
     out = {}
     for prec in (opm.PREC_MIXED, opm.PREC_FP64):
-        ens = opm.Ensemble(member_cases, precision=prec)
+        ens = opm.Ensemble(member_cases, precision=prec, member_split=split)
         # launch shape from the autotuner (untimed: one trial report step per
         # shape, states restored afterwards), then the timed work as one
         # captured graph holding the single persistent launch
@@ -313,7 +346,26 @@ def bench_ensemble(args):
                      "lin_its": sum(r["lin_its"] for r in reps),
                      "cell_newton_its_per_s": round(sum(r["cell_newton_its"] for r in reps) / wall, 1),
                      "launch_shape": tuning}
+        if nm == 64:
+            out[prec]["vs_fp64_oracle"] = c4_oracle_errors(ens, member_cases, dt)
         del ens, graph
+    # one workgroup per member (each member's ILU(0) of the whole system), FP32
+    # factors, the same report steps: what the split launch is measured against
+    ref_steps = min(steps, args.one_wg_steps)
+    one = None
+    if split is not None and ref_steps > 0:
+        ens = opm.Ensemble(member_cases, precision=opm.PREC_MIXED)
+        tuning = ens.autotune(dt, cache=args.tuning_cache)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ens.launch(dt, ref_steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        reps = ens.read_reports()
+        one = {"members_steps_per_s": round(nm * ref_steps / wall, 3), "steps": ref_steps,
+               "members_ok": sum(1 for r in reps if r["status"] == 0 and r["steps_done"] == ref_steps),
+               "launch_shape": tuning}
+        del ens
     # single-system FP64 path, member by member, on a sample spread over sizes
     order = sorted(range(nm), key=lambda m: member_cases[m].n_active)
     k = max(1, min(args.baseline_members, nm))
@@ -332,8 +384,15 @@ def bench_ensemble(args):
             "unit": "members-steps/s", "n_gpus": 1, "steps": steps, "warmup": 1,
             "higher_is_better": True, "dtype": "f64+f32-ilu", "data": "synthetic",
             "config": {"workload": f"{nm} members, grids 20..60 x 20..60 x 20..30, 15-day steps",
-                       "total_cells": sum(c.n_active for c in member_cases)},
+                       "total_cells": sum(c.n_active for c in member_cases),
+                       "member_preconditioner": ("ILU(0) of the whole member" if split is None else
+                                                 f"block ILU0 on {split[0]}x{split[1]} whole-column "
+                                                 "subdomains per member")},
             "ensemble_mixed": out[opm.PREC_MIXED], "ensemble_fp64": out[opm.PREC_FP64],
+            "one_workgroup_per_member_mixed": one,
+            "speedup_vs_one_workgroup_per_member": (round(out[opm.PREC_MIXED]["members_steps_per_s"] /
+                                                          one["members_steps_per_s"], 2)
+                                                    if one else None),
             "single_system_fp64": {"members_steps_per_s": round(base_rate, 4),
                                    "sample": f"members {sample}, first {base_steps} steps each"},
             "speedup_vs_single_fp64": round(out[opm.PREC_MIXED]["members_steps_per_s"] / base_rate, 2),
@@ -747,6 +806,12 @@ def main():
     ap.add_argument("--lr", type=float, default=3e-3, help="Adam step size (c5-guess)")
     ap.add_argument("--save-net", default=None, help="save the trained parameters (.npy)")
     ap.add_argument("--members", type=int, default=64, help="ensemble size (c4-ensemble)")
+    ap.add_argument("--member-split", default="6x6",
+                    help="c4-ensemble: AxB whole-column subdomains of a block ILU0 in every member "
+                         "(none: each member's ILU(0) of the whole system, one workgroup each)")
+    ap.add_argument("--one-wg-steps", type=int, default=5,
+                    help="c4-ensemble: report steps of the one-workgroup-per-member reference run "
+                         "(0: none)")
     ap.add_argument("--tuning-cache", default=None,
                     help="JSON file of autotuned ensemble launch shapes (c4-ensemble)")
     ap.add_argument("--baseline-members", type=int, default=4,

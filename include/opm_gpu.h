@@ -781,16 +781,26 @@ int opm_advance_guess(const opm_problem* pb, double* y, const double* y_nm1, dou
                       int32_t* guess_used, void* stream);
 
 /* Launch shape of the ensemble kernel: the schedule knobs that the
- * autotuner chooses.  threads: workgroup size per member (128 or 256);
+ * autotuner chooses.  threads: workgroup size (128 or 256);
  * fac_window: keep the previous level's ILU(0) pivots in LDS during the
  * factorisation (allowed when every member has at most 640 rows per level);
  * ring: members whose LDS ring (the values of the last sweep_span +
  * max_level + 1 rows, rounded up to a power of two) fits sweep through the
  * ring, the others through the two-level LDS window; sweep_bytes: out, the
  * sweep storage of a launch (set by opm_ensemble_default_config and
- * opm_ensemble_configure). */
+ * opm_ensemble_configure); wgs: 0 one workgroup per member, else (in) the
+ * workgroups of the launch (at least n_members, at most 2048, ring 0):
+ * members built with a block-ILU0 topology (opm_topology_build_blocks) get
+ * workgroups in proportion to their rows, at most one per subdomain, each
+ * owning a contiguous range of the member's subdomains (its rows in
+ * assembly, vector operations and SpMV, its subdomains in the factorisation
+ * and sweeps), the member's workgroups meeting at device-memory barriers
+ * for halo reads and reductions; out, the workgroups configured.  Every
+ * workgroup of such a launch must be resident at once (checked against the
+ * device's occupancy: OPM_EINVAL otherwise); a barrier that waits too long
+ * fails the member with OPM_EHIP instead of hanging. */
 typedef struct opm_ensemble_config {
-  int32_t threads, fac_window, ring, sweep_bytes;
+  int32_t threads, fac_window, ring, sweep_bytes, wgs;
 } opm_ensemble_config;
 
 /* The shape opm_ensemble_launch uses (256 threads, factor window when
@@ -813,11 +823,12 @@ int opm_ensemble_launch_config(const void* work, int32_t n_members, int precisio
 
 /* Autotuner: times one report step of length dt_report of the whole
  * ensemble for every valid shape (threads 256/128 x ring off/on x factor
- * window on/off), restoring the members' states before each trial and at
+ * window on/off, and with members that have subdomains also as many
+ * workgroups as the device has compute units), restoring the members' states before each trial and at
  * the end, then configures the workspace with the fastest shape among the
  * trials in which every member completed the step (status OPM_OK) and
  * returns it in best; OPM_ENOTCONV (the workspace keeps the last trial's shape) if no trial
- * completed.  seconds (host, optional, >= 8 entries) receives the trial
+ * completed.  seconds (host, optional, >= 16 entries) receives the trial
  * times in trial order, n_tried (host, optional) their number.  Host,
  * synchronous; results of later launches do not depend on the shape beyond
  * the order of summation in reductions. */
@@ -857,7 +868,11 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
  *     neighbouring plane that is not yet written before it gives up
  *     (default 262144; 0 gives up at once, to exercise the failure path): a
  *     sweep that gives up returns NaN, so the Krylov solver reports
- *     non-finite values instead of hanging. */
+ *     non-finite values instead of hanging.
+ *   OPM_OPT_ENSEMBLE_SPIN: polls a member barrier of an ensemble launch
+ *     with several workgroups per member makes before it gives up (default
+ *     4194304; 0 gives up at once, to exercise the failure path): the
+ *     member then reports OPM_EHIP. */
 #define OPM_OPT_SWEEP_MODE 1
 #define OPM_OPT_KRYLOV_CHUNK 2
 #define OPM_OPT_SWEEP_KERNEL 3
@@ -866,6 +881,7 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
 #define OPM_OPT_ASSEMBLY 6
 #define OPM_OPT_PLANE_SWEEP 7
 #define OPM_OPT_PLANE_SPIN 8
+#define OPM_OPT_ENSEMBLE_SPIN 9
 int opm_set_option(int option, int value);
 
 const char* opm_strerror(int code);

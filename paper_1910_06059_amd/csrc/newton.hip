@@ -28,6 +28,7 @@ long assemble_max_workgroups(const opm_problem* pb);
 extern int g_assembly_kernel;
 extern int g_plane_sweep;
 extern int g_plane_spin;
+extern int g_ens_spin;
 int launch_accumulation(const opm_problem* pb, const double* y, double* acc0, hipStream_t s);
 size_t ilu_bytes(const opm_problem* pb, int precision);
 int ilu_factor(const opm_problem* pb, const double* J, void* ilu, int precision, int32_t* status,
@@ -472,6 +473,10 @@ int opm_set_option(int option, int value) {
     case OPM_OPT_PLANE_SPIN:
       if (value < 0) return OPM_EINVAL;
       g_plane_spin = value;
+      return OPM_OK;
+    case OPM_OPT_ENSEMBLE_SPIN:
+      if (value < 0) return OPM_EINVAL;
+      g_ens_spin = value;
       return OPM_OK;
     case OPM_OPT_KRYLOV_CHUNK:
       if (value < 0) return OPM_EINVAL;

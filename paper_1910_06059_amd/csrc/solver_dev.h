@@ -94,12 +94,24 @@ struct Topo {
   const int32_t* up_pos;
   const int32_t* level_ptr;
   int n, nlev, max_level;
+  // The rows of level l that a walk takes: [level_ptr[l lstride + s0],
+  // level_ptr[l lstride + s1]).  The whole level: lstride 1, s0 0, s1 1; the
+  // subdomains [s0, s1) of a block ILU0: level_ptr = sub_level_ptr,
+  // lstride = n_sub + 1.
+  int lstride, s0, s1;
 };
 
 __host__ __device__ inline Topo topo_of(const opm_problem* pb) {
   return Topo{pb->perm,   pb->diag_pos,  pb->lo_blk,   pb->lo_tblk, pb->lo_pos,
               pb->up_blk, pb->up_pos,    pb->level_ptr, pb->n_cells, pb->n_levels,
-              pb->max_level};
+              pb->max_level, 1, 0, 1};
+}
+
+__host__ __device__ inline int lvl_begin(const Topo& t, int l) {
+  return t.level_ptr[l * t.lstride + t.s0];
+}
+__host__ __device__ inline int lvl_end(const Topo& t, int l) {
+  return t.level_ptr[l * t.lstride + t.s1];
 }
 
 // Inverse of a 3x3 block by cofactors; false on a zero or non-finite
@@ -213,11 +225,11 @@ __device__ __forceinline__ void factor_levels_wg(const Topo& t, const double* J,
                                                  int32_t* status, double* win) {
   const int L = t.max_level;
   FacJob next;
-  int npos = t.level_ptr[0] + threadIdx.x;
-  if (PREFETCH && npos < t.level_ptr[1]) load_fac(t, J, npos, next);
+  int npos = lvl_begin(t, 0) + threadIdx.x;
+  if (PREFETCH && npos < lvl_end(t, 0)) load_fac(t, J, npos, next);
   int prev0 = 0, prev1 = 0, buf = 0;
   for (int l = 0; l < t.nlev; ++l) {
-    const int p0 = t.level_ptr[l], p1 = t.level_ptr[l + 1];
+    const int p0 = lvl_begin(t, l), p1 = lvl_end(t, l);
     for (int pos = p0 + threadIdx.x; pos < p1; pos += NT) {
       FacJob cur;
       if (PREFETCH && pos == p0 + (int)threadIdx.x)
@@ -244,8 +256,8 @@ __device__ __forceinline__ void factor_levels_wg(const Topo& t, const double* J,
       }
     }
     if (PREFETCH && l + 1 < t.nlev) {
-      npos = p1 + threadIdx.x;
-      if (npos < t.level_ptr[l + 2]) load_fac(t, J, npos, next);
+      npos = lvl_begin(t, l + 1) + threadIdx.x;
+      if (npos < lvl_end(t, l + 1)) load_fac(t, J, npos, next);
     }
     __syncthreads();
     prev0 = p0;
@@ -365,17 +377,17 @@ __device__ __forceinline__ void wg_sweep(const Topo& t, IluView<T> v, const doub
   SweepJob<T> next, cur;
   {
     const int l0 = FWD ? 0 : t.nlev - 1;
-    if (t.level_ptr[l0] + tid < t.level_ptr[l0 + 1]) load(t.level_ptr[l0] + tid, next);
+    if (lvl_begin(t, l0) + tid < lvl_end(t, l0)) load(lvl_begin(t, l0) + tid, next);
   }
   int prev0 = 0, prev1 = 0, buf = 0;
   for (int k = 0; k < t.nlev; ++k) {
     const int l = FWD ? k : t.nlev - 1 - k;
-    const int p0 = t.level_ptr[l], p1 = t.level_ptr[l + 1];
+    const int p0 = lvl_begin(t, l), p1 = lvl_end(t, l);
     cur = next;
     if (k + 1 < t.nlev) {
       const int ln = FWD ? l + 1 : l - 1;
-      const int q0 = t.level_ptr[ln];
-      if (q0 + tid < t.level_ptr[ln + 1]) load(q0 + tid, next);
+      const int q0 = lvl_begin(t, ln);
+      if (q0 + tid < lvl_end(t, ln)) load(q0 + tid, next);
     }
     if (p0 + tid < p1) wg_row<T, FWD>(cur, v, x, win, L, buf, prev0, prev1, p0, p0 + tid);
     for (int pos = p0 + tid + NT; pos < p1; pos += NT) {   // levels wider than the workgroup

@@ -122,7 +122,7 @@ EXPORTS = [
 ]
 
 OPT_SWEEP_MODE, OPT_KRYLOV_CHUNK, OPT_SWEEP_KERNEL, OPT_BLOCK_DEPTH, OPT_KRYLOV_GRAPH = 1, 2, 3, 4, 5
-OPT_ASSEMBLY, OPT_PLANE_SWEEP, OPT_PLANE_SPIN = 6, 7, 8
+OPT_ASSEMBLY, OPT_PLANE_SWEEP, OPT_PLANE_SPIN, OPT_ENSEMBLE_SPIN = 6, 7, 8, 9
 
 _lib = None
 
@@ -782,7 +782,8 @@ _ENS_REPORT_DOUBLES = ctypes.sizeof(EnsembleReport) // 8
 
 
 class EnsembleConfig(ctypes.Structure):
-    _fields_ = [("threads", _i32), ("fac_window", _i32), ("ring", _i32), ("sweep_bytes", _i32)]
+    _fields_ = [("threads", _i32), ("fac_window", _i32), ("ring", _i32), ("sweep_bytes", _i32),
+                ("wgs", _i32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -813,13 +814,29 @@ def _ensemble_lib():
     return L
 
 
+def member_blocks(case: _cases.Case, split: Optional[Sequence[int]]):
+    """Subdomain box (bx, by, bz) of an a x b split of the case's columns
+    (None: the member's ILU(0) of the whole system)."""
+    if split is None:
+        return None
+    a, b = (int(v) for v in split)
+    return (-(-case.nx // a), -(-case.ny // b), case.nz)
+
+
 class Ensemble:
     """Independent members advanced together by one persistent kernel launch
-    per call (one workgroup per member)."""
+    per call (one workgroup per member).  member_split = (a, b) gives every
+    member the block ILU0 over a x b whole-column subdomains (boxes of
+    ceil(nx / a) x ceil(ny / b) x nz cells, sec. 2.5): the workgroup walks the
+    subdomains' local levels together, nx/a + ny/b + nz - 2 of them instead of
+    the nx + ny + nz - 2 levels of the member's ILU(0)."""
 
-    def __init__(self, member_cases, precision=PREC_MIXED, device="cuda"):
+    def __init__(self, member_cases, precision=PREC_MIXED, device="cuda",
+                 member_split: Optional[Sequence[int]] = None):
         L = _ensemble_lib()
-        self.members = [GpuModel(c, device=device) for c in member_cases]
+        self.member_split = None if member_split is None else tuple(int(v) for v in member_split)
+        self.members = [GpuModel(c, device=device, ilu_blocks=member_blocks(c, self.member_split))
+                        for c in member_cases]
         self.precision = precision
         self.dev = self.members[0].dev
         nm = len(self.members)
@@ -837,20 +854,24 @@ class Ensemble:
                "opm_ensemble_prepare")
         self.reports = torch.zeros((nm, _ENS_REPORT_DOUBLES), dtype=torch.float64, device=self.dev)
         self.n_cells = [m.n for m in self.members]
+        # the default shape (one workgroup per member); None when it does not
+        # fit in LDS (split members then need configure or autotune)
         self.config = EnsembleConfig()
-        _check(L.opm_ensemble_default_config(self.problems, nm, precision,
-                                             ctypes.byref(self.config)),
-               "opm_ensemble_default_config")
+        if L.opm_ensemble_default_config(self.problems, nm, precision,
+                                         ctypes.byref(self.config)) != OK:
+            self.config = None
         self.tuning = None
 
     def signature(self) -> str:
         """Key of the tuning cache: precision and the members' grids."""
         import hashlib
-        dims = ";".join(f"{m.case.nx}x{m.case.ny}x{m.case.nz}:{m.n}" for m in self.members)
+        dims = ";".join(f"{m.case.nx}x{m.case.ny}x{m.case.nz}:{m.n}:{m.ilu_blocks}"
+                        for m in self.members)
         return f"p{self.precision}-" + hashlib.sha256(dims.encode()).hexdigest()[:16]
 
-    def configure(self, threads: int, fac_window: int, ring: int) -> None:
-        c = EnsembleConfig(threads=threads, fac_window=fac_window, ring=ring, sweep_bytes=0)
+    def configure(self, threads: int, fac_window: int, ring: int, wgs: int = 0) -> None:
+        c = EnsembleConfig(threads=threads, fac_window=fac_window, ring=ring, sweep_bytes=0,
+                           wgs=wgs)
         _check(_ensemble_lib().opm_ensemble_configure(
             self.problems, self.n_members, self.precision, ctypes.c_void_p(self.work.data_ptr()),
             ctypes.byref(c)), "opm_ensemble_configure")
@@ -866,7 +887,8 @@ class Ensemble:
         if cache and os.path.exists(cache):
             entry = json.load(open(cache)).get(key)
             if entry:
-                self.configure(entry["threads"], entry["fac_window"], entry["ring"])
+                self.configure(entry["threads"], entry["fac_window"], entry["ring"],
+                               entry.get("wgs", 0))
                 self.tuning = {"cached": True, **entry}
                 return self.tuning
         o = opts or default_opts(self.members[0].case, precision=self.precision)
@@ -890,6 +912,8 @@ class Ensemble:
     def launch(self, dt_report, n_steps, opts: Optional[NewtonOpts] = None):
         """Enqueue one launch with the current shape (asynchronous)."""
         o = opts or default_opts(self.members[0].case, precision=self.precision)
+        if self.config is None:
+            raise OpmError(EINVAL, "Ensemble.launch: no launch shape fits (configure or autotune)")
         _check(_ensemble_lib().opm_ensemble_launch_config(
             ctypes.c_void_p(self.work.data_ptr()), self.n_members, self.precision, self.max_level,
             ctypes.byref(self.config), dt_report, n_steps, ctypes.byref(o),

@@ -108,14 +108,21 @@ def test_c5_block_ilu0_three_steps(opm):
 
 
 @pytest.mark.slow
+@pytest.mark.parametrize("split", [None, (6, 6)], ids=["whole", "split6x6"])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_c4_largest_members(opm, precision):
+def test_c4_largest_members(opm, precision, split):
+    """The three largest ensemble members, one report step, against the
+    oracle's states: one workgroup per member with each member's ILU(0), and
+    the benchmarked launch (6x6 whole-column block ILU0 per member, the
+    members' workgroups in proportion to their rows over 256)."""
     d = _golden("c4_largest.npz")
     members = [int(m) for m in d["members"]]
     ms = [cases.config4_member(m) for m in members]
-    print(f"C4 members {members} ({[c.n_active for c in ms]} cells), precision {precision}",
-          flush=True)
-    ens = opm.Ensemble(ms, precision=precision)
+    print(f"C4 members {members} ({[c.n_active for c in ms]} cells), precision {precision}, "
+          f"split {split}", flush=True)
+    ens = opm.Ensemble(ms, precision=precision, member_split=split)
+    if split is not None:
+        ens.configure(256, 0, 0, 256)
     ens.launch(ms[0].report_dt[0], 1)
     torch.cuda.synchronize()
     reps = ens.read_reports()
@@ -125,6 +132,38 @@ def test_c4_largest_members(opm, precision):
         idx = d[f"m{m}_idx"]
         yo = np.stack([d[f"m{m}_p"][0], d[f"m{m}_sw"][0], d[f"m{m}_sg"][0]], axis=1)
         _compare(states[k][idx], yo, f"C4 member {m}")
+
+
+@pytest.mark.slow
+def test_c4_split_members_match_single_system_path(opm):
+    """All 64 ensemble members in the benchmarked launch shape (FP64, 6x6
+    whole-column block ILU0 per member, 256 workgroups) against the
+    single-system path's run of every member on the same partition: the same
+    Newton iterations, states within 1e-9 (only the order of summation in
+    the reductions differs)."""
+    split = (6, 6)
+    ms = [cases.config4_member(m) for m in range(64)]
+    ens = opm.Ensemble(ms, precision=0, member_split=split)
+    ens.configure(256, 0, 0, 256)
+    dt = ms[0].report_dt[0]
+    ens.launch(dt, 1)
+    torch.cuda.synchronize()
+    reps = ens.read_reports()
+    states = ens.states()
+    worst = (0.0, 0.0)
+    for m, case in enumerate(ms):
+        assert reps[m]["status"] == 0 and reps[m]["steps_done"] == 1, (m, reps[m])
+        g = opm.GpuModel(case, ilu_blocks=opm.member_blocks(case, split))
+        y = g.initial_state()
+        st, rep = g.advance(y, dt)
+        assert st == 0, m
+        yg = y.cpu().numpy()
+        ep = np.abs(states[m][:, 0] - yg[:, 0]).max() / np.abs(yg[:, 0]).max()
+        es = np.abs(states[m][:, 1:] - yg[:, 1:]).max()
+        worst = (max(worst[0], ep), max(worst[1], es))
+        assert ep <= 1e-9 and es <= 1e-9, (m, ep, es)
+        assert reps[m]["newton_its"] == rep.newton_its, m
+    print(f"64 members: max p_rel {worst[0]:.2e}, max s_abs {worst[1]:.2e}", flush=True)
 
 
 def _switch_case(inj_psi, prod_stb):

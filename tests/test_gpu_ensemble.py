@@ -235,3 +235,118 @@ def test_ensemble_graph_capture_tuned_shape(opm):
         _ = ens.read_reports()
     for m in range(3):
         assert np.array_equal(ens.states()[m], ref[m])
+
+
+SPLIT = (2, 2)
+
+
+def _split_ensemble(opm, ms, precision, wgs):
+    ens = opm.Ensemble(ms, precision=precision, member_split=SPLIT)
+    ens.configure(256, 0, 0, wgs)
+    return ens
+
+
+def test_split_members_match_single_system_path(opm):
+    """Several workgroups per member (each a range of the member's 2x2
+    block-ILU0 column subdomains, meeting at device-memory barriers) give the
+    single-system path's block-ILU0 run of every member: the same Newton
+    iterations, states within 1e-9 (only the order of summation in the
+    reductions differs)."""
+    ms = _members()
+    ens = _split_ensemble(opm, ms, opm.PREC_FP64, 12)
+    # the larger members got more than one workgroup
+    assert ens.config.wgs > len(ms)
+    dt = 10 * DAY
+    ens.launch(dt, 1)
+    torch.cuda.synchronize()
+    reps = ens.read_reports()
+    for m, case in enumerate(ms):
+        assert reps[m]["status"] == 0 and reps[m]["steps_done"] == 1, (m, reps[m])
+        g = opm.GpuModel(case, ilu_blocks=opm.member_blocks(case, SPLIT))
+        y = g.initial_state()
+        st, rep = g.advance(y, dt)
+        assert st == 0
+        yg = y.cpu().numpy()
+        ye = ens.states()[m]
+        assert np.abs(ye[:, 0] - yg[:, 0]).max() <= 1e-9 * np.abs(yg[:, 0]).max(), m
+        assert np.abs(ye[:, 1:] - yg[:, 1:]).max() <= 1e-9, m
+        assert reps[m]["newton_its"] == rep.newton_its, m
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_split_members_match_oracle(opm, precision):
+    """Split members, FP64 and FP32 factors, two report steps, against the
+    oracle's run of every member (1e-6)."""
+    ms = _members()
+    ens = _split_ensemble(opm, ms, precision, 256)
+    dt = 10 * DAY
+    ens.launch(dt, 2)
+    torch.cuda.synchronize()
+    reps = ens.read_reports()
+    for m, case in enumerate(ms):
+        assert reps[m]["status"] == 0 and reps[m]["steps_done"] == 2, (m, reps[m])
+        om = oracle.Model(case)
+        y = case.initial_state()
+        for _ in range(2):
+            st, y, _ = om.advance(y, dt)
+            assert st == 0
+        _check(ens.states()[m], y, f"split member {m}")
+
+
+def test_split_members_graph_replay(opm):
+    """The launch with several workgroups per member (a reset of the barrier
+    words and the persistent kernel) replays from a graph with the eager
+    launches' bits."""
+    ms = _members()[:3]
+    dt = 5 * DAY
+    eager = _split_ensemble(opm, ms, opm.PREC_MIXED, 8)
+    for _ in range(2):
+        eager.launch(dt, 1)
+        torch.cuda.synchronize()
+    ref = eager.states()
+    ens = _split_ensemble(opm, ms, opm.PREC_MIXED, 8)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ens.launch(dt, 1)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        g.replay()
+        torch.cuda.synchronize()
+        _ = ens.read_reports()
+    for m in range(3):
+        assert np.array_equal(ens.states()[m], ref[m]), m
+
+
+def test_split_members_barrier_gives_up(opm):
+    """A member barrier that gives up (forced from the host: a spin limit of
+    zero polls) fails exactly the members with several workgroups, with
+    OPM_EHIP, instead of hanging; the next launch with the normal limit
+    works again."""
+    ms = _members()
+    ens = _split_ensemble(opm, ms, opm.PREC_MIXED, 12)
+    assert ens.config.wgs > len(ms)
+    dt = 10 * DAY
+    try:
+        opm.set_option(opm.OPT_ENSEMBLE_SPIN, 0)
+        ens.launch(dt, 1)
+        torch.cuda.synchronize()
+        reps = ens.read_reports()
+    finally:
+        opm.set_option(opm.OPT_ENSEMBLE_SPIN, 1 << 22)
+    failed = [m for m in range(len(ms)) if reps[m]["status"] == opm.EHIP]
+    assert failed
+    for m in range(len(ms)):
+        assert reps[m]["status"] in (0, opm.EHIP), (m, reps[m])
+        if m in failed:   # only members with subdomains to share out
+            assert ens.members[m].pb.n_sub > 1, m
+    for t, mm in zip(ens.y, ens.members):
+        t.copy_(mm.initial_state())
+    ens.launch(dt, 1)
+    torch.cuda.synchronize()
+    for m, case in enumerate(ms):
+        assert ens.read_reports()[m]["status"] == 0, m
+        _check(ens.states()[m], _oracle_step(case, dt), f"member {m} after the failed launch")
