@@ -178,15 +178,18 @@ __global__ __launch_bounds__(kBlock) void k_update(int n, double* y, const doubl
   if (!isfinite(y0) || !isfinite(y1) || !isfinite(y2)) flags[1] = 1;
 }
 
+// Phase events of two consecutive Newton iterations (the times of an
+// iteration's factorisation, solve and update are read at the next wait).
 struct Events {
-  hipEvent_t e[5];
+  hipEvent_t e[2][5];
   bool ok = false;
 };
 
 Events& events() {
   static thread_local Events ev;
   if (!ev.ok) {
-    for (auto& x : ev.e) (void)hipEventCreate(&x);
+    for (auto& set : ev.e)
+      for (auto& x : set) (void)hipEventCreate(&x);
     ev.ok = true;
   }
   return ev;
@@ -242,11 +245,17 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
   std::memset(&cw, 0, sizeof cw);
   if (use_cpr) cw = cpr_carve(pb, w.cpr);
   int status = OPM_ENOTCONV;
+  int pend = -1;   // the event set of an iteration whose later phases are not yet timed
+  auto time_rest = [&](hipEvent_t* E) {
+    rep->t_factor += elapsed(E[1], E[2]);
+    rep->t_krylov += elapsed(E[2], E[3]);
+  };
   for (int it = 0;; ++it) {
-    OPM_TRY_HIP(hipEventRecord(ev.e[0], s));
+    hipEvent_t* E = ev.e[it & 1];
+    OPM_TRY_HIP(hipEventRecord(E[0], s));
     OPM_TRY(launch_assemble(pb, y, w.acc0, dt, w.R, w.J, w.norms, s, std_wells ? ww.C : nullptr));
     if (std_wells) OPM_TRY(well_system(pb, y, dt, ww, w.flags, s));
-    OPM_TRY_HIP(hipEventRecord(ev.e[1], s));
+    OPM_TRY_HIP(hipEventRecord(E[1], s));
     double nrm[8];
     int32_t flags[4];
     OPM_TRY_HIP(hipMemcpyAsync(nrm, w.norms, sizeof(nrm), hipMemcpyDeviceToHost, s));
@@ -255,7 +264,12 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
       OPM_TRY_HIP(hipMemcpyAsync(wn.data(), ww.wn, sizeof(double) * wn.size(),
                                  hipMemcpyDeviceToHost, s));
     OPM_TRY_HIP(hipStreamSynchronize(s));
-    rep->t_assemble += elapsed(ev.e[0], ev.e[1]);
+    rep->t_assemble += elapsed(E[0], E[1]);
+    if (pend >= 0) {
+      time_rest(ev.e[pend]);
+      rep->t_update += elapsed(ev.e[pend][3], ev.e[pend][4]);
+      pend = -1;
+    }
     for (int c = 0; c < 3; ++c) {
       rep->cnv[c] = nrm[c];
       rep->mb[c] = nrm[3 + c];
@@ -280,7 +294,9 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
     }
     OPM_TRY(ilu_factor(pb, w.J, w.ilu, o->precision, &w.flags[0], s));
     if (use_cpr) OPM_TRY(cpr_setup(pb, w.J, cw, &w.flags[0], s));
-    OPM_TRY_HIP(hipEventRecord(ev.e[2], s));
+    // the factorisation's flag: read by the solver's own first wait
+    OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    OPM_TRY_HIP(hipEventRecord(E[2], s));
     opm_solve_report lr;
     if (std_wells) OPM_TRY(well_rhs(pb, ww, w.R, s));   // R_r - sum C D^-1 R_w
     if (o->krylov == OPM_KRYLOV_GMRES)
@@ -289,18 +305,12 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
     else
       OPM_TRY(bicgstab(pb, w.J, w.ilu, o->precision, w.R, w.d, o->lin_rtol, o->lin_maxit,
                        w.krylov, &lr, s, std_wells ? &ws : nullptr, use_cpr ? &cw : nullptr));
-    OPM_TRY_HIP(hipEventRecord(ev.e[3], s));
+    OPM_TRY_HIP(hipEventRecord(E[3], s));
     rep->lin_its += lr.its;
-    OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
-    OPM_TRY_HIP(hipStreamSynchronize(s));
-    rep->t_factor += elapsed(ev.e[1], ev.e[2]);
-    rep->t_krylov += elapsed(ev.e[2], ev.e[3]);
-    if (flags[0] != 0) {
-      status = flags[0];
-      break;
-    }
-    if (lr.status != OPM_OK) {
-      status = lr.status;
+    if (flags[0] != 0 || lr.status != OPM_OK) {
+      OPM_TRY_HIP(hipEventSynchronize(E[3]));
+      time_rest(E);
+      status = flags[0] != 0 ? flags[0] : lr.status;
       break;
     }
     if (std_wells)
@@ -311,9 +321,8 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
                        pb->fluid.eps_switch,
                        w.flags);
     OPM_TRY_HIP(hipGetLastError());
-    OPM_TRY_HIP(hipEventRecord(ev.e[4], s));
-    OPM_TRY_HIP(hipEventSynchronize(ev.e[4]));
-    rep->t_update += elapsed(ev.e[3], ev.e[4]);
+    OPM_TRY_HIP(hipEventRecord(E[4], s));
+    pend = it & 1;
     rep->newton_its++;
     rep->cell_newton_its += (double)n;
   }
