@@ -735,8 +735,12 @@ struct PlaneTab {
   unsigned spin;    // polls of a wait before it gives up (0: at once)
 };
 
+// The ILU(0) of the whole lattice only: with a block-ILU0 topology the
+// positions go by (local level, subdomain, cell), so a plane's rows on one
+// diagonal are not one contiguous range.
 inline bool plane_capable(const opm_problem* pb) {
-  return pb->box_cell && pb->cell_box && pb->nx > 0 && pb->ny > 0 && pb->nz > 0 &&
+  return pb->n_sub == 0 && pb->box_cell && pb->cell_box && pb->nx > 0 && pb->ny > 0 &&
+         pb->nz > 0 &&
          std::min(pb->nx, pb->ny) <= kPlaneThreads && pb->nz <= 4096 &&
          pb->nx + pb->ny - 1 <= 4096;
 }
@@ -867,7 +871,10 @@ __global__ __launch_bounds__(kPlaneThreads) void k_sweep_planes(Topo t, IluView<
   T* xch = FWD ? v.z : static_cast<T*>(p.xb);
   const int2v none = int2v{0, 0};
   for (int s = tid; s < p.D; s += kPlaneThreads) {
-    const int2v e = p.rng[(size_t)k * p.D + (FWD ? s : p.D - 1 - s)];
+    int2v e = p.rng[(size_t)k * p.D + (FWD ? s : p.D - 1 - s)];
+    // a diagonal of a plane holds at most W rows (the ring's capacity);
+    // empty ranges are (INT_MAX, -1)
+    if (e.x < e.y) e.y = min(e.y, e.x + p.W);
     rl[s] = e.x < e.y ? e : none;
   }
   if (tid == 0) {
