@@ -619,13 +619,16 @@ def bench_kernels(args):
         "spmv": (lambda: L.opm_spmv(pbp, sp(J), sp(R), sp(x), st),
                  spmv_bytes_per_cell(g.nnzb, n) * n, "k_spmv"),
         "ilu0_apply_fp64": (lambda: L.opm_ilu0_apply(pbp, sp(ilu[0]), 0, sp(R), sp(x), st),
-                            sweep_bytes_per_cell(0) * n, "k_fwd_level + k_bwd_level (FP64)"),
+                            sweep_bytes_per_cell(0) * n,
+                            "k_plane_reset + k_sweep_planes forward and backward (FP64)"),
         "ilu0_apply_fp32": (lambda: L.opm_ilu0_apply(pbp, sp(ilu[1]), 1, sp(R), sp(x), st),
-                            sweep_bytes_per_cell(1) * n, "k_fwd_level + k_bwd_level (FP32)"),
+                            sweep_bytes_per_cell(1) * n,
+                            "k_plane_reset + k_sweep_planes forward and backward (FP32)"),
         "assemble": (lambda: L.opm_assemble(pbp, sp(yk), sp(acc0), dt, sp(Rb), sp(Jb), sp(norms), st),
                      assemble_bytes(n, g.nnzb, g.nf), "k_assemble_tiled + k_norms_final"),
         "ilu0_factor_fp64": (lambda: L.opm_ilu0_factor(pbp, sp(J), sp(ilu_tmp[0]), 0, sp(status), st),
-                             factor_bytes_per_cell(0) * n, "k_pack + k_factor_level (FP64)"),
+                             factor_bytes_per_cell(0) * n,
+                             "k_pack + k_factor_level + k_plane_init + k_plane_fill (FP64)"),
         "block_apply_fp64": (lambda: L.opm_ilu0_apply(pbb, sp(bilu[0]), 0, sp(R), sp(x), st),
                              block_sweep_bytes_per_cell(0) * n,
                              f"k_apply_blocks (FP64, {gb.pb.n_sub} subdomains of {blk})"),

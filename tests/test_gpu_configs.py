@@ -12,7 +12,11 @@ largest pressure, saturations within 1e-6 absolute (after every report step).
   stored by tests/golden/make_golden.py;
 * the three largest members of the 64-member ensemble (108k, 100k and 98k
   cells, levels wider than the factor's LDS window) for one report step in
-  the batched launch, FP64 and FP32 ILU(0), against stored oracle states;
+  the batched launch, FP64 and FP32 factors, one workgroup per member with
+  each member's ILU(0) and in the benchmarked launch (block ILU0 on 6x6
+  whole-column subdomains per member, 256 workgroups), against stored
+  oracle states; all 64 members in the benchmarked launch against the
+  single-system path on the same partition;
 * forced time-step cuts (a tight Newton cap) on live oil and on standard wells
   with binding limits, against the oracle's runs with the same cap.
 The oracle runs use its OpenMP build (the plain build's bits).
