@@ -831,6 +831,21 @@ __device__ __forceinline__ void coherent_store(float* p, float x) {
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The re-read of a value found not yet written (the slow path): the load and
+// its wait in one block, so that the compiler counts no load of this loop
+// among those in flight (a counted load here would make it wait for every
+// prefetch issued since, at the next use of any of them).
+__device__ __forceinline__ double coherent_reread(const double* p) {
+  unsigned long long b;
+  asm volatile("global_load_dwordx2 %0, %1, off sc1\n\ts_waitcnt vmcnt(0)" : "=v"(b) : "v"(p));
+  return __builtin_bit_cast(double, b);
+}
+__device__ __forceinline__ float coherent_reread(const float* p) {
+  unsigned b;
+  asm volatile("global_load_dword %0, %1, off sc1\n\ts_waitcnt vmcnt(0)" : "=v"(b) : "v"(p));
+  return __builtin_bit_cast(float, b);
+}
+
 // A row of a plane step: its sweep data, and the value of its off-plane
 // neighbour (loaded with the data; re-read at use while it holds the marker).
 template <typename T>
@@ -895,23 +910,41 @@ __global__ __launch_bounds__(kPlaneThreads) void k_sweep_planes(Topo t, IluView<
   }
   auto range = [&](int s) { return s < p.D ? rl[s] : none; };
   // rows rg of a step whose in-plane neighbours are the rows prg
+  // the row's record (neighbour positions and cell; the blocks and D^{-1}
+  // in 16-byte pieces, the values of the slot-major arrays): 25 vector
+  // loads per row in FP64, 16 in FP32, so that two steps of rows stay
+  // within the 63 loads a wave can have in flight
+  typedef typename Vec16<T>::type V;
+  constexpr unsigned kV = 16 / sizeof(T);
+  const V* rec = reinterpret_cast<const V*>(FWD ? v.rec_f : v.rec_b);
+  const int4v* idx = FWD ? v.idx_f : v.idx_b;
   auto fetch = [&](PlaneJob<T>& J, const int2v& rg, const int2v& prg) {
     const int cnt = rg.y - rg.x;
     J.have = tid < cnt;
     J.pos = J.have ? rg.x + tid : 0;
     const unsigned up = (unsigned)J.pos;
     SweepJob<T>& j = J.j;
-    j.cell = t.perm[up];
+    const int4v ix = idx[up];
 #pragma unroll
-    for (unsigned q = 0; q < 3; ++q) j.kp[q] = FWD ? t.lo_pos[3u * up + q] : t.up_pos[3u * up + q];
+    for (unsigned c = 0; c < (unsigned)kRecValues / kV; ++c) {
+      const V w = rec[c * ns + up];
 #pragma unroll
-    for (unsigned e = 0; e < 27; ++e) j.a[e] = FWD ? v.lov[e * ns + up] : v.upv[e * ns + up];
-#pragma unroll
-    for (unsigned e = 0; e < 9; ++e) j.D[e] = v.dinv[e * ns + up];
+      for (unsigned l = 0; l < kV; ++l) {
+        const unsigned e = c * kV + l;
+        if (e < 27u)
+          j.a[e] = w[l];
+        else
+          j.D[e - 27u] = w[l];
+      }
+    }
     if (!FWD) {
 #pragma unroll
       for (unsigned c = 0; c < 3; ++c) j.rhs[c] = v.z[c * ns + up];
     }
+    j.kp[0] = ix.x;
+    j.kp[1] = ix.y;
+    j.kp[2] = ix.z;
+    j.cell = ix.w;
     // the off-plane neighbour: the one listed that is not on the previous
     // diagonal of this plane
     int ko = -1;
@@ -937,23 +970,33 @@ __global__ __launch_bounds__(kPlaneThreads) void k_sweep_planes(Topo t, IluView<
   int2v prv = none;
   fetch(jobs[0], rgs[0], none);
   fetch(jobs[1], rgs[1], rgs[0]);
-  auto step = [&](PlaneJob<T>& J, const int2v& rg, int s) {
-    // the off-plane value: re-read until written (bounded)
-    auto unset3 = [&]() {
-      return J.ko >= 0 && (is_unset(J.xo[0]) || is_unset(J.xo[1]) || is_unset(J.xo[2]));
-    };
+  // Step s, first part: its off-plane values (loaded with its rows two steps
+  // ago), re-read into other registers while they hold the marker (bounded);
+  // done before the rows of step s + 2 are requested, so that no later wait
+  // for them covers those loads.
+  auto check = [&](const PlaneJob<T>& J, int s, T* xo) {
+    const bool unset = J.ko >= 0 && (is_unset(J.xo[0]) || is_unset(J.xo[1]) || is_unset(J.xo[2]));
+    xo[0] = J.xo[0];
+    xo[1] = J.xo[1];
+    xo[2] = J.xo[2];
     bool gave_up = J.ko >= 0 && p.spin == 0;
-    if (unset3() && !gave_up) {
+    if (unset && !gave_up) {
+      const unsigned uo = (unsigned)J.ko;
       for (unsigned it = 0;; ++it) {
         if (it == p.spin) {
           gave_up = true;
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        const unsigned uo = (unsigned)J.ko;
+        T xr[3];
 #pragma unroll
-        for (unsigned c = 0; c < 3; ++c) J.xo[c] = coherent_load(xch + c * ns + uo);
-        if (!unset3()) break;
+        for (unsigned c = 0; c < 3; ++c) xr[c] = coherent_reread(xch + c * ns + uo);
+        if (!is_unset(xr[0]) && !is_unset(xr[1]) && !is_unset(xr[2])) {
+          xo[0] = xr[0];
+          xo[1] = xr[1];
+          xo[2] = xr[2];
+          break;
+        }
         if ((it & 63) == 63 &&
             __hip_atomic_load(p.abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
           gave_up = true;
@@ -965,19 +1008,38 @@ __global__ __launch_bounds__(kPlaneThreads) void k_sweep_planes(Topo t, IluView<
       __hip_atomic_store(p.abort_w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       fail[s % 3] = 1;
     }
-    T out[3];
-    solve_row<T, FWD>(J.j, [&](int kp, T* xv) {
-      if (kp >= prv.x && kp < prv.y) {
-        const T* w = ring + (unsigned)(((s + 1) & 1) * p.W + (kp - prv.x)) * 3u;
-        xv[0] = w[0];
-        xv[1] = w[1];
-        xv[2] = w[2];
-      } else {   // the off-plane neighbour (the only other lower one)
-        xv[0] = J.xo[0];
-        xv[1] = J.xo[1];
-        xv[2] = J.xo[2];
+  };
+  // Second part: the rows (every lane computes; a missing neighbour, or a
+  // lane without a row, reads zeros: its blocks are zero, so each skipped
+  // term adds an exact zero and the rows' results are solve_row's bits),
+  // then the results to the ring and the exchange vector.
+  auto solve = [&](const PlaneJob<T>& J, const T* xo, const int2v& rg, int s) {
+    const SweepJob<T>& j = J.j;
+    T acc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = FWD ? j.rhs[c] : (T)0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int kp = j.kp[q];
+      const int off = kp - prv.x;
+      const bool in_ring = kp >= 0 && off >= 0 && kp < prv.y;
+      const T* w = ring + (unsigned)(((s + 1) & 1) * p.W + (in_ring ? off : 0)) * 3u;
+      T xv[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xv[c] = kp < 0 ? (T)0 : in_ring ? w[c] : xo[c];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const T t = j.a[9 * q + 3 * a] * xv[0] + j.a[9 * q + 3 * a + 1] * xv[1] +
+                    j.a[9 * q + 3 * a + 2] * xv[2];
+        acc[a] = FWD ? acc[a] - t : acc[a] + t;
       }
-    }, out);
+    }
+    T out[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T d = j.D[3 * a] * acc[0] + j.D[3 * a + 1] * acc[1] + j.D[3 * a + 2] * acc[2];
+      out[a] = FWD ? d : j.rhs[a] - d;
+    }
     if (J.have) {
       const unsigned pos = (unsigned)J.pos;
       T* w = ring + (unsigned)((s & 1) * p.W + (J.pos - rg.x)) * 3u;
@@ -985,7 +1047,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_sweep_planes(Topo t, IluView<
       for (unsigned c = 0; c < 3; ++c) {
         w[c] = out[c];
         coherent_store(xch + c * ns + pos, out[c]);
-        if (!FWD) x[3u * (unsigned)J.j.cell + c] = (double)out[c];
+        if (!FWD) x[3u * (unsigned)j.cell + c] = (double)out[c];
       }
     }
     if (tid == 0) fail[(s + 1) % 3] = 0;
@@ -999,9 +1061,11 @@ __global__ __launch_bounds__(kPlaneThreads) void k_sweep_planes(Topo t, IluView<
     for (int qq = 0; qq < 3; ++qq) {
       const int s = s0 + qq;
       if (s >= p.D) break;
+      T xo[3];
+      check(jobs[qq], s, xo);
       rgs[(qq + 2) % 3] = range(s + 2);
       fetch(jobs[(qq + 2) % 3], rgs[(qq + 2) % 3], rgs[(qq + 1) % 3]);
-      if (!step(jobs[qq], rgs[qq], s)) {
+      if (!solve(jobs[qq], xo, rgs[qq], s)) {
         ok = false;
         break;
       }
@@ -1070,8 +1134,10 @@ int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* stat
     hipLaunchKernelGGL(k_factor_level<T>, dim3(blocks_for(p1 - p0, kBlock)), dim3(kBlock), 0, s,
                        t, J, v, p0, p1, status);
   }
-  if (plane_capable(pb)) {   // the plane table of the sweeps
+  if (plane_capable(pb)) {   // the plane table and the row records of the sweeps
     const PlaneTab pt = plane_tab<T>(pb, ilu);
+    hipLaunchKernelGGL(k_pack_records<T>, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock), 0,
+                       s, t, v);
     hipLaunchKernelGGL(k_plane_init, dim3(blocks_for((long)pt.D * pt.nz, 256)), dim3(256), 0, s,
                        pt);
     hipLaunchKernelGGL(k_plane_fill, dim3(blocks_for(pb->n_cells, 256)), dim3(256), 0, s, t,
