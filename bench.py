@@ -628,7 +628,8 @@ def bench_kernels(args):
                      assemble_bytes(n, g.nnzb, g.nf), "k_assemble_tiled + k_norms_final"),
         "ilu0_factor_fp64": (lambda: L.opm_ilu0_factor(pbp, sp(J), sp(ilu_tmp[0]), 0, sp(status), st),
                              factor_bytes_per_cell(0) * n,
-                             "k_pack + k_factor_level + k_plane_init + k_plane_fill (FP64)"),
+                             "k_pack + k_plane_init + k_plane_fill + k_plane_factor_reset + "
+                             "k_factor_planes + k_pack_records (FP64)"),
         "block_apply_fp64": (lambda: L.opm_ilu0_apply(pbb, sp(bilu[0]), 0, sp(R), sp(x), st),
                              block_sweep_bytes_per_cell(0) * n,
                              f"k_apply_blocks (FP64, {gb.pb.n_sub} subdomains of {blk})"),

@@ -39,8 +39,11 @@
  *    needs a non-null stream, so the library creates one capture stream per
  *    device (default priority) on first use.  A mutex serialises the cache
  *    and the capture streams between host threads; OPM_OPT_KRYLOV_GRAPH = 0
- *    turns the cache off.  The graph runtime's own objects aside, nothing
- *    else persists between calls.
+ *    turns the cache off.  Besides the cache and the graph runtime's own
+ *    objects, what persists between calls is: the process-wide values of
+ *    opm_set_option, the kernels' LDS attributes, per-host-thread HIP events
+ *    of the Newton step's phase timers, and per device the static 5 MiB
+ *    scratch array of opm_assemble_noalloc (see there).
  *  - stream is a hipStream_t (NULL = default stream).  Calls are asynchronous
  *    on that stream unless their comment says that they synchronise.
  *  - Every entry point returns an int status: OPM_OK (0) or a negative code;
@@ -433,7 +436,9 @@ size_t opm_ilu0_bytes(const opm_problem* pb, int precision);
  * (exact ILU(0) for a pattern without triangles, which the 7-point TPFA
  * stencil is) and level-ordered copies of the off-diagonal blocks, in FP64 or
  * FP32.  status (device int, may be NULL) receives OPM_ESINGULAR on a zero or
- * non-finite pivot. */
+ * non-finite pivot, and OPM_EHIP if the plane-pipelined factorisation of a
+ * lattice system (OPM_OPT_PLANE_SWEEP) gave up waiting for a neighbouring
+ * plane (OPM_OPT_PLANE_SPIN). */
 int opm_ilu0_factor(const opm_problem* pb, const double* J, void* ilu, int precision,
                     int32_t* status, void* stream);
 
@@ -861,9 +866,9 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
  *   OPM_OPT_ASSEMBLY: 1 (default) the LDS-tiled assembly where the problem
  *     allows it (box_cell set, dead oil, fixed-source wells), 0 always the
  *     row-per-lane assembly.
- *   OPM_OPT_PLANE_SWEEP: sweeps of the ILU(0) of a large system (sweep mode
- *     1): 1 (default) plane-pipelined where box_cell and cell_box are set
- *     (one workgroup per z-plane), 0 one launch per level.
+ *   OPM_OPT_PLANE_SWEEP: factorisation and sweeps of the ILU(0) of a large
+ *     system (sweep mode 1): 1 (default) plane-pipelined where box_cell and
+ *     cell_box are set (one workgroup per z-plane), 0 one launch per level.
  *   OPM_OPT_PLANE_SPIN: re-reads a plane sweep makes of a value of the
  *     neighbouring plane that is not yet written before it gives up
  *     (default 262144; 0 gives up at once, to exercise the failure path): a

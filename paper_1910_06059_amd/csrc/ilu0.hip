@@ -1082,6 +1082,103 @@ __global__ __launch_bounds__(kPlaneThreads) void k_sweep_planes(Topo t, IluView<
   }
 }
 
+// The pivot recursion pipelined over z-planes like the sweeps: plane k walks
+// its diagonals, a row's lower neighbours being the previous diagonal of its
+// plane (their D^{-1} in an LDS ring) and the same diagonal of plane k - 1,
+// whose D^{-1} is read from dinv64 (filled with the marker beforehand,
+// written through to the coherence point) until it no longer holds the
+// marker.  The row arithmetic is finish_fac's: the per-level launches' bits.
+// A wait that gives up raises the abort word and sets the status to OPM_EHIP.
+// (the rows only: the padding past n keeps what the other launch shapes leave)
+template <typename T>
+__global__ __launch_bounds__(256) void k_plane_factor_reset(IluView<T> v, PlaneTab p, int n) {
+  double u;
+  unset_value(u);
+  const unsigned ns = (unsigned)v.ns, total = 9u * ns;
+  for (unsigned e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256)
+    if (e % ns < (unsigned)n) v.dinv64[e] = u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p.abort_w = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPlaneThreads) void k_factor_planes(Topo t, const double* J,
+                                                                 IluView<T> v, PlaneTab p,
+                                                                 int32_t* status) {
+  extern __shared__ unsigned char smem_fplanes[];
+  double* ring = reinterpret_cast<double*>(smem_fplanes);               // [2][W][9]
+  int2v* rl = reinterpret_cast<int2v*>(ring + 2 * 9 * (size_t)p.W);   // [D]
+  __shared__ int fail[3];
+  const int k = (int)blockIdx.x;
+  const int tid = (int)threadIdx.x;
+  const unsigned ns = (unsigned)v.ns;
+  const int2v none = int2v{0, 0};
+  for (int s = tid; s < p.D; s += kPlaneThreads) {
+    int2v e = p.rng[(size_t)k * p.D + s];
+    if (e.x < e.y) e.y = min(e.y, e.x + p.W);
+    rl[s] = e.x < e.y ? e : none;
+  }
+  if (tid == 0) fail[0] = 0;
+  __syncthreads();
+  int2v prv = none;
+  for (int s = 0; s < p.D; ++s) {
+    const int2v rg = rl[s];
+    if (tid < rg.y - rg.x) {
+      const int pos = rg.x + tid;
+      FacJob j;
+      load_fac(t, J, pos, j);
+      double inv[9];
+      bool gave_up = false;
+      finish_fac<T>(j, pos, v,
+                    [&](int kp, double* Dk) {
+                      if (kp >= prv.x && kp < prv.y) {
+                        const double* w = ring + (unsigned)(((s + 1) & 1) * p.W + (kp - prv.x)) * 9u;
+#pragma unroll
+                        for (int e = 0; e < 9; ++e) Dk[e] = w[e];
+                        return;
+                      }
+                      for (unsigned it = 0;; ++it) {
+                        bool ready = true;
+#pragma unroll
+                        for (unsigned e = 0; e < 9; ++e) {
+                          Dk[e] = coherent_load(v.dinv64 + e * ns + (unsigned)kp);
+                          ready = ready && !is_unset(Dk[e]);
+                        }
+                        if (ready) return;
+                        if (it >= p.spin ||
+                            ((it & 63) == 63 && __hip_atomic_load(p.abort_w, __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+                          gave_up = true;
+#pragma unroll
+                          for (int e = 0; e < 9; ++e) Dk[e] = 0.0;
+                          return;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                      }
+                    },
+                    status, inv);
+      double* w = ring + (unsigned)((s & 1) * p.W + tid) * 9u;
+#pragma unroll
+      for (unsigned e = 0; e < 9; ++e) {
+        w[e] = inv[e];
+        coherent_store(v.dinv64 + e * ns + (unsigned)pos, inv[e]);
+      }
+      if (gave_up) {
+        __hip_atomic_store(p.abort_w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (status) *status = OPM_EHIP;
+        fail[s % 3] = 1;
+      }
+    }
+    if (tid == 0) fail[(s + 1) % 3] = 0;
+    __syncthreads();
+    if (fail[s % 3] != 0) break;
+    prv = rg;
+  }
+}
+
+inline size_t factor_planes_lds(const PlaneTab& p) {
+  return sizeof(double) * 2 * 9 * (size_t)p.W + sizeof(int2v) * (size_t)p.D;
+}
+
 template <typename T>
 int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* status, int mode,
                 hipStream_t s) {
@@ -1129,20 +1226,31 @@ int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* stat
     OPM_TRY_HIP(hipGetLastError());
     return OPM_OK;
   }
-  for (int l = 0; l < pb->n_levels; ++l) {
-    const int p0 = pb->level_ptr_h[l], p1 = pb->level_ptr_h[l + 1];
-    hipLaunchKernelGGL(k_factor_level<T>, dim3(blocks_for(p1 - p0, kBlock)), dim3(kBlock), 0, s,
-                       t, J, v, p0, p1, status);
-  }
-  if (plane_capable(pb)) {   // the plane table and the row records of the sweeps
+  if (plane_capable(pb)) {   // the plane table (of the pipelined factorisation and sweeps)
     const PlaneTab pt = plane_tab<T>(pb, ilu);
-    hipLaunchKernelGGL(k_pack_records<T>, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock), 0,
-                       s, t, v);
     hipLaunchKernelGGL(k_plane_init, dim3(blocks_for((long)pt.D * pt.nz, 256)), dim3(256), 0, s,
                        pt);
     hipLaunchKernelGGL(k_plane_fill, dim3(blocks_for(pb->n_cells, 256)), dim3(256), 0, s, t,
                        pb->cell_box, pt);
   }
+  const bool planes = g_plane_sweep > 0 && plane_capable(pb) &&
+                      factor_planes_lds(plane_tab<T>(pb, ilu)) <= 64 * 1024;
+  if (planes) {
+    const PlaneTab pt = plane_tab<T>(pb, ilu);
+    hipLaunchKernelGGL(k_plane_factor_reset<T>, dim3(blocks_for(9 * (long)v.ns, 256 * 8)),
+                       dim3(256), 0, s, v, pt, pb->n_cells);
+    hipLaunchKernelGGL(k_factor_planes<T>, dim3(pt.nz), dim3(kPlaneThreads), factor_planes_lds(pt),
+                       s, t, J, v, pt, status);
+  } else {
+    for (int l = 0; l < pb->n_levels; ++l) {
+      const int p0 = pb->level_ptr_h[l], p1 = pb->level_ptr_h[l + 1];
+      hipLaunchKernelGGL(k_factor_level<T>, dim3(blocks_for(p1 - p0, kBlock)), dim3(kBlock), 0,
+                         s, t, J, v, p0, p1, status);
+    }
+  }
+  if (plane_capable(pb))   // the row records of the sweeps
+    hipLaunchKernelGGL(k_pack_records<T>, dim3(blocks_for(pb->n_cells, kBlock)), dim3(kBlock), 0,
+                       s, t, v);
   OPM_TRY_HIP(hipGetLastError());
   return OPM_OK;
 }

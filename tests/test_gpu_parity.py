@@ -419,20 +419,27 @@ def _plane_systems():
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_plane_sweep_bitwise_equal(opm, precision):
-    """The plane-pipelined sweeps (one workgroup per z-plane, the
-    values exchanged between planes through marked vectors) give the
-    per-level launches' bits: the same row arithmetic in the same order, on
-    full, masked, tall and one-column grids."""
+    """The plane-pipelined factorisation and sweeps (one workgroup per
+    z-plane, the values exchanged between planes through marked vectors)
+    give the per-level launches' bits: the same row arithmetic in the same
+    order, on full, masked, tall and one-column grids."""
     for case in _plane_systems():
         print(f"plane sweep: {case.name} precision {precision}", flush=True)
         g = opm.GpuModel(case)
         y = g.state(cases.random_state(case, 5))
         acc0 = g.accumulation(g.state(cases.random_state(case, 6)))
         R, J, _ = g.assemble(y, acc0, DAY)
+        ns = (g.n + 63) // 64 * 64
+        npiv = 8 * 9 * ns if precision == 0 else 8 * 9 * ns + 4 * 9 * ns
         opm.set_option(opm.OPT_SWEEP_MODE, 1)
         try:
-            ilu, status = g.ilu0_factor(J, precision)
-            assert int(status.item()) == 0
+            facs = []
+            for planes in (0, 1):
+                opm.set_option(opm.OPT_PLANE_SWEEP, planes)
+                ilu, status = g.ilu0_factor(J, precision)
+                assert int(status.item()) == 0
+                facs.append(ilu[:npiv].clone())
+            assert torch.equal(facs[0], facs[1]), (case.name, "pivots")
             xs = []
             for planes in (0, 1):
                 opm.set_option(opm.OPT_PLANE_SWEEP, planes)
