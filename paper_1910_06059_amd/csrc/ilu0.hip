@@ -374,14 +374,29 @@ struct BlockStage {
   bool in;   // k is a level of the sweep
 };
 
-template <typename T, bool FWD>
-__device__ __forceinline__ BlockStage block_index(IluView<T> v, const int* lp, int nlev, int k,
+// Level bounds of the workgroup's subdomain: from the LDS table, or (at
+// most 64 levels) from registers, lane l of every wavefront holding level
+// l's bounds (a read is then a lane read, no LDS round trip).
+template <bool REG>
+struct LevelBounds {
+  const int* lp;
+  int b, e;
+  __device__ __forceinline__ int begin(int l) const {
+    return REG ? __builtin_amdgcn_readlane(b, l) : lp[2 * l];
+  }
+  __device__ __forceinline__ int end(int l) const {
+    return REG ? __builtin_amdgcn_readlane(e, l) : lp[2 * l + 1];
+  }
+};
+
+template <typename T, bool FWD, typename LB>
+__device__ __forceinline__ BlockStage block_index(IluView<T> v, const LB& lb, int nlev, int k,
                                                   int row) {
   BlockStage st;
   const int kk = k < nlev ? k : nlev - 1;
   const int l = FWD ? kk : nlev - 1 - kk;
-  st.p0 = lp[2 * l];
-  st.p1 = lp[2 * l + 1];
+  st.p0 = lb.begin(l);
+  st.p1 = lb.end(l);
   st.pos = max(min(st.p0 + row, st.p1 - 1), 0);
   st.in = k < nlev;
   st.ix = (FWD ? v.idx_f : v.idx_b)[(unsigned)st.pos];
@@ -401,9 +416,10 @@ __device__ __forceinline__ void block_data(IluView<T> v, const BlockRhs& q, cons
   const unsigned a = (unsigned)min(eq, 2);
   j.live = st.in && st.p0 + row < st.p1 && eq < 3;
   const unsigned ns = (unsigned)v.ns, up = (unsigned)st.pos;
-  j.kp[0] = st.ix.x < 0 ? zslot : st.ix.x;
-  j.kp[1] = st.ix.y < 0 ? zslot : st.ix.y;
-  j.kp[2] = st.ix.z < 0 ? zslot : st.ix.z;
+  // (an absent neighbour, -1, is the largest unsigned value: the zero row)
+  j.kp[0] = (int)min((unsigned)st.ix.x, (unsigned)zslot);
+  j.kp[1] = (int)min((unsigned)st.ix.y, (unsigned)zslot);
+  j.kp[2] = (int)min((unsigned)st.ix.z, (unsigned)zslot);
   j.cell = st.ix.w;
   j.slot = (FWD ? base : base - (st.p1 - st.p0)) + (st.pos - st.p0);
   // buffer loads: one 32-bit lane offset per level, the chunk offsets in
@@ -445,7 +461,7 @@ __device__ __forceinline__ void block_data(IluView<T> v, const BlockRhs& q, cons
   } else {
     // y of the row (forward result); slots of lanes past the level's end
     // stay inside the subdomain
-    j.rhs = zl[3u * (unsigned)max(j.slot, 0) + a];
+    j.rhs = zl[__umul24((unsigned)max(j.slot, 0), 3u) + a];
   }
   // keep every load of the stage here, ahead of the computation of the
   // current level (the compiler would otherwise sink some of them to their
@@ -456,11 +472,25 @@ __device__ __forceinline__ void block_data(IluView<T> v, const BlockRhs& q, cons
   __builtin_amdgcn_sched_barrier(0);
 }
 
+// The neighbour values of a row (the previous level's results).  A missing
+// neighbour reads the zero row: x = 0 exactly, as in the other sweep
+// kernels (slots are below 2^24: 24-bit multiplies).
+template <typename T>
+__device__ __forceinline__ void block_x(const BlockJob<T>& j, const Lds<T>* zl, T* xv) {
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const Lds<T>* w = zl + __umul24((unsigned)j.kp[s], 3u);
+    xv[3 * s] = w[0];
+    xv[3 * s + 1] = w[1];
+    xv[3 * s + 2] = w[2];
+  }
+}
+
 // Every lane computes (the shuffles need all lanes); only rows of the level
-// store.
+// store.  xv: block_x of the row.
 template <typename T, bool FWD, int MODE>
-__device__ __forceinline__ void block_row(const BlockJob<T>& j, Lds<T>* zl, double* x,
-                                          const BlockRhs& q, double& ss) {
+__device__ __forceinline__ void block_row(const BlockJob<T>& j, const T* xv, Lds<T>* zl,
+                                          double* x, const BlockRhs& q, double& ss) {
   const int eq = block_lane_eq();
   const unsigned a = (unsigned)min(eq, 2);
   // forward right-hand side (the same expressions as the unfused vector
@@ -472,18 +502,15 @@ __device__ __forceinline__ void block_row(const BlockJob<T>& j, Lds<T>* zl, doub
   T acc = FWD ? rhs : (T)0;
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
-    // a missing neighbour reads the zero row: x = 0 exactly, as in the
-    // other sweep kernels
-    const Lds<T>* w = zl + 3u * (unsigned)j.kp[s];
-    const T x0 = w[0], x1 = w[1], x2 = w[2];
-    const T t = j.a[3 * s] * x0 + j.a[3 * s + 1] * x1 + j.a[3 * s + 2] * x2;
+    const T t = j.a[3 * s] * xv[3 * s] + j.a[3 * s + 1] * xv[3 * s + 1] +
+                j.a[3 * s + 2] * xv[3 * s + 2];
     acc = FWD ? acc - t : acc + t;
   }
   const T acc0 = quad_lane<0>(acc), acc1 = quad_lane<1>(acc), acc2 = quad_lane<2>(acc);
   const T d = j.d[0] * acc0 + j.d[1] * acc1 + j.d[2] * acc2;
   const T out = FWD ? d : j.rhs - d;
   if (!j.live) return;
-  zl[3u * (unsigned)j.slot + a] = out;
+  zl[__umul24((unsigned)j.slot, 3u) + a] = out;
   if (!FWD) x[3u * (unsigned)j.cell + a] = (double)out;
   if (FWD && MODE == kry::kFuseBegin) q.f.p[3u * (unsigned)j.cell + a] = u;
   if (FWD && MODE == kry::kFuseS) {
@@ -494,20 +521,37 @@ __device__ __forceinline__ void block_row(const BlockJob<T>& j, Lds<T>* zl, doub
 
 // Rows of a level beyond the first NT / 64 * 16 (subdomains with wider
 // levels).
-template <typename T, int NT, bool FWD, int MODE>
+template <typename T, int NT, bool FWD, int MODE, typename LB>
 __device__ __forceinline__ void block_extra(IluView<T> v, const BlockRhs& q, Lds<T>* zl, double* x,
-                                            const int* lp, int nlev, int k, int base, int zslot,
+                                            const LB& lb, int nlev, int k, int base, int zslot,
                                             double& ss) {
   constexpr int kRows = NT / 64 * kRowsPerWave;
   const int l = FWD ? k : nlev - 1 - k;
-  const int w = lp[2 * l + 1] - lp[2 * l];
+  const int w = lb.end(l) - lb.begin(l);
   // uniform trip count: every lane joins the shuffles of every round
   for (int r0 = kRows; r0 < w; r0 += kRows) {
     const int row = r0 + block_lane_row();
-    const BlockStage st = block_index<T, FWD>(v, lp, nlev, k, row);
+    const BlockStage st = block_index<T, FWD>(v, lb, nlev, k, row);
     BlockJob<T> j;
     block_data<T, FWD, MODE>(v, q, zl, row, base, zslot, st, j);
-    block_row<T, FWD, MODE>(j, zl, x, q, ss);
+    T xv[9];
+    block_x(j, zl, xv);
+    block_row<T, FWD, MODE>(j, xv, zl, x, q, ss);
+  }
+}
+
+// The end of a level: a workgroup barrier, or for a one-wavefront
+// workgroup a wavefront-scope fence (the wavefront's LDS operations are
+// performed in order, so the next level's reads see this level's writes
+// without waiting for them to complete).
+template <int NT>
+__device__ __forceinline__ void level_barrier() {
+  if (NT == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
   }
 }
 
@@ -517,33 +561,34 @@ __device__ __forceinline__ void block_extra(IluView<T> v, const BlockRhs& q, Lds
 // earlier, so no load waits for one issued in the previous step.  The
 // stages rotate through register rings (3 indices, DEPTH + 1 jobs), fully
 // unrolled over a period of P steps so that every ring slot is a register.
-template <typename T, int NT, bool FWD, bool WIDE, int DEPTH, int MODE, typename Gate>
+template <typename T, int NT, bool FWD, bool WIDE, int DEPTH, int MODE, typename LB,
+          typename Gate>
 __device__ __forceinline__ bool block_sweep(IluView<T> v, BlockRhs& q, Lds<T>* zl, double* x,
-                                            const int* lp, int nlev, int nrows, int zslot,
+                                            const LB& lb, int nlev, int nrows, int zslot,
                                             double& ss, Gate gate) {
   constexpr int ND = DEPTH + 1, NI = 3;
   constexpr int P = ND % NI == 0 ? ND : ND * NI;
   const int row = block_lane_row();
   auto next_base = [&](int b, int k) {
     const int l = FWD ? k : nlev - 1 - k;
-    const int w = k < nlev ? lp[2 * l + 1] - lp[2 * l] : 0;
+    const int w = k < nlev ? lb.end(l) - lb.begin(l) : 0;
     return FWD ? b + w : b - w;
   };
   int ik = 0;                                 // index stage: next level
   int dk = 0, db = FWD ? 0 : nrows;           // data stage: next level and its base
   int ck = 0, cb = db;                        // compute stage
-  auto index = [&]() { return block_index<T, FWD>(v, lp, nlev, ik++, row); };
+  auto index = [&]() { return block_index<T, FWD>(v, lb, nlev, ik++, row); };
   auto data = [&](const BlockStage& st, BlockJob<T>& j) {
     block_data<T, FWD, MODE>(v, q, zl, row, db, zslot, st, j);
     const int w = st.in ? st.p1 - st.p0 : 0;
     db = FWD ? db + w : db - w;
     ++dk;
   };
-  auto compute = [&](const BlockJob<T>& j) {
-    block_row<T, FWD, MODE>(j, zl, x, q, ss);
-    if (WIDE) block_extra<T, NT, FWD, MODE>(v, q, zl, x, lp, nlev, ck, cb, zslot, ss);
+  auto compute = [&](const BlockJob<T>& j, const T* xv) {
+    block_row<T, FWD, MODE>(j, xv, zl, x, q, ss);
+    if (WIDE) block_extra<T, NT, FWD, MODE>(v, q, zl, x, lb, nlev, ck, cb, zslot, ss);
     cb = next_base(cb, ck++);
-    __syncthreads();
+    level_barrier<NT>();
   };
   BlockJob<T> jobs[ND];
   BlockStage idx[NI];
@@ -559,14 +604,29 @@ __device__ __forceinline__ bool block_sweep(IluView<T> v, BlockRhs& q, Lds<T>* z
   // with the first levels' loads in flight: the decisions that need the
   // iteration's scalars (their loads overlap those of the sweep)
   if (!gate(q)) return false;
-  for (int k = 0; k < nlev; k += P) {
+  // whole periods of P steps without an exit between their steps (an exit
+  // per step would leave the compiler, where the exits join, without a
+  // count of the loads in flight, and it would wait for all of them at the
+  // next period), then the last partial period step by step
+  // the current level's neighbour reads go out first: their LDS latency
+  // overlaps the issue of the later levels' loads
+  auto step = [&](int qq) __attribute__((always_inline)) {
+    T xv[9];
+    block_x(jobs[qq % ND], zl, xv);
+    __builtin_amdgcn_sched_barrier(0);
+    idx[(qq + DEPTH + 2) % NI] = index();
+    data(idx[(qq + DEPTH) % NI], jobs[(qq + DEPTH) % ND]);
+    compute(jobs[qq % ND], xv);
+  };
+  int k = 0;
+  for (; k + P <= nlev; k += P) {
 #pragma unroll
-    for (int qq = 0; qq < P; ++qq) {
-      if (k + qq >= nlev) break;
-      idx[(qq + DEPTH + 2) % NI] = index();
-      data(idx[(qq + DEPTH) % NI], jobs[(qq + DEPTH) % ND]);
-      compute(jobs[qq % ND]);
-    }
+    for (int qq = 0; qq < P; ++qq) step(qq);
+  }
+#pragma unroll
+  for (int qq = 0; qq < P - 1; ++qq) {
+    if (k + qq >= nlev) break;
+    step(qq);
   }
   return true;
 }
@@ -579,7 +639,7 @@ __device__ __forceinline__ bool block_sweep(IluView<T> v, BlockRhs& q, Lds<T>* z
 // (every workgroup evaluates them on the same partials and returns at once
 // if the iteration does not run); with the s update the workgroup's partial
 // of <s, s> goes to f.part_out.
-template <typename T, int NT, bool WIDE, int DEPTH, int MODE>
+template <typename T, int NT, bool WIDE, int DEPTH, int MODE, bool LVR>
 __global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t* slp, int nsub,
                                                       int nlev, int max_sub, const double* r,
                                                       double* x, const int32_t* skip,
@@ -613,6 +673,14 @@ __global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t
   }
   int nrows = 0;
   for (int l = 0; l < nlev; ++l) nrows += lp[2 * l + 1] - lp[2 * l];
+  LevelBounds<LVR> lb{lp, 0, 0};
+  if (LVR) {
+    const int lane = (int)(threadIdx.x & 63u);
+    if (lane < nlev) {
+      lb.b = lp[2 * lane];
+      lb.e = lp[2 * lane + 1];
+    }
+  }
   BlockRhs q{r, f, 0.0, 0.0, 0.0};
   // the iteration's tests and scalars (every workgroup on the same partials)
   auto gate = [&](BlockRhs& qq) -> bool {
@@ -625,14 +693,14 @@ __global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t
   };
   auto open = [](BlockRhs&) { return true; };
   double ss = 0.0;
-  if (!block_sweep<T, NT, true, WIDE, DEPTH, MODE>(v, q, zl, x, lp, nlev, nrows, max_sub, ss,
+  if (!block_sweep<T, NT, true, WIDE, DEPTH, MODE>(v, q, zl, x, lb, nlev, nrows, max_sub, ss,
                                                    gate))
     return;
   if (MODE == kry::kFuseS) {
     const double tot = block_sum<NT>(ss, red);
     if (threadIdx.x == 0) f.part_out[blockIdx.x] = tot;
   }
-  block_sweep<T, NT, false, WIDE, DEPTH, MODE>(v, q, zl, x, lp, nlev, nrows, max_sub, ss, open);
+  block_sweep<T, NT, false, WIDE, DEPTH, MODE>(v, q, zl, x, lb, nlev, nrows, max_sub, ss, open);
 }
 
 // Both sweeps by one workgroup of NT threads through the LDS ring with
@@ -667,8 +735,9 @@ size_t factor_lds(const opm_problem* pb) { return sizeof(double) * 2 * 9 * (size
 
 // one flag per (kernel, precision): slots 0-5 level-window kernels, 12-21
 // (FP64) and 24-33 (FP32) ring sweeps, 34-39 block-ILU0 factorisation,
-// 64-99 (FP64) and 100-135 (FP32) block-ILU0 sweeps (12 per fused mode)
-bool g_lds_attr_set[136] = {};
+// 64-99 (FP64) and 100-135 (FP32) block-ILU0 sweeps (12 per fused mode),
+// 136-153 (FP64) and 154-171 (FP32) those with level bounds in registers
+bool g_lds_attr_set[172] = {};
 
 // Dynamic LDS up to the 160 KB of a workgroup less the kernel's static LDS.
 template <typename K>
@@ -1261,19 +1330,26 @@ int apply_blocks(const opm_problem* pb, IluView<T> v, const double* r, double* x
                  const int32_t* skip, const kry::Fused& f, hipStream_t s) {
   const size_t lds = block_lds<T>(pb);
   const int slot = (sizeof(T) == 8 ? 64 : 100) + 12 * MODE;
-#define OPM_BLOCKS(NT, D, SL)                                                                    \
-  do {                                                                                           \
-    if (!block_sweep_wide(pb)) {                                                                 \
-      OPM_TRY(allow_lds(k_apply_blocks<T, NT, false, D, MODE>, slot + SL));                      \
-      hipLaunchKernelGGL((k_apply_blocks<T, NT, false, D, MODE>), dim3(pb->n_sub), dim3(NT), lds, \
-                         s, v, pb->sub_level_ptr, pb->n_sub, pb->n_levels, pb->max_sub, r, x,    \
-                         skip, f);                                                               \
-    } else {                                                                                     \
-      OPM_TRY(allow_lds(k_apply_blocks<T, NT, true, D, MODE>, slot + SL + 1));                   \
-      hipLaunchKernelGGL((k_apply_blocks<T, NT, true, D, MODE>), dim3(pb->n_sub), dim3(NT), lds,  \
-                         s, v, pb->sub_level_ptr, pb->n_sub, pb->n_levels, pb->max_sub, r, x,    \
-                         skip, f);                                                               \
-    }                                                                                            \
+  // level bounds in registers where a subdomain has at most 64 levels
+  const int rslot = (sizeof(T) == 8 ? 136 : 154) + 6 * MODE;
+#define OPM_BLOCKS(NT, D, SL)                                                                     \
+  do {                                                                                            \
+    if (!block_sweep_wide(pb) && pb->n_levels <= 64) {                                            \
+      OPM_TRY(allow_lds(k_apply_blocks<T, NT, false, D, MODE, true>, rslot + SL / 2));            \
+      hipLaunchKernelGGL((k_apply_blocks<T, NT, false, D, MODE, true>), dim3(pb->n_sub),          \
+                         dim3(NT), lds, s, v, pb->sub_level_ptr, pb->n_sub, pb->n_levels,         \
+                         pb->max_sub, r, x, skip, f);                                             \
+    } else if (!block_sweep_wide(pb)) {                                                           \
+      OPM_TRY(allow_lds(k_apply_blocks<T, NT, false, D, MODE, false>, slot + SL));                \
+      hipLaunchKernelGGL((k_apply_blocks<T, NT, false, D, MODE, false>), dim3(pb->n_sub),         \
+                         dim3(NT), lds, s, v, pb->sub_level_ptr, pb->n_sub, pb->n_levels,         \
+                         pb->max_sub, r, x, skip, f);                                             \
+    } else {                                                                                      \
+      OPM_TRY(allow_lds(k_apply_blocks<T, NT, true, D, MODE, false>, slot + SL + 1));             \
+      hipLaunchKernelGGL((k_apply_blocks<T, NT, true, D, MODE, false>), dim3(pb->n_sub),          \
+                         dim3(NT), lds, s, v, pb->sub_level_ptr, pb->n_sub, pb->n_levels,         \
+                         pb->max_sub, r, x, skip, f);                                             \
+    }                                                                                             \
   } while (0)
   // one level of data in flight (two measured no faster on 9000- to
   // 500000-cell systems; the fused forms only have one)
