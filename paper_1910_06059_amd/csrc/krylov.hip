@@ -73,6 +73,10 @@ __device__ __forceinline__ void store_partial(double v, double* part, double* sh
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// Keeps a value's computation (and the loads it waits for) ahead of the
+// branches that follow.
+__device__ __forceinline__ void keep_value(double v) { asm volatile("" ::"v"(v)); }
+
 using ilu::kSpmvRowsPerWave;
 using ilu::spmv_group;
 using ilu::spmv_groups;
@@ -148,13 +152,22 @@ __global__ __launch_bounds__(NT) void k_spmv_rv(int n, const int32_t* row_ptr,
                                                      const int32_t* col, const double* J, Work w,
                                                      WellCorr wc) {
   __shared__ double sh[NT / kWave];
-  if (w.sc->state != kRunning) return;
+  const int state = w.sc->state;   // (not changed by this kernel)
   double acc = 0.0;
   const int lane = threadIdx.x & (kWave - 1), ng = spmv_groups(n);
-  for (int g = blockIdx.x * (NT / kWave) + threadIdx.x / kWave; g < ng;
-       g += gridDim.x * (NT / kWave)) {
-    int row, comp;
-    double yv;
+  const int g0 = blockIdx.x * (NT / kWave) + threadIdx.x / kWave, gs = gridDim.x * (NT / kWave);
+  // the first group's products are formed while the state word is read
+  int row = 0, comp = 0;
+  double yv = 0.0;
+  bool own = false;
+  if (g0 < ng) own = spmv_group(n, row_ptr, col, J, w.ph, g0, lane, row, comp, yv, wc);
+  keep_value(yv);
+  if (state != kRunning) return;
+  if (own) {
+    w.v[3 * row + comp] = yv;
+    acc += w.rh[3 * row + comp] * yv;
+  }
+  for (int g = g0 + gs; g < ng; g += gs) {
     if (spmv_group(n, row_ptr, col, J, w.ph, g, lane, row, comp, yv, wc)) {
       w.v[3 * row + comp] = yv;
       acc += w.rh[3 * row + comp] * yv;
@@ -197,18 +210,36 @@ __global__ __launch_bounds__(NT) void k_spmv_t(int n, const int32_t* row_ptr,
                                                     int nss, WellCorr wc) {
   __shared__ double sh[NT / kWave];
   __shared__ int word;
+  // the state word (read once for the workgroup) and the partials of
+  // <s, s> go out first, the first group's products are formed while they
+  // are in flight
+  int st0 = 0;
+  if (threadIdx.x == 0) st0 = w.sc->state;
+  const double pss = CHECK ? kry::partial_first(w.part_ss, nss) : 0.0;
+  const int lane = threadIdx.x & (kWave - 1), ng = spmv_groups(n);
+  const int g0 = blockIdx.x * (NT / kWave) + threadIdx.x / kWave, gs = gridDim.x * (NT / kWave);
+  int row = 0, comp = 0;
+  double yv = 0.0;
+  bool own = false;
+  if (g0 < ng) own = spmv_group(n, row_ptr, col, J, w.sh, g0, lane, row, comp, yv, wc);
+  keep_value(yv);
+  keep_value(pss);
+  if (threadIdx.x == 0) word = st0;
+  __syncthreads();
+  const int state = word;
   if (CHECK) {
-    const int state = kry::read_state(w.sc, &word);
-    if (!kry::half_step_check<NT>(*w.sc, state, w.part_ss, nss, sh)) return;
-  } else if (w.sc->state != kRunning) {
+    const double share = kry::partials_share<NT>(w.part_ss, nss, pss);
+    if (!kry::half_step_check_share<NT>(*w.sc, state, share, sh)) return;
+  } else if (state != kRunning) {
     return;
   }
   double ts = 0.0, tt = 0.0;
-  const int lane = threadIdx.x & (kWave - 1), ng = spmv_groups(n);
-  for (int g = blockIdx.x * (NT / kWave) + threadIdx.x / kWave; g < ng;
-       g += gridDim.x * (NT / kWave)) {
-    int row, comp;
-    double yv;
+  if (own) {
+    w.t[3 * row + comp] = yv;
+    ts += yv * w.s[3 * row + comp];
+    tt += yv * yv;
+  }
+  for (int g = g0 + gs; g < ng; g += gs) {
     if (spmv_group(n, row_ptr, col, J, w.sh, g, lane, row, comp, yv, wc)) {
       w.t[3 * row + comp] = yv;
       ts += yv * w.s[3 * row + comp];
@@ -226,14 +257,29 @@ __global__ __launch_bounds__(kBlock) void k_x(int N, double* x, Work w, int G) {
   Scalars& sc = *w.sc;
   const int state = sc.state;
   const double alpha = sc.alpha;
+  // the first partials and the first element's vectors go out with the
+  // scalars (clamped indices: no branch around the loads)
+  const double pts = kry::partial_first(w.part_ts, G);
+  const double ptt = kry::partial_first(w.part_tt, G);
+  const int k0 = blockIdx.x * kBlock + threadIdx.x, ks = gridDim.x * kBlock;
+  const int kc = min(k0, N - 1);
+  const double x0 = x[kc], ph0 = w.ph[kc], sh0 = w.sh[kc], s0 = w.s[kc], t0 = w.t[kc],
+               rh0 = w.rh[kc];
+  keep_value(pts);
+  keep_value(ptt);
+  keep_value(x0);
+  keep_value(ph0);
+  keep_value(sh0);
+  keep_value(s0);
+  keep_value(t0);
+  keep_value(rh0);
   if (state == kHalfPending) {
-    for (int k = blockIdx.x * kBlock + threadIdx.x; k < N; k += gridDim.x * kBlock)
-      x[k] += alpha * w.ph[k];
+    for (int k = k0; k < N; k += ks) x[k] += alpha * w.ph[k];
     return;
   }
   if (state != kRunning) return;
-  const double ts = sum_partials(w.part_ts, G, sh);
-  const double tt = sum_partials(w.part_tt, G, sh);
+  const double ts = block_sum<kBlock>(kry::partials_share<kBlock>(w.part_ts, G, pts), sh);
+  const double tt = block_sum<kBlock>(kry::partials_share<kBlock>(w.part_tt, G, ptt), sh);
   if (tt == 0.0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc.status = OPM_EBREAKDOWN;
@@ -243,7 +289,14 @@ __global__ __launch_bounds__(kBlock) void k_x(int N, double* x, Work w, int G) {
   }
   const double omega = ts / tt;
   double rr = 0.0, rhr = 0.0;
-  for (int k = blockIdx.x * kBlock + threadIdx.x; k < N; k += gridDim.x * kBlock) {
+  if (k0 < N) {
+    x[k0] = x0 + (alpha * ph0 + omega * sh0);
+    const double r = s0 - omega * t0;
+    w.r[k0] = r;
+    rr += r * r;
+    rhr += rh0 * r;
+  }
+  for (int k = k0 + ks; k < N; k += ks) {
     x[k] += alpha * w.ph[k] + omega * w.sh[k];
     const double r = w.s[k] - omega * w.t[k];
     w.r[k] = r;

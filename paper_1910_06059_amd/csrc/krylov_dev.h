@@ -110,12 +110,29 @@ __device__ __forceinline__ bool alpha_step(Scalars& sc, int state, const double*
   return true;
 }
 
-// Half-step exit test ||s|| <= tol.  Returns true if the iteration goes on.
+// The first of this thread's partials of a sum of G >= 1 (a clamped index:
+// no branch around the load, so that it can go out early).
+__device__ __forceinline__ double partial_first(const double* part, int G) {
+  return part[min((int)threadIdx.x, G - 1)];
+}
+
+// This thread's share of the sum of G partials (sum_partials before its
+// workgroup sum, in the same order) from its first partial.
 template <int NT>
-__device__ __forceinline__ bool half_step_check(Scalars& sc, int state, const double* part_ss,
-                                                int G, double* sh) {
+__device__ __forceinline__ double partials_share(const double* part, int G, double first) {
+  double v = 0.0;
+  if ((int)threadIdx.x < G) v += first;
+  for (int k = threadIdx.x + NT; k < G; k += NT) v += part[k];
+  return v;
+}
+
+// Half-step exit test ||s|| <= tol on the threads' shares of the partials
+// of <s, s>.  Returns true if the iteration goes on.
+template <int NT>
+__device__ __forceinline__ bool half_step_check_share(Scalars& sc, int state, double share,
+                                                      double* sh) {
   if (state != kRunning) return false;
-  const double snorm = sqrt(sum_partials<NT>(part_ss, G, sh));
+  const double snorm = sqrt(block_sum<NT>(share, sh));
   if (snorm <= sc.tol) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc.half = 1;
@@ -126,6 +143,15 @@ __device__ __forceinline__ bool half_step_check(Scalars& sc, int state, const do
     return false;
   }
   return true;
+}
+
+// Half-step exit test ||s|| <= tol.  Returns true if the iteration goes on.
+template <int NT>
+__device__ __forceinline__ bool half_step_check(Scalars& sc, int state, const double* part_ss,
+                                                int G, double* sh) {
+  if (state != kRunning) return false;
+  return half_step_check_share<NT>(sc, state,
+                                   partials_share<NT>(part_ss, G, partial_first(part_ss, G)), sh);
 }
 
 // The state word read once per workgroup (every wavefront of the workgroup
