@@ -374,6 +374,8 @@ struct BlockStage {
   bool in;   // k is a level of the sweep
 };
 
+__device__ const int32_t kZeroWord = 0;
+
 // Level bounds of the workgroup's subdomain: from the LDS table, or (at
 // most 64 levels) from registers, lane l of every wavefront holding level
 // l's bounds (a read is then a lane read, no LDS round trip).
@@ -646,21 +648,35 @@ __global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t
                                                       kry::Fused f) {
   __shared__ double red[NT / 64];
   __shared__ int word;
-  if (MODE == kry::kFuseNone && skip && *skip != 0) return;
+  // the skip flag or the iteration's state word (read once for the
+  // workgroup) go out together with the level bounds
+  // (a uniform read in every wavefront; thread 0's value is the workgroup's;
+  // without a skip flag the zero word is read: no branch around the load)
+  typedef const __attribute__((address_space(1))) int32_t GlobalWord;
+  const int skipv = MODE == kry::kFuseNone ? *(GlobalWord*)(skip ? skip : &kZeroWord) : 0;
+  const int st0 = MODE != kry::kFuseNone ? f.sc->state : 0;
   extern __shared__ unsigned char smem[];
   // [max_sub + 1][3], the last row zero; an LDS-qualified pointer keeps the
   // address arithmetic in 32 bits
   Lds<T>* zl = (Lds<T>*)reinterpret_cast<T*>(smem);
   int* lp = reinterpret_cast<int*>(smem + sizeof(T) * 3 * ((size_t)max_sub + 1));
   const int s = blockIdx.x;
+  LevelBounds<LVR> lb{lp, 0, 0};
+  if (LVR) {   // every wavefront: lane l holds level l
+    const int lane = (int)(threadIdx.x & 63u);
+    if (lane < nlev) {
+      lb.b = slp[(size_t)lane * (nsub + 1) + s];
+      lb.e = slp[(size_t)lane * (nsub + 1) + s + 1];
+    }
+  }
   for (int l = threadIdx.x; l < nlev; l += NT) {
     lp[2 * l] = slp[(size_t)l * (nsub + 1) + s];
     lp[2 * l + 1] = slp[(size_t)l * (nsub + 1) + s + 1];
   }
   if (threadIdx.x < 3) zl[3 * (size_t)max_sub + threadIdx.x] = (T)0;
-  // the iteration's state word, read once for the workgroup with the table
-  if (MODE != kry::kFuseNone && threadIdx.x == 0) word = f.sc->state;
+  if (MODE != kry::kFuseNone && threadIdx.x == 0) word = st0;
   __syncthreads();
+  if (MODE == kry::kFuseNone && skipv != 0) return;
   int state = kry::kRunning;
   if (MODE != kry::kFuseNone) {
     state = word;
@@ -673,14 +689,6 @@ __global__ __launch_bounds__(NT) void k_apply_blocks(IluView<T> v, const int32_t
   }
   int nrows = 0;
   for (int l = 0; l < nlev; ++l) nrows += lp[2 * l + 1] - lp[2 * l];
-  LevelBounds<LVR> lb{lp, 0, 0};
-  if (LVR) {
-    const int lane = (int)(threadIdx.x & 63u);
-    if (lane < nlev) {
-      lb.b = lp[2 * lane];
-      lb.e = lp[2 * lane + 1];
-    }
-  }
   BlockRhs q{r, f, 0.0, 0.0, 0.0};
   // the iteration's tests and scalars (every workgroup on the same partials)
   auto gate = [&](BlockRhs& qq) -> bool {

@@ -48,6 +48,22 @@ __device__ __forceinline__ double sum_partials(const double* part, int G, double
   return block_sum<NT>(v, sh);
 }
 
+// The first of this thread's partials of a sum of G >= 1 (a clamped index:
+// no branch around the load, so that it can go out early).
+__device__ __forceinline__ double partial_first(const double* part, int G) {
+  return part[min((int)threadIdx.x, G - 1)];
+}
+
+// This thread's share of the sum of G partials (sum_partials before its
+// workgroup sum, in the same order) from its first partial.
+template <int NT>
+__device__ __forceinline__ double partials_share(const double* part, int G, double first) {
+  double v = 0.0;
+  if ((int)threadIdx.x < G) v += first;
+  for (int k = threadIdx.x + NT; k < G; k += NT) v += part[k];
+  return v;
+}
+
 // Start of an iteration: the convergence / iteration-cap / breakdown tests
 // on the residual of the previous iteration.  Returns true if the iteration
 // runs, with beta and omega of p = r + beta (p - omega v).  `state` is the
@@ -60,8 +76,10 @@ __device__ __forceinline__ bool begin_iteration(Scalars& s, int state, const dou
     if (state == kHalfPending && blockIdx.x == 0 && threadIdx.x == 0) s.state = kDone;
     return false;
   }
-  const double rr = sum_partials<NT>(part_rr, G, sh);
-  const double rho = sum_partials<NT>(part_rhr, G, sh);
+  // both first partials go out before either sum waits for its loads
+  const double f_rr = partial_first(part_rr, G), f_rhr = partial_first(part_rhr, G);
+  const double rr = block_sum<NT>(partials_share<NT>(part_rr, G, f_rr), sh);
+  const double rho = block_sum<NT>(partials_share<NT>(part_rhr, G, f_rhr), sh);
   const int its = s.its;
   const double rnorm = sqrt(rr);
   int verdict = kRunning, status = OPM_OK;
@@ -108,22 +126,6 @@ __device__ __forceinline__ bool alpha_step(Scalars& sc, int state, const double*
   alpha = sc.rho / rv;
   if (blockIdx.x == 0 && threadIdx.x == 0) sc.alpha = alpha;
   return true;
-}
-
-// The first of this thread's partials of a sum of G >= 1 (a clamped index:
-// no branch around the load, so that it can go out early).
-__device__ __forceinline__ double partial_first(const double* part, int G) {
-  return part[min((int)threadIdx.x, G - 1)];
-}
-
-// This thread's share of the sum of G partials (sum_partials before its
-// workgroup sum, in the same order) from its first partial.
-template <int NT>
-__device__ __forceinline__ double partials_share(const double* part, int G, double first) {
-  double v = 0.0;
-  if ((int)threadIdx.x < G) v += first;
-  for (int k = threadIdx.x + NT; k < G; k += NT) v += part[k];
-  return v;
 }
 
 // Half-step exit test ||s|| <= tol on the threads' shares of the partials
