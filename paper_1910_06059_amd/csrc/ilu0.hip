@@ -163,7 +163,10 @@ __global__ __launch_bounds__(kBlock) void k_pack_records(Topo t, IluView<T> v) {
 // launch).  Inside a subdomain the rows go level by level with workgroup
 // barriers.  The rows of subdomain s on level l are the positions
 // [slp[l (nsub+1) + s], slp[l (nsub+1) + s + 1]).
-template <typename T, int NT>
+// LVR: at most 64 levels, their bounds held in registers (lane l of every
+// wavefront holds level l's), so that the next level's loads need no read
+// of its bounds first.
+template <typename T, int NT, bool LVR>
 __global__ __launch_bounds__(NT) void k_factor_blocks(Topo t, const double* J, IluView<T> v,
                                                        const int32_t* slp, int nsub,
                                                        int max_width, int32_t* status) {
@@ -171,9 +174,22 @@ __global__ __launch_bounds__(NT) void k_factor_blocks(Topo t, const double* J, I
   // (every lower neighbour in the subdomain lies on the previous level)
   extern __shared__ double fwin[];   // [2][max_width][9]
   const int s = blockIdx.x;
+  int rb = 0, re = 0;
+  if (LVR) {
+    const int lane = (int)(threadIdx.x & 63u);
+    if (lane < t.nlev) {
+      rb = slp[(size_t)lane * (nsub + 1) + s];
+      re = slp[(size_t)lane * (nsub + 1) + s + 1];
+    }
+  }
   auto range = [&](int l, int& p0, int& p1) {
-    p0 = slp[(size_t)l * (nsub + 1) + s];
-    p1 = slp[(size_t)l * (nsub + 1) + s + 1];
+    if (LVR) {
+      p0 = __builtin_amdgcn_readlane(rb, l);
+      p1 = __builtin_amdgcn_readlane(re, l);
+    } else {
+      p0 = slp[(size_t)l * (nsub + 1) + s];
+      p1 = slp[(size_t)l * (nsub + 1) + s + 1];
+    }
   };
   int p0, p1;
   range(0, p0, p1);
@@ -744,8 +760,9 @@ size_t factor_lds(const opm_problem* pb) { return sizeof(double) * 2 * 9 * (size
 // one flag per (kernel, precision): slots 0-5 level-window kernels, 12-21
 // (FP64) and 24-33 (FP32) ring sweeps, 34-39 block-ILU0 factorisation,
 // 64-99 (FP64) and 100-135 (FP32) block-ILU0 sweeps (12 per fused mode),
-// 136-153 (FP64) and 154-171 (FP32) those with level bounds in registers
-bool g_lds_attr_set[172] = {};
+// 136-153 (FP64) and 154-171 (FP32) those with level bounds in registers,
+// 172-177 block-ILU0 factorisation with level bounds in registers
+bool g_lds_attr_set[178] = {};
 
 // Dynamic LDS up to the 160 KB of a workgroup less the kernel's static LDS.
 template <typename K>
@@ -1263,23 +1280,27 @@ int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* stat
   Topo t = topo_of(pb);
   if (mode == 2) {   // block ILU0: one workgroup per subdomain
     const size_t lds = sizeof(double) * 2 * 9 * (size_t)pb->max_width;
-    const int slot = sizeof(T) == 8 ? 34 : 37;
+    // level bounds in registers where a subdomain has at most 64 levels
+    const bool lvr = pb->n_levels <= 64;
+    const int slot = (sizeof(T) == 8 ? 34 : 37) + (lvr ? 138 : 0);
+#define OPM_FACTOR_BLOCKS(NT, SL)                                                              \
+  do {                                                                                         \
+    if (lvr) {                                                                                 \
+      OPM_TRY(allow_lds(k_factor_blocks<T, NT, true>, slot + SL));                             \
+      hipLaunchKernelGGL((k_factor_blocks<T, NT, true>), dim3(pb->n_sub), dim3(NT), lds, s, t, \
+                         J, v, pb->sub_level_ptr, pb->n_sub, pb->max_width, status);           \
+    } else {                                                                                   \
+      OPM_TRY(allow_lds(k_factor_blocks<T, NT, false>, slot + SL));                            \
+      hipLaunchKernelGGL((k_factor_blocks<T, NT, false>), dim3(pb->n_sub), dim3(NT), lds, s,   \
+                         t, J, v, pb->sub_level_ptr, pb->n_sub, pb->max_width, status);        \
+    }                                                                                          \
+  } while (0)
     switch (block_threads(pb)) {
-      case 64:
-        OPM_TRY(allow_lds(k_factor_blocks<T, 64>, slot));
-        hipLaunchKernelGGL((k_factor_blocks<T, 64>), dim3(pb->n_sub), dim3(64), lds, s, t, J, v,
-                           pb->sub_level_ptr, pb->n_sub, pb->max_width, status);
-        break;
-      case 128:
-        OPM_TRY(allow_lds(k_factor_blocks<T, 128>, slot + 1));
-        hipLaunchKernelGGL((k_factor_blocks<T, 128>), dim3(pb->n_sub), dim3(128), lds, s, t, J,
-                           v, pb->sub_level_ptr, pb->n_sub, pb->max_width, status);
-        break;
-      default:
-        OPM_TRY(allow_lds(k_factor_blocks<T, 256>, slot + 2));
-        hipLaunchKernelGGL((k_factor_blocks<T, 256>), dim3(pb->n_sub), dim3(256), lds, s, t, J,
-                           v, pb->sub_level_ptr, pb->n_sub, pb->max_width, status);
+      case 64: OPM_FACTOR_BLOCKS(64, 0); break;
+      case 128: OPM_FACTOR_BLOCKS(128, 1); break;
+      default: OPM_FACTOR_BLOCKS(256, 2); break;
     }
+#undef OPM_FACTOR_BLOCKS
     hipLaunchKernelGGL(k_pack_block_records<T>, dim3(blocks_for(pb->n_cells, kPackRows)),
                        dim3(256), 0, s, t, pb->row_ptr, J, v, pb->slot);
     OPM_TRY_HIP(hipGetLastError());
