@@ -42,8 +42,12 @@
  *    turns the cache off.  Besides the cache and the graph runtime's own
  *    objects, what persists between calls is: the process-wide values of
  *    opm_set_option, the kernels' LDS attributes, per-host-thread HIP events
- *    of the Newton step's phase timers, and per device the static 5 MiB
- *    scratch array of opm_assemble_noalloc (see there).
+ *    of the Newton step's phase timers and 48 bytes of pinned host memory
+ *    for its status reads, per host thread and device an event and 96 bytes
+ *    of pinned host memory for opm_bicgstab's reads of its iteration state
+ *    (the host polls these events rather than sleeping in a blocking wait),
+ *    and per device the static 5 MiB scratch array of opm_assemble_noalloc
+ *    (see there).
  *  - stream is a hipStream_t (NULL = default stream).  Calls are asynchronous
  *    on that stream unless their comment says that they synchronise.
  *  - Every entry point returns an int status: OPM_OK (0) or a negative code;

@@ -35,6 +35,17 @@ inline int blocks_for(long n, int per_block) { return (int)((n + per_block - 1) 
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Host wait for an event by polling it (a blocking wait may put the thread
+// to sleep and wake it well after the work ended, with the device idle
+// until the next launch); after about four million polls it blocks.
+inline hipError_t spin_wait(hipEvent_t e) {
+  for (long k = 0; k < (1L << 22); ++k) {
+    const hipError_t q = hipEventQuery(e);
+    if (q != hipErrorNotReady) return q;
+  }
+  return hipEventSynchronize(e);
+}
+
 // Sum over a workgroup, fixed tree order (deterministic).  All threads of the
 // block must call it; the result is returned to every thread.  `sh` needs
 // blockDim.x / 64 doubles of LDS.

@@ -417,9 +417,37 @@ int capture_stream(int device, hipStream_t* out) {
 // Enqueue the whole solve; returns after reading the final scalars.
 // ws (may be null): standard wells, solved through their Schur complement.
 // cpr (may be null): CPR-AMG set up for J, with ilu as its second stage.
+namespace {
+// Per host thread and device: pinned host memory for the iteration's
+// scalars and an event the host polls for their copy.
+struct StateRead {
+  int device = -1;
+  hipEvent_t ev = nullptr;
+  Scalars* host = nullptr;
+};
+
+StateRead* state_read() {
+  static thread_local std::vector<StateRead> reads;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  for (auto& r : reads)
+    if (r.device == dev) return &r;
+  StateRead r;
+  r.device = dev;
+  void* p = nullptr;
+  if (hipEventCreateWithFlags(&r.ev, hipEventDisableTiming) != hipSuccess) return nullptr;
+  if (hipHostMalloc(&p, sizeof(Scalars), hipHostMallocDefault) != hipSuccess) return nullptr;
+  r.host = (Scalars*)p;
+  reads.push_back(r);
+  return &reads.back();
+}
+}  // namespace
+
 int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, const double* b,
              double* x, double rtol, int maxit, void* work, opm_solve_report* rep,
              hipStream_t st, const WellSchur* ws, const CprWork* cpr) {
+  StateRead* sr = state_read();
+  if (!sr) return OPM_EHIP;
   const int n = pb->n_cells, N = 3 * n;
   Work w = carve(pb, work);
   const int G = vec_grid(N), Gr = std::min(kMaxGrid, std::max(1, spmv_blocks(n)));
@@ -553,8 +581,10 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
     // a final begin turns a pending half-step exit into done and performs the
     // convergence test of the last full iteration
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBlock), 0, st, 0, w, G);
-    OPM_TRY_HIP(hipMemcpyAsync(&host, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
-    OPM_TRY_HIP(hipStreamSynchronize(st));
+    OPM_TRY_HIP(hipMemcpyAsync(sr->host, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    OPM_TRY_HIP(hipEventRecord(sr->ev, st));
+    OPM_TRY_HIP(spin_wait(sr->ev));
+    host = *sr->host;
     if (host.state == kDone) break;
     if (launched > maxit + 2) {   // cannot happen: k_begin enforces maxit
       host.status = OPM_ENOTCONV;

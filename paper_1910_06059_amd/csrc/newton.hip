@@ -179,20 +179,38 @@ __global__ __launch_bounds__(kBlock) void k_update(int n, double* y, const doubl
 }
 
 // Phase events of two consecutive Newton iterations (the times of an
-// iteration's factorisation, solve and update are read at the next wait).
+// iteration's factorisation, solve and update are read at the next wait),
+// and pinned host words for the step's status reads (the norms and flags
+// after the assembly, the factorisation's flag, whose copy then does not
+// hold the host until the factorisation ends).
 struct Events {
   hipEvent_t e[2][5];
+  hipEvent_t done = nullptr;   // polled for the status reads
+  double* nrm = nullptr;     // [8]
+  int32_t* flags = nullptr;  // [4]
   bool ok = false;
 };
 
-Events& events() {
+Events* events() {
   static thread_local Events ev;
   if (!ev.ok) {
     for (auto& set : ev.e)
-      for (auto& x : set) (void)hipEventCreate(&x);
+      if (set[0] == nullptr)
+        for (auto& x : set)
+          if (hipEventCreate(&x) != hipSuccess) return nullptr;
+    if (!ev.done && hipEventCreateWithFlags(&ev.done, hipEventDisableTiming) != hipSuccess)
+      return nullptr;
+    if (!ev.nrm) {
+      void* p = nullptr;
+      if (hipHostMalloc(&p, 8 * sizeof(double) + 4 * sizeof(int32_t), hipHostMallocDefault) !=
+          hipSuccess)
+        return nullptr;
+      ev.nrm = (double*)p;
+      ev.flags = (int32_t*)(ev.nrm + 8);
+    }
     ev.ok = true;
   }
-  return ev;
+  return &ev;
 }
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -227,7 +245,9 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
                 const opm_newton_opts* o, void* work, opm_newton_report* rep, hipStream_t s) {
   const int n = pb->n_cells;
   NewtonWork w = carve(pb, o->precision, work);
-  Events& ev = events();
+  Events* evp = events();
+  if (!evp) return OPM_EHIP;
+  Events& ev = *evp;
   memset(rep, 0, sizeof(*rep));
   OPM_TRY(launch_accumulation(pb, y_prev, w.acc0, s));
   hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, w.flags);
@@ -256,14 +276,15 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
     OPM_TRY(launch_assemble(pb, y, w.acc0, dt, w.R, w.J, w.norms, s, std_wells ? ww.C : nullptr));
     if (std_wells) OPM_TRY(well_system(pb, y, dt, ww, w.flags, s));
     OPM_TRY_HIP(hipEventRecord(E[1], s));
-    double nrm[8];
-    int32_t flags[4];
-    OPM_TRY_HIP(hipMemcpyAsync(nrm, w.norms, sizeof(nrm), hipMemcpyDeviceToHost, s));
-    OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    double* nrm = ev.nrm;
+    int32_t* flags = ev.flags;
+    OPM_TRY_HIP(hipMemcpyAsync(nrm, w.norms, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+    OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (std_wells)
       OPM_TRY_HIP(hipMemcpyAsync(wn.data(), ww.wn, sizeof(double) * wn.size(),
                                  hipMemcpyDeviceToHost, s));
-    OPM_TRY_HIP(hipStreamSynchronize(s));
+    OPM_TRY_HIP(hipEventRecord(ev.done, s));
+    OPM_TRY_HIP(spin_wait(ev.done));
     rep->t_assemble += elapsed(E[0], E[1]);
     if (pend >= 0) {
       time_rest(ev.e[pend]);
@@ -294,8 +315,9 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
     }
     OPM_TRY(ilu_factor(pb, w.J, w.ilu, o->precision, &w.flags[0], s));
     if (use_cpr) OPM_TRY(cpr_setup(pb, w.J, cw, &w.flags[0], s));
-    // the factorisation's flag: read by the solver's own first wait
-    OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    // the factorisation's flag (pinned: the copy is queued, the solver's
+    // launches follow at once; read once the solve has been waited for)
+    OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     OPM_TRY_HIP(hipEventRecord(E[2], s));
     opm_solve_report lr;
     if (std_wells) OPM_TRY(well_rhs(pb, ww, w.R, s));   // R_r - sum C D^-1 R_w
@@ -307,6 +329,7 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
                        w.krylov, &lr, s, std_wells ? &ws : nullptr, use_cpr ? &cw : nullptr));
     OPM_TRY_HIP(hipEventRecord(E[3], s));
     rep->lin_its += lr.its;
+    OPM_TRY_HIP(hipEventSynchronize(E[2]));   // (the flag's copy; the solve waited past it)
     if (flags[0] != 0 || lr.status != OPM_OK) {
       OPM_TRY_HIP(hipEventSynchronize(E[3]));
       time_rest(E);
@@ -439,7 +462,10 @@ int advance(const opm_problem* pb, double* y, const double* y_nm1, double dt,
       }
     }
   }
-  OPM_TRY_HIP(hipStreamSynchronize(s));
+  Events* evp = events();
+  if (!evp) return OPM_EHIP;
+  OPM_TRY_HIP(hipEventRecord(evp->done, s));
+  OPM_TRY_HIP(spin_wait(evp->done));
   report->status = status;
   return status;
 }
