@@ -41,10 +41,24 @@ struct Fused {
 
 // Sum of the G partials of a reduction by NT threads (identical in every
 // workgroup of the same size).
+// A thread's partials are loaded eight at a time (clamped indices, those
+// past G taken as exact zeros: v starts at +0 and never becomes -0, so
+// adding +0 changes nothing) and added in index order, the same sum as one
+// load at a time with all eight loads in flight together.
 template <int NT>
 __device__ __forceinline__ double sum_partials(const double* part, int G, double* sh) {
   double v = 0.0;
-  for (int k = threadIdx.x; k < G; k += NT) v += part[k];
+  for (int k0 = threadIdx.x; k0 < G; k0 += 8 * NT) {
+    double p[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + u * NT;
+      const double pv = part[min(k, G - 1)];
+      p[u] = k < G ? pv : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += p[u];
+  }
   return block_sum<NT>(v, sh);
 }
 
