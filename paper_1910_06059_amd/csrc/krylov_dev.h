@@ -74,7 +74,18 @@ template <int NT>
 __device__ __forceinline__ double partials_share(const double* part, int G, double first) {
   double v = 0.0;
   if ((int)threadIdx.x < G) v += first;
-  for (int k = threadIdx.x + NT; k < G; k += NT) v += part[k];
+  // the rest eight at a time, as in sum_partials
+  for (int k0 = threadIdx.x + NT; k0 < G; k0 += 8 * NT) {
+    double p[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + u * NT;
+      const double pv = part[min(k, G - 1)];
+      p[u] = k < G ? pv : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += p[u];
+  }
   return v;
 }
 
