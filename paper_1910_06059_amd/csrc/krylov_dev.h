@@ -101,19 +101,22 @@ __device__ __forceinline__ bool begin_iteration(Scalars& s, int state, const dou
     if (state == kHalfPending && blockIdx.x == 0 && threadIdx.x == 0) s.state = kDone;
     return false;
   }
-  // both first partials go out before either sum waits for its loads
+  // the iteration's scalars (not written by this kernel) and both first
+  // partials go out before either sum waits (no load moves above the sums'
+  // barriers)
+  const int its = s.its, maxit = s.maxit;
+  const double tol = s.tol, om_prev = s.omega, rho0 = s.rho0, alpha = s.alpha;
   const double f_rr = partial_first(part_rr, G), f_rhr = partial_first(part_rhr, G);
   const double rr = block_sum<NT>(partials_share<NT>(part_rr, G, f_rr), sh);
   const double rho = block_sum<NT>(partials_share<NT>(part_rhr, G, f_rhr), sh);
-  const int its = s.its;
   const double rnorm = sqrt(rr);
   int verdict = kRunning, status = OPM_OK;
-  if (rnorm <= s.tol) {
+  if (rnorm <= tol) {
     verdict = kDone;
-  } else if (its > 0 && s.omega == 0.0) {
+  } else if (its > 0 && om_prev == 0.0) {
     verdict = kDone;
     status = OPM_EBREAKDOWN;
-  } else if (its >= s.maxit) {
+  } else if (its >= maxit) {
     verdict = kDone;
     status = OPM_ENOTCONV;
   } else if (fabs(rho) < 1e-300) {
@@ -128,8 +131,8 @@ __device__ __forceinline__ bool begin_iteration(Scalars& s, int state, const dou
     }
     return false;
   }
-  beta = its == 0 ? 0.0 : (rho / s.rho0) * (s.alpha / s.omega);
-  om = s.omega;
+  beta = its == 0 ? 0.0 : (rho / rho0) * (alpha / om_prev);
+  om = om_prev;
   if (blockIdx.x == 0 && threadIdx.x == 0) s.rho = rho;
   return true;
 }
@@ -140,6 +143,7 @@ template <int NT>
 __device__ __forceinline__ bool alpha_step(Scalars& sc, int state, const double* part_rv, int G,
                                            double* sh, double& alpha) {
   if (state != kRunning) return false;
+  const double rho = sc.rho;   // (read before the sum's barriers)
   const double rv = sum_partials<NT>(part_rv, G, sh);
   if (rv == 0.0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -148,7 +152,7 @@ __device__ __forceinline__ bool alpha_step(Scalars& sc, int state, const double*
     }
     return false;
   }
-  alpha = sc.rho / rv;
+  alpha = rho / rv;
   if (blockIdx.x == 0 && threadIdx.x == 0) sc.alpha = alpha;
   return true;
 }
@@ -159,8 +163,9 @@ template <int NT>
 __device__ __forceinline__ bool half_step_check_share(Scalars& sc, int state, double share,
                                                       double* sh) {
   if (state != kRunning) return false;
+  const double tol = sc.tol;   // (read before the sum's barriers)
   const double snorm = sqrt(block_sum<NT>(share, sh));
-  if (snorm <= sc.tol) {
+  if (snorm <= tol) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc.half = 1;
       sc.relres = snorm / sc.bnorm;
