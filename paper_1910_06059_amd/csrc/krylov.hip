@@ -257,6 +257,8 @@ __global__ __launch_bounds__(kBlock) void k_x(int N, double* x, Work w, int G) {
   Scalars& sc = *w.sc;
   const int state = sc.state;
   const double alpha = sc.alpha;
+  const double rho = sc.rho;   // (for the updates at the end)
+  const int its = sc.its;
   // the first partials and the first element's vectors go out with the
   // scalars (clamped indices: no branch around the loads)
   const double pts = kry::partial_first(w.part_ts, G);
@@ -307,8 +309,8 @@ __global__ __launch_bounds__(kBlock) void k_x(int N, double* x, Work w, int G) {
   store_partial(rhr, w.part_rhr, sh);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc.omega = omega;
-    sc.rho0 = sc.rho;
-    sc.its += 1;
+    sc.rho0 = rho;
+    sc.its = its + 1;
   }
 }
 
