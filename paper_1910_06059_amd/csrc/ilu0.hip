@@ -1380,9 +1380,14 @@ int apply_blocks(const opm_problem* pb, IluView<T> v, const double* r, double* x
                          pb->max_sub, r, x, skip, f);                                             \
     }                                                                                             \
   } while (0)
-  // one level of data in flight (two measured no faster on 9000- to
-  // 500000-cell systems; the fused forms only have one)
-  const int depth = MODE == kry::kFuseNone && g_block_depth == 2 ? 2 : 1;
+  // levels of data in flight: automatically two where the subdomains fill
+  // the GPU (256 or more: bound by bandwidth, 64.0 against 66.6 us at 500k
+  // cells), else one (latency-bound: 11.79 against 11.11 us at 9000 cells);
+  // the fused forms only have one
+  const int depth = MODE == kry::kFuseNone &&
+                            (g_block_depth == 2 || (g_block_depth == 0 && pb->n_sub >= 256))
+                        ? 2
+                        : 1;
   switch (block_sweep_threads(pb) * 4 + depth) {
     case 64 * 4 + 1: OPM_BLOCKS(64, 1, 0); break;
     case 128 * 4 + 1: OPM_BLOCKS(128, 1, 2); break;
