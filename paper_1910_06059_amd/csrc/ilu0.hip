@@ -157,16 +157,28 @@ __global__ __launch_bounds__(kBlock) void k_pack_records(Topo t, IluView<T> v) {
   v.idx_b[pos] = int4v{t.up_pos[3 * p], t.up_pos[3 * p + 1], t.up_pos[3 * p + 2], cell};
 }
 
+// The end of a level: a workgroup barrier, or for a one-wavefront
+// workgroup a wavefront-scope fence (the wavefront's LDS operations are
+// performed in order, so the next level's reads see this level's writes
+// without waiting for them to complete).
+template <int NT>
+__device__ __forceinline__ void level_barrier() {
+  if (NT == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------ block ILU0
 // One workgroup per subdomain (the blocks of the block ILU0 are independent,
 // so the whole factorisation and each whole preconditioner solve are one
 // launch).  Inside a subdomain the rows go level by level with workgroup
 // barriers.  The rows of subdomain s on level l are the positions
 // [slp[l (nsub+1) + s], slp[l (nsub+1) + s + 1]).
-// LVR: at most 64 levels, their bounds held in registers (lane l of every
-// wavefront holds level l's), so that the next level's loads need no read
-// of its bounds first.
-template <typename T, int NT, bool LVR>
+template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_factor_blocks(Topo t, const double* J, IluView<T> v,
                                                        const int32_t* slp, int nsub,
                                                        int max_width, int32_t* status) {
@@ -174,22 +186,9 @@ __global__ __launch_bounds__(NT) void k_factor_blocks(Topo t, const double* J, I
   // (every lower neighbour in the subdomain lies on the previous level)
   extern __shared__ double fwin[];   // [2][max_width][9]
   const int s = blockIdx.x;
-  int rb = 0, re = 0;
-  if (LVR) {
-    const int lane = (int)(threadIdx.x & 63u);
-    if (lane < t.nlev) {
-      rb = slp[(size_t)lane * (nsub + 1) + s];
-      re = slp[(size_t)lane * (nsub + 1) + s + 1];
-    }
-  }
   auto range = [&](int l, int& p0, int& p1) {
-    if (LVR) {
-      p0 = __builtin_amdgcn_readlane(rb, l);
-      p1 = __builtin_amdgcn_readlane(re, l);
-    } else {
-      p0 = slp[(size_t)l * (nsub + 1) + s];
-      p1 = slp[(size_t)l * (nsub + 1) + s + 1];
-    }
+    p0 = slp[(size_t)l * (nsub + 1) + s];
+    p1 = slp[(size_t)l * (nsub + 1) + s + 1];
   };
   int p0, p1;
   range(0, p0, p1);
@@ -233,6 +232,123 @@ __global__ __launch_bounds__(NT) void k_factor_blocks(Topo t, const double* J, I
     buf ^= 1;
     p0 = q0;
     p1 = q1;
+  }
+}
+
+// The data load_fac reads, split in its three dependent parts: the row's
+// cell and lower-block indices, the diagonal block's index, the blocks.
+struct FacIdx {
+  int i;
+  int blk[3], tblk[3], kpos[3];
+};
+
+__device__ __forceinline__ void load_fac_idx(const Topo& t, int pos, FacIdx& a) {
+  a.i = t.perm[pos];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    a.blk[s] = t.lo_blk[3 * pos + s];
+    a.tblk[s] = t.lo_tblk[3 * pos + s];
+    a.kpos[s] = t.lo_pos[3 * pos + s];
+  }
+}
+
+__device__ __forceinline__ void load_fac_blocks(const double* J, int dpos, const FacIdx& a,
+                                                FacJob& j) {
+  const double* Aii = J + 9 * (size_t)dpos;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) j.D[e] = Aii[e];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int b = a.blk[s];
+    j.kp[s] = b < 0 ? -1 : a.kpos[s];
+    const double* A = J + 9 * (size_t)(b < 0 ? 0 : b);
+    const double* B = J + 9 * (size_t)(b < 0 ? 0 : a.tblk[s]);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      j.Aik[s][e] = A[e];
+      j.Aki[s][e] = B[e];
+    }
+  }
+}
+
+// Block-ILU0 pivot recursion of a subdomain of at most 64 levels (their
+// bounds in registers, lane l holding level l's), its loads spread over
+// three levels: while level l is computed, the blocks of level l+1, the
+// diagonal-block index of level l+2 and the indices of level l+3 are
+// loaded, each from values loaded a level earlier, so that no level waits
+// for load_fac's chain of three dependent loads.  Lanes past a level's end
+// load a clamped row and compute nothing.  The values and the arithmetic
+// are k_factor_blocks' (bitwise equal pivots).
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_factor_blocks_pipe(Topo t, const double* J, IluView<T> v,
+                                                            const int32_t* slp, int nsub,
+                                                            int max_width, int32_t* status) {
+  extern __shared__ double fwin[];   // [2][max_width][9]
+  const int s = blockIdx.x, nlev = t.nlev, tid = (int)threadIdx.x;
+  int rb = 0, re = 0;
+  {
+    const int lane = tid & 63;
+    if (lane < nlev) {
+      rb = slp[(size_t)lane * (nsub + 1) + s];
+      re = slp[(size_t)lane * (nsub + 1) + s + 1];
+    }
+  }
+  auto pos_of = [&](int l) {
+    const int lc = min(l, nlev - 1);
+    const int p0 = __builtin_amdgcn_readlane(rb, lc), p1 = __builtin_amdgcn_readlane(re, lc);
+    return max(min(p0 + tid, p1 - 1), 0);
+  };
+  FacIdx a1, a2, a3;
+  int b1, b2;
+  FacJob next;
+  {
+    FacIdx a0;
+    load_fac_idx(t, pos_of(0), a0);
+    load_fac_idx(t, pos_of(1), a1);
+    load_fac_idx(t, pos_of(2), a2);
+    const int b0 = t.diag_pos[a0.i];
+    b1 = t.diag_pos[a1.i];
+    load_fac_blocks(J, b0, a0, next);
+  }
+  int prev0 = 0, prev1 = 0, buf = 0;
+  for (int l = 0; l < nlev; ++l) {
+    const int p0 = __builtin_amdgcn_readlane(rb, l), p1 = __builtin_amdgcn_readlane(re, l);
+    const FacJob cur = next;
+    load_fac_blocks(J, b1, a1, next);
+    b2 = t.diag_pos[a2.i];
+    load_fac_idx(t, pos_of(l + 3), a3);
+    auto finish = [&](const FacJob& j, int pos) {
+      double inv[9];
+      finish_fac<T>(j, pos, v,
+                    [&](int kp, double* Dk) {
+                      if (kp >= prev0 && kp < prev1) {
+                        const double* w = fwin + ((size_t)(buf ^ 1) * max_width + (kp - prev0)) * 9;
+#pragma unroll
+                        for (int e = 0; e < 9; ++e) Dk[e] = w[e];
+                      } else {
+#pragma unroll
+                        for (int e = 0; e < 9; ++e) Dk[e] = v.dinv64[(size_t)e * v.ns + kp];
+                      }
+                    },
+                    status, inv);
+      double* w = fwin + ((size_t)buf * max_width + (pos - p0)) * 9;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) w[e] = inv[e];
+    };
+    if (p0 + tid < p1) finish(cur, p0 + tid);
+    // rows of levels wider than the workgroup
+    for (int pos = p0 + NT + tid; pos < p1; pos += NT) {
+      FacJob extra;
+      load_fac(t, J, pos, extra);
+      finish(extra, pos);
+    }
+    level_barrier<NT>();
+    prev0 = p0;
+    prev1 = p1;
+    buf ^= 1;
+    a1 = a2;
+    a2 = a3;
+    b1 = b2;
   }
 }
 
@@ -558,21 +674,6 @@ __device__ __forceinline__ void block_extra(IluView<T> v, const BlockRhs& q, Lds
   }
 }
 
-// The end of a level: a workgroup barrier, or for a one-wavefront
-// workgroup a wavefront-scope fence (the wavefront's LDS operations are
-// performed in order, so the next level's reads see this level's writes
-// without waiting for them to complete).
-template <int NT>
-__device__ __forceinline__ void level_barrier() {
-  if (NT == 64) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else {
-    __syncthreads();
-  }
-}
-
 // DEPTH: levels whose data is in flight while a level is computed.  At the
 // step that computes level s the index stage loads level s + DEPTH + 2 and
 // the data stage loads level s + DEPTH from the index loaded two steps
@@ -761,7 +862,7 @@ size_t factor_lds(const opm_problem* pb) { return sizeof(double) * 2 * 9 * (size
 // (FP64) and 24-33 (FP32) ring sweeps, 34-39 block-ILU0 factorisation,
 // 64-99 (FP64) and 100-135 (FP32) block-ILU0 sweeps (12 per fused mode),
 // 136-153 (FP64) and 154-171 (FP32) those with level bounds in registers,
-// 172-177 block-ILU0 factorisation with level bounds in registers
+// 172-177 block-ILU0 factorisation with its loads spread over levels
 bool g_lds_attr_set[178] = {};
 
 // Dynamic LDS up to the 160 KB of a workgroup less the kernel's static LDS.
@@ -1280,18 +1381,19 @@ int factor_impl(const opm_problem* pb, const double* J, void* ilu, int32_t* stat
   Topo t = topo_of(pb);
   if (mode == 2) {   // block ILU0: one workgroup per subdomain
     const size_t lds = sizeof(double) * 2 * 9 * (size_t)pb->max_width;
-    // level bounds in registers where a subdomain has at most 64 levels
+    // the recursion with its loads spread over three levels where a
+    // subdomain has at most 64 levels
     const bool lvr = pb->n_levels <= 64;
     const int slot = (sizeof(T) == 8 ? 34 : 37) + (lvr ? 138 : 0);
 #define OPM_FACTOR_BLOCKS(NT, SL)                                                              \
   do {                                                                                         \
     if (lvr) {                                                                                 \
-      OPM_TRY(allow_lds(k_factor_blocks<T, NT, true>, slot + SL));                             \
-      hipLaunchKernelGGL((k_factor_blocks<T, NT, true>), dim3(pb->n_sub), dim3(NT), lds, s, t, \
+      OPM_TRY(allow_lds(k_factor_blocks_pipe<T, NT>, slot + SL));                              \
+      hipLaunchKernelGGL((k_factor_blocks_pipe<T, NT>), dim3(pb->n_sub), dim3(NT), lds, s, t,  \
                          J, v, pb->sub_level_ptr, pb->n_sub, pb->max_width, status);           \
     } else {                                                                                   \
-      OPM_TRY(allow_lds(k_factor_blocks<T, NT, false>, slot + SL));                            \
-      hipLaunchKernelGGL((k_factor_blocks<T, NT, false>), dim3(pb->n_sub), dim3(NT), lds, s,   \
+      OPM_TRY(allow_lds(k_factor_blocks<T, NT>, slot + SL));                                   \
+      hipLaunchKernelGGL((k_factor_blocks<T, NT>), dim3(pb->n_sub), dim3(NT), lds, s,          \
                          t, J, v, pb->sub_level_ptr, pb->n_sub, pb->max_width, status);        \
     }                                                                                          \
   } while (0)
