@@ -96,10 +96,12 @@ NewtonWork carve(const opm_problem* pb, int precision, void* work) {
   c += align256(sizeof(double) * N);
   w.J = (double*)c;
   c += align256(sizeof(double) * 9 * (size_t)pb->nnzb);
+  // the flags end their 256-byte slot, right before the norms: one copy
+  // reads both
+  w.flags = (int32_t*)(c + 256 - 4 * sizeof(int32_t));
+  c += 256;
   w.norms = (double*)c;
   c += align256(norms_bytes(pb));
-  w.flags = (int32_t*)c;
-  c += 256;
   w.mean_save = (uint8_t*)c;
   c += align256((size_t)pb->n_cells);
   std::memset(&w.wells, 0, sizeof w.wells);
@@ -205,8 +207,8 @@ Events* events() {
       if (hipHostMalloc(&p, 8 * sizeof(double) + 4 * sizeof(int32_t), hipHostMallocDefault) !=
           hipSuccess)
         return nullptr;
-      ev.nrm = (double*)p;
-      ev.flags = (int32_t*)(ev.nrm + 8);
+      ev.flags = (int32_t*)p;   // [flags][norms], as in the workspace
+      ev.nrm = (double*)((char*)p + 4 * sizeof(int32_t));
     }
     ev.ok = true;
   }
@@ -278,8 +280,8 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
     OPM_TRY_HIP(hipEventRecord(E[1], s));
     double* nrm = ev.nrm;
     int32_t* flags = ev.flags;
-    OPM_TRY_HIP(hipMemcpyAsync(nrm, w.norms, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-    OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, 4 * sizeof(int32_t) + 8 * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
     if (std_wells)
       OPM_TRY_HIP(hipMemcpyAsync(wn.data(), ww.wn, sizeof(double) * wn.size(),
                                  hipMemcpyDeviceToHost, s));
