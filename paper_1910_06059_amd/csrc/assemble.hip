@@ -433,7 +433,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_assemble_tiled(TileArgs a) {
   }
   // ---- phase 4: the block rows.  The rows of an x-run of the tile are
   // consecutive in J; each run's rows are staged in LDS in J's order and the
-  // wavefront writes the run out as one contiguous range.
+  // wavefront writes the run out as one contiguous range (streaming stores:
+  // no block of J is read again by this kernel).
   if (!a.J) return;
   const int wave = l / kWave, lane = l % kWave, run = lane / kTX;
   int nbk = 1;
@@ -480,7 +481,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_assemble_tiled(TileArgs a) {
       const int len = 9 * (re - rb);
       const double* from = stage + r * kRunStage;
       double* to = a.J + 9 * (size_t)rb;
-      for (int e = lane; e < len; e += kWave) to[e] = from[e];
+      for (int e = lane; e < len; e += kWave) __builtin_nontemporal_store(from[e], to + e);
     }
   }
 }
