@@ -481,7 +481,17 @@ __global__ __launch_bounds__(kBlock, 2) void k_assemble_tiled(TileArgs a) {
       const int len = 9 * (re - rb);
       const double* from = stage + r * kRunStage;
       double* to = a.J + 9 * (size_t)rb;
-      for (int e = lane; e < len; e += kWave) __builtin_nontemporal_store(from[e], to + e);
+      // 16-byte stores from the first 16-byte boundary of the range (h: one
+      // leading value before it), a trailing value after the last pair
+      const int h = (int)(((uintptr_t)to >> 3) & 1u), np = (len - h) / 2;
+      if (lane == 0 && h) __builtin_nontemporal_store(from[0], to);
+      typedef double Pair __attribute__((ext_vector_type(2)));
+      for (int e = lane; e < np; e += kWave) {
+        const Pair v = {from[h + 2 * e], from[h + 2 * e + 1]};
+        __builtin_nontemporal_store(v, reinterpret_cast<Pair*>(to + h + 2 * e));
+      }
+      if (lane == 0 && h + 2 * np < len)
+        __builtin_nontemporal_store(from[len - 1], to + len - 1);
     }
   }
 }
