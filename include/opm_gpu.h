@@ -863,7 +863,7 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
  *     level skipping their loads (5: 512, 6: 256 threads).
  *   OPM_OPT_BLOCK_DEPTH: block-ILU0 sweeps, levels whose data is loaded
  *     while a level is computed: 0 automatic (2 for a system of 256 or more
- *     subdomains, else 1; the sweeps fused with BiCGStab always 1), 1 or 2.
+ *     subdomains, else 1), 1 or 2.
  *   OPM_OPT_KRYLOV_GRAPH: 1 (default) replays each chunk of BiCGStab
  *     iterations after the first chunk of a solve as a HIP graph captured
  *     once per set of arguments (kept until the process ends, at most 16),

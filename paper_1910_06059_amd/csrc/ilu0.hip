@@ -1484,19 +1484,16 @@ int apply_blocks(const opm_problem* pb, IluView<T> v, const double* r, double* x
   } while (0)
   // levels of data in flight: automatically two where the subdomains fill
   // the GPU (256 or more: bound by bandwidth, 64.0 against 66.6 us at 500k
-  // cells), else one (latency-bound: 11.79 against 11.11 us at 9000 cells);
-  // the fused forms only have one
-  const int depth = MODE == kry::kFuseNone &&
-                            (g_block_depth == 2 || (g_block_depth == 0 && pb->n_sub >= 256))
-                        ? 2
-                        : 1;
+  // cells), else one (latency-bound: 11.79 against 11.11 us at 9000 cells)
+  const int depth =
+      g_block_depth == 2 || (g_block_depth == 0 && pb->n_sub >= 256) ? 2 : 1;
   switch (block_sweep_threads(pb) * 4 + depth) {
     case 64 * 4 + 1: OPM_BLOCKS(64, 1, 0); break;
     case 128 * 4 + 1: OPM_BLOCKS(128, 1, 2); break;
     case 256 * 4 + 1: OPM_BLOCKS(256, 1, 4); break;
-    case 64 * 4 + 2: OPM_BLOCKS(64, MODE == kry::kFuseNone ? 2 : 1, 6); break;
-    case 128 * 4 + 2: OPM_BLOCKS(128, MODE == kry::kFuseNone ? 2 : 1, 8); break;
-    default: OPM_BLOCKS(256, MODE == kry::kFuseNone ? 2 : 1, 10); break;
+    case 64 * 4 + 2: OPM_BLOCKS(64, 2, 6); break;
+    case 128 * 4 + 2: OPM_BLOCKS(128, 2, 8); break;
+    default: OPM_BLOCKS(256, 2, 10); break;
   }
 #undef OPM_BLOCKS
   OPM_TRY_HIP(hipGetLastError());

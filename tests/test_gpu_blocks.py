@@ -171,13 +171,16 @@ def test_block_bicgstab_matches_oracle_iterations(opm):
     assert np.linalg.norm(res) <= 1e-6 * np.linalg.norm(R) * 1.0001
 
 
+@pytest.mark.parametrize("depth", [0, 2], ids=["auto", "depth2"])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_block_fused_krylov(opm, precision):
+def test_block_fused_krylov(opm, precision, depth):
     """With one workgroup per subdomain the p and s updates of BiCGStab (and
     the tests before them) run inside the preconditioner sweeps; the solve
     takes the same iterations as the unfused sequence of kernels (the same
     preconditioner by per-level launches) and the same solution to the
-    rounding of the reordered dot products."""
+    rounding of the reordered dot products, with one level of loads in
+    flight (automatic at 42 subdomains) or two (as on systems of 256 or
+    more subdomains)."""
     make, blk = CASES["C2_columns"]
     case = make()
     g = opm.GpuModel(case, ilu_blocks=blk)
@@ -185,6 +188,7 @@ def test_block_fused_krylov(opm, precision):
     Jg = torch.from_numpy(J).to(g.dev)
     out = []
     try:
+        opm.set_option(opm.OPT_BLOCK_DEPTH, depth)
         for mode in (-1, 1):
             opm.set_option(opm.OPT_SWEEP_MODE, mode)
             ilu, _ = g.ilu0_factor(Jg, precision)
@@ -193,6 +197,7 @@ def test_block_fused_krylov(opm, precision):
             out.append((x.cpu().numpy(), rep.its, rep.half))
     finally:
         opm.set_option(opm.OPT_SWEEP_MODE, -1)
+        opm.set_option(opm.OPT_BLOCK_DEPTH, 0)
     (x0, i0, h0), (x1, i1, h1) = out
     assert (i0, h0) == (i1, h1)
     # FP32 sweeps pass the last-bit differences of the dot products on at
