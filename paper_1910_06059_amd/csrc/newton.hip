@@ -272,6 +272,8 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
     rep->t_factor += elapsed(E[1], E[2]);
     rep->t_krylov += elapsed(E[2], E[3]);
   };
+  // the previous convergence test's norms relative to the tolerances
+  double far_c = HUGE_VAL, far_m = HUGE_VAL;
   for (int it = 0;; ++it) {
     hipEvent_t* E = ev.e[it & 1];
     OPM_TRY_HIP(hipEventRecord(E[0], s));
@@ -286,6 +288,19 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
       OPM_TRY_HIP(hipMemcpyAsync(wn.data(), ww.wn, sizeof(double) * wn.size(),
                                  hipMemcpyDeviceToHost, s));
     OPM_TRY_HIP(hipEventRecord(ev.done, s));
+    // Where the previous test was far from converging (more than a thousand
+    // times a tolerance; the first test of a step), the factorisation is
+    // queued before the host reads this test's norms, so that the device
+    // factorises while the host decides; a test that then converges leaves
+    // a factorisation nobody reads (the flag words and norms were copied
+    // before it).
+    const bool ahead = it < o->max_newton && (far_c > 1e3 || far_m > 1e3);
+    auto factor = [&]() -> int {
+      OPM_TRY(ilu_factor(pb, w.J, w.ilu, o->precision, &w.flags[0], s));
+      if (use_cpr) OPM_TRY(cpr_setup(pb, w.J, cw, &w.flags[0], s));
+      return OPM_OK;
+    };
+    if (ahead) OPM_TRY(factor());
     OPM_TRY_HIP(spin_wait(ev.done));
     rep->t_assemble += elapsed(E[0], E[1]);
     if (pend >= 0) {
@@ -299,6 +314,8 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
     }
     double cmax = nrm[6];
     for (double v : wn) cmax = std::isnan(v) ? v : std::fmax(cmax, v);
+    far_c = cmax / o->tol_cnv;
+    far_m = nrm[7] / o->tol_mb;
     if (flags[1] || !std::isfinite(cmax) || !std::isfinite(nrm[7])) {
       status = OPM_ENONFINITE;
       break;
@@ -315,8 +332,7 @@ int newton_step(const opm_problem* pb, double* y, const double* y_prev, double d
       status = OPM_ENOTCONV;
       break;
     }
-    OPM_TRY(ilu_factor(pb, w.J, w.ilu, o->precision, &w.flags[0], s));
-    if (use_cpr) OPM_TRY(cpr_setup(pb, w.J, cw, &w.flags[0], s));
+    if (!ahead) OPM_TRY(factor());
     // the factorisation's flag (pinned: the copy is queued, the solver's
     // launches follow at once; read once the solve has been waited for)
     OPM_TRY_HIP(hipMemcpyAsync(flags, w.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
