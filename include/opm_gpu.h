@@ -43,9 +43,10 @@
  *    objects, what persists between calls is: the process-wide values of
  *    opm_set_option, the kernels' LDS attributes, per-host-thread HIP events
  *    of the Newton step's phase timers and 48 bytes of pinned host memory
- *    for its status reads, per host thread and device an event and 96 bytes
- *    of pinned host memory for opm_bicgstab's reads of its iteration state
- *    (the host polls these events rather than sleeping in a blocking wait),
+ *    for its status reads, per host thread and device two events, 192
+ *    bytes of pinned host memory for opm_bicgstab's reads of its iteration
+ *    state and the iteration count of its last solve (the host polls these
+ *    events rather than sleeping in a blocking wait),
  *    and per device the static 5 MiB scratch array of opm_assemble_noalloc
  *    (see there).
  *  - stream is a hipStream_t (NULL = default stream).  Calls are asynchronous
@@ -467,8 +468,13 @@ size_t opm_krylov_bytes(const opm_problem* pb);
 
 /* Right-preconditioned BiCGStab (sec. 2.3.1), x0 = 0, stops when
  * ||r||_2 <= rtol ||b||_2 or after maxit iterations.  b, x: device [n][3];
- * work: device, opm_krylov_bytes; report: HOST struct (the call then
- * synchronises the stream). */
+ * work: device, opm_krylov_bytes; report: HOST struct.  The call returns
+ * once x and the report are final: the host reads the iteration state after
+ * each chunk of iterations, and where the last solve's iteration count says
+ * that the next chunk will be needed it is queued before that read.  A chunk
+ * so queued may still be on the stream when the call returns (its kernels
+ * find the solve done and change neither x nor work, which must stay
+ * allocated until the stream has passed it, as for any queued work). */
 int opm_bicgstab(const opm_problem* pb, const double* J, const void* ilu, int precision,
                  const double* b, double* x, double rtol, int32_t maxit, void* work,
                  opm_solve_report* report, void* stream);

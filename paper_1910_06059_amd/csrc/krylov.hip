@@ -420,12 +420,17 @@ int capture_stream(int device, hipStream_t* out) {
 // ws (may be null): standard wells, solved through their Schur complement.
 // cpr (may be null): CPR-AMG set up for J, with ilu as its second stage.
 namespace {
-// Per host thread and device: pinned host memory for the iteration's
-// scalars and an event the host polls for their copy.
+// Per host thread and device: pinned host memory for two reads of the
+// iteration's scalars and the events the host polls for their copies (the
+// next chunk's read can be queued while the host waits for one); pending:
+// the read of a chunk queued after the last solve's final read; last_its:
+// the iterations the last solve took.
 struct StateRead {
   int device = -1;
-  hipEvent_t ev = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
   Scalars* host = nullptr;
+  hipEvent_t pending = nullptr;
+  int last_its = 0;
 };
 
 StateRead* state_read() {
@@ -437,8 +442,9 @@ StateRead* state_read() {
   StateRead r;
   r.device = dev;
   void* p = nullptr;
-  if (hipEventCreateWithFlags(&r.ev, hipEventDisableTiming) != hipSuccess) return nullptr;
-  if (hipHostMalloc(&p, sizeof(Scalars), hipHostMallocDefault) != hipSuccess) return nullptr;
+  for (auto& e : r.ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  if (hipHostMalloc(&p, 2 * sizeof(Scalars), hipHostMallocDefault) != hipSuccess) return nullptr;
   r.host = (Scalars*)p;
   reads.push_back(r);
   return &reads.back();
@@ -450,6 +456,12 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
              hipStream_t st, const WellSchur* ws, const CprWork* cpr) {
   StateRead* sr = state_read();
   if (!sr) return OPM_EHIP;
+  // the last solve's read of a chunk queued after it ended has landed before
+  // its buffer is written again
+  if (sr->pending) {
+    OPM_TRY_HIP(spin_wait(sr->pending));
+    sr->pending = nullptr;
+  }
   const int n = pb->n_cells, N = 3 * n;
   Work w = carve(pb, work);
   const int G = vec_grid(N), Gr = std::min(kMaxGrid, std::max(1, spmv_blocks(n)));
@@ -463,7 +475,6 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
   kry::Fused fb{w.r, w.p, w.v, nullptr, w.part_rr, w.part_rhr, G, nullptr, w.sc};
   kry::Fused fs{w.r, nullptr, w.v, w.s, w.part_rv, nullptr, Gr, w.part_ss, w.sc};
   Scalars host;
-  int launched = 0;
   const WellCorr wc = ws ? ws->wc() : WellCorr{nullptr, nullptr, nullptr};
   auto prec = [&](const double* r, double* z, hipStream_t st) -> int {
     return cpr ? cpr_apply(pb, J, ilu, precision, *cpr, r, z, st, &w.sc->state)
@@ -542,7 +553,8 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
     key.plane_sweep = g_plane_sweep;
     key.plane_spin = g_plane_spin;
   }
-  for (int pass = 0;; ++pass) {
+  // One chunk and the read of the state after it (pass p: buffer p % 2).
+  auto enqueue_pass = [&](int pass) -> int {
     hipGraphExec_t exec = nullptr;
     std::unique_lock<std::mutex> lock(g_graph_mutex, std::defer_lock);
     if (g_krylov_graph == 1) {
@@ -579,20 +591,45 @@ int bicgstab(const opm_problem* pb, const double* J, void* ilu, int precision, c
       OPM_TRY(enqueue_chunk(st));
     }
     if (lock.owns_lock()) lock.unlock();
-    launched += chunk;
     // a final begin turns a pending half-step exit into done and performs the
     // convergence test of the last full iteration
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(kBlock), 0, st, 0, w, G);
-    OPM_TRY_HIP(hipMemcpyAsync(sr->host, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
-    OPM_TRY_HIP(hipEventRecord(sr->ev, st));
-    OPM_TRY_HIP(spin_wait(sr->ev));
-    host = *sr->host;
+    OPM_TRY_HIP(hipMemcpyAsync(sr->host + (pass & 1), w.sc, sizeof(Scalars),
+                               hipMemcpyDeviceToHost, st));
+    OPM_TRY_HIP(hipEventRecord(sr->ev[pass & 1], st));
+    return OPM_OK;
+  };
+  // A chunk goes out before the read of the one ahead of it where the last
+  // solve's iterations say that it will be needed to the full (half a chunk
+  // to spare), so that the device runs it while the host waits for that
+  // read; otherwise the next chunk waits for the read.  A chunk queued past
+  // the end of the solve finds the state done in every kernel and changes
+  // nothing.
+  int queued = 0;
+  auto queue = [&]() -> int {
+    OPM_TRY(enqueue_pass(queued));
+    ++queued;
+    return OPM_OK;
+  };
+  auto needed = [&](int q) {
+    return (q + 1) * chunk + chunk / 2 <= sr->last_its && q * chunk <= maxit + 2;
+  };
+  OPM_TRY(queue());
+  if (needed(1)) OPM_TRY(queue());
+  int pass = 0;
+  for (;; ++pass) {
+    OPM_TRY_HIP(spin_wait(sr->ev[pass & 1]));
+    host = sr->host[pass & 1];
     if (host.state == kDone) break;
-    if (launched > maxit + 2) {   // cannot happen: k_begin enforces maxit
+    if ((pass + 1) * chunk > maxit + 2) {   // cannot happen: k_begin enforces maxit
       host.status = OPM_ENOTCONV;
       break;
     }
+    if (queued == pass + 1) OPM_TRY(queue());
+    if (queued == pass + 2 && needed(pass + 2)) OPM_TRY(queue());
   }
+  sr->pending = queued > pass + 1 ? sr->ev[(pass + 1) & 1] : nullptr;
+  sr->last_its = host.its;
   if (rep) {
     rep->status = host.status;
     rep->half = host.half;
