@@ -868,8 +868,9 @@ int opm_ensemble_autotune(const opm_problem* members, int32_t n_members, int pre
  *     256 or 128 threads (2, 3, 4) or with wavefronts that have no row in a
  *     level skipping their loads (5: 512, 6: 256 threads).
  *   OPM_OPT_BLOCK_DEPTH: block-ILU0 sweeps, levels whose data is loaded
- *     while a level is computed: 0 automatic (2 for a system of 256 or more
- *     subdomains, else 1), 1 or 2.
+ *     while a level is computed: 0 automatic (2 for the sweeps fused with
+ *     BiCGStab, and for the others on a system of 256 or more subdomains;
+ *     else 1), 1 or 2.
  *   OPM_OPT_KRYLOV_GRAPH: 1 (default) replays each chunk of BiCGStab
  *     iterations after the first chunk of a solve as a HIP graph captured
  *     once per set of arguments (kept until the process ends, at most 16),

@@ -686,7 +686,9 @@ __device__ __forceinline__ bool block_sweep(IluView<T> v, BlockRhs& q, Lds<T>* z
                                             const LB& lb, int nlev, int nrows, int zslot,
                                             double& ss, Gate gate) {
   constexpr int ND = DEPTH + 1, NI = 3;
-  constexpr int P = ND % NI == 0 ? ND : ND * NI;
+  // (two turns of the rings at DEPTH 2: the waits at a period's end drain
+  // the loads in flight, so a longer period drains less often)
+  constexpr int P = ND % NI == 0 ? 2 * ND : ND * NI;
   const int row = block_lane_row();
   auto next_base = [&](int b, int k) {
     const int l = FWD ? k : nlev - 1 - k;
@@ -1482,11 +1484,15 @@ int apply_blocks(const opm_problem* pb, IluView<T> v, const double* r, double* x
                          pb->max_sub, r, x, skip, f);                                             \
     }                                                                                             \
   } while (0)
-  // levels of data in flight: automatically two where the subdomains fill
-  // the GPU (256 or more: bound by bandwidth, 64.0 against 66.6 us at 500k
-  // cells), else one (latency-bound: 11.79 against 11.11 us at 9000 cells)
-  const int depth =
-      g_block_depth == 2 || (g_block_depth == 0 && pb->n_sub >= 256) ? 2 : 1;
+  // levels of data in flight: automatically two for the sweeps fused with
+  // BiCGStab (at 9000 cells the Krylov time of 20 steps 68.7 -> 67.5 ms) and
+  // for the others where the subdomains fill the GPU (256 or more: bound by
+  // bandwidth, 64.0 against 66.6 us at 500k cells), else one (latency-bound:
+  // 10.89 against 11.08 us at 9000 cells)
+  const int depth = g_block_depth == 2 || (g_block_depth == 0 && (MODE != kry::kFuseNone ||
+                                                                  pb->n_sub >= 256))
+                        ? 2
+                        : 1;
   switch (block_sweep_threads(pb) * 4 + depth) {
     case 64 * 4 + 1: OPM_BLOCKS(64, 1, 0); break;
     case 128 * 4 + 1: OPM_BLOCKS(128, 1, 2); break;
