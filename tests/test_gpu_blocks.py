@@ -206,6 +206,35 @@ def test_block_fused_krylov(opm, precision, depth):
 
 
 @pytest.mark.parametrize("blk", [None, (4, 4, 15)], ids=["single", "blocks"])
+def test_krylov_chunks_queued_ahead(opm, blk):
+    """After a long solve the next one queues chunks of iterations ahead of
+    its state reads, past its own end: its solution and report equal those of
+    the same solve after a short one (no chunk queued ahead), bitwise, also
+    when it stops at the iteration cap."""
+    case = cases.config2()
+    g = opm.GpuModel(case, ilu_blocks=blk)
+    y = g.state(cases.random_state(case, 11))
+    acc0 = g.accumulation(g.state(cases.random_state(case, 12)))
+    R, J, _ = g.assemble(y, acc0, DAY)
+    b = -R
+    ilu, _ = g.ilu0_factor(J)
+
+    def after(rtol_before, rtol, maxit):
+        g.bicgstab(J, ilu, b, rtol=rtol_before)
+        x, rep = g.bicgstab(J, ilu, b, rtol=rtol, maxit=maxit)
+        torch.cuda.synchronize()
+        return x.clone(), (rep.status, rep.its, rep.half, rep.rel_res)
+
+    for rtol, maxit in ((1e-3, 500), (1e-12, 5)):
+        x_short, r_short = after(0.9, rtol, maxit)
+        x_long, r_long = after(1e-12, rtol, maxit)
+        assert r_short == r_long
+        assert torch.equal(x_short, x_long)
+        if maxit == 5:
+            assert r_long[0] == opm.ENOTCONV and r_long[1] == 5
+
+
+@pytest.mark.parametrize("blk", [None, (4, 4, 15)], ids=["single", "blocks"])
 def test_krylov_graph_replay(opm, blk):
     """Chunks of BiCGStab iterations replayed from a captured HIP graph give
     bitwise the solutions of the kernel-by-kernel enqueue, over several
